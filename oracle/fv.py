@@ -1,0 +1,255 @@
+"""Residual R(u) of the cell-centred finite-volume momentum balance.
+
+Paper passages followed (Cardiff et al., arXiv 2502.17217):
+  * Residual form R(u) = 0 and the static linear-geometry residual:
+    Section 2.2, Eq. (residual); total Lagrangian form for finite strain:
+    Appendix A, Eq. (momentum_TL), with F = I + (grad u)^T.
+  * Surface integral by one-point quadrature per face: Section 2.3.2,
+    Eq. (divStressDiscret): internal faces Gamma_f . sigma_f, displacement
+    faces Gamma_d . sigma_P, traction faces |Gamma_t| T_bar.
+  * Interpolation weight w_f = n.(x_N - x_f) / n.(x_N - x_P):
+    Eq. (stressInterp).
+  * Least-squares cell gradient: Eq. (leastSquaresGrad) and the G_P
+    tensor that follows it; boundary faces are excluded.
+  * Rhie-Chow stabilisation: Section 2.3.3, Eq. (RhieChow), with
+    K_bar = 2 mu + lambda and Delta = d/(d.n).
+  * Laws: Appendix B, Eq. (linearElastic) and Eq. (neoHook).
+
+Readings where the paper is silent or inconsistent (all listed in the
+design notes of the repository):
+  * LS weights: the gradient sum uses w_f|Gamma| but G_P uses
+    (1-w_f)|Gamma|; the two agree only when w_f = 1/2.  One weight
+    omega_f = |Gamma_f| is used in both, which keeps the stated
+    exactness for linear fields on distorted meshes.
+  * Face quantities: the face stress is sigma(grad u_f) with
+    grad u_f = w_f grad u_P + (1 - w_f) grad u_N (identical to
+    interpolating cell stresses for the linear law); the face gradient
+    in the Rhie-Chow term uses the same interpolation.
+  * Finite strain: total Lagrangian on the fixed reference mesh; the
+    face traction is (cof F_f Gamma_o) . sigma(F_f); displacement faces
+    use F_P.  The Rhie-Chow term keeps K_bar = 2 mu + lambda.
+  * Prescribed boundary values (displacements, tractions, pressures) are
+    all multiplied by the load factor of the current increment;
+    a pressure patch applies the dead load -p Gamma_o.
+  * Plane strain (2-D): unit depth; the neo-Hookean law works on the
+    3x3 tensors with F_zz = 1.
+
+All functions accept real or complex displacements; nothing non-analytic
+is applied to u, so the complex step gives exact derivatives.
+"""
+
+import numpy as np
+
+from .geometry import mesh_geometry
+
+DISP, TRAC, PRES = 1, 2, 3
+_TYPE = {"displacement": DISP, "traction": TRAC, "pressure": PRES}
+
+
+def material_constants(mat):
+    """Lame constants, bulk modulus and K_bar (Appendix B; Section 2.3.3)."""
+    E, nu = float(mat.E), float(mat.nu)
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    kappa = E / (3.0 * (1.0 - 2.0 * nu))
+    return dict(mu=mu, lam=lam, kappa=kappa, Kbar=2.0 * mu + lam,
+                law=mat.law, alpha_rc=float(mat.alpha_rc), alpha_pc=float(mat.alpha_pc))
+
+
+def _scatter(idx, vals, n):
+    """out[idx[i]] += vals[i] along axis 0; works for real and complex."""
+    if np.iscomplexobj(vals):
+        return _scatter(idx, vals.real, n) + 1j * _scatter(idx, vals.imag, n)
+    flat = vals.reshape(vals.shape[0], -1)
+    out = np.stack([np.bincount(idx, weights=flat[:, k], minlength=n)
+                    for k in range(flat.shape[1])], axis=1)
+    return out.reshape((n,) + vals.shape[1:])
+
+
+def prepare(mesh, mat):
+    """Mesh-only and material-only quantities (computed once per mesh)."""
+    dim = mesh["dim"]
+    geo = mesh_geometry(mesh)
+    n_int = mesh["n_internal"]
+    nf = mesh["n_faces"]
+    nc = mesh["n_cells"]
+    P = mesh["owner"][:n_int].astype(np.int64)
+    N = mesh["neighbour"].astype(np.int64)
+    Gam = geo["Gamma"][:n_int]
+    magG = np.linalg.norm(Gam, axis=1)
+    n = Gam / magG[:, None]
+    xP, xN, xf = geo["xc"][P], geo["xc"][N], geo["xf"][:n_int]
+    d = xN - xP
+    dn = np.einsum("fi,fi->f", d, n)
+    if np.any(dn <= 0.0):
+        raise ValueError("internal face with d.n <= 0")
+    w = np.einsum("fi,fi->f", n, xN - xf) / dn          # Eq. (stressInterp)
+    Delta = d / dn[:, None]                             # over-relaxed vector
+    magd = np.linalg.norm(d, axis=1)
+    magDelta = np.linalg.norm(Delta, axis=1)
+
+    # least-squares vectors, omega_f = |Gamma_f| in both sum and G_P
+    dd = np.einsum("fi,fi->f", d, d)
+    outer = magG[:, None, None] * d[:, :, None] * d[:, None, :] / dd[:, None, None]
+    G = _scatter(P, outer, nc) + _scatter(N, outer, nc)
+    Ginv = np.linalg.inv(G)
+    c_own = magG[:, None] * np.einsum("fij,fj->fi", Ginv[P], d) / dd[:, None]
+    c_nb = magG[:, None] * np.einsum("fij,fj->fi", Ginv[N], -d) / dd[:, None]
+
+    # boundary faces
+    b = np.arange(n_int, nf)
+    Pb = mesh["owner"][n_int:].astype(np.int64)
+    Gb = geo["Gamma"][n_int:]
+    magGb = np.linalg.norm(Gb, axis=1)
+    nb_hat = Gb / magGb[:, None]
+    db = geo["xf"][n_int:] - geo["xc"][Pb]
+    dbn = np.einsum("fi,fi->f", db, nb_hat)
+    btype = np.zeros(nf - n_int, dtype=np.int64)
+    bval = np.zeros((nf - n_int, dim))
+    for p in mesh["patches"]:
+        s = slice(p["start"] - n_int, p["start"] - n_int + p["size"])
+        btype[s] = _TYPE[p["type"]]
+        if p.get("per_face") is not None:
+            bval[s] = p["per_face"]
+        else:
+            bval[s] = np.asarray(p["value"][:dim])
+    if np.any(btype == 0):
+        raise ValueError("boundary face without a patch")
+    disp = btype == DISP
+    if np.any(dbn[disp] <= 0.0):
+        raise ValueError("displacement face with d.n <= 0")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Deltab = np.where(disp[:, None], db / dbn[:, None], 0.0)
+    return dict(mesh=mesh, dim=dim, nc=nc, n_int=n_int, geo=geo, mat=material_constants(mat),
+                P=P, N=N, Gam=Gam, magG=magG, n=n, d=d, magd=magd, w=w, Delta=Delta,
+                magDelta=magDelta, G=G, c_own=c_own, c_nb=c_nb,
+                Pb=Pb, Gb=Gb, magGb=magGb, db=db, magdb=np.linalg.norm(db, axis=1),
+                Deltab=Deltab, magDeltab=np.linalg.norm(Deltab, axis=1),
+                btype=btype, bval=bval)
+
+
+def gradient(u, pr):
+    """Least-squares cell gradient, (grad u)_P[i, j] = d u_j / d x_i.
+
+    Eq. (leastSquaresGrad): sum over internal faces of c_{P,f} (x) (u_N - u_P).
+    """
+    P, N = pr["P"], pr["N"]
+    du = u[N] - u[P]
+    g_own = pr["c_own"][:, :, None] * du[:, None, :]
+    g_nb = pr["c_nb"][:, :, None] * (-du)[:, None, :]
+    return _scatter(P, g_own, pr["nc"]) + _scatter(N, g_nb, pr["nc"])
+
+
+def stress_linear_elastic(g, c):
+    """Eq. (linearElastic): sigma = mu grad u + mu grad u^T + lambda tr(grad u) I."""
+    dim = g.shape[-1]
+    tr = np.trace(g, axis1=-2, axis2=-1)
+    eye = np.eye(dim)
+    return c["mu"] * (g + np.swapaxes(g, -1, -2)) + c["lam"] * tr[..., None, None] * eye
+
+
+def _embed3(g):
+    if g.shape[-1] == 3:
+        return g
+    out = np.zeros(g.shape[:-2] + (3, 3), dtype=g.dtype)
+    out[..., :2, :2] = g
+    return out
+
+
+def cofactor(F):
+    """cof F = det(F) F^{-T} for 3x3 tensors (polynomial, so complex-safe)."""
+    c = np.empty_like(F)
+    c[..., 0, 0] = F[..., 1, 1] * F[..., 2, 2] - F[..., 1, 2] * F[..., 2, 1]
+    c[..., 0, 1] = F[..., 1, 2] * F[..., 2, 0] - F[..., 1, 0] * F[..., 2, 2]
+    c[..., 0, 2] = F[..., 1, 0] * F[..., 2, 1] - F[..., 1, 1] * F[..., 2, 0]
+    c[..., 1, 0] = F[..., 0, 2] * F[..., 2, 1] - F[..., 0, 1] * F[..., 2, 2]
+    c[..., 1, 1] = F[..., 0, 0] * F[..., 2, 2] - F[..., 0, 2] * F[..., 2, 0]
+    c[..., 1, 2] = F[..., 0, 1] * F[..., 2, 0] - F[..., 0, 0] * F[..., 2, 1]
+    c[..., 2, 0] = F[..., 0, 1] * F[..., 1, 2] - F[..., 0, 2] * F[..., 1, 1]
+    c[..., 2, 1] = F[..., 0, 2] * F[..., 1, 0] - F[..., 0, 0] * F[..., 1, 2]
+    c[..., 2, 2] = F[..., 0, 0] * F[..., 1, 1] - F[..., 0, 1] * F[..., 1, 0]
+    return c
+
+
+def neo_hookean(g, c):
+    """Eq. (neoHook) with F = I + (grad u)^T (Appendix A).
+
+    Returns (sigma, cof F), both 3x3.
+    """
+    g3 = _embed3(g)
+    F = np.eye(3) + np.swapaxes(g3, -1, -2)
+    cof = cofactor(F)
+    J = np.einsum("...j,...j->...", F[..., 0, :], cof[..., 0, :])   # expansion along row 0
+    b = F @ np.swapaxes(F, -1, -2)
+    bbar = np.power(J, -2.0 / 3.0)[..., None, None] * b
+    dev = bbar - (np.trace(bbar, axis1=-2, axis2=-1) / 3.0)[..., None, None] * np.eye(3)
+    sigma = (c["mu"] / J)[..., None, None] * dev \
+        + (0.5 * c["kappa"] * (J * J - 1.0) / J)[..., None, None] * np.eye(3)
+    return sigma, cof
+
+
+def traction(g, Gam, c):
+    """Force on an area vector Gamma from the stress at displacement gradient g.
+
+    Linear geometry: Gamma . sigma(g) (Eq. divStressDiscret).
+    Total Lagrangian: (J F^{-T} Gamma_o) . sigma with J F^{-T} = cof F
+    (Eq. momentum_TL).
+    """
+    dim = g.shape[-1]
+    if c["law"] == "linear_elastic":
+        s = stress_linear_elastic(g, c)
+        return np.einsum("fi,fij->fj", Gam, s)
+    if c["law"] == "neo_hookean":
+        s, cof = neo_hookean(g, c)
+        G3 = np.zeros((Gam.shape[0], 3))
+        G3[:, :dim] = Gam
+        a = np.einsum("fik,fk->fi", cof, G3)
+        t = np.einsum("fi,fij->fj", a, s)
+        return t[:, :dim]
+    raise ValueError("unknown law %r" % (c["law"],))
+
+
+def residual(u, pr, load=1.0, parts=False):
+    """R(u) per cell, shape [n_cells, dim] (Eq. residual, static, no body force).
+
+    R_P = sum_f [traction_f + Rhie-Chow_f] with outward orientation: each
+    internal face is evaluated once from its owner's side and added to the
+    owner and subtracted from the neighbour.
+    """
+    c = pr["mat"]
+    nc, dim = pr["nc"], pr["dim"]
+    u = np.asarray(u).reshape(nc, dim)
+    g = gradient(u, pr)
+    P, N, w = pr["P"], pr["N"], pr["w"]
+    aK = c["alpha_rc"] * c["Kbar"]
+
+    # internal faces
+    gf = w[:, None, None] * g[P] + (1.0 - w)[:, None, None] * g[N]
+    T_int = traction(gf, pr["Gam"], c)
+    jump = (pr["magDelta"] / pr["magd"])[:, None] * (u[N] - u[P])
+    Dg = np.einsum("fi,fij->fj", pr["Delta"], gf)
+    RC_int = aK * (jump - Dg) * pr["magG"][:, None]
+
+    # boundary faces
+    Pb, bt = pr["Pb"], pr["btype"]
+    T_b = np.zeros((Pb.shape[0], dim), dtype=np.result_type(u, float))
+    RC_b = np.zeros_like(T_b)
+    m = bt == DISP
+    if np.any(m):
+        gP = g[Pb[m]]
+        T_b[m] = traction(gP, pr["Gb"][m], c)
+        ubar = load * pr["bval"][m]
+        jumpb = (pr["magDeltab"][m] / pr["magdb"][m])[:, None] * (ubar - u[Pb[m]])
+        Dgb = np.einsum("fi,fij->fj", pr["Deltab"][m], gP)
+        RC_b[m] = aK * (jumpb - Dgb) * pr["magGb"][m][:, None]
+    m = bt == TRAC
+    T_b[m] = load * pr["magGb"][m][:, None] * pr["bval"][m]
+    m = bt == PRES
+    T_b[m] = -load * pr["bval"][m][:, :1] * pr["Gb"][m]
+
+    def assemble(fint, fb):
+        return (_scatter(P, fint, nc) - _scatter(N, fint, nc) + _scatter(Pb, fb, nc))
+
+    if parts:
+        return dict(traction=assemble(T_int, T_b), rc=assemble(RC_int, RC_b), grad=g)
+    return assemble(T_int + RC_int, T_b + RC_b)

@@ -1,0 +1,80 @@
+"""Jacobian-vector products and the compact-stencil approximate Jacobian.
+
+Paper passages:
+  * J v ~ (R(u + eps v) - R(u)) / eps: Section 3.2, Eq. (JF).  The paper
+    leaves the choice of eps open; the reading used here is the
+    Walker-Pernice form eps = sqrt(eps_mach) sqrt(1 + ||u||_2) / ||v||_2.
+  * Exact directional derivative for checking the finite difference:
+    complex step, J v = Im R(u + i h v) / h (all residual arithmetic is
+    analytic in u).
+  * Approximate Jacobian J_tilde: Section 3.1, the block diagonal and
+    off-diagonal coefficients after Eq. (SegSys): off-diagonal
+    alpha K_bar |Delta||Gamma|/|d| I, diagonal minus the sum over
+    internal and displacement faces; no inertia term (static problems),
+    alpha = alpha_pc.  Blocks are scalar times identity, so the scalar
+    matrix is returned (component decoupling, Eq. SegSysX-Z).
+"""
+
+import numpy as np
+import scipy.sparse as sp
+
+from .fv import residual, DISP
+
+SQRT_EPS_MACH = np.sqrt(np.finfo(np.float64).eps)
+
+
+def eps_walker_pernice(u, v):
+    nv = np.linalg.norm(v)
+    if nv == 0.0:
+        return 0.0
+    return SQRT_EPS_MACH * np.sqrt(1.0 + np.linalg.norm(u)) / nv
+
+
+def jv_fd(u, v, pr, load=1.0, eps=None, Ru=None):
+    """Finite-difference J v (Eq. JF); returns (Jv, eps)."""
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    if eps is None:
+        eps = eps_walker_pernice(u, v)
+    if eps == 0.0:
+        return np.zeros_like(v), 0.0
+    if Ru is None:
+        Ru = residual(u, pr, load).reshape(-1)
+    Rp = residual(u + eps * v, pr, load).reshape(-1)
+    return (Rp - Ru) / eps, eps
+
+
+def jv_complex_step(u, v, pr, load=1.0, h=1e-30):
+    """Exact J v by the complex step: Im R(u + i h v) / h."""
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    return residual(u + 1j * h * v, pr, load).reshape(-1).imag / h
+
+
+def brute_force_jacobian(u, pr, load=1.0, h=1e-30):
+    """Dense J, column j = complex-step J e_j (tiny meshes only)."""
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    n = u.size
+    J = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        J[:, j] = jv_complex_step(u, e, pr, load, h)
+    return J
+
+
+def approximate_jacobian_scalar(pr):
+    """Scalar matrix A with J_tilde = A (x) I_dim (cells interleaved with components)."""
+    c = pr["mat"]
+    aK = c["alpha_pc"] * c["Kbar"]
+    nc = pr["nc"]
+    P, N = pr["P"], pr["N"]
+    coef = aK * pr["magDelta"] / pr["magd"] * pr["magG"]
+    m = pr["btype"] == DISP
+    coef_b = aK * pr["magDeltab"][m] / pr["magdb"][m] * pr["magGb"][m]
+    diag = -(np.bincount(P, weights=coef, minlength=nc) + np.bincount(N, weights=coef, minlength=nc)
+             + np.bincount(pr["Pb"][m], weights=coef_b, minlength=nc))
+    rows = np.concatenate([P, N, np.arange(nc)])
+    cols = np.concatenate([N, P, np.arange(nc)])
+    vals = np.concatenate([coef, coef, diag])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nc, nc))
