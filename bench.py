@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark: Jacobian-free J.v evaluations per second at 1M cells on one MI355X.
+
+Workload: the neo-Hookean cantilever 10x1x1 m, 1000x100x10 hexes (1,000,000
+cells, 3,000,000 dofs), E = 1 MPa, nu = 0.45, clamped at x = 0, dead shear
+traction on x = 10.  State u: a large-deflection bending field (tip ~3 m,
+30% of the length) sampled at the nominal cell centres; direction v ~ N(0,1)
+(seed 30) normalised.  One step = one J.v = (R(u + eps v) - R(u))/eps with
+R(u) cached and eps from sqrt(eps_mach) sqrt(1+|u|)/|v| computed on the
+device: step-size norms, gradient pass, flux pass.  All inputs are resident
+in HBM before the timed region.
+
+Prints ONE JSON line with the metric, the roofline of the dominant kernel
+(algorithmic bytes / measured kernel time, against 8 TB/s), the oracle's
+CPU time for the same J.v (cpu_baseline), and the parity of the GPU J.v
+against the oracle.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "J·v evals/s & HBM GB/s at 1M cells; batched solves/s + p99 latency vs plain"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def nominal_centres(meta):
+    import numpy as np
+    nx, ny, nz = meta["n"]
+    Lx, Ly, Lz = meta["L"]
+    idx = np.arange(nx * ny * nz)
+    i, j, k = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    return np.stack([(i + 0.5) * Lx / nx, (j + 0.5) * Ly / ny, (k + 0.5) * Lz / nz], axis=1)
+
+
+def algorithmic_bytes(info, dim):
+    """Bytes each kernel must move once per launch with this data layout."""
+    nc, nd = info["n_cells"], info["n_dof"]
+    n_int, n_bnd, n_slots = info["n_internal_faces"], info["n_boundary_faces"], info["n_slots"]
+    n_slices = (nc + 63) // 64
+    slots = n_slots * 8 + (n_slices + 1) * 4
+    uv = 2 * nd * 8
+    xc = nc * dim * 8
+    grad = nc * dim * dim * 8
+    face = n_int * 32
+    bface = n_bnd * 80
+    return {
+        "eps": uv,
+        "gradient": uv + xc + face + slots + grad,
+        "flux": uv + xc + grad + face + bface + slots + 2 * nd * 8,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=str, default="1000,100,10", help="cells nx,ny,nz of the cantilever")
+    ap.add_argument("--law", default="neo_hookean")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    from paper_2502_17217_amd import jfnk
+
+    nx, ny, nz = (int(x) for x in args.n.split(","))
+    t = time.time()
+    cfg = mg.config_c3(nx, ny, nz)
+    m, mat = cfg["mesh"], cfg["material"]
+    mat.law = args.law
+    log("mesh %dx%dx%d generated in %.1fs" % (nx, ny, nz, time.time() - t))
+    t = time.time()
+    gm = jfnk.create_mesh(m, mat)
+    log("device mesh built in %.1fs (host setup %.0f ms, bandwidth %d)" %
+        (time.time() - t, gm.info["setup_ms"], gm.info["bandwidth"]))
+    xcn = nominal_centres(m["meta"])
+    u_ext = mg.configs.bending_field(xcn, L=10.0, tip=3.0 * nx / 1000.0 if nx < 1000 else 3.0).reshape(-1)
+    v_ext = mg.configs.random_unit_vector(gm.n_dof, 30)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    ud, vd = gm.to_internal(dev(u_ext)), gm.to_internal(dev(v_ext))
+    work = jfnk.make_workspace(gm, 0)
+    Ru = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    jfnk.residual(gm, 1.0, ud, Ru, work)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work)
+    torch.cuda.synchronize()
+    log("warmup done (%d J.v)" % args.warmup)
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    value = 1000.0 / ms_per_step
+    log("timed %d J.v: %.4f ms/step (wall %.3fs)" % (args.steps, ms_per_step, wall))
+
+    # per-kernel durations (HIP events around each kernel on the same stream)
+    jfnk.profile_enable(gm, True)
+    nprof = min(args.steps, 200)
+    for _ in range(nprof):
+        jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work)
+    prof = jfnk.profile_read(gm, reset=True)
+    jfnk.profile_enable(gm, False)
+    ab = algorithmic_bytes(gm.info, 3)
+    kern = {}
+    for name in ("eps", "gradient", "flux"):
+        ms, calls = prof[name]
+        avg = ms / max(calls, 1)
+        kern[name] = dict(avg_ms=avg, calls=calls, bytes=ab[name],
+                          gbs=ab[name] / (avg * 1e-3) / 1e9 if avg > 0 else None)
+    dom = max(("gradient", "flux"), key=lambda k: kern[k]["avg_ms"])
+    ach = kern[dom]["gbs"]
+    total_bytes = sum(ab.values())
+    log("kernels: " + json.dumps(kern))
+
+    if args.copy_mb:
+        a = torch.empty(args.copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB copied 3x" % args.copy_mb)
+
+    parity = None
+    cpu = None
+    if not (args.no_parity and args.no_cpu_baseline):
+        from threadpoolctl import threadpool_limits
+        from oracle.fv import prepare, residual
+        from oracle.jacobian import jv_fd
+        with threadpool_limits(1):
+            t = time.time()
+            pr = prepare(m, mat)
+            log("oracle geometry prepared in %.1fs" % (time.time() - t))
+            Ru_o = residual(u_ext, pr, 1.0).reshape(-1)
+            eps_g = jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work, return_eps=True)[1]
+            t = time.perf_counter()
+            Jo, eps_o = jv_fd(u_ext, v_ext, pr, 1.0, eps=None, Ru=Ru_o)
+            cpu_s = time.perf_counter() - t
+        log("oracle J.v in %.2fs" % cpu_s)
+        Jg = gm.to_external(Jv).cpu().numpy()
+        parity = dict(jv_rel_l2=float(np.linalg.norm(Jg - Jo) / np.linalg.norm(Jo)),
+                      eps_gpu=eps_g, eps_oracle=eps_o,
+                      residual_rel_inf=float(np.abs(gm.to_external(Ru).cpu().numpy() - Ru_o).max()
+                                             / np.abs(Ru_o).max()))
+        log("parity: " + json.dumps(parity))
+        if not args.no_cpu_baseline:
+            cpu = dict(value=1.0 / cpu_s, unit="J·v evals/s", cores=1, kind="oracle",
+                       sample="one FD J.v (R(u) cached, geometry precomputed and untimed) of the "
+                              "same %d-cell workload, numpy FP64, single thread" % gm.n_cells)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "J·v evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "neo-Hookean cantilever J.v, %dx%dx%d hex (%d cells, %d dofs), "
+                               "large-deflection state, auto eps" % (nx, ny, nz, gm.n_cells, gm.n_dof),
+                   "law": mat.law, "cells": gm.n_cells, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,
+                     "kernel": dom},
+        "jv_hbm_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
+        "kernels": kern,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    gm.close()
+
+
+if __name__ == "__main__":
+    main()

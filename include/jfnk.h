@@ -1,0 +1,255 @@
+/*
+ * jfnk.h -- C ABI of the MI355X (gfx950) Jacobian-free Newton-Krylov library
+ * for cell-centred finite-volume solid mechanics.
+ *
+ * The operations follow Cardiff, Armfield, Tukovic & Batistic, "A
+ * Jacobian-free Newton-Krylov method for cell-centred finite volume solid
+ * mechanics" (arXiv 2502.17217):
+ *   - mesh, cells, faces and boundary classes: Section 2.3 (cell-centred
+ *     finite volume discretisation), boundary types of Section 2.1;
+ *   - residual R(u) = 0: Section 2.2, Eq. (residual); total Lagrangian form
+ *     Appendix A, Eq. (momentum_TL); laws Appendix B;
+ *   - J v ~ (R(u + eps v) - R(u)) / eps: Section 3.2, Eq. (JF);
+ *   - right-preconditioned GMRES with the compact-stencil approximate
+ *     Jacobian as preconditioner: Section 3.2; the approximate Jacobian
+ *     itself: Section 3.1 (coefficients after Eq. SegSys);
+ *   - Newton-Raphson, Eq. (NewtonRaphson), with the convergence checks of
+ *     Section 3.3 and equal load increments.
+ *
+ * Conventions
+ *   Vectors: device pointers to FP64, interleaved [cell][component] (the
+ *   paper's blocked layout, Section 2.2) in the mesh's INTERNAL cell order,
+ *   which is a bandwidth-reducing (reverse Cuthill-McKee) renumbering of the
+ *   input cells.  jfnk_mesh_order() returns the map; jfnk_to_internal() and
+ *   jfnk_to_external() permute vectors on the device.
+ *   Ownership: the caller owns every vector and the workspace (e.g. torch
+ *   tensors).  The library owns only the mesh handle (its packed device
+ *   geometry and a few pinned host scalars), freed by jfnk_destroy_mesh().
+ *   It never frees caller memory.
+ *   Streams: `stream` is a hipStream_t (NULL = default stream).  jfnk_residual,
+ *   jfnk_jv and the permutations only enqueue work; solvers synchronise the
+ *   stream to read convergence scalars and return when finished.
+ *   Errors: every call returns a jfnk_status; no C++ exception crosses the
+ *   ABI.  jfnk_last_error() gives a thread-local message for the last
+ *   failing call on this thread.  A call that fails with JFNK_E_ARG or
+ *   JFNK_E_MESH enqueues no device work.
+ *   Sign convention: R is the out-of-balance force of Eq. (residual); its
+ *   Jacobian is negative (semi-)definite for small strains, like J_tilde.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JFNK_OK = 0,
+  JFNK_E_ARG = -1,            /* invalid argument (null pointer, bad size, bad option) */
+  JFNK_E_MESH = -2,           /* invalid mesh: index out of range, open cell, d.n <= 0, singular G_P */
+  JFNK_E_OOM = -3,            /* device or pinned host allocation failed */
+  JFNK_E_HIP = -4,            /* HIP runtime error */
+  JFNK_E_NOT_CONVERGED = -5,  /* iteration limit reached; outputs hold the last iterate */
+  JFNK_E_DIVERGED = -6,       /* residual grew beyond the divergence limit */
+  JFNK_E_NAN = -7,            /* NaN/Inf in a residual or Krylov quantity */
+  JFNK_E_BREAKDOWN = -8,      /* Krylov stagnation: no progress over a restart cycle */
+  JFNK_E_BUSY = -9            /* server: no capacity for the request right now */
+} jfnk_status;
+
+/* Boundary classes of Section 2.3: prescribed displacement, prescribed
+ * traction; a pressure patch is a traction -p n on the undeformed face
+ * (dead load).  Symmetry planes are not supported. */
+typedef enum {
+  JFNK_BC_DISPLACEMENT = 1,
+  JFNK_BC_TRACTION = 2,
+  JFNK_BC_PRESSURE = 3
+} jfnk_bc_type;
+
+/* One boundary patch: faces [start, start + size) of the face list.
+ * value: displacement vector, traction vector, or value[0] = pressure.
+ * per_face: NULL, or host array [size][dim] overriding value face by face.
+ * Every prescribed value is multiplied by the current load factor. */
+typedef struct {
+  int32_t type;
+  int64_t start;
+  int64_t size;
+  double value[3];
+  const double* per_face;
+} jfnk_patch;
+
+/* Polyhedral mesh, OpenFOAM conventions (Section 2.3, Figure of cell P):
+ * internal faces first; face f has vertices face_pts[face_ptr[f] ..
+ * face_ptr[f+1]) ordered so that the right-hand normal points out of
+ * owner[f]; 2-D (plane strain, unit depth) faces are edges p0 -> p1 whose
+ * outward side is on the right.  All arrays are host memory and are only
+ * read during jfnk_create_mesh. */
+typedef struct {
+  int32_t dim;                 /* 2 or 3 */
+  int64_t n_points;
+  const double* points;        /* [n_points][dim] */
+  int64_t n_cells;
+  int64_t n_faces;
+  int64_t n_internal;
+  const int64_t* face_ptr;     /* [n_faces + 1] */
+  const int32_t* face_pts;     /* [face_ptr[n_faces]] */
+  const int32_t* owner;        /* [n_faces] */
+  const int32_t* neighbour;    /* [n_internal] */
+  int32_t n_patches;
+  const jfnk_patch* patches;   /* must cover faces [n_internal, n_faces) exactly */
+} jfnk_mesh_desc;
+
+typedef enum { JFNK_LINEAR_ELASTIC = 0, JFNK_NEO_HOOKEAN = 1 } jfnk_law;
+
+/* Appendix B laws.  alpha_rc scales the Rhie-Chow term of the residual
+ * (Eq. RhieChow); alpha_pc scales the approximate Jacobian used for
+ * preconditioning (unity in the paper, Section 3.1). */
+typedef struct {
+  int32_t law;
+  double E;
+  double nu;
+  double alpha_rc;
+  double alpha_pc;
+} jfnk_material;
+
+typedef struct jfnk_mesh jfnk_mesh;
+
+typedef struct {
+  int64_t n_cells;
+  int32_t dim;
+  int64_t n_dof;               /* n_cells * dim */
+  int64_t n_internal_faces;
+  int64_t n_boundary_faces;
+  int64_t bandwidth;           /* max |P - N| over internal faces after renumbering */
+  int64_t device_bytes;        /* device memory owned by the handle */
+  double setup_ms;             /* host time spent in jfnk_create_mesh */
+  int64_t n_slots;             /* cell-face slots in the packed slot map (incl. padding) */
+} jfnk_mesh_info;
+
+/* Build the mesh handle: validates the mesh, renumbers cells, computes the
+ * geometry of Section 2.3 in FP64 on the host (face area vectors and
+ * centroids by fan triangulation, cell volumes and centroids by pyramids,
+ * interpolation weights of Eq. stressInterp) and uploads packed arrays.
+ * Errors: JFNK_E_ARG (null/inconsistent sizes), JFNK_E_MESH (see above, the
+ * message names the offending cell or face), JFNK_E_OOM, JFNK_E_HIP. */
+jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat,
+                             void* stream, jfnk_mesh** out);
+jfnk_status jfnk_destroy_mesh(jfnk_mesh* mesh);
+
+/* Host-only dry run of jfnk_create_mesh: the same validation and
+ * preprocessing, no device work.  Fills *info (device_bytes is what the
+ * handle would allocate); if non-NULL, xc_out [n_cells][dim] and vol_out
+ * [n_cells] receive the cell centroids and volumes in INPUT cell order.
+ * Used for admission control (memory footprint) and host-side checks. */
+jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat,
+                              jfnk_mesh_info* info, double* xc_out, double* vol_out);
+jfnk_status jfnk_get_mesh_info(const jfnk_mesh* mesh, jfnk_mesh_info* info);
+
+/* old_of_new[i] = input cell index of internal cell i (host array [n_cells]). */
+jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new);
+/* d_out[internal order] <- d_in[input order], and the inverse; [n_cells][dim] FP64. */
+jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
+jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
+
+/* Workspace bytes for jfnk_residual / jfnk_jv (op = 0) or for jfnk_gmres and
+ * jfnk_newton_solve with the given restart length and preconditioner
+ * (op = 1).  The caller allocates at least that many bytes of device memory,
+ * 256-byte aligned, and passes it as d_work. */
+jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t restart,
+                                int32_t precond, size_t* bytes);
+
+/* R(u) of Eq. (residual) (static, no body force) at load factor `load`.
+ * d_u, d_R: [n_cells][dim]; d_R may not alias d_u.  Asynchronous. */
+jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, double* d_R,
+                          void* d_work, void* stream);
+
+/* J v ~ (R(u + eps v) - R(u)) / eps (Eq. JF) using the cached d_Ru = R(u)
+ * (if d_Ru is NULL it is computed first, into the workspace).
+ * eps > 0 is used as given; eps <= 0 selects
+ *   eps = sqrt(eps_mach) * sqrt(1 + ||u||_2) / ||v||_2
+ * computed on the device (a zero v gives J v = 0).
+ * If eps_used is non-NULL (host pointer) the call synchronises the stream
+ * and stores the eps used; otherwise it is fully asynchronous. */
+jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
+                    const double* d_v, double eps, double* d_Jv, double* eps_used,
+                    void* d_work, void* stream);
+
+typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2 } jfnk_precond;
+
+/* GMRES options (Section 3.2; restarted, right preconditioned, classical
+ * Gram-Schmidt applied twice).  The run stops when the true residual
+ * |b - J x| <= max(rtol |b|, atol), after max_it Arnoldi steps, or on
+ * stagnation.  precond: J_tilde (alpha_pc) as diagonal (Jacobi, FP64) or
+ * as an FP32 aggregation-AMG V-cycle with Chebyshev smoothing (flexible
+ * GMRES).  eps <= 0 selects the automatic J v step. */
+typedef struct {
+  int32_t restart;
+  int32_t max_it;
+  double rtol;
+  double atol;
+  int32_t precond;
+  int32_t cheb_degree;
+  double eps;
+} jfnk_gmres_opts;
+
+/* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
+ * k = 1..n_increments the loads are scaled by k/n_increments; iterate until
+ * |R(u)| <= max(rtol |R(u_0)|, atol); each linear solve uses relative
+ * tolerance eta. */
+typedef struct {
+  int32_t n_increments;
+  int32_t max_newton_it;
+  double rtol;
+  double atol;
+  double eta;
+  jfnk_gmres_opts gmres;
+} jfnk_newton_opts;
+
+typedef struct {
+  int32_t newton_it;           /* total Newton iterations */
+  int32_t gmres_it;            /* total Arnoldi steps */
+  int32_t restarts;            /* GMRES restart cycles */
+  int32_t jv_evals;
+  double res0;                 /* |R| at the start of the last increment (Newton) or |b| (GMRES) */
+  double res_final;            /* final |R| (Newton) or true |b - J x| (GMRES) */
+  double eps_last;             /* last J v step used */
+  double t_ms[8];              /* phase times: 0 total, 1 J.v, 2 orthogonalisation, 3 preconditioner,
+                                  4 residual, 5 setup, 6 host control, 7 reserved */
+} jfnk_stats;
+
+/* Solve J(u) x = b with J v from Eq. (JF) at state d_u (load factor `load`,
+ * cached d_Ru = R(u), required).  d_x holds the initial guess on entry and
+ * the solution on return.  Returns JFNK_OK, JFNK_E_NOT_CONVERGED,
+ * JFNK_E_BREAKDOWN or JFNK_E_NAN (d_x then holds the last iterate). */
+jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
+                       const double* d_b, double* d_x, const jfnk_gmres_opts* opts,
+                       jfnk_stats* stats, void* d_work, void* stream);
+
+/* Newton-Raphson with load increments; d_u holds the initial guess on entry
+ * and the final iterate on return. */
+jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, double* d_u,
+                              jfnk_stats* stats, void* d_work, void* stream);
+
+/* Kernel timing for measurement tools.  While enabled, every residual / J v
+ * evaluation on this mesh records HIP events around each of its kernels on
+ * the caller's stream.  jfnk_profile_read() waits for the recorded events and
+ * returns accumulated milliseconds and launch counts per kernel class:
+ * [0] step-size norms, [1] gradient pass, [2] flux/divergence pass,
+ * [3] preconditioner, then optionally resets.  Not for concurrent callers. */
+jfnk_status jfnk_profile_enable(jfnk_mesh* mesh, int32_t on);
+jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms /*[4]*/, int64_t* calls /*[4]*/,
+                              int32_t reset);
+
+/* Thread-local message describing the last non-OK status on this thread. */
+const char* jfnk_last_error(void);
+
+/* Library version string. */
+const char* jfnk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JFNK_H */

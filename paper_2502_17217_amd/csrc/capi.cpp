@@ -1,0 +1,494 @@
+// The C ABI of the library (include/jfnk.h): argument checking, error
+// translation, mesh upload, and the Newton driver.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "solver.h"
+
+namespace jfnk {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+jfnk_status guarded(F&& f) {
+  try {
+    f();
+    return JFNK_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return JFNK_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return JFNK_E_ARG;
+  }
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  b.alloc(std::max<size_t>(v.size() * sizeof(T), 256));
+  if (!v.empty())
+    JFNK_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+size_t device_bytes_of(const HostMesh& h) {
+  auto b = [](size_t x) { return std::max<size_t>(x, 256); };
+  return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
+         b(h.xc.size() * 8) + b(h.face.size() * 8) + b(h.bface.size() * 8) +
+         b(h.old_of_new.size() * 4) + b(size_t(h.n_cells) * 8);
+}
+
+void check_mesh(const jfnk_mesh* m) {
+  JFNK_REQUIRE(m != nullptr, JFNK_E_ARG, "null mesh handle");
+}
+
+void check_ptr(const void* p, const char* what) {
+  JFNK_REQUIRE(p != nullptr, JFNK_E_ARG, std::string("null device pointer: ") + what);
+}
+
+void check_work(const void* w) {
+  JFNK_REQUIRE(w != nullptr, JFNK_E_ARG, "null workspace");
+  JFNK_REQUIRE((reinterpret_cast<uintptr_t>(w) & 255) == 0, JFNK_E_ARG,
+               "workspace must be 256-byte aligned");
+}
+
+void check_opts(const jfnk_gmres_opts& o) {
+  JFNK_REQUIRE(o.restart >= 1 && o.restart < kMaxBasis, JFNK_E_ARG, "gmres: restart out of range");
+  JFNK_REQUIRE(o.max_it >= 1, JFNK_E_ARG, "gmres: max_it must be >= 1");
+  JFNK_REQUIRE(o.rtol >= 0 && o.atol >= 0, JFNK_E_ARG, "gmres: negative tolerance");
+  JFNK_REQUIRE(o.precond >= JFNK_PC_NONE && o.precond <= JFNK_PC_AMG32, JFNK_E_ARG,
+               "gmres: unknown preconditioner");
+  JFNK_REQUIRE(o.precond != JFNK_PC_AMG32 || (o.cheb_degree >= 1 && o.cheb_degree <= 16), JFNK_E_ARG,
+               "gmres: cheb_degree must lie in [1, 16]");
+}
+
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  JFNK_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int Profiler::begin(int cls, hipStream_t s) {
+  Rec r{get(), get(), cls};
+  JFNK_HIP(hipEventRecord(r.a, s));
+  pending.push_back(r);
+  return int(pending.size()) - 1;
+}
+
+void Profiler::end(int idx, hipStream_t s) { JFNK_HIP(hipEventRecord(pending[idx].b, s)); }
+
+void Profiler::collect() {
+  for (Rec& r : pending) {
+    JFNK_HIP(hipEventSynchronize(r.b));
+    float t = 0;
+    JFNK_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    calls[r.cls] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (Rec& r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+void DevBuf::alloc(size_t b) {
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+  }
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    throw Error{JFNK_E_OOM, "device allocation of " + std::to_string(b) + " bytes failed"};
+  }
+  bytes = b;
+}
+
+}  // namespace jfnk
+
+using namespace jfnk;
+
+extern "C" {
+
+const char* jfnk_last_error(void) { return g_last_error.c_str(); }
+
+const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
+
+jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat, void* stream,
+                             jfnk_mesh** out) {
+  return guarded([&] {
+    JFNK_REQUIRE(desc && mat && out, JFNK_E_ARG, "create_mesh: null argument");
+    *out = nullptr;
+    const double t0 = now_ms();
+    auto m = std::make_unique<jfnk_mesh>();
+    m->mat = make_material(*mat);
+    build_host_mesh(*desc, m->mat, m->host);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const HostMesh& h = m->host;
+    upload(m->b_slice_ptr, h.slice_ptr, s);
+    upload(m->b_slot_nb, h.slot_nb, s);
+    upload(m->b_slot_fc, h.slot_fc, s);
+    upload(m->b_xc, h.xc, s);
+    upload(m->b_face, h.face, s);
+    upload(m->b_bface, h.bface, s);
+    upload(m->b_order, h.old_of_new, s);
+    std::vector<double> dinv(h.n_cells);
+    for (int64_t c = 0; c < h.n_cells; ++c) dinv[c] = 1.0 / h.pc_diag[c];
+    upload(m->b_pc_dinv, dinv, s);
+    JFNK_HIP(hipStreamSynchronize(s));
+    JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m->pinned), sizeof(double) * 4 * kMaxBasis,
+                           hipHostMallocDefault));
+    MeshDev& d = m->dev;
+    d.n_cells = int32_t(h.n_cells);
+    d.dim = h.dim;
+    d.n_slices = int32_t(h.slice_ptr.size() - 1);
+    d.law = m->mat.law;
+    d.slice_ptr = m->b_slice_ptr.as<int32_t>();
+    d.slot_nb = m->b_slot_nb.as<int32_t>();
+    d.slot_fc = m->b_slot_fc.as<int32_t>();
+    d.xc = m->b_xc.as<double>();
+    d.face = m->b_face.as<double>();
+    d.bface = m->b_bface.as<double>();
+    d.mu = m->mat.mu;
+    d.lam = m->mat.lam;
+    d.kappa = m->mat.kappa;
+    d.aK = m->mat.alpha_rc * m->mat.Kbar;
+    jfnk_mesh_info& in = m->info;
+    in.n_cells = h.n_cells;
+    in.dim = h.dim;
+    in.n_dof = h.n_cells * h.dim;
+    in.n_internal_faces = h.n_int;
+    in.n_boundary_faces = h.n_bnd;
+    in.bandwidth = h.bandwidth;
+    in.device_bytes = int64_t(m->b_slice_ptr.bytes + m->b_slot_nb.bytes + m->b_slot_fc.bytes +
+                              m->b_xc.bytes + m->b_face.bytes + m->b_bface.bytes + m->b_order.bytes +
+                              m->b_pc_dinv.bytes);
+    in.n_slots = int64_t(h.slot_nb.size());
+    in.setup_ms = now_ms() - t0;
+    *out = m.release();
+  });
+}
+
+jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat,
+                              jfnk_mesh_info* info, double* xc_out, double* vol_out) {
+  return guarded([&] {
+    JFNK_REQUIRE(desc && mat && info, JFNK_E_ARG, "inspect_mesh: null argument");
+    const double t0 = now_ms();
+    Material mt = make_material(*mat);
+    HostMesh h;
+    build_host_mesh(*desc, mt, h);
+    std::memset(info, 0, sizeof(*info));
+    info->n_cells = h.n_cells;
+    info->dim = h.dim;
+    info->n_dof = h.n_cells * h.dim;
+    info->n_internal_faces = h.n_int;
+    info->n_boundary_faces = h.n_bnd;
+    info->bandwidth = h.bandwidth;
+    info->device_bytes = int64_t(device_bytes_of(h));
+    info->setup_ms = now_ms() - t0;
+    info->n_slots = int64_t(h.slot_nb.size());
+    for (int64_t i = 0; i < h.n_cells; ++i) {
+      const int64_t o = h.old_of_new[i];
+      if (xc_out)
+        for (int k = 0; k < h.dim; ++k) xc_out[o * h.dim + k] = h.xc[i * h.dim + k];
+      if (vol_out) vol_out[o] = h.vol[i];
+    }
+  });
+}
+
+jfnk_status jfnk_destroy_mesh(jfnk_mesh* mesh) {
+  return guarded([&] {
+    if (!mesh) return;
+    if (mesh->amg) amg_destroy(mesh->amg);
+    if (mesh->pinned) (void)hipHostFree(mesh->pinned);
+    delete mesh;
+  });
+}
+
+jfnk_status jfnk_profile_enable(jfnk_mesh* mesh, int32_t on) {
+  return guarded([&] {
+    check_mesh(mesh);
+    mesh->prof.on = on != 0;
+  });
+}
+
+jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms, int64_t* calls, int32_t reset) {
+  return guarded([&] {
+    check_mesh(mesh);
+    mesh->prof.collect();
+    for (int k = 0; k < 4; ++k) {
+      if (ms) ms[k] = mesh->prof.ms[k];
+      if (calls) calls[k] = mesh->prof.calls[k];
+      if (reset) {
+        mesh->prof.ms[k] = 0;
+        mesh->prof.calls[k] = 0;
+      }
+    }
+  });
+}
+
+jfnk_status jfnk_get_mesh_info(const jfnk_mesh* mesh, jfnk_mesh_info* info) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(info, JFNK_E_ARG, "null info");
+    *info = mesh->info;
+  });
+}
+
+jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(old_of_new, JFNK_E_ARG, "null output");
+    std::memcpy(old_of_new, mesh->host.old_of_new.data(), sizeof(int32_t) * mesh->host.n_cells);
+  });
+}
+
+jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_in, "in");
+    check_ptr(d_out, "out");
+    JFNK_REQUIRE(d_in != d_out, JFNK_E_ARG, "permutation cannot run in place");
+    launch_permute(mesh->b_order.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, true,
+                   static_cast<hipStream_t>(stream));
+  });
+}
+
+jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_in, "in");
+    check_ptr(d_out, "out");
+    JFNK_REQUIRE(d_in != d_out, JFNK_E_ARG, "permutation cannot run in place");
+    launch_permute(mesh->b_order.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, false,
+                   static_cast<hipStream_t>(stream));
+  });
+}
+
+jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t restart, int32_t precond,
+                                size_t* bytes) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(bytes, JFNK_E_ARG, "null output");
+    JFNK_REQUIRE(op == 0 || op == 1, JFNK_E_ARG, "workspace_size: op must be 0 or 1");
+    Carver c(nullptr);
+    FvWork fw;
+    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    if (op == 1) {
+      JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
+      JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG32, JFNK_E_ARG,
+                   "workspace_size: unknown preconditioner");
+      KrylovWork kw;
+      kw.carve(c, mesh->host.n_cells * mesh->host.dim, restart, precond_work_floats(mesh, precond));
+    }
+    *bytes = c.off;
+  });
+}
+
+jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, double* d_R, void* d_work,
+                          void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_ptr(d_R, "R");
+    check_work(d_work);
+    JFNK_REQUIRE(d_u != d_R, JFNK_E_ARG, "residual: R may not alias u");
+    JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "residual: load factor not finite");
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    residual_into(mesh, load, d_u, d_R, fw, static_cast<hipStream_t>(stream));
+  });
+}
+
+jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
+                    const double* d_v, double eps, double* d_Jv, double* eps_used, void* d_work,
+                    void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_ptr(d_v, "v");
+    check_ptr(d_Jv, "Jv");
+    check_work(d_work);
+    JFNK_REQUIRE(d_Jv != d_u && d_Jv != d_v && d_Jv != d_Ru, JFNK_E_ARG, "jv: output aliases an input");
+    JFNK_REQUIRE(std::isfinite(eps) && std::isfinite(load), JFNK_E_ARG, "jv: eps/load not finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    const double* Ru = d_Ru;
+    if (!Ru) {
+      residual_into(mesh, load, d_u, fw.ru, fw, s);
+      Ru = fw.ru;
+    }
+    jv_into(mesh, load, d_u, Ru, d_v, eps, d_Jv, fw, s);
+    if (eps_used) {
+      JFNK_HIP(hipMemcpyAsync(mesh->pinned, fw.scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipStreamSynchronize(s));
+      *eps_used = mesh->pinned[0];
+    }
+  });
+}
+
+jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
+                       const double* d_b, double* d_x, const jfnk_gmres_opts* opts, jfnk_stats* stats,
+                       void* d_work, void* stream) {
+  jfnk_status st = JFNK_OK;
+  jfnk_status g = guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_ptr(d_Ru, "Ru");
+    check_ptr(d_b, "b");
+    check_ptr(d_x, "x");
+    check_work(d_work);
+    JFNK_REQUIRE(opts, JFNK_E_ARG, "gmres: null options");
+    check_opts(*opts);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    KrylovWork kw;
+    kw.carve(c, mesh->host.n_cells * mesh->host.dim, opts->restart,
+             precond_work_floats(mesh, opts->precond));
+    precond_setup(mesh, opts->precond, s);
+    double t_ms[8] = {0};
+    GmresResult r = gmres_solve(mesh, load, d_u, d_Ru, d_b, d_x, false, *opts, fw, kw, s, t_ms);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->gmres_it = r.iterations;
+      stats->restarts = r.restarts;
+      stats->jv_evals = r.jv;
+      stats->res0 = r.bnorm;
+      stats->res_final = r.res_true;
+      std::memcpy(stats->t_ms, t_ms, sizeof(t_ms));
+    }
+    st = r.status;
+    if (st == JFNK_E_NOT_CONVERGED) set_last_error("gmres: iteration limit reached");
+    if (st == JFNK_E_BREAKDOWN) set_last_error("gmres: stagnation (true residual not decreasing)");
+    if (st == JFNK_E_NAN) set_last_error("gmres: NaN/Inf encountered");
+  });
+  return g != JFNK_OK ? g : st;
+}
+
+jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, double* d_u,
+                              jfnk_stats* stats, void* d_work, void* stream) {
+  jfnk_status st = JFNK_OK;
+  jfnk_status g = guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_work(d_work);
+    JFNK_REQUIRE(opts, JFNK_E_ARG, "newton: null options");
+    JFNK_REQUIRE(opts->n_increments >= 1 && opts->max_newton_it >= 1, JFNK_E_ARG,
+                 "newton: n_increments and max_newton_it must be >= 1");
+    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0, JFNK_E_ARG,
+                 "newton: bad tolerance");
+    check_opts(opts->gmres);
+    const double t0 = now_ms();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = mesh->host.n_cells * mesh->host.dim;
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    KrylovWork kw;
+    kw.carve(c, n, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    const double ts = now_ms();
+    precond_setup(mesh, opts->gmres.precond, s);
+    double t_ms[8] = {0};
+    t_ms[5] = now_ms() - ts;
+    jfnk_gmres_opts go = opts->gmres;
+    go.rtol = opts->eta;
+    go.atol = 0.0;
+    jfnk_stats sl{};
+    auto norm = [&](const double* x) {
+      blas_mdot(x, 0, 1, x, n, fw.partials, kw.h + kMaxBasis, false, s);
+      JFNK_HIP(hipMemcpyAsync(mesh->pinned, kw.h + kMaxBasis, sizeof(double), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipStreamSynchronize(s));
+      return std::sqrt(mesh->pinned[0]);
+    };
+    for (int inc = 1; inc <= opts->n_increments && st == JFNK_OK; ++inc) {
+      const double load = double(inc) / opts->n_increments;
+      residual_into(mesh, load, d_u, kw.R, fw, s);
+      const double r0 = norm(kw.R);
+      JFNK_REQUIRE(std::isfinite(r0), JFNK_E_NAN, "newton: initial residual not finite");
+      sl.res0 = r0;
+      double rn = r0;
+      int it = 0;
+      while (true) {
+        if (!std::isfinite(rn)) {
+          st = JFNK_E_NAN;
+          set_last_error("newton: residual became NaN/Inf");
+          break;
+        }
+        if (rn <= std::max(opts->rtol * r0, opts->atol)) break;
+        if (it >= opts->max_newton_it) {
+          st = JFNK_E_NOT_CONVERGED;
+          set_last_error("newton: iteration limit reached in increment " + std::to_string(inc));
+          break;
+        }
+        if (rn > 1e8 * std::max(r0, 1e-300)) {
+          st = JFNK_E_DIVERGED;
+          set_last_error("newton: residual diverged in increment " + std::to_string(inc));
+          break;
+        }
+        blas_lincomb(-1.0, kw.R, 0.0, kw.R, kw.b, n, s);
+        JFNK_HIP(hipMemsetAsync(kw.du, 0, sizeof(double) * n, s));
+        GmresResult r = gmres_solve(mesh, load, d_u, kw.R, kw.b, kw.du, true, go, fw, kw, s, t_ms);
+        sl.gmres_it += r.iterations;
+        sl.restarts += r.restarts;
+        sl.jv_evals += r.jv;
+        if (r.status == JFNK_E_NAN) {
+          st = JFNK_E_NAN;
+          set_last_error("newton: NaN/Inf in the linear solve");
+          break;
+        }
+        blas_axpby(1.0, kw.du, 1.0, d_u, n, s);
+        residual_into(mesh, load, d_u, kw.R, fw, s);
+        rn = norm(kw.R);
+        ++it;
+        sl.newton_it++;
+      }
+      sl.res_final = rn;
+    }
+    t_ms[0] = now_ms() - t0;
+    if (stats) {
+      sl.eps_last = 0;
+      std::memcpy(sl.t_ms, t_ms, sizeof(t_ms));
+      *stats = sl;
+    }
+  });
+  return g != JFNK_OK ? g : st;
+}
+
+}  // extern "C"

@@ -1,0 +1,398 @@
+// Residual and Jacobian-free J.v kernels for gfx950.
+//
+// Two passes over the cells, one lane per cell, gather-only (no atomics):
+//   k_gradient: least-squares gradient of w = u + eps v (Eq. leastSquaresGrad,
+//               weights omega_f = |Gamma_f| in both the sum and G_P).  G_P is
+//               rebuilt from the cell centroids and face areas on the fly, so
+//               no per-slot least-squares vectors are stored:
+//               grad w_P = G_P^{-1} sum_f |Gamma|/(d.d) d (x) (w_N - w_P).
+//   k_flux:     face forces (Eq. divStressDiscret) + Rhie-Chow stabilisation
+//               (Eq. RhieChow) summed over the cell's faces in a fixed slot
+//               order, then either R(w) or (R(w) - R(u))/eps (Eq. JF).
+// Every internal face is evaluated from identical operands in owner
+// orientation by both adjacent cells (operand selection, one code path), so
+// the two contributions are exact negatives and the sum telescopes.
+//
+// Rhie-Chow, written in the jump form of Appendix D:
+//   alpha K_bar [ |Delta| (w_N - w_P)/|d| - Delta . grad w_f ] |Gamma|
+//     = alpha K_bar |Gamma|^2 / (d . Gamma) [ (w_N - w_P) - d . grad w_f ],
+// since Delta = d/(d.n), |Delta|/|d| = 1/(d.n) and n = Gamma/|Gamma|.
+//
+// Neo-Hookean total-Lagrangian face force (Appendix A/B): with a = cof(F) Gamma
+// and F^T a = J Gamma, (a . sigma) simplifies to
+//   mu J^{-2/3} F Gamma + [ kappa/2 (J - 1/J) - mu/3 J^{-5/3} tr(F F^T) ] a.
+#include "internal.h"
+
+namespace jfnk {
+
+namespace {
+
+__device__ __forceinline__ int xcd_block(int bid, int nb_launch) {
+  // Hardware hands consecutive workgroup ids to the 8 XCDs round-robin;
+  // give each XCD one contiguous range of cell blocks so that neighbouring
+  // cells (close in the bandwidth-reduced order) share an L2.
+  const int per = nb_launch / kNumXcd;
+  return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+template <int D>
+__device__ __forceinline__ void load_w(const double* __restrict__ u, const double* __restrict__ v,
+                                       double eps, int c, double (&w)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double uk = u[size_t(c) * D + k];
+    w[k] = v ? fma(eps, v[size_t(c) * D + k], uk) : uk;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void load_xc(const double* __restrict__ xc, int c, double (&x)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[k] = xc[size_t(c) * D + k];
+}
+
+template <int D>
+__device__ __forceinline__ void load_grad(const double* __restrict__ g, int c, double (&o)[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) o[i][j] = g[size_t(c) * D * D + i * D + j];
+}
+
+template <int D>
+__device__ __forceinline__ void load_gamma_w(const double* __restrict__ face, int f, double (&G)[D],
+                                             double& wf) {
+  const double2* r = reinterpret_cast<const double2*>(face + size_t(f) * kFaceRec);
+  const double2 a = r[0], b = r[1];
+  if constexpr (D == 3) {
+    G[0] = a.x; G[1] = a.y; G[2] = b.x; wf = b.y;
+  } else {
+    G[0] = a.x; G[1] = a.y; wf = b.x;
+  }
+}
+
+// ---------------------------------------------------------------- laws
+template <int D>
+__device__ __forceinline__ void traction_le(const MeshDev& m, const double (&g)[D][D],
+                                            const double (&G)[D], double (&t)[D]) {
+  double tr = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) tr += g[k][k];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) s = fma(G[i], g[i][j] + g[j][i], s);
+    t[j] = fma(m.mu, s, m.lam * tr * G[j]);
+  }
+}
+
+__device__ __forceinline__ void traction_nh3(const MeshDev& m, const double (&g)[3][3],
+                                             const double (&G)[3], double (&t)[3]) {
+  double F[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) F[a][b] = (a == b ? 1.0 : 0.0) + g[b][a];
+  double C[3][3];
+  C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  const double J = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+  double trb = 0, a[3], FG[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    a[i] = C[i][0] * G[0] + C[i][1] * G[1] + C[i][2] * G[2];
+    FG[i] = F[i][0] * G[0] + F[i][1] * G[1] + F[i][2] * G[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) trb = fma(F[i][k], F[i][k], trb);
+  }
+  const double cj = cbrt(J);
+  const double Jm23 = 1.0 / (cj * cj);
+  const double invJ = 1.0 / J;
+  const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
+  const double cf = m.mu * Jm23;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] = fma(cf, FG[i], ca * a[i]);
+}
+
+__device__ __forceinline__ void traction_nh2(const MeshDev& m, const double (&g)[2][2],
+                                             const double (&G)[2], double (&t)[2]) {
+  // plane strain: F_zz = 1, out-of-plane terms vanish for an in-plane Gamma
+  const double F00 = 1.0 + g[0][0], F01 = g[1][0], F10 = g[0][1], F11 = 1.0 + g[1][1];
+  const double J = F00 * F11 - F01 * F10;
+  const double a0 = F11 * G[0] - F10 * G[1];
+  const double a1 = -F01 * G[0] + F00 * G[1];
+  const double FG0 = F00 * G[0] + F01 * G[1];
+  const double FG1 = F10 * G[0] + F11 * G[1];
+  const double trb = F00 * F00 + F01 * F01 + F10 * F10 + F11 * F11 + 1.0;
+  const double cj = cbrt(J);
+  const double Jm23 = 1.0 / (cj * cj);
+  const double invJ = 1.0 / J;
+  const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
+  const double cf = m.mu * Jm23;
+  t[0] = fma(cf, FG0, ca * a0);
+  t[1] = fma(cf, FG1, ca * a1);
+}
+
+template <int D, int LAW>
+__device__ __forceinline__ void traction(const MeshDev& m, const double (&g)[D][D],
+                                         const double (&G)[D], double (&t)[D]) {
+  if constexpr (LAW == JFNK_LINEAR_ELASTIC) {
+    traction_le<D>(m, g, G, t);
+  } else if constexpr (D == 3) {
+    traction_nh3(m, g, G, t);
+  } else {
+    traction_nh2(m, g, G, t);
+  }
+}
+
+// Force on the owner side of an internal face (owner A, neighbour B).
+template <int D, int LAW>
+__device__ __forceinline__ void internal_face_force(const MeshDev& m, const double (&G)[D], double wf,
+                                                    const double (&xA)[D], const double (&xB)[D],
+                                                    const double (&wA)[D], const double (&wB)[D],
+                                                    const double (&gA)[D][D], const double (&gB)[D][D],
+                                                    double (&f)[D]) {
+  double gf[D][D];
+  const double wb = 1.0 - wf;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) gf[i][j] = fma(wf, gA[i][j], wb * gB[i][j]);
+  traction<D, LAW>(m, gf, G, f);
+  double d[D], dG = 0, GG = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    d[k] = xB[k] - xA[k];
+    dG = fma(d[k], G[k], dG);
+    GG = fma(G[k], G[k], GG);
+  }
+  const double coef = m.aK * GG / dG;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double dg = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) dg = fma(d[i], gf[i][j], dg);
+    f[j] = fma(coef, (wB[j] - wA[j]) - dg, f[j]);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gradient(MeshDev m, const double* __restrict__ u,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ d_eps,
+                                                     double* __restrict__ grad, int nb_real) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= nb_real) return;
+  const int c = lb * kBlock + threadIdx.x;
+  if (c >= m.n_cells) return;
+  const double eps = (v != nullptr) ? *d_eps : 0.0;
+  double wP[D], xP[D];
+  load_w<D>(u, v, eps, c, wP);
+  load_xc<D>(m.xc, c, xP);
+  double Gs[D][D], M[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) Gs[i][j] = M[i][j] = 0.0;
+  const int slice = c / kSlice, lane = c % kSlice;
+  const int s0 = m.slice_ptr[slice];
+  const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
+  for (int k = 0; k < width; ++k) {
+    const int idx = s0 + k * kSlice + lane;
+    const int nb = m.slot_nb[idx];
+    if (nb < 0) continue;
+    int f = m.slot_fc[idx];
+    f = f >= 0 ? f : ~f;
+    double G[D], wf;
+    load_gamma_w<D>(m.face, f, G, wf);
+    double xN[D], wN[D];
+    load_xc<D>(m.xc, nb, xN);
+    load_w<D>(u, v, eps, nb, wN);
+    double d[D], dd = 0, GG = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      d[q] = xN[q] - xP[q];
+      dd = fma(d[q], d[q], dd);
+      GG = fma(G[q], G[q], GG);
+    }
+    const double wt = sqrt(GG) / dd;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double wd = wt * d[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        Gs[i][j] = fma(wd, d[j], Gs[i][j]);
+        M[i][j] = fma(wd, wN[j] - wP[j], M[i][j]);
+      }
+    }
+  }
+  double out[D][D];
+  if constexpr (D == 3) {
+    const double a00 = Gs[1][1] * Gs[2][2] - Gs[1][2] * Gs[1][2];
+    const double a01 = Gs[0][2] * Gs[1][2] - Gs[0][1] * Gs[2][2];
+    const double a02 = Gs[0][1] * Gs[1][2] - Gs[0][2] * Gs[1][1];
+    const double a11 = Gs[0][0] * Gs[2][2] - Gs[0][2] * Gs[0][2];
+    const double a12 = Gs[0][1] * Gs[0][2] - Gs[0][0] * Gs[1][2];
+    const double a22 = Gs[0][0] * Gs[1][1] - Gs[0][1] * Gs[0][1];
+    const double inv = 1.0 / (Gs[0][0] * a00 + Gs[0][1] * a01 + Gs[0][2] * a02);
+    const double A[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        out[i][j] = (A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]) * inv;
+  } else {
+    const double inv = 1.0 / (Gs[0][0] * Gs[1][1] - Gs[0][1] * Gs[0][1]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      out[0][j] = (Gs[1][1] * M[0][j] - Gs[0][1] * M[1][j]) * inv;
+      out[1][j] = (-Gs[0][1] * M[0][j] + Gs[0][0] * M[1][j]) * inv;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) grad[size_t(c) * D * D + i * D + j] = out[i][j];
+}
+
+template <int D, int LAW>
+__global__ __launch_bounds__(kBlock) void k_flux(MeshDev m, const double* __restrict__ u,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ d_eps,
+                                                 const double* __restrict__ grad,
+                                                 const double* __restrict__ Ru,
+                                                 double* __restrict__ out, double load, int nb_real) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= nb_real) return;
+  const int c = lb * kBlock + threadIdx.x;
+  if (c >= m.n_cells) return;
+  const double eps = (v != nullptr) ? *d_eps : 0.0;
+  double wP[D], xP[D], gP[D][D], R[D];
+  load_w<D>(u, v, eps, c, wP);
+  load_xc<D>(m.xc, c, xP);
+  load_grad<D>(grad, c, gP);
+#pragma unroll
+  for (int k = 0; k < D; ++k) R[k] = 0.0;
+  const int slice = c / kSlice, lane = c % kSlice;
+  const int s0 = m.slice_ptr[slice];
+  const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
+  for (int k = 0; k < width; ++k) {
+    const int idx = s0 + k * kSlice + lane;
+    const int nb = m.slot_nb[idx];
+    if (nb >= 0) {
+      const int fs = m.slot_fc[idx];
+      const bool own = fs >= 0;
+      const int f = own ? fs : ~fs;
+      double G[D], wf, xN[D], wN[D], gN[D][D];
+      load_gamma_w<D>(m.face, f, G, wf);
+      load_xc<D>(m.xc, nb, xN);
+      load_w<D>(u, v, eps, nb, wN);
+      load_grad<D>(grad, nb, gN);
+      // canonical operands: A = owner, B = neighbour of the face
+      double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        xA[i] = own ? xP[i] : xN[i];
+        xB[i] = own ? xN[i] : xP[i];
+        wA[i] = own ? wP[i] : wN[i];
+        wB[i] = own ? wN[i] : wP[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          gA[i][j] = own ? gP[i][j] : gN[i][j];
+          gB[i][j] = own ? gN[i][j] : gP[i][j];
+        }
+      }
+      internal_face_force<D, LAW>(m, G, wf, xA, xB, wA, wB, gA, gB, fo);
+#pragma unroll
+      for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
+    } else if (nb == kSlotBoundary) {
+      const double* r = m.bface + size_t(m.slot_fc[idx]) * kBfaceRec;
+      const int type = int(r[9]);
+      if (type == kBcDisp) {
+        double G[D], db[D], ub[D], t[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          G[q] = r[q];
+          db[q] = r[3 + q];
+          ub[q] = load * r[6 + q];
+        }
+        traction<D, LAW>(m, gP, G, t);
+        double dG = 0, GG = 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          dG = fma(db[q], G[q], dG);
+          GG = fma(G[q], G[q], GG);
+        }
+        const double coef = m.aK * GG / dG;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double dg = 0;
+#pragma unroll
+          for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
+          R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
+        }
+      } else {
+        // traction: |Gamma| T_bar, pressure: -p Gamma (stored pre-multiplied)
+#pragma unroll
+        for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
+      }
+    }
+  }
+  if (Ru != nullptr) {
+    const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      out[size_t(c) * D + q] = eps != 0.0 ? (R[q] - Ru[size_t(c) * D + q]) * ie : 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(c) * D + q] = R[q];
+  }
+}
+
+inline void grid_for(int n_cells, int& nb_real, int& nb_launch) {
+  nb_real = (n_cells + kBlock - 1) / kBlock;
+  nb_launch = ((nb_real + kNumXcd - 1) / kNumXcd) * kNumXcd;
+}
+
+}  // namespace
+
+void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+                     double* grad, hipStream_t s) {
+  int nr, nl;
+  grid_for(m.n_cells, nr, nl);
+  if (m.dim == 3)
+    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kBlock), 0, s, m, u, v, d_eps, grad, nr);
+  else
+    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kBlock), 0, s, m, u, v, d_eps, grad, nr);
+  JFNK_HIP(hipGetLastError());
+}
+
+void launch_flux(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+                 const double* grad, const double* Ru, double* out, double load, hipStream_t s) {
+  int nr, nl;
+  grid_for(m.n_cells, nr, nl);
+  const dim3 g(nl), b(kBlock);
+  if (m.dim == 3) {
+    if (m.law == JFNK_NEO_HOOKEAN)
+      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+    else
+      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+  } else {
+    if (m.law == JFNK_NEO_HOOKEAN)
+      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+    else
+      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+  }
+  JFNK_HIP(hipGetLastError());
+}
+
+}  // namespace jfnk

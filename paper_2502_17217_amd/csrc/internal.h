@@ -1,0 +1,158 @@
+// Internal declarations shared by the host code and the HIP kernels of the
+// JFNK library.  Nothing here is part of the public ABI (see include/jfnk.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "jfnk.h"
+
+namespace jfnk {
+
+// Error carried from the inside of the library to the C ABI, where it is
+// turned into a status code and a thread-local message.
+struct Error {
+  jfnk_status status;
+  std::string msg;
+};
+
+void set_last_error(const std::string& msg);
+
+#define JFNK_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::jfnk::Error{JFNK_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define JFNK_REQUIRE(cond, status, msg)                  \
+  do {                                                   \
+    if (!(cond)) throw ::jfnk::Error{(status), (msg)};   \
+  } while (0)
+
+// Cells are processed one per lane; 64 consecutive cells (one wavefront)
+// form an ELL slice whose slot arrays are stored [slot][lane].
+constexpr int kSlice = 64;
+constexpr int kBlock = 256;
+constexpr int kNumXcd = 8;
+// slot_nb values
+constexpr int kSlotBoundary = -1;
+constexpr int kSlotPad = -2;
+// stride (doubles) of one internal-face record {Gamma, w} and of one
+// boundary-face record {Gamma(3), d_b(3), value(3), type}
+constexpr int kFaceRec = 4;
+constexpr int kBfaceRec = 10;
+// boundary type codes in the record
+constexpr int kBcDisp = 1, kBcTrac = 2, kBcPres = 3;
+
+// Read-only device view of one mesh, passed by value to kernels.
+struct MeshDev {
+  int32_t n_cells;
+  int32_t dim;
+  int32_t n_slices;
+  int32_t law;
+  const int32_t* slice_ptr;  // [n_slices + 1], in slots (multiples of kSlice)
+  const int32_t* slot_nb;    // neighbour cell, kSlotBoundary or kSlotPad
+  const int32_t* slot_fc;    // internal: face (owner side) or ~face (neighbour side); boundary: bface
+  const double* xc;          // [n_cells][dim] cell centroids
+  const double* face;        // [n_internal][4] {Gamma (owner-outward), w_f} (2-D: Gx, Gy, w, 0)
+  const double* bface;       // [n_boundary][10]
+  double mu, lam, kappa;     // law constants (Appendix B)
+  double aK;                 // alpha_rc * K_bar, K_bar = 2 mu + lambda
+};
+
+// Host-side result of mesh preprocessing (all in internal numbering).
+struct HostMesh {
+  int dim = 0;
+  int64_t n_cells = 0, n_int = 0, n_bnd = 0;
+  std::vector<int32_t> old_of_new, new_of_old;
+  std::vector<double> xc, vol;
+  std::vector<double> face;         // n_int * kFaceRec
+  std::vector<int32_t> fown, fnb;   // internal faces, owner < neighbour
+  std::vector<double> bface;        // n_bnd * kBfaceRec
+  std::vector<int32_t> bown;
+  std::vector<int32_t> slice_ptr, slot_nb, slot_fc;
+  std::vector<double> pc_diag;      // approximate Jacobian, scalar diagonal (alpha_pc)
+  std::vector<double> pc_off;       // per internal face off-diagonal coefficient
+  int64_t bandwidth = 0;
+};
+
+struct Material {
+  int law = JFNK_LINEAR_ELASTIC;
+  double E = 0, nu = 0, alpha_rc = 1, alpha_pc = 1;
+  double mu = 0, lam = 0, kappa = 0, Kbar = 0;
+};
+
+Material make_material(const jfnk_material& m);
+void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm);
+
+// Device buffer with RAII.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void alloc(size_t b);
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct AmgHierarchy;  // FP32 preconditioner (amg.cpp)
+
+// HIP-event timing of kernel classes (enabled per mesh for measurement).
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t calls[4] = {0, 0, 0, 0};
+  hipEvent_t get();
+  // Record a start event; returns the index for end().
+  int begin(int cls, hipStream_t s);
+  void end(int idx, hipStream_t s);
+  void collect();
+  ~Profiler();
+};
+
+}  // namespace jfnk
+
+// The opaque handle of the ABI.
+struct jfnk_mesh {
+  jfnk::Material mat;
+  jfnk::HostMesh host;
+  jfnk::MeshDev dev{};
+  jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_face, b_bface, b_order, b_pc_dinv;
+  double* pinned = nullptr;         // pinned host scalars for D2H reads
+  jfnk_mesh_info info{};
+  jfnk::AmgHierarchy* amg = nullptr;
+  jfnk::Profiler prof;
+};
+
+namespace jfnk {
+
+// ---- kernel launchers (fv_kernels.hip, blas.hip) ----
+// grad_w[cell][dim*dim] of w = u + eps*v (v may be null; eps from *d_eps if non-null).
+void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+                     double* grad, hipStream_t s);
+// out = (R(w) - Ru)/eps if Ru != null else R(w).
+void launch_flux(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+                 const double* grad, const double* Ru, double* out, double load, hipStream_t s);
+// d_eps = sqrt(eps_mach) sqrt(1 + |u|)/|v|, from two norms; partials: >= kRedBlocks*2 doubles.
+void launch_eps(const double* u, const double* v, int64_t n, double* partials, double* d_eps,
+                hipStream_t s);
+void launch_set_scalar(double* d, double value, hipStream_t s);
+void launch_permute(const int32_t* old_of_new, const double* in, double* out, int64_t n_cells,
+                    int dim, bool to_internal, hipStream_t s);
+
+constexpr int kRedBlocks = 512;  // fixed number of partial sums for reductions
+
+}  // namespace jfnk

@@ -1,0 +1,471 @@
+// Host preprocessing of a polyhedral mesh (once per mesh):
+//   * validation of the OpenFOAM-style description;
+//   * geometry of Section 2.3 in FP64: face area vectors Gamma_f and
+//     centroids x_f by fan triangulation about the mean vertex, cell volumes
+//     and centroids by face pyramids about the mean face centroid;
+//   * bandwidth-reducing renumbering (reverse Cuthill-McKee, kept only when
+//     it beats the input order);
+//   * packed arrays for the kernels: internal-face records {Gamma, w_f} in
+//     owner orientation (w_f of Eq. stressInterp), boundary-face records,
+//     and a sliced-ELL cell -> face slot map (64 cells per slice);
+//   * the compact-stencil approximate Jacobian of Section 3.1 (scalar
+//     coefficients alpha_pc K_bar |Delta||Gamma|/|d|; blocks are scalar
+//     times identity) for the preconditioners.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace jfnk {
+
+Material make_material(const jfnk_material& m) {
+  JFNK_REQUIRE(m.law == JFNK_LINEAR_ELASTIC || m.law == JFNK_NEO_HOOKEAN, JFNK_E_ARG,
+               "material: unknown law");
+  JFNK_REQUIRE(m.E > 0 && std::isfinite(m.E), JFNK_E_ARG, "material: E must be positive");
+  JFNK_REQUIRE(m.nu > -1.0 && m.nu < 0.5, JFNK_E_ARG, "material: nu must lie in (-1, 0.5)");
+  JFNK_REQUIRE(m.alpha_rc >= 0 && m.alpha_pc > 0, JFNK_E_ARG,
+               "material: alpha_rc >= 0 and alpha_pc > 0 required");
+  Material r;
+  r.law = m.law;
+  r.E = m.E;
+  r.nu = m.nu;
+  r.alpha_rc = m.alpha_rc;
+  r.alpha_pc = m.alpha_pc;
+  r.mu = m.E / (2.0 * (1.0 + m.nu));
+  r.lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+  r.kappa = m.E / (3.0 * (1.0 - 2.0 * m.nu));
+  r.Kbar = 2.0 * r.mu + r.lam;
+  return r;
+}
+
+namespace {
+
+struct V3 {
+  double x = 0, y = 0, z = 0;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+std::string s_face(int64_t f) { return "face " + std::to_string(f); }
+std::string s_cell(int64_t c) { return "cell " + std::to_string(c); }
+
+// Breadth-first search over the cell graph from `start`, visiting neighbours
+// in order of increasing degree (Cuthill-McKee); marks visited cells with
+// `stamp`.  Returns the visit order and the index where the last level starts.
+void bfs(int32_t start, const std::vector<int64_t>& aptr, const std::vector<int32_t>& adj,
+         const std::vector<int32_t>& deg, std::vector<int32_t>& mark, int32_t stamp,
+         std::vector<int32_t>& out, size_t& last_level_begin, int& n_levels) {
+  out.clear();
+  out.push_back(start);
+  mark[start] = stamp;
+  size_t level_begin = 0;
+  n_levels = 0;
+  std::vector<int32_t> nb;
+  while (level_begin < out.size()) {
+    size_t level_end = out.size();
+    last_level_begin = level_begin;
+    ++n_levels;
+    for (size_t i = level_begin; i < level_end; ++i) {
+      int32_t c = out[i];
+      nb.clear();
+      for (int64_t k = aptr[c]; k < aptr[c + 1]; ++k)
+        if (mark[adj[k]] != stamp) {
+          mark[adj[k]] = stamp;
+          nb.push_back(adj[k]);
+        }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+        return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
+      });
+      out.insert(out.end(), nb.begin(), nb.end());
+    }
+    level_begin = level_end;
+  }
+}
+
+// Reverse Cuthill-McKee order (old index of each new position); each
+// connected component starts from a pseudo-peripheral cell.
+std::vector<int32_t> rcm(int64_t nc, const std::vector<int64_t>& aptr,
+                         const std::vector<int32_t>& adj) {
+  std::vector<int32_t> deg(nc), mark(nc, 0), done(nc, 0), order, comp;
+  order.reserve(nc);
+  for (int64_t c = 0; c < nc; ++c) deg[c] = int32_t(aptr[c + 1] - aptr[c]);
+  int32_t stamp = 0;
+  for (int64_t s0 = 0; s0 < nc; ++s0) {
+    if (done[s0]) continue;
+    int32_t start = int32_t(s0);
+    size_t last = 0;
+    int levels = 0;
+    bfs(start, aptr, adj, deg, mark, ++stamp, comp, last, levels);
+    for (int iter = 0; iter < 8; ++iter) {
+      int32_t cand = comp[last];
+      for (size_t i = last; i < comp.size(); ++i)
+        if (deg[comp[i]] < deg[cand]) cand = comp[i];
+      size_t last2 = 0;
+      int levels2 = 0;
+      std::vector<int32_t> comp2;
+      bfs(cand, aptr, adj, deg, mark, ++stamp, comp2, last2, levels2);
+      if (levels2 <= levels) break;
+      start = cand;
+      levels = levels2;
+      last = last2;
+      comp.swap(comp2);
+    }
+    for (int32_t c : comp) done[c] = 1;
+    order.insert(order.end(), comp.begin(), comp.end());
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+}  // namespace
+
+void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm) {
+  const int dim = d.dim;
+  JFNK_REQUIRE(dim == 2 || dim == 3, JFNK_E_ARG, "mesh: dim must be 2 or 3");
+  JFNK_REQUIRE(d.points && d.face_ptr && d.face_pts && d.owner, JFNK_E_ARG, "mesh: null array");
+  JFNK_REQUIRE(d.n_cells > 0 && d.n_cells < (int64_t(1) << 31) - 64, JFNK_E_ARG,
+               "mesh: n_cells out of range");
+  JFNK_REQUIRE(d.n_internal >= 0 && d.n_internal <= d.n_faces && d.n_faces < (int64_t(1) << 31),
+               JFNK_E_ARG, "mesh: inconsistent face counts");
+  JFNK_REQUIRE(d.n_internal == 0 || d.neighbour, JFNK_E_ARG, "mesh: null neighbour array");
+  const int64_t nc = d.n_cells, nf = d.n_faces, ni = d.n_internal, nb = nf - ni;
+  JFNK_REQUIRE(d.face_ptr[0] == 0, JFNK_E_MESH, "mesh: face_ptr[0] must be 0");
+  for (int64_t f = 0; f < nf; ++f) {
+    int64_t k = d.face_ptr[f + 1] - d.face_ptr[f];
+    JFNK_REQUIRE(dim == 2 ? k == 2 : k >= 3, JFNK_E_MESH,
+                 "mesh: " + s_face(f) + " has a wrong number of vertices");
+    for (int64_t i = d.face_ptr[f]; i < d.face_ptr[f + 1]; ++i)
+      JFNK_REQUIRE(d.face_pts[i] >= 0 && d.face_pts[i] < d.n_points, JFNK_E_MESH,
+                   "mesh: " + s_face(f) + " has a vertex index out of range");
+    JFNK_REQUIRE(d.owner[f] >= 0 && d.owner[f] < nc, JFNK_E_MESH,
+                 "mesh: owner of " + s_face(f) + " out of range");
+    if (f < ni)
+      JFNK_REQUIRE(d.neighbour[f] >= 0 && d.neighbour[f] < nc && d.neighbour[f] != d.owner[f],
+                   JFNK_E_MESH, "mesh: neighbour of " + s_face(f) + " invalid");
+  }
+
+  // ---- boundary classification from the patches ----
+  std::vector<int8_t> btype(nb, 0);
+  std::vector<double> bval(nb * 3, 0.0);
+  JFNK_REQUIRE(d.n_patches >= 0 && (d.n_patches == 0 || d.patches), JFNK_E_ARG,
+               "mesh: null patch array");
+  for (int32_t p = 0; p < d.n_patches; ++p) {
+    const jfnk_patch& pt = d.patches[p];
+    JFNK_REQUIRE(pt.type >= 1 && pt.type <= 3, JFNK_E_ARG,
+                 "mesh: patch " + std::to_string(p) + " has an unknown type");
+    JFNK_REQUIRE(pt.start >= ni && pt.size >= 0 && pt.start + pt.size <= nf, JFNK_E_ARG,
+                 "mesh: patch " + std::to_string(p) + " face range outside the boundary faces");
+    for (int64_t i = 0; i < pt.size; ++i) {
+      int64_t b = pt.start - ni + i;
+      JFNK_REQUIRE(btype[b] == 0, JFNK_E_ARG,
+                   "mesh: boundary " + s_face(pt.start + i) + " is in two patches");
+      btype[b] = int8_t(pt.type);
+      for (int k = 0; k < dim; ++k)
+        bval[b * 3 + k] = pt.per_face ? pt.per_face[i * dim + k] : pt.value[k];
+      if (pt.type == JFNK_BC_PRESSURE) bval[b * 3] = pt.per_face ? pt.per_face[i * dim] : pt.value[0];
+    }
+  }
+  for (int64_t b = 0; b < nb; ++b)
+    JFNK_REQUIRE(btype[b] != 0, JFNK_E_ARG, "mesh: boundary " + s_face(ni + b) + " is in no patch");
+
+  // ---- face geometry (input order) ----
+  auto P = [&](int32_t i) {
+    V3 r;
+    r.x = d.points[int64_t(i) * dim];
+    r.y = d.points[int64_t(i) * dim + 1];
+    if (dim == 3) r.z = d.points[int64_t(i) * dim + 2];
+    return r;
+  };
+  std::vector<V3> Gam(nf), xf(nf);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int64_t a = d.face_ptr[f], k = d.face_ptr[f + 1] - a;
+    if (dim == 2) {
+      V3 p0 = P(d.face_pts[a]), p1 = P(d.face_pts[a + 1]);
+      Gam[f] = {p1.y - p0.y, -(p1.x - p0.x), 0.0};
+      xf[f] = 0.5 * (p0 + p1);
+    } else {
+      V3 xbar;
+      for (int64_t i = 0; i < k; ++i) xbar = xbar + P(d.face_pts[a + i]);
+      xbar = (1.0 / double(k)) * xbar;
+      V3 g;
+      std::vector<V3> tri_a(k), tri_c(k);
+      for (int64_t i = 0; i < k; ++i) {
+        V3 pi = P(d.face_pts[a + i]), pj = P(d.face_pts[a + (i + 1) % k]);
+        tri_a[i] = 0.5 * cross(pi - xbar, pj - xbar);
+        tri_c[i] = (1.0 / 3.0) * (pi + pj + xbar);
+        g = g + tri_a[i];
+      }
+      double mg = std::sqrt(dot(g, g));
+      JFNK_REQUIRE(mg > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
+      V3 n = (1.0 / mg) * g, c;
+      double wsum = 0;
+      for (int64_t i = 0; i < k; ++i) {
+        double w = dot(tri_a[i], n);
+        wsum += w;
+        c = c + w * tri_c[i];
+      }
+      Gam[f] = g;
+      xf[f] = (1.0 / wsum) * c;
+    }
+    JFNK_REQUIRE(dot(Gam[f], Gam[f]) > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
+  }
+
+  // ---- cell geometry (input order) ----
+  std::vector<int32_t> nfc(nc, 0);
+  std::vector<V3> xbar(nc);
+  for (int64_t f = 0; f < nf; ++f) {
+    nfc[d.owner[f]]++;
+    xbar[d.owner[f]] = xbar[d.owner[f]] + xf[f];
+    if (f < ni) {
+      nfc[d.neighbour[f]]++;
+      xbar[d.neighbour[f]] = xbar[d.neighbour[f]] + xf[f];
+    }
+  }
+  for (int64_t c = 0; c < nc; ++c) {
+    JFNK_REQUIRE(nfc[c] >= dim + 1, JFNK_E_MESH, "mesh: " + s_cell(c) + " has too few faces");
+    xbar[c] = (1.0 / double(nfc[c])) * xbar[c];
+  }
+  std::vector<double> vol(nc, 0.0);
+  std::vector<V3> mom(nc);
+  const double cfrac = dim == 3 ? 0.75 : 2.0 / 3.0, vfrac = dim == 3 ? 1.0 / 3.0 : 0.5;
+  auto add_pyr = [&](int32_t c, V3 g_out, V3 x) {
+    V3 r = x - xbar[c];
+    double v = vfrac * dot(g_out, r);
+    vol[c] += v;
+    mom[c] = mom[c] + v * (xbar[c] + cfrac * r);
+  };
+  for (int64_t f = 0; f < nf; ++f) {
+    add_pyr(d.owner[f], Gam[f], xf[f]);
+    if (f < ni) add_pyr(d.neighbour[f], -1.0 * Gam[f], xf[f]);
+  }
+  std::vector<V3> xc0(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    JFNK_REQUIRE(vol[c] > 0 && std::isfinite(vol[c]), JFNK_E_MESH,
+                 "mesh: " + s_cell(c) + " has a non-positive volume");
+    xc0[c] = (1.0 / vol[c]) * mom[c];
+  }
+
+  // ---- renumbering ----
+  std::vector<int64_t> aptr(nc + 1, 0);
+  for (int64_t f = 0; f < ni; ++f) {
+    aptr[d.owner[f] + 1]++;
+    aptr[d.neighbour[f] + 1]++;
+  }
+  for (int64_t c = 0; c < nc; ++c) aptr[c + 1] += aptr[c];
+  std::vector<int32_t> adj(aptr[nc]);
+  {
+    std::vector<int64_t> pos(aptr.begin(), aptr.end() - 1);
+    for (int64_t f = 0; f < ni; ++f) {
+      adj[pos[d.owner[f]]++] = d.neighbour[f];
+      adj[pos[d.neighbour[f]]++] = d.owner[f];
+    }
+  }
+  auto bandwidth_of = [&](const std::vector<int32_t>& nofo) {
+    int64_t bw = 0;
+    for (int64_t f = 0; f < ni; ++f)
+      bw = std::max<int64_t>(bw, std::llabs(int64_t(nofo[d.owner[f]]) - nofo[d.neighbour[f]]));
+    return bw;
+  };
+  std::vector<int32_t> ident(nc);
+  std::iota(ident.begin(), ident.end(), 0);
+  int64_t bw_in = bandwidth_of(ident);
+  std::vector<int32_t> order = rcm(nc, aptr, adj);
+  std::vector<int32_t> nofo(nc);
+  for (int64_t i = 0; i < nc; ++i) nofo[order[i]] = int32_t(i);
+  int64_t bw_rcm = bandwidth_of(nofo);
+  if (bw_rcm >= bw_in) {
+    order = ident;
+    nofo = ident;
+  }
+  hm.bandwidth = std::min(bw_in, bw_rcm);
+  hm.old_of_new = order;
+  hm.new_of_old = nofo;
+  hm.dim = dim;
+  hm.n_cells = nc;
+  hm.n_int = ni;
+  hm.n_bnd = nb;
+  hm.xc.assign(nc * dim, 0.0);
+  hm.vol.assign(nc, 0.0);
+  for (int64_t i = 0; i < nc; ++i) {
+    int32_t o = order[i];
+    hm.vol[i] = vol[o];
+    hm.xc[i * dim] = xc0[o].x;
+    hm.xc[i * dim + 1] = xc0[o].y;
+    if (dim == 3) hm.xc[i * dim + 2] = xc0[o].z;
+  }
+  auto XC = [&](int32_t c) {
+    V3 r;
+    r.x = hm.xc[int64_t(c) * dim];
+    r.y = hm.xc[int64_t(c) * dim + 1];
+    if (dim == 3) r.z = hm.xc[int64_t(c) * dim + 2];
+    return r;
+  };
+
+  // ---- internal faces in the new numbering, owner < neighbour ----
+  std::vector<int64_t> fperm(ni);
+  std::vector<int32_t> o2(ni), n2(ni);
+  std::vector<int8_t> flip(ni);
+  for (int64_t f = 0; f < ni; ++f) {
+    int32_t a = nofo[d.owner[f]], b = nofo[d.neighbour[f]];
+    flip[f] = a > b;
+    o2[f] = std::min(a, b);
+    n2[f] = std::max(a, b);
+  }
+  std::iota(fperm.begin(), fperm.end(), 0);
+  std::stable_sort(fperm.begin(), fperm.end(), [&](int64_t x, int64_t y) {
+    return o2[x] != o2[y] ? o2[x] < o2[y] : n2[x] < n2[y];
+  });
+  const double aKp = mat.alpha_pc * mat.Kbar;
+  hm.face.assign(ni * kFaceRec, 0.0);
+  hm.fown.resize(ni);
+  hm.fnb.resize(ni);
+  hm.pc_off.resize(ni);
+  hm.pc_diag.assign(nc, 0.0);
+  for (int64_t j = 0; j < ni; ++j) {
+    int64_t f = fperm[j];
+    int32_t A = o2[f], B = n2[f];
+    V3 g = flip[f] ? -1.0 * Gam[f] : Gam[f];
+    double mg = std::sqrt(dot(g, g));
+    V3 n = (1.0 / mg) * g;
+    V3 dAB = XC(B) - XC(A);
+    double dn = dot(dAB, n);
+    JFNK_REQUIRE(dn > 0, JFNK_E_MESH,
+                 "mesh: " + s_face(f) + " has d.n <= 0 (cell centroids on the wrong side)");
+    double w = dot(n, XC(B) - xf[f]) / dn;
+    double* r = &hm.face[j * kFaceRec];
+    if (dim == 3) {
+      r[0] = g.x; r[1] = g.y; r[2] = g.z; r[3] = w;
+    } else {
+      r[0] = g.x; r[1] = g.y; r[2] = w; r[3] = 0.0;
+    }
+    hm.fown[j] = A;
+    hm.fnb[j] = B;
+    double a = aKp * mg / dn;    // alpha K_bar |Delta| |Gamma| / |d| = alpha K_bar |Gamma| / (d.n)
+    hm.pc_off[j] = a;
+    hm.pc_diag[A] -= a;
+    hm.pc_diag[B] -= a;
+  }
+
+  // ---- boundary faces sorted by new owner ----
+  std::vector<int64_t> bperm(nb);
+  std::iota(bperm.begin(), bperm.end(), 0);
+  std::stable_sort(bperm.begin(), bperm.end(), [&](int64_t x, int64_t y) {
+    return nofo[d.owner[ni + x]] < nofo[d.owner[ni + y]];
+  });
+  hm.bface.assign(nb * kBfaceRec, 0.0);
+  hm.bown.resize(nb);
+  for (int64_t j = 0; j < nb; ++j) {
+    int64_t b = bperm[j], f = ni + b;
+    int32_t c = nofo[d.owner[f]];
+    V3 g = Gam[f];
+    V3 db = xf[f] - XC(c);
+    double mg = std::sqrt(dot(g, g));
+    double* r = &hm.bface[j * kBfaceRec];
+    r[0] = g.x; r[1] = g.y; r[2] = g.z;
+    r[3] = db.x; r[4] = db.y; r[5] = db.z;
+    const double* v = &bval[b * 3];
+    if (btype[b] == JFNK_BC_DISPLACEMENT) {
+      double dbn = dot(db, g) / mg;
+      JFNK_REQUIRE(dbn > 0, JFNK_E_MESH, "mesh: displacement " + s_face(f) + " has d.n <= 0");
+      r[6] = v[0]; r[7] = v[1]; r[8] = v[2];
+      r[9] = kBcDisp;
+      double a = aKp * mg / dbn;
+      hm.pc_diag[c] -= a;
+    } else if (btype[b] == JFNK_BC_TRACTION) {
+      r[6] = mg * v[0]; r[7] = mg * v[1]; r[8] = mg * v[2];   // |Gamma| T_bar
+      r[9] = kBcTrac;
+    } else {
+      r[6] = -v[0] * g.x; r[7] = -v[0] * g.y; r[8] = -v[0] * g.z;  // -p Gamma
+      r[9] = kBcPres;
+    }
+    if (dim == 2) { r[2] = r[5] = r[8] = 0.0; }
+    hm.bown[j] = c;
+  }
+
+  // ---- least-squares matrix check (the kernels rebuild G_P on the fly) ----
+  {
+    std::vector<double> G(nc * 6, 0.0);
+    for (int64_t j = 0; j < ni; ++j) {
+      const double* r = &hm.face[j * kFaceRec];
+      V3 g = dim == 3 ? V3{r[0], r[1], r[2]} : V3{r[0], r[1], 0.0};
+      double mg = std::sqrt(dot(g, g));
+      V3 dd = XC(hm.fnb[j]) - XC(hm.fown[j]);
+      double wt = mg / dot(dd, dd);
+      double e[6] = {dd.x * dd.x, dd.x * dd.y, dd.x * dd.z, dd.y * dd.y, dd.y * dd.z, dd.z * dd.z};
+      for (int k = 0; k < 6; ++k) {
+        G[hm.fown[j] * 6 + k] += wt * e[k];
+        G[hm.fnb[j] * 6 + k] += wt * e[k];
+      }
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+      const double* g = &G[c * 6];
+      double det, scale;
+      if (dim == 3) {
+        det = g[0] * (g[3] * g[5] - g[4] * g[4]) - g[1] * (g[1] * g[5] - g[4] * g[2]) +
+              g[2] * (g[1] * g[4] - g[3] * g[2]);
+        scale = std::pow((g[0] + g[3] + g[5]) / 3.0, 3);
+      } else {
+        det = g[0] * g[3] - g[1] * g[1];
+        scale = std::pow((g[0] + g[3]) / 2.0, 2);
+      }
+      JFNK_REQUIRE(det > 1e-10 * scale && scale > 0, JFNK_E_MESH,
+                   "mesh: input " + s_cell(order[c]) +
+                       " has a singular least-squares matrix (too few internal-face directions)");
+    }
+  }
+
+  // ---- sliced-ELL slot map ----
+  std::vector<int32_t> cnt(nc + 1, 0);
+  for (int64_t j = 0; j < ni; ++j) {
+    cnt[hm.fown[j] + 1]++;
+    cnt[hm.fnb[j] + 1]++;
+  }
+  for (int64_t j = 0; j < nb; ++j) cnt[hm.bown[j] + 1]++;
+  for (int64_t c = 0; c < nc; ++c) cnt[c + 1] += cnt[c];
+  std::vector<int32_t> snb(cnt[nc]), sfc(cnt[nc]);
+  {
+    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t j = 0; j < ni; ++j) {  // faces ascend, so each cell's list is sorted by face
+      int32_t A = hm.fown[j], B = hm.fnb[j];
+      snb[pos[A]] = B;
+      sfc[pos[A]++] = int32_t(j);
+      snb[pos[B]] = A;
+      sfc[pos[B]++] = ~int32_t(j);
+    }
+    for (int64_t j = 0; j < nb; ++j) {
+      int32_t c = hm.bown[j];
+      snb[pos[c]] = kSlotBoundary;
+      sfc[pos[c]++] = int32_t(j);
+    }
+  }
+  const int64_t n_slices = (nc + kSlice - 1) / kSlice;
+  hm.slice_ptr.assign(n_slices + 1, 0);
+  for (int64_t s = 0; s < n_slices; ++s) {
+    int32_t w = 0;
+    for (int64_t c = s * kSlice; c < std::min<int64_t>(nc, (s + 1) * kSlice); ++c)
+      w = std::max(w, cnt[c + 1] - cnt[c]);
+    JFNK_REQUIRE(int64_t(hm.slice_ptr[s]) + int64_t(w) * kSlice < (int64_t(1) << 31), JFNK_E_ARG,
+                 "mesh: too many face slots");
+    hm.slice_ptr[s + 1] = hm.slice_ptr[s] + w * kSlice;
+  }
+  hm.slot_nb.assign(hm.slice_ptr[n_slices], kSlotPad);
+  hm.slot_fc.assign(hm.slice_ptr[n_slices], 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t s = c / kSlice, lane = c % kSlice;
+    for (int32_t k = 0; k < cnt[c + 1] - cnt[c]; ++k) {
+      int64_t idx = hm.slice_ptr[s] + int64_t(k) * kSlice + lane;
+      hm.slot_nb[idx] = snb[cnt[c] + k];
+      hm.slot_fc[idx] = sfc[cnt[c] + k];
+    }
+  }
+}
+
+}  // namespace jfnk

@@ -1,0 +1,36 @@
+// Preconditioner dispatch (Section 3.2: the compact-stencil approximate
+// Jacobian J_tilde of Section 3.1 as the preconditioning matrix P).
+//   JACOBI : z = diag(J_tilde)^{-1} r in FP64 (block-Jacobi; the blocks are
+//            scalar times identity).
+//   AMG32  : FP32 aggregation-AMG V-cycle on the scalar J_tilde with
+//            Chebyshev smoothing (amg.cpp / amg_kernels.hip).
+#include "blas.h"
+#include "solver.h"
+
+namespace jfnk {
+
+size_t amg_work_floats(const jfnk_mesh* m);
+void amg_setup(jfnk_mesh* m, hipStream_t s);
+void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s);
+
+size_t precond_work_floats(const jfnk_mesh* m, int precond) {
+  return precond == JFNK_PC_AMG32 ? amg_work_floats(m) : 0;
+}
+
+void precond_setup(jfnk_mesh* m, int precond, hipStream_t s) {
+  if (precond == JFNK_PC_AMG32) amg_setup(m, s);
+}
+
+void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
+                   KrylovWork& kw, hipStream_t s) {
+  const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
+  if (precond == JFNK_PC_JACOBI) {
+    blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, s);
+  } else if (precond == JFNK_PC_AMG32) {
+    amg_apply(m, cheb_degree, r, z, kw.pc, s);
+  } else {
+    JFNK_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace jfnk

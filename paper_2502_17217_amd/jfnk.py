@@ -1,0 +1,332 @@
+"""Python binding of libjfnk.so (include/jfnk.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts mesh
+dictionaries (see ``meshgen``) and torch CUDA tensors into the C ABI's
+structures and raw device pointers.  Torch is used for device memory and
+streams only.  If the library is not built, importing this module fails.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjfnk.so")
+
+OK, E_ARG, E_MESH, E_OOM, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_NAN, E_BREAKDOWN, E_BUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_OOM", -4: "E_HIP", -5: "E_NOT_CONVERGED",
+                -6: "E_DIVERGED", -7: "E_NAN", -8: "E_BREAKDOWN", -9: "E_BUSY"}
+BC = {"displacement": 1, "traction": 2, "pressure": 3}
+LAW = {"linear_elastic": 0, "neo_hookean": 1}
+PC_NONE, PC_JACOBI, PC_AMG32 = 0, 1, 2
+PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32}
+
+
+class jfnk_patch(C.Structure):
+    _fields_ = [("type", C.c_int32), ("start", C.c_int64), ("size", C.c_int64),
+                ("value", C.c_double * 3), ("per_face", C.c_void_p)]
+
+
+class jfnk_mesh_desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_points", C.c_int64), ("points", C.c_void_p),
+                ("n_cells", C.c_int64), ("n_faces", C.c_int64), ("n_internal", C.c_int64),
+                ("face_ptr", C.c_void_p), ("face_pts", C.c_void_p), ("owner", C.c_void_p),
+                ("neighbour", C.c_void_p), ("n_patches", C.c_int32), ("patches", C.c_void_p)]
+
+
+class jfnk_material(C.Structure):
+    _fields_ = [("law", C.c_int32), ("E", C.c_double), ("nu", C.c_double),
+                ("alpha_rc", C.c_double), ("alpha_pc", C.c_double)]
+
+
+class jfnk_mesh_info(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("dim", C.c_int32), ("n_dof", C.c_int64),
+                ("n_internal_faces", C.c_int64), ("n_boundary_faces", C.c_int64),
+                ("bandwidth", C.c_int64), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
+                ("n_slots", C.c_int64)]
+
+
+class jfnk_gmres_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
+                ("eps", C.c_double)]
+
+
+class jfnk_newton_opts(C.Structure):
+    _fields_ = [("n_increments", C.c_int32), ("max_newton_it", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("eta", C.c_double), ("gmres", jfnk_gmres_opts)]
+
+
+class jfnk_stats(C.Structure):
+    _fields_ = [("newton_it", C.c_int32), ("gmres_it", C.c_int32), ("restarts", C.c_int32),
+                ("jv_evals", C.c_int32), ("res0", C.c_double), ("res_final", C.c_double),
+                ("eps_last", C.c_double), ("t_ms", C.c_double * 8)]
+
+    def as_dict(self):
+        return dict(newton_it=self.newton_it, gmres_it=self.gmres_it, restarts=self.restarts,
+                    jv_evals=self.jv_evals, res0=self.res0, res_final=self.res_final,
+                    eps_last=self.eps_last, t_ms=list(self.t_ms))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libjfnk.so is not built (run __graft_entry__.build() or "
+                          "python paper_2502_17217_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "jfnk_create_mesh": [vp, vp, vp, C.POINTER(vp)],
+        "jfnk_destroy_mesh": [vp],
+        "jfnk_inspect_mesh": [vp, vp, C.POINTER(jfnk_mesh_info), vp, vp],
+        "jfnk_get_mesh_info": [vp, C.POINTER(jfnk_mesh_info)],
+        "jfnk_mesh_order": [vp, vp],
+        "jfnk_to_internal": [vp, vp, vp, vp],
+        "jfnk_to_external": [vp, vp, vp, vp],
+        "jfnk_workspace_size": [vp, i32, i32, i32, C.POINTER(C.c_size_t)],
+        "jfnk_residual": [vp, d, vp, vp, vp, vp],
+        "jfnk_jv": [vp, d, vp, vp, vp, d, vp, C.POINTER(d), vp, vp],
+        "jfnk_gmres": [vp, d, vp, vp, vp, vp, C.POINTER(jfnk_gmres_opts), C.POINTER(jfnk_stats), vp, vp],
+        "jfnk_newton_solve": [vp, C.POINTER(jfnk_newton_opts), vp, C.POINTER(jfnk_stats), vp, vp],
+        "jfnk_profile_enable": [vp, i32],
+        "jfnk_profile_read": [vp, vp, vp, i32],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.jfnk_last_error.restype = C.c_char_p
+    lib.jfnk_last_error.argtypes = []
+    lib.jfnk_version.restype = C.c_char_p
+    lib.jfnk_version.argtypes = []
+    return lib
+
+
+_lib = _load()
+
+
+class JfnkError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.jfnk_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+
+
+def _check(status, where, allow=()):
+    if status != OK and status not in allow:
+        raise JfnkError(status, where)
+    return status
+
+
+def version():
+    return _lib.jfnk_version().decode()
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dptr(t, n=None, name="tensor", dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+class Workspace:
+    """Device workspace (torch uint8 buffer) with a 256-byte aligned pointer."""
+
+    def __init__(self, nbytes, device="cuda"):
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.ptr = (base + 255) & ~255
+
+    @property
+    def c(self):
+        return C.c_void_p(self.ptr)
+
+
+def _make_desc(mesh):
+    """Build a jfnk_mesh_desc; returns (desc, keepalive list of host arrays)."""
+    keep = []
+    dim = int(mesh["dim"])
+    pts = np.ascontiguousarray(mesh["points"], dtype=np.float64)
+    fptr = np.ascontiguousarray(mesh["face_ptr"], dtype=np.int64)
+    fpts = np.ascontiguousarray(mesh["face_pts"], dtype=np.int32)
+    own = np.ascontiguousarray(mesh["owner"], dtype=np.int32)
+    nb = np.ascontiguousarray(mesh["neighbour"], dtype=np.int32)
+    keep += [pts, fptr, fpts, own, nb]
+    patches = (jfnk_patch * max(1, len(mesh["patches"])))()
+    for i, p in enumerate(mesh["patches"]):
+        patches[i].type = BC[p["type"]]
+        patches[i].start = p["start"]
+        patches[i].size = p["size"]
+        for k in range(3):
+            patches[i].value[k] = float(p["value"][k])
+        if p.get("per_face") is not None:
+            pf = np.ascontiguousarray(p["per_face"], dtype=np.float64)
+            keep.append(pf)
+            patches[i].per_face = pf.ctypes.data
+        else:
+            patches[i].per_face = None
+    keep.append(patches)
+    desc = jfnk_mesh_desc(dim, pts.shape[0], pts.ctypes.data, int(mesh["n_cells"]),
+                          int(mesh["n_faces"]), int(mesh["n_internal"]), fptr.ctypes.data,
+                          fpts.ctypes.data, own.ctypes.data, nb.ctypes.data,
+                          len(mesh["patches"]), C.cast(patches, C.c_void_p))
+    return desc, keep
+
+
+def _make_material(material):
+    get = (lambda k: getattr(material, k)) if hasattr(material, "law") else (lambda k: material[k])
+    return jfnk_material(LAW[get("law")], get("E"), get("nu"), get("alpha_rc"), get("alpha_pc"))
+
+
+def _info_dict(info):
+    return {k: getattr(info, k) for k, _ in jfnk_mesh_info._fields_}
+
+
+def inspect_mesh(mesh, material, geometry=False):
+    """Host-only validation and preprocessing (no GPU needed).
+
+    Returns the info dict, plus (xc, vol) in input cell order if geometry=True.
+    """
+    desc, keep = _make_desc(mesh)
+    mat = _make_material(material)
+    info = jfnk_mesh_info()
+    xc = vol = None
+    if geometry:
+        xc = np.zeros((int(mesh["n_cells"]), int(mesh["dim"])))
+        vol = np.zeros(int(mesh["n_cells"]))
+    _check(_lib.jfnk_inspect_mesh(C.byref(desc), C.byref(mat), C.byref(info),
+                                  xc.ctypes.data if geometry else None,
+                                  vol.ctypes.data if geometry else None), "jfnk_inspect_mesh")
+    del keep
+    return (_info_dict(info), xc, vol) if geometry else _info_dict(info)
+
+
+class Mesh:
+    """Owner of a jfnk_mesh handle built from a meshgen-style dictionary."""
+
+    def __init__(self, mesh, material, stream=None):
+        desc, keep = _make_desc(mesh)
+        mat = _make_material(material)
+        h = C.c_void_p()
+        _check(_lib.jfnk_create_mesh(C.byref(desc), C.byref(mat), _stream(stream), C.byref(h)),
+               "jfnk_create_mesh")
+        del keep
+        self.handle = h
+        info = jfnk_mesh_info()
+        _check(_lib.jfnk_get_mesh_info(h, C.byref(info)), "jfnk_get_mesh_info")
+        self.info = _info_dict(info)
+        self.dim = info.dim
+        self.n_cells = info.n_cells
+        self.n_dof = info.n_dof
+        order = np.empty(self.n_cells, dtype=np.int32)
+        _check(_lib.jfnk_mesh_order(h, order.ctypes.data), "jfnk_mesh_order")
+        self.old_of_new = order
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.jfnk_destroy_mesh(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # vectors in internal order <-> input order (device permutation kernels)
+    def to_internal(self, x, out=None, stream=None):
+        out = torch.empty_like(x) if out is None else out
+        _check(_lib.jfnk_to_internal(self.handle, _dptr(x, self.n_dof, "x"), _dptr(out, self.n_dof, "out"),
+                                     _stream(stream)), "jfnk_to_internal")
+        return out
+
+    def to_external(self, x, out=None, stream=None):
+        out = torch.empty_like(x) if out is None else out
+        _check(_lib.jfnk_to_external(self.handle, _dptr(x, self.n_dof, "x"), _dptr(out, self.n_dof, "out"),
+                                     _stream(stream)), "jfnk_to_external")
+        return out
+
+
+def create_mesh(mesh, material, stream=None):
+    return Mesh(mesh, material, stream)
+
+
+def workspace_size(mesh, op=0, restart=30, precond=PC_JACOBI):
+    n = C.c_size_t()
+    _check(_lib.jfnk_workspace_size(mesh.handle, op, restart, precond, C.byref(n)), "jfnk_workspace_size")
+    return n.value
+
+
+def make_workspace(mesh, op=0, restart=30, precond=PC_JACOBI):
+    return Workspace(workspace_size(mesh, op, restart, precond))
+
+
+def residual(mesh, load, u, R, work, stream=None):
+    _check(_lib.jfnk_residual(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"), _dptr(R, mesh.n_dof, "R"),
+                              work.c, _stream(stream)), "jfnk_residual")
+    return R
+
+
+def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
+    e = C.c_double(0.0)
+    _check(_lib.jfnk_jv(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"),
+                        _dptr(Ru, mesh.n_dof, "Ru") if Ru is not None else None,
+                        _dptr(v, mesh.n_dof, "v"), float(eps), _dptr(Jv, mesh.n_dof, "Jv"),
+                        C.byref(e) if return_eps else None, work.c, _stream(stream)), "jfnk_jv")
+    return (Jv, e.value) if return_eps else Jv
+
+
+def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0):
+    if isinstance(precond, str):
+        precond = PRECOND[precond]
+    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps)
+
+
+def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, **gm):
+    return jfnk_newton_opts(n_increments, max_newton_it, rtol, atol, eta, gmres_opts(**gm))
+
+
+def gmres(mesh, load, u, Ru, b, x, opts, work, stream=None, allow=(E_NOT_CONVERGED, E_BREAKDOWN)):
+    st = jfnk_stats()
+    s = _lib.jfnk_gmres(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"), _dptr(Ru, mesh.n_dof, "Ru"),
+                        _dptr(b, mesh.n_dof, "b"), _dptr(x, mesh.n_dof, "x"), C.byref(opts), C.byref(st),
+                        work.c, _stream(stream))
+    _check(s, "jfnk_gmres", allow)
+    return s, st.as_dict()
+
+
+def newton_solve(mesh, opts, u, work, stream=None, allow=(E_NOT_CONVERGED,)):
+    st = jfnk_stats()
+    s = _lib.jfnk_newton_solve(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), C.byref(st),
+                               work.c, _stream(stream))
+    _check(s, "jfnk_newton_solve", allow)
+    return s, st.as_dict()
+
+
+def profile_enable(mesh, on=True):
+    _check(_lib.jfnk_profile_enable(mesh.handle, 1 if on else 0), "jfnk_profile_enable")
+
+
+def profile_read(mesh, reset=True):
+    """Accumulated kernel milliseconds and call counts: eps, gradient, flux, preconditioner."""
+    ms = (C.c_double * 4)()
+    calls = (C.c_int64 * 4)()
+    _check(_lib.jfnk_profile_read(mesh.handle, ms, calls, 1 if reset else 0), "jfnk_profile_read")
+    names = ["eps", "gradient", "flux", "precond"]
+    return {n: (ms[i], calls[i]) for i, n in enumerate(names)}
