@@ -43,20 +43,21 @@ def nominal_centres(meta):
 
 
 def algorithmic_bytes(info, dim):
-    """Bytes each kernel must move once per launch with this data layout."""
+    """Bytes each kernel must move once per launch with this data layout
+    (every array counted once, at its full size)."""
     nc, nd = info["n_cells"], info["n_dof"]
     n_int, n_bnd, n_slots = info["n_internal_faces"], info["n_boundary_faces"], info["n_slots"]
     n_slices = (nc + 63) // 64
     slots = n_slots * 8 + (n_slices + 1) * 4
-    uv = 2 * nd * 8
+    vec = nd * 8
     xc = nc * dim * 8
-    grad = nc * dim * dim * 8
-    face = n_int * 32
-    bface = n_bnd * 80
+    rec = nc * (dim + dim * dim) * 8        # {w, grad w} per cell
     return {
-        "eps": uv,
-        "gradient": uv + xc + face + slots + grad,
-        "flux": uv + xc + grad + face + bface + slots + 2 * nd * 8,
+        "eps": 2 * vec,
+        # reads u, v, centroids, |Gamma|, slot map; writes the record
+        "gradient": 2 * vec + xc + n_int * 8 + slots + rec,
+        # reads record, centroids, Gamma and w_f, boundary records, slot map, R(u); writes J v
+        "flux": rec + xc + n_int * (dim + 1) * 8 + n_bnd * 80 + slots + 2 * vec,
     }
 
 

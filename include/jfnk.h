@@ -17,11 +17,14 @@
  *     Section 3.3 and equal load increments.
  *
  * Conventions
- *   Vectors: device pointers to FP64, interleaved [cell][component] (the
- *   paper's blocked layout, Section 2.2) in the mesh's INTERNAL cell order,
- *   which is a bandwidth-reducing (reverse Cuthill-McKee) renumbering of the
- *   input cells.  jfnk_mesh_order() returns the map; jfnk_to_internal() and
- *   jfnk_to_external() permute vectors on the device.
+ *   Vectors: device pointers to n_cells * dim FP64 values in the INTERNAL
+ *   layout: the mesh's bandwidth-reducing (reverse Cuthill-McKee) cell order,
+ *   component-major ([component][cell], one contiguous array per displacement
+ *   component, so that consecutive GPU lanes touch consecutive addresses).
+ *   The EXTERNAL layout is the paper's blocked vector of Section 2.2:
+ *   interleaved [cell][component] in input cell order.  jfnk_to_internal()
+ *   and jfnk_to_external() convert on the device; jfnk_mesh_order() returns
+ *   the cell map.
  *   Ownership: the caller owns every vector and the workspace (e.g. torch
  *   tensors).  The library owns only the mesh handle (its packed device
  *   geometry and a few pinned host scalars), freed by jfnk_destroy_mesh().
@@ -149,7 +152,8 @@ jfnk_status jfnk_get_mesh_info(const jfnk_mesh* mesh, jfnk_mesh_info* info);
 
 /* old_of_new[i] = input cell index of internal cell i (host array [n_cells]). */
 jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new);
-/* d_out[internal order] <- d_in[input order], and the inverse; [n_cells][dim] FP64. */
+/* External (interleaved [cell][dim], input order) -> internal ([dim][cell],
+ * internal order), and the inverse.  Out-of-place; asynchronous. */
 jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 
@@ -161,7 +165,7 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
                                 int32_t precond, size_t* bytes);
 
 /* R(u) of Eq. (residual) (static, no body force) at load factor `load`.
- * d_u, d_R: [n_cells][dim]; d_R may not alias d_u.  Asynchronous. */
+ * d_u, d_R: internal layout; d_R may not alias d_u.  Asynchronous. */
 jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, double* d_R,
                           void* d_work, void* stream);
 

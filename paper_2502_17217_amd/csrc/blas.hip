@@ -32,22 +32,38 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
   return r;
 }
 
+// Two squared norms; each thread keeps four independent loads in flight per
+// vector (fixed element assignment, so the result is deterministic).
 __global__ __launch_bounds__(kBlock) void k_norm2_pair(const double* __restrict__ a,
                                                        const double* __restrict__ b, int64_t n,
                                                        double* __restrict__ partials) {
   __shared__ double sh[4];
-  double sa = 0, sb = 0;
+  double sa[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0};
   const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-    const double x = a[i], y = b[i];
-    sa = fma(x, x, sa);
-    sb = fma(y, y, sb);
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = a[i + q * stride];
+      y[q] = b[i + q * stride];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sa[q] = fma(x[q], x[q], sa[q]);
+      sb[q] = fma(y[q], y[q], sb[q]);
+    }
   }
-  sa = block_sum(sa, sh);
-  sb = block_sum(sb, sh);
+  for (int q = 0; i < n; i += stride, ++q) {
+    const double x = a[i], y = b[i];
+    sa[q & 3] = fma(x, x, sa[q & 3]);
+    sb[q & 3] = fma(y, y, sb[q & 3]);
+  }
+  double ta = block_sum((sa[0] + sa[1]) + (sa[2] + sa[3]), sh);
+  double tb = block_sum((sb[0] + sb[1]) + (sb[2] + sb[3]), sh);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = sa;
-    partials[2 * blockIdx.x + 1] = sb;
+    partials[2 * blockIdx.x] = ta;
+    partials[2 * blockIdx.x + 1] = tb;
   }
 }
 
@@ -70,6 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_eps_final(const double* __restrict__
 
 __global__ void k_set(double* d, double v) { d[0] = v; }
 
+// Interleaved input-order [cell][dim] <-> component-major internal-order [dim][cell].
 __global__ __launch_bounds__(kBlock) void k_permute(const int32_t* __restrict__ old_of_new,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ out, int64_t n_cells,
@@ -79,9 +96,9 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int32_t* __restrict__ 
   const int64_t o = old_of_new[i];
   for (int k = 0; k < dim; ++k) {
     if (to_internal)
-      out[i * dim + k] = in[o * dim + k];
+      out[k * n_cells + i] = in[o * dim + k];
     else
-      out[o * dim + k] = in[i * dim + k];
+      out[o * dim + k] = in[k * n_cells + i];
   }
 }
 
@@ -161,14 +178,15 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(double a, const double* __re
     y[i] = fma(a, x[i], b * z[i]);
 }
 
-// z[c*dim+k] = dinv[c] * r[c*dim+k]  (diagonal of the scalar approximate Jacobian)
+// z[k][c] = dinv[c] * r[k][c]  (diagonal of the scalar approximate Jacobian,
+// applied to every component of the component-major vector)
 __global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ dinv,
                                                    const double* __restrict__ r,
                                                    double* __restrict__ z, int64_t n_cells, int dim) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n_cells; c += stride) {
     const double s = dinv[c];
-    for (int k = 0; k < dim; ++k) z[c * dim + k] = s * r[c * dim + k];
+    for (int k = 0; k < dim; ++k) z[k * n_cells + c] = s * r[k * n_cells + c];
   }
 }
 

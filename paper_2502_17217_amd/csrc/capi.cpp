@@ -36,6 +36,15 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Transpose a row-major [rows][cols] host array (row stride `ld`) into
+// component-major [cols][rows].
+std::vector<double> to_soa(const std::vector<double>& a, int64_t rows, int cols, int ld) {
+  std::vector<double> out(size_t(rows) * cols);
+  for (int64_t r = 0; r < rows; ++r)
+    for (int k = 0; k < cols; ++k) out[size_t(k) * rows + r] = a[size_t(r) * ld + k];
+  return out;
+}
+
 template <class T>
 void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
   b.alloc(std::max<size_t>(v.size() * sizeof(T), 256));
@@ -46,7 +55,8 @@ void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
 size_t device_bytes_of(const HostMesh& h) {
   auto b = [](size_t x) { return std::max<size_t>(x, 256); };
   return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
-         b(h.xc.size() * 8) + b(h.face.size() * 8) + b(h.bface.size() * 8) +
+         b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
+         b(h.magG.size() * 8) + b(h.bface.size() * 8) +
          b(h.old_of_new.size() * 4) + b(size_t(h.n_cells) * 8);
 }
 
@@ -160,8 +170,14 @@ jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* ma
     upload(m->b_slice_ptr, h.slice_ptr, s);
     upload(m->b_slot_nb, h.slot_nb, s);
     upload(m->b_slot_fc, h.slot_fc, s);
-    upload(m->b_xc, h.xc, s);
-    upload(m->b_face, h.face, s);
+    upload(m->b_xc, to_soa(h.xc, h.n_cells, h.dim, h.dim), s);
+    upload(m->b_fG, to_soa(h.face, h.n_int, h.dim, kFaceRec), s);
+    {
+      std::vector<double> fw(h.n_int);
+      for (int64_t j = 0; j < h.n_int; ++j) fw[j] = h.face[j * kFaceRec + (h.dim == 3 ? 3 : 2)];
+      upload(m->b_fw, fw, s);
+    }
+    upload(m->b_magG, h.magG, s);
     upload(m->b_bface, h.bface, s);
     upload(m->b_order, h.old_of_new, s);
     std::vector<double> dinv(h.n_cells);
@@ -179,7 +195,10 @@ jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* ma
     d.slot_nb = m->b_slot_nb.as<int32_t>();
     d.slot_fc = m->b_slot_fc.as<int32_t>();
     d.xc = m->b_xc.as<double>();
-    d.face = m->b_face.as<double>();
+    d.n_int = int32_t(h.n_int);
+    d.fG = m->b_fG.as<double>();
+    d.fw = m->b_fw.as<double>();
+    d.magG = m->b_magG.as<double>();
     d.bface = m->b_bface.as<double>();
     d.mu = m->mat.mu;
     d.lam = m->mat.lam;
@@ -193,7 +212,9 @@ jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* ma
     in.n_boundary_faces = h.n_bnd;
     in.bandwidth = h.bandwidth;
     in.device_bytes = int64_t(m->b_slice_ptr.bytes + m->b_slot_nb.bytes + m->b_slot_fc.bytes +
-                              m->b_xc.bytes + m->b_face.bytes + m->b_bface.bytes + m->b_order.bytes +
+                              m->b_xc.bytes + m->b_fG.bytes + m->b_fw.bytes + m->b_magG.bytes +
+                              m->b_bface.bytes +
+                              m->b_order.bytes +
                               m->b_pc_dinv.bytes);
     in.n_slots = int64_t(h.slot_nb.size());
     in.setup_ms = now_ms() - t0;

@@ -6,6 +6,8 @@
 //               rebuilt from the cell centroids and face areas on the fly, so
 //               no per-slot least-squares vectors are stored:
 //               grad w_P = G_P^{-1} sum_f |Gamma|/(d.d) d (x) (w_N - w_P).
+//               It writes the record {w, grad w} of every cell (component-
+//               major arrays) for the second pass.
 //   k_flux:     face forces (Eq. divStressDiscret) + Rhie-Chow stabilisation
 //               (Eq. RhieChow) summed over the cell's faces in a fixed slot
 //               order, then either R(w) or (R(w) - R(u))/eps (Eq. JF).
@@ -17,6 +19,12 @@
 //   alpha K_bar [ |Delta| (w_N - w_P)/|d| - Delta . grad w_f ] |Gamma|
 //     = alpha K_bar |Gamma|^2 / (d . Gamma) [ (w_N - w_P) - d . grad w_f ],
 // since Delta = d/(d.n), |Delta|/|d| = 1/(d.n) and n = Gamma/|Gamma|.
+//
+// Data layout: vectors, centroids, face data and the per-cell record are
+// component-major (one array of n values per component) so that the 64 lanes
+// of a wavefront, which handle 64 consecutive cells, read consecutive
+// addresses for their own cell and -- in a bandwidth-reduced cell order --
+// nearly consecutive addresses for the same neighbour slot.
 //
 // Neo-Hookean total-Lagrangian face force (Appendix A/B): with a = cof(F) Gamma
 // and F^T a = J Gamma, (a . sigma) simplifies to
@@ -31,44 +39,28 @@ __device__ __forceinline__ int xcd_block(int bid, int nb_launch) {
   // Hardware hands consecutive workgroup ids to the 8 XCDs round-robin;
   // give each XCD one contiguous range of cell blocks so that neighbouring
   // cells (close in the bandwidth-reduced order) share an L2.
+#if JFNK_XCD_REMAP
   const int per = nb_launch / kNumXcd;
   return (bid % kNumXcd) * per + bid / kNumXcd;
+#else
+  return bid;
+#endif
 }
 
 template <int D>
 __device__ __forceinline__ void load_w(const double* __restrict__ u, const double* __restrict__ v,
-                                       double eps, int c, double (&w)[D]) {
+                                       double eps, int n, int c, double (&w)[D]) {
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double uk = u[size_t(c) * D + k];
-    w[k] = v ? fma(eps, v[size_t(c) * D + k], uk) : uk;
+    const double uk = u[size_t(k) * n + c];
+    w[k] = v ? fma(eps, v[size_t(k) * n + c], uk) : uk;
   }
 }
 
 template <int D>
-__device__ __forceinline__ void load_xc(const double* __restrict__ xc, int c, double (&x)[D]) {
+__device__ __forceinline__ void load_soa(const double* __restrict__ a, int n, int c, double (&x)[D]) {
 #pragma unroll
-  for (int k = 0; k < D; ++k) x[k] = xc[size_t(c) * D + k];
-}
-
-template <int D>
-__device__ __forceinline__ void load_grad(const double* __restrict__ g, int c, double (&o)[D][D]) {
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) o[i][j] = g[size_t(c) * D * D + i * D + j];
-}
-
-template <int D>
-__device__ __forceinline__ void load_gamma_w(const double* __restrict__ face, int f, double (&G)[D],
-                                             double& wf) {
-  const double2* r = reinterpret_cast<const double2*>(face + size_t(f) * kFaceRec);
-  const double2 a = r[0], b = r[1];
-  if constexpr (D == 3) {
-    G[0] = a.x; G[1] = a.y; G[2] = b.x; wf = b.y;
-  } else {
-    G[0] = a.x; G[1] = a.y; wf = b.x;
-  }
+  for (int k = 0; k < D; ++k) x[k] = a[size_t(k) * n + c];
 }
 
 // ---------------------------------------------------------------- laws
@@ -185,19 +177,39 @@ __device__ __forceinline__ void internal_face_force(const MeshDev& m, const doub
 }
 
 // ---------------------------------------------------------------- kernels
+// Slots are processed in unrolled chunks of kChunk: all slot indices of a
+// chunk are loaded first, then all gathers are issued, so that a wavefront
+// has many independent memory requests in flight.
+#ifndef JFNK_CHUNK
+#define JFNK_CHUNK 6
+#endif
+constexpr int kChunk = JFNK_CHUNK;
+
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_gradient(MeshDev m, const double* __restrict__ u,
+__device__ __forceinline__ void load_rec(const double* __restrict__ rec, int n, int c, double (&w)[D],
+                                         double (&g)[D][D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) w[k] = rec[size_t(k) * n + c];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) g[i][j] = rec[size_t(D + i * D + j) * n + c];
+}
+
+template <int D>
+__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev m, const double* __restrict__ u,
                                                      const double* __restrict__ v,
                                                      const double* __restrict__ d_eps,
-                                                     double* __restrict__ grad, int nb_real) {
+                                                     double* __restrict__ rec, int nb_real) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   if (lb >= nb_real) return;
-  const int c = lb * kBlock + threadIdx.x;
-  if (c >= m.n_cells) return;
+  const int c = lb * kFvBlock + threadIdx.x;
+  const int n = m.n_cells;
+  if (c >= n) return;
   const double eps = (v != nullptr) ? *d_eps : 0.0;
   double wP[D], xP[D];
-  load_w<D>(u, v, eps, c, wP);
-  load_xc<D>(m.xc, c, xP);
+  load_w<D>(u, v, eps, n, c, wP);
+  load_soa<D>(m.xc, n, c, xP);
   double Gs[D][D], M[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -206,36 +218,45 @@ __global__ __launch_bounds__(kBlock) void k_gradient(MeshDev m, const double* __
   const int slice = c / kSlice, lane = c % kSlice;
   const int s0 = m.slice_ptr[slice];
   const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
-  for (int k = 0; k < width; ++k) {
-    const int idx = s0 + k * kSlice + lane;
-    const int nb = m.slot_nb[idx];
-    if (nb < 0) continue;
-    int f = m.slot_fc[idx];
-    f = f >= 0 ? f : ~f;
-    double G[D], wf;
-    load_gamma_w<D>(m.face, f, G, wf);
-    double xN[D], wN[D];
-    load_xc<D>(m.xc, nb, xN);
-    load_w<D>(u, v, eps, nb, wN);
-    double d[D], dd = 0, GG = 0;
+  for (int k0 = 0; k0 < width; k0 += kChunk) {
+    int nb[kChunk], fc[kChunk];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      d[q] = xN[q] - xP[q];
-      dd = fma(d[q], d[q], dd);
-      GG = fma(G[q], G[q], GG);
+    for (int k = 0; k < kChunk; ++k) {
+      const int idx = s0 + (k0 + k) * kSlice + lane;
+      nb[k] = (k0 + k < width) ? m.slot_nb[idx] : kSlotPad;
+      fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
     }
-    const double wt = sqrt(GG) / dd;
+    double mg[kChunk], xN[kChunk][D], wN[kChunk][D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const double wd = wt * d[i];
+    for (int k = 0; k < kChunk; ++k) {
+      const int nn = nb[k] >= 0 ? nb[k] : c;
+      const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
+      mg[k] = nb[k] >= 0 ? m.magG[f] : 0.0;
+      load_soa<D>(m.xc, n, nn, xN[k]);
+      load_w<D>(u, v, eps, n, nn, wN[k]);
+    }
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        Gs[i][j] = fma(wd, d[j], Gs[i][j]);
-        M[i][j] = fma(wd, wN[j] - wP[j], M[i][j]);
+    for (int k = 0; k < kChunk; ++k) {
+      if (nb[k] < 0) continue;
+      double d[D], dd = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        d[q] = xN[k][q] - xP[q];
+        dd = fma(d[q], d[q], dd);
+      }
+      const double wt = mg[k] / dd;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double wd = wt * d[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          Gs[i][j] = fma(wd, d[j], Gs[i][j]);
+          M[i][j] = fma(wd, wN[k][j] - wP[j], M[i][j]);
+        }
       }
     }
   }
-  double out[D][D];
+  double g[D][D];
   if constexpr (D == 3) {
     const double a00 = Gs[1][1] * Gs[2][2] - Gs[1][2] * Gs[1][2];
     const double a01 = Gs[0][2] * Gs[1][2] - Gs[0][1] * Gs[2][2];
@@ -248,149 +269,155 @@ __global__ __launch_bounds__(kBlock) void k_gradient(MeshDev m, const double* __
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-        out[i][j] = (A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]) * inv;
+      for (int j = 0; j < 3; ++j) g[i][j] = (A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]) * inv;
   } else {
     const double inv = 1.0 / (Gs[0][0] * Gs[1][1] - Gs[0][1] * Gs[0][1]);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      out[0][j] = (Gs[1][1] * M[0][j] - Gs[0][1] * M[1][j]) * inv;
-      out[1][j] = (-Gs[0][1] * M[0][j] + Gs[0][0] * M[1][j]) * inv;
+      g[0][j] = (Gs[1][1] * M[0][j] - Gs[0][1] * M[1][j]) * inv;
+      g[1][j] = (-Gs[0][1] * M[0][j] + Gs[0][0] * M[1][j]) * inv;
     }
   }
 #pragma unroll
+  for (int k = 0; k < D; ++k) rec[size_t(k) * n + c] = wP[k];
+#pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) grad[size_t(c) * D * D + i * D + j] = out[i][j];
+    for (int j = 0; j < D; ++j) rec[size_t(D + i * D + j) * n + c] = g[i][j];
 }
 
 template <int D, int LAW>
-__global__ __launch_bounds__(kBlock) void k_flux(MeshDev m, const double* __restrict__ u,
-                                                 const double* __restrict__ v,
+__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, const double* __restrict__ rec,
                                                  const double* __restrict__ d_eps,
-                                                 const double* __restrict__ grad,
                                                  const double* __restrict__ Ru,
                                                  double* __restrict__ out, double load, int nb_real) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   if (lb >= nb_real) return;
-  const int c = lb * kBlock + threadIdx.x;
-  if (c >= m.n_cells) return;
-  const double eps = (v != nullptr) ? *d_eps : 0.0;
+  const int c = lb * kFvBlock + threadIdx.x;
+  const int n = m.n_cells;
+  if (c >= n) return;
   double wP[D], xP[D], gP[D][D], R[D];
-  load_w<D>(u, v, eps, c, wP);
-  load_xc<D>(m.xc, c, xP);
-  load_grad<D>(grad, c, gP);
+  load_rec<D>(rec, n, c, wP, gP);
+  load_soa<D>(m.xc, n, c, xP);
 #pragma unroll
   for (int k = 0; k < D; ++k) R[k] = 0.0;
   const int slice = c / kSlice, lane = c % kSlice;
   const int s0 = m.slice_ptr[slice];
   const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
-  for (int k = 0; k < width; ++k) {
-    const int idx = s0 + k * kSlice + lane;
-    const int nb = m.slot_nb[idx];
-    if (nb >= 0) {
-      const int fs = m.slot_fc[idx];
-      const bool own = fs >= 0;
-      const int f = own ? fs : ~fs;
-      double G[D], wf, xN[D], wN[D], gN[D][D];
-      load_gamma_w<D>(m.face, f, G, wf);
-      load_xc<D>(m.xc, nb, xN);
-      load_w<D>(u, v, eps, nb, wN);
-      load_grad<D>(grad, nb, gN);
-      // canonical operands: A = owner, B = neighbour of the face
-      double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
+  for (int k0 = 0; k0 < width; k0 += kChunk) {
+    int nb[kChunk], fc[kChunk];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        xA[i] = own ? xP[i] : xN[i];
-        xB[i] = own ? xN[i] : xP[i];
-        wA[i] = own ? wP[i] : wN[i];
-        wB[i] = own ? wN[i] : wP[i];
+    for (int k = 0; k < kChunk; ++k) {
+      const int idx = s0 + (k0 + k) * kSlice + lane;
+      nb[k] = (k0 + k < width) ? m.slot_nb[idx] : kSlotPad;
+      fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
+    }
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-          gA[i][j] = own ? gP[i][j] : gN[i][j];
-          gB[i][j] = own ? gN[i][j] : gP[i][j];
+    for (int k = 0; k < kChunk; ++k) {
+      if (nb[k] >= 0) {
+        const bool own = fc[k] >= 0;
+        const int f = own ? fc[k] : ~fc[k];
+        double G[D], xN[D], wN[D], gN[D][D];
+        load_soa<D>(m.fG, m.n_int, f, G);
+        const double wf = m.fw[f];
+        load_rec<D>(rec, n, nb[k], wN, gN);
+        load_soa<D>(m.xc, n, nb[k], xN);
+        // canonical operands: A = owner, B = neighbour of the face
+        double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          xA[i] = own ? xP[i] : xN[i];
+          xB[i] = own ? xN[i] : xP[i];
+          wA[i] = own ? wP[i] : wN[i];
+          wB[i] = own ? wN[i] : wP[i];
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            gA[i][j] = own ? gP[i][j] : gN[i][j];
+            gB[i][j] = own ? gN[i][j] : gP[i][j];
+          }
         }
-      }
-      internal_face_force<D, LAW>(m, G, wf, xA, xB, wA, wB, gA, gB, fo);
+        internal_face_force<D, LAW>(m, G, wf, xA, xB, wA, wB, gA, gB, fo);
 #pragma unroll
-      for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
-    } else if (nb == kSlotBoundary) {
-      const double* r = m.bface + size_t(m.slot_fc[idx]) * kBfaceRec;
-      const int type = int(r[9]);
-      if (type == kBcDisp) {
-        double G[D], db[D], ub[D], t[D];
+        for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
+      } else if (nb[k] == kSlotBoundary) {
+        const double* r = m.bface + size_t(fc[k]) * kBfaceRec;
+        const int type = int(r[9]);
+        if (type == kBcDisp) {
+          double G[D], db[D], ub[D], t[D];
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          G[q] = r[q];
-          db[q] = r[3 + q];
-          ub[q] = load * r[6 + q];
+          for (int q = 0; q < D; ++q) {
+            G[q] = r[q];
+            db[q] = r[3 + q];
+            ub[q] = load * r[6 + q];
+          }
+          traction<D, LAW>(m, gP, G, t);
+          double dG = 0, GG = 0;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            dG = fma(db[q], G[q], dG);
+            GG = fma(G[q], G[q], GG);
+          }
+          const double coef = m.aK * GG / dG;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            double dg = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
+            R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
+          }
+        } else {
+          // traction: |Gamma| T_bar, pressure: -p Gamma (stored pre-multiplied)
+#pragma unroll
+          for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
         }
-        traction<D, LAW>(m, gP, G, t);
-        double dG = 0, GG = 0;
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-          dG = fma(db[q], G[q], dG);
-          GG = fma(G[q], G[q], GG);
-        }
-        const double coef = m.aK * GG / dG;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          double dg = 0;
-#pragma unroll
-          for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
-          R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
-        }
-      } else {
-        // traction: |Gamma| T_bar, pressure: -p Gamma (stored pre-multiplied)
-#pragma unroll
-        for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
       }
     }
   }
   if (Ru != nullptr) {
+    const double eps = *d_eps;
     const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q)
-      out[size_t(c) * D + q] = eps != 0.0 ? (R[q] - Ru[size_t(c) * D + q]) * ie : 0.0;
+      out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - Ru[size_t(q) * n + c]) * ie : 0.0;
   } else {
 #pragma unroll
-    for (int q = 0; q < D; ++q) out[size_t(c) * D + q] = R[q];
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
   }
 }
 
 inline void grid_for(int n_cells, int& nb_real, int& nb_launch) {
-  nb_real = (n_cells + kBlock - 1) / kBlock;
+  nb_real = (n_cells + kFvBlock - 1) / kFvBlock;
   nb_launch = ((nb_real + kNumXcd - 1) / kNumXcd) * kNumXcd;
 }
 
 }  // namespace
 
 void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
-                     double* grad, hipStream_t s) {
+                     double* rec, hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
   if (m.dim == 3)
-    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kBlock), 0, s, m, u, v, d_eps, grad, nr);
+    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, d_eps, rec, nr);
   else
-    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kBlock), 0, s, m, u, v, d_eps, grad, nr);
+    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, d_eps, rec, nr);
   JFNK_HIP(hipGetLastError());
 }
 
-void launch_flux(const MeshDev& m, const double* u, const double* v, const double* d_eps,
-                 const double* grad, const double* Ru, double* out, double load, hipStream_t s) {
+void launch_flux(const MeshDev& m, const double* rec, const double* d_eps, const double* Ru,
+                 double* out, double load, hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
-  const dim3 g(nl), b(kBlock);
+  const dim3 g(nl), b(kFvBlock);
   if (m.dim == 3) {
     if (m.law == JFNK_NEO_HOOKEAN)
-      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
     else
-      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
   } else {
     if (m.law == JFNK_NEO_HOOKEAN)
-      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
     else
-      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, u, v, d_eps, grad, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
   }
   JFNK_HIP(hipGetLastError());
 }

@@ -38,6 +38,17 @@ void set_last_error(const std::string& msg);
 constexpr int kSlice = 64;
 constexpr int kBlock = 256;
 constexpr int kNumXcd = 8;
+// launch shape of the two cell passes (tuned on gfx950)
+#ifndef JFNK_FV_BLOCK
+#define JFNK_FV_BLOCK 256
+#endif
+#ifndef JFNK_FV_MINWAVES
+#define JFNK_FV_MINWAVES 1
+#endif
+#ifndef JFNK_XCD_REMAP
+#define JFNK_XCD_REMAP 1
+#endif
+constexpr int kFvBlock = JFNK_FV_BLOCK;
 // slot_nb values
 constexpr int kSlotBoundary = -1;
 constexpr int kSlotPad = -2;
@@ -48,18 +59,24 @@ constexpr int kBfaceRec = 10;
 // boundary type codes in the record
 constexpr int kBcDisp = 1, kBcTrac = 2, kBcPres = 3;
 
-// Read-only device view of one mesh, passed by value to kernels.
+// Read-only device view of one mesh, passed by value to kernels.  Cell and
+// face arrays are component-major (structure of arrays) so that 64 lanes
+// reading consecutive cells or faces touch consecutive addresses.
 struct MeshDev {
   int32_t n_cells;
   int32_t dim;
   int32_t n_slices;
   int32_t law;
+  int32_t n_int;
+  int32_t pad_;
   const int32_t* slice_ptr;  // [n_slices + 1], in slots (multiples of kSlice)
   const int32_t* slot_nb;    // neighbour cell, kSlotBoundary or kSlotPad
   const int32_t* slot_fc;    // internal: face (owner side) or ~face (neighbour side); boundary: bface
-  const double* xc;          // [n_cells][dim] cell centroids
-  const double* face;        // [n_internal][4] {Gamma (owner-outward), w_f} (2-D: Gx, Gy, w, 0)
-  const double* bface;       // [n_boundary][10]
+  const double* xc;          // [dim][n_cells] cell centroids
+  const double* fG;          // [dim][n_int] Gamma_f, outward from the owner
+  const double* fw;          // [n_int] interpolation weight w_f of the owner
+  const double* magG;        // [n_int] |Gamma_f|
+  const double* bface;       // [n_boundary][10] {Gamma, d_b, value, type}
   double mu, lam, kappa;     // law constants (Appendix B)
   double aK;                 // alpha_rc * K_bar, K_bar = 2 mu + lambda
 };
@@ -71,6 +88,7 @@ struct HostMesh {
   std::vector<int32_t> old_of_new, new_of_old;
   std::vector<double> xc, vol;
   std::vector<double> face;         // n_int * kFaceRec
+  std::vector<double> magG;         // n_int, |Gamma_f| (least-squares weights)
   std::vector<int32_t> fown, fnb;   // internal faces, owner < neighbour
   std::vector<double> bface;        // n_bnd * kBfaceRec
   std::vector<int32_t> bown;
@@ -130,7 +148,7 @@ struct jfnk_mesh {
   jfnk::Material mat;
   jfnk::HostMesh host;
   jfnk::MeshDev dev{};
-  jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_face, b_bface, b_order, b_pc_dinv;
+  jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_order, b_pc_dinv;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   jfnk_mesh_info info{};
   jfnk::AmgHierarchy* amg = nullptr;
@@ -140,12 +158,15 @@ struct jfnk_mesh {
 namespace jfnk {
 
 // ---- kernel launchers (fv_kernels.hip, blas.hip) ----
-// grad_w[cell][dim*dim] of w = u + eps*v (v may be null; eps from *d_eps if non-null).
+// Per-cell record of w = u + eps*v (v may be null; eps from *d_eps), written by
+// the gradient pass and gathered by the flux pass: {w, grad w} stored
+// component-major, rec_doubles(dim) arrays of n_cells doubles.
+inline int rec_doubles(int dim) { return dim + dim * dim; }
 void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
-                     double* grad, hipStream_t s);
+                     double* rec, hipStream_t s);
 // out = (R(w) - Ru)/eps if Ru != null else R(w).
-void launch_flux(const MeshDev& m, const double* u, const double* v, const double* d_eps,
-                 const double* grad, const double* Ru, double* out, double load, hipStream_t s);
+void launch_flux(const MeshDev& m, const double* rec, const double* d_eps, const double* Ru,
+                 double* out, double load, hipStream_t s);
 // d_eps = sqrt(eps_mach) sqrt(1 + |u|)/|v|, from two norms; partials: >= kRedBlocks*2 doubles.
 void launch_eps(const double* u, const double* v, int64_t n, double* partials, double* d_eps,
                 hipStream_t s);
@@ -153,6 +174,6 @@ void launch_set_scalar(double* d, double value, hipStream_t s);
 void launch_permute(const int32_t* old_of_new, const double* in, double* out, int64_t n_cells,
                     int dim, bool to_internal, hipStream_t s);
 
-constexpr int kRedBlocks = 512;  // fixed number of partial sums for reductions
+constexpr int kRedBlocks = 1024;  // fixed number of partial sums for reductions
 
 }  // namespace jfnk

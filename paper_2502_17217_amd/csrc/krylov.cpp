@@ -43,7 +43,7 @@ void residual_into(jfnk_mesh* m, double load, const double* u, double* R, FvWork
   launch_gradient(m->dev, u, nullptr, nullptr, fw.grad, s);
   if (t >= 0) p.end(t, s);
   t = p.on ? p.begin(2, s) : -1;
-  launch_flux(m->dev, u, nullptr, nullptr, fw.grad, nullptr, R, load, s);
+  launch_flux(m->dev, fw.grad, nullptr, nullptr, R, load, s);
   if (t >= 0) p.end(t, s);
 }
 
@@ -61,7 +61,7 @@ void jv_into(jfnk_mesh* m, double load, const double* u, const double* Ru, const
   launch_gradient(m->dev, u, v, d_eps, fw.grad, s);
   if (t >= 0) p.end(t, s);
   t = p.on ? p.begin(2, s) : -1;
-  launch_flux(m->dev, u, v, d_eps, fw.grad, Ru, Jv, load, s);
+  launch_flux(m->dev, fw.grad, d_eps, Ru, Jv, load, s);
   if (t >= 0) p.end(t, s);
 }
 

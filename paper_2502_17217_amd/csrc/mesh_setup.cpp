@@ -323,8 +323,24 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   std::stable_sort(fperm.begin(), fperm.end(), [&](int64_t x, int64_t y) {
     return o2[x] != o2[y] ? o2[x] < o2[y] : n2[x] < n2[y];
   });
+  // Face numbering for coalesced access: faces are grouped by the 64-cell
+  // slice of their owner, then by their rank among the owner's faces, then by
+  // the owner's lane, so that the k-th owned face of 64 consecutive cells
+  // occupies consecutive records.
+  {
+    std::vector<int32_t> rank(ni, 0);
+    for (int64_t j = 1; j < ni; ++j)
+      if (o2[fperm[j]] == o2[fperm[j - 1]]) rank[fperm[j]] = rank[fperm[j - 1]] + 1;
+    std::stable_sort(fperm.begin(), fperm.end(), [&](int64_t x, int64_t y) {
+      const int32_t sx = o2[x] / kSlice, sy = o2[y] / kSlice;
+      if (sx != sy) return sx < sy;
+      if (rank[x] != rank[y]) return rank[x] < rank[y];
+      return o2[x] < o2[y];
+    });
+  }
   const double aKp = mat.alpha_pc * mat.Kbar;
   hm.face.assign(ni * kFaceRec, 0.0);
+  hm.magG.assign(ni, 0.0);
   hm.fown.resize(ni);
   hm.fnb.resize(ni);
   hm.pc_off.resize(ni);
@@ -346,6 +362,7 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
     } else {
       r[0] = g.x; r[1] = g.y; r[2] = w; r[3] = 0.0;
     }
+    hm.magG[j] = mg;
     hm.fown[j] = A;
     hm.fnb[j] = B;
     double a = aKp * mg / dn;    // alpha K_bar |Delta| |Gamma| / |d| = alpha K_bar |Gamma| / (d.n)

@@ -27,12 +27,12 @@ struct Carver {
 
 // Regions used by jfnk_residual / jfnk_jv.
 struct FvWork {
-  double* grad = nullptr;      // [n_cells][dim*dim]
+  double* grad = nullptr;      // [n_cells][rec_doubles(dim)] per-cell {w, x_c, grad w}
   double* ru = nullptr;        // [n_dof] R(u) when not supplied
   double* partials = nullptr;  // [kRedBlocks * kMaxBasis]
   double* scalars = nullptr;   // [64]: 0 eps, 1.. reserved
   void carve(Carver& c, int64_t n_cells, int dim) {
-    grad = c.take<double>(size_t(n_cells) * dim * dim);
+    grad = c.take<double>(size_t(n_cells) * rec_doubles(dim));
     ru = c.take<double>(size_t(n_cells) * dim);
     partials = c.take<double>(size_t(kRedBlocks) * kMaxBasis);
     scalars = c.take<double>(64);
