@@ -1,18 +1,449 @@
-// FP32 aggregation-AMG preconditioner (placeholder until the hierarchy is built).
+// Host setup and V-cycle driver of the FP32 smoothed-aggregation AMG
+// preconditioner built on the compact-stencil approximate Jacobian J_tilde
+// (Section 3.1, coefficients after Eq. SegSys; used as the preconditioning
+// matrix in Section 3.2).
+//
+// J_tilde = -A (x) I_dim with A the scalar symmetric, diagonally dominant
+// M-matrix sum_f alpha K_bar |Delta||Gamma|/|d| (neighbour differences) plus
+// the displacement-face terms on the diagonal.  The preconditioner returns
+// z ~ J_tilde^{-1} r = -A^{-1} r by one V-cycle on A applied to every
+// displacement component at once:
+//   setup (FP64, once per mesh): greedy aggregation on the strength graph
+//   |a_ij| >= theta sqrt(a_ii a_jj) (theta = 0.08, which keeps the weak
+//   direction of stretched cells out of the aggregates), smoothed prolongator
+//   P = (I - omega D^{-1} A) P_tent with omega = 4/(3 lambda_max(D^{-1}A)),
+//   Galerkin coarse operators R A P with R = P^T, a dense inverse on the
+//   coarsest level; everything is stored on the device in FP32;
+//   apply (FP32 kernels): Chebyshev(k) pre-smoothing from zero on the interval
+//   [lambda_max/30, 1.1 lambda_max] of D^{-1} A, restriction, recursion,
+//   prolongation, Chebyshev(k) post-smoothing.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "amg.h"
 #include "solver.h"
 
 namespace jfnk {
 
-struct AmgHierarchy {};
+namespace {
 
-size_t amg_work_floats(const jfnk_mesh*) { return 0; }
+constexpr double kTheta = 0.08;
+constexpr int64_t kDenseMax = 400;
+constexpr int kMaxLevels = 16;
 
-void amg_setup(jfnk_mesh*, hipStream_t) {
-  throw Error{JFNK_E_ARG, "AMG preconditioner is not available in this build"};
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-void amg_apply(jfnk_mesh*, int, const double*, double*, float*, hipStream_t) {
-  throw Error{JFNK_E_ARG, "AMG preconditioner is not available in this build"};
+HostCsr fine_operator(const HostMesh& h) {
+  HostCsr A;
+  const int64_t n = h.n_cells;
+  A.n = A.m = n;
+  std::vector<int32_t> cnt(n + 1, 1);
+  for (int64_t j = 0; j < h.n_int; ++j) {
+    cnt[h.fown[j]]++;
+    cnt[h.fnb[j]]++;
+  }
+  A.ptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) A.ptr[i + 1] = A.ptr[i] + cnt[i];
+  A.col.resize(A.ptr[n]);
+  A.val.resize(A.ptr[n]);
+  std::vector<int32_t> pos(A.ptr.begin(), A.ptr.end() - 1);
+  for (int64_t i = 0; i < n; ++i) {
+    A.col[pos[i]] = int32_t(i);
+    A.val[pos[i]++] = -h.pc_diag[i];
+  }
+  for (int64_t j = 0; j < h.n_int; ++j) {
+    const int32_t a = h.fown[j], b = h.fnb[j];
+    A.col[pos[a]] = b;
+    A.val[pos[a]++] = -h.pc_off[j];
+    A.col[pos[b]] = a;
+    A.val[pos[b]++] = -h.pc_off[j];
+  }
+  // sort each row by column
+  std::vector<std::pair<int32_t, double>> tmp;
+  for (int64_t i = 0; i < n; ++i) {
+    tmp.clear();
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) tmp.emplace_back(A.col[k], A.val[k]);
+    std::sort(tmp.begin(), tmp.end());
+    for (size_t k = 0; k < tmp.size(); ++k) {
+      A.col[A.ptr[i] + k] = tmp[k].first;
+      A.val[A.ptr[i] + k] = tmp[k].second;
+    }
+  }
+  return A;
+}
+
+std::vector<double> diagonal(const HostCsr& A) {
+  std::vector<double> d(A.n, 0.0);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (A.col[k] == i) d[i] = A.val[k];
+  return d;
+}
+
+// lambda_max of D^{-1} A by power iteration from a fixed start vector.
+double lambda_max(const HostCsr& A, const std::vector<double>& d) {
+  const int64_t n = A.n;
+  std::vector<double> x(n), y(n);
+  for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
+  double lam = 1.0;
+  for (int it = 0; it < 20; ++it) {
+    double nrm = 0;
+    for (int64_t i = 0; i < n; ++i) nrm += x[i] * x[i];
+    nrm = std::sqrt(nrm);
+    for (int64_t i = 0; i < n; ++i) x[i] /= nrm;
+    double num = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      double s = 0;
+      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+      y[i] = s / d[i];
+      num += y[i] * x[i];
+    }
+    lam = num;
+    x.swap(y);
+  }
+  return lam;
+}
+
+std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, int64_t& nagg) {
+  const int64_t n = A.n;
+  auto strong = [&](int64_t i, int32_t k) {
+    const int32_t j = A.col[k];
+    return j != i && std::fabs(A.val[k]) >= kTheta * std::sqrt(std::fabs(d[i] * d[j]));
+  };
+  std::vector<int32_t> agg(n, -1);
+  nagg = 0;
+  // pass 1: seed aggregates whose strong neighbourhood is still free
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free = true, any = false;
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k)) {
+        any = true;
+        if (agg[A.col[k]] >= 0) {
+          free = false;
+          break;
+        }
+      }
+    if (!free || !any) continue;
+    agg[i] = int32_t(nagg);
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k)) agg[A.col[k]] = int32_t(nagg);
+    ++nagg;
+  }
+  // pass 2: attach leftovers to the most strongly connected pass-1 aggregate
+  std::vector<int32_t> agg1 = agg;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg1[i] >= 0) continue;
+    double best = 0;
+    int32_t ba = -1;
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k) && agg1[A.col[k]] >= 0 && std::fabs(A.val[k]) > best) {
+        best = std::fabs(A.val[k]);
+        ba = agg1[A.col[k]];
+      }
+    if (ba >= 0) agg[i] = ba;
+  }
+  // pass 3: remaining nodes with their free strong neighbours, or singletons
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = int32_t(nagg);
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = int32_t(nagg);
+    ++nagg;
+  }
+  return agg;
+}
+
+// P = (I - omega D^{-1} A) P_tent
+HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& d,
+                             const std::vector<int32_t>& agg, int64_t nagg, double omega) {
+  HostCsr P;
+  P.n = A.n;
+  P.m = nagg;
+  P.ptr.assign(A.n + 1, 0);
+  std::vector<double> acc(nagg, 0.0);
+  std::vector<int32_t> mark(nagg, -1), cols;
+  for (int64_t i = 0; i < A.n; ++i) {
+    cols.clear();
+    auto add = [&](int32_t c, double v) {
+      if (mark[c] != i) {
+        mark[c] = int32_t(i);
+        acc[c] = 0.0;
+        cols.push_back(c);
+      }
+      acc[c] += v;
+    };
+    add(agg[i], 1.0);
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) add(agg[A.col[k]], -omega * A.val[k] / d[i]);
+    std::sort(cols.begin(), cols.end());
+    for (int32_t c : cols) {
+      if (acc[c] == 0.0) continue;
+      P.col.push_back(c);
+      P.val.push_back(acc[c]);
+    }
+    P.ptr[i + 1] = int32_t(P.col.size());
+  }
+  return P;
+}
+
+HostCsr transpose(const HostCsr& M) {
+  HostCsr T;
+  T.n = M.m;
+  T.m = M.n;
+  T.ptr.assign(M.m + 1, 0);
+  for (int32_t c : M.col) T.ptr[c + 1]++;
+  for (int64_t i = 0; i < M.m; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(M.col.size());
+  T.val.resize(M.val.size());
+  std::vector<int32_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int64_t i = 0; i < M.n; ++i)
+    for (int32_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+      const int32_t c = M.col[k];
+      T.col[pos[c]] = int32_t(i);
+      T.val[pos[c]++] = M.val[k];
+    }
+  return T;
+}
+
+HostCsr multiply(const HostCsr& X, const HostCsr& Y) {
+  HostCsr Z;
+  Z.n = X.n;
+  Z.m = Y.m;
+  Z.ptr.assign(X.n + 1, 0);
+  std::vector<double> acc(Y.m, 0.0);
+  std::vector<int32_t> mark(Y.m, -1), cols;
+  for (int64_t i = 0; i < X.n; ++i) {
+    cols.clear();
+    for (int32_t a = X.ptr[i]; a < X.ptr[i + 1]; ++a) {
+      const int32_t j = X.col[a];
+      const double xv = X.val[a];
+      for (int32_t b = Y.ptr[j]; b < Y.ptr[j + 1]; ++b) {
+        const int32_t c = Y.col[b];
+        if (mark[c] != i) {
+          mark[c] = int32_t(i);
+          acc[c] = 0.0;
+          cols.push_back(c);
+        }
+        acc[c] += xv * Y.val[b];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t c : cols) {
+      Z.col.push_back(c);
+      Z.val.push_back(acc[c]);
+    }
+    Z.ptr[i + 1] = int32_t(Z.col.size());
+  }
+  return Z;
+}
+
+// Inverse of a small SPD matrix by Cholesky (FP64), returned row-major in FP32.
+std::vector<float> dense_inverse(const HostCsr& A) {
+  const int64_t n = A.n;
+  std::vector<double> L(n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) L[i * n + A.col[k]] = A.val[k];
+  double shift = 0;
+  for (int64_t i = 0; i < n; ++i) shift = std::max(shift, std::fabs(L[i * n + i]));
+  shift *= 1e-12;
+  for (int64_t j = 0; j < n; ++j) {
+    double s = L[j * n + j] + shift;
+    for (int64_t k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    JFNK_REQUIRE(s > 0, JFNK_E_MESH, "amg: coarse operator not positive definite");
+    const double ljj = std::sqrt(s);
+    L[j * n + j] = ljj;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double t = L[i * n + j];
+      for (int64_t k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / ljj;
+    }
+  }
+  std::vector<float> inv(n * n);
+  std::vector<double> x(n);
+  for (int64_t c = 0; c < n; ++c) {
+    for (int64_t i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int64_t k = 0; k < i; ++k) t -= L[i * n + k] * x[k];
+      x[i] = t / L[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double t = x[i];
+      for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * x[k];
+      x[i] = t / L[i * n + i];
+    }
+    for (int64_t i = 0; i < n; ++i) inv[i * n + c] = float(x[i]);
+  }
+  return inv;
+}
+
+struct ChebCoef {
+  double inv_theta;
+  std::vector<double> c1, c2;
+};
+
+ChebCoef cheb_coefficients(double lmax, int degree) {
+  const double hi = 1.1 * lmax, lo = hi / 30.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  ChebCoef c;
+  c.inv_theta = 1.0 / theta;
+  double rho_old = 1.0 / sigma;
+  for (int k = 1; k < degree; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_old);
+    c.c1.push_back(rho * rho_old);
+    c.c2.push_back(2.0 * rho / delta);
+    rho_old = rho;
+  }
+  return c;
+}
+
+}  // namespace
+
+void DevCsr::upload(const HostCsr& h, hipStream_t s) {
+  n = int32_t(h.n);
+  m = int32_t(h.m);
+  std::vector<float> v(h.val.begin(), h.val.end());
+  ptr.alloc(std::max<size_t>(h.ptr.size() * 4, 256));
+  col.alloc(std::max<size_t>(h.col.size() * 4, 256));
+  val.alloc(std::max<size_t>(v.size() * 4, 256));
+  JFNK_HIP(hipMemcpyAsync(ptr.p, h.ptr.data(), h.ptr.size() * 4, hipMemcpyHostToDevice, s));
+  if (!h.col.empty()) {
+    JFNK_HIP(hipMemcpyAsync(col.p, h.col.data(), h.col.size() * 4, hipMemcpyHostToDevice, s));
+    JFNK_HIP(hipMemcpyAsync(val.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  JFNK_HIP(hipStreamSynchronize(s));
+}
+
+size_t amg_work_floats(const jfnk_mesh* m) {
+  // upper bound before setup: five work vectors per level with a geometric
+  // level-size bound (each level at most 3/4 of the previous one)
+  const int64_t n = m->host.n_cells;
+  return size_t(5) * m->host.dim * size_t(4 * n + 64 * kMaxLevels) + 2 * kDenseMax * m->host.dim;
+}
+
+void amg_setup(jfnk_mesh* m, hipStream_t s) {
+  if (m->amg) return;
+  const double t0 = now_ms();
+  auto H = new AmgHierarchy();
+  try {
+    H->dim = m->host.dim;
+    HostCsr A = fine_operator(m->host);
+    const double nnz0 = double(A.nnz());
+    size_t off = 0;
+    auto take = [&](int64_t count) {
+      size_t o = off;
+      off += size_t(count) * H->dim;
+      off = (off + 63) & ~size_t(63);
+      return o;
+    };
+    while (true) {
+      AmgLevel L;
+      L.n = A.n;
+      std::vector<double> d = diagonal(A);
+      const bool last = A.n <= kDenseMax || int(H->levels.size()) + 1 >= kMaxLevels;
+      H->op_complexity += double(A.nnz()) / nnz0;
+      if (last) {
+        L.off_x = take(A.n);
+        L.off_b = take(A.n);
+        H->coarse_inv.alloc(size_t(A.n) * A.n * 4);
+        std::vector<float> inv = dense_inverse(A);
+        JFNK_HIP(hipMemcpyAsync(H->coarse_inv.p, inv.data(), inv.size() * 4, hipMemcpyHostToDevice, s));
+        JFNK_HIP(hipStreamSynchronize(s));
+        H->n_coarse = A.n;
+        H->levels.push_back(std::move(L));
+        break;
+      }
+      L.lmax = lambda_max(A, d);
+      int64_t nagg = 0;
+      std::vector<int32_t> agg = aggregate(A, d, nagg);
+      HostCsr P = smoothed_prolongator(A, d, agg, nagg, 4.0 / (3.0 * L.lmax));
+      HostCsr R = transpose(P);
+      HostCsr Ac = multiply(R, multiply(A, P));
+      L.A.upload(A, s);
+      L.P.upload(P, s);
+      L.R.upload(R, s);
+      std::vector<float> dinv(A.n);
+      for (int64_t i = 0; i < A.n; ++i) dinv[i] = float(1.0 / d[i]);
+      L.dinv.alloc(dinv.size() * 4);
+      JFNK_HIP(hipMemcpyAsync(L.dinv.p, dinv.data(), dinv.size() * 4, hipMemcpyHostToDevice, s));
+      JFNK_HIP(hipStreamSynchronize(s));
+      L.off_x = take(A.n);
+      L.off_b = take(A.n);
+      L.off_r = take(A.n);
+      L.off_d0 = take(A.n);
+      L.off_d1 = take(A.n);
+      H->levels.push_back(std::move(L));
+      if (nagg >= A.n) {  // no coarsening possible: solve densely if small, else stop here
+        JFNK_REQUIRE(nagg <= kDenseMax, JFNK_E_MESH, "amg: aggregation stalled on a large level");
+      }
+      A = std::move(Ac);
+    }
+    H->work_floats = off;
+    JFNK_REQUIRE(H->work_floats <= amg_work_floats(m), JFNK_E_ARG,
+                 "amg: hierarchy larger than the workspace bound");
+    H->setup_ms = now_ms() - t0;
+  } catch (...) {
+    delete H;
+    throw;
+  }
+  m->amg = H;
+}
+
+namespace {
+
+void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s) {
+  const AmgLevel& L = H.levels[l];
+  const int dim = H.dim;
+  float* x = w + L.off_x;
+  float* b = w + L.off_b;
+  if (l + 1 == H.levels.size()) {
+    amg_dense(H.coarse_inv.as<float>(), b, x, int(H.n_coarse), dim, s);
+    return;
+  }
+  float* r = w + L.off_r;
+  float* d0 = w + L.off_d0;
+  float* d1 = w + L.off_d1;
+  const float* dinv = L.dinv.as<float>();
+  ChebCoef cc = cheb_coefficients(L.lmax, degree);
+  // pre-smoothing from x = 0
+  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s);
+  for (int k = 0; k + 1 < degree; ++k) {
+    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s);
+    std::swap(d0, d1);
+  }
+  // coarse-grid correction
+  amg_residual(L.A, b, x, r, dim, s);
+  const AmgLevel& C = H.levels[l + 1];
+  amg_spmv(L.R, r, w + C.off_b, false, dim, s);
+  vcycle(H, l + 1, degree, w, s);
+  amg_spmv(L.P, w + C.off_x, x, true, dim, s);
+  // post-smoothing
+  d0 = w + L.off_d0;
+  d1 = w + L.off_d1;
+  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s);
+  for (int k = 0; k + 1 < degree; ++k) {
+    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s);
+    std::swap(d0, d1);
+  }
+}
+
+}  // namespace
+
+void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s) {
+  JFNK_REQUIRE(m->amg != nullptr, JFNK_E_ARG, "amg: not set up");
+  JFNK_REQUIRE(work != nullptr, JFNK_E_ARG, "amg: no workspace");
+  const AmgHierarchy& H = *m->amg;
+  const AmgLevel& L0 = H.levels[0];
+  Profiler& p = m->prof;
+  const int t = p.on ? p.begin(3, s) : -1;
+  amg_cast_in(r, work + L0.off_b, L0.n, H.dim, s);
+  vcycle(H, 0, cheb_degree, work, s);
+  amg_cast_out(work + L0.off_x, z, L0.n, H.dim, s);
+  if (t >= 0) p.end(t, s);
 }
 
 void amg_destroy(AmgHierarchy* a) { delete a; }

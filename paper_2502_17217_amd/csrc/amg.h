@@ -1,0 +1,62 @@
+// FP32 smoothed-aggregation AMG for the compact-stencil approximate Jacobian.
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace jfnk {
+
+// Host CSR matrix (FP64) used during setup.
+struct HostCsr {
+  int64_t n = 0, m = 0;              // rows, cols
+  std::vector<int32_t> ptr, col;
+  std::vector<double> val;
+  int64_t nnz() const { return int64_t(col.size()); }
+};
+
+// Device CSR matrix (FP32 values).
+struct DevCsr {
+  int32_t n = 0, m = 0;
+  DevBuf ptr, col, val;
+  void upload(const HostCsr& h, hipStream_t s);
+};
+
+struct AmgLevel {
+  int64_t n = 0;
+  DevCsr A, P, R;         // operator; prolongation (n x n_next); restriction = P^T
+  DevBuf dinv;            // FP32 inverse diagonal of A
+  double lmax = 2.0;      // largest eigenvalue estimate of D^{-1} A
+  size_t off_x = 0, off_b = 0, off_r = 0, off_d0 = 0, off_d1 = 0;  // workspace offsets (floats)
+};
+
+struct AmgHierarchy {
+  std::vector<AmgLevel> levels;      // last level is solved by the dense inverse
+  DevBuf coarse_inv;                 // [n_c][n_c] FP32
+  int64_t n_coarse = 0;
+  int dim = 3;
+  size_t work_floats = 0;
+  double op_complexity = 0;          // sum nnz(A_l) / nnz(A_0)
+  double setup_ms = 0;
+};
+
+// ---- kernels (amg_kernels.hip); vectors are component-major FP32 [dim][n] ----
+void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s);
+void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s);
+// Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d
+void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
+                     float inv_theta, int dim, hipStream_t s);
+// Chebyshev start from a given x: r = D^-1 (b - A x), d = r/theta, x += d
+void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
+                    float inv_theta, int dim, hipStream_t s);
+// one Chebyshev step: r -= D^-1 A d_in; d_out = c1 d_in + c2 r; x += d_out
+void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
+                   float c1, float c2, int dim, hipStream_t s);
+// r = b - A x
+void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s);
+// y = M x (restriction) or y += M x (prolongation, accumulate = true)
+void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s);
+// x = inv * b (dense, n x n)
+void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s);
+
+}  // namespace jfnk

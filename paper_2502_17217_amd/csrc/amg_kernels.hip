@@ -1,0 +1,217 @@
+// FP32 kernels of the AMG V-cycle (gfx950).  One thread per matrix row;
+// every kernel handles all displacement components (component-major arrays
+// [dim][n]) so that a matrix row is read once for the dim right-hand sides.
+#include "amg.h"
+
+namespace jfnk {
+
+namespace {
+
+constexpr int kB = 256;
+
+inline int blocks_for(int64_t n) { return int((n + kB - 1) / kB); }
+
+template <int D>
+__device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                        const float* __restrict__ val, const float* __restrict__ x,
+                                        int m, int i, float (&s)[D]) {
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = 0.f;
+  const int a = ptr[i], b = ptr[i + 1];
+  for (int k = a; k < b; ++k) {
+    const float v = val[k];
+    const int j = col[k];
+#pragma unroll
+    for (int q = 0; q < D; ++q) s[q] = fmaf(v, x[size_t(q) * m + j], s[q]);
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_cast_in(const double* __restrict__ r, float* __restrict__ b,
+                                                int64_t total) {
+  const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
+  if (i < total) b[i] = float(r[i]);
+}
+
+__global__ __launch_bounds__(kB) void k_cast_out(const float* __restrict__ x, double* __restrict__ z,
+                                                 int64_t total) {
+  const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
+  if (i < total) z[i] = -double(x[i]);   // J_tilde = -A
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restrict__ dinv,
+                                                    const float* __restrict__ b, float* __restrict__ x,
+                                                    float* __restrict__ r, float* __restrict__ d,
+                                                    float inv_theta) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const float di = dinv[i];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    const float ri = di * b[o];
+    const float dd = ri * inv_theta;
+    r[o] = ri;
+    d[o] = dd;
+    x[o] = dd;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const float* __restrict__ val,
+                                                   const float* __restrict__ dinv,
+                                                   const float* __restrict__ b, const float* __restrict__ x,
+                                                   float* __restrict__ r, float* __restrict__ d,
+                                                   float inv_theta) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float s[D];
+  row_dot<D>(ptr, col, val, x, n, i, s);
+  const float di = dinv[i];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    const float ri = di * (b[o] - s[q]);
+    r[o] = ri;
+    d[o] = ri * inv_theta;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restrict__ d, float* __restrict__ x) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int q = 0; q < D; ++q) x[size_t(q) * n + i] += d[size_t(q) * n + i];
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const float* __restrict__ val,
+                                                  const float* __restrict__ dinv,
+                                                  const float* __restrict__ d_in, float* __restrict__ d_out,
+                                                  float* __restrict__ r, float* __restrict__ x, float c1,
+                                                  float c2) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float s[D];
+  row_dot<D>(ptr, col, val, d_in, n, i, s);
+  const float di = dinv[i];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    const float ri = r[o] - di * s[q];
+    const float dd = fmaf(c1, d_in[o], c2 * ri);
+    r[o] = ri;
+    d_out[o] = dd;
+    x[o] += dd;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const float* __restrict__ val, const float* __restrict__ b,
+                                                 const float* __restrict__ x, float* __restrict__ r) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float s[D];
+  row_dot<D>(ptr, col, val, x, n, i, s);
+#pragma unroll
+  for (int q = 0; q < D; ++q) r[size_t(q) * n + i] = b[size_t(q) * n + i] - s[q];
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __restrict__ ptr,
+                                             const int32_t* __restrict__ col, const float* __restrict__ val,
+                                             const float* __restrict__ x, float* __restrict__ y, int accumulate) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float s[D];
+  row_dot<D>(ptr, col, val, x, m, i, s);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    y[o] = accumulate ? y[o] + s[q] : s[q];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, const float* __restrict__ b,
+                                              float* __restrict__ x, int n) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float s[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = 0.f;
+  for (int j = 0; j < n; ++j) {
+    const float a = inv[size_t(i) * n + j];
+#pragma unroll
+    for (int q = 0; q < D; ++q) s[q] = fmaf(a, b[size_t(q) * n + j], s[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) x[size_t(q) * n + i] = s[q];
+}
+
+}  // namespace
+
+#define JFNK_DIM_DISPATCH(dim, KERNEL, ...)                                        \
+  do {                                                                             \
+    if ((dim) == 3)                                                                \
+      hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__);                                  \
+    else                                                                           \
+      hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__);                                  \
+    JFNK_HIP(hipGetLastError());                                                   \
+  } while (0)
+
+void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s) {
+  const int64_t t = n * dim;
+  hipLaunchKernelGGL(k_cast_in, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t);
+  JFNK_HIP(hipGetLastError());
+}
+
+void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s) {
+  const int64_t t = n * dim;
+  hipLaunchKernelGGL(k_cast_out, dim3(blocks_for(t)), dim3(kB), 0, s, x, z, t);
+  JFNK_HIP(hipGetLastError());
+}
+
+void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
+                     float inv_theta, int dim, hipStream_t s) {
+  JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dinv, b, x, r, d,
+                    inv_theta);
+}
+
+void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
+                    float inv_theta, int dim, hipStream_t s) {
+  // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
+  // by other rows' products in the first pass)
+  JFNK_DIM_DISPATCH(dim, k_cheb_start, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
+                    A.col.as<int32_t>(), A.val.as<float>(), dinv, b, x, r, d, inv_theta);
+  JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x);
+}
+
+void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
+                   float c1, float c2, int dim, hipStream_t s) {
+  JFNK_DIM_DISPATCH(dim, k_cheb_step, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
+                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2);
+}
+
+void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s) {
+  JFNK_DIM_DISPATCH(dim, k_residual, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
+                    A.col.as<int32_t>(), A.val.as<float>(), b, x, r);
+}
+
+void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s) {
+  JFNK_DIM_DISPATCH(dim, k_spmv, dim3(blocks_for(M.n)), dim3(kB), 0, s, M.n, M.m, M.ptr.as<int32_t>(),
+                    M.col.as<int32_t>(), M.val.as<float>(), x, y, accumulate ? 1 : 0);
+}
+
+void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s) {
+  JFNK_DIM_DISPATCH(dim, k_dense, dim3(blocks_for(n)), dim3(kB), 0, s, inv, b, x, n);
+}
+
+}  // namespace jfnk

@@ -129,8 +129,10 @@ Profiler::~Profiler() {
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
-DevBuf::~DevBuf() {
+void DevBuf::release() noexcept {
   if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
 }
 
 void DevBuf::alloc(size_t b) {

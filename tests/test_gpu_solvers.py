@@ -100,3 +100,49 @@ def test_neo_hookean_cantilever_increments(lib):
     assert st == lib.OK
     assert err <= 1e-8
     assert np.abs(ug.reshape(-1, 3)[:, 1]).max() > 0.05
+
+
+# ---------------------------------------------------------------- FP32 AMG preconditioner
+# The preconditioner's internals (aggregates, smoother interval) only change
+# iteration counts: they are checked through the converged FP64 solution and
+# through the iteration count against the Jacobi preconditioner.
+
+def _newton_both(lib, m, mat, n_inc, rtol, eta, restart=30, precond="amg32", max_it=20000):
+    ug, st, stats = _solve_gpu(lib, m, mat, n_increments=n_inc, max_newton_it=20, rtol=rtol, eta=eta,
+                               restart=restart, max_it=max_it, precond=precond, cheb_degree=3)
+    return ug, st, stats
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_amg32_fgmres_linear_elastic(lib, dim):
+    if dim == 2:
+        m = mg.box_mesh_2d(61, 47, 1.3, 1.0, jitter=0.15, seed=21)
+    else:
+        m = mg.box_mesh_3d(17, 15, 13, 1.0, 0.9, 0.8, jitter=0.15, seed=22)
+    mg.set_patch(m, "xmin", "displacement", (0.0,) * dim)
+    mg.set_patch(m, "xmax", "traction", (1e6, -3e5, 2e5)[:dim])
+    mat = mg.Material("linear_elastic", 200e9, 0.3)
+    pr = prepare(m, mat)
+    uo, _ = o_newton(pr, n_increments=1, rtol=1e-6, max_newton_it=3, eta=1e-12, precond="lu",
+                     max_krylov_it=600)
+    ua, st_a, sa = _newton_both(lib, m, mat, 1, 1e-11, 1e-11, restart=50, precond="amg32")
+    uj, st_j, sj = _newton_both(lib, m, mat, 1, 1e-11, 1e-11, restart=50, precond="jacobi")
+    ea = np.linalg.norm(ua - uo) / np.linalg.norm(uo)
+    ej = np.linalg.norm(uj - uo) / np.linalg.norm(uo)
+    print(dim, "amg32 err", ea, sa["gmres_it"], " jacobi err", ej, sj["gmres_it"])
+    assert st_a == lib.OK
+    assert ea <= 1e-8
+    assert sa["gmres_it"] * 3 < sj["gmres_it"]
+
+
+def test_amg32_neo_hookean_cantilever(lib):
+    m = mg.cantilever_mesh(40, 8, 4, L=(10.0, 1.0, 1.0), tau=400.0)
+    mat = mg.Material("neo_hookean", 1e6, 0.45)
+    pr = prepare(m, mat)
+    uo, so = o_newton(pr, n_increments=4, rtol=1e-9, max_newton_it=15, eta=1e-6, precond="lu",
+                      max_krylov_it=3000)
+    ug, st, stats = _newton_both(lib, m, mat, 4, 1e-9, 1e-6, restart=50, precond="amg32")
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print("NH amg32 rel L2", err, stats, so["newton_it"], so["gmres_it"])
+    assert st == lib.OK
+    assert err <= 1e-7
