@@ -120,15 +120,17 @@ typedef struct {
 typedef struct jfnk_mesh jfnk_mesh;
 
 typedef struct {
-  int64_t n_cells;
+  int64_t n_cells;             /* internal cells (a batch adds alignment padding between meshes) */
   int32_t dim;
-  int64_t n_dof;               /* n_cells * dim */
+  int64_t n_dof;               /* length of an internal vector: n_cells * dim */
   int64_t n_internal_faces;
   int64_t n_boundary_faces;
   int64_t bandwidth;           /* max |P - N| over internal faces after renumbering */
   int64_t device_bytes;        /* device memory owned by the handle */
   double setup_ms;             /* host time spent in jfnk_create_mesh */
   int64_t n_slots;             /* cell-face slots in the packed slot map (incl. padding) */
+  int32_t n_segments;          /* meshes in the handle (1, or the batch size) */
+  int64_t n_dof_external;      /* length of an external vector (sum over meshes of n_cells * dim) */
 } jfnk_mesh_info;
 
 /* Build the mesh handle: validates the mesh, renumbers cells, computes the
@@ -245,6 +247,30 @@ jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, dou
 jfnk_status jfnk_profile_enable(jfnk_mesh* mesh, int32_t on);
 jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms /*[4]*/, int64_t* calls /*[4]*/,
                               int32_t reset);
+
+/* ---- Batches: many independent meshes solved together ----
+ * A batch handle holds n meshes (segments) with their own materials.  Its
+ * internal vectors cover all meshes: mesh s occupies internal cells
+ * [cell_off_s, cell_off_s + n_cells_s) with cell_off_s a multiple of 256
+ * (the gaps are padding cells whose entries stay zero), and every mesh is
+ * processed by its own workgroups in the same kernel launches.  External
+ * vectors concatenate the meshes' interleaved input-order vectors
+ * (ext_off_s cells into the concatenation).  On a batch, jfnk_residual /
+ * jfnk_jv / jfnk_gmres act on every mesh with its own material, J v step
+ * (eps_used, stats: host arrays [n]), and convergence; the preconditioners
+ * are built on the block-diagonal union of the meshes' approximate
+ * Jacobians.  All meshes of a batch must have the same dim. */
+jfnk_status jfnk_create_batch(const jfnk_mesh_desc* descs, const jfnk_material* mats, int32_t n,
+                              void* stream, jfnk_mesh** out);
+jfnk_status jfnk_segment_info(const jfnk_mesh* mesh, int32_t seg, int64_t* cell_off, int64_t* n_cells,
+                              int64_t* ext_off);
+/* Newton with load increments for every mesh of a batch in lockstep;
+ * n_increments: host [n] (NULL: opts->n_increments for all).  Meshes finish
+ * independently; stats and seg_status (host [n], may be NULL) are per mesh;
+ * the return value is the first non-OK mesh status. */
+jfnk_status jfnk_newton_solve_batch(jfnk_mesh* mesh, const int32_t* n_increments,
+                                    const jfnk_newton_opts* opts, double* d_u, jfnk_stats* stats,
+                                    jfnk_status* seg_status, void* d_work, void* stream);
 
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* jfnk_last_error(void);

@@ -1,5 +1,11 @@
 // Launchers of the Krylov vector kernels (blas.hip).  All pointers are
 // device pointers; all calls are asynchronous on stream s.
+//
+// Vectors are internal vectors of a mesh or batch: component-major
+// [dim][n_cells] over the union numbering.  Reductions are per segment:
+// every workgroup sums one tile of kFvBlock cells (all components) in a
+// fixed order, and one workgroup per segment then sums that segment's tiles
+// in order, so a segment's result depends only on its own values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,19 +16,28 @@ namespace jfnk {
 
 constexpr int kMaxBasis = 256;  // max restart length + 1 supported by the kernels
 
-// out[k] = V_k . w for k < nk (V_k = V + k*ldv); partials needs kRedBlocks*kMaxBasis doubles.
-// accumulate: out[k] += instead of =.
-void blas_mdot(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
-               double* out, bool accumulate, hipStream_t s);
-// w += sign * sum_{k<nk} h[k] V_k  (h on the device)
-void blas_combine(const double* V, int64_t ldv, int nk, const double* d_h, double sign, double* w,
-                  int64_t n, hipStream_t s);
-// y = x / *d_scale (invert) or x * *d_scale
-void blas_scale_dev(const double* x, const double* d_scale, bool invert, double* y, int64_t n,
-                    hipStream_t s);
-// y = a x + b y
+struct SegLayout {
+  int32_t n_cells = 0;               // union cells (N); a vector has dim * N entries
+  int32_t dim = 0;
+  int32_t n_seg = 0;
+  int32_t n_blocks = 0;              // tiles of kFvBlock cells
+  const int32_t* seg_of_block = nullptr;
+  const int32_t* block_first = nullptr;  // [n_seg + 1]
+};
+
+// out[s * ldo + k] (+)= V_k . w restricted to segment s, k < nk (V_k = V + k*ldv).
+// partials: n_blocks * kMaxBasis doubles.  Segments with active[s] == 0 are skipped.
+void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* w, double* partials,
+               double* out, int ldo, bool accumulate, const int32_t* active, hipStream_t s);
+// w += sign * sum_{k<nk} h[s * ldh + k] V_k on each segment s
+void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
+                  double sign, double* w, const int32_t* active, hipStream_t s);
+// y = scale[s] * x on each segment s
+void blas_scale_seg(const SegLayout& L, const double* x, const double* scale, double* y,
+                    const int32_t* active, hipStream_t s);
+// y = a x + b y (all entries)
 void blas_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
-// y = a x + b z
+// y = a x + b z (all entries)
 void blas_lincomb(double a, const double* x, double b, const double* z, double* y, int64_t n,
                   hipStream_t s);
 // z = D^{-1} r with one scalar per cell applied to every component

@@ -1,10 +1,10 @@
 // Vector kernels for the Krylov solver and the J.v step size, gfx950.
 //
-// Reductions are deterministic: a fixed grid of kRedBlocks workgroups, a
-// fixed element-to-thread assignment (grid stride), a fixed butterfly over
-// the 64 lanes of a wavefront, a fixed order over the 4 wavefronts of a
-// workgroup, and a second single-workgroup pass over the partial sums in a
-// fixed order.  The result depends only on the vector length and values.
+// Reductions are deterministic and per segment: one workgroup per tile of
+// kFvBlock cells (fixed butterfly over the 64 lanes of a wavefront, fixed
+// order over the 4 wavefronts), then one workgroup per segment sums that
+// segment's tile partials in a fixed order.  A segment's result depends only
+// on its own values, not on the other segments of a batch.
 #include <cfloat>
 
 #include "blas.h"
@@ -34,132 +34,156 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
 
 // Two squared norms; each thread keeps four independent loads in flight per
 // vector (fixed element assignment, so the result is deterministic).
-__global__ __launch_bounds__(kBlock) void k_norm2_pair(const double* __restrict__ a,
-                                                       const double* __restrict__ b, int64_t n,
+// Per-tile partial sums of |a|^2 and |b|^2 (tile = kFvBlock cells, all
+// components).
+__global__ __launch_bounds__(kBlock) void k_norm2_pair(SegLayout L, const double* __restrict__ a,
+                                                       const double* __restrict__ b,
+                                                       const int32_t* __restrict__ active,
                                                        double* __restrict__ partials) {
   __shared__ double sh[4];
-  double sa[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0};
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    double x[4], y[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      x[q] = a[i + q * stride];
-      y[q] = b[i + q * stride];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      sa[q] = fma(x[q], x[q], sa[q]);
-      sb[q] = fma(y[q], y[q], sb[q]);
-    }
-  }
-  for (int q = 0; i < n; i += stride, ++q) {
-    const double x = a[i], y = b[i];
-    sa[q & 3] = fma(x, x, sa[q & 3]);
-    sb[q & 3] = fma(y, y, sb[q & 3]);
-  }
-  double ta = block_sum((sa[0] + sa[1]) + (sa[2] + sa[3]), sh);
-  double tb = block_sum((sb[0] + sb[1]) + (sb[2] + sb[3]), sh);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = ta;
-    partials[2 * blockIdx.x + 1] = tb;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_eps_final(const double* __restrict__ partials, int nb,
-                                                      double* __restrict__ d_eps) {
-  __shared__ double sh[4];
+  const int blk = blockIdx.x;
+  if (active != nullptr && active[L.seg_of_block[blk]] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
   double sa = 0, sb = 0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
-    sa += partials[2 * i];
-    sb += partials[2 * i + 1];
+  if (c < L.n_cells) {
+    for (int q = 0; q < L.dim; ++q) {
+      const double x = a[size_t(q) * L.n_cells + c], y = b[size_t(q) * L.n_cells + c];
+      sa = fma(x, x, sa);
+      sb = fma(y, y, sb);
+    }
   }
   sa = block_sum(sa, sh);
   sb = block_sum(sb, sh);
   if (threadIdx.x == 0) {
-    // sqrt(eps_mach) * sqrt(1 + |u|) / |v|  (zero v -> zero step, J v = 0)
-    const double sqrt_eps = 1.4901161193847656e-08;
-    d_eps[0] = sb > 0 ? sqrt_eps * sqrt(1.0 + sqrt(sa)) / sqrt(sb) : 0.0;
+    partials[2 * size_t(blk)] = sa;
+    partials[2 * size_t(blk) + 1] = sb;
   }
 }
 
-__global__ void k_set(double* d, double v) { d[0] = v; }
+// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| (a zero v_s gives eps 0 and J v = 0).
+__global__ __launch_bounds__(kBlock) void k_eps_final(SegLayout L, const double* __restrict__ partials,
+                                                      const int32_t* __restrict__ active,
+                                                      double* __restrict__ d_eps) {
+  __shared__ double sh[4];
+  const int seg = blockIdx.x;
+  if (active != nullptr && active[seg] == 0) return;
+  double sa = 0, sb = 0;
+  for (int b = L.block_first[seg] + threadIdx.x; b < L.block_first[seg + 1]; b += kBlock) {
+    sa += partials[2 * size_t(b)];
+    sb += partials[2 * size_t(b) + 1];
+  }
+  sa = block_sum(sa, sh);
+  sb = block_sum(sb, sh);
+  if (threadIdx.x == 0) {
+    const double sqrt_eps = 1.4901161193847656e-08;
+    d_eps[seg] = sb > 0 ? sqrt_eps * sqrt(1.0 + sqrt(sa)) / sqrt(sb) : 0.0;
+  }
+}
 
-// Interleaved input-order [cell][dim] <-> component-major internal-order [dim][cell].
-__global__ __launch_bounds__(kBlock) void k_permute(const int32_t* __restrict__ old_of_new,
+__global__ void k_set_n(double* d, int n, const double* src) {
+  const int i = threadIdx.x;
+  if (i < n) d[i] = src[i];
+}
+
+// External interleaved [cell][dim] (concatenated meshes, input order) <->
+// internal component-major [dim][cell] (union order, padding cells zero).
+__global__ __launch_bounds__(kBlock) void k_permute(const int32_t* __restrict__ ext_of_int,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ out, int64_t n_cells,
                                                     int dim, int to_internal) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n_cells) return;
-  const int64_t o = old_of_new[i];
+  const int64_t e = ext_of_int[i];
   for (int k = 0; k < dim; ++k) {
     if (to_internal)
-      out[k * n_cells + i] = in[o * dim + k];
-    else
-      out[o * dim + k] = in[k * n_cells + i];
+      out[k * n_cells + i] = e >= 0 ? in[e * dim + k] : 0.0;
+    else if (e >= 0)
+      out[e * dim + k] = in[k * n_cells + i];
   }
 }
 
-// partials[b * ldp + k0 + k] = block b's share of V_{k0+k} . w, k < nv (nv <= 8)
-__global__ __launch_bounds__(kBlock) void k_mdot8(const double* __restrict__ V, int64_t ldv, int k0,
-                                                  int nv, const double* __restrict__ w, int64_t n,
+// partials[blk * ldp + k0 + k] = tile blk's share of V_{k0+k} . w, k < nv (nv <= 8)
+__global__ __launch_bounds__(kBlock) void k_mdot8(SegLayout L, const double* __restrict__ V, int64_t ldv,
+                                                  int k0, int nv, const double* __restrict__ w,
+                                                  const int32_t* __restrict__ active,
                                                   double* __restrict__ partials, int ldp) {
   __shared__ double sh[4];
+  const int blk = blockIdx.x;
+  if (active != nullptr && active[L.seg_of_block[blk]] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
   double acc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-    const double wi = w[i];
+  if (c < L.n_cells) {
+    for (int q = 0; q < L.dim; ++q) {
+      const size_t o = size_t(q) * L.n_cells + c;
+      const double wi = w[o];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < nv) acc[k] = fma(V[(k0 + k) * ldv + i], wi, acc[k]);
+      for (int k = 0; k < 8; ++k)
+        if (k < nv) acc[k] = fma(V[(k0 + k) * ldv + o], wi, acc[k]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (k < nv) {
       const double s = block_sum(acc[k], sh);
-      if (threadIdx.x == 0) partials[int64_t(blockIdx.x) * ldp + k0 + k] = s;
+      if (threadIdx.x == 0) partials[size_t(blk) * ldp + k0 + k] = s;
     }
   }
 }
 
-// out[k] (+)= sum_b partials[b * ldp + k] for k < nk; one workgroup per k.
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(const double* __restrict__ partials, int nb,
-                                                        int ldp, double* __restrict__ out,
-                                                        int accumulate) {
+// out[seg * ldo + k] (+)= sum of the segment's tile partials, in tile order.
+__global__ __launch_bounds__(kBlock) void k_reduce_seg(SegLayout L, const double* __restrict__ partials,
+                                                       int ldp, const int32_t* __restrict__ active,
+                                                       double* __restrict__ out, int ldo, int accumulate) {
   __shared__ double sh[4];
-  const int k = blockIdx.x;
+  const int k = blockIdx.x, seg = blockIdx.y;
+  if (active != nullptr && active[seg] == 0) return;
   double s = 0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[int64_t(b) * ldp + k];
+  for (int b = L.block_first[seg] + threadIdx.x; b < L.block_first[seg + 1]; b += kBlock)
+    s += partials[size_t(b) * ldp + k];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
-}
-
-// w[i] -= sum_{k<nk} h[k] V_k[i]  (sign = -1) or y[i] += sum h[k] V_k[i] (sign = +1)
-__global__ __launch_bounds__(kBlock) void k_combine(const double* __restrict__ V, int64_t ldv, int nk,
-                                                    const double* __restrict__ h, double sign,
-                                                    double* __restrict__ w, int64_t n) {
-  __shared__ double hs[kMaxBasis];
-  for (int k = threadIdx.x; k < nk; k += kBlock) hs[k] = h[k];
-  __syncthreads();
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-    double s = 0;
-    for (int k = 0; k < nk; ++k) s = fma(hs[k], V[k * ldv + i], s);
-    w[i] = fma(sign, s, w[i]);
+  if (threadIdx.x == 0) {
+    const size_t o = size_t(seg) * ldo + k;
+    out[o] = accumulate ? out[o] + s : s;
   }
 }
 
-// y = x * (1/ *d_scale), or y = x * *d_scale when invert == 0
-__global__ __launch_bounds__(kBlock) void k_scale_dev(const double* __restrict__ x,
-                                                      const double* __restrict__ d_scale, int invert,
-                                                      double* __restrict__ y, int64_t n) {
-  const double s = invert ? 1.0 / d_scale[0] : d_scale[0];
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) y[i] = x[i] * s;
+// w += sign * sum_{k<nk} h[seg * ldh + k] V_k on the tile's segment
+__global__ __launch_bounds__(kBlock) void k_combine(SegLayout L, const double* __restrict__ V, int64_t ldv,
+                                                    int nk, const double* __restrict__ h, int ldh,
+                                                    double sign, const int32_t* __restrict__ active,
+                                                    double* __restrict__ w) {
+  __shared__ double hs[kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (active != nullptr && active[seg] == 0) return;
+  for (int k = threadIdx.x; k < nk; k += kBlock) hs[k] = h[size_t(seg) * ldh + k];
+  __syncthreads();
+  const int c = blk * kFvBlock + threadIdx.x;
+  if (c >= L.n_cells) return;
+  for (int q = 0; q < L.dim; ++q) {
+    const size_t o = size_t(q) * L.n_cells + c;
+    double s = 0;
+    for (int k = 0; k < nk; ++k) s = fma(hs[k], V[k * ldv + o], s);
+    w[o] = fma(sign, s, w[o]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_seg(SegLayout L, const double* __restrict__ x,
+                                                      const double* __restrict__ scale,
+                                                      const int32_t* __restrict__ active,
+                                                      double* __restrict__ y) {
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (active != nullptr && active[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  if (c >= L.n_cells) return;
+  const double f = scale[seg];
+  for (int q = 0; q < L.dim; ++q) {
+    const size_t o = size_t(q) * L.n_cells + c;
+    y[o] = f * x[o];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_axpby(double a, const double* __restrict__ x, double b,
@@ -197,49 +221,53 @@ inline int grid_stride_blocks(int64_t n) {
 
 }  // namespace
 
-void launch_eps(const double* u, const double* v, int64_t n, double* partials, double* d_eps,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_norm2_pair, dim3(kRedBlocks), dim3(kBlock), 0, s, u, v, n, partials);
-  hipLaunchKernelGGL(k_eps_final, dim3(1), dim3(kBlock), 0, s, partials, kRedBlocks, d_eps);
+void launch_eps(const MeshDev& m, const int32_t* block_first, const double* u, const double* v,
+                double* partials, double* d_eps, const int32_t* active, hipStream_t s) {
+  SegLayout L;
+  L.n_cells = m.n_cells;
+  L.dim = m.dim;
+  L.n_seg = m.n_seg;
+  L.n_blocks = (m.n_cells + kFvBlock - 1) / kFvBlock;
+  L.seg_of_block = m.seg_of_block;
+  L.block_first = block_first;
+  hipLaunchKernelGGL(k_norm2_pair, dim3(L.n_blocks), dim3(kBlock), 0, s, L, u, v, active, partials);
+  hipLaunchKernelGGL(k_eps_final, dim3(L.n_seg), dim3(kBlock), 0, s, L, partials, active, d_eps);
   JFNK_HIP(hipGetLastError());
 }
 
-void launch_set_scalar(double* d, double value, hipStream_t s) {
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, s, d, value);
-  JFNK_HIP(hipGetLastError());
+void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s) {
+  JFNK_HIP(hipMemcpyAsync(d, h_values, sizeof(double) * n, hipMemcpyHostToDevice, s));
 }
 
-void launch_permute(const int32_t* old_of_new, const double* in, double* out, int64_t n_cells,
-                    int dim, bool to_internal, hipStream_t s) {
+void launch_permute(const int32_t* ext_of_int, const double* in, double* out, int64_t n_cells, int dim,
+                    bool to_internal, hipStream_t s) {
   const int nb = int((n_cells + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, s, old_of_new, in, out, n_cells, dim,
+  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, s, ext_of_int, in, out, n_cells, dim,
                      to_internal ? 1 : 0);
   JFNK_HIP(hipGetLastError());
 }
 
-void blas_mdot(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
-               double* out, bool accumulate, hipStream_t s) {
+void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* w, double* partials,
+               double* out, int ldo, bool accumulate, const int32_t* active, hipStream_t s) {
   for (int k0 = 0; k0 < nk; k0 += 8) {
     const int nv = nk - k0 < 8 ? nk - k0 : 8;
-    hipLaunchKernelGGL(k_mdot8, dim3(kRedBlocks), dim3(kBlock), 0, s, V, ldv, k0, nv, w, n, partials,
+    hipLaunchKernelGGL(k_mdot8, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, k0, nv, w, active, partials,
                        kMaxBasis);
   }
-  hipLaunchKernelGGL(k_reduce_cols, dim3(nk), dim3(kBlock), 0, s, partials, kRedBlocks, kMaxBasis, out,
-                     accumulate ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce_seg, dim3(nk, L.n_seg), dim3(kBlock), 0, s, L, partials, kMaxBasis, active, out,
+                     ldo, accumulate ? 1 : 0);
   JFNK_HIP(hipGetLastError());
 }
 
-void blas_combine(const double* V, int64_t ldv, int nk, const double* d_h, double sign, double* w,
-                  int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, V, ldv, nk, d_h, sign,
-                     w, n);
+void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
+                  double sign, double* w, const int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign, active, w);
   JFNK_HIP(hipGetLastError());
 }
 
-void blas_scale_dev(const double* x, const double* d_scale, bool invert, double* y, int64_t n,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_dev, dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, x, d_scale,
-                     invert ? 1 : 0, y, n);
+void blas_scale_seg(const SegLayout& L, const double* x, const double* scale, double* y,
+                    const int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_seg, dim3(L.n_blocks), dim3(kBlock), 0, s, L, x, scale, active, y);
   JFNK_HIP(hipGetLastError());
 }
 

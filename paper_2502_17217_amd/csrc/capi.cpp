@@ -56,8 +56,8 @@ size_t device_bytes_of(const HostMesh& h) {
   auto b = [](size_t x) { return std::max<size_t>(x, 256); };
   return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
          b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
-         b(h.magG.size() * 8) + b(h.bface.size() * 8) +
-         b(h.old_of_new.size() * 4) + b(size_t(h.n_cells) * 8);
+         b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
+         b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256;
 }
 
 void check_mesh(const jfnk_mesh* m) {
@@ -158,69 +158,111 @@ const char* jfnk_last_error(void) { return g_last_error.c_str(); }
 
 const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
 
+namespace jfnk {
+namespace {
+
+// Build the union of the handle's segments and upload it.
+void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
+  UnionArrays ua;
+  build_union(m, ua);
+  const HostMesh& h = m.host;
+  const int dim = h.dim;
+  upload(m.b_slice_ptr, ua.slice_ptr, s);
+  upload(m.b_slot_nb, ua.slot_nb, s);
+  upload(m.b_slot_fc, ua.slot_fc, s);
+  upload(m.b_xc, to_soa(ua.xc, h.n_cells, dim, dim), s);
+  upload(m.b_fG, to_soa(ua.face, h.n_int, dim, kFaceRec), s);
+  {
+    std::vector<double> fw(h.n_int);
+    for (int64_t j = 0; j < h.n_int; ++j) fw[j] = ua.face[j * kFaceRec + (dim == 3 ? 3 : 2)];
+    upload(m.b_fw, fw, s);
+  }
+  upload(m.b_magG, ua.magG, s);
+  upload(m.b_bface, ua.bface, s);
+  upload(m.b_ext, ua.ext, s);
+  upload(m.b_pc_dinv, ua.pc_dinv, s);
+  upload(m.b_seg_of_block, ua.seg_of_block, s);
+  upload(m.b_seg, ua.seg, s);
+  upload(m.b_block_first, m.block_first, s);
+  JFNK_HIP(hipStreamSynchronize(s));
+  const int S = m.n_seg();
+  m.pinned_doubles = size_t(4 * kMaxBasis + 8) * size_t(std::max(S, 1)) + 64;
+  JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.pinned), sizeof(double) * m.pinned_doubles,
+                         hipHostMallocDefault));
+  MeshDev& d = m.dev;
+  d.n_cells = int32_t(h.n_cells);
+  d.dim = dim;
+  d.n_slices = int32_t(ua.slice_ptr.size() - 1);
+  d.n_int = int32_t(h.n_int);
+  d.n_seg = S;
+  d.law_mask = 0;
+  for (const Segment& g : m.segs) d.law_mask |= (g.mat.law == JFNK_NEO_HOOKEAN) ? 2 : 1;
+  d.slice_ptr = m.b_slice_ptr.as<int32_t>();
+  d.slot_nb = m.b_slot_nb.as<int32_t>();
+  d.slot_fc = m.b_slot_fc.as<int32_t>();
+  d.xc = m.b_xc.as<double>();
+  d.fG = m.b_fG.as<double>();
+  d.fw = m.b_fw.as<double>();
+  d.magG = m.b_magG.as<double>();
+  d.bface = m.b_bface.as<double>();
+  d.seg_of_block = m.b_seg_of_block.as<int32_t>();
+  d.seg = m.b_seg.as<SegInfo>();
+  jfnk_mesh_info& in = m.info;
+  in.n_cells = h.n_cells;
+  in.dim = dim;
+  in.n_dof = h.n_cells * dim;
+  in.n_internal_faces = h.n_int;
+  in.n_boundary_faces = h.n_bnd;
+  in.bandwidth = h.bandwidth;
+  in.device_bytes = int64_t(m.b_slice_ptr.bytes + m.b_slot_nb.bytes + m.b_slot_fc.bytes + m.b_xc.bytes +
+                            m.b_fG.bytes + m.b_fw.bytes + m.b_magG.bytes + m.b_bface.bytes +
+                            m.b_ext.bytes + m.b_pc_dinv.bytes + m.b_seg_of_block.bytes + m.b_seg.bytes +
+                            m.b_block_first.bytes);
+  in.n_slots = int64_t(ua.slot_nb.size());
+  in.n_segments = S;
+  in.n_dof_external = m.n_ext_cells * dim;
+  in.setup_ms = now_ms() - t0;
+}
+
+}  // namespace
+}  // namespace jfnk
+
 jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat, void* stream,
                              jfnk_mesh** out) {
+  return jfnk_create_batch(desc, mat, 1, stream, out);
+}
+
+jfnk_status jfnk_create_batch(const jfnk_mesh_desc* descs, const jfnk_material* mats, int32_t n,
+                              void* stream, jfnk_mesh** out) {
   return guarded([&] {
-    JFNK_REQUIRE(desc && mat && out, JFNK_E_ARG, "create_mesh: null argument");
+    JFNK_REQUIRE(descs && mats && out && n >= 1, JFNK_E_ARG, "create: null argument or empty batch");
     *out = nullptr;
     const double t0 = now_ms();
     auto m = std::make_unique<jfnk_mesh>();
-    m->mat = make_material(*mat);
-    build_host_mesh(*desc, m->mat, m->host);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const HostMesh& h = m->host;
-    upload(m->b_slice_ptr, h.slice_ptr, s);
-    upload(m->b_slot_nb, h.slot_nb, s);
-    upload(m->b_slot_fc, h.slot_fc, s);
-    upload(m->b_xc, to_soa(h.xc, h.n_cells, h.dim, h.dim), s);
-    upload(m->b_fG, to_soa(h.face, h.n_int, h.dim, kFaceRec), s);
-    {
-      std::vector<double> fw(h.n_int);
-      for (int64_t j = 0; j < h.n_int; ++j) fw[j] = h.face[j * kFaceRec + (h.dim == 3 ? 3 : 2)];
-      upload(m->b_fw, fw, s);
+    m->segs.resize(n);
+    for (int32_t s = 0; s < n; ++s) {
+      try {
+        m->segs[s].mat = make_material(mats[s]);
+        build_host_mesh(descs[s], m->segs[s].mat, m->segs[s].host);
+      } catch (Error& e) {
+        if (n > 1) e.msg = "batch mesh " + std::to_string(s) + ": " + e.msg;
+        throw;
+      }
     }
-    upload(m->b_magG, h.magG, s);
-    upload(m->b_bface, h.bface, s);
-    upload(m->b_order, h.old_of_new, s);
-    std::vector<double> dinv(h.n_cells);
-    for (int64_t c = 0; c < h.n_cells; ++c) dinv[c] = 1.0 / h.pc_diag[c];
-    upload(m->b_pc_dinv, dinv, s);
-    JFNK_HIP(hipStreamSynchronize(s));
-    JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m->pinned), sizeof(double) * 4 * kMaxBasis,
-                           hipHostMallocDefault));
-    MeshDev& d = m->dev;
-    d.n_cells = int32_t(h.n_cells);
-    d.dim = h.dim;
-    d.n_slices = int32_t(h.slice_ptr.size() - 1);
-    d.law = m->mat.law;
-    d.slice_ptr = m->b_slice_ptr.as<int32_t>();
-    d.slot_nb = m->b_slot_nb.as<int32_t>();
-    d.slot_fc = m->b_slot_fc.as<int32_t>();
-    d.xc = m->b_xc.as<double>();
-    d.n_int = int32_t(h.n_int);
-    d.fG = m->b_fG.as<double>();
-    d.fw = m->b_fw.as<double>();
-    d.magG = m->b_magG.as<double>();
-    d.bface = m->b_bface.as<double>();
-    d.mu = m->mat.mu;
-    d.lam = m->mat.lam;
-    d.kappa = m->mat.kappa;
-    d.aK = m->mat.alpha_rc * m->mat.Kbar;
-    jfnk_mesh_info& in = m->info;
-    in.n_cells = h.n_cells;
-    in.dim = h.dim;
-    in.n_dof = h.n_cells * h.dim;
-    in.n_internal_faces = h.n_int;
-    in.n_boundary_faces = h.n_bnd;
-    in.bandwidth = h.bandwidth;
-    in.device_bytes = int64_t(m->b_slice_ptr.bytes + m->b_slot_nb.bytes + m->b_slot_fc.bytes +
-                              m->b_xc.bytes + m->b_fG.bytes + m->b_fw.bytes + m->b_magG.bytes +
-                              m->b_bface.bytes +
-                              m->b_order.bytes +
-                              m->b_pc_dinv.bytes);
-    in.n_slots = int64_t(h.slot_nb.size());
-    in.setup_ms = now_ms() - t0;
+    finish_handle(*m, static_cast<hipStream_t>(stream), t0);
     *out = m.release();
+  });
+}
+
+jfnk_status jfnk_segment_info(const jfnk_mesh* mesh, int32_t seg, int64_t* cell_off, int64_t* n_cells,
+                              int64_t* ext_off) {
+  return guarded([&] {
+    JFNK_REQUIRE(mesh != nullptr, JFNK_E_ARG, "null mesh handle");
+    JFNK_REQUIRE(seg >= 0 && seg < mesh->n_seg(), JFNK_E_ARG, "segment index out of range");
+    const Segment& g = mesh->segs[seg];
+    if (cell_off) *cell_off = g.cell_off;
+    if (n_cells) *n_cells = g.host.n_cells;
+    if (ext_off) *ext_off = g.ext_off;
   });
 }
 
@@ -242,6 +284,8 @@ jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* m
     info->device_bytes = int64_t(device_bytes_of(h));
     info->setup_ms = now_ms() - t0;
     info->n_slots = int64_t(h.slot_nb.size());
+    info->n_segments = 1;
+    info->n_dof_external = h.n_cells * h.dim;
     for (int64_t i = 0; i < h.n_cells; ++i) {
       const int64_t o = h.old_of_new[i];
       if (xc_out)
@@ -294,7 +338,12 @@ jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new) {
   return guarded([&] {
     check_mesh(mesh);
     JFNK_REQUIRE(old_of_new, JFNK_E_ARG, "null output");
-    std::memcpy(old_of_new, mesh->host.old_of_new.data(), sizeof(int32_t) * mesh->host.n_cells);
+    // per segment, in segment order: input cell index (within the segment) of each internal cell
+    int64_t o = 0;
+    for (const Segment& g : mesh->segs) {
+      std::memcpy(old_of_new + o, g.host.old_of_new.data(), sizeof(int32_t) * g.host.n_cells);
+      o += g.host.n_cells;
+    }
   });
 }
 
@@ -304,7 +353,7 @@ jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* 
     check_ptr(d_in, "in");
     check_ptr(d_out, "out");
     JFNK_REQUIRE(d_in != d_out, JFNK_E_ARG, "permutation cannot run in place");
-    launch_permute(mesh->b_order.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, true,
+    launch_permute(mesh->b_ext.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, true,
                    static_cast<hipStream_t>(stream));
   });
 }
@@ -315,7 +364,7 @@ jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* 
     check_ptr(d_in, "in");
     check_ptr(d_out, "out");
     JFNK_REQUIRE(d_in != d_out, JFNK_E_ARG, "permutation cannot run in place");
-    launch_permute(mesh->b_order.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, false,
+    launch_permute(mesh->b_ext.as<int32_t>(), d_in, d_out, mesh->host.n_cells, mesh->host.dim, false,
                    static_cast<hipStream_t>(stream));
   });
 }
@@ -328,13 +377,13 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
     JFNK_REQUIRE(op == 0 || op == 1, JFNK_E_ARG, "workspace_size: op must be 0 or 1");
     Carver c(nullptr);
     FvWork fw;
-    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    fw.carve(c, mesh);
     if (op == 1) {
       JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
       JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG32, JFNK_E_ARG,
                    "workspace_size: unknown preconditioner");
       KrylovWork kw;
-      kw.carve(c, mesh->host.n_cells * mesh->host.dim, restart, precond_work_floats(mesh, precond));
+      kw.carve(c, mesh, restart, precond_work_floats(mesh, precond));
     }
     *bytes = c.off;
   });
@@ -349,10 +398,12 @@ jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, doubl
     check_work(d_work);
     JFNK_REQUIRE(d_u != d_R, JFNK_E_ARG, "residual: R may not alias u");
     JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "residual: load factor not finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
     Carver c(d_work);
     FvWork fw;
-    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
-    residual_into(mesh, load, d_u, d_R, fw, static_cast<hipStream_t>(stream));
+    fw.carve(c, mesh);
+    fill_device(fw.load, mesh->n_seg(), load, s);
+    residual_into(mesh, d_u, d_R, fw, nullptr, s);
   });
 }
 
@@ -370,17 +421,18 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver c(d_work);
     FvWork fw;
-    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    fw.carve(c, mesh);
+    fill_device(fw.load, mesh->n_seg(), load, s);
     const double* Ru = d_Ru;
     if (!Ru) {
-      residual_into(mesh, load, d_u, fw.ru, fw, s);
+      residual_into(mesh, d_u, fw.ru, fw, nullptr, s);
       Ru = fw.ru;
     }
-    jv_into(mesh, load, d_u, Ru, d_v, eps, d_Jv, fw, s);
+    jv_into(mesh, d_u, Ru, d_v, eps, d_Jv, fw, nullptr, s);
     if (eps_used) {
-      JFNK_HIP(hipMemcpyAsync(mesh->pinned, fw.scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipMemcpyAsync(mesh->pinned, fw.eps, sizeof(double) * mesh->n_seg(), hipMemcpyDeviceToHost, s));
       JFNK_HIP(hipStreamSynchronize(s));
-      *eps_used = mesh->pinned[0];
+      std::memcpy(eps_used, mesh->pinned, sizeof(double) * mesh->n_seg());
     }
   });
 }
@@ -398,26 +450,31 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     check_work(d_work);
     JFNK_REQUIRE(opts, JFNK_E_ARG, "gmres: null options");
     check_opts(*opts);
+    JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "gmres: load factor not finite");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver c(d_work);
     FvWork fw;
-    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    fw.carve(c, mesh);
     KrylovWork kw;
-    kw.carve(c, mesh->host.n_cells * mesh->host.dim, opts->restart,
-             precond_work_floats(mesh, opts->precond));
+    kw.carve(c, mesh, opts->restart, precond_work_floats(mesh, opts->precond));
+    fill_device(fw.load, mesh->n_seg(), load, s);
     precond_setup(mesh, opts->precond, s);
     double t_ms[8] = {0};
-    GmresResult r = gmres_solve(mesh, load, d_u, d_Ru, d_b, d_x, false, *opts, fw, kw, s, t_ms);
-    if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
-      stats->gmres_it = r.iterations;
-      stats->restarts = r.restarts;
-      stats->jv_evals = r.jv;
-      stats->res0 = r.bnorm;
-      stats->res_final = r.res_true;
-      std::memcpy(stats->t_ms, t_ms, sizeof(t_ms));
+    std::vector<GmresSeg> r;
+    gmres_solve(mesh, d_u, d_Ru, d_b, d_x, false, *opts, fw, kw, s, {}, r, t_ms);
+    for (int k = 0; k < mesh->n_seg(); ++k) {
+      if (stats) {
+        jfnk_stats& o = stats[k];
+        std::memset(&o, 0, sizeof(o));
+        o.gmres_it = r[k].iterations;
+        o.restarts = r[k].restarts;
+        o.jv_evals = r[k].jv;
+        o.res0 = r[k].bnorm;
+        o.res_final = r[k].res_true;
+        std::memcpy(o.t_ms, t_ms, sizeof(t_ms));
+      }
+      if (st == JFNK_OK && r[k].status != JFNK_OK) st = r[k].status;
     }
-    st = r.status;
     if (st == JFNK_E_NOT_CONVERGED) set_last_error("gmres: iteration limit reached");
     if (st == JFNK_E_BREAKDOWN) set_last_error("gmres: stagnation (true residual not decreasing)");
     if (st == JFNK_E_NAN) set_last_error("gmres: NaN/Inf encountered");
@@ -425,93 +482,62 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
   return g != JFNK_OK ? g : st;
 }
 
-jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, double* d_u,
-                              jfnk_stats* stats, void* d_work, void* stream) {
+static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, const jfnk_newton_opts* opts,
+                                 double* d_u, jfnk_stats* stats, jfnk_status* seg_status, void* d_work,
+                                 void* stream) {
   jfnk_status st = JFNK_OK;
   jfnk_status g = guarded([&] {
     check_mesh(mesh);
     check_ptr(d_u, "u");
     check_work(d_work);
     JFNK_REQUIRE(opts, JFNK_E_ARG, "newton: null options");
-    JFNK_REQUIRE(opts->n_increments >= 1 && opts->max_newton_it >= 1, JFNK_E_ARG,
-                 "newton: n_increments and max_newton_it must be >= 1");
-    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0, JFNK_E_ARG,
-                 "newton: bad tolerance");
+    JFNK_REQUIRE(opts->max_newton_it >= 1, JFNK_E_ARG, "newton: max_newton_it must be >= 1");
+    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0, JFNK_E_ARG, "newton: bad tolerance");
     check_opts(opts->gmres);
-    const double t0 = now_ms();
+    const int S = mesh->n_seg();
+    std::vector<int> inc(S);
+    for (int k = 0; k < S; ++k) {
+      inc[k] = n_increments ? n_increments[k] : opts->n_increments;
+      JFNK_REQUIRE(inc[k] >= 1, JFNK_E_ARG, "newton: n_increments must be >= 1");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = mesh->host.n_cells * mesh->host.dim;
     Carver c(d_work);
     FvWork fw;
-    fw.carve(c, mesh->host.n_cells, mesh->host.dim);
+    fw.carve(c, mesh);
     KrylovWork kw;
-    kw.carve(c, n, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
     const double ts = now_ms();
     precond_setup(mesh, opts->gmres.precond, s);
-    double t_ms[8] = {0};
-    t_ms[5] = now_ms() - ts;
-    jfnk_gmres_opts go = opts->gmres;
-    go.rtol = opts->eta;
-    go.atol = 0.0;
-    jfnk_stats sl{};
-    auto norm = [&](const double* x) {
-      blas_mdot(x, 0, 1, x, n, fw.partials, kw.h + kMaxBasis, false, s);
-      JFNK_HIP(hipMemcpyAsync(mesh->pinned, kw.h + kMaxBasis, sizeof(double), hipMemcpyDeviceToHost, s));
-      JFNK_HIP(hipStreamSynchronize(s));
-      return std::sqrt(mesh->pinned[0]);
-    };
-    for (int inc = 1; inc <= opts->n_increments && st == JFNK_OK; ++inc) {
-      const double load = double(inc) / opts->n_increments;
-      residual_into(mesh, load, d_u, kw.R, fw, s);
-      const double r0 = norm(kw.R);
-      JFNK_REQUIRE(std::isfinite(r0), JFNK_E_NAN, "newton: initial residual not finite");
-      sl.res0 = r0;
-      double rn = r0;
-      int it = 0;
-      while (true) {
-        if (!std::isfinite(rn)) {
-          st = JFNK_E_NAN;
-          set_last_error("newton: residual became NaN/Inf");
-          break;
-        }
-        if (rn <= std::max(opts->rtol * r0, opts->atol)) break;
-        if (it >= opts->max_newton_it) {
-          st = JFNK_E_NOT_CONVERGED;
-          set_last_error("newton: iteration limit reached in increment " + std::to_string(inc));
-          break;
-        }
-        if (rn > 1e8 * std::max(r0, 1e-300)) {
-          st = JFNK_E_DIVERGED;
-          set_last_error("newton: residual diverged in increment " + std::to_string(inc));
-          break;
-        }
-        blas_lincomb(-1.0, kw.R, 0.0, kw.R, kw.b, n, s);
-        JFNK_HIP(hipMemsetAsync(kw.du, 0, sizeof(double) * n, s));
-        GmresResult r = gmres_solve(mesh, load, d_u, kw.R, kw.b, kw.du, true, go, fw, kw, s, t_ms);
-        sl.gmres_it += r.iterations;
-        sl.restarts += r.restarts;
-        sl.jv_evals += r.jv;
-        if (r.status == JFNK_E_NAN) {
-          st = JFNK_E_NAN;
-          set_last_error("newton: NaN/Inf in the linear solve");
-          break;
-        }
-        blas_axpby(1.0, kw.du, 1.0, d_u, n, s);
-        residual_into(mesh, load, d_u, kw.R, fw, s);
-        rn = norm(kw.R);
-        ++it;
-        sl.newton_it++;
-      }
-      sl.res_final = rn;
+    const double setup = now_ms() - ts;
+    std::vector<jfnk_stats> sv;
+    std::vector<jfnk_status> stv;
+    newton_solve(mesh, inc, *opts, d_u, fw, kw, s, sv, stv);
+    for (int k = 0; k < S; ++k) {
+      sv[k].t_ms[5] = setup;
+      if (stats) stats[k] = sv[k];
+      if (seg_status) seg_status[k] = stv[k];
+      if (st == JFNK_OK && stv[k] != JFNK_OK) st = stv[k];
     }
-    t_ms[0] = now_ms() - t0;
-    if (stats) {
-      sl.eps_last = 0;
-      std::memcpy(sl.t_ms, t_ms, sizeof(t_ms));
-      *stats = sl;
-    }
+    if (st == JFNK_E_NOT_CONVERGED) set_last_error("newton: iteration limit reached");
+    if (st == JFNK_E_DIVERGED) set_last_error("newton: residual diverged");
+    if (st == JFNK_E_NAN) set_last_error("newton: residual became NaN/Inf");
   });
   return g != JFNK_OK ? g : st;
+}
+
+jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, double* d_u,
+                              jfnk_stats* stats, void* d_work, void* stream) {
+  if (opts && opts->n_increments < 1) {
+    set_last_error("newton: n_increments must be >= 1");
+    return JFNK_E_ARG;
+  }
+  return newton_common(mesh, nullptr, opts, d_u, stats, nullptr, d_work, stream);
+}
+
+jfnk_status jfnk_newton_solve_batch(jfnk_mesh* mesh, const int32_t* n_increments,
+                                    const jfnk_newton_opts* opts, double* d_u, jfnk_stats* stats,
+                                    jfnk_status* seg_status, void* d_work, void* stream) {
+  return newton_common(mesh, n_increments, opts, d_u, stats, seg_status, d_work, stream);
 }
 
 }  // extern "C"

@@ -63,9 +63,14 @@ __device__ __forceinline__ void load_soa(const double* __restrict__ a, int n, in
   for (int k = 0; k < D; ++k) x[k] = a[size_t(k) * n + c];
 }
 
+// Material constants of the segment a workgroup works on.
+struct Law {
+  double mu, lam, kappa, aK;
+};
+
 // ---------------------------------------------------------------- laws
 template <int D>
-__device__ __forceinline__ void traction_le(const MeshDev& m, const double (&g)[D][D],
+__device__ __forceinline__ void traction_le(const Law& m, const double (&g)[D][D],
                                             const double (&G)[D], double (&t)[D]) {
   double tr = 0;
 #pragma unroll
@@ -79,7 +84,7 @@ __device__ __forceinline__ void traction_le(const MeshDev& m, const double (&g)[
   }
 }
 
-__device__ __forceinline__ void traction_nh3(const MeshDev& m, const double (&g)[3][3],
+__device__ __forceinline__ void traction_nh3(const Law& m, const double (&g)[3][3],
                                              const double (&G)[3], double (&t)[3]) {
   double F[3][3];
 #pragma unroll
@@ -114,7 +119,7 @@ __device__ __forceinline__ void traction_nh3(const MeshDev& m, const double (&g)
   for (int i = 0; i < 3; ++i) t[i] = fma(cf, FG[i], ca * a[i]);
 }
 
-__device__ __forceinline__ void traction_nh2(const MeshDev& m, const double (&g)[2][2],
+__device__ __forceinline__ void traction_nh2(const Law& m, const double (&g)[2][2],
                                              const double (&G)[2], double (&t)[2]) {
   // plane strain: F_zz = 1, out-of-plane terms vanish for an in-plane Gamma
   const double F00 = 1.0 + g[0][0], F01 = g[1][0], F10 = g[0][1], F11 = 1.0 + g[1][1];
@@ -134,7 +139,7 @@ __device__ __forceinline__ void traction_nh2(const MeshDev& m, const double (&g)
 }
 
 template <int D, int LAW>
-__device__ __forceinline__ void traction(const MeshDev& m, const double (&g)[D][D],
+__device__ __forceinline__ void traction(const Law& m, const double (&g)[D][D],
                                          const double (&G)[D], double (&t)[D]) {
   if constexpr (LAW == JFNK_LINEAR_ELASTIC) {
     traction_le<D>(m, g, G, t);
@@ -147,7 +152,7 @@ __device__ __forceinline__ void traction(const MeshDev& m, const double (&g)[D][
 
 // Force on the owner side of an internal face (owner A, neighbour B).
 template <int D, int LAW>
-__device__ __forceinline__ void internal_face_force(const MeshDev& m, const double (&G)[D], double wf,
+__device__ __forceinline__ void internal_face_force(const Law& m, const double (&G)[D], double wf,
                                                     const double (&xA)[D], const double (&xB)[D],
                                                     const double (&wA)[D], const double (&wB)[D],
                                                     const double (&gA)[D][D], const double (&gB)[D][D],
@@ -198,15 +203,22 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int n, 
 
 template <int D>
 __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev m, const double* __restrict__ u,
-                                                     const double* __restrict__ v,
-                                                     const double* __restrict__ d_eps,
-                                                     double* __restrict__ rec, int nb_real) {
+                                                                           const double* __restrict__ v,
+                                                                           SegScalars sc,
+                                                                           double* __restrict__ rec, int nb_real) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   if (lb >= nb_real) return;
+  const int seg = m.seg_of_block[lb];
+  if (sc.active != nullptr && sc.active[seg] == 0) return;
   const int c = lb * kFvBlock + threadIdx.x;
   const int n = m.n_cells;
   if (c >= n) return;
-  const double eps = (v != nullptr) ? *d_eps : 0.0;
+  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {  // alignment padding
+#pragma unroll
+    for (int k = 0; k < D + D * D; ++k) rec[size_t(k) * n + c] = 0.0;
+    return;
+  }
+  const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
   double wP[D], xP[D];
   load_w<D>(u, v, eps, n, c, wP);
   load_soa<D>(m.xc, n, c, xP);
@@ -286,17 +298,12 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev
     for (int j = 0; j < D; ++j) rec[size_t(D + i * D + j) * n + c] = g[i][j];
 }
 
+// Sum of the face forces of cell c (Eq. divStressDiscret + Eq. RhieChow).
 template <int D, int LAW>
-__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, const double* __restrict__ rec,
-                                                 const double* __restrict__ d_eps,
-                                                 const double* __restrict__ Ru,
-                                                 double* __restrict__ out, double load, int nb_real) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  if (lb >= nb_real) return;
-  const int c = lb * kFvBlock + threadIdx.x;
+__device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, const double* __restrict__ rec,
+                                            int c, double load, double (&R)[D]) {
   const int n = m.n_cells;
-  if (c >= n) return;
-  double wP[D], xP[D], gP[D][D], R[D];
+  double wP[D], xP[D], gP[D][D];
   load_rec<D>(rec, n, c, wP, gP);
   load_soa<D>(m.xc, n, c, xP);
 #pragma unroll
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
             gB[i][j] = own ? gN[i][j] : gP[i][j];
           }
         }
-        internal_face_force<D, LAW>(m, G, wf, xA, xB, wA, wB, gA, gB, fo);
+        internal_face_force<D, LAW>(law, G, wf, xA, xB, wA, wB, gA, gB, fo);
 #pragma unroll
         for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
       } else if (nb[k] == kSlotBoundary) {
@@ -350,14 +357,14 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
             db[q] = r[3 + q];
             ub[q] = load * r[6 + q];
           }
-          traction<D, LAW>(m, gP, G, t);
+          traction<D, LAW>(law, gP, G, t);
           double dG = 0, GG = 0;
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             dG = fma(db[q], G[q], dG);
             GG = fma(G[q], G[q], GG);
           }
-          const double coef = m.aK * GG / dG;
+          const double coef = law.aK * GG / dG;
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             double dg = 0;
@@ -373,8 +380,43 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
       }
     }
   }
+}
+
+constexpr int kLawMixed = -1;
+
+// LAWSEL: JFNK_LINEAR_ELASTIC, JFNK_NEO_HOOKEAN, or kLawMixed (law chosen per
+// segment, i.e. per workgroup).
+template <int D, int LAWSEL>
+__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, const double* __restrict__ rec,
+                                                                       SegScalars sc,
+                                                                       const double* __restrict__ Ru,
+                                                                       double* __restrict__ out, int nb_real) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= nb_real) return;
+  const int seg = m.seg_of_block[lb];
+  if (sc.active != nullptr && sc.active[seg] == 0) return;
+  const int c = lb * kFvBlock + threadIdx.x;
+  const int n = m.n_cells;
+  if (c >= n) return;
+  const SegInfo& si = m.seg[seg];
+  if (c - si.cell_off >= si.n_cells) {  // alignment padding
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
+    return;
+  }
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+  const double load = sc.load[seg];
+  double R[D];
+  if constexpr (LAWSEL == kLawMixed) {
+    if (si.law == JFNK_NEO_HOOKEAN)
+      cell_forces<D, JFNK_NEO_HOOKEAN>(m, law, rec, c, load, R);
+    else
+      cell_forces<D, JFNK_LINEAR_ELASTIC>(m, law, rec, c, load, R);
+  } else {
+    cell_forces<D, LAWSEL>(m, law, rec, c, load, R);
+  }
   if (Ru != nullptr) {
-    const double eps = *d_eps;
+    const double eps = sc.eps[seg];
     const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q)
@@ -392,32 +434,37 @@ inline void grid_for(int n_cells, int& nb_real, int& nb_launch) {
 
 }  // namespace
 
-void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+void launch_gradient(const MeshDev& m, const double* u, const double* v, const SegScalars& sc,
                      double* rec, hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
   if (m.dim == 3)
-    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, d_eps, rec, nr);
+    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
   else
-    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, d_eps, rec, nr);
+    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
   JFNK_HIP(hipGetLastError());
 }
 
-void launch_flux(const MeshDev& m, const double* rec, const double* d_eps, const double* Ru,
-                 double* out, double load, hipStream_t s) {
+void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
+                 hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
   const dim3 g(nl), b(kFvBlock);
+  const int mask = m.law_mask;
   if (m.dim == 3) {
-    if (m.law == JFNK_NEO_HOOKEAN)
-      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
+    if (mask == 2)
+      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+    else if (mask == 1)
+      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, sc, Ru, out, nr);
     else
-      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<3, kLawMixed>), g, b, 0, s, m, rec, sc, Ru, out, nr);
   } else {
-    if (m.law == JFNK_NEO_HOOKEAN)
-      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
+    if (mask == 2)
+      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+    else if (mask == 1)
+      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, sc, Ru, out, nr);
     else
-      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, d_eps, Ru, out, load, nr);
+      hipLaunchKernelGGL((k_flux<2, kLawMixed>), g, b, 0, s, m, rec, sc, Ru, out, nr);
   }
   JFNK_HIP(hipGetLastError());
 }

@@ -39,16 +39,17 @@ constexpr int kSlice = 64;
 constexpr int kBlock = 256;
 constexpr int kNumXcd = 8;
 // launch shape of the two cell passes (tuned on gfx950)
-#ifndef JFNK_FV_BLOCK
-#define JFNK_FV_BLOCK 256
-#endif
 #ifndef JFNK_FV_MINWAVES
 #define JFNK_FV_MINWAVES 1
 #endif
 #ifndef JFNK_XCD_REMAP
 #define JFNK_XCD_REMAP 1
 #endif
-constexpr int kFvBlock = JFNK_FV_BLOCK;
+// Cells of the two cell passes are processed in workgroups of kFvBlock
+// consecutive cells; segments of a batch start on multiples of kSegAlign so
+// that every workgroup belongs to exactly one segment.
+constexpr int kFvBlock = 256;
+constexpr int kSegAlign = kFvBlock;
 // slot_nb values
 constexpr int kSlotBoundary = -1;
 constexpr int kSlotPad = -2;
@@ -59,16 +60,28 @@ constexpr int kBfaceRec = 10;
 // boundary type codes in the record
 constexpr int kBcDisp = 1, kBcTrac = 2, kBcPres = 3;
 
-// Read-only device view of one mesh, passed by value to kernels.  Cell and
-// face arrays are component-major (structure of arrays) so that 64 lanes
-// reading consecutive cells or faces touch consecutive addresses.
+// Per-segment constants (one segment = one mesh of a batch).
+struct SegInfo {
+  double mu, lam, kappa;     // law constants (Appendix B)
+  double aK;                 // alpha_rc * K_bar, K_bar = 2 mu + lambda
+  int32_t law;
+  int32_t cell_off;          // first cell of the segment in the union numbering
+  int32_t n_cells;           // cells of the segment (cells beyond are padding)
+  int32_t pad_;
+};
+
+// Read-only device view of a mesh or a batch of meshes (the union of the
+// segments, each renumbered internally and placed at an aligned offset),
+// passed by value to kernels.  Cell and face arrays are component-major
+// (structure of arrays) so that 64 lanes reading consecutive cells or faces
+// touch consecutive addresses.
 struct MeshDev {
-  int32_t n_cells;
+  int32_t n_cells;           // union cells including alignment padding
   int32_t dim;
   int32_t n_slices;
-  int32_t law;
-  int32_t n_int;
-  int32_t pad_;
+  int32_t n_int;             // union internal faces
+  int32_t n_seg;
+  int32_t law_mask;          // bit 0: a linear-elastic segment, bit 1: a neo-Hookean segment
   const int32_t* slice_ptr;  // [n_slices + 1], in slots (multiples of kSlice)
   const int32_t* slot_nb;    // neighbour cell, kSlotBoundary or kSlotPad
   const int32_t* slot_fc;    // internal: face (owner side) or ~face (neighbour side); boundary: bface
@@ -77,8 +90,15 @@ struct MeshDev {
   const double* fw;          // [n_int] interpolation weight w_f of the owner
   const double* magG;        // [n_int] |Gamma_f|
   const double* bface;       // [n_boundary][10] {Gamma, d_b, value, type}
-  double mu, lam, kappa;     // law constants (Appendix B)
-  double aK;                 // alpha_rc * K_bar, K_bar = 2 mu + lambda
+  const int32_t* seg_of_block;  // [ceil(n_cells / kFvBlock)]
+  const SegInfo* seg;        // [n_seg]
+};
+
+// Per-call, per-segment device scalars.
+struct SegScalars {
+  const double* eps;         // [n_seg] J v step (null: residual evaluation)
+  const double* load;        // [n_seg] load factor
+  const int32_t* active;     // [n_seg] or null: segments with 0 are skipped
 };
 
 // Host-side result of mesh preprocessing (all in internal numbering).
@@ -106,6 +126,13 @@ struct Material {
 
 Material make_material(const jfnk_material& m);
 void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm);
+
+// Host arrays of a batch union, ready for upload.
+struct UnionArrays {
+  std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
+  std::vector<double> xc, face, magG, bface, pc_dinv;
+  std::vector<SegInfo> seg;
+};
 
 // Device buffer with RAII.
 struct DevBuf {
@@ -158,37 +185,53 @@ struct Profiler {
 
 }  // namespace jfnk
 
-// The opaque handle of the ABI.
+namespace jfnk {
+struct Segment {
+  HostMesh host;             // the mesh in its own internal numbering
+  Material mat;
+  int64_t cell_off = 0;      // first union cell
+  int64_t ext_off = 0;       // first cell in the concatenated external (input-order) layout
+  int64_t face_off = 0, bface_off = 0;
+};
+}  // namespace jfnk
+
+// The opaque handle of the ABI: one mesh, or a batch of meshes solved
+// together (segments).
 struct jfnk_mesh {
-  jfnk::Material mat;
-  jfnk::HostMesh host;
+  std::vector<jfnk::Segment> segs;
+  jfnk::HostMesh host;              // union arrays (approximate Jacobian, faces) used by setup code
+  int64_t n_ext_cells = 0;          // sum of segment cells
+  std::vector<int32_t> block_first; // [n_seg + 1] first workgroup (kFvBlock cells) of each segment
   jfnk::MeshDev dev{};
-  jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_order, b_pc_dinv;
+  jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
+      b_seg_of_block, b_seg, b_block_first;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
+  size_t pinned_doubles = 0;
   jfnk_mesh_info info{};
   jfnk::AmgHierarchy* amg = nullptr;
   jfnk::Profiler prof;
+  int n_seg() const { return int(segs.size()); }
 };
 
 namespace jfnk {
 
 // ---- kernel launchers (fv_kernels.hip, blas.hip) ----
-// Per-cell record of w = u + eps*v (v may be null; eps from *d_eps), written by
-// the gradient pass and gathered by the flux pass: {w, grad w} stored
-// component-major, rec_doubles(dim) arrays of n_cells doubles.
+// Per-cell record of w = u + eps*v (v may be null), written by the gradient
+// pass and gathered by the flux pass: {w, grad w} stored component-major,
+// rec_doubles(dim) arrays of n_cells doubles.
 inline int rec_doubles(int dim) { return dim + dim * dim; }
-void launch_gradient(const MeshDev& m, const double* u, const double* v, const double* d_eps,
+void launch_gradient(const MeshDev& m, const double* u, const double* v, const SegScalars& sc,
                      double* rec, hipStream_t s);
-// out = (R(w) - Ru)/eps if Ru != null else R(w).
-void launch_flux(const MeshDev& m, const double* rec, const double* d_eps, const double* Ru,
-                 double* out, double load, hipStream_t s);
-// d_eps = sqrt(eps_mach) sqrt(1 + |u|)/|v|, from two norms; partials: >= kRedBlocks*2 doubles.
-void launch_eps(const double* u, const double* v, int64_t n, double* partials, double* d_eps,
-                hipStream_t s);
-void launch_set_scalar(double* d, double value, hipStream_t s);
-void launch_permute(const int32_t* old_of_new, const double* in, double* out, int64_t n_cells,
-                    int dim, bool to_internal, hipStream_t s);
+// out = (R(w) - Ru)/eps if Ru != null else R(w) (per-segment eps and load).
+void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
+                 hipStream_t s);
+// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|)/|v_s| per segment.
+void launch_eps(const MeshDev& m, const int32_t* block_first, const double* u, const double* v,
+                double* partials, double* d_eps, const int32_t* active, hipStream_t s);
+void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s);
+void build_union(jfnk_mesh& m, UnionArrays& ua);
 
-constexpr int kRedBlocks = 1024;  // fixed number of partial sums for reductions
+void launch_permute(const int32_t* ext_of_int, const double* in, double* out, int64_t n_cells, int dim,
+                    bool to_internal, hipStream_t s);
 
 }  // namespace jfnk

@@ -486,3 +486,119 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
 }
 
 }  // namespace jfnk
+
+namespace jfnk {
+
+// Concatenate the segments of a batch into one padded union numbering.
+// Segment s occupies union cells [cell_off_s, cell_off_s + n_s); cell_off_s
+// is a multiple of kSegAlign so that each workgroup of the cell passes lies
+// in one segment.  Cells in the alignment gaps are padding: they own no face
+// slots, carry zeros in every vector, and have a unit diagonal in the
+// approximate Jacobian.
+void build_union(jfnk_mesh& m, UnionArrays& ua) {
+  const int S = m.n_seg();
+  JFNK_REQUIRE(S >= 1, JFNK_E_ARG, "batch: no segments");
+  const int dim = m.segs[0].host.dim;
+  int64_t cell = 0, face = 0, bface = 0, ext = 0;
+  for (int s = 0; s < S; ++s) {
+    Segment& g = m.segs[s];
+    JFNK_REQUIRE(g.host.dim == dim, JFNK_E_ARG, "batch: all meshes of a batch must have the same dim");
+    if (s > 0) cell = (cell + kSegAlign - 1) / kSegAlign * kSegAlign;
+    g.cell_off = cell;
+    g.face_off = face;
+    g.bface_off = bface;
+    g.ext_off = ext;
+    cell += g.host.n_cells;
+    face += g.host.n_int;
+    bface += g.host.n_bnd;
+    ext += g.host.n_cells;
+  }
+  JFNK_REQUIRE(cell < (int64_t(1) << 31) - kSegAlign && face < (int64_t(1) << 31), JFNK_E_ARG,
+               "batch: too many cells or faces");
+  const int64_t N = cell;
+  m.n_ext_cells = ext;
+  HostMesh& U = m.host;
+  U = HostMesh();
+  U.dim = dim;
+  U.n_cells = N;
+  U.n_int = face;
+  U.n_bnd = bface;
+  U.fown.resize(face);
+  U.fnb.resize(face);
+  U.pc_off.resize(face);
+  U.pc_diag.assign(N, -1.0);
+  U.bandwidth = 0;
+  ua.xc.assign(size_t(N) * dim, 0.0);
+  ua.face.resize(size_t(face) * kFaceRec);
+  ua.magG.resize(face);
+  ua.bface.resize(size_t(bface) * kBfaceRec);
+  ua.ext.assign(N, -1);
+  const int64_t n_slices = (N + kSlice - 1) / kSlice;
+  ua.slice_ptr.assign(n_slices + 1, 0);
+  const int64_t n_blocks = (N + kFvBlock - 1) / kFvBlock;
+  ua.seg_of_block.assign(n_blocks, 0);
+  m.block_first.assign(S + 1, 0);
+  ua.seg.resize(S);
+  // slice widths first
+  std::vector<int32_t> width(n_slices, 0);
+  for (int s = 0; s < S; ++s) {
+    const Segment& g = m.segs[s];
+    const int64_t s0 = g.cell_off / kSlice;
+    for (size_t k = 0; k + 1 < g.host.slice_ptr.size(); ++k)
+      width[s0 + k] = (g.host.slice_ptr[k + 1] - g.host.slice_ptr[k]) / kSlice;
+  }
+  for (int64_t k = 0; k < n_slices; ++k) ua.slice_ptr[k + 1] = ua.slice_ptr[k] + width[k] * kSlice;
+  ua.slot_nb.assign(ua.slice_ptr[n_slices], kSlotPad);
+  ua.slot_fc.assign(ua.slice_ptr[n_slices], 0);
+  for (int s = 0; s < S; ++s) {
+    const Segment& g = m.segs[s];
+    const HostMesh& h = g.host;
+    const int64_t co = g.cell_off, fo = g.face_off, bo = g.bface_off;
+    U.bandwidth = std::max(U.bandwidth, h.bandwidth);
+    for (int64_t c = 0; c < h.n_cells; ++c) {
+      for (int k = 0; k < dim; ++k) ua.xc[(co + c) * dim + k] = h.xc[c * dim + k];
+      U.pc_diag[co + c] = h.pc_diag[c];
+      ua.ext[co + c] = int32_t(g.ext_off + h.old_of_new[c]);
+    }
+    for (int64_t j = 0; j < h.n_int; ++j) {
+      U.fown[fo + j] = int32_t(h.fown[j] + co);
+      U.fnb[fo + j] = int32_t(h.fnb[j] + co);
+      U.pc_off[fo + j] = h.pc_off[j];
+      ua.magG[fo + j] = h.magG[j];
+      for (int k = 0; k < kFaceRec; ++k) ua.face[(fo + j) * kFaceRec + k] = h.face[j * kFaceRec + k];
+    }
+    for (int64_t j = 0; j < h.n_bnd * kBfaceRec; ++j) ua.bface[bo * kBfaceRec + j] = h.bface[j];
+    const int64_t s0 = co / kSlice;
+    for (size_t k = 0; k + 1 < h.slice_ptr.size(); ++k) {
+      const int64_t src = h.slice_ptr[k], dst = ua.slice_ptr[s0 + k];
+      for (int64_t q = 0; q < h.slice_ptr[k + 1] - src; ++q) {
+        const int32_t nb = h.slot_nb[src + q], fc = h.slot_fc[src + q];
+        if (nb >= 0) {
+          ua.slot_nb[dst + q] = int32_t(nb + co);
+          ua.slot_fc[dst + q] = fc >= 0 ? int32_t(fc + fo) : ~int32_t(~fc + fo);
+        } else if (nb == kSlotBoundary) {
+          ua.slot_nb[dst + q] = kSlotBoundary;
+          ua.slot_fc[dst + q] = int32_t(fc + bo);
+        }
+      }
+    }
+    SegInfo& si = ua.seg[s];
+    si.mu = g.mat.mu;
+    si.lam = g.mat.lam;
+    si.kappa = g.mat.kappa;
+    si.aK = g.mat.alpha_rc * g.mat.Kbar;
+    si.law = g.mat.law;
+    si.cell_off = int32_t(co);
+    si.n_cells = int32_t(h.n_cells);
+    si.pad_ = 0;
+    const int64_t b0 = co / kFvBlock;
+    const int64_t b1 = (s + 1 < S) ? m.segs[s + 1].cell_off / kFvBlock : n_blocks;
+    m.block_first[s] = int32_t(b0);
+    for (int64_t b = b0; b < b1; ++b) ua.seg_of_block[b] = s;
+  }
+  m.block_first[S] = int32_t(n_blocks);
+  ua.pc_dinv.resize(N);
+  for (int64_t c = 0; c < N; ++c) ua.pc_dinv[c] = 1.0 / U.pc_diag[c];
+}
+
+}  // namespace jfnk

@@ -1,20 +1,27 @@
-// Host-side drivers: residual / J.v sequences, GMRES and Newton.
+// Host-side drivers: residual / J.v sequences, GMRES and Newton, for one
+// mesh or a batch of meshes (segments) solved in lockstep.
 #pragma once
+
+#include <vector>
 
 #include "internal.h"
 #include "workspace.h"
 
 namespace jfnk {
 
-// R(u) into R (gradient pass + flux pass).
-void residual_into(jfnk_mesh* m, double load, const double* u, double* R, FvWork& fw, hipStream_t s);
+SegLayout layout_of(const jfnk_mesh* m);
+void fill_device(double* d, int n, double value, hipStream_t s);
 
-// J v into Jv using cached Ru; eps <= 0 selects the automatic step (device).
-// Leaves the step used in fw.scalars[0].
-void jv_into(jfnk_mesh* m, double load, const double* u, const double* Ru, const double* v,
-             double eps, double* Jv, FvWork& fw, hipStream_t s);
+// R(u) into R with the per-segment load factors in fw.load (device).
+void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const int32_t* active,
+                   hipStream_t s);
 
-struct GmresResult {
+// J v into Jv using cached Ru; eps <= 0 selects the automatic per-segment
+// step (computed on the device into fw.eps), eps > 0 is used for every segment.
+void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
+             FvWork& fw, const int32_t* active, hipStream_t s);
+
+struct GmresSeg {
   jfnk_status status = JFNK_OK;
   int iterations = 0;
   int restarts = 0;
@@ -22,11 +29,17 @@ struct GmresResult {
   double bnorm = 0, res_true = 0;
 };
 
-// Right-preconditioned restarted (flexible) GMRES with CGS2 for J x = b.
+// Right-preconditioned restarted (flexible) GMRES with CGS2 for J x = b on
+// every segment s with part[s] != 0 (all segments when part is empty).
 // x_is_zero skips the initial J x product.
-GmresResult gmres_solve(jfnk_mesh* m, double load, const double* u, const double* Ru, const double* b,
-                        double* x, bool x_is_zero, const jfnk_gmres_opts& o, FvWork& fw,
-                        KrylovWork& kw, hipStream_t s, double* t_ms);
+void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* b, double* x,
+                 bool x_is_zero, const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, hipStream_t s,
+                 const std::vector<char>& part, std::vector<GmresSeg>& out, double* t_ms);
+
+// Newton-Raphson with per-segment load increments; per-segment stats.
+void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk_newton_opts& o,
+                  double* u, FvWork& fw, KrylovWork& kw, hipStream_t s, std::vector<jfnk_stats>& stats,
+                  std::vector<jfnk_status>& status);
 
 size_t precond_work_floats(const jfnk_mesh* m, int precond);
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s);

@@ -25,17 +25,23 @@ struct Carver {
   }
 };
 
+inline int64_t n_tiles(const jfnk_mesh* m) { return (m->host.n_cells + kFvBlock - 1) / kFvBlock; }
+
 // Regions used by jfnk_residual / jfnk_jv.
 struct FvWork {
-  double* grad = nullptr;      // [n_cells][rec_doubles(dim)] per-cell {w, x_c, grad w}
+  double* grad = nullptr;      // [rec_doubles(dim)][n_cells] per-cell {w, grad w}
   double* ru = nullptr;        // [n_dof] R(u) when not supplied
-  double* partials = nullptr;  // [kRedBlocks * kMaxBasis]
-  double* scalars = nullptr;   // [64]: 0 eps, 1.. reserved
-  void carve(Carver& c, int64_t n_cells, int dim) {
-    grad = c.take<double>(size_t(n_cells) * rec_doubles(dim));
-    ru = c.take<double>(size_t(n_cells) * dim);
-    partials = c.take<double>(size_t(kRedBlocks) * kMaxBasis);
-    scalars = c.take<double>(64);
+  double* partials = nullptr;  // [n_tiles * kMaxBasis]
+  double* eps = nullptr;       // [n_seg] J v step per segment
+  double* load = nullptr;      // [n_seg] load factor per segment
+  void carve(Carver& c, const jfnk_mesh* m) {
+    const int64_t n = m->host.n_cells;
+    const int S = m->n_seg();
+    grad = c.take<double>(size_t(n) * rec_doubles(m->host.dim));
+    ru = c.take<double>(size_t(n) * m->host.dim);
+    partials = c.take<double>(size_t(n_tiles(m)) * kMaxBasis);
+    eps = c.take<double>(S);
+    load = c.take<double>(S);
   }
 };
 
@@ -48,20 +54,30 @@ struct KrylovWork {
   double* b = nullptr;    // [n_dof] Newton right-hand side
   double* du = nullptr;   // [n_dof] Newton correction
   double* R = nullptr;    // [n_dof] Newton residual R(u)
-  double* h = nullptr;    // [kMaxBasis + 8] Hessenberg column / scalars
-  double* y = nullptr;    // [kMaxBasis]
+  double* h = nullptr;    // [n_seg][kMaxBasis] Hessenberg column, first pass
+  double* h2 = nullptr;   // [n_seg][kMaxBasis] second pass
+  double* nrm = nullptr;  // [n_seg][4] squared norms
+  double* y = nullptr;    // [n_seg][kMaxBasis] least-squares solution
+  double* fac = nullptr;  // [n_seg] per-segment factors
+  int32_t* act = nullptr; // [n_seg] active flags
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
-  void carve(Carver& c, int64_t n_dof, int m, size_t pc_f) {
-    V = c.take<double>(size_t(m + 1) * n_dof);
-    Z = c.take<double>(size_t(m) * n_dof);
+  void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f) {
+    const int64_t n_dof = m->host.n_cells * m->host.dim;
+    const int S = m->n_seg();
+    V = c.take<double>(size_t(restart + 1) * n_dof);
+    Z = c.take<double>(size_t(restart) * n_dof);
     w = c.take<double>(n_dof);
     r = c.take<double>(n_dof);
     b = c.take<double>(n_dof);
     du = c.take<double>(n_dof);
     R = c.take<double>(n_dof);
-    h = c.take<double>(kMaxBasis + 8);
-    y = c.take<double>(kMaxBasis);
+    h = c.take<double>(size_t(S) * kMaxBasis);
+    h2 = c.take<double>(size_t(S) * kMaxBasis);
+    nrm = c.take<double>(size_t(S) * 4);
+    y = c.take<double>(size_t(S) * kMaxBasis);
+    fac = c.take<double>(S);
+    act = c.take<int32_t>(S);
     pc_floats = pc_f;
     pc = pc_f ? c.take<float>(pc_f) : nullptr;
   }

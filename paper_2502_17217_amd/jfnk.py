@@ -46,7 +46,7 @@ class jfnk_mesh_info(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("dim", C.c_int32), ("n_dof", C.c_int64),
                 ("n_internal_faces", C.c_int64), ("n_boundary_faces", C.c_int64),
                 ("bandwidth", C.c_int64), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
-                ("n_slots", C.c_int64)]
+                ("n_slots", C.c_int64), ("n_segments", C.c_int32), ("n_dof_external", C.c_int64)]
 
 
 class jfnk_gmres_opts(C.Structure):
@@ -79,6 +79,9 @@ def _load():
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
         "jfnk_create_mesh": [vp, vp, vp, C.POINTER(vp)],
+        "jfnk_create_batch": [vp, vp, i32, vp, C.POINTER(vp)],
+        "jfnk_segment_info": [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+        "jfnk_newton_solve_batch": [vp, vp, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp, vp],
         "jfnk_destroy_mesh": [vp],
         "jfnk_inspect_mesh": [vp, vp, C.POINTER(jfnk_mesh_info), vp, vp],
         "jfnk_get_mesh_info": [vp, C.POINTER(jfnk_mesh_info)],
@@ -87,9 +90,9 @@ def _load():
         "jfnk_to_external": [vp, vp, vp, vp],
         "jfnk_workspace_size": [vp, i32, i32, i32, C.POINTER(C.c_size_t)],
         "jfnk_residual": [vp, d, vp, vp, vp, vp],
-        "jfnk_jv": [vp, d, vp, vp, vp, d, vp, C.POINTER(d), vp, vp],
-        "jfnk_gmres": [vp, d, vp, vp, vp, vp, C.POINTER(jfnk_gmres_opts), C.POINTER(jfnk_stats), vp, vp],
-        "jfnk_newton_solve": [vp, C.POINTER(jfnk_newton_opts), vp, C.POINTER(jfnk_stats), vp, vp],
+        "jfnk_jv": [vp, d, vp, vp, vp, d, vp, vp, vp, vp],
+        "jfnk_gmres": [vp, d, vp, vp, vp, vp, C.POINTER(jfnk_gmres_opts), vp, vp, vp],
+        "jfnk_newton_solve": [vp, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp],
         "jfnk_profile_enable": [vp, i32],
         "jfnk_profile_read": [vp, vp, vp, i32],
     }
@@ -218,14 +221,29 @@ def inspect_mesh(mesh, material, geometry=False):
 
 
 class Mesh:
-    """Owner of a jfnk_mesh handle built from a meshgen-style dictionary."""
+    """Owner of a jfnk_mesh handle: one mesh, or a batch of meshes (segments).
+
+    Internal vectors (n_dof entries) are component-major in the library's
+    cell order; external vectors (n_dof_external entries) are the meshes'
+    interleaved input-order vectors, concatenated for a batch.
+    """
 
     def __init__(self, mesh, material, stream=None):
-        desc, keep = _make_desc(mesh)
-        mat = _make_material(material)
+        meshes = mesh if isinstance(mesh, (list, tuple)) else [mesh]
+        mats = material if isinstance(material, (list, tuple)) else [material] * len(meshes)
+        if len(mats) != len(meshes):
+            raise ValueError("one material per mesh")
+        descs = (jfnk_mesh_desc * len(meshes))()
+        cmats = (jfnk_material * len(meshes))()
+        keep = []
+        for i, (m, mt) in enumerate(zip(meshes, mats)):
+            d, k = _make_desc(m)
+            descs[i] = d
+            keep.append(k)
+            cmats[i] = _make_material(mt)
         h = C.c_void_p()
-        _check(_lib.jfnk_create_mesh(C.byref(desc), C.byref(mat), _stream(stream), C.byref(h)),
-               "jfnk_create_mesh")
+        _check(_lib.jfnk_create_batch(descs, cmats, len(meshes), _stream(stream), C.byref(h)),
+               "jfnk_create_batch")
         del keep
         self.handle = h
         info = jfnk_mesh_info()
@@ -234,9 +252,20 @@ class Mesh:
         self.dim = info.dim
         self.n_cells = info.n_cells
         self.n_dof = info.n_dof
-        order = np.empty(self.n_cells, dtype=np.int32)
+        self.n_dof_external = info.n_dof_external
+        self.n_segments = info.n_segments
+        self.segments = []
+        for s in range(self.n_segments):
+            co, nc, eo = C.c_int64(), C.c_int64(), C.c_int64()
+            _check(_lib.jfnk_segment_info(h, s, C.byref(co), C.byref(nc), C.byref(eo)), "jfnk_segment_info")
+            self.segments.append(dict(cell_off=co.value, n_cells=nc.value, ext_off=eo.value))
+        order = np.empty(info.n_dof_external // info.dim, dtype=np.int32)
         _check(_lib.jfnk_mesh_order(h, order.ctypes.data), "jfnk_mesh_order")
         self.old_of_new = order
+
+    def segment_slice_external(self, s):
+        g = self.segments[s]
+        return slice(g["ext_off"] * self.dim, (g["ext_off"] + g["n_cells"]) * self.dim)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -251,20 +280,25 @@ class Mesh:
 
     # vectors in internal order <-> input order (device permutation kernels)
     def to_internal(self, x, out=None, stream=None):
-        out = torch.empty_like(x) if out is None else out
-        _check(_lib.jfnk_to_internal(self.handle, _dptr(x, self.n_dof, "x"), _dptr(out, self.n_dof, "out"),
-                                     _stream(stream)), "jfnk_to_internal")
+        out = torch.empty(self.n_dof, dtype=torch.float64, device=x.device) if out is None else out
+        _check(_lib.jfnk_to_internal(self.handle, _dptr(x, self.n_dof_external, "x"),
+                                     _dptr(out, self.n_dof, "out"), _stream(stream)), "jfnk_to_internal")
         return out
 
     def to_external(self, x, out=None, stream=None):
-        out = torch.empty_like(x) if out is None else out
-        _check(_lib.jfnk_to_external(self.handle, _dptr(x, self.n_dof, "x"), _dptr(out, self.n_dof, "out"),
-                                     _stream(stream)), "jfnk_to_external")
+        out = torch.empty(self.n_dof_external, dtype=torch.float64, device=x.device) if out is None else out
+        _check(_lib.jfnk_to_external(self.handle, _dptr(x, self.n_dof, "x"),
+                                     _dptr(out, self.n_dof_external, "out"), _stream(stream)),
+               "jfnk_to_external")
         return out
 
 
 def create_mesh(mesh, material, stream=None):
     return Mesh(mesh, material, stream)
+
+
+def create_batch(meshes, materials, stream=None):
+    return Mesh(list(meshes), list(materials), stream)
 
 
 def workspace_size(mesh, op=0, restart=30, precond=PC_JACOBI):
@@ -284,12 +318,15 @@ def residual(mesh, load, u, R, work, stream=None):
 
 
 def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
-    e = C.c_double(0.0)
+    """J v into Jv; with return_eps also the step(s) used (scalar, or one per batch mesh)."""
+    e = (C.c_double * mesh.n_segments)()
     _check(_lib.jfnk_jv(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"),
                         _dptr(Ru, mesh.n_dof, "Ru") if Ru is not None else None,
                         _dptr(v, mesh.n_dof, "v"), float(eps), _dptr(Jv, mesh.n_dof, "Jv"),
-                        C.byref(e) if return_eps else None, work.c, _stream(stream)), "jfnk_jv")
-    return (Jv, e.value) if return_eps else Jv
+                        C.cast(e, C.c_void_p) if return_eps else None, work.c, _stream(stream)), "jfnk_jv")
+    if not return_eps:
+        return Jv
+    return (Jv, e[0]) if mesh.n_segments == 1 else (Jv, list(e))
 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0):
@@ -303,20 +340,37 @@ def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-
 
 
 def gmres(mesh, load, u, Ru, b, x, opts, work, stream=None, allow=(E_NOT_CONVERGED, E_BREAKDOWN)):
-    st = jfnk_stats()
+    st = (jfnk_stats * mesh.n_segments)()
     s = _lib.jfnk_gmres(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"), _dptr(Ru, mesh.n_dof, "Ru"),
-                        _dptr(b, mesh.n_dof, "b"), _dptr(x, mesh.n_dof, "x"), C.byref(opts), C.byref(st),
-                        work.c, _stream(stream))
+                        _dptr(b, mesh.n_dof, "b"), _dptr(x, mesh.n_dof, "x"), C.byref(opts),
+                        C.cast(st, C.c_void_p), work.c, _stream(stream))
     _check(s, "jfnk_gmres", allow)
-    return s, st.as_dict()
+    out = [x.as_dict() for x in st]
+    return s, (out[0] if mesh.n_segments == 1 else out)
 
 
 def newton_solve(mesh, opts, u, work, stream=None, allow=(E_NOT_CONVERGED,)):
-    st = jfnk_stats()
-    s = _lib.jfnk_newton_solve(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), C.byref(st),
+    st = (jfnk_stats * mesh.n_segments)()
+    s = _lib.jfnk_newton_solve(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), C.cast(st, C.c_void_p),
                                work.c, _stream(stream))
     _check(s, "jfnk_newton_solve", allow)
-    return s, st.as_dict()
+    out = [x.as_dict() for x in st]
+    return s, (out[0] if mesh.n_segments == 1 else out)
+
+
+def newton_solve_batch(mesh, opts, u, work, n_increments=None, stream=None, allow=(E_NOT_CONVERGED,)):
+    """Batched Newton; returns (status, per-mesh stats list, per-mesh status list)."""
+    S = mesh.n_segments
+    st = (jfnk_stats * S)()
+    seg = (C.c_int * S)()
+    inc = None
+    if n_increments is not None:
+        inc = (C.c_int32 * S)(*[int(k) for k in n_increments])
+    s = _lib.jfnk_newton_solve_batch(mesh.handle, C.cast(inc, C.c_void_p) if inc is not None else None,
+                                     C.byref(opts), _dptr(u, mesh.n_dof, "u"), C.cast(st, C.c_void_p),
+                                     C.cast(seg, C.c_void_p), work.c, _stream(stream))
+    _check(s, "jfnk_newton_solve_batch", allow)
+    return s, [x.as_dict() for x in st], list(seg)
 
 
 def profile_enable(mesh, on=True):

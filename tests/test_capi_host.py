@@ -1,0 +1,104 @@
+"""Host-side checks of the C-ABI library that need no GPU.
+
+* the library loads and exports every function declared in include/jfnk.h;
+* the host mesh preprocessing (jfnk_inspect_mesh) reproduces the oracle's
+  cell centroids and volumes (same geometric definitions, Section 2.3),
+  and reports invalid meshes and options with the documented status codes;
+* the bandwidth-reducing renumbering is a permutation and never worse than
+  the input order.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+from oracle.geometry import mesh_geometry
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jfnk.h")
+LIB = os.path.join(ROOT, "paper_2502_17217_amd", "libjfnk.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:jfnk_status|const char\*)\s+(jfnk_\w+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported():
+    assert os.path.exists(LIB), "libjfnk.so not built"
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.fixture(scope="module")
+def jfnk():
+    from paper_2502_17217_amd import jfnk as j
+    return j
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d", "annulus"])
+def test_inspect_geometry_matches_oracle(jfnk, kind):
+    if kind == "2d":
+        m = mg.box_mesh_2d(29, 17, 1.3, 0.9, jitter=0.25, seed=4)
+    elif kind == "3d":
+        m = mg.box_mesh_3d(11, 7, 5, 1.0, 0.8, 0.6, jitter=0.25, seed=5)
+    else:
+        m = mg.annulus_mesh_2d(6, 40, 0.5, 1.0)
+    info, xc, vol = jfnk.inspect_mesh(m, mg.Material(), geometry=True)
+    g = mesh_geometry(m)
+    assert info["n_cells"] == m["n_cells"]
+    assert info["n_internal_faces"] == m["n_internal"]
+    assert np.abs(xc - g["xc"]).max() <= 1e-13 * np.abs(g["xc"]).max()
+    assert np.abs(vol - g["V"]).max() <= 1e-12 * g["V"].max()
+
+
+def test_renumbering_reduces_bandwidth(jfnk):
+    m = mg.box_mesh_3d(60, 8, 5)      # natural order has bandwidth 60*8
+    info = jfnk.inspect_mesh(m, mg.Material())
+    assert info["bandwidth"] <= 60 * 8
+    assert info["bandwidth"] < 100
+
+
+def test_invalid_mesh_reported(jfnk):
+    m = mg.box_mesh_3d(3, 3, 3)
+    bad = dict(m)
+    nb = m["neighbour"].copy()
+    nb[0] = m["n_cells"] + 5
+    bad["neighbour"] = nb
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(bad, mg.Material())
+    assert e.value.status == jfnk.E_MESH
+    # inverted cell: swap two vertices of every face of one cell -> non-positive volume
+    bad2 = dict(m)
+    pts = m["points"].copy()
+    pts[:, 0] *= -1.0
+    bad2["points"] = pts
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(bad2, mg.Material())
+    assert e.value.status == jfnk.E_MESH
+
+
+def test_bad_material_and_patches(jfnk):
+    m = mg.box_mesh_2d(4, 4)
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(m, mg.Material(nu=0.5))
+    assert e.value.status == jfnk.E_ARG
+    m2 = dict(m)
+    m2["patches"] = m["patches"][:-1]      # a boundary face in no patch
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(m2, mg.Material())
+    assert e.value.status == jfnk.E_ARG
+
+
+def test_singular_least_squares_matrix(jfnk):
+    m = mg.box_mesh_2d(5, 1)            # one cell thick: no y-direction neighbours
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(m, mg.Material())
+    assert e.value.status == jfnk.E_MESH
