@@ -61,6 +61,133 @@ def algorithmic_bytes(info, dim):
     }
 
 
+def _plain_opts(jfnk, n_increments, rtol, eta, restart, max_it):
+    """One-solve-at-a-time FP64 path: FP64 diagonal (block-Jacobi) preconditioner."""
+    return jfnk.newton_opts(n_increments=n_increments, max_newton_it=20, rtol=rtol, eta=eta,
+                            restart=restart, max_it=max_it, precond="jacobi")
+
+
+def _fast_opts(jfnk, n_increments, rtol, eta, restart, max_it):
+    """FP32 aggregation-AMG / Chebyshev(3) preconditioner inside flexible GMRES."""
+    return jfnk.newton_opts(n_increments=n_increments, max_newton_it=20, rtol=rtol, eta=eta,
+                            restart=restart, max_it=max_it, precond="amg32", cheb_degree=3)
+
+
+def _solve_plain(jfnk, torch, mesh, material, opts):
+    gm = jfnk.create_mesh(mesh, material)
+    w = jfnk.make_workspace(gm, 1, restart=opts.gmres.restart, precond=opts.gmres.precond)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    st, stats = jfnk.newton_solve(gm, opts, u, w)
+    out = gm.to_external(u).cpu().numpy()
+    gm.close()
+    return st, stats, out
+
+
+def batched_vs_plain(n_problems, log):
+    """Batched linear-elastic block solves (one handle per dimension, FP32 AMG
+    preconditioner) against the same problems solved one at a time on the
+    FP64 path, both to a final relative residual of 1e-8."""
+    import numpy as np
+    import torch
+    import meshgen as mg
+    from paper_2502_17217_amd import jfnk
+    cfg = mg.config_c4(n_problems)
+    probs = cfg["problems"]
+    rtol, restart = 1e-8, 30
+    t_plain, t_batch, sol_plain, ok_plain = 0.0, 0.0, [], 0
+    plain = _plain_opts(jfnk, 1, rtol, rtol, restart, 100000)
+    _solve_plain(jfnk, torch, probs[0]["mesh"], probs[0]["material"], plain)       # warm-up
+    for p in probs:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats, u = _solve_plain(jfnk, torch, p["mesh"], p["material"], plain)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t
+        sol_plain.append(u)
+        ok_plain += int(st == jfnk.OK)
+    log("batched leg: plain FP64 path %.2fs for %d solves (%d converged)" % (t_plain, len(probs), ok_plain))
+    fast = _fast_opts(jfnk, 1, rtol, rtol, restart, 100000)
+    max_diff, ok_batch, gmres_it = 0.0, 0, []
+    for dim in (2, 3):
+        idx = [i for i, p in enumerate(probs) if p["mesh"]["dim"] == dim]
+        if not idx:
+            continue
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        gm = jfnk.create_batch([probs[i]["mesh"] for i in idx], [probs[i]["material"] for i in idx])
+        w = jfnk.make_workspace(gm, 1, restart=restart, precond=jfnk.PC_AMG32)
+        u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+        st, stats, seg = jfnk.newton_solve_batch(gm, fast, u, w)
+        ue = gm.to_external(u).cpu().numpy()
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t
+        for k, i in enumerate(idx):
+            us = ue[gm.segment_slice_external(k)]
+            ref = sol_plain[i]
+            max_diff = max(max_diff, float(np.linalg.norm(us - ref) / max(np.linalg.norm(ref), 1e-300)))
+            ok_batch += int(seg[k] == jfnk.OK)
+            gmres_it.append(stats[k]["gmres_it"])
+        gm.close()
+    log("batched leg: batched FP32-AMG path %.2fs (%d converged), max rel diff vs plain %.2e"
+        % (t_batch, ok_batch, max_diff))
+    cells = int(sum(p["mesh"]["n_cells"] for p in probs))
+    return {"workload": "%d linear-elastic 2D/3D block solves, %d cells in total, final rel. residual 1e-8"
+                        % (len(probs), cells),
+            "solves_per_s": len(probs) / t_batch, "plain_solves_per_s": len(probs) / t_plain,
+            "speedup": t_plain / t_batch, "converged": ok_batch, "plain_converged": ok_plain,
+            "max_rel_l2_vs_plain": max_diff, "median_gmres_it": float(np.median(gmres_it)),
+            "timing": "host wall clock incl. device mesh setup, solve and copy-out"}
+
+
+def serving(rate, seconds, max_cells, log):
+    """Poisson request stream through the request server (FP32-AMG flexible
+    GMRES, continuous admission onto 4 streams) against the same requests
+    solved one after another on the FP64 path."""
+    import numpy as np
+    import torch
+    import meshgen as mg
+    from paper_2502_17217_amd import jfnk
+    reqs = mg.config_c5_stream(rate=rate, duration=seconds, hi=max_cells)
+    rtol, eta, restart = 1e-8, 1e-4, 30
+    srv = jfnk.Server(hbm_budget=64 << 30, max_slots=4)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if r["t_arrival"] > now:
+            time.sleep(r["t_arrival"] - now)
+        tickets.append(srv.submit(r["mesh"], r["material"],
+                                  _fast_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000)))
+    res = [srv.wait(t) for t in tickets]
+    t_all = time.perf_counter() - t0
+    mt = srv.metrics()
+    srv.close()
+    ok = sum(int(i["status"] == jfnk.OK) for i, _ in res)
+    log("serving leg: %d requests in %.2fs, p50 %.1f ms, p99 %.1f ms, %d converged"
+        % (len(reqs), t_all, mt["p50_ms"], mt["p99_ms"], ok))
+    # the same requests one after another on the FP64 path (no arrival gaps)
+    t_plain, lat, max_diff = 0.0, [], 0.0
+    for r, (_, u) in zip(reqs, res):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats, up = _solve_plain(jfnk, torch, r["mesh"], r["material"],
+                                     _plain_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000))
+        dt = time.perf_counter() - t
+        t_plain += dt
+        lat.append(dt * 1e3)
+        max_diff = max(max_diff, float(np.linalg.norm(u - up) / max(np.linalg.norm(up), 1e-300)))
+    log("serving leg: plain sequential FP64 path %.2fs, max rel diff %.2e" % (t_plain, max_diff))
+    return {"workload": "Poisson stream %.0f req/s for %.0f s (%d requests), 5k-%.0fk cells, 70%% linear "
+                        "elastic / 30%% neo-Hookean with 1-5 increments, Newton rtol 1e-8"
+                        % (rate, seconds, len(reqs), max_cells / 1e3),
+            "p50_ms": mt["p50_ms"], "p99_ms": mt["p99_ms"], "solves_per_s": mt["solves_per_s"],
+            "completed": mt["completed"], "converged": ok, "hbm_peak_bytes": mt["hbm_peak"],
+            "plain_solves_per_s": len(reqs) / t_plain,
+            "plain_p50_ms_service": float(np.percentile(lat, 50)),
+            "plain_p99_ms_service": float(np.percentile(lat, 99)),
+            "max_rel_l2_served_vs_plain": max_diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +199,15 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-solve and serving measurements")
+    ap.add_argument("--batch-problems", type=int, default=48,
+                    help="problems of the batched workload (log-uniform 1k-100k cells)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="length of the Poisson request stream of the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
+    ap.add_argument("--serve-max-cells", type=float, default=1e5,
+                    help="largest request of the serving leg (log-uniform from 5k cells)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -177,6 +313,11 @@ def main():
                        sample="one FD J.v (R(u) cached, geometry precomputed and untimed) of the "
                               "same %d-cell workload, numpy FP64, single thread" % gm.n_cells)
 
+    extras = None
+    if not args.no_extras:
+        extras = {"batched": batched_vs_plain(args.batch_problems, log),
+                  "serving": serving(args.serve_rate, args.serve_seconds, args.serve_max_cells, log)}
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -200,6 +341,7 @@ def main():
         "kernels": kern,
         "cpu_baseline": cpu,
         "parity": parity,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
     gm.close()

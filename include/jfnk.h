@@ -272,6 +272,60 @@ jfnk_status jfnk_newton_solve_batch(jfnk_mesh* mesh, const int32_t* n_increments
                                     const jfnk_newton_opts* opts, double* d_u, jfnk_stats* stats,
                                     jfnk_status* seg_status, void* d_work, void* stream);
 
+/* ---- Serving: a request loop with continuous admission ----
+ * Requests (a mesh, its material and Newton options) are queued in arrival
+ * order.  Each of max_slots workers owns a HIP stream; a free worker takes
+ * the next request, validates and preprocesses its mesh on the host, then
+ * reserves the request's device footprint (mesh arrays + solver workspace +
+ * preconditioner) from hbm_budget, waiting in arrival order until it fits,
+ * and runs the solve on its stream.  Requests that arrive while others run
+ * are admitted as soon as a slot and memory are free, and their kernels
+ * overlap with the running ones on the device.  Each solve keeps its mesh,
+ * Krylov basis and Newton state on the device until it completes; the
+ * solution is copied to the caller's host array.  A request's result does
+ * not depend on what else is running (same kernels, same order).
+ * Latency = completion - submission (server clock).  dry_run_us_per_kcell
+ * > 0 replaces the solve by a host sleep of that many microseconds per
+ * 1000 cells and never touches the GPU (scheduler tests). */
+typedef struct jfnk_server jfnk_server;
+
+typedef struct {
+  size_t hbm_budget;             /* device bytes the server may hold for requests */
+  int32_t max_slots;             /* concurrent requests (one HIP stream each), >= 1 */
+  int32_t max_queue;             /* queued requests before submit returns JFNK_E_BUSY */
+  double dry_run_us_per_kcell;   /* > 0: scheduler-only mode, see above */
+} jfnk_server_opts;
+
+typedef struct {
+  int32_t status;                /* jfnk_status of the request */
+  int32_t state;                 /* 0 queued, 1 running, 2 done */
+  double t_submit_ms, t_start_ms, t_done_ms;   /* server clock */
+  double latency_ms;             /* t_done - t_submit */
+  int64_t footprint_bytes;
+  int64_t n_cells;
+  jfnk_stats stats;
+} jfnk_request_info;
+
+typedef struct {
+  int64_t submitted, completed, rejected, running, queued;
+  int64_t hbm_in_use, hbm_peak;
+  double p50_ms, p99_ms, mean_ms, max_ms;      /* latency of completed requests */
+  double solves_per_s;           /* completed / (last completion - first submission) */
+} jfnk_server_metrics;
+
+jfnk_status jfnk_server_create(const jfnk_server_opts* opts, jfnk_server** out);
+/* Copies the mesh description; u_out (host [n_cells * dim], interleaved
+ * input order, may be NULL) is written when the request completes and must
+ * stay valid until then.  Returns JFNK_E_BUSY when the queue is full. */
+jfnk_status jfnk_server_submit(jfnk_server* srv, const jfnk_mesh_desc* desc, const jfnk_material* mat,
+                               const jfnk_newton_opts* opts, double* u_out, uint64_t* ticket);
+jfnk_status jfnk_server_poll(jfnk_server* srv, uint64_t ticket, jfnk_request_info* info);
+/* Blocks until the request is done. */
+jfnk_status jfnk_server_wait(jfnk_server* srv, uint64_t ticket, jfnk_request_info* info);
+jfnk_status jfnk_server_metrics_get(jfnk_server* srv, jfnk_server_metrics* m);
+/* Finishes running and queued requests, then stops the workers. */
+jfnk_status jfnk_server_destroy(jfnk_server* srv);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* jfnk_last_error(void);
 

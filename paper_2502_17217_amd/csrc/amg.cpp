@@ -318,12 +318,13 @@ void DevCsr::upload(const HostCsr& h, hipStream_t s) {
   JFNK_HIP(hipStreamSynchronize(s));
 }
 
-size_t amg_work_floats(const jfnk_mesh* m) {
+size_t amg_work_floats(int64_t n, int dim) {
   // upper bound before setup: five work vectors per level with a geometric
   // level-size bound (each level at most 3/4 of the previous one)
-  const int64_t n = m->host.n_cells;
-  return size_t(5) * m->host.dim * size_t(4 * n + 64 * kMaxLevels) + 2 * kDenseMax * m->host.dim;
+  return size_t(5) * dim * size_t(4 * n + 64 * kMaxLevels) + 2 * kDenseMax * dim;
 }
+
+size_t amg_work_floats(const jfnk_mesh* m) { return amg_work_floats(m->host.n_cells, m->host.dim); }
 
 void amg_setup(jfnk_mesh* m, hipStream_t s) {
   if (m->amg) return;
@@ -383,7 +384,7 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
       A = std::move(Ac);
     }
     H->work_floats = off;
-    JFNK_REQUIRE(H->work_floats <= amg_work_floats(m), JFNK_E_ARG,
+    JFNK_REQUIRE(H->work_floats <= amg_work_floats(m->host.n_cells, m->host.dim), JFNK_E_ARG,
                  "amg: hierarchy larger than the workspace bound");
     H->setup_ms = now_ms() - t0;
   } catch (...) {

@@ -52,13 +52,6 @@ void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
     JFNK_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-size_t device_bytes_of(const HostMesh& h) {
-  auto b = [](size_t x) { return std::max<size_t>(x, 256); };
-  return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
-         b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
-         b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
-         b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256;
-}
 
 void check_mesh(const jfnk_mesh* m) {
   JFNK_REQUIRE(m != nullptr, JFNK_E_ARG, "null mesh handle");
@@ -85,6 +78,14 @@ void check_opts(const jfnk_gmres_opts& o) {
 }
 
 }  // namespace
+
+size_t device_bytes_of(const HostMesh& h) {
+  auto b = [](size_t x) { return std::max<size_t>(x, 256); };
+  return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
+         b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
+         b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
+         b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256;
+}
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
@@ -129,18 +130,26 @@ Profiler::~Profiler() {
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
+AllocContext& alloc_context() {
+  thread_local AllocContext ctx;
+  return ctx;
+}
+
 void DevBuf::release() noexcept {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (stream)
+      (void)hipFreeAsync(p, stream);
+    else
+      (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
 }
 
 void DevBuf::alloc(size_t b) {
-  if (p) {
-    (void)hipFree(p);
-    p = nullptr;
-  }
-  hipError_t e = hipMalloc(&p, b);
+  release();
+  stream = alloc_context().stream;
+  hipError_t e = stream ? hipMallocAsync(&p, b, stream) : hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
     throw Error{JFNK_E_OOM, "device allocation of " + std::to_string(b) + " bytes failed"};
@@ -152,14 +161,7 @@ void DevBuf::alloc(size_t b) {
 
 using namespace jfnk;
 
-extern "C" {
-
-const char* jfnk_last_error(void) { return g_last_error.c_str(); }
-
-const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
-
 namespace jfnk {
-namespace {
 
 // Build the union of the handle's segments and upload it.
 void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
@@ -187,8 +189,14 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   JFNK_HIP(hipStreamSynchronize(s));
   const int S = m.n_seg();
   m.pinned_doubles = size_t(4 * kMaxBasis + 8) * size_t(std::max(S, 1)) + 64;
-  JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.pinned), sizeof(double) * m.pinned_doubles,
-                         hipHostMallocDefault));
+  AllocContext& ac = alloc_context();
+  if (ac.pinned && ac.pinned_doubles >= m.pinned_doubles) {
+    m.pinned = ac.pinned;
+    m.pinned_owned = false;
+  } else {
+    JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.pinned), sizeof(double) * m.pinned_doubles,
+                           hipHostMallocDefault));
+  }
   MeshDev& d = m.dev;
   d.n_cells = int32_t(h.n_cells);
   d.dim = dim;
@@ -224,8 +232,14 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   in.setup_ms = now_ms() - t0;
 }
 
-}  // namespace
 }  // namespace jfnk
+
+extern "C" {
+
+const char* jfnk_last_error(void) { return g_last_error.c_str(); }
+
+const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
+
 
 jfnk_status jfnk_create_mesh(const jfnk_mesh_desc* desc, const jfnk_material* mat, void* stream,
                              jfnk_mesh** out) {
@@ -299,7 +313,7 @@ jfnk_status jfnk_destroy_mesh(jfnk_mesh* mesh) {
   return guarded([&] {
     if (!mesh) return;
     if (mesh->amg) amg_destroy(mesh->amg);
-    if (mesh->pinned) (void)hipHostFree(mesh->pinned);
+    if (mesh->pinned && mesh->pinned_owned) (void)hipHostFree(mesh->pinned);
     delete mesh;
   });
 }

@@ -134,14 +134,28 @@ struct UnionArrays {
   std::vector<SegInfo> seg;
 };
 
+// Allocation context of the calling thread: when `stream` is set (the
+// request workers of the server), device buffers are allocated and freed
+// stream-ordered on it, so that one request's allocations never wait for
+// the work of requests running on other streams; `pinned` (if set) is a
+// caller-owned pinned host buffer of `pinned_doubles` doubles that new mesh
+// handles use instead of allocating their own.
+struct AllocContext {
+  hipStream_t stream = nullptr;
+  double* pinned = nullptr;
+  size_t pinned_doubles = 0;
+};
+AllocContext& alloc_context();
+
 // Device buffer with RAII.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t stream = nullptr;  // non-null: allocated with hipMallocAsync on this stream
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), stream(o.stream) {
     o.p = nullptr;
     o.bytes = 0;
   }
@@ -150,6 +164,7 @@ struct DevBuf {
       release();
       p = o.p;
       bytes = o.bytes;
+      stream = o.stream;
       o.p = nullptr;
       o.bytes = 0;
     }
@@ -207,6 +222,7 @@ struct jfnk_mesh {
       b_seg_of_block, b_seg, b_block_first;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
+  bool pinned_owned = true;
   jfnk_mesh_info info{};
   jfnk::AmgHierarchy* amg = nullptr;
   jfnk::Profiler prof;
@@ -230,6 +246,9 @@ void launch_eps(const MeshDev& m, const int32_t* block_first, const double* u, c
                 double* partials, double* d_eps, const int32_t* active, hipStream_t s);
 void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s);
 void build_union(jfnk_mesh& m, UnionArrays& ua);
+// Upload the union of m's segments on stream s (mesh handle setup).
+void finish_handle(jfnk_mesh& m, hipStream_t s, double t0);
+size_t device_bytes_of(const HostMesh& h);
 
 void launch_permute(const int32_t* ext_of_int, const double* in, double* out, int64_t n_cells, int dim,
                     bool to_internal, hipStream_t s);

@@ -10,11 +10,16 @@
 namespace jfnk {
 
 size_t amg_work_floats(const jfnk_mesh* m);
+size_t amg_work_floats(int64_t n, int dim);
 void amg_setup(jfnk_mesh* m, hipStream_t s);
 void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s);
 
 size_t precond_work_floats(const jfnk_mesh* m, int precond) {
   return precond == JFNK_PC_AMG32 ? amg_work_floats(m) : 0;
+}
+
+size_t precond_work_floats(int64_t n_cells, int dim, int precond) {
+  return precond == JFNK_PC_AMG32 ? amg_work_floats(n_cells, dim) : 0;
 }
 
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s) {

@@ -42,6 +42,7 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk
                   std::vector<jfnk_status>& status);
 
 size_t precond_work_floats(const jfnk_mesh* m, int precond);
+size_t precond_work_floats(int64_t n_cells, int dim, int precond);
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s);
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
                    KrylovWork& kw, hipStream_t s);

@@ -25,7 +25,8 @@ struct Carver {
   }
 };
 
-inline int64_t n_tiles(const jfnk_mesh* m) { return (m->host.n_cells + kFvBlock - 1) / kFvBlock; }
+inline int64_t n_tiles(int64_t n_cells) { return (n_cells + kFvBlock - 1) / kFvBlock; }
+inline int64_t n_tiles(const jfnk_mesh* m) { return n_tiles(m->host.n_cells); }
 
 // Regions used by jfnk_residual / jfnk_jv.
 struct FvWork {
@@ -34,15 +35,14 @@ struct FvWork {
   double* partials = nullptr;  // [n_tiles * kMaxBasis]
   double* eps = nullptr;       // [n_seg] J v step per segment
   double* load = nullptr;      // [n_seg] load factor per segment
-  void carve(Carver& c, const jfnk_mesh* m) {
-    const int64_t n = m->host.n_cells;
-    const int S = m->n_seg();
-    grad = c.take<double>(size_t(n) * rec_doubles(m->host.dim));
-    ru = c.take<double>(size_t(n) * m->host.dim);
-    partials = c.take<double>(size_t(n_tiles(m)) * kMaxBasis);
+  void carve(Carver& c, int64_t n, int dim, int S) {
+    grad = c.take<double>(size_t(n) * rec_doubles(dim));
+    ru = c.take<double>(size_t(n) * dim);
+    partials = c.take<double>(size_t(n_tiles(n)) * kMaxBasis);
     eps = c.take<double>(S);
     load = c.take<double>(S);
   }
+  void carve(Carver& c, const jfnk_mesh* m) { carve(c, m->host.n_cells, m->host.dim, m->n_seg()); }
 };
 
 // Additional regions used by the Krylov solver and Newton.
@@ -63,8 +63,9 @@ struct KrylovWork {
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
   void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f) {
-    const int64_t n_dof = m->host.n_cells * m->host.dim;
-    const int S = m->n_seg();
+    carve(c, m->host.n_cells * m->host.dim, m->n_seg(), restart, pc_f);
+  }
+  void carve(Carver& c, int64_t n_dof, int S, int restart, size_t pc_f) {
     V = c.take<double>(size_t(restart + 1) * n_dof);
     Z = c.take<double>(size_t(restart) * n_dof);
     w = c.take<double>(n_dof);
@@ -82,5 +83,15 @@ struct KrylovWork {
     pc = pc_f ? c.take<float>(pc_f) : nullptr;
   }
 };
+
+// Workspace bytes of a solve (op 1) on n cells of dimension dim in S segments.
+inline size_t solve_workspace_bytes(int64_t n, int dim, int S, int restart, size_t pc_floats) {
+  Carver c(nullptr);
+  FvWork fw;
+  fw.carve(c, n, dim, S);
+  KrylovWork kw;
+  kw.carve(c, n * dim, S, restart, pc_floats);
+  return c.off;
+}
 
 }  // namespace jfnk

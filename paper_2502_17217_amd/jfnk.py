@@ -384,3 +384,96 @@ def profile_read(mesh, reset=True):
     _check(_lib.jfnk_profile_read(mesh.handle, ms, calls, 1 if reset else 0), "jfnk_profile_read")
     names = ["eps", "gradient", "flux", "precond"]
     return {n: (ms[i], calls[i]) for i, n in enumerate(names)}
+
+
+# ---------------------------------------------------------------- serving
+class jfnk_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("max_queue", C.c_int32),
+                ("dry_run_us_per_kcell", C.c_double)]
+
+
+class jfnk_request_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("state", C.c_int32), ("t_submit_ms", C.c_double),
+                ("t_start_ms", C.c_double), ("t_done_ms", C.c_double), ("latency_ms", C.c_double),
+                ("footprint_bytes", C.c_int64), ("n_cells", C.c_int64), ("stats", jfnk_stats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        return d
+
+
+class jfnk_server_metrics(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("running", C.c_int64), ("queued", C.c_int64), ("hbm_in_use", C.c_int64),
+                ("hbm_peak", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("solves_per_s", C.c_double)]
+
+
+def _server_sigs():
+    vp, i32 = C.c_void_p, C.c_int32
+    sig = {
+        "jfnk_server_create": [C.POINTER(jfnk_server_opts), C.POINTER(vp)],
+        "jfnk_server_submit": [vp, vp, vp, C.POINTER(jfnk_newton_opts), vp, C.POINTER(C.c_uint64)],
+        "jfnk_server_poll": [vp, C.c_uint64, C.POINTER(jfnk_request_info)],
+        "jfnk_server_wait": [vp, C.c_uint64, C.POINTER(jfnk_request_info)],
+        "jfnk_server_metrics_get": [vp, C.POINTER(jfnk_server_metrics)],
+        "jfnk_server_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(_lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+
+
+_server_sigs()
+
+
+class Server:
+    """Request loop of the library: continuous admission onto concurrent
+    streams under an HBM budget (see include/jfnk.h)."""
+
+    def __init__(self, hbm_budget, max_slots=4, max_queue=1 << 20, dry_run_us_per_kcell=0.0):
+        o = jfnk_server_opts(int(hbm_budget), int(max_slots), int(max_queue), float(dry_run_us_per_kcell))
+        h = C.c_void_p()
+        _check(_lib.jfnk_server_create(C.byref(o), C.byref(h)), "jfnk_server_create")
+        self.handle = h
+        self._out = {}
+
+    def submit(self, mesh, material, opts, keep_solution=True):
+        desc, keep = _make_desc(mesh)
+        mat = _make_material(material)
+        out = np.zeros(int(mesh["n_cells"]) * int(mesh["dim"])) if keep_solution else None
+        t = C.c_uint64()
+        _check(_lib.jfnk_server_submit(self.handle, C.byref(desc), C.byref(mat), C.byref(opts),
+                                       out.ctypes.data if out is not None else None, C.byref(t)),
+               "jfnk_server_submit")
+        del keep
+        self._out[t.value] = out
+        return t.value
+
+    def poll(self, ticket):
+        info = jfnk_request_info()
+        _check(_lib.jfnk_server_poll(self.handle, ticket, C.byref(info)), "jfnk_server_poll")
+        return info.as_dict()
+
+    def wait(self, ticket):
+        info = jfnk_request_info()
+        _check(_lib.jfnk_server_wait(self.handle, ticket, C.byref(info)), "jfnk_server_wait")
+        return info.as_dict(), self._out.get(ticket)
+
+    def metrics(self):
+        m = jfnk_server_metrics()
+        _check(_lib.jfnk_server_metrics_get(self.handle, C.byref(m)), "jfnk_server_metrics_get")
+        return {k: getattr(m, k) for k, _ in m._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(_lib.jfnk_server_destroy(self.handle), "jfnk_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

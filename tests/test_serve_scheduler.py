@@ -1,0 +1,117 @@
+"""Scheduler and admission logic of the request server, on the CPU.
+
+The server runs in dry-run mode: the solve is replaced by a host sleep
+proportional to the mesh size, so the queueing, HBM admission, rejection and
+latency accounting are exercised without a GPU.  Footprints are the real
+ones (host preprocessing of each mesh).
+"""
+
+import time
+
+import pytest
+
+import meshgen as mg
+
+
+@pytest.fixture(scope="module")
+def jfnk():
+    from paper_2502_17217_amd import jfnk as j
+    return j
+
+
+def _mesh(n):
+    m = mg.box_mesh_3d(n, n, n)
+    mg.set_patch(m, "zmin", "displacement", (0, 0, 0))
+    return m
+
+
+def test_admission_respects_budget_and_order(jfnk):
+    meshes = [_mesh(n) for n in (6, 10, 8, 12, 6, 9)]
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    probe = jfnk.Server(hbm_budget=1 << 40, max_slots=1, dry_run_us_per_kcell=10.0)
+    foot = []
+    for m in meshes:
+        info, _ = probe.wait(probe.submit(m, mg.Material(), opts, keep_solution=False))
+        foot.append(info["footprint_bytes"])
+    probe.close()
+    budget = int(max(foot) * 1.3)           # forces one large request at a time
+    srv = jfnk.Server(hbm_budget=budget, max_slots=4, dry_run_us_per_kcell=20000.0)
+    tickets = [srv.submit(m, mg.Material(), opts, keep_solution=False) for m in meshes]
+    peak_running = 0
+    while True:
+        mt = srv.metrics()
+        assert mt["hbm_in_use"] <= budget
+        peak_running = max(peak_running, mt["running"])
+        if mt["completed"] == len(meshes):
+            break
+        time.sleep(0.002)
+    infos = [srv.wait(t)[0] for t in tickets]
+    mt = srv.metrics()
+    srv.close()
+    assert all(i["status"] == jfnk.OK for i in infos)
+    assert mt["hbm_peak"] <= budget
+    # started in submission order (FIFO reservations)
+    starts = [i["t_start_ms"] for i in infos]
+    assert starts == sorted(starts)
+    assert mt["p99_ms"] >= mt["p50_ms"] > 0
+    assert mt["solves_per_s"] > 0
+    assert all(i["latency_ms"] >= i["t_done_ms"] - i["t_start_ms"] for i in infos)
+
+
+def test_concurrency_when_memory_allows(jfnk):
+    meshes = [_mesh(6) for _ in range(8)]
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=4, dry_run_us_per_kcell=100000.0)   # ~21 ms each
+    t0 = time.time()
+    tickets = [srv.submit(m, mg.Material(), opts, keep_solution=False) for m in meshes]
+    infos = [srv.wait(t)[0] for t in tickets]
+    wall = time.time() - t0
+    srv.close()
+    # 8 requests on 4 slots: about two rounds, not eight
+    assert wall < 6 * 0.0216
+    running_overlap = sum(1 for i in infos[1:] if i["t_start_ms"] < infos[0]["t_done_ms"])
+    assert running_overlap >= 3
+
+
+def test_oversized_request_rejected_others_served(jfnk):
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    small, big = _mesh(5), _mesh(14)
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=1, dry_run_us_per_kcell=1.0)
+    fs = srv.wait(srv.submit(small, mg.Material(), opts, keep_solution=False))[0]["footprint_bytes"]
+    srv.close()
+    srv = jfnk.Server(hbm_budget=int(fs * 2), max_slots=2, dry_run_us_per_kcell=1.0)
+    t1 = srv.submit(big, mg.Material(), opts, keep_solution=False)
+    t2 = srv.submit(small, mg.Material(), opts, keep_solution=False)
+    i1, i2 = srv.wait(t1)[0], srv.wait(t2)[0]
+    mt = srv.metrics()
+    srv.close()
+    assert i1["status"] == jfnk.E_OOM
+    assert i2["status"] == jfnk.OK
+    assert mt["rejected"] == 1 and mt["completed"] == 1
+
+
+def test_invalid_request_isolated(jfnk):
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    good = _mesh(5)
+    bad = dict(good)
+    bad["points"] = good["points"] * [-1.0, 1.0, 1.0]      # inverted cells
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=2, dry_run_us_per_kcell=1.0)
+    tb = srv.submit(bad, mg.Material(), opts, keep_solution=False)
+    tg = srv.submit(good, mg.Material(), opts, keep_solution=False)
+    assert srv.wait(tb)[0]["status"] == jfnk.E_MESH
+    assert srv.wait(tg)[0]["status"] == jfnk.OK
+    srv.close()
+
+
+def test_queue_limit(jfnk):
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=1, max_queue=2, dry_run_us_per_kcell=200000.0)
+    m = _mesh(6)
+    ts = [srv.submit(m, mg.Material(), opts, keep_solution=False) for _ in range(3)]
+    with pytest.raises(jfnk.JfnkError) as e:
+        for _ in range(3):
+            ts.append(srv.submit(m, mg.Material(), opts, keep_solution=False))
+    assert e.value.status == jfnk.E_BUSY
+    for t in ts:
+        srv.wait(t)
+    srv.close()
