@@ -33,6 +33,30 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, dim, law, shape):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary of the default workload, or None when the kernel
+    sources have changed since those counters were taken (or for another
+    workload)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "jv_kernels_nh_cantilever_1M_traffic.md")
+    if shape != (1000, 100, 10) or law != "neo_hookean" or not os.path.exists(path):
+        return None
+    block = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not block:
+        return None
+    rec = json.loads(block.group(1))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec["source_hash"]:
+        return None
+    name = {"flux": "jfnk::k_flux<%d, 1>" % dim, "gradient": "jfnk::k_gradient<%d>" % dim}.get(kernel)
+    k = rec["kernels"].get(name)
+    return k["traffic_bytes"] if k else None
+
+
 def nominal_centres(meta):
     import numpy as np
     nx, ny, nz = meta["n"]
@@ -73,119 +97,171 @@ def _fast_opts(jfnk, n_increments, rtol, eta, restart, max_it):
                             restart=restart, max_it=max_it, precond="amg32", cheb_degree=3)
 
 
+_FAILED = (-5, -6, -7, -8)   # not converged, diverged, NaN, breakdown: reported, not raised
+
+
 def _solve_plain(jfnk, torch, mesh, material, opts):
     gm = jfnk.create_mesh(mesh, material)
     w = jfnk.make_workspace(gm, 1, restart=opts.gmres.restart, precond=opts.gmres.precond)
     u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
-    st, stats = jfnk.newton_solve(gm, opts, u, w)
+    st, stats = jfnk.newton_solve(gm, opts, u, w, allow=_FAILED)
     out = gm.to_external(u).cpu().numpy()
     gm.close()
     return st, stats, out
 
 
-def batched_vs_plain(n_problems, log):
-    """Batched linear-elastic block solves (one handle per dimension, FP32 AMG
-    preconditioner) against the same problems solved one at a time on the
-    FP64 path, both to a final relative residual of 1e-8."""
-    import numpy as np
-    import torch
-    import meshgen as mg
-    from paper_2502_17217_amd import jfnk
-    cfg = mg.config_c4(n_problems)
-    probs = cfg["problems"]
-    rtol, restart = 1e-8, 30
-    t_plain, t_batch, sol_plain, ok_plain = 0.0, 0.0, [], 0
-    plain = _plain_opts(jfnk, 1, rtol, rtol, restart, 100000)
-    _solve_plain(jfnk, torch, probs[0]["mesh"], probs[0]["material"], plain)       # warm-up
-    for p in probs:
+def _one_at_a_time(jfnk, torch, problems, make_opts, log, label):
+    """Solve each problem alone, one after another; returns (seconds, solutions, ok flags, latencies_ms)."""
+    total, sols, ok, lat = 0.0, [], [], []
+    for i, p in enumerate(problems):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        st, stats, u = _solve_plain(jfnk, torch, p["mesh"], p["material"], plain)
+        st, stats, u = _solve_plain(jfnk, torch, p["mesh"], p["material"], make_opts(p))
         torch.cuda.synchronize()
-        t_plain += time.perf_counter() - t
-        sol_plain.append(u)
-        ok_plain += int(st == jfnk.OK)
-    log("batched leg: plain FP64 path %.2fs for %d solves (%d converged)" % (t_plain, len(probs), ok_plain))
-    fast = _fast_opts(jfnk, 1, rtol, rtol, restart, 100000)
-    max_diff, ok_batch, gmres_it = 0.0, 0, []
+        dt = time.perf_counter() - t
+        total += dt
+        lat.append(dt * 1e3)
+        sols.append(u)
+        ok.append(st == jfnk.OK)
+        if i % 8 == 7 or i + 1 == len(problems):
+            log("%s: %d/%d solved alone, %.2fs so far" % (label, i + 1, len(problems), total))
+    return total, sols, ok, lat
+
+
+def _rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _max_rel(pairs):
+    """Largest relative L2 difference over the pairs where both solves converged."""
+    vals = [_rel(a, b) for a, b, ok in pairs if ok]
+    return max(vals) if vals else None
+
+
+def _batched(jfnk, torch, problems, opts, restart):
+    """All problems in one handle per dimension; returns (seconds, solutions, per-problem status, gmres its)."""
+    total, sols, seg_ok, its = 0.0, [None] * len(problems), [0] * len(problems), [0] * len(problems)
     for dim in (2, 3):
-        idx = [i for i, p in enumerate(probs) if p["mesh"]["dim"] == dim]
+        idx = [i for i, p in enumerate(problems) if p["mesh"]["dim"] == dim]
         if not idx:
             continue
         torch.cuda.synchronize()
         t = time.perf_counter()
-        gm = jfnk.create_batch([probs[i]["mesh"] for i in idx], [probs[i]["material"] for i in idx])
+        gm = jfnk.create_batch([problems[i]["mesh"] for i in idx], [problems[i]["material"] for i in idx])
         w = jfnk.make_workspace(gm, 1, restart=restart, precond=jfnk.PC_AMG32)
         u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
-        st, stats, seg = jfnk.newton_solve_batch(gm, fast, u, w)
+        st, stats, seg = jfnk.newton_solve_batch(gm, opts, u, w)
         ue = gm.to_external(u).cpu().numpy()
         torch.cuda.synchronize()
-        t_batch += time.perf_counter() - t
+        total += time.perf_counter() - t
         for k, i in enumerate(idx):
-            us = ue[gm.segment_slice_external(k)]
-            ref = sol_plain[i]
-            max_diff = max(max_diff, float(np.linalg.norm(us - ref) / max(np.linalg.norm(ref), 1e-300)))
-            ok_batch += int(seg[k] == jfnk.OK)
-            gmres_it.append(stats[k]["gmres_it"])
+            sols[i] = ue[gm.segment_slice_external(k)].copy()
+            seg_ok[i] = int(seg[k] == jfnk.OK)
+            its[i] = stats[k]["gmres_it"]
         gm.close()
-    log("batched leg: batched FP32-AMG path %.2fs (%d converged), max rel diff vs plain %.2e"
-        % (t_batch, ok_batch, max_diff))
+    return total, sols, seg_ok, its
+
+
+def batched_vs_plain(n_problems, n_plain, log):
+    """Linear-elastic block solves to a final relative residual of 1e-8:
+    batched (one handle per dimension, FP32 AMG preconditioner) against the
+    same problems solved one at a time with the same preconditioner, and
+    against the one-at-a-time FP64 path (FP64 diagonal preconditioner) on
+    the first n_plain problems (that path needs thousands of iterations)."""
+    import numpy as np
+    import torch
+    import meshgen as mg
+    from paper_2502_17217_amd import jfnk
+    probs = mg.config_c4(n_problems)["problems"]
+    rtol, restart = 1e-8, 30
+    fast = _fast_opts(jfnk, 1, rtol, rtol, restart, 100000)
+    _solve_plain(jfnk, torch, probs[0]["mesh"], probs[0]["material"], fast)    # warm-up
+    t_b, sol_b, ok_b, its = _batched(jfnk, torch, probs, fast, restart)
+    log("batched leg: %d problems batched in %.2fs (%d converged)" % (len(probs), t_b, sum(ok_b)))
+    t_a, sol_a, ok_a, _ = _one_at_a_time(jfnk, torch, probs, lambda p: fast, log, "batched leg, FP32-AMG")
+    sample = probs[:n_plain]
+    t_bs, sol_bs, ok_bs, _ = _batched(jfnk, torch, sample, fast, restart)
+    t_p, sol_p, ok_p, _ = _one_at_a_time(jfnk, torch, sample,
+                                         lambda p: _plain_opts(jfnk, 1, rtol, rtol, restart, 20000),
+                                         log, "batched leg, FP64 plain")
     cells = int(sum(p["mesh"]["n_cells"] for p in probs))
-    return {"workload": "%d linear-elastic 2D/3D block solves, %d cells in total, final rel. residual 1e-8"
-                        % (len(probs), cells),
-            "solves_per_s": len(probs) / t_batch, "plain_solves_per_s": len(probs) / t_plain,
-            "speedup": t_plain / t_batch, "converged": ok_batch, "plain_converged": ok_plain,
-            "max_rel_l2_vs_plain": max_diff, "median_gmres_it": float(np.median(gmres_it)),
-            "timing": "host wall clock incl. device mesh setup, solve and copy-out"}
+    return {"workload": "%d linear-elastic 2D/3D block solves (1k-100k cells, %d in total), "
+                        "final relative residual 1e-8" % (len(probs), cells),
+            "solves_per_s": len(probs) / t_b, "converged": int(sum(ok_b)),
+            "alone_fp32pc_solves_per_s": len(probs) / t_a, "alone_fp32pc_converged": sum(ok_a),
+            "speedup_vs_alone_fp32pc": t_a / t_b,
+            "max_rel_l2_batched_vs_alone": _max_rel(
+                (a, b, x and y) for a, b, x, y in zip(sol_b, sol_a, ok_b, ok_a)),
+            "plain_fp64_sample": len(sample),
+            "plain_fp64_solves_per_s": len(sample) / t_p, "plain_fp64_converged": sum(ok_p),
+            "batched_sample_solves_per_s": len(sample) / t_bs,
+            "speedup_vs_plain_fp64": t_p / t_bs,
+            "max_rel_l2_batched_vs_plain_fp64": _max_rel(
+                (a, b, x and y) for a, b, x, y in zip(sol_bs, sol_p, ok_bs, ok_p)),
+            "median_gmres_it": float(np.median(its)),
+            "timing": "host wall clock incl. device mesh setup, preconditioner setup, solve and copy-out"}
 
 
-def serving(rate, seconds, max_cells, log):
-    """Poisson request stream through the request server (FP32-AMG flexible
-    GMRES, continuous admission onto 4 streams) against the same requests
-    solved one after another on the FP64 path."""
+def serving(rate, seconds, max_cells, n_plain, log):
+    """Request server (FP32-AMG flexible GMRES, continuous admission onto 4
+    streams) on a Poisson stream: latency percentiles at the offered rate,
+    then the same requests all submitted at once (capacity in solves/s),
+    against the same requests solved one after another alone (same
+    preconditioner) and the one-at-a-time FP64 path on the first n_plain."""
     import numpy as np
     import torch
     import meshgen as mg
     from paper_2502_17217_amd import jfnk
     reqs = mg.config_c5_stream(rate=rate, duration=seconds, hi=max_cells)
     rtol, eta, restart = 1e-8, 1e-4, 30
-    srv = jfnk.Server(hbm_budget=64 << 30, max_slots=4)
-    t0 = time.perf_counter()
-    tickets = []
-    for r in reqs:
-        now = time.perf_counter() - t0
-        if r["t_arrival"] > now:
-            time.sleep(r["t_arrival"] - now)
-        tickets.append(srv.submit(r["mesh"], r["material"],
-                                  _fast_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000)))
-    res = [srv.wait(t) for t in tickets]
-    t_all = time.perf_counter() - t0
-    mt = srv.metrics()
-    srv.close()
-    ok = sum(int(i["status"] == jfnk.OK) for i, _ in res)
-    log("serving leg: %d requests in %.2fs, p50 %.1f ms, p99 %.1f ms, %d converged"
-        % (len(reqs), t_all, mt["p50_ms"], mt["p99_ms"], ok))
-    # the same requests one after another on the FP64 path (no arrival gaps)
-    t_plain, lat, max_diff = 0.0, [], 0.0
-    for r, (_, u) in zip(reqs, res):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        st, stats, up = _solve_plain(jfnk, torch, r["mesh"], r["material"],
-                                     _plain_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000))
-        dt = time.perf_counter() - t
-        t_plain += dt
-        lat.append(dt * 1e3)
-        max_diff = max(max_diff, float(np.linalg.norm(u - up) / max(np.linalg.norm(up), 1e-300)))
-    log("serving leg: plain sequential FP64 path %.2fs, max rel diff %.2e" % (t_plain, max_diff))
-    return {"workload": "Poisson stream %.0f req/s for %.0f s (%d requests), 5k-%.0fk cells, 70%% linear "
-                        "elastic / 30%% neo-Hookean with 1-5 increments, Newton rtol 1e-8"
+    mk = lambda r: _fast_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000)
+
+    def run(paced):
+        srv = jfnk.Server(hbm_budget=64 << 30, max_slots=4)
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            now = time.perf_counter() - t0
+            if paced and r["t_arrival"] > now:
+                time.sleep(r["t_arrival"] - now)
+            tickets.append(srv.submit(r["mesh"], r["material"], mk(r)))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        mt = srv.metrics()
+        srv.close()
+        return res, wall, mt
+
+    res, t_all, mt = run(True)
+    ok = [i["status"] == jfnk.OK for i, _ in res]
+    log("serving leg: %d requests at %.0f req/s in %.2fs, p50 %.1f ms, p99 %.1f ms, %d converged"
+        % (len(reqs), rate, t_all, mt["p50_ms"], mt["p99_ms"], sum(ok)))
+    res_sat, t_sat, mt_sat = run(False)
+    log("serving leg: the same requests submitted at once: %.2fs" % t_sat)
+    t_a, sol_a, ok_a, lat_a = _one_at_a_time(jfnk, torch, reqs, mk, log, "serving leg, alone")
+    sample = reqs[:n_plain]
+    t_p, sol_p, ok_p, _ = _one_at_a_time(
+        jfnk, torch, sample, lambda r: _plain_opts(jfnk, r["n_increments"], rtol, eta, restart, 20000),
+        log, "serving leg, FP64 plain")
+    return {"workload": "Poisson stream %.0f req/s for %.0f s (%d requests), 3D blocks of 5k-%.0fk cells, "
+                        "70%% linear elastic / 30%% neo-Hookean with 1-5 increments, Newton rtol 1e-8"
                         % (rate, seconds, len(reqs), max_cells / 1e3),
-            "p50_ms": mt["p50_ms"], "p99_ms": mt["p99_ms"], "solves_per_s": mt["solves_per_s"],
-            "completed": mt["completed"], "converged": ok, "hbm_peak_bytes": mt["hbm_peak"],
-            "plain_solves_per_s": len(reqs) / t_plain,
-            "plain_p50_ms_service": float(np.percentile(lat, 50)),
-            "plain_p99_ms_service": float(np.percentile(lat, 99)),
-            "max_rel_l2_served_vs_plain": max_diff}
+            "p50_ms": mt["p50_ms"], "p99_ms": mt["p99_ms"], "solves_per_s_at_rate": mt["solves_per_s"],
+            "converged": sum(ok), "hbm_peak_bytes": mt["hbm_peak"],
+            "saturated_solves_per_s": len(reqs) / t_sat, "saturated_p99_ms": mt_sat["p99_ms"],
+            "alone_fp32pc_solves_per_s": len(reqs) / t_a, "alone_fp32pc_converged": sum(ok_a),
+            "alone_p50_ms_service": float(np.percentile(lat_a, 50)),
+            "alone_p99_ms_service": float(np.percentile(lat_a, 99)),
+            "speedup_saturated_vs_alone": t_a / t_sat,
+            "max_rel_l2_served_vs_alone": _max_rel(
+                (u, a, x and y) for (_, u), a, x, y in zip(res, sol_a, ok, ok_a)),
+            "bitwise_served_equals_saturated": all(
+                np.array_equal(u, v) for (_, u), (_, v) in zip(res, res_sat)),
+            "plain_fp64_sample": len(sample), "plain_fp64_solves_per_s": len(sample) / t_p,
+            "plain_fp64_converged": sum(ok_p),
+            "alone_fp32pc_sample_solves_per_s": len(sample) / (sum(lat_a[:len(sample)]) * 1e-3),
+            "max_rel_l2_served_vs_plain_fp64": _max_rel(
+                (u, a, x and y) for (_, u), a, x, y in zip(res, sol_p, ok, ok_p))}
 
 
 def main():
@@ -203,9 +279,11 @@ def main():
                     help="skip the batched-solve and serving measurements")
     ap.add_argument("--batch-problems", type=int, default=48,
                     help="problems of the batched workload (log-uniform 1k-100k cells)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
+    ap.add_argument("--plain-sample", type=int, default=4,
+                    help="problems solved on the FP64 diagonal-preconditioned path in each leg")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson request stream of the serving leg")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
+    ap.add_argument("--serve-rate", type=float, default=8.0, help="requests per second")
     ap.add_argument("--serve-max-cells", type=float, default=1e5,
                     help="largest request of the serving leg (log-uniform from 5k cells)")
     args = ap.parse_args()
@@ -315,8 +393,8 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = {"batched": batched_vs_plain(args.batch_problems, log),
-                  "serving": serving(args.serve_rate, args.serve_seconds, args.serve_max_cells, log)}
+        extras = {"batched": batched_vs_plain(args.batch_problems, args.plain_sample, log),
+                  "serving": serving(args.serve_rate, args.serve_seconds, args.serve_max_cells, args.plain_sample, log)}
 
     out = {
         "metric": METRIC,
@@ -335,8 +413,9 @@ def main():
                                "large-deflection state, auto eps" % (nx, ny, nz, gm.n_cells, gm.n_dof),
                    "law": mat.law, "cells": gm.n_cells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,
-                     "kernel": dom},
+                     "frac": ach / HBM_PEAK_GBS if ach else None,
+                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz)),
+                     "kernel": dom, "algorithmic_bytes": kern[dom]["bytes"]},
         "jv_hbm_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "kernels": kern,
         "cpu_baseline": cpu,

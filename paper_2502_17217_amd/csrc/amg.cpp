@@ -30,7 +30,7 @@ namespace jfnk {
 namespace {
 
 constexpr double kTheta = 0.08;
-constexpr int64_t kDenseMax = 400;
+constexpr int64_t kDenseMax = 200;
 constexpr int kMaxLevels = 16;
 
 double now_ms() {
@@ -148,9 +148,15 @@ std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, i
       }
     if (ba >= 0) agg[i] = ba;
   }
-  // pass 3: remaining nodes with their free strong neighbours, or singletons
+  // pass 3: remaining nodes with their free strong neighbours, or singletons.
+  // Nodes without any strong neighbour (padding rows of a batch, a mesh that
+  // has already been reduced to one coarse unknown) stay out of the coarse
+  // space: the smoother alone treats them.
   for (int64_t i = 0; i < n; ++i) {
     if (agg[i] >= 0) continue;
+    bool any = false;
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1] && !any; ++k) any = strong(i, k);
+    if (!any) continue;
     agg[i] = int32_t(nagg);
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
       if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = int32_t(nagg);
@@ -178,8 +184,9 @@ HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& d,
       }
       acc[c] += v;
     };
-    add(agg[i], 1.0);
-    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) add(agg[A.col[k]], -omega * A.val[k] / d[i]);
+    if (agg[i] >= 0) add(agg[i], 1.0);
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (agg[A.col[k]] >= 0) add(agg[A.col[k]], -omega * A.val[k] / d[i]);
     std::sort(cols.begin(), cols.end());
     for (int32_t c : cols) {
       if (acc[c] == 0.0) continue;
@@ -276,7 +283,7 @@ std::vector<float> dense_inverse(const HostCsr& A) {
       for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * x[k];
       x[i] = t / L[i * n + i];
     }
-    for (int64_t i = 0; i < n; ++i) inv[i * n + c] = float(x[i]);
+    for (int64_t i = 0; i < n; ++i) inv[c * n + i] = float(x[i]);   // column-major
   }
   return inv;
 }
@@ -378,9 +385,7 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
       L.off_d0 = take(A.n);
       L.off_d1 = take(A.n);
       H->levels.push_back(std::move(L));
-      if (nagg >= A.n) {  // no coarsening possible: solve densely if small, else stop here
-        JFNK_REQUIRE(nagg <= kDenseMax, JFNK_E_MESH, "amg: aggregation stalled on a large level");
-      }
+      JFNK_REQUIRE(nagg > 0 && nagg < A.n, JFNK_E_MESH, "amg: aggregation stalled on a large level");
       A = std::move(Ac);
     }
     H->work_floats = off;

@@ -32,7 +32,7 @@ struct AmgLevel {
 
 struct AmgHierarchy {
   std::vector<AmgLevel> levels;      // last level is solved by the dense inverse
-  DevBuf coarse_inv;                 // [n_c][n_c] FP32
+  DevBuf coarse_inv;                 // [n_c][n_c] FP32, column-major
   int64_t n_coarse = 0;
   int dim = 3;
   size_t work_floats = 0;

@@ -139,21 +139,39 @@ __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __rest
   }
 }
 
+// x = A_c^{-1} b on the coarsest level.  inv is column-major (column j
+// contiguous), so the 64 lanes of a wave read consecutive rows of one column
+// and b[j] is a broadcast; the four waves of a workgroup take every fourth
+// column and their partial sums meet in LDS.
 template <int D>
 __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, const float* __restrict__ b,
                                               float* __restrict__ x, int n) {
-  const int i = blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
+  constexpr int kWaves = kB / 64;
+  __shared__ float part[kWaves][D][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   float s[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.f;
-  for (int j = 0; j < n; ++j) {
-    const float a = inv[size_t(i) * n + j];
+  if (i < n) {
+    for (int j = wave; j < n; j += kWaves) {
+      const float a = inv[size_t(j) * n + i];
 #pragma unroll
-    for (int q = 0; q < D; ++q) s[q] = fmaf(a, b[size_t(q) * n + j], s[q]);
+      for (int q = 0; q < D; ++q) s[q] = fmaf(a, b[size_t(q) * n + j], s[q]);
+    }
   }
 #pragma unroll
-  for (int q = 0; q < D; ++q) x[size_t(q) * n + i] = s[q];
+  for (int q = 0; q < D; ++q) part[wave][q][lane] = s[q];
+  __syncthreads();
+  if (wave == 0 && i < n) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      float t = part[0][q][lane];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) t += part[w][q][lane];
+      x[size_t(q) * n + i] = t;
+    }
+  }
 }
 
 }  // namespace
@@ -211,7 +229,7 @@ void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int di
 }
 
 void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s) {
-  JFNK_DIM_DISPATCH(dim, k_dense, dim3(blocks_for(n)), dim3(kB), 0, s, inv, b, x, n);
+  JFNK_DIM_DISPATCH(dim, k_dense, dim3((n + 63) / 64), dim3(kB), 0, s, inv, b, x, n);
 }
 
 }  // namespace jfnk

@@ -126,3 +126,28 @@ def test_batch_newton_parity_and_alone_vs_mixed(lib, precond):
         assert diff <= 1e-8
         g1.close()
     gm.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_many_meshes_amg32(lib, dim):
+    """Two dozen meshes in one AMG32 hierarchy: every mesh coarsens to a
+    single unknown long before the union does, and the padding rows of the
+    256-cell alignment never couple to anything."""
+    probs = [p for p in mg.config_c4(64, seed=11, lo=60, hi=900)["problems"] if p["mesh"]["dim"] == dim][:24]
+    assert len(probs) >= 20
+    gm = lib.create_batch([p["mesh"] for p in probs], [p["material"] for p in probs])
+    work = lib.make_workspace(gm, 1, restart=40, precond=lib.PC_AMG32)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    opts = lib.newton_opts(max_newton_it=20, rtol=1e-10, eta=1e-10, restart=40, max_it=20000,
+                           precond="amg32", cheb_degree=3)
+    st, stats, seg = lib.newton_solve_batch(gm, opts, u, work)
+    assert st == lib.OK and all(x == lib.OK for x in seg), (st, seg)
+    ue = gm.to_external(u).cpu().numpy()
+    for s in (0, len(probs) // 2, len(probs) - 1):
+        m, mat = probs[s]["mesh"], probs[s]["material"]
+        uo, _ = o_newton(prepare(m, mat), n_increments=1, rtol=1e-10, max_newton_it=20, eta=1e-11,
+                         precond="lu", max_krylov_it=4000)
+        err = np.linalg.norm(ue[gm.segment_slice_external(s)] - uo) / np.linalg.norm(uo)
+        print("mesh", s, m["n_cells"], "err", err, stats[s]["gmres_it"])
+        assert err <= 1e-8
+    gm.close()
