@@ -23,7 +23,6 @@ Modules
   krylov    restarted (flexible) GMRES with classical Gram-Schmidt and
             re-orthogonalisation, right preconditioning
   newton    Newton-Raphson with equal load increments
-  loops     pure-Python per-face loop residual for tiny meshes
 """
 
 from .geometry import mesh_geometry
