@@ -131,6 +131,8 @@ typedef struct {
   int64_t n_slots;             /* cell-face slots in the packed slot map (incl. padding) */
   int32_t n_segments;          /* meshes in the handle (1, or the batch size) */
   int64_t n_dof_external;      /* length of an external vector (sum over meshes of n_cells * dim) */
+  int32_t tiled;               /* 1: cells ordered in compact tiles of 256 and the LDS-staged kernels run */
+  int32_t tile_halo_max;       /* largest number of outside neighbours of one tile (0 if not tiled) */
 } jfnk_mesh_info;
 
 /* Build the mesh handle: validates the mesh, renumbers cells, computes the

@@ -84,7 +84,9 @@ size_t device_bytes_of(const HostMesh& h) {
   return b(h.slice_ptr.size() * 4) + b(h.slot_nb.size() * 4) + b(h.slot_fc.size() * 4) +
          b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
          b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
-         b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256;
+         b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256 +
+         // tiles: slot_loc, halo_ptr and at most one halo entry per slot
+         (h.tiled ? 2 * b(h.slot_nb.size() * 4) + b(size_t(h.n_cells / kFvBlock + 2) * 4) : 0);
 }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -186,6 +188,11 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   upload(m.b_seg_of_block, ua.seg_of_block, s);
   upload(m.b_seg, ua.seg, s);
   upload(m.b_block_first, m.block_first, s);
+  if (h.tiled) {
+    upload(m.b_slot_loc, ua.slot_loc, s);
+    upload(m.b_halo_ptr, ua.halo_ptr, s);
+    upload(m.b_halo_cells, ua.halo_cells, s);
+  }
   JFNK_HIP(hipStreamSynchronize(s));
   const int S = m.n_seg();
   m.pinned_doubles = size_t(4 * kMaxBasis + 8) * size_t(std::max(S, 1)) + 64;
@@ -215,6 +222,11 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.bface = m.b_bface.as<double>();
   d.seg_of_block = m.b_seg_of_block.as<int32_t>();
   d.seg = m.b_seg.as<SegInfo>();
+  d.tiled = h.tiled ? 1 : 0;
+  d.halo_stride = int32_t(kFvBlock + ua.halo_max);
+  d.slot_loc = h.tiled ? m.b_slot_loc.as<int32_t>() : nullptr;
+  d.halo_ptr = h.tiled ? m.b_halo_ptr.as<int32_t>() : nullptr;
+  d.halo_cells = h.tiled ? m.b_halo_cells.as<int32_t>() : nullptr;
   jfnk_mesh_info& in = m.info;
   in.n_cells = h.n_cells;
   in.dim = dim;
@@ -225,10 +237,13 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   in.device_bytes = int64_t(m.b_slice_ptr.bytes + m.b_slot_nb.bytes + m.b_slot_fc.bytes + m.b_xc.bytes +
                             m.b_fG.bytes + m.b_fw.bytes + m.b_magG.bytes + m.b_bface.bytes +
                             m.b_ext.bytes + m.b_pc_dinv.bytes + m.b_seg_of_block.bytes + m.b_seg.bytes +
-                            m.b_block_first.bytes);
+                            m.b_block_first.bytes + m.b_slot_loc.bytes + m.b_halo_ptr.bytes +
+                            m.b_halo_cells.bytes);
   in.n_slots = int64_t(ua.slot_nb.size());
   in.n_segments = S;
   in.n_dof_external = m.n_ext_cells * dim;
+  in.tiled = d.tiled;
+  in.tile_halo_max = int32_t(ua.halo_max);
   in.setup_ms = now_ms() - t0;
 }
 
@@ -300,6 +315,8 @@ jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* m
     info->n_slots = int64_t(h.slot_nb.size());
     info->n_segments = 1;
     info->n_dof_external = h.n_cells * h.dim;
+    info->tiled = h.tiled ? 1 : 0;
+    info->tile_halo_max = int32_t(h.tile_halo_max);
     for (int64_t i = 0; i < h.n_cells; ++i) {
       const int64_t o = h.old_of_new[i];
       if (xc_out)

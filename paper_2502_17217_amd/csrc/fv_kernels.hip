@@ -201,27 +201,44 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int n, 
     for (int j = 0; j < D; ++j) g[i][j] = rec[size_t(D + i * D + j) * n + c];
 }
 
+// Neighbour data of the gradient pass: w = u + eps v and the centroid of
+// cell j, either gathered from global memory (j = cell number) or read from
+// the workgroup's LDS copy of its tile and halo (j = position in the copy).
 template <int D>
-__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev m, const double* __restrict__ u,
-                                                                           const double* __restrict__ v,
-                                                                           SegScalars sc,
-                                                                           double* __restrict__ rec, int nb_real) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  if (lb >= nb_real) return;
-  const int seg = m.seg_of_block[lb];
-  if (sc.active != nullptr && sc.active[seg] == 0) return;
-  const int c = lb * kFvBlock + threadIdx.x;
-  const int n = m.n_cells;
-  if (c >= n) return;
-  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {  // alignment padding
-#pragma unroll
-    for (int k = 0; k < D + D * D; ++k) rec[size_t(k) * n + c] = 0.0;
-    return;
+struct GradGlobal {
+  const double* u;
+  const double* v;
+  const double* xc;
+  double eps;
+  int n;
+  __device__ __forceinline__ void get(int j, double (&w)[D], double (&x)[D]) const {
+    load_w<D>(u, v, eps, n, j, w);
+    load_soa<D>(xc, n, j, x);
   }
-  const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
+};
+
+template <int D>
+struct GradLds {
+  const double* lds;  // [D][S] w, then [D][S] centroids
+  int S;
+  __device__ __forceinline__ void get(int j, double (&w)[D], double (&x)[D]) const {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      w[k] = lds[k * S + j];
+      x[k] = lds[(D + k) * S + j];
+    }
+  }
+};
+
+// Least-squares gradient of cell c (Eq. leastSquaresGrad with the weight
+// |Gamma_f| in the sum and in G_P) and its record {w, grad w}.  ids holds
+// the neighbour ids of the slots in the source's numbering; self is c's id.
+template <int D, class Src>
+__device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, const int32_t* __restrict__ ids,
+                                              int self, int c, double* __restrict__ rec) {
+  const int n = m.n_cells;
   double wP[D], xP[D];
-  load_w<D>(u, v, eps, n, c, wP);
-  load_soa<D>(m.xc, n, c, xP);
+  src.get(self, wP, xP);
   double Gs[D][D], M[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -235,17 +252,16 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       const int idx = s0 + (k0 + k) * kSlice + lane;
-      nb[k] = (k0 + k < width) ? m.slot_nb[idx] : kSlotPad;
+      nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
       fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
     }
     double mg[kChunk], xN[kChunk][D], wN[kChunk][D];
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
-      const int nn = nb[k] >= 0 ? nb[k] : c;
+      const int nn = nb[k] >= 0 ? nb[k] : self;
       const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
       mg[k] = nb[k] >= 0 ? m.magG[f] : 0.0;
-      load_soa<D>(m.xc, n, nn, xN[k]);
-      load_w<D>(u, v, eps, n, nn, wN[k]);
+      src.get(nn, wN[k], xN[k]);
     }
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
@@ -298,14 +314,114 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev
     for (int j = 0; j < D; ++j) rec[size_t(D + i * D + j) * n + c] = g[i][j];
 }
 
-// Sum of the face forces of cell c (Eq. divStressDiscret + Eq. RhieChow).
-template <int D, int LAW>
-__device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, const double* __restrict__ rec,
-                                            int c, double load, double (&R)[D]) {
+template <int D>
+__device__ __forceinline__ void zero_rec(double* __restrict__ rec, int n, int c) {
+#pragma unroll
+  for (int k = 0; k < D + D * D; ++k) rec[size_t(k) * n + c] = 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev m, const double* __restrict__ u,
+                                                                           const double* __restrict__ v,
+                                                                           SegScalars sc,
+                                                                           double* __restrict__ rec, int nb_real) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= nb_real) return;
+  const int seg = m.seg_of_block[lb];
+  if (sc.active != nullptr && sc.active[seg] == 0) return;
+  const int c = lb * kFvBlock + threadIdx.x;
   const int n = m.n_cells;
+  if (c >= n) return;
+  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {  // alignment padding
+    zero_rec<D>(rec, n, c);
+    return;
+  }
+  const GradGlobal<D> src{u, v, m.xc, (v != nullptr) ? sc.eps[seg] : 0.0, n};
+  gradient_cell<D>(m, src, m.slot_nb, c, c, rec);
+}
+
+// Tiled gradient pass: one workgroup per tile; w and the centroids of the
+// tile's cells and halo are staged in LDS with all lanes active, then every
+// neighbour is read from LDS.  Exits before the barrier are uniform over the
+// workgroup.
+template <int D>
+__global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const double* __restrict__ u,
+                                                             const double* __restrict__ v, SegScalars sc,
+                                                             double* __restrict__ rec, int nb_real) {
+  extern __shared__ double lds[];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= nb_real) return;
+  const int seg = m.seg_of_block[tile];
+  if (sc.active != nullptr && sc.active[seg] == 0) return;
+  const int n = m.n_cells, S = m.halo_stride;
+  const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
+  const int base = tile * kFvBlock;
+  const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+  for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
+    const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
+    double w[D], x[D];
+    if (cg < n) {
+      load_w<D>(u, v, eps, n, cg, w);
+      load_soa<D>(m.xc, n, cg, x);
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k) w[k] = x[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lds[k * S + i] = w[k];
+      lds[(D + k) * S + i] = x[k];
+    }
+  }
+  __syncthreads();
+  const int c = base + threadIdx.x;
+  if (c >= n) return;
+  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {
+    zero_rec<D>(rec, n, c);
+    return;
+  }
+  const GradLds<D> src{lds, S};
+  gradient_cell<D>(m, src, m.slot_loc, threadIdx.x, c, rec);
+}
+
+// Neighbour data of the flux pass: the record {w, grad w} and the centroid
+// of cell j, gathered from global memory or read from the LDS copy.
+template <int D>
+struct FluxGlobal {
+  const double* rec;
+  const double* xc;
+  int n;
+  __device__ __forceinline__ void get(int j, double (&w)[D], double (&g)[D][D], double (&x)[D]) const {
+    load_rec<D>(rec, n, j, w, g);
+    load_soa<D>(xc, n, j, x);
+  }
+};
+
+template <int D>
+struct FluxLds {
+  const double* lds;  // rows: w (D), grad w (D*D), centroid (D), each of length S
+  int S;
+  __device__ __forceinline__ void get(int j, double (&w)[D], double (&g)[D][D], double (&x)[D]) const {
+#pragma unroll
+    for (int k = 0; k < D; ++k) w[k] = lds[k * S + j];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) g[a][b] = lds[(D + a * D + b) * S + j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = lds[(D + D * D + k) * S + j];
+  }
+};
+
+// Sum of the face forces of cell c (Eq. divStressDiscret + Eq. RhieChow);
+// ids holds the neighbour ids of the slots in the source's numbering and
+// self is c's id.
+template <int D, int LAW, class Src>
+__device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, const Src& src,
+                                            const int32_t* __restrict__ ids, int self, int c, double load,
+                                            double (&R)[D]) {
   double wP[D], xP[D], gP[D][D];
-  load_rec<D>(rec, n, c, wP, gP);
-  load_soa<D>(m.xc, n, c, xP);
+  src.get(self, wP, gP, xP);
 #pragma unroll
   for (int k = 0; k < D; ++k) R[k] = 0.0;
   const int slice = c / kSlice, lane = c % kSlice;
@@ -316,7 +432,7 @@ __device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, co
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       const int idx = s0 + (k0 + k) * kSlice + lane;
-      nb[k] = (k0 + k < width) ? m.slot_nb[idx] : kSlotPad;
+      nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
       fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
     }
 #pragma unroll
@@ -327,8 +443,7 @@ __device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, co
         double G[D], xN[D], wN[D], gN[D][D];
         load_soa<D>(m.fG, m.n_int, f, G);
         const double wf = m.fw[f];
-        load_rec<D>(rec, n, nb[k], wN, gN);
-        load_soa<D>(m.xc, n, nb[k], xN);
+        src.get(nb[k], wN, gN, xN);
         // canonical operands: A = owner, B = neighbour of the face
         double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
 #pragma unroll
@@ -384,6 +499,33 @@ __device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, co
 
 constexpr int kLawMixed = -1;
 
+// R(w), or (R(w) - R(u))/eps when Ru is given, of cell c (not padding).
+template <int D, int LAWSEL, class Src>
+__device__ __forceinline__ void flux_cell(const MeshDev& m, const SegInfo& si, const Src& src,
+                                          const int32_t* __restrict__ ids, int self, int c, double load,
+                                          double eps, const double* __restrict__ Ru, double* __restrict__ out) {
+  const int n = m.n_cells;
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+  double R[D];
+  if constexpr (LAWSEL == kLawMixed) {
+    if (si.law == JFNK_NEO_HOOKEAN)
+      cell_forces<D, JFNK_NEO_HOOKEAN>(m, law, src, ids, self, c, load, R);
+    else
+      cell_forces<D, JFNK_LINEAR_ELASTIC>(m, law, src, ids, self, c, load, R);
+  } else {
+    cell_forces<D, LAWSEL>(m, law, src, ids, self, c, load, R);
+  }
+  if (Ru != nullptr) {
+    const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - Ru[size_t(q) * n + c]) * ie : 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
+  }
+}
+
 // LAWSEL: JFNK_LINEAR_ELASTIC, JFNK_NEO_HOOKEAN, or kLawMixed (law chosen per
 // segment, i.e. per workgroup).
 template <int D, int LAWSEL>
@@ -404,27 +546,49 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
     for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
     return;
   }
-  const Law law{si.mu, si.lam, si.kappa, si.aK};
-  const double load = sc.load[seg];
-  double R[D];
-  if constexpr (LAWSEL == kLawMixed) {
-    if (si.law == JFNK_NEO_HOOKEAN)
-      cell_forces<D, JFNK_NEO_HOOKEAN>(m, law, rec, c, load, R);
-    else
-      cell_forces<D, JFNK_LINEAR_ELASTIC>(m, law, rec, c, load, R);
-  } else {
-    cell_forces<D, LAWSEL>(m, law, rec, c, load, R);
-  }
-  if (Ru != nullptr) {
-    const double eps = sc.eps[seg];
-    const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+  const FluxGlobal<D> src{rec, m.xc, n};
+  flux_cell<D, LAWSEL>(m, si, src, m.slot_nb, c, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
+}
+
+// Tiled flux pass: the records and centroids of the tile's cells and halo
+// are staged in LDS (rows of length halo_stride), then every neighbour is
+// read from LDS.  Exits before the barrier are uniform over the workgroup.
+template <int D, int LAWSEL>
+__global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
+                                                         SegScalars sc, const double* __restrict__ Ru,
+                                                         double* __restrict__ out, int nb_real) {
+  extern __shared__ double lds[];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= nb_real) return;
+  const int seg = m.seg_of_block[tile];
+  if (sc.active != nullptr && sc.active[seg] == 0) return;
+  const int n = m.n_cells, S = m.halo_stride;
+  const int base = tile * kFvBlock;
+  const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+  constexpr int kRows = 2 * D + D * D;
+  for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
+    const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
+    if (cg < n) {
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-      out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - Ru[size_t(q) * n + c]) * ie : 0.0;
-  } else {
+      for (int r = 0; r < D + D * D; ++r) lds[r * S + i] = rec[size_t(r) * n + cg];
 #pragma unroll
-    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
+      for (int k = 0; k < D; ++k) lds[(D + D * D + k) * S + i] = m.xc[size_t(k) * n + cg];
+    } else {
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) lds[r * S + i] = 0.0;
+    }
   }
+  __syncthreads();
+  const int c = base + threadIdx.x;
+  if (c >= n) return;
+  const SegInfo& si = m.seg[seg];
+  if (c - si.cell_off >= si.n_cells) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
+    return;
+  }
+  const FluxLds<D> src{lds, S};
+  flux_cell<D, LAWSEL>(m, si, src, m.slot_loc, threadIdx.x, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
 }
 
 inline void grid_for(int n_cells, int& nb_real, int& nb_launch) {
@@ -438,33 +602,54 @@ void launch_gradient(const MeshDev& m, const double* u, const double* v, const S
                      double* rec, hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
-  if (m.dim == 3)
+  if (m.tiled) {
+    const size_t lds = sizeof(double) * 2 * m.dim * size_t(m.halo_stride);
+    if (m.dim == 3)
+      hipLaunchKernelGGL(k_gradient_tiled<3>, dim3(nl), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr);
+    else
+      hipLaunchKernelGGL(k_gradient_tiled<2>, dim3(nl), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr);
+  } else if (m.dim == 3) {
     hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
-  else
+  } else {
     hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
+  }
   JFNK_HIP(hipGetLastError());
 }
 
-void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
+namespace {
+
+template <int D, int LAWSEL>
+void flux_launch(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
                  hipStream_t s) {
   int nr, nl;
   grid_for(m.n_cells, nr, nl);
-  const dim3 g(nl), b(kFvBlock);
+  if (m.tiled) {
+    const size_t lds = sizeof(double) * (2 * D + D * D) * size_t(m.halo_stride);
+    hipLaunchKernelGGL((k_flux_tiled<D, LAWSEL>), dim3(nl), dim3(kFvBlock), lds, s, m, rec, sc, Ru, out, nr);
+  } else {
+    hipLaunchKernelGGL((k_flux<D, LAWSEL>), dim3(nl), dim3(kFvBlock), 0, s, m, rec, sc, Ru, out, nr);
+  }
+}
+
+}  // namespace
+
+void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
+                 hipStream_t s) {
   const int mask = m.law_mask;
   if (m.dim == 3) {
     if (mask == 2)
-      hipLaunchKernelGGL((k_flux<3, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<3, JFNK_NEO_HOOKEAN>(m, rec, sc, Ru, out, s);
     else if (mask == 1)
-      hipLaunchKernelGGL((k_flux<3, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<3, JFNK_LINEAR_ELASTIC>(m, rec, sc, Ru, out, s);
     else
-      hipLaunchKernelGGL((k_flux<3, kLawMixed>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<3, kLawMixed>(m, rec, sc, Ru, out, s);
   } else {
     if (mask == 2)
-      hipLaunchKernelGGL((k_flux<2, JFNK_NEO_HOOKEAN>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<2, JFNK_NEO_HOOKEAN>(m, rec, sc, Ru, out, s);
     else if (mask == 1)
-      hipLaunchKernelGGL((k_flux<2, JFNK_LINEAR_ELASTIC>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<2, JFNK_LINEAR_ELASTIC>(m, rec, sc, Ru, out, s);
     else
-      hipLaunchKernelGGL((k_flux<2, kLawMixed>), g, b, 0, s, m, rec, sc, Ru, out, nr);
+      flux_launch<2, kLawMixed>(m, rec, sc, Ru, out, s);
   }
   JFNK_HIP(hipGetLastError());
 }

@@ -50,6 +50,10 @@ constexpr int kNumXcd = 8;
 // that every workgroup belongs to exactly one segment.
 constexpr int kFvBlock = 256;
 constexpr int kSegAlign = kFvBlock;
+// LDS budget of one workgroup of the tiled (LDS-staged) cell passes: the
+// tile's kFvBlock cells plus its halo, (2 dim + dim^2) doubles per cell
+constexpr int kTileLdsBytes = 64 * 1024;
+inline int64_t tile_halo_limit(int dim) { return kTileLdsBytes / (8 * (2 * dim + dim * dim)) - kFvBlock; }
 // slot_nb values
 constexpr int kSlotBoundary = -1;
 constexpr int kSlotPad = -2;
@@ -92,6 +96,14 @@ struct MeshDev {
   const double* bface;       // [n_boundary][10] {Gamma, d_b, value, type}
   const int32_t* seg_of_block;  // [ceil(n_cells / kFvBlock)]
   const SegInfo* seg;        // [n_seg]
+  // tiles (tiled != 0): slot_loc gives the neighbour's position in the
+  // workgroup's LDS copy (0..kFvBlock-1: inside the tile, kFvBlock + h:
+  // entry h of the tile's halo list) or the slot_nb code of other slots
+  int32_t tiled;
+  int32_t halo_stride;       // kFvBlock + largest halo: LDS row length
+  const int32_t* slot_loc;   // [n_slots]
+  const int32_t* halo_ptr;   // [n_tiles + 1]
+  const int32_t* halo_cells; // [halo_ptr[n_tiles]] cell numbers
 };
 
 // Per-call, per-segment device scalars.
@@ -116,6 +128,8 @@ struct HostMesh {
   std::vector<double> pc_diag;      // approximate Jacobian, scalar diagonal (alpha_pc)
   std::vector<double> pc_off;       // per internal face off-diagonal coefficient
   int64_t bandwidth = 0;
+  bool tiled = false;               // cell order is in compact tiles whose halos fit the LDS budget
+  int64_t tile_halo_max = 0;
 };
 
 struct Material {
@@ -130,6 +144,8 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
 // Host arrays of a batch union, ready for upload.
 struct UnionArrays {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
+  std::vector<int32_t> slot_loc, halo_ptr, halo_cells;
+  int64_t halo_max = 0;
   std::vector<double> xc, face, magG, bface, pc_dinv;
   std::vector<SegInfo> seg;
 };
@@ -219,7 +235,7 @@ struct jfnk_mesh {
   std::vector<int32_t> block_first; // [n_seg + 1] first workgroup (kFvBlock cells) of each segment
   jfnk::MeshDev dev{};
   jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
-      b_seg_of_block, b_seg, b_block_first;
+      b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
   bool pinned_owned = true;

@@ -125,6 +125,106 @@ std::vector<int32_t> rcm(int64_t nc, const std::vector<int64_t>& aptr,
   return order;
 }
 
+// Tile order (old index of each new position): recursive coordinate
+// bisection of the cell centroids into tiles of kFvBlock cells, so that the
+// cells one workgroup handles form a compact block and most of their face
+// neighbours lie in the same tile.  Each axis is measured in typical cell
+// lengths along it (median |d_a| over the internal faces whose unit normal
+// has |n_a| >= 0.9), so that stretched cells still give blocks that are
+// compact in cell counts.  Inside a tile the input order is kept.
+std::vector<int32_t> tile_order(int dim, const std::vector<V3>& xc, const std::vector<V3>& Gam,
+                                const int32_t* owner, const int32_t* nbr, int64_t ni) {
+  const int64_t nc = int64_t(xc.size());
+  double scale[3] = {1.0, 1.0, 1.0};
+  {
+    std::vector<double> len[3];
+    for (int64_t f = 0; f < ni; ++f) {
+      const V3 g = Gam[f];
+      const double mg = std::sqrt(dot(g, g));
+      const V3 dd = xc[nbr[f]] - xc[owner[f]];
+      const double n[3] = {g.x / mg, g.y / mg, g.z / mg}, dv[3] = {dd.x, dd.y, dd.z};
+      for (int a = 0; a < dim; ++a)
+        if (std::fabs(n[a]) >= 0.9) len[a].push_back(std::fabs(dv[a]));
+    }
+    double found = 0;
+    int nfound = 0;
+    for (int a = 0; a < dim; ++a) {
+      if (len[a].empty()) {
+        scale[a] = 0;
+        continue;
+      }
+      auto mid = len[a].begin() + len[a].size() / 2;
+      std::nth_element(len[a].begin(), mid, len[a].end());
+      scale[a] = *mid > 0 ? *mid : 0;
+      if (scale[a] > 0) {
+        found += std::log(scale[a]);
+        ++nfound;
+      }
+    }
+    const double fallback = nfound ? std::exp(found / nfound) : 1.0;
+    for (int a = 0; a < dim; ++a)
+      if (!(scale[a] > 0)) scale[a] = fallback;
+  }
+  auto coord = [&](int32_t c, int a) {
+    const V3& x = xc[c];
+    return (a == 0 ? x.x : a == 1 ? x.y : x.z) / scale[a];
+  };
+  std::vector<int32_t> idx(nc);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::vector<std::pair<int64_t, int64_t>> stack{{0, nc}};
+  while (!stack.empty()) {
+    const auto [lo, hi] = stack.back();
+    stack.pop_back();
+    const int64_t n = hi - lo;
+    if (n <= kFvBlock) {
+      std::sort(idx.begin() + lo, idx.begin() + hi);
+      continue;
+    }
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = lo; i < hi; ++i)
+      for (int a = 0; a < dim; ++a) {
+        const double v = coord(idx[i], a);
+        mn[a] = std::min(mn[a], v);
+        mx[a] = std::max(mx[a], v);
+      }
+    int axis = 0;
+    for (int a = 1; a < dim; ++a)
+      if (mx[a] - mn[a] > mx[axis] - mn[axis]) axis = a;
+    const int64_t tiles = (n + kFvBlock - 1) / kFvBlock;
+    const int64_t left = (tiles / 2) * kFvBlock;
+    std::nth_element(idx.begin() + lo, idx.begin() + lo + left, idx.begin() + hi,
+                     [&](int32_t a, int32_t b) {
+                       const double ca = coord(a, axis), cb = coord(b, axis);
+                       return ca < cb || (ca == cb && a < b);
+                     });
+    stack.push_back({lo + left, hi});
+    stack.push_back({lo, lo + left});
+  }
+  return idx;
+}
+
+// Largest number of distinct cells outside a tile of kFvBlock cells that
+// share an internal face with a cell of the tile (cell numbers: new_of_old).
+int64_t max_tile_halo(const std::vector<int32_t>& new_of_old, const int32_t* owner, const int32_t* nbr,
+                      int64_t ni) {
+  std::vector<int64_t> key;
+  key.reserve(size_t(2 * ni));
+  for (int64_t f = 0; f < ni; ++f) {
+    const int64_t a = new_of_old[owner[f]], b = new_of_old[nbr[f]];
+    if (a / kFvBlock == b / kFvBlock) continue;
+    key.push_back((a / kFvBlock) << 32 | b);
+    key.push_back((b / kFvBlock) << 32 | a);
+  }
+  std::sort(key.begin(), key.end());
+  key.erase(std::unique(key.begin(), key.end()), key.end());
+  int64_t best = 0, run = 0;
+  for (size_t i = 0; i < key.size(); ++i) {
+    run = (i > 0 && (key[i] >> 32) == (key[i - 1] >> 32)) ? run + 1 : 1;
+    best = std::max(best, run);
+  }
+  return best;
+}
+
 }  // namespace
 
 void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm) {
@@ -276,16 +376,31 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   };
   std::vector<int32_t> ident(nc);
   std::iota(ident.begin(), ident.end(), 0);
-  int64_t bw_in = bandwidth_of(ident);
-  std::vector<int32_t> order = rcm(nc, aptr, adj);
-  std::vector<int32_t> nofo(nc);
-  for (int64_t i = 0; i < nc; ++i) nofo[order[i]] = int32_t(i);
-  int64_t bw_rcm = bandwidth_of(nofo);
-  if (bw_rcm >= bw_in) {
-    order = ident;
-    nofo = ident;
+  std::vector<int32_t> order, nofo(nc);
+  // Preferred order: compact tiles whose neighbour halos fit the LDS budget
+  // of the tiled kernels; otherwise RCM when it narrows the bandwidth.
+#ifndef JFNK_ORDER_MODE
+#define JFNK_ORDER_MODE 0   // 0: tiles if their halos fit, else RCM/input; 1: input; 2: RCM; 3: tiles
+#endif
+  hm.tiled = false;
+  if (JFNK_ORDER_MODE == 0 || JFNK_ORDER_MODE == 3) {
+    order = tile_order(dim, xc0, Gam, d.owner, d.neighbour, ni);
+    for (int64_t i = 0; i < nc; ++i) nofo[order[i]] = int32_t(i);
+    const int64_t hmax = max_tile_halo(nofo, d.owner, d.neighbour, ni);
+    hm.tiled = hmax <= tile_halo_limit(dim);
+    hm.tile_halo_max = hm.tiled ? hmax : 0;
+    if (!hm.tiled && JFNK_ORDER_MODE == 0) order.clear();
   }
-  hm.bandwidth = std::min(bw_in, bw_rcm);
+  if (order.empty()) {
+    const int64_t bw_in = bandwidth_of(ident);
+    order = (JFNK_ORDER_MODE == 1) ? ident : rcm(nc, aptr, adj);
+    for (int64_t i = 0; i < nc; ++i) nofo[order[i]] = int32_t(i);
+    if (JFNK_ORDER_MODE == 0 && bandwidth_of(nofo) >= bw_in) {
+      order = ident;
+      nofo = ident;
+    }
+  }
+  hm.bandwidth = bandwidth_of(nofo);
   hm.old_of_new = order;
   hm.new_of_old = nofo;
   hm.dim = dim;
@@ -597,6 +712,45 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     for (int64_t b = b0; b < b1; ++b) ua.seg_of_block[b] = s;
   }
   m.block_first[S] = int32_t(n_blocks);
+  // Tiles for the LDS-staged kernels (tiles never cross segments, since
+  // segments start on multiples of kFvBlock).
+  U.tiled = true;
+  for (const Segment& g : m.segs) U.tiled = U.tiled && g.host.tiled;
+  ua.halo_max = 0;
+  ua.halo_ptr.assign(n_blocks + 1, 0);
+  ua.halo_cells.clear();
+  ua.slot_loc.clear();
+  if (U.tiled) {
+    ua.slot_loc.assign(ua.slot_nb.size(), kSlotPad);
+    std::vector<int32_t> halo;
+    for (int64_t t = 0; t < n_blocks; ++t) {
+      const int64_t c0 = t * kFvBlock, c1 = std::min<int64_t>(N, c0 + kFvBlock);
+      const int64_t sl0 = c0 / kSlice, sl1 = (c1 - 1) / kSlice;
+      halo.clear();
+      for (int64_t sl = sl0; sl <= sl1; ++sl)
+        for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
+          const int32_t nb = ua.slot_nb[q];
+          if (nb >= 0 && nb / kFvBlock != t) halo.push_back(nb);
+        }
+      std::sort(halo.begin(), halo.end());
+      halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+      for (int64_t sl = sl0; sl <= sl1; ++sl)
+        for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
+          const int32_t nb = ua.slot_nb[q];
+          if (nb < 0)
+            ua.slot_loc[q] = nb;
+          else if (nb / kFvBlock == t)
+            ua.slot_loc[q] = int32_t(nb - c0);
+          else
+            ua.slot_loc[q] =
+                kFvBlock + int32_t(std::lower_bound(halo.begin(), halo.end(), nb) - halo.begin());
+        }
+      ua.halo_cells.insert(ua.halo_cells.end(), halo.begin(), halo.end());
+      ua.halo_ptr[t + 1] = int32_t(ua.halo_cells.size());
+      ua.halo_max = std::max<int64_t>(ua.halo_max, int64_t(halo.size()));
+    }
+    JFNK_REQUIRE(ua.halo_max <= tile_halo_limit(dim), JFNK_E_MESH, "mesh: tile halo exceeds the LDS budget");
+  }
   ua.pc_dinv.resize(N);
   for (int64_t c = 0; c < N; ++c) ua.pc_dinv[c] = 1.0 / U.pc_diag[c];
 }

@@ -59,11 +59,19 @@ def test_inspect_geometry_matches_oracle(jfnk, kind):
     assert np.abs(vol - g["V"]).max() <= 1e-12 * g["V"].max()
 
 
-def test_renumbering_reduces_bandwidth(jfnk):
-    m = mg.box_mesh_3d(60, 8, 5)      # natural order has bandwidth 60*8
+def test_cells_ordered_in_compact_tiles(jfnk):
+    """Cells are renumbered into tiles of 256 that are compact blocks: on a
+    60x8x5 box a tile's outside neighbours number about its surface (a
+    brick of ~8x8x4 cells has 256), far below the 2x256 neighbours of a
+    slab of the natural order, and within the LDS budget of the kernels."""
+    m = mg.box_mesh_3d(60, 8, 5)
     info = jfnk.inspect_mesh(m, mg.Material())
-    assert info["bandwidth"] <= 60 * 8
-    assert info["bandwidth"] < 100
+    assert info["tiled"] == 1
+    assert 0 < info["tile_halo_max"] <= 300
+    # stretched cells: tiles stay compact in cell counts, not in metres
+    m = mg.box_mesh_3d(200, 20, 6, 10.0, 1.0, 1.0)
+    info = jfnk.inspect_mesh(m, mg.Material())
+    assert info["tiled"] == 1 and info["tile_halo_max"] <= 300
 
 
 def test_invalid_mesh_reported(jfnk):
