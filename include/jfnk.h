@@ -191,7 +191,12 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2 } jfnk_pr
  * |b - J x| <= max(rtol |b|, atol), after max_it Arnoldi steps, or on
  * stagnation.  precond: J_tilde (alpha_pc) as diagonal (Jacobi, FP64) or
  * as an FP32 aggregation-AMG V-cycle with Chebyshev smoothing (flexible
- * GMRES).  eps <= 0 selects the automatic J v step. */
+ * GMRES).  eps <= 0 selects the automatic J v step.
+ * The Givens rotations and the small least-squares problem are updated on
+ * the device, so Arnoldi steps are enqueued in runs of step_chunk steps
+ * between host checks of the convergence flags (0: the handle's value,
+ * chosen by jfnk_autotune, default 1); graphs = 1 replays each run from a
+ * HIP graph captured on first use (results are identical either way). */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -200,6 +205,8 @@ typedef struct {
   int32_t precond;
   int32_t cheb_degree;
   double eps;
+  int32_t step_chunk;
+  int32_t graphs;
 } jfnk_gmres_opts;
 
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
@@ -223,8 +230,10 @@ typedef struct {
   double res0;                 /* |R| at the start of the last increment (Newton) or |b| (GMRES) */
   double res_final;            /* final |R| (Newton) or true |b - J x| (GMRES) */
   double eps_last;             /* last J v step used */
-  double t_ms[8];              /* phase times: 0 total, 1 J.v, 2 orthogonalisation, 3 preconditioner,
-                                  4 residual, 5 setup, 6 host control, 7 reserved */
+  double t_ms[8];              /* host wall times: 0 total, 2 Arnoldi steps (J.v, preconditioner and
+                                  orthogonalisation, enqueued asynchronously), 4 Newton residuals,
+                                  5 preconditioner setup, 6 true residuals and cycle ends; 1, 3, 7
+                                  unused (per-kernel times: jfnk_profile_read) */
 } jfnk_stats;
 
 /* Solve J(u) x = b with J v from Eq. (JF) at state d_u (load factor `load`,
@@ -306,6 +315,7 @@ typedef struct {
   int64_t footprint_bytes;
   int64_t n_cells;
   jfnk_stats stats;
+  char error[160];             /* message of a failed request (empty otherwise) */
 } jfnk_request_info;
 
 typedef struct {

@@ -401,13 +401,13 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
 
 namespace {
 
-void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s) {
+void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s, const int32_t* gate) {
   const AmgLevel& L = H.levels[l];
   const int dim = H.dim;
   float* x = w + L.off_x;
   float* b = w + L.off_b;
   if (l + 1 == H.levels.size()) {
-    amg_dense(H.coarse_inv.as<float>(), b, x, int(H.n_coarse), dim, s);
+    amg_dense(H.coarse_inv.as<float>(), b, x, int(H.n_coarse), dim, s, gate);
     return;
   }
   float* r = w + L.off_r;
@@ -416,39 +416,40 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s
   const float* dinv = L.dinv.as<float>();
   ChebCoef cc = cheb_coefficients(L.lmax, degree);
   // pre-smoothing from x = 0
-  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s);
+  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate);
   for (int k = 0; k + 1 < degree; ++k) {
-    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s);
+    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate);
     std::swap(d0, d1);
   }
   // coarse-grid correction
-  amg_residual(L.A, b, x, r, dim, s);
+  amg_residual(L.A, b, x, r, dim, s, gate);
   const AmgLevel& C = H.levels[l + 1];
-  amg_spmv(L.R, r, w + C.off_b, false, dim, s);
-  vcycle(H, l + 1, degree, w, s);
-  amg_spmv(L.P, w + C.off_x, x, true, dim, s);
+  amg_spmv(L.R, r, w + C.off_b, false, dim, s, gate);
+  vcycle(H, l + 1, degree, w, s, gate);
+  amg_spmv(L.P, w + C.off_x, x, true, dim, s, gate);
   // post-smoothing
   d0 = w + L.off_d0;
   d1 = w + L.off_d1;
-  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s);
+  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate);
   for (int k = 0; k + 1 < degree; ++k) {
-    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s);
+    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate);
     std::swap(d0, d1);
   }
 }
 
 }  // namespace
 
-void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s) {
+void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s,
+               const int32_t* gate) {
   JFNK_REQUIRE(m->amg != nullptr, JFNK_E_ARG, "amg: not set up");
   JFNK_REQUIRE(work != nullptr, JFNK_E_ARG, "amg: no workspace");
   const AmgHierarchy& H = *m->amg;
   const AmgLevel& L0 = H.levels[0];
   Profiler& p = m->prof;
   const int t = p.on ? p.begin(3, s) : -1;
-  amg_cast_in(r, work + L0.off_b, L0.n, H.dim, s);
-  vcycle(H, 0, cheb_degree, work, s);
-  amg_cast_out(work + L0.off_x, z, L0.n, H.dim, s);
+  amg_cast_in(r, work + L0.off_b, L0.n, H.dim, s, gate);
+  vcycle(H, 0, cheb_degree, work, s, gate);
+  amg_cast_out(work + L0.off_x, z, L0.n, H.dim, s, gate);
   if (t >= 0) p.end(t, s);
 }
 

@@ -41,22 +41,24 @@ struct AmgHierarchy {
 };
 
 // ---- kernels (amg_kernels.hip); vectors are component-major FP32 [dim][n] ----
-void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s);
-void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s);
+void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate);
+void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate);
 // Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d
 void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s);
+                     float inv_theta, int dim, hipStream_t s, const int32_t* gate);
 // Chebyshev start from a given x: r = D^-1 (b - A x), d = r/theta, x += d
 void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s);
+                    float inv_theta, int dim, hipStream_t s, const int32_t* gate);
 // one Chebyshev step: r -= D^-1 A d_in; d_out = c1 d_in + c2 r; x += d_out
 void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s);
+                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate);
 // r = b - A x
-void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s);
+void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
+                  const int32_t* gate);
 // y = M x (restriction) or y += M x (prolongation, accumulate = true)
-void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s);
+void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s,
+              const int32_t* gate);
 // x = inv * b (dense, n x n)
-void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s);
+void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s, const int32_t* gate);
 
 }  // namespace jfnk

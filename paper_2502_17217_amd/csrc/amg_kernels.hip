@@ -27,13 +27,17 @@ __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const i
 }
 
 __global__ __launch_bounds__(kB) void k_cast_in(const double* __restrict__ r, float* __restrict__ b,
-                                                int64_t total) {
+                                                int64_t total,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
   if (i < total) b[i] = float(r[i]);
 }
 
 __global__ __launch_bounds__(kB) void k_cast_out(const float* __restrict__ x, double* __restrict__ z,
-                                                 int64_t total) {
+                                                 int64_t total,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
   if (i < total) z[i] = -double(x[i]);   // J_tilde = -A
 }
@@ -42,7 +46,9 @@ template <int D>
 __global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restrict__ dinv,
                                                     const float* __restrict__ b, float* __restrict__ x,
                                                     float* __restrict__ r, float* __restrict__ d,
-                                                    float inv_theta) {
+                                                    float inv_theta,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   const float di = dinv[i];
@@ -64,7 +70,9 @@ __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restr
                                                    const float* __restrict__ dinv,
                                                    const float* __restrict__ b, const float* __restrict__ x,
                                                    float* __restrict__ r, float* __restrict__ d,
-                                                   float inv_theta) {
+                                                   float inv_theta,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   float s[D];
@@ -80,7 +88,9 @@ __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restr
 }
 
 template <int D>
-__global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restrict__ d, float* __restrict__ x) {
+__global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restrict__ d, float* __restrict__ x,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
@@ -94,7 +104,9 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
                                                   const float* __restrict__ dinv,
                                                   const float* __restrict__ d_in, float* __restrict__ d_out,
                                                   float* __restrict__ r, float* __restrict__ x, float c1,
-                                                  float c2) {
+                                                  float c2,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   float s[D];
@@ -115,7 +127,9 @@ template <int D>
 __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ val, const float* __restrict__ b,
-                                                 const float* __restrict__ x, float* __restrict__ r) {
+                                                 const float* __restrict__ x, float* __restrict__ r,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   float s[D];
@@ -127,7 +141,9 @@ __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restric
 template <int D>
 __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __restrict__ ptr,
                                              const int32_t* __restrict__ col, const float* __restrict__ val,
-                                             const float* __restrict__ x, float* __restrict__ y, int accumulate) {
+                                             const float* __restrict__ x, float* __restrict__ y, int accumulate,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   float s[D];
@@ -145,7 +161,9 @@ __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __rest
 // column and their partial sums meet in LDS.
 template <int D>
 __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, const float* __restrict__ b,
-                                              float* __restrict__ x, int n) {
+                                              float* __restrict__ x, int n,
+    const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   constexpr int kWaves = kB / 64;
   __shared__ float part[kWaves][D][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -185,51 +203,53 @@ __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, con
     JFNK_HIP(hipGetLastError());                                                   \
   } while (0)
 
-void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s) {
+void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
   const int64_t t = n * dim;
-  hipLaunchKernelGGL(k_cast_in, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t);
+  hipLaunchKernelGGL(k_cast_in, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t, gate);
   JFNK_HIP(hipGetLastError());
 }
 
-void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s) {
+void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
   const int64_t t = n * dim;
-  hipLaunchKernelGGL(k_cast_out, dim3(blocks_for(t)), dim3(kB), 0, s, x, z, t);
+  hipLaunchKernelGGL(k_cast_out, dim3(blocks_for(t)), dim3(kB), 0, s, x, z, t, gate);
   JFNK_HIP(hipGetLastError());
 }
 
 void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s) {
+                     float inv_theta, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dinv, b, x, r, d,
-                    inv_theta);
+                    inv_theta, gate);
 }
 
 void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s) {
+                    float inv_theta, int dim, hipStream_t s, const int32_t* gate) {
   // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
   // by other rows' products in the first pass)
   JFNK_DIM_DISPATCH(dim, k_cheb_start, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), dinv, b, x, r, d, inv_theta);
-  JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x);
+                    A.col.as<int32_t>(), A.val.as<float>(), dinv, b, x, r, d, inv_theta, gate);
+  JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, gate);
 }
 
 void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s) {
+                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_cheb_step, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2);
+                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, gate);
 }
 
-void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s) {
+void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
+                  const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_residual, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), b, x, r);
+                    A.col.as<int32_t>(), A.val.as<float>(), b, x, r, gate);
 }
 
-void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s) {
+void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s,
+              const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_spmv, dim3(blocks_for(M.n)), dim3(kB), 0, s, M.n, M.m, M.ptr.as<int32_t>(),
-                    M.col.as<int32_t>(), M.val.as<float>(), x, y, accumulate ? 1 : 0);
+                    M.col.as<int32_t>(), M.val.as<float>(), x, y, accumulate ? 1 : 0, gate);
 }
 
-void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s) {
-  JFNK_DIM_DISPATCH(dim, k_dense, dim3((n + 63) / 64), dim3(kB), 0, s, inv, b, x, n);
+void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s, const int32_t* gate) {
+  JFNK_DIM_DISPATCH(dim, k_dense, dim3((n + 63) / 64), dim3(kB), 0, s, inv, b, x, n, gate);
 }
 
 }  // namespace jfnk

@@ -29,9 +29,11 @@ struct SegLayout {
 // partials: n_blocks * kMaxBasis doubles.  Segments with active[s] == 0 are skipped.
 void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* w, double* partials,
                double* out, int ldo, bool accumulate, const int32_t* active, hipStream_t s);
-// w += sign * sum_{k<nk} h[s * ldh + k] V_k on each segment s
+// w += sign * sum_{k<nk} h[s * ldh + k] V_k on each segment s (k < min(nk, nk_seg[s]) when
+// nk_seg is given)
 void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
-                  double sign, double* w, const int32_t* active, hipStream_t s);
+                  double sign, double* w, const int32_t* active, hipStream_t s,
+                  const int32_t* nk_seg = nullptr);
 // y = scale[s] * x on each segment s
 void blas_scale_seg(const SegLayout& L, const double* x, const double* scale, double* y,
                     const int32_t* active, hipStream_t s);
@@ -40,8 +42,23 @@ void blas_axpby(double a, const double* x, double b, double* y, int64_t n, hipSt
 // y = a x + b z (all entries)
 void blas_lincomb(double a, const double* x, double b, const double* z, double* y, int64_t n,
                   hipStream_t s);
+// ---- fused reductions (cgs_kernels.hip) ----
+void fill_int(int32_t* d, int n, int32_t v, hipStream_t s);
+// true if some segment has more tiles than the in-kernel finish handles
+bool any_large_segment(const SegLayout& L, const int32_t* h_block_first);
+// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| per active segment
+void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
+                      double* partials, int32_t* tickets, double* eps, hipStream_t s);
+struct GmresDev;
+// Both classical Gram-Schmidt passes of Arnoldi step j against V_0..V_{nk-1}
+// and the device Givens update (h, h2: [n_seg][kMaxBasis], nrm: [n_seg][4]).
+void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv, int nk, double* w,
+               double* h, double* h2, double* nrm, double* partials, int32_t* tickets, int32_t* counters,
+               const GmresDev& G, int j, int max_it, hipStream_t s);
+
 // z = D^{-1} r with one scalar per cell applied to every component
+// (skipped entirely when gate is given and *gate == 0)
 void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim,
-                 hipStream_t s);
+                 hipStream_t s, const int32_t* gate = nullptr);
 
 }  // namespace jfnk

@@ -9,76 +9,11 @@
 
 #include "blas.h"
 #include "internal.h"
+#include "reduce_dev.h"
 
 namespace jfnk {
 
 namespace {
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
-// Sum over a 256-thread workgroup; valid in thread 0.
-__device__ __forceinline__ double block_sum(double x, double* sh) {
-  x = wave_sum(x);
-  const int w = threadIdx.x / 64;
-  if ((threadIdx.x & 63) == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0;
-  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-  __syncthreads();
-  return r;
-}
-
-// Two squared norms; each thread keeps four independent loads in flight per
-// vector (fixed element assignment, so the result is deterministic).
-// Per-tile partial sums of |a|^2 and |b|^2 (tile = kFvBlock cells, all
-// components).
-__global__ __launch_bounds__(kBlock) void k_norm2_pair(SegLayout L, const double* __restrict__ a,
-                                                       const double* __restrict__ b,
-                                                       const int32_t* __restrict__ active,
-                                                       double* __restrict__ partials) {
-  __shared__ double sh[4];
-  const int blk = blockIdx.x;
-  if (active != nullptr && active[L.seg_of_block[blk]] == 0) return;
-  const int c = blk * kFvBlock + threadIdx.x;
-  double sa = 0, sb = 0;
-  if (c < L.n_cells) {
-    for (int q = 0; q < L.dim; ++q) {
-      const double x = a[size_t(q) * L.n_cells + c], y = b[size_t(q) * L.n_cells + c];
-      sa = fma(x, x, sa);
-      sb = fma(y, y, sb);
-    }
-  }
-  sa = block_sum(sa, sh);
-  sb = block_sum(sb, sh);
-  if (threadIdx.x == 0) {
-    partials[2 * size_t(blk)] = sa;
-    partials[2 * size_t(blk) + 1] = sb;
-  }
-}
-
-// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| (a zero v_s gives eps 0 and J v = 0).
-__global__ __launch_bounds__(kBlock) void k_eps_final(SegLayout L, const double* __restrict__ partials,
-                                                      const int32_t* __restrict__ active,
-                                                      double* __restrict__ d_eps) {
-  __shared__ double sh[4];
-  const int seg = blockIdx.x;
-  if (active != nullptr && active[seg] == 0) return;
-  double sa = 0, sb = 0;
-  for (int b = L.block_first[seg] + threadIdx.x; b < L.block_first[seg + 1]; b += kBlock) {
-    sa += partials[2 * size_t(b)];
-    sb += partials[2 * size_t(b) + 1];
-  }
-  sa = block_sum(sa, sh);
-  sb = block_sum(sb, sh);
-  if (threadIdx.x == 0) {
-    const double sqrt_eps = 1.4901161193847656e-08;
-    d_eps[seg] = sb > 0 ? sqrt_eps * sqrt(1.0 + sqrt(sa)) / sqrt(sb) : 0.0;
-  }
-}
 
 __global__ void k_set_n(double* d, int n, const double* src) {
   const int i = threadIdx.x;
@@ -151,13 +86,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_seg(SegLayout L, const double
 
 // w += sign * sum_{k<nk} h[seg * ldh + k] V_k on the tile's segment
 __global__ __launch_bounds__(kBlock) void k_combine(SegLayout L, const double* __restrict__ V, int64_t ldv,
-                                                    int nk, const double* __restrict__ h, int ldh,
+                                                    int nk_all, const double* __restrict__ h, int ldh,
                                                     double sign, const int32_t* __restrict__ active,
+                                                    const int32_t* __restrict__ nk_seg,
                                                     double* __restrict__ w) {
   __shared__ double hs[kMaxBasis];
   const int blk = blockIdx.x;
   const int seg = L.seg_of_block[blk];
   if (active != nullptr && active[seg] == 0) return;
+  const int nk = nk_seg != nullptr ? min(nk_all, nk_seg[seg]) : nk_all;
   for (int k = threadIdx.x; k < nk; k += kBlock) hs[k] = h[size_t(seg) * ldh + k];
   __syncthreads();
   const int c = blk * kFvBlock + threadIdx.x;
@@ -206,7 +143,9 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(double a, const double* __re
 // applied to every component of the component-major vector)
 __global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ dinv,
                                                    const double* __restrict__ r,
-                                                   double* __restrict__ z, int64_t n_cells, int dim) {
+                                                   double* __restrict__ z, int64_t n_cells, int dim,
+                                                   const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n_cells; c += stride) {
     const double s = dinv[c];
@@ -220,20 +159,6 @@ inline int grid_stride_blocks(int64_t n) {
 }
 
 }  // namespace
-
-void launch_eps(const MeshDev& m, const int32_t* block_first, const double* u, const double* v,
-                double* partials, double* d_eps, const int32_t* active, hipStream_t s) {
-  SegLayout L;
-  L.n_cells = m.n_cells;
-  L.dim = m.dim;
-  L.n_seg = m.n_seg;
-  L.n_blocks = (m.n_cells + kFvBlock - 1) / kFvBlock;
-  L.seg_of_block = m.seg_of_block;
-  L.block_first = block_first;
-  hipLaunchKernelGGL(k_norm2_pair, dim3(L.n_blocks), dim3(kBlock), 0, s, L, u, v, active, partials);
-  hipLaunchKernelGGL(k_eps_final, dim3(L.n_seg), dim3(kBlock), 0, s, L, partials, active, d_eps);
-  JFNK_HIP(hipGetLastError());
-}
 
 void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s) {
   JFNK_HIP(hipMemcpyAsync(d, h_values, sizeof(double) * n, hipMemcpyHostToDevice, s));
@@ -260,8 +185,9 @@ void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const d
 }
 
 void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
-                  double sign, double* w, const int32_t* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign, active, w);
+                  double sign, double* w, const int32_t* active, hipStream_t s, const int32_t* nk_seg) {
+  hipLaunchKernelGGL(k_combine, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign, active,
+                     nk_seg, w);
   JFNK_HIP(hipGetLastError());
 }
 
@@ -283,9 +209,9 @@ void blas_lincomb(double a, const double* x, double b, const double* z, double* 
 }
 
 void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim,
-                 hipStream_t s) {
+                 hipStream_t s, const int32_t* gate) {
   hipLaunchKernelGGL(k_jacobi, dim3(grid_stride_blocks(n_cells)), dim3(kBlock), 0, s, dinv, r, z,
-                     n_cells, dim);
+                     n_cells, dim, gate);
   JFNK_HIP(hipGetLastError());
 }
 

@@ -75,6 +75,29 @@ void check_opts(const jfnk_gmres_opts& o) {
                "gmres: unknown preconditioner");
   JFNK_REQUIRE(o.precond != JFNK_PC_AMG32 || (o.cheb_degree >= 1 && o.cheb_degree <= 16), JFNK_E_ARG,
                "gmres: cheb_degree must lie in [1, 16]");
+  JFNK_REQUIRE(o.step_chunk >= 0 && o.step_chunk <= o.restart, JFNK_E_ARG,
+               "gmres: step_chunk must lie in [0, restart]");
+  JFNK_REQUIRE(o.graphs == 0 || o.graphs == 1, JFNK_E_ARG, "gmres: graphs must be 0 or 1");
+}
+
+// Stream the solvers run on: the caller's, or, when the caller passes the
+// null stream (which cannot be captured) and graphs are requested, the
+// handle's own stream ordered after the caller's work.
+hipStream_t solver_stream(jfnk_mesh* m, hipStream_t s, bool graphs) {
+  if (s != nullptr || !graphs) return s;
+  if (!m->solve_stream) JFNK_HIP(hipStreamCreateWithFlags(&m->solve_stream, hipStreamNonBlocking));
+  if (!m->ev[2]) JFNK_HIP(hipEventCreateWithFlags(&m->ev[2], hipEventDisableTiming));
+  JFNK_HIP(hipEventRecord(m->ev[2], s));
+  JFNK_HIP(hipStreamWaitEvent(m->solve_stream, m->ev[2], 0));
+  return m->solve_stream;
+}
+
+// The caller's stream waits for the solver's.
+void join_stream(jfnk_mesh* m, hipStream_t caller, hipStream_t used) {
+  if (used == caller) return;
+  if (!m->ev[3]) JFNK_HIP(hipEventCreateWithFlags(&m->ev[3], hipEventDisableTiming));
+  JFNK_HIP(hipEventRecord(m->ev[3], used));
+  JFNK_HIP(hipStreamWaitEvent(caller, m->ev[3], 0));
 }
 
 }  // namespace
@@ -137,8 +160,14 @@ AllocContext& alloc_context() {
   return ctx;
 }
 
+std::shared_mutex& capture_mutex() {
+  static std::shared_mutex mu;
+  return mu;
+}
+
 void DevBuf::release() noexcept {
   if (p) {
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
     if (stream)
       (void)hipFreeAsync(p, stream);
     else
@@ -151,6 +180,7 @@ void DevBuf::release() noexcept {
 void DevBuf::alloc(size_t b) {
   release();
   stream = alloc_context().stream;
+  std::shared_lock<std::shared_mutex> lk(capture_mutex());
   hipError_t e = stream ? hipMallocAsync(&p, b, stream) : hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
@@ -162,6 +192,16 @@ void DevBuf::alloc(size_t b) {
 }  // namespace jfnk
 
 using namespace jfnk;
+
+jfnk_mesh::~jfnk_mesh() {
+  if (amg) amg_destroy(amg);   // its buffers take the capture lock themselves
+  std::shared_lock<std::shared_mutex> lk(capture_mutex());
+  graphs.clear();
+  for (hipEvent_t& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (solve_stream) (void)hipStreamDestroy(solve_stream);
+  if (pinned && pinned_owned) (void)hipHostFree(pinned);
+}
 
 namespace jfnk {
 
@@ -201,6 +241,7 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     m.pinned = ac.pinned;
     m.pinned_owned = false;
   } else {
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
     JFNK_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.pinned), sizeof(double) * m.pinned_doubles,
                            hipHostMallocDefault));
   }
@@ -222,6 +263,11 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.bface = m.b_bface.as<double>();
   d.seg_of_block = m.b_seg_of_block.as<int32_t>();
   d.seg = m.b_seg.as<SegInfo>();
+  {
+    SegLayout L;
+    L.n_seg = S;
+    m.any_large = any_large_segment(L, m.block_first.data());
+  }
   d.tiled = h.tiled ? 1 : 0;
   d.halo_stride = int32_t(kFvBlock + ua.halo_max);
   d.slot_loc = h.tiled ? m.b_slot_loc.as<int32_t>() : nullptr;
@@ -329,8 +375,6 @@ jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* m
 jfnk_status jfnk_destroy_mesh(jfnk_mesh* mesh) {
   return guarded([&] {
     if (!mesh) return;
-    if (mesh->amg) amg_destroy(mesh->amg);
-    if (mesh->pinned && mesh->pinned_owned) (void)hipHostFree(mesh->pinned);
     delete mesh;
   });
 }
@@ -433,6 +477,7 @@ jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
+    fw.zero_counters(s);
     fill_device(fw.load, mesh->n_seg(), load, s);
     residual_into(mesh, d_u, d_R, fw, nullptr, s);
   });
@@ -453,6 +498,7 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
+    fw.zero_counters(s);
     fill_device(fw.load, mesh->n_seg(), load, s);
     const double* Ru = d_Ru;
     if (!Ru) {
@@ -482,10 +528,12 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     JFNK_REQUIRE(opts, JFNK_E_ARG, "gmres: null options");
     check_opts(*opts);
     JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "gmres: load factor not finite");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    const hipStream_t s = solver_stream(mesh, caller, opts->graphs != 0);
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
+    fw.zero_counters(s);
     KrylovWork kw;
     kw.carve(c, mesh, opts->restart, precond_work_floats(mesh, opts->precond));
     fill_device(fw.load, mesh->n_seg(), load, s);
@@ -493,6 +541,7 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     double t_ms[8] = {0};
     std::vector<GmresSeg> r;
     gmres_solve(mesh, d_u, d_Ru, d_b, d_x, false, *opts, fw, kw, s, {}, r, t_ms);
+    join_stream(mesh, caller, s);
     for (int k = 0; k < mesh->n_seg(); ++k) {
       if (stats) {
         jfnk_stats& o = stats[k];
@@ -531,10 +580,12 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
       inc[k] = n_increments ? n_increments[k] : opts->n_increments;
       JFNK_REQUIRE(inc[k] >= 1, JFNK_E_ARG, "newton: n_increments must be >= 1");
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    const hipStream_t s = solver_stream(mesh, caller, opts->gmres.graphs != 0);
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
+    fw.zero_counters(s);
     KrylovWork kw;
     kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
     const double ts = now_ms();
@@ -543,6 +594,7 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     std::vector<jfnk_stats> sv;
     std::vector<jfnk_status> stv;
     newton_solve(mesh, inc, *opts, d_u, fw, kw, s, sv, stv);
+    join_stream(mesh, caller, s);
     for (int k = 0; k < S; ++k) {
       sv[k].t_ms[5] = setup;
       if (stats) stats[k] = sv[k];

@@ -1,0 +1,287 @@
+// Fused kernels of one Arnoldi step's classical Gram-Schmidt (applied twice)
+// and of the J v step size (Section 3.2, Eq. JF), gfx950.
+//
+// One workgroup per tile of kFvBlock cells.  A pass computes its tile's
+// partial sums and, for segments of at most kFuseTiles tiles, the last tile
+// of the segment to finish adds the segment's partials (one tile per lane,
+// fixed butterfly) and writes the result, so a whole pass is one launch.  Larger segments leave
+// their partials to a separate reduction launch (k_reduce_large), spread
+// over one workgroup per (column, segment).  Which of the two a segment
+// takes depends only on its own size, so a mesh gets the same bits alone
+// and inside a batch.
+//
+//   pass 1: h = V^T w and |w|^2 (before orthogonalisation)
+//   pass 2: w -= V h, then h2 = V^T w
+//   pass 3: w -= V h2, then |w|^2, and (when every segment is small) the
+//           device Givens update of each segment in its last tile.
+#include "blas.h"
+#include "gmres_step_dev.h"
+#include "reduce_dev.h"
+
+namespace jfnk {
+
+namespace {
+
+__device__ __forceinline__ bool small_segment(const SegLayout& L, int seg, int& first, int& n) {
+  first = L.block_first[seg];
+  n = L.block_first[seg + 1] - first;
+  return n <= kFuseTiles;
+}
+
+// w -= sum_k coef[k] V_k on cell c of the tile (all components)
+__device__ __forceinline__ void combine_cell(const SegLayout& L, const double* __restrict__ V, int64_t ldv,
+                                             int nk, const double* __restrict__ coef, double* __restrict__ w,
+                                             int c) {
+  for (int q = 0; q < L.dim; ++q) {
+    const size_t o = size_t(q) * L.n_cells + c;
+    double s = 0;
+    for (int k = 0; k < nk; ++k) s = fma(coef[k], V[k * ldv + o], s);
+    w[o] -= s;
+  }
+}
+
+// Tile sums of V_k . w (k < nk): per-wavefront butterfly sums go to
+// wsum[wave][k] (store_tile_sums adds the four wavefronts in fixed order).
+__device__ __forceinline__ void tile_dots(const SegLayout& L, const double* __restrict__ V, int64_t ldv,
+                                          int nk, const double* __restrict__ w, int c,
+                                          double (*wsum)[kMaxBasis]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k0 = 0; k0 < nk; k0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    if (c < L.n_cells) {
+      for (int q = 0; q < L.dim; ++q) {
+        const size_t o = size_t(q) * L.n_cells + c;
+        const double wi = w[o];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k0 + k < nk) acc[k] = fma(V[(k0 + k) * ldv + o], wi, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k0 + k < nk) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) wsum[wave][k0 + k] = s;
+      }
+  }
+}
+
+// Segment sum of partial column col over tiles first .. first+n-1 (n <= 64),
+// one tile per lane and a fixed butterfly; valid in every lane of the wave.
+__device__ __forceinline__ double segment_column_sum(const double* __restrict__ partials, int first, int n,
+                                                     int col) {
+  const int lane = threadIdx.x & 63;
+  const double x = lane < n ? partials[size_t(first + lane) * kMaxBasis + col] : 0.0;
+  return wave_sum(x);
+}
+
+// |w|^2 over the tile's cells: per-wavefront sums into wsum[wave][col].
+__device__ __forceinline__ void tile_norm2(const SegLayout& L, const double* __restrict__ w, int c,
+                                           double (*wsum)[kMaxBasis], int col) {
+  double s = 0;
+  if (c < L.n_cells)
+    for (int q = 0; q < L.dim; ++q) {
+      const double x = w[size_t(q) * L.n_cells + c];
+      s = fma(x, x, s);
+    }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6][col] = s;
+}
+
+// partials[blk][k] = fixed-order sum of the four wavefront sums, k < ncol
+// (after a barrier).
+__device__ __forceinline__ void store_tile_sums(double (*wsum)[kMaxBasis], int ncol, double* __restrict__ partials,
+                                                int blk) {
+  __syncthreads();
+  for (int k = threadIdx.x; k < ncol; k += kBlock)
+    partials[size_t(blk) * kMaxBasis + k] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+}
+
+// Passes 1 and 2.  coef == nullptr: pass 1 (also |w|^2 into column nk,
+// finished into nrm[4 seg + 1]); otherwise pass 2 (w -= V coef first).
+__global__ __launch_bounds__(kBlock) void k_cgs_pass(SegLayout L, const double* __restrict__ V, int64_t ldv,
+                                                     int nk, double* __restrict__ w,
+                                                     const double* __restrict__ coef,
+                                                     const int32_t* __restrict__ act,
+                                                     double* __restrict__ partials, int32_t* __restrict__ tickets,
+                                                     double* __restrict__ out, double* __restrict__ nrm) {
+  __shared__ double wsum[4][kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (act != nullptr && act[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  if (coef != nullptr && c < L.n_cells) combine_cell(L, V, ldv, nk, coef + size_t(seg) * kMaxBasis, w, c);
+  tile_dots(L, V, ldv, nk, w, c, wsum);
+  const int ncol = coef == nullptr ? nk + 1 : nk;
+  if (coef == nullptr) tile_norm2(L, w, c, wsum, nk);
+  store_tile_sums(wsum, ncol, partials, blk);
+  int first, n;
+  if (!small_segment(L, seg, first, n)) return;
+  if (!last_tile_of_segment(tickets + seg, n)) return;
+  // each wavefront finishes every fourth column
+  const int wave = threadIdx.x >> 6;
+  for (int k = wave; k < ncol; k += 4) {
+    const double t = segment_column_sum(partials, first, n, k);
+    if ((threadIdx.x & 63) == 0) {
+      if (k < nk)
+        out[size_t(seg) * kMaxBasis + k] = t;
+      else
+        nrm[4 * seg + 1] = t;
+    }
+  }
+}
+
+// Pass 3: w -= V h2, |w|^2 into nrm[4 seg]; with finish != 0 (every segment
+// small) the last tile of each segment also takes the Givens step, and the
+// last segment to finish publishes the count of segments still active.
+__global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* __restrict__ V, int64_t ldv,
+                                                     int nk, double* __restrict__ w,
+                                                     const double* __restrict__ h1, const double* __restrict__ h2,
+                                                     const int32_t* __restrict__ act_in,
+                                                     double* __restrict__ partials, int32_t* __restrict__ tickets,
+                                                     int32_t* __restrict__ counters, double* __restrict__ nrm,
+                                                     GmresDev G, int j, int max_it, int finish) {
+  __shared__ double wsum[4][kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (act_in[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  if (c < L.n_cells) combine_cell(L, V, ldv, nk, h2 + size_t(seg) * kMaxBasis, w, c);
+  tile_norm2(L, w, c, wsum, 0);
+  store_tile_sums(wsum, 1, partials, blk);
+  int first, n;
+  if (!small_segment(L, seg, first, n)) return;
+  if (!last_tile_of_segment(tickets + seg, n)) return;
+  if (threadIdx.x >= 64) return;
+  const double t = segment_column_sum(partials, first, n, 0);
+  if (threadIdx.x != 0) return;
+  nrm[4 * seg] = t;
+  if (!finish) return;
+  // segments taking this step = the active count published by the previous step
+  const int taking = G.nact[0];
+  const int a = givens_update(G, seg, j, max_it, h1 + size_t(seg) * kMaxBasis, h2 + size_t(seg) * kMaxBasis,
+                              t, nrm[4 * seg + 1]);
+  atomicAdd(counters + 1, a);
+  __threadfence();
+  if (atomicAdd(counters, 1) == taking - 1) {
+    G.nact[0] = atomicAdd(counters + 1, 0);
+    counters[0] = 0;
+    counters[1] = 0;
+  }
+}
+
+// Segment sums of partial columns col0 .. col0+ncol-1 for segments larger
+// than kFuseTiles: out[seg * ldo + k].
+__global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const double* __restrict__ partials,
+                                                         int col0, const int32_t* __restrict__ act,
+                                                         double* __restrict__ out, int ldo) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x, seg = blockIdx.y;
+  if (act != nullptr && act[seg] == 0) return;
+  int first, n;
+  if (small_segment(L, seg, first, n)) return;
+  double s = 0;
+  for (int b = first + threadIdx.x; b < first + n; b += kBlock) s += partials[size_t(b) * kMaxBasis + col0 + k];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[size_t(seg) * ldo + k] = s;
+}
+
+// J v step size, fused: tile sums of |u|^2 and |v|^2 (columns 0 and 1 of the
+// tile's partial row) and, for small segments, eps in the last tile:
+// eps = sqrt(eps_mach) sqrt(1 + |u|) / |v| (0 when v = 0).
+__device__ __forceinline__ double eps_of(double uu, double vv) {
+  const double sqrt_eps = 1.4901161193847656e-08;
+  return vv > 0 ? sqrt_eps * sqrt(1.0 + sqrt(uu)) / sqrt(vv) : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double* __restrict__ u,
+                                                      const double* __restrict__ v,
+                                                      const int32_t* __restrict__ act,
+                                                      double* __restrict__ partials, int32_t* __restrict__ tickets,
+                                                      double* __restrict__ eps) {
+  __shared__ double wsum[4][kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (act != nullptr && act[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  tile_norm2(L, u, c, wsum, 0);
+  tile_norm2(L, v, c, wsum, 1);
+  store_tile_sums(wsum, 2, partials, blk);
+  int first, n;
+  if (!small_segment(L, seg, first, n)) return;
+  if (!last_tile_of_segment(tickets + seg, n)) return;
+  if (threadIdx.x >= 64) return;
+  const double tu = segment_column_sum(partials, first, n, 0);
+  const double tv = segment_column_sum(partials, first, n, 1);
+  if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
+}
+
+__global__ __launch_bounds__(kBlock) void k_eps_large(SegLayout L, const double* __restrict__ partials,
+                                                      const int32_t* __restrict__ act, double* __restrict__ eps) {
+  __shared__ double sh[4];
+  const int seg = blockIdx.x;
+  if (act != nullptr && act[seg] == 0) return;
+  int first, n;
+  if (small_segment(L, seg, first, n)) return;
+  double su = 0, sv = 0;
+  for (int b = first + threadIdx.x; b < first + n; b += kBlock) {
+    su += partials[size_t(b) * kMaxBasis];
+    sv += partials[size_t(b) * kMaxBasis + 1];
+  }
+  su = block_sum(su, sh);
+  sv = block_sum(sv, sh);
+  if (threadIdx.x == 0) eps[seg] = eps_of(su, sv);
+}
+
+__global__ void k_fill_int(int32_t* d, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = v;
+}
+
+}  // namespace
+
+bool any_large_segment(const SegLayout& L, const int32_t* h_block_first) {
+  for (int s = 0; s < L.n_seg; ++s)
+    if (h_block_first[s + 1] - h_block_first[s] > kFuseTiles) return true;
+  return false;
+}
+
+void fill_int(int32_t* d, int n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, d, n, v);
+  JFNK_HIP(hipGetLastError());
+}
+
+void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
+                      double* partials, int32_t* tickets, double* eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_eps_tiles, dim3(L.n_blocks), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
+  if (any_large) hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kBlock), 0, s, L, partials, act, eps);
+  JFNK_HIP(hipGetLastError());
+}
+
+void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv, int nk, double* w,
+               double* h, double* h2, double* nrm, double* partials, int32_t* tickets, int32_t* counters,
+               const GmresDev& G, int j, int max_it, hipStream_t s) {
+  const int32_t* act = G.act;
+  const dim3 g(L.n_blocks), b(kBlock);
+  // pass 1
+  hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, nullptr, act, partials, tickets, h, nrm);
+  if (any_large) {
+    hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), b, 0, s, L, partials, 0, act, h, kMaxBasis);
+    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), b, 0, s, L, partials, nk, act, nrm + 1, 4);
+  }
+  // pass 2
+  hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, h, act, partials, tickets, h2, nrm);
+  if (any_large) hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), b, 0, s, L, partials, 0, act, h2, kMaxBasis);
+  // pass 3 (+ Givens when every segment is small)
+  hipLaunchKernelGGL(k_cgs_last, g, b, 0, s, L, V, ldv, nk, w, h, h2, act, partials, tickets, counters, nrm, G, j,
+                     max_it, any_large ? 0 : 1);
+  if (any_large) {
+    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), b, 0, s, L, partials, 0, act, nrm, 4);
+    gmres_step_finish(G, L.n_seg, j, max_it, h, h2, nrm, s);
+  }
+  JFNK_HIP(hipGetLastError());
+}
+
+}  // namespace jfnk

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -163,6 +164,11 @@ struct AllocContext {
 };
 AllocContext& alloc_context();
 
+// HIP graph capture (exclusive) against allocation, free and other
+// device-wide calls made by other threads (shared): the runtime may reject
+// such calls while any stream of the process is being captured.
+std::shared_mutex& capture_mutex();
+
 // Device buffer with RAII.
 struct DevBuf {
   void* p = nullptr;
@@ -226,6 +232,26 @@ struct Segment {
 };
 }  // namespace jfnk
 
+namespace jfnk {
+// HIP graphs of runs of Arnoldi steps, captured once per set of launch
+// arguments (workspace, state vectors, options) and replayed every cycle.
+struct StepGraphs {
+  const void* work = nullptr;
+  const double* u = nullptr;
+  const double* Ru = nullptr;
+  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0;
+  double eps = 0;
+  std::vector<hipGraphExec_t> exec;  // one per chunk of steps (null until captured)
+  void clear();
+};
+
+// Launch choices made by the autotuner (jfnk_autotune) or the defaults.
+struct Tuning {
+  int step_chunk = 1;    // Arnoldi steps enqueued between host convergence checks
+  int tuned = 0;         // 1 once jfnk_autotune has run
+};
+}  // namespace jfnk
+
 // The opaque handle of the ABI: one mesh, or a batch of meshes solved
 // together (segments).
 struct jfnk_mesh {
@@ -242,7 +268,16 @@ struct jfnk_mesh {
   jfnk_mesh_info info{};
   jfnk::AmgHierarchy* amg = nullptr;
   jfnk::Profiler prof;
+  jfnk::StepGraphs graphs;
+  jfnk::Tuning tune;
+  hipStream_t solve_stream = nullptr;   // own stream for graph capture when the caller passes the null stream
+  bool any_large = true;                // a segment has more tiles than the fused reductions finish in-kernel
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int n_seg() const { return int(segs.size()); }
+  jfnk_mesh() = default;
+  jfnk_mesh(const jfnk_mesh&) = delete;
+  jfnk_mesh& operator=(const jfnk_mesh&) = delete;
+  ~jfnk_mesh();   // releases graphs, events, the own stream, AMG and owned pinned memory
 };
 
 namespace jfnk {
@@ -257,9 +292,6 @@ void launch_gradient(const MeshDev& m, const double* u, const double* v, const S
 // out = (R(w) - Ru)/eps if Ru != null else R(w) (per-segment eps and load).
 void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
                  hipStream_t s);
-// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|)/|v_s| per segment.
-void launch_eps(const MeshDev& m, const int32_t* block_first, const double* u, const double* v,
-                double* partials, double* d_eps, const int32_t* active, hipStream_t s);
 void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s);
 void build_union(jfnk_mesh& m, UnionArrays& ua);
 // Upload the union of m's segments on stream s (mesh handle setup).

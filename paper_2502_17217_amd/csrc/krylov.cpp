@@ -19,8 +19,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <shared_mutex>
 #include <vector>
 
+#include "gmres_dev.h"
 #include "solver.h"
 
 namespace jfnk {
@@ -32,9 +35,9 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-__global__ void k_fill(double* d, int n, double v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = v;
+__global__ void k_fill(double* d, int64_t n, double v) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = v;
 }
 
 // Per-segment squared norms of x (device scratch kw.nrm, column 0).
@@ -77,8 +80,9 @@ SegLayout layout_of(const jfnk_mesh* m) {
   return L;
 }
 
-void fill_device(double* d, int n, double value, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, d, n, value);
+void fill_device(double* d, int64_t n, double value, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill, dim3(unsigned(std::max<int64_t>(blocks, 1))), dim3(256), 0, s, d, n, value);
   JFNK_HIP(hipGetLastError());
 }
 
@@ -101,7 +105,7 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
   if (eps > 0)
     fill_device(fw.eps, m->n_seg(), eps, s);
   else
-    launch_eps(m->dev, m->b_block_first.as<int32_t>(), u, v, fw.partials, fw.eps, active, s);
+    launch_eps_fused(layout_of(m), m->any_large, u, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
   if (t >= 0) p.end(t, s);
   SegScalars sc{fw.eps, fw.load, active};
   t = p.on ? p.begin(1, s) : -1;
@@ -111,6 +115,40 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
   launch_flux(m->dev, fw.grad, sc, Ru, Jv, s);
   if (t >= 0) p.end(t, s);
 }
+
+void StepGraphs::clear() {
+  for (hipGraphExec_t& e : exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  exec.clear();
+  work = nullptr;
+}
+
+namespace {
+
+// Arnoldi steps j0 <= j < j1 for every active segment: z_j = P^{-1} v_j,
+// w = J z_j, two classical Gram-Schmidt passes, |w|, the device-side Givens
+// update, and v_{j+1} = w / h_{j+1,j}.  No host interaction: capturable.
+void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const double* Ru,
+                   const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, int j0, int j1, hipStream_t s) {
+  const int S = m->n_seg();
+  const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
+  for (int j = j0; j < j1; ++j) {
+    double* Vj = kw.V + size_t(j) * n;
+    double* Zj = kw.Z + size_t(j) * n;
+    precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
+    jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s);
+    cgs2_step(L, m->any_large, kw.V, n, j + 1, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, fw.cgs_tickets(),
+              fw.step_counters(), kw.gd, j, o.max_it, s);
+    if (j + 1 < o.restart) blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
+  }
+}
+
+hipEvent_t mesh_event(jfnk_mesh* m, int i) {
+  if (!m->ev[i]) JFNK_HIP(hipEventCreateWithFlags(&m->ev[i], hipEventDisableTiming));
+  return m->ev[i];
+}
+
+}  // namespace
 
 void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* b, double* x,
                  bool x_is_zero, const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, hipStream_t s,
@@ -139,7 +177,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   }
   // r = b - J x
   if (x_is_zero) {
-    JFNK_HIP(hipMemcpyAsync(kw.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    blas_lincomb(1.0, b, 0.0, b, kw.r, n, s);
   } else {
     jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s);
     for (int g = 0; g < S; ++g) out[g].jv += part[g];
@@ -151,14 +189,38 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
     prev[g] = beta[g];
     out[g].res_true = beta[g];
   }
-  const size_t ldH = size_t(mr + 1);
-  std::vector<double> H(size_t(S) * ldH * mr), cs(size_t(S) * mr), sn(size_t(S) * mr),
-      gv(size_t(S) * (mr + 1));
-  std::vector<double> yv(size_t(S) * kMaxBasis), fac(S);
-  std::vector<int> kk(S);
+  GmresDev& G = kw.gd;
+  gmres_zero_counters(G, S, s);
+  const int K = std::min(mr, o.step_chunk > 0 ? o.step_chunk : std::max(1, m->tune.step_chunk));
+  const int n_chunks = (mr + K - 1) / K;
+  // Graphs need a capturable stream and unchanged launch arguments.
+  const bool use_graphs = o.graphs != 0 && s != nullptr && !m->prof.on;
+  if (use_graphs) {
+    StepGraphs& sg = m->graphs;
+    const void* work = static_cast<const void*>(kw.V);
+    if (sg.work != work || sg.u != u || sg.Ru != Ru || sg.restart != mr || sg.precond != o.precond ||
+        sg.cheb != o.cheb_degree || sg.chunk != K || sg.eps != o.eps || sg.max_it != o.max_it) {
+      sg.clear();
+      sg.work = work;
+      sg.u = u;
+      sg.Ru = Ru;
+      sg.restart = mr;
+      sg.precond = o.precond;
+      sg.cheb = o.cheb_degree;
+      sg.chunk = K;
+      sg.eps = o.eps;
+      sg.max_it = o.max_it;
+      sg.exec.assign(n_chunks, nullptr);
+    }
+  }
+  // pinned host layout: [0, S) norms, then int32 its/kk/flag, then chunk flags
+  double* pin = m->pinned;
+  int32_t* pin_i = reinterpret_cast<int32_t*>(pin + S);
+  int32_t* pin_nact = pin_i + 3 * S + 8;
+  double* stage = m->pinned + m->pinned_doubles / 2;
+  std::vector<int> its(S, 0);
   std::vector<char> act(S);
   while (true) {
-    // which segments run a cycle
     bool any = false;
     for (int g = 0; g < S; ++g) {
       act[g] = 0;
@@ -169,7 +231,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       } else if (beta[g] <= target[g] || out[g].bnorm == 0.0) {
         out[g].status = JFNK_OK;
         done[g] = 1;
-      } else if (out[g].iterations >= o.max_it) {
+      } else if (its[g] >= o.max_it) {
         out[g].status = JFNK_E_NOT_CONVERGED;
         done[g] = 1;
       } else {
@@ -178,123 +240,81 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       }
     }
     if (!any) break;
-    std::vector<char> ran = act;
-    upload_flags(m, act, kw.act, s);
-    for (int g = 0; g < S; ++g) fac[g] = act[g] ? 1.0 / beta[g] : 0.0;
-    upload_doubles(m, fac, kw.fac, s);
+    // cycle start: flags, beta and targets in one upload (the staging area is
+    // rewritten only after the synchronisation at the end of the cycle)
+    for (int g = 0; g < S; ++g) {
+      stage[g] = act[g] ? 1.0 : 0.0;
+      stage[S + g] = beta[g];
+      stage[2 * S + g] = target[g];
+    }
+    JFNK_HIP(hipMemcpyAsync(kw.stage, stage, sizeof(double) * 3 * S, hipMemcpyHostToDevice, s));
+    gmres_cycle_init(G, S, kw.stage, s);
     blas_scale_seg(L, kw.r, kw.fac, kw.V, kw.act, s);
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    std::fill(kk.begin(), kk.end(), 0);
-    for (int g = 0; g < S; ++g) gv[size_t(g) * (mr + 1)] = beta[g];
-    for (int j = 0; j < mr; ++j) {
-      double* Vj = kw.V + size_t(j) * n;
-      double* Zj = kw.Z + size_t(j) * n;
-      const double tp = now_ms();
-      if (o.precond == JFNK_PC_NONE)
-        JFNK_HIP(hipMemcpyAsync(Zj, Vj, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-      else
-        precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
-      const double tj = now_ms();
-      jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s);
-      const double tc = now_ms();
-      // |w| before orthogonalisation (breakdown test), then CGS2
-      blas_mdot(L, kw.w, 0, 1, kw.w, fw.partials, kw.nrm + 1, 4, false, kw.act, s);
-      blas_mdot(L, kw.V, n, j + 1, kw.w, fw.partials, kw.h, kMaxBasis, false, kw.act, s);
-      blas_combine(L, kw.V, n, j + 1, kw.h, kMaxBasis, -1.0, kw.w, kw.act, s);
-      blas_mdot(L, kw.V, n, j + 1, kw.w, fw.partials, kw.h2, kMaxBasis, false, kw.act, s);
-      blas_combine(L, kw.V, n, j + 1, kw.h2, kMaxBasis, -1.0, kw.w, kw.act, s);
-      blas_mdot(L, kw.w, 0, 1, kw.w, fw.partials, kw.nrm, 4, false, kw.act, s);
-      // Hessenberg columns of all segments: [S][j+1] twice, norms [S][4]
-      double* ph = m->pinned;
-      double* ph2 = ph + size_t(S) * (j + 1);
-      double* pn = ph2 + size_t(S) * (j + 1);
-      JFNK_HIP(hipMemcpy2DAsync(ph, sizeof(double) * (j + 1), kw.h, sizeof(double) * kMaxBasis,
-                                sizeof(double) * (j + 1), S, hipMemcpyDeviceToHost, s));
-      JFNK_HIP(hipMemcpy2DAsync(ph2, sizeof(double) * (j + 1), kw.h2, sizeof(double) * kMaxBasis,
-                                sizeof(double) * (j + 1), S, hipMemcpyDeviceToHost, s));
-      JFNK_HIP(hipMemcpyAsync(pn, kw.nrm, sizeof(double) * 4 * S, hipMemcpyDeviceToHost, s));
-      JFNK_HIP(hipStreamSynchronize(s));
-      if (t_ms) {
-        t_ms[3] += tj - tp;
-        t_ms[1] += tc - tj;
-        t_ms[2] += now_ms() - tc;
+    const double ts = now_ms();
+    // runs of K steps; while run c executes, the host waits for run c-1's
+    // count of active segments and stops enqueueing when it is zero
+    for (int c = 0; c < n_chunks; ++c) {
+      const int j0 = c * K, j1 = std::min(mr, j0 + K);
+      if (use_graphs) {
+        hipGraphExec_t& ex = m->graphs.exec[c];
+        if (!ex) {
+          std::unique_lock<std::shared_mutex> lk(capture_mutex());
+          hipGraph_t gr = nullptr;
+          JFNK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          try {
+            enqueue_steps(m, L, u, Ru, o, fw, kw, j0, j1, s);
+          } catch (...) {
+            (void)hipStreamEndCapture(s, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            throw;
+          }
+          JFNK_HIP(hipStreamEndCapture(s, &gr));
+          const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          JFNK_HIP(e);
+        }
+        JFNK_HIP(hipGraphLaunch(ex, s));
+      } else {
+        enqueue_steps(m, L, u, Ru, o, fw, kw, j0, j1, s);
       }
-      bool still = false;
-      for (int g = 0; g < S; ++g) {
-        fac[g] = 0.0;
-        if (!act[g]) continue;
-        out[g].jv++;
-        const double hn = std::sqrt(pn[4 * g]);
-        const double w0 = std::sqrt(pn[4 * g + 1]);
-        double* Hj = &H[(size_t(g) * mr + j) * ldH];
-        double* c = &cs[size_t(g) * mr];
-        double* sg = &sn[size_t(g) * mr];
-        double* gg = &gv[size_t(g) * (mr + 1)];
-        for (int i = 0; i <= j; ++i) Hj[i] = ph[size_t(g) * (j + 1) + i] + ph2[size_t(g) * (j + 1) + i];
-        Hj[j + 1] = hn;
-        if (!std::isfinite(hn) || !std::isfinite(w0)) {
-          out[g].status = JFNK_E_NAN;
-          done[g] = 1;
-          act[g] = 0;
-          ran[g] = 0;
-          continue;
-        }
-        for (int i = 0; i < j; ++i) {
-          const double t = c[i] * Hj[i] + sg[i] * Hj[i + 1];
-          Hj[i + 1] = -sg[i] * Hj[i] + c[i] * Hj[i + 1];
-          Hj[i] = t;
-        }
-        const double rr = std::hypot(Hj[j], Hj[j + 1]);
-        c[j] = Hj[j] / rr;
-        sg[j] = Hj[j + 1] / rr;
-        Hj[j] = rr;
-        Hj[j + 1] = 0.0;
-        gg[j + 1] = -sg[j] * gg[j];
-        gg[j] = c[j] * gg[j];
-        out[g].iterations++;
-        kk[g] = j + 1;
-        const bool breakdown = hn <= 1e-14 * std::max(w0, 1e-300);
-        if (breakdown || std::fabs(gg[j + 1]) <= target[g] || out[g].iterations >= o.max_it) {
-          act[g] = 0;
-        } else {
-          fac[g] = 1.0 / hn;
-          still = true;
-        }
+      JFNK_HIP(hipMemcpyAsync(pin_nact + (c & 63), G.nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipEventRecord(mesh_event(m, c & 1), s));
+      if (c > 0) {
+        JFNK_HIP(hipEventSynchronize(mesh_event(m, (c - 1) & 1)));
+        if (pin_nact[(c - 1) & 63] == 0) break;
       }
-      if (!still || j + 1 == mr) break;
-      upload_flags(m, act, kw.act, s);
-      upload_doubles(m, fac, kw.fac, s);
-      blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
     }
-    // y = H^{-1} g per segment, x += Z y
-    int kmax = 0;
-    std::fill(yv.begin(), yv.end(), 0.0);
-    for (int g = 0; g < S; ++g) {
-      if (!ran[g]) continue;
-      const int k = kk[g];
-      kmax = std::max(kmax, k);
-      const double* gg = &gv[size_t(g) * (mr + 1)];
-      double* y = &yv[size_t(g) * kMaxBasis];
-      for (int i = k - 1; i >= 0; --i) {
-        double t = gg[i];
-        for (int l = i + 1; l < k; ++l) t -= H[(size_t(g) * mr + l) * ldH + i] * y[l];
-        y[i] = t / H[(size_t(g) * mr + i) * ldH + i];
-      }
-      out[g].restarts++;
-    }
-    if (kmax == 0) continue;
-    upload_flags(m, ran, kw.act, s);
-    upload_doubles(m, yv, kw.y, s);
-    blas_combine(L, kw.Z, n, kmax, kw.y, kMaxBasis, 1.0, x, kw.act, s);
-    // true residual
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s);
+    const double te = now_ms();
+    // x += Z y on the segments that ran, then the true residual
+    gmres_lsq(G, S, kw.y, s);
+    blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s);
     blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
-    seg_norms2(m, L, kw.r, fw, kw, kw.act, s, v2);
+    blas_mdot(L, kw.r, 0, 1, kw.r, fw.partials, kw.nrm, 4, false, G.ran, s);
+    JFNK_HIP(hipMemcpy2DAsync(pin, sizeof(double), kw.nrm, 4 * sizeof(double), sizeof(double), S,
+                              hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipMemcpyAsync(pin_i, G.its, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipMemcpyAsync(pin_i + S, G.kk, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipMemcpyAsync(pin_i + 2 * S, G.flag, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipStreamSynchronize(s));
+    if (t_ms) {
+      t_ms[2] += te - ts;
+      t_ms[6] += now_ms() - te;
+    }
     for (int g = 0; g < S; ++g) {
-      if (!ran[g]) continue;
+      if (!act[g]) continue;
+      const int steps = pin_i[g] - its[g];
+      its[g] = pin_i[g];
+      out[g].iterations = its[g];
+      out[g].jv += steps;
+      if (pin_i[2 * S + g]) {
+        out[g].status = JFNK_E_NAN;
+        done[g] = 1;
+        continue;
+      }
+      if (pin_i[S + g] > 0) out[g].restarts++;
       out[g].jv++;
-      beta[g] = std::sqrt(v2[g]);
+      beta[g] = std::sqrt(pin[g]);
       out[g].res_true = beta[g];
       if (beta[g] > 0.999 * prev[g] && beta[g] > target[g]) {
         if (++stalls[g] >= 3) {
@@ -384,7 +404,7 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
     }
     // J du = -R on the segments that need a step (du = 0 elsewhere)
     blas_lincomb(-1.0, kw.R, 0.0, kw.R, kw.b, n, s);
-    JFNK_HIP(hipMemsetAsync(kw.du, 0, sizeof(double) * n, s));
+    fill_device(kw.du, n, 0.0, s);
     gmres_solve(m, u, kw.R, kw.b, kw.du, true, go, fw, kw, s, part, gres, t_ms);
     for (int g = 0; g < S; ++g) {
       if (!part[g]) continue;

@@ -12,7 +12,8 @@ namespace jfnk {
 size_t amg_work_floats(const jfnk_mesh* m);
 size_t amg_work_floats(int64_t n, int dim);
 void amg_setup(jfnk_mesh* m, hipStream_t s);
-void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s);
+void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s,
+               const int32_t* gate);
 
 size_t precond_work_floats(const jfnk_mesh* m, int precond) {
   return precond == JFNK_PC_AMG32 ? amg_work_floats(m) : 0;
@@ -26,15 +27,19 @@ void precond_setup(jfnk_mesh* m, int precond, hipStream_t s) {
   if (precond == JFNK_PC_AMG32) amg_setup(m, s);
 }
 
+// The kernels return at once when gate (the count of segments still taking
+// Arnoldi steps) is zero, so that steps enqueued past convergence cost only
+// their launches.
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
                    KrylovWork& kw, hipStream_t s) {
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
+  const int32_t* gate = kw.gd.nact;
   if (precond == JFNK_PC_JACOBI) {
-    blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, s);
+    blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, s, gate);
   } else if (precond == JFNK_PC_AMG32) {
-    amg_apply(m, cheb_degree, r, z, kw.pc, s);
+    amg_apply(m, cheb_degree, r, z, kw.pc, s, gate);
   } else {
-    JFNK_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    blas_lincomb(1.0, r, 0.0, r, z, n, s);   // a kernel copy (capturable in a graph)
   }
 }
 

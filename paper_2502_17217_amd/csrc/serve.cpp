@@ -11,6 +11,7 @@
 // device arrays are allocated and freed stream-ordered on the worker's
 // stream, so no request waits for the work of another one.
 #include <algorithm>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -175,6 +176,7 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   Carver c(work.p);
   FvWork fw;
   fw.carve(c, m.get());
+  fw.zero_counters(stream);
   KrylovWork kw;
   kw.carve(c, m.get(), o.gmres.restart, pcf);
   precond_setup(m.get(), o.gmres.precond, stream);
@@ -206,6 +208,7 @@ void worker_loop(jfnk_server* S) {
   const bool gpu = S->opts.dry_run_us_per_kcell <= 0;
   if (gpu) {
     (void)hipSetDevice(S->device);
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
     (void)hipStreamCreate(&stream);  // default priority
     (void)hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(double) * pinned_doubles, hipHostMallocDefault);
   }
@@ -229,8 +232,13 @@ void worker_loop(jfnk_server* S) {
       run_request(S, r, ticket, stream, pinned, pinned_doubles);
     } catch (const Error& e) {
       r->info.status = e.status;
+      std::snprintf(r->info.error, sizeof(r->info.error), "%s", e.msg.c_str());
+    } catch (const std::exception& e) {
+      r->info.status = JFNK_E_ARG;
+      std::snprintf(r->info.error, sizeof(r->info.error), "%s", e.what());
     } catch (...) {
       r->info.status = JFNK_E_ARG;
+      std::snprintf(r->info.error, sizeof(r->info.error), "unknown failure");
     }
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -248,6 +256,7 @@ void worker_loop(jfnk_server* S) {
     }
     S->cv_done.notify_all();
   }
+  std::shared_lock<std::shared_mutex> lk(capture_mutex());
   if (stream) (void)hipStreamDestroy(stream);
   if (pinned) (void)hipHostFree(pinned);
 }

@@ -10,7 +10,7 @@
 namespace jfnk {
 
 SegLayout layout_of(const jfnk_mesh* m);
-void fill_device(double* d, int n, double value, hipStream_t s);
+void fill_device(double* d, int64_t n, double value, hipStream_t s);
 
 // R(u) into R with the per-segment load factors in fw.load (device).
 void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const int32_t* active,

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "blas.h"
+#include "gmres_dev.h"
 #include "internal.h"
 
 namespace jfnk {
@@ -35,13 +36,22 @@ struct FvWork {
   double* partials = nullptr;  // [n_tiles * kMaxBasis]
   double* eps = nullptr;       // [n_seg] J v step per segment
   double* load = nullptr;      // [n_seg] load factor per segment
-  void carve(Carver& c, int64_t n, int dim, int S) {
+  int32_t* tickets = nullptr;  // [2 n_seg + 8] arrival counters of the fused reductions (zero between launches)
+  int S = 0;
+  void carve(Carver& c, int64_t n, int dim, int S_) {
+    S = S_;
     grad = c.take<double>(size_t(n) * rec_doubles(dim));
     ru = c.take<double>(size_t(n) * dim);
     partials = c.take<double>(size_t(n_tiles(n)) * kMaxBasis);
     eps = c.take<double>(S);
     load = c.take<double>(S);
+    tickets = c.take<int32_t>(size_t(2) * S + 8);
   }
+  int32_t* eps_tickets() const { return tickets; }
+  int32_t* cgs_tickets() const { return tickets + S; }
+  int32_t* step_counters() const { return tickets + 2 * S; }
+  // The caller's workspace starts uninitialised: clear the counters once.
+  void zero_counters(hipStream_t s) const { fill_int(tickets, 2 * S + 8, 0, s); }
   void carve(Carver& c, const jfnk_mesh* m) { carve(c, m->host.n_cells, m->host.dim, m->n_seg()); }
 };
 
@@ -60,6 +70,8 @@ struct KrylovWork {
   double* y = nullptr;    // [n_seg][kMaxBasis] least-squares solution
   double* fac = nullptr;  // [n_seg] per-segment factors
   int32_t* act = nullptr; // [n_seg] active flags
+  double* stage = nullptr;  // [3 n_seg] per-cycle values uploaded by the host
+  GmresDev gd;            // device Arnoldi bookkeeping (shares fac and act)
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
   void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f) {
@@ -79,6 +91,20 @@ struct KrylovWork {
     y = c.take<double>(size_t(S) * kMaxBasis);
     fac = c.take<double>(S);
     act = c.take<int32_t>(S);
+    stage = c.take<double>(size_t(3) * S);
+    gd.mr = restart;
+    gd.H = c.take<double>(size_t(S) * restart * (restart + 1));
+    gd.cs = c.take<double>(size_t(S) * restart);
+    gd.sn = c.take<double>(size_t(S) * restart);
+    gd.g = c.take<double>(size_t(S) * (restart + 1));
+    gd.target = c.take<double>(S);
+    gd.fac = fac;
+    gd.act = act;
+    gd.ran = c.take<int32_t>(S);
+    gd.kk = c.take<int32_t>(S);
+    gd.its = c.take<int32_t>(S);
+    gd.flag = c.take<int32_t>(S);
+    gd.nact = c.take<int32_t>(4);
     pc_floats = pc_f;
     pc = pc_f ? c.take<float>(pc_f) : nullptr;
   }

@@ -53,7 +53,7 @@ class jfnk_mesh_info(C.Structure):
 class jfnk_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
-                ("eps", C.c_double)]
+                ("eps", C.c_double), ("step_chunk", C.c_int32), ("graphs", C.c_int32)]
 
 
 class jfnk_newton_opts(C.Structure):
@@ -330,10 +330,11 @@ def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
     return (Jv, e[0]) if mesh.n_segments == 1 else (Jv, list(e))
 
 
-def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0):
+def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
+               step_chunk=0, graphs=1):
     if isinstance(precond, str):
         precond = PRECOND[precond]
-    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps)
+    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs)
 
 
 def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, **gm):
@@ -396,11 +397,13 @@ class jfnk_server_opts(C.Structure):
 class jfnk_request_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("state", C.c_int32), ("t_submit_ms", C.c_double),
                 ("t_start_ms", C.c_double), ("t_done_ms", C.c_double), ("latency_ms", C.c_double),
-                ("footprint_bytes", C.c_int64), ("n_cells", C.c_int64), ("stats", jfnk_stats)]
+                ("footprint_bytes", C.c_int64), ("n_cells", C.c_int64), ("stats", jfnk_stats),
+                ("error", C.c_char * 160)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("stats", "error")}
         d["stats"] = self.stats.as_dict()
+        d["error"] = self.error.decode(errors="replace")
         return d
 
 

@@ -48,7 +48,9 @@ def test_served_equals_alone_and_oracle(lib, precond):
     mt = srv.metrics()
     srv.close()
     print(precond, mt)
-    assert mt["completed"] == len(reqs) and mt["hbm_peak"] <= int(3.2 * f0)
+    print([(i["status"], i["error"]) for i, _ in served])
+    assert mt["completed"] == len(reqs), [(i["status"], i["error"]) for i, _ in served]
+    assert mt["hbm_peak"] <= int(3.2 * f0)
     for k, ((m, mat, inc), (info, u)) in enumerate(zip(reqs, served)):
         assert info["status"] == lib.OK, info
         gm = lib.create_mesh(m, mat)

@@ -61,14 +61,14 @@ def test_admission_respects_budget_and_order(jfnk):
 def test_concurrency_when_memory_allows(jfnk):
     meshes = [_mesh(6) for _ in range(8)]
     opts = jfnk.newton_opts(restart=30, precond="jacobi")
-    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=4, dry_run_us_per_kcell=100000.0)   # ~21 ms each
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=4, dry_run_us_per_kcell=1000000.0)   # ~0.22 s each
     t0 = time.time()
     tickets = [srv.submit(m, mg.Material(), opts, keep_solution=False) for m in meshes]
     infos = [srv.wait(t)[0] for t in tickets]
     wall = time.time() - t0
     srv.close()
     # 8 requests on 4 slots: about two rounds, not eight
-    assert wall < 6 * 0.0216
+    assert wall < 6 * 0.216
     running_overlap = sum(1 for i in infos[1:] if i["t_start_ms"] < infos[0]["t_done_ms"])
     assert running_overlap >= 3
 
