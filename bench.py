@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-solve and serving measurements")
     ap.add_argument("--batch-problems", type=int, default=48,
@@ -313,6 +314,17 @@ def main():
     v_ext = mg.configs.random_unit_vector(gm.n_dof, 30)
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     ud, vd = gm.to_internal(dev(u_ext)), gm.to_internal(dev(v_ext))
+    tune = None
+    if not args.no_tune:
+        # the project's tuner picks the cell-pass launch shape (and Arnoldi
+        # schedule) on this mesh and state; untimed, reported
+        t = time.time()
+        tw = jfnk.make_workspace(gm, 1, restart=30, precond=jfnk.PC_AMG32)
+        tune = jfnk.autotune(gm, jfnk.gmres_opts(restart=30, max_it=200, rtol=1e-3, precond="amg32"), ud, tw)
+        del tw
+        log("autotune in %.1fs: lds %d persist %d step_chunk %d graphs %d; J.v candidates %s" %
+            (time.time() - t, tune["lds_kernels"], tune["persist"], tune["step_chunk"], tune["graphs"],
+             ", ".join("%d/%d %.1fus" % (c["lds"], c["persist"], c["ms"] * 1e3) for c in tune["jv"])))
     work = jfnk.make_workspace(gm, 0)
     Ru = torch.empty_like(ud)
     Jv = torch.empty_like(ud)
@@ -420,6 +432,7 @@ def main():
         "kernels": kern,
         "cpu_baseline": cpu,
         "parity": parity,
+        "autotune": tune,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

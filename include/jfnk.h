@@ -196,7 +196,8 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2 } jfnk_pr
  * the device, so Arnoldi steps are enqueued in runs of step_chunk steps
  * between host checks of the convergence flags (0: the handle's value,
  * chosen by jfnk_autotune, default 1); graphs = 1 replays each run from a
- * HIP graph captured on first use (results are identical either way). */
+ * HIP graph captured on first use, 0 launches directly, 2 takes the
+ * handle's choice (default: graphs); results are identical either way. */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -337,6 +338,33 @@ jfnk_status jfnk_server_wait(jfnk_server* srv, uint64_t ticket, jfnk_request_inf
 jfnk_status jfnk_server_metrics_get(jfnk_server* srv, jfnk_server_metrics* m);
 /* Finishes running and queued requests, then stops the workers. */
 jfnk_status jfnk_server_destroy(jfnk_server* srv);
+
+/* ---- Tuning ----
+ * jfnk_autotune times, on this handle's own mesh (or batch) and state u
+ * (device, internal layout, load factor `load`), the launch shapes and
+ * schedules that give identical results and keeps the fastest in the
+ * handle: the cell passes of J v (LDS-staged tiles or direct gathers; one
+ * workgroup per tile or a persistent grid), and the Arnoldi schedule
+ * (steps per host check, HIP-graph replay) on one GMRES solve of
+ * J x = -R(u) with `opts`.  Later solves use the choice when their options
+ * ask for the handle's values (step_chunk = 0, graphs = 2).  d_work: a
+ * solve workspace (op 1) for opts.restart and opts.precond.  The report
+ * (may be NULL) lists every candidate and its time. */
+typedef struct {
+  int32_t lds_kernels;         /* chosen: 1 LDS-staged cell passes, 0 gathers */
+  int32_t persist;             /* chosen: workgroups of a persistent launch (0: one per tile) */
+  int32_t step_chunk;          /* chosen Arnoldi steps per host check */
+  int32_t graphs;              /* chosen: 1 replay step runs from HIP graphs */
+  int32_t n_jv;
+  int32_t jv_lds[16], jv_persist[16];
+  double jv_ms[16];            /* mean time of one J v per candidate */
+  int32_t n_solve;
+  int32_t solve_chunk[8], solve_graphs[8];
+  double solve_ms[8];          /* time of the same GMRES solve per candidate */
+} jfnk_tune_report;
+
+jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const double* d_u, double load,
+                          void* d_work, void* stream, jfnk_tune_report* report);
 
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* jfnk_last_error(void);

@@ -77,7 +77,7 @@ void check_opts(const jfnk_gmres_opts& o) {
                "gmres: cheb_degree must lie in [1, 16]");
   JFNK_REQUIRE(o.step_chunk >= 0 && o.step_chunk <= o.restart, JFNK_E_ARG,
                "gmres: step_chunk must lie in [0, restart]");
-  JFNK_REQUIRE(o.graphs == 0 || o.graphs == 1, JFNK_E_ARG, "gmres: graphs must be 0 or 1");
+  JFNK_REQUIRE(o.graphs >= 0 && o.graphs <= 2, JFNK_E_ARG, "gmres: graphs must be 0, 1 or 2");
 }
 
 // Stream the solvers run on: the caller's, or, when the caller passes the
@@ -90,6 +90,10 @@ hipStream_t solver_stream(jfnk_mesh* m, hipStream_t s, bool graphs) {
   JFNK_HIP(hipEventRecord(m->ev[2], s));
   JFNK_HIP(hipStreamWaitEvent(m->solve_stream, m->ev[2], 0));
   return m->solve_stream;
+}
+
+bool wants_graphs(const jfnk_mesh* m, const jfnk_gmres_opts& o) {
+  return (o.graphs == 2 ? m->tune.graphs : o.graphs) != 0;
 }
 
 // The caller's stream waits for the solver's.
@@ -269,6 +273,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     m.any_large = any_large_segment(L, m.block_first.data());
   }
   d.tiled = h.tiled ? 1 : 0;
+  d.lds_kernels = d.tiled;
+  d.persist = 0;
   d.halo_stride = int32_t(kFvBlock + ua.halo_max);
   d.slot_loc = h.tiled ? m.b_slot_loc.as<int32_t>() : nullptr;
   d.halo_ptr = h.tiled ? m.b_halo_ptr.as<int32_t>() : nullptr;
@@ -298,6 +304,22 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
 extern "C" {
 
 const char* jfnk_last_error(void) { return g_last_error.c_str(); }
+
+jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const double* d_u, double load,
+                          void* d_work, void* stream, jfnk_tune_report* report) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_work(d_work);
+    JFNK_REQUIRE(opts, JFNK_E_ARG, "autotune: null options");
+    check_opts(*opts);
+    JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "autotune: load factor not finite");
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    const hipStream_t s = solver_stream(mesh, caller, true);
+    autotune(mesh, *opts, d_u, load, d_work, s, report);
+    join_stream(mesh, caller, s);
+  });
+}
 
 const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
 
@@ -529,7 +551,7 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     check_opts(*opts);
     JFNK_REQUIRE(std::isfinite(load), JFNK_E_ARG, "gmres: load factor not finite");
     const hipStream_t caller = static_cast<hipStream_t>(stream);
-    const hipStream_t s = solver_stream(mesh, caller, opts->graphs != 0);
+    const hipStream_t s = solver_stream(mesh, caller, wants_graphs(mesh, *opts));
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
@@ -581,7 +603,7 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
       JFNK_REQUIRE(inc[k] >= 1, JFNK_E_ARG, "newton: n_increments must be >= 1");
     }
     const hipStream_t caller = static_cast<hipStream_t>(stream);
-    const hipStream_t s = solver_stream(mesh, caller, opts->gmres.graphs != 0);
+    const hipStream_t s = solver_stream(mesh, caller, wants_graphs(mesh, opts->gmres));
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);

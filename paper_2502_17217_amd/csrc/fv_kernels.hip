@@ -29,6 +29,8 @@
 // Neo-Hookean total-Lagrangian face force (Appendix A/B): with a = cof(F) Gamma
 // and F^T a = J Gamma, (a . sigma) simplifies to
 //   mu J^{-2/3} F Gamma + [ kappa/2 (J - 1/J) - mu/3 J^{-5/3} tr(F F^T) ] a.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace jfnk {
@@ -320,24 +322,31 @@ __device__ __forceinline__ void zero_rec(double* __restrict__ rec, int n, int c)
   for (int k = 0; k < D + D * D; ++k) rec[size_t(k) * n + c] = 0.0;
 }
 
+// Every cell pass loops over the tiles it - blockIdx.x = 0, G, 2G, ... of a
+// launch of G workgroups (G = one per tile, or a persistent grid chosen by
+// the tuner; G is a multiple of the XCD count, so a workgroup stays on the
+// tiles its XCD owns).
 template <int D>
 __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev m, const double* __restrict__ u,
                                                                            const double* __restrict__ v,
                                                                            SegScalars sc,
-                                                                           double* __restrict__ rec, int nb_real) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  if (lb >= nb_real) return;
-  const int seg = m.seg_of_block[lb];
-  if (sc.active != nullptr && sc.active[seg] == 0) return;
-  const int c = lb * kFvBlock + threadIdx.x;
+                                                                           double* __restrict__ rec, int nb_real,
+                                                                           int nb_launch) {
   const int n = m.n_cells;
-  if (c >= n) return;
-  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {  // alignment padding
-    zero_rec<D>(rec, n, c);
-    return;
+  for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
+    const int lb = xcd_block(it, nb_launch);
+    if (lb >= nb_real) continue;
+    const int seg = m.seg_of_block[lb];
+    if (sc.active != nullptr && sc.active[seg] == 0) continue;
+    const int c = lb * kFvBlock + threadIdx.x;
+    if (c >= n) continue;
+    if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {  // alignment padding
+      zero_rec<D>(rec, n, c);
+      continue;
+    }
+    const GradGlobal<D> src{u, v, m.xc, (v != nullptr) ? sc.eps[seg] : 0.0, n};
+    gradient_cell<D>(m, src, m.slot_nb, c, c, rec);
   }
-  const GradGlobal<D> src{u, v, m.xc, (v != nullptr) ? sc.eps[seg] : 0.0, n};
-  gradient_cell<D>(m, src, m.slot_nb, c, c, rec);
 }
 
 // Tiled gradient pass: one workgroup per tile; w and the centroids of the
@@ -347,41 +356,45 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev
 template <int D>
 __global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const double* __restrict__ u,
                                                              const double* __restrict__ v, SegScalars sc,
-                                                             double* __restrict__ rec, int nb_real) {
+                                                             double* __restrict__ rec, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  if (tile >= nb_real) return;
-  const int seg = m.seg_of_block[tile];
-  if (sc.active != nullptr && sc.active[seg] == 0) return;
   const int n = m.n_cells, S = m.halo_stride;
-  const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
-  const int base = tile * kFvBlock;
-  const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
-  for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
-    const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
-    double w[D], x[D];
-    if (cg < n) {
-      load_w<D>(u, v, eps, n, cg, w);
-      load_soa<D>(m.xc, n, cg, x);
-    } else {
+  for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
+    const int tile = xcd_block(it, nb_launch);
+    if (tile >= nb_real) continue;
+    const int seg = m.seg_of_block[tile];
+    if (sc.active != nullptr && sc.active[seg] == 0) continue;
+    const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
+    const int base = tile * kFvBlock;
+    const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
+      const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
+      double w[D], x[D];
+      if (cg < n) {
+        load_w<D>(u, v, eps, n, cg, w);
+        load_soa<D>(m.xc, n, cg, x);
+      } else {
 #pragma unroll
-      for (int k = 0; k < D; ++k) w[k] = x[k] = 0.0;
-    }
+        for (int k = 0; k < D; ++k) w[k] = x[k] = 0.0;
+      }
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      lds[k * S + i] = w[k];
-      lds[(D + k) * S + i] = x[k];
+      for (int k = 0; k < D; ++k) {
+        lds[k * S + i] = w[k];
+        lds[(D + k) * S + i] = x[k];
+      }
     }
+    __syncthreads();
+    const int c = base + threadIdx.x;
+    if (c < n) {
+      if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {
+        zero_rec<D>(rec, n, c);
+      } else {
+        const GradLds<D> src{lds, S};
+        gradient_cell<D>(m, src, m.slot_loc, threadIdx.x, c, rec);
+      }
+    }
+    __syncthreads();  // the LDS copy is rewritten for the next tile
   }
-  __syncthreads();
-  const int c = base + threadIdx.x;
-  if (c >= n) return;
-  if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {
-    zero_rec<D>(rec, n, c);
-    return;
-  }
-  const GradLds<D> src{lds, S};
-  gradient_cell<D>(m, src, m.slot_loc, threadIdx.x, c, rec);
 }
 
 // Neighbour data of the flux pass: the record {w, grad w} and the centroid
@@ -532,22 +545,25 @@ template <int D, int LAWSEL>
 __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, const double* __restrict__ rec,
                                                                        SegScalars sc,
                                                                        const double* __restrict__ Ru,
-                                                                       double* __restrict__ out, int nb_real) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  if (lb >= nb_real) return;
-  const int seg = m.seg_of_block[lb];
-  if (sc.active != nullptr && sc.active[seg] == 0) return;
-  const int c = lb * kFvBlock + threadIdx.x;
+                                                                       double* __restrict__ out, int nb_real,
+                                                                       int nb_launch) {
   const int n = m.n_cells;
-  if (c >= n) return;
-  const SegInfo& si = m.seg[seg];
-  if (c - si.cell_off >= si.n_cells) {  // alignment padding
+  for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
+    const int lb = xcd_block(it, nb_launch);
+    if (lb >= nb_real) continue;
+    const int seg = m.seg_of_block[lb];
+    if (sc.active != nullptr && sc.active[seg] == 0) continue;
+    const int c = lb * kFvBlock + threadIdx.x;
+    if (c >= n) continue;
+    const SegInfo& si = m.seg[seg];
+    if (c - si.cell_off >= si.n_cells) {  // alignment padding
 #pragma unroll
-    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
-    return;
+      for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
+      continue;
+    }
+    const FluxGlobal<D> src{rec, m.xc, n};
+    flux_cell<D, LAWSEL>(m, si, src, m.slot_nb, c, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
   }
-  const FluxGlobal<D> src{rec, m.xc, n};
-  flux_cell<D, LAWSEL>(m, si, src, m.slot_nb, c, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
 }
 
 // Tiled flux pass: the records and centroids of the tile's cells and halo
@@ -556,62 +572,71 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
 template <int D, int LAWSEL>
 __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
                                                          SegScalars sc, const double* __restrict__ Ru,
-                                                         double* __restrict__ out, int nb_real) {
+                                                         double* __restrict__ out, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  if (tile >= nb_real) return;
-  const int seg = m.seg_of_block[tile];
-  if (sc.active != nullptr && sc.active[seg] == 0) return;
   const int n = m.n_cells, S = m.halo_stride;
-  const int base = tile * kFvBlock;
-  const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
   constexpr int kRows = 2 * D + D * D;
-  for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
-    const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
-    if (cg < n) {
+  for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
+    const int tile = xcd_block(it, nb_launch);
+    if (tile >= nb_real) continue;
+    const int seg = m.seg_of_block[tile];
+    if (sc.active != nullptr && sc.active[seg] == 0) continue;
+    const int base = tile * kFvBlock;
+    const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
+      const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
+      if (cg < n) {
 #pragma unroll
-      for (int r = 0; r < D + D * D; ++r) lds[r * S + i] = rec[size_t(r) * n + cg];
+        for (int r = 0; r < D + D * D; ++r) lds[r * S + i] = rec[size_t(r) * n + cg];
 #pragma unroll
-      for (int k = 0; k < D; ++k) lds[(D + D * D + k) * S + i] = m.xc[size_t(k) * n + cg];
-    } else {
+        for (int k = 0; k < D; ++k) lds[(D + D * D + k) * S + i] = m.xc[size_t(k) * n + cg];
+      } else {
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) lds[r * S + i] = 0.0;
+        for (int r = 0; r < kRows; ++r) lds[r * S + i] = 0.0;
+      }
     }
-  }
-  __syncthreads();
-  const int c = base + threadIdx.x;
-  if (c >= n) return;
-  const SegInfo& si = m.seg[seg];
-  if (c - si.cell_off >= si.n_cells) {
+    __syncthreads();
+    const int c = base + threadIdx.x;
+    if (c < n) {
+      const SegInfo& si = m.seg[seg];
+      if (c - si.cell_off >= si.n_cells) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
-    return;
+        for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
+      } else {
+        const FluxLds<D> src{lds, S};
+        flux_cell<D, LAWSEL>(m, si, src, m.slot_loc, threadIdx.x, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru,
+                             out);
+      }
+    }
+    __syncthreads();  // the LDS copy is rewritten for the next tile
   }
-  const FluxLds<D> src{lds, S};
-  flux_cell<D, LAWSEL>(m, si, src, m.slot_loc, threadIdx.x, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
 }
 
-inline void grid_for(int n_cells, int& nb_real, int& nb_launch) {
-  nb_real = (n_cells + kFvBlock - 1) / kFvBlock;
+// nb_real tiles, nb_launch = tiles rounded up to the XCD count, and the
+// number of workgroups launched (persistent grid when the tuner set one).
+inline void grid_for(const MeshDev& m, int& nb_real, int& nb_launch, int& grid) {
+  nb_real = (m.n_cells + kFvBlock - 1) / kFvBlock;
   nb_launch = ((nb_real + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  grid = nb_launch;
+  if (m.persist > 0) grid = std::min(nb_launch, ((m.persist + kNumXcd - 1) / kNumXcd) * kNumXcd);
 }
 
 }  // namespace
 
 void launch_gradient(const MeshDev& m, const double* u, const double* v, const SegScalars& sc,
                      double* rec, hipStream_t s) {
-  int nr, nl;
-  grid_for(m.n_cells, nr, nl);
-  if (m.tiled) {
+  int nr, nl, g;
+  grid_for(m, nr, nl, g);
+  if (m.tiled && m.lds_kernels) {
     const size_t lds = sizeof(double) * 2 * m.dim * size_t(m.halo_stride);
     if (m.dim == 3)
-      hipLaunchKernelGGL(k_gradient_tiled<3>, dim3(nl), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr);
+      hipLaunchKernelGGL(k_gradient_tiled<3>, dim3(g), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr, nl);
     else
-      hipLaunchKernelGGL(k_gradient_tiled<2>, dim3(nl), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr);
+      hipLaunchKernelGGL(k_gradient_tiled<2>, dim3(g), dim3(kFvBlock), lds, s, m, u, v, sc, rec, nr, nl);
   } else if (m.dim == 3) {
-    hipLaunchKernelGGL(k_gradient<3>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
+    hipLaunchKernelGGL(k_gradient<3>, dim3(g), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr, nl);
   } else {
-    hipLaunchKernelGGL(k_gradient<2>, dim3(nl), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr);
+    hipLaunchKernelGGL(k_gradient<2>, dim3(g), dim3(kFvBlock), 0, s, m, u, v, sc, rec, nr, nl);
   }
   JFNK_HIP(hipGetLastError());
 }
@@ -621,13 +646,13 @@ namespace {
 template <int D, int LAWSEL>
 void flux_launch(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
                  hipStream_t s) {
-  int nr, nl;
-  grid_for(m.n_cells, nr, nl);
-  if (m.tiled) {
+  int nr, nl, g;
+  grid_for(m, nr, nl, g);
+  if (m.tiled && m.lds_kernels) {
     const size_t lds = sizeof(double) * (2 * D + D * D) * size_t(m.halo_stride);
-    hipLaunchKernelGGL((k_flux_tiled<D, LAWSEL>), dim3(nl), dim3(kFvBlock), lds, s, m, rec, sc, Ru, out, nr);
+    hipLaunchKernelGGL((k_flux_tiled<D, LAWSEL>), dim3(g), dim3(kFvBlock), lds, s, m, rec, sc, Ru, out, nr, nl);
   } else {
-    hipLaunchKernelGGL((k_flux<D, LAWSEL>), dim3(nl), dim3(kFvBlock), 0, s, m, rec, sc, Ru, out, nr);
+    hipLaunchKernelGGL((k_flux<D, LAWSEL>), dim3(g), dim3(kFvBlock), 0, s, m, rec, sc, Ru, out, nr, nl);
   }
 }
 

@@ -101,6 +101,8 @@ struct MeshDev {
   // workgroup's LDS copy (0..kFvBlock-1: inside the tile, kFvBlock + h:
   // entry h of the tile's halo list) or the slot_nb code of other slots
   int32_t tiled;
+  int32_t lds_kernels;       // 1: use the LDS-staged passes on a tiled mesh (tuner's choice)
+  int32_t persist;           // workgroups of a persistent cell-pass launch (0: one per tile)
   int32_t halo_stride;       // kFvBlock + largest halo: LDS row length
   const int32_t* slot_loc;   // [n_slots]
   const int32_t* halo_ptr;   // [n_tiles + 1]
@@ -248,6 +250,7 @@ struct StepGraphs {
 // Launch choices made by the autotuner (jfnk_autotune) or the defaults.
 struct Tuning {
   int step_chunk = 1;    // Arnoldi steps enqueued between host convergence checks
+  int graphs = 1;        // replay runs of steps from HIP graphs
   int tuned = 0;         // 1 once jfnk_autotune has run
 };
 }  // namespace jfnk

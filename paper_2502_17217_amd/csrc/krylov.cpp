@@ -194,7 +194,8 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   const int K = std::min(mr, o.step_chunk > 0 ? o.step_chunk : std::max(1, m->tune.step_chunk));
   const int n_chunks = (mr + K - 1) / K;
   // Graphs need a capturable stream and unchanged launch arguments.
-  const bool use_graphs = o.graphs != 0 && s != nullptr && !m->prof.on;
+  const int graphs = o.graphs == 2 ? m->tune.graphs : o.graphs;
+  const bool use_graphs = graphs != 0 && s != nullptr && !m->prof.on;
   if (use_graphs) {
     StepGraphs& sg = m->graphs;
     const void* work = static_cast<const void*>(kw.V);

@@ -47,5 +47,7 @@ void precond_setup(jfnk_mesh* m, int precond, hipStream_t s);
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
                    KrylovWork& kw, hipStream_t s);
 void amg_destroy(AmgHierarchy* a);
+void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o, const double* u, double load, void* work, hipStream_t s,
+              jfnk_tune_report* rep);
 
 }  // namespace jfnk

@@ -72,6 +72,21 @@ class jfnk_stats(C.Structure):
                     eps_last=self.eps_last, t_ms=list(self.t_ms))
 
 
+class jfnk_tune_report(C.Structure):
+    _fields_ = [("lds_kernels", C.c_int32), ("persist", C.c_int32), ("step_chunk", C.c_int32),
+                ("graphs", C.c_int32), ("n_jv", C.c_int32), ("jv_lds", C.c_int32 * 16),
+                ("jv_persist", C.c_int32 * 16), ("jv_ms", C.c_double * 16), ("n_solve", C.c_int32),
+                ("solve_chunk", C.c_int32 * 8), ("solve_graphs", C.c_int32 * 8), ("solve_ms", C.c_double * 8)]
+
+    def as_dict(self):
+        return {"lds_kernels": self.lds_kernels, "persist": self.persist, "step_chunk": self.step_chunk,
+                "graphs": self.graphs,
+                "jv": [{"lds": self.jv_lds[i], "persist": self.jv_persist[i], "ms": self.jv_ms[i]}
+                       for i in range(self.n_jv)],
+                "solve": [{"step_chunk": self.solve_chunk[i], "graphs": self.solve_graphs[i],
+                           "ms": self.solve_ms[i]} for i in range(self.n_solve)]}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libjfnk.so is not built (run __graft_entry__.build() or "
@@ -96,6 +111,7 @@ def _load():
         "jfnk_newton_solve": [vp, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp],
         "jfnk_profile_enable": [vp, i32],
         "jfnk_profile_read": [vp, vp, vp, i32],
+        "jfnk_autotune": [vp, C.POINTER(jfnk_gmres_opts), vp, d, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -331,7 +347,7 @@ def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
-               step_chunk=0, graphs=1):
+               step_chunk=0, graphs=2):
     if isinstance(precond, str):
         precond = PRECOND[precond]
     return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs)
@@ -373,6 +389,15 @@ def newton_solve_batch(mesh, opts, u, work, n_increments=None, stream=None, allo
                                      C.cast(seg, C.c_void_p), work.c, _stream(stream))
     _check(s, "jfnk_newton_solve_batch", allow)
     return s, [x.as_dict() for x in st], list(seg)
+
+
+def autotune(mesh, opts, u, work, load=1.0, stream=None):
+    """Time the equivalent launch shapes and Arnoldi schedules on this handle
+    and keep the fastest (see include/jfnk.h); returns the report."""
+    rep = jfnk_tune_report()
+    _check(_lib.jfnk_autotune(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), float(load), work.c,
+                              _stream(stream), C.byref(rep)), "jfnk_autotune")
+    return rep.as_dict()
 
 
 def profile_enable(mesh, on=True):
