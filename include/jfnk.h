@@ -311,7 +311,7 @@ typedef struct {
 typedef struct {
   int32_t status;                /* jfnk_status of the request */
   int32_t state;                 /* 0 queued, 1 running, 2 done */
-  double t_submit_ms, t_start_ms, t_done_ms;   /* server clock */
+  double t_submit_ms, t_start_ms, t_done_ms;   /* server clock; start = HBM reservation granted */
   double latency_ms;             /* t_done - t_submit */
   int64_t footprint_bytes;
   int64_t n_cells;

@@ -113,7 +113,11 @@ size_t device_bytes_of(const HostMesh& h) {
          b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
          b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256 +
          // tiles: slot_loc, halo_ptr and at most one halo entry per slot
-         (h.tiled ? 2 * b(h.slot_nb.size() * 4) + b(size_t(h.n_cells / kFvBlock + 2) * 4) : 0);
+         // tiles: slot_loc, slot_lf, halo and incoming-face lists (at most one entry per slot each),
+         // per-tile offsets, packed face positions
+         (h.tiled ? 3 * b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 2) + 3 * b(size_t(h.n_cells / kFvBlock + 2) * 4) +
+                        b(size_t(h.n_int) * 4)
+                  : 0);
 }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -236,6 +240,12 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     upload(m.b_slot_loc, ua.slot_loc, s);
     upload(m.b_halo_ptr, ua.halo_ptr, s);
     upload(m.b_halo_cells, ua.halo_cells, s);
+    upload(m.b_slot_lf, ua.slot_lf, s);
+    upload(m.b_fbeg, ua.fbeg, s);
+    upload(m.b_face_loc, ua.face_loc, s);
+    upload(m.b_in_ptr, ua.in_ptr, s);
+    upload(m.b_in_face, ua.in_face, s);
+    upload(m.b_in_loc, ua.in_loc, s);
   }
   JFNK_HIP(hipStreamSynchronize(s));
   const int S = m.n_seg();
@@ -279,6 +289,15 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.slot_loc = h.tiled ? m.b_slot_loc.as<int32_t>() : nullptr;
   d.halo_ptr = h.tiled ? m.b_halo_ptr.as<int32_t>() : nullptr;
   d.halo_cells = h.tiled ? m.b_halo_cells.as<int32_t>() : nullptr;
+  d.slot_lf = h.tiled ? m.b_slot_lf.as<int16_t>() : nullptr;
+  d.fbeg = h.tiled ? m.b_fbeg.as<int32_t>() : nullptr;
+  d.face_loc = h.tiled ? m.b_face_loc.as<int32_t>() : nullptr;
+  d.in_ptr = h.tiled ? m.b_in_ptr.as<int32_t>() : nullptr;
+  d.in_face = h.tiled ? m.b_in_face.as<int32_t>() : nullptr;
+  d.in_loc = h.tiled ? m.b_in_loc.as<int32_t>() : nullptr;
+  d.face_stride = int32_t(std::max<int64_t>(ua.faces_max, 1));
+  // the deduplicating LDS flux pass needs its staged tile and face forces in LDS
+  if (d.tiled && flux_lds_bytes(dim, d.halo_stride, d.face_stride) > size_t(kFluxLdsBytes) * 2) d.lds_kernels = 0;
   jfnk_mesh_info& in = m.info;
   in.n_cells = h.n_cells;
   in.dim = dim;
@@ -290,7 +309,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
                             m.b_fG.bytes + m.b_fw.bytes + m.b_magG.bytes + m.b_bface.bytes +
                             m.b_ext.bytes + m.b_pc_dinv.bytes + m.b_seg_of_block.bytes + m.b_seg.bytes +
                             m.b_block_first.bytes + m.b_slot_loc.bytes + m.b_halo_ptr.bytes +
-                            m.b_halo_cells.bytes);
+                            m.b_halo_cells.bytes + m.b_slot_lf.bytes + m.b_fbeg.bytes + m.b_face_loc.bytes +
+                            m.b_in_ptr.bytes + m.b_in_face.bytes + m.b_in_loc.bytes);
   in.n_slots = int64_t(ua.slot_nb.size());
   in.n_segments = S;
   in.n_dof_external = m.n_ext_cells * dim;

@@ -426,6 +426,43 @@ struct FluxLds {
   }
 };
 
+// Boundary face bf of cell P added to R: displacement faces Gamma . sigma_P
+// plus the Rhie-Chow term against load * u_bar; traction faces
+// load |Gamma| T_bar and pressure faces -load p Gamma (stored pre-multiplied).
+template <int D, int LAW>
+__device__ __forceinline__ void boundary_force(const MeshDev& m, const Law& law, int bf, double load,
+                                               const double (&wP)[D], const double (&gP)[D][D], double (&R)[D]) {
+  const double* r = m.bface + size_t(bf) * kBfaceRec;
+  const int type = int(r[9]);
+  if (type == kBcDisp) {
+    double G[D], db[D], ub[D], t[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      G[q] = r[q];
+      db[q] = r[3 + q];
+      ub[q] = load * r[6 + q];
+    }
+    traction<D, LAW>(law, gP, G, t);
+    double dG = 0, GG = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      dG = fma(db[q], G[q], dG);
+      GG = fma(G[q], G[q], GG);
+    }
+    const double coef = law.aK * GG / dG;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double dg = 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
+      R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
+  }
+}
+
 // Sum of the face forces of cell c (Eq. divStressDiscret + Eq. RhieChow);
 // ids holds the neighbour ids of the slots in the source's numbering and
 // self is c's id.
@@ -475,36 +512,7 @@ __device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, co
 #pragma unroll
         for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
       } else if (nb[k] == kSlotBoundary) {
-        const double* r = m.bface + size_t(fc[k]) * kBfaceRec;
-        const int type = int(r[9]);
-        if (type == kBcDisp) {
-          double G[D], db[D], ub[D], t[D];
-#pragma unroll
-          for (int q = 0; q < D; ++q) {
-            G[q] = r[q];
-            db[q] = r[3 + q];
-            ub[q] = load * r[6 + q];
-          }
-          traction<D, LAW>(law, gP, G, t);
-          double dG = 0, GG = 0;
-#pragma unroll
-          for (int q = 0; q < D; ++q) {
-            dG = fma(db[q], G[q], dG);
-            GG = fma(G[q], G[q], GG);
-          }
-          const double coef = law.aK * GG / dG;
-#pragma unroll
-          for (int j = 0; j < D; ++j) {
-            double dg = 0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
-            R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
-          }
-        } else {
-          // traction: |Gamma| T_bar, pressure: -p Gamma (stored pre-multiplied)
-#pragma unroll
-          for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
-        }
+        boundary_force<D, LAW>(m, law, fc[k], load, wP, gP, R);
       }
     }
   }
@@ -566,16 +574,129 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
   }
 }
 
-// Tiled flux pass: the records and centroids of the tile's cells and halo
-// are staged in LDS (rows of length halo_stride), then every neighbour is
-// read from LDS.  Exits before the barrier are uniform over the workgroup.
+// Tiled flux pass.  The records and centroids of the tile's cells and halo
+// are staged in LDS (rows of length halo_stride).  Phase A evaluates every
+// internal face touching the tile once, spread evenly over the workgroup
+// (owner first, the canonical operand order), into LDS; phase B sums each
+// cell's slots in slot order (face forces from LDS with the sign of the
+// side, boundary faces evaluated in place), the same sequence of operations
+// as the gather pass, so both give the same bits.  Exits before a barrier
+// are uniform over the workgroup.
+// Face data of up to kEnt entries of the tile's face list (entries
+// e = threadIdx.x + j * kFvBlock), loaded before the staging barrier so that
+// every global load of the tile is in flight at once.
+constexpr int kEnt = 4;
+template <int D>
+struct FaceBatch {
+  int n = 0;
+  int lo[kEnt], ln[kEnt];
+  double G[kEnt][D], wf[kEnt];
+};
+
+template <int D>
+__device__ __forceinline__ void load_faces(const MeshDev& m, int tile, int e0, FaceBatch<D>& fb) {
+  const int f0 = m.fbeg[tile], n_own = m.fbeg[tile + 1] - f0;
+  const int i0 = m.in_ptr[tile], n_ent = n_own + m.in_ptr[tile + 1] - i0;
+  fb.n = 0;
+#pragma unroll
+  for (int j = 0; j < kEnt; ++j) {
+    const int e = e0 + j * kFvBlock;
+    if (e >= n_ent) break;
+    const int f = e < n_own ? f0 + e : m.in_face[i0 + e - n_own];
+    const int packed = e < n_own ? m.face_loc[f] : m.in_loc[i0 + e - n_own];
+    fb.lo[j] = packed & 0xffff;
+    fb.ln[j] = packed >> 16;
+    load_soa<D>(m.fG, m.n_int, f, fb.G[j]);
+    fb.wf[j] = m.fw[f];
+    fb.n = j + 1;
+  }
+}
+
+// Phase A: the loaded faces, owner first (the canonical operand order).
+template <int D, int LAW>
+__device__ __forceinline__ void face_forces(const SegInfo& si, const FluxLds<D>& src, int e0, const FaceBatch<D>& fb,
+                                            double* __restrict__ ff, int fs) {
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+#pragma unroll
+  for (int j = 0; j < kEnt; ++j) {
+    if (j >= fb.n) break;
+    double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
+    src.get(fb.lo[j], wA, gA, xA);
+    src.get(fb.ln[j], wB, gB, xB);
+    internal_face_force<D, LAW>(law, fb.G[j], fb.wf[j], xA, xB, wA, wB, gA, gB, fo);
+#pragma unroll
+    for (int q = 0; q < D; ++q) ff[q * fs + e0 + j * kFvBlock] = fo[q];
+  }
+}
+
+// Phase B: cell c sums its slots in slot order (face forces from LDS with
+// the sign of its side, boundary faces evaluated in place).
+// Slot metadata of one chunk of a cell's slots.
+struct SlotChunk {
+  int nb[kChunk], fc[kChunk], lf[kChunk];
+};
+
+__device__ __forceinline__ void load_slots(const MeshDev& m, int s0, int width, int lane, int k0, SlotChunk& sl) {
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int idx = s0 + (k0 + k) * kSlice + lane;
+    const bool in = k0 + k < width;
+    sl.nb[k] = in ? m.slot_loc[idx] : kSlotPad;
+    sl.fc[k] = in ? m.slot_fc[idx] : 0;
+    sl.lf[k] = in ? int(m.slot_lf[idx]) : 0;
+  }
+}
+
+// first: the cell's first chunk of slots, loaded before the tile's barriers
+template <int D, int LAW>
+__device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& si, const FluxLds<D>& src, int self,
+                                              int c, double load, const double* __restrict__ ff, int fs,
+                                              const SlotChunk& first, double (&R)[D]) {
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+  double wP[D], xP[D], gP[D][D];
+  src.get(self, wP, gP, xP);
+#pragma unroll
+  for (int q = 0; q < D; ++q) R[q] = 0.0;
+  const int slice = c / kSlice, lane = c % kSlice;
+  const int s0 = m.slice_ptr[slice];
+  const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
+  for (int k0 = 0; k0 < width; k0 += kChunk) {
+    SlotChunk cur;
+    if (k0 == 0)
+      cur = first;
+    else
+      load_slots(m, s0, width, lane, k0, cur);
+    const int* nb = cur.nb;
+    const int* fc = cur.fc;
+    const int* lf = cur.lf;
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      if (nb[k] >= 0) {
+        const bool own = fc[k] >= 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) R[q] += own ? ff[q * fs + lf[k]] : -ff[q * fs + lf[k]];
+      } else if (nb[k] == kSlotBoundary) {
+        boundary_force<D, LAW>(m, law, fc[k], load, wP, gP, R);
+      }
+    }
+  }
+}
+
+// Tiled flux pass.  The records and centroids of the tile's cells and halo
+// are staged in LDS (rows of length halo_stride).  Phase A evaluates every
+// internal face touching the tile once, spread evenly over the workgroup
+// (owner first, the canonical operand order), into LDS; phase B sums each
+// cell's slots in slot order, the same sequence of operations as the
+// gather pass, so both give the same bits.  Exits before a barrier are
+// uniform over the workgroup.
 template <int D, int LAWSEL>
 __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
                                                          SegScalars sc, const double* __restrict__ Ru,
                                                          double* __restrict__ out, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
-  const int n = m.n_cells, S = m.halo_stride;
+  const int n = m.n_cells, S = m.halo_stride, fs = m.face_stride;
   constexpr int kRows = 2 * D + D * D;
+  double* ff = lds + kRows * S;
   for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
     const int tile = xcd_block(it, nb_launch);
     if (tile >= nb_real) continue;
@@ -583,6 +704,22 @@ __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double
     if (sc.active != nullptr && sc.active[seg] == 0) continue;
     const int base = tile * kFvBlock;
     const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    const int n_ent = m.fbeg[tile + 1] - m.fbeg[tile] + m.in_ptr[tile + 1] - m.in_ptr[tile];
+    FaceBatch<D> fb;
+    load_faces<D>(m, tile, threadIdx.x, fb);
+    // this cell's first chunk of slots and R(u), also ahead of the barriers
+    const int c = base + threadIdx.x;
+    SlotChunk first;
+    double ru[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) ru[q] = 0.0;
+    if (c < n) {
+      const int s0 = m.slice_ptr[c / kSlice];
+      load_slots(m, s0, (m.slice_ptr[c / kSlice + 1] - s0) / kSlice, c % kSlice, 0, first);
+      if (Ru != nullptr)
+#pragma unroll
+        for (int q = 0; q < D; ++q) ru[q] = Ru[size_t(q) * n + c];
+    }
     for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
       const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
       if (cg < n) {
@@ -596,16 +733,47 @@ __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double
       }
     }
     __syncthreads();
-    const int c = base + threadIdx.x;
-    if (c < n) {
-      const SegInfo& si = m.seg[seg];
-      if (c - si.cell_off >= si.n_cells) {
-#pragma unroll
-        for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;
+    const SegInfo& si = m.seg[seg];
+    const FluxLds<D> src{lds, S};
+    // phase A, kEnt entries per thread per round (one round unless the tile
+    // touches more than kEnt * kFvBlock faces)
+    for (int e0 = threadIdx.x;; e0 += kEnt * kFvBlock) {
+      if (e0 != threadIdx.x) load_faces<D>(m, tile, e0, fb);
+      if constexpr (LAWSEL == kLawMixed) {
+        if (si.law == JFNK_NEO_HOOKEAN)
+          face_forces<D, JFNK_NEO_HOOKEAN>(si, src, e0, fb, ff, fs);
+        else
+          face_forces<D, JFNK_LINEAR_ELASTIC>(si, src, e0, fb, ff, fs);
       } else {
-        const FluxLds<D> src{lds, S};
-        flux_cell<D, LAWSEL>(m, si, src, m.slot_loc, threadIdx.x, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru,
-                             out);
+        face_forces<D, LAWSEL>(si, src, e0, fb, ff, fs);
+      }
+      if (e0 - int(threadIdx.x) + kEnt * kFvBlock >= n_ent) break;
+    }
+    __syncthreads();
+    if (c < n) {
+      if (c - si.cell_off < si.n_cells) {
+        const double load = sc.load[seg];
+        double R[D];
+        if constexpr (LAWSEL == kLawMixed) {
+          if (si.law == JFNK_NEO_HOOKEAN)
+            tile_cell_sum<D, JFNK_NEO_HOOKEAN>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
+          else
+            tile_cell_sum<D, JFNK_LINEAR_ELASTIC>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
+        } else {
+          tile_cell_sum<D, LAWSEL>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
+        }
+        if (Ru != nullptr) {
+          const double eps = sc.eps[seg];
+          const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+#pragma unroll
+          for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - ru[q]) * ie : 0.0;
+        } else {
+#pragma unroll
+          for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;  // alignment padding
       }
     }
     __syncthreads();  // the LDS copy is rewritten for the next tile
@@ -649,7 +817,7 @@ void flux_launch(const MeshDev& m, const double* rec, const SegScalars& sc, cons
   int nr, nl, g;
   grid_for(m, nr, nl, g);
   if (m.tiled && m.lds_kernels) {
-    const size_t lds = sizeof(double) * (2 * D + D * D) * size_t(m.halo_stride);
+    const size_t lds = flux_lds_bytes(D, m.halo_stride, m.face_stride);
     hipLaunchKernelGGL((k_flux_tiled<D, LAWSEL>), dim3(g), dim3(kFvBlock), lds, s, m, rec, sc, Ru, out, nr, nl);
   } else {
     hipLaunchKernelGGL((k_flux<D, LAWSEL>), dim3(g), dim3(kFvBlock), 0, s, m, rec, sc, Ru, out, nr, nl);

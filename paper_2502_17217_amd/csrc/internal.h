@@ -55,6 +55,12 @@ constexpr int kSegAlign = kFvBlock;
 // tile's kFvBlock cells plus its halo, (2 dim + dim^2) doubles per cell
 constexpr int kTileLdsBytes = 64 * 1024;
 inline int64_t tile_halo_limit(int dim) { return kTileLdsBytes / (8 * (2 * dim + dim * dim)) - kFvBlock; }
+// LDS of one flux workgroup (staged tile + halo, then the in-tile face
+// forces); at most this, so that two workgroups share a compute unit
+constexpr int kFluxLdsBytes = 80 * 1024;
+inline size_t flux_lds_bytes(int dim, int64_t halo_stride, int64_t face_stride) {
+  return sizeof(double) * (size_t(2 * dim + dim * dim) * size_t(halo_stride) + size_t(dim) * size_t(face_stride));
+}
 // slot_nb values
 constexpr int kSlotBoundary = -1;
 constexpr int kSlotPad = -2;
@@ -107,6 +113,20 @@ struct MeshDev {
   const int32_t* slot_loc;   // [n_slots]
   const int32_t* halo_ptr;   // [n_tiles + 1]
   const int32_t* halo_cells; // [halo_ptr[n_tiles]] cell numbers
+  // Face lists of the tiles for the LDS flux pass.  Tile t evaluates each
+  // internal face touching it once: the faces its cells own (the contiguous
+  // range fbeg[t] .. fbeg[t+1]-1, owner < neighbour) and the incoming faces
+  // owned by an earlier tile (in_face[in_ptr[t] ..]); face_loc / in_loc pack
+  // the LDS positions of owner (low 16 bits) and neighbour (high 16 bits).
+  // slot_lf gives, for every internal slot, the face's entry in its tile's
+  // list (owned faces first, then incoming), -1 for the other slots.
+  const int32_t* fbeg;       // [n_tiles + 1]
+  const int32_t* face_loc;   // [n_int]
+  const int32_t* in_ptr;     // [n_tiles + 1]
+  const int32_t* in_face;    // [in_ptr[n_tiles]]
+  const int32_t* in_loc;     // [in_ptr[n_tiles]]
+  const int16_t* slot_lf;    // [n_slots]
+  int32_t face_stride;       // largest face list of a tile: LDS row length of the face forces
 };
 
 // Per-call, per-segment device scalars.
@@ -147,8 +167,9 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
 // Host arrays of a batch union, ready for upload.
 struct UnionArrays {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
-  std::vector<int32_t> slot_loc, halo_ptr, halo_cells;
-  int64_t halo_max = 0;
+  std::vector<int32_t> slot_loc, halo_ptr, halo_cells, fbeg, face_loc, in_ptr, in_face, in_loc;
+  std::vector<int16_t> slot_lf;
+  int64_t halo_max = 0, faces_max = 0;
   std::vector<double> xc, face, magG, bface, pc_dinv;
   std::vector<SegInfo> seg;
 };
@@ -264,7 +285,8 @@ struct jfnk_mesh {
   std::vector<int32_t> block_first; // [n_seg + 1] first workgroup (kFvBlock cells) of each segment
   jfnk::MeshDev dev{};
   jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
-      b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells;
+      b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells, b_slot_lf, b_fbeg,
+      b_face_loc, b_in_ptr, b_in_face, b_in_loc;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
   bool pinned_owned = true;

@@ -722,6 +722,24 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   ua.slot_loc.clear();
   if (U.tiled) {
     ua.slot_loc.assign(ua.slot_nb.size(), kSlotPad);
+    ua.slot_lf.assign(ua.slot_nb.size(), int16_t(-1));
+    ua.fbeg.assign(n_blocks + 1, 0);
+    ua.face_loc.assign(size_t(U.n_int), 0);
+    ua.in_ptr.assign(n_blocks + 1, 0);
+    ua.in_face.clear();
+    ua.in_loc.clear();
+    ua.faces_max = 0;
+    {
+      // owned faces of tile t: owners ascend with the face number (slice order)
+      int64_t f = 0;
+      for (int64_t t = 0; t <= n_blocks; ++t) {
+        while (f < U.n_int && U.fown[f] / kFvBlock < t) ++f;
+        ua.fbeg[t] = int32_t(f);
+      }
+      for (int64_t j = 1; j < U.n_int; ++j)
+        JFNK_REQUIRE(U.fown[j] / kFvBlock >= U.fown[j - 1] / kFvBlock, JFNK_E_MESH,
+                     "mesh: internal faces not grouped by owner tile");
+    }
     std::vector<int32_t> halo;
     for (int64_t t = 0; t < n_blocks; ++t) {
       const int64_t c0 = t * kFvBlock, c1 = std::min<int64_t>(N, c0 + kFvBlock);
@@ -748,8 +766,35 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       ua.halo_cells.insert(ua.halo_cells.end(), halo.begin(), halo.end());
       ua.halo_ptr[t + 1] = int32_t(ua.halo_cells.size());
       ua.halo_max = std::max<int64_t>(ua.halo_max, int64_t(halo.size()));
+      // face list: owned faces (entries 0 .. n_own-1), then incoming faces
+      auto loc_of = [&](int32_t cell) {
+        return cell / kFvBlock == t
+                   ? int32_t(cell - c0)
+                   : kFvBlock + int32_t(std::lower_bound(halo.begin(), halo.end(), cell) - halo.begin());
+      };
+      const int32_t f0 = ua.fbeg[t], n_own = ua.fbeg[t + 1] - f0;
+      for (int32_t f = f0; f < f0 + n_own; ++f)
+        ua.face_loc[f] = loc_of(U.fown[f]) | (loc_of(U.fnb[f]) << 16);
+      int32_t n_in = 0;
+      for (int64_t sl = sl0; sl <= sl1; ++sl)
+        for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
+          const int32_t nb = ua.slot_nb[q], fc = ua.slot_fc[q];
+          if (nb < 0) continue;
+          if (fc >= 0) {
+            ua.slot_lf[q] = int16_t(fc - f0);
+          } else if (nb / kFvBlock == t) {
+            ua.slot_lf[q] = int16_t(~fc - f0);   // owner in this tile
+          } else {
+            ua.in_face.push_back(~fc);
+            ua.in_loc.push_back(loc_of(U.fown[~fc]) | (loc_of(U.fnb[~fc]) << 16));
+            ua.slot_lf[q] = int16_t(n_own + n_in++);
+          }
+        }
+      ua.in_ptr[t + 1] = int32_t(ua.in_face.size());
+      ua.faces_max = std::max<int64_t>(ua.faces_max, int64_t(n_own) + n_in);
     }
     JFNK_REQUIRE(ua.halo_max <= tile_halo_limit(dim), JFNK_E_MESH, "mesh: tile halo exceeds the LDS budget");
+    JFNK_REQUIRE(ua.faces_max < 32768, JFNK_E_MESH, "mesh: too many faces inside a tile");
   }
   ua.pc_dinv.resize(N);
   for (int64_t c = 0; c < N; ++c) ua.pc_dinv[c] = 1.0 / U.pc_diag[c];

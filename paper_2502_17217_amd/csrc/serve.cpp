@@ -105,13 +105,18 @@ namespace {
 
 // Wait for reservation turn `ticket`; then take `foot` bytes (waiting until
 // they fit) or, with foot == 0, just pass the turn on.
-void take_turn(jfnk_server* S, uint64_t ticket, size_t foot) {
+// Waits for this ticket's turn and for foot bytes of budget; returns the
+// server clock at the grant (taken under the lock, so grant times follow
+// the ticket order).
+double take_turn(jfnk_server* S, uint64_t ticket, size_t foot) {
   std::unique_lock<std::mutex> lk(S->mu);
   S->cv_budget.wait(lk, [&] { return S->budget_serving == ticket && S->in_use + foot <= S->opts.hbm_budget; });
   S->in_use += foot;
   S->peak = std::max(S->peak, S->in_use);
   S->budget_serving++;
+  const double t = clock_ms() - S->t0;
   S->cv_budget.notify_all();
+  return t;
 }
 
 void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream, double* pinned,
@@ -140,7 +145,7 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
     throw Error{JFNK_E_OOM, "request footprint " + std::to_string(foot) + " exceeds the server's HBM budget"};
   }
   // reservation in request order
-  take_turn(S, ticket, foot);
+  const double t_grant = take_turn(S, ticket, foot);
   struct Release {
     jfnk_server* S;
     size_t foot;
@@ -150,7 +155,7 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
       S->cv_budget.notify_all();
     }
   } release{S, foot};
-  info.t_start_ms = clock_ms() - S->t0;
+  info.t_start_ms = t_grant;
   info.state = 1;
   if (S->opts.dry_run_us_per_kcell > 0) {
     std::this_thread::sleep_for(std::chrono::microseconds(
