@@ -33,7 +33,7 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel, dim, law, shape):
+def measured_traffic(kernel, dim, law, shape, lds):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE summary of the default workload, or None when the kernel
     sources have changed since those counters were taken (or for another
@@ -52,7 +52,9 @@ def measured_traffic(kernel, dim, law, shape):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest()[:16] != rec["source_hash"]:
         return None
-    name = {"flux": "jfnk::k_flux<%d, 1>" % dim, "gradient": "jfnk::k_gradient<%d>" % dim}.get(kernel)
+    tiled = "_tiled" if lds else ""
+    name = {"flux": "jfnk::k_flux%s<%d, 1>" % (tiled, dim),
+            "gradient": "jfnk::k_gradient%s<%d>" % (tiled, dim)}.get(kernel)
     k = rec["kernels"].get(name)
     return k["traffic_bytes"] if k else None
 
@@ -66,22 +68,38 @@ def nominal_centres(meta):
     return np.stack([(i + 0.5) * Lx / nx, (j + 0.5) * Ly / ny, (k + 0.5) * Lz / nz], axis=1)
 
 
-def algorithmic_bytes(info, dim):
+def algorithmic_bytes(info, dim, lds_kernels):
     """Bytes each kernel must move once per launch with this data layout
-    (every array counted once, at its full size)."""
+    (every array counted once, at its full size; data staged for a tile's
+    halo and re-read from cache is not counted)."""
     nc, nd = info["n_cells"], info["n_dof"]
     n_int, n_bnd, n_slots = info["n_internal_faces"], info["n_boundary_faces"], info["n_slots"]
     n_slices = (nc + 63) // 64
-    slots = n_slots * 8 + (n_slices + 1) * 4
+    n_tiles = (nc + 255) // 256
+    slots = n_slots * 8 + (n_slices + 1) * 4          # neighbour/local index and face index per slot
     vec = nd * 8
     xc = nc * dim * 8
-    rec = nc * (dim + dim * dim) * 8        # {w, grad w} per cell
+    rec = nc * (dim + dim * dim) * 8                 # {w, grad w} per cell
+    face = n_int * (dim + 1) * 8                     # Gamma_f, w_f
+    if lds_kernels:
+        halo = info["tile_halo_total"] * 4 + (n_tiles + 1) * 4
+        incoming = info["tile_incoming_total"] * 8 + (n_tiles + 1) * 4
+        return {
+            "eps": 2 * vec,
+            # u, v, centroids, halo lists, |Gamma|, slot map; writes the record
+            "gradient": 2 * vec + xc + halo + n_int * 8 + slots + rec,
+            # record, centroids, halo lists, face data and packed positions, incoming
+            # faces, tile face offsets, boundary records, slot map + slot face entry,
+            # R(u); writes J v
+            "flux": rec + xc + halo + face + n_int * 4 + incoming + (n_tiles + 1) * 4 + n_bnd * 80
+                    + slots + n_slots * 2 + 2 * vec,
+        }
     return {
         "eps": 2 * vec,
         # reads u, v, centroids, |Gamma|, slot map; writes the record
         "gradient": 2 * vec + xc + n_int * 8 + slots + rec,
         # reads record, centroids, Gamma and w_f, boundary records, slot map, R(u); writes J v
-        "flux": rec + xc + n_int * (dim + 1) * 8 + n_bnd * 80 + slots + 2 * vec,
+        "flux": rec + xc + face + n_bnd * 80 + slots + 2 * vec,
     }
 
 
@@ -356,7 +374,7 @@ def main():
         jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work)
     prof = jfnk.profile_read(gm, reset=True)
     jfnk.profile_enable(gm, False)
-    ab = algorithmic_bytes(gm.info, 3)
+    ab = algorithmic_bytes(gm.info, 3, tune["lds_kernels"] if tune else gm.info["tiled"])
     kern = {}
     for name in ("eps", "gradient", "flux"):
         ms, calls = prof[name]
@@ -426,7 +444,8 @@ def main():
                    "law": mat.law, "cells": gm.n_cells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS if ach else None,
-                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz)),
+                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz),
+                                                 tune["lds_kernels"] if tune else gm.info["tiled"]),
                      "kernel": dom, "algorithmic_bytes": kern[dom]["bytes"]},
         "jv_hbm_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "kernels": kern,

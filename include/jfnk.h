@@ -133,6 +133,8 @@ typedef struct {
   int64_t n_dof_external;      /* length of an external vector (sum over meshes of n_cells * dim) */
   int32_t tiled;               /* 1: cells ordered in compact tiles of 256 and the LDS-staged kernels run */
   int32_t tile_halo_max;       /* largest number of outside neighbours of one tile (0 if not tiled) */
+  int64_t tile_halo_total;     /* sum over tiles of their outside neighbours (0 if not tiled) */
+  int64_t tile_incoming_total; /* sum over tiles of the faces they take from an earlier tile */
 } jfnk_mesh_info;
 
 /* Build the mesh handle: validates the mesh, renumbers cells, computes the

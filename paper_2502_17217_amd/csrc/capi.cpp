@@ -316,6 +316,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   in.n_dof_external = m.n_ext_cells * dim;
   in.tiled = d.tiled;
   in.tile_halo_max = int32_t(ua.halo_max);
+  in.tile_halo_total = int64_t(ua.halo_cells.size());
+  in.tile_incoming_total = int64_t(ua.in_face.size());
   in.setup_ms = now_ms() - t0;
 }
 

@@ -47,7 +47,8 @@ class jfnk_mesh_info(C.Structure):
                 ("n_internal_faces", C.c_int64), ("n_boundary_faces", C.c_int64),
                 ("bandwidth", C.c_int64), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
                 ("n_slots", C.c_int64), ("n_segments", C.c_int32), ("n_dof_external", C.c_int64),
-                ("tiled", C.c_int32), ("tile_halo_max", C.c_int32)]
+                ("tiled", C.c_int32), ("tile_halo_max", C.c_int32), ("tile_halo_total", C.c_int64),
+                ("tile_incoming_total", C.c_int64)]
 
 
 class jfnk_gmres_opts(C.Structure):
