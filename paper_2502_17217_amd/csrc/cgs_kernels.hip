@@ -68,12 +68,18 @@ __device__ __forceinline__ void tile_dots(const SegLayout& L, const double* __re
   }
 }
 
+// Tile partial sums are stored column-major, partials[col * n_blocks + tile],
+// so that a segment's tiles of one column are contiguous.
+__device__ __forceinline__ size_t pidx(const SegLayout& L, int col, int tile) {
+  return size_t(col) * L.n_blocks + tile;
+}
+
 // Segment sum of partial column col over tiles first .. first+n-1 (n <= 64),
 // one tile per lane and a fixed butterfly; valid in every lane of the wave.
-__device__ __forceinline__ double segment_column_sum(const double* __restrict__ partials, int first, int n,
-                                                     int col) {
+__device__ __forceinline__ double segment_column_sum(const SegLayout& L, const double* __restrict__ partials,
+                                                     int first, int n, int col) {
   const int lane = threadIdx.x & 63;
-  const double x = lane < n ? partials[size_t(first + lane) * kMaxBasis + col] : 0.0;
+  const double x = lane < n ? partials[pidx(L, col, first + lane)] : 0.0;
   return wave_sum(x);
 }
 
@@ -92,11 +98,11 @@ __device__ __forceinline__ void tile_norm2(const SegLayout& L, const double* __r
 
 // partials[blk][k] = fixed-order sum of the four wavefront sums, k < ncol
 // (after a barrier).
-__device__ __forceinline__ void store_tile_sums(double (*wsum)[kMaxBasis], int ncol, double* __restrict__ partials,
-                                                int blk) {
+__device__ __forceinline__ void store_tile_sums(const SegLayout& L, double (*wsum)[kMaxBasis], int ncol,
+                                                double* __restrict__ partials, int blk) {
   __syncthreads();
   for (int k = threadIdx.x; k < ncol; k += kBlock)
-    partials[size_t(blk) * kMaxBasis + k] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+    partials[pidx(L, k, blk)] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
 }
 
 // Passes 1 and 2.  coef == nullptr: pass 1 (also |w|^2 into column nk,
@@ -116,14 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_cgs_pass(SegLayout L, const double* 
   tile_dots(L, V, ldv, nk, w, c, wsum);
   const int ncol = coef == nullptr ? nk + 1 : nk;
   if (coef == nullptr) tile_norm2(L, w, c, wsum, nk);
-  store_tile_sums(wsum, ncol, partials, blk);
+  store_tile_sums(L, wsum, ncol, partials, blk);
   int first, n;
   if (!small_segment(L, seg, first, n)) return;
   if (!last_tile_of_segment(tickets + seg, n)) return;
   // each wavefront finishes every fourth column
   const int wave = threadIdx.x >> 6;
   for (int k = wave; k < ncol; k += 4) {
-    const double t = segment_column_sum(partials, first, n, k);
+    const double t = segment_column_sum(L, partials, first, n, k);
     if ((threadIdx.x & 63) == 0) {
       if (k < nk)
         out[size_t(seg) * kMaxBasis + k] = t;
@@ -150,12 +156,12 @@ __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* 
   const int c = blk * kFvBlock + threadIdx.x;
   if (c < L.n_cells) combine_cell(L, V, ldv, nk, h2 + size_t(seg) * kMaxBasis, w, c);
   tile_norm2(L, w, c, wsum, 0);
-  store_tile_sums(wsum, 1, partials, blk);
+  store_tile_sums(L, wsum, 1, partials, blk);
   int first, n;
   if (!small_segment(L, seg, first, n)) return;
   if (!last_tile_of_segment(tickets + seg, n)) return;
   if (threadIdx.x >= 64) return;
-  const double t = segment_column_sum(partials, first, n, 0);
+  const double t = segment_column_sum(L, partials, first, n, 0);
   if (threadIdx.x != 0) return;
   nrm[4 * seg] = t;
   if (!finish) return;
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const doub
   int first, n;
   if (small_segment(L, seg, first, n)) return;
   double s = 0;
-  for (int b = first + threadIdx.x; b < first + n; b += kBlock) s += partials[size_t(b) * kMaxBasis + col0 + k];
+  for (int b = first + threadIdx.x; b < first + n; b += kBlock) s += partials[pidx(L, col0 + k, b)];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) out[size_t(seg) * ldo + k] = s;
 }
@@ -208,13 +214,13 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
   const int c = blk * kFvBlock + threadIdx.x;
   tile_norm2(L, u, c, wsum, 0);
   tile_norm2(L, v, c, wsum, 1);
-  store_tile_sums(wsum, 2, partials, blk);
+  store_tile_sums(L, wsum, 2, partials, blk);
   int first, n;
   if (!small_segment(L, seg, first, n)) return;
   if (!last_tile_of_segment(tickets + seg, n)) return;
   if (threadIdx.x >= 64) return;
-  const double tu = segment_column_sum(partials, first, n, 0);
-  const double tv = segment_column_sum(partials, first, n, 1);
+  const double tu = segment_column_sum(L, partials, first, n, 0);
+  const double tv = segment_column_sum(L, partials, first, n, 1);
   if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
 }
 
@@ -227,8 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_eps_large(SegLayout L, const double*
   if (small_segment(L, seg, first, n)) return;
   double su = 0, sv = 0;
   for (int b = first + threadIdx.x; b < first + n; b += kBlock) {
-    su += partials[size_t(b) * kMaxBasis];
-    sv += partials[size_t(b) * kMaxBasis + 1];
+    su += partials[pidx(L, 0, b)];
+    sv += partials[pidx(L, 1, b)];
   }
   su = block_sum(su, sh);
   sv = block_sum(sv, sh);

@@ -235,6 +235,28 @@ struct GradLds {
 // Least-squares gradient of cell c (Eq. leastSquaresGrad with the weight
 // |Gamma_f| in the sum and in G_P) and its record {w, grad w}.  ids holds
 // the neighbour ids of the slots in the source's numbering; self is c's id.
+// Neighbour ids and |Gamma_f| of one chunk of a cell's slots.
+struct GradChunk {
+  int nb[kChunk];
+  double mg[kChunk];
+};
+
+__device__ __forceinline__ void load_grad_chunk(const MeshDev& m, const int32_t* __restrict__ ids, int s0,
+                                                int width, int lane, int k0, GradChunk& gc) {
+  int fc[kChunk];
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int idx = s0 + (k0 + k) * kSlice + lane;
+    gc.nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
+    fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
+    gc.mg[k] = gc.nb[k] >= 0 ? m.magG[f] : 0.0;
+  }
+}
+
 template <int D, class Src>
 __device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, const int32_t* __restrict__ ids,
                                               int self, int c, double* __restrict__ rec) {
@@ -250,19 +272,14 @@ __device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, 
   const int s0 = m.slice_ptr[slice];
   const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
   for (int k0 = 0; k0 < width; k0 += kChunk) {
-    int nb[kChunk], fc[kChunk];
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      const int idx = s0 + (k0 + k) * kSlice + lane;
-      nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
-      fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
-    }
-    double mg[kChunk], xN[kChunk][D], wN[kChunk][D];
+    GradChunk gc;
+    load_grad_chunk(m, ids, s0, width, lane, k0, gc);
+    const int* nb = gc.nb;
+    const double* mg = gc.mg;
+    double xN[kChunk][D], wN[kChunk][D];
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       const int nn = nb[k] >= 0 ? nb[k] : self;
-      const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
-      mg[k] = nb[k] >= 0 ? m.magG[f] : 0.0;
       src.get(nn, wN[k], xN[k]);
     }
 #pragma unroll
@@ -367,6 +384,7 @@ __global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const do
     const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
     const int base = tile * kFvBlock;
     const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    const int c = base + threadIdx.x;
     for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
       const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
       double w[D], x[D];
@@ -384,7 +402,6 @@ __global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const do
       }
     }
     __syncthreads();
-    const int c = base + threadIdx.x;
     if (c < n) {
       if (c - m.seg[seg].cell_off >= m.seg[seg].n_cells) {
         zero_rec<D>(rec, n, c);
