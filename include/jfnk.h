@@ -135,6 +135,10 @@ typedef struct {
   int32_t tile_halo_max;       /* largest number of outside neighbours of one tile (0 if not tiled) */
   int64_t tile_halo_total;     /* sum over tiles of their outside neighbours (0 if not tiled) */
   int64_t tile_incoming_total; /* sum over tiles of the faces they take from an earlier tile */
+  int32_t tile_ring2_max;      /* largest second ring of a tile: outside cells adjacent to its halo */
+  int64_t tile_ring2_total;    /* sum over tiles of their second rings */
+  int32_t tile_faces_max;      /* largest number of internal faces touching one tile */
+  int32_t fused;               /* 1: the single-pass J.v kernel fits (tile, two rings and faces in LDS) */
 } jfnk_mesh_info;
 
 /* Build the mesh handle: validates the mesh, renumbers cells, computes the
@@ -256,7 +260,8 @@ jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, dou
  * evaluation on this mesh records HIP events around each of its kernels on
  * the caller's stream.  jfnk_profile_read() waits for the recorded events and
  * returns accumulated milliseconds and launch counts per kernel class:
- * [0] step-size norms, [1] gradient pass, [2] flux/divergence pass,
+ * [0] step-size norms, [1] gradient pass, [2] flux/divergence pass (or the
+ * fused single pass, which has no separate gradient pass),
  * [3] preconditioner, then optionally resets.  Not for concurrent callers. */
 jfnk_status jfnk_profile_enable(jfnk_mesh* mesh, int32_t on);
 jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms /*[4]*/, int64_t* calls /*[4]*/,
@@ -345,15 +350,16 @@ jfnk_status jfnk_server_destroy(jfnk_server* srv);
  * jfnk_autotune times, on this handle's own mesh (or batch) and state u
  * (device, internal layout, load factor `load`), the launch shapes and
  * schedules that give identical results and keeps the fastest in the
- * handle: the cell passes of J v (LDS-staged tiles or direct gathers; one
- * workgroup per tile or a persistent grid), and the Arnoldi schedule
+ * handle: the cell passes of J v (one fused pass per tile, LDS-staged
+ * gradient and flux passes, or direct gathers; one workgroup per tile or a
+ * persistent grid), and the Arnoldi schedule
  * (steps per host check, HIP-graph replay) on one GMRES solve of
  * J x = -R(u) with `opts`.  Later solves use the choice when their options
  * ask for the handle's values (step_chunk = 0, graphs = 2).  d_work: a
  * solve workspace (op 1) for opts.restart and opts.precond.  The report
  * (may be NULL) lists every candidate and its time. */
 typedef struct {
-  int32_t lds_kernels;         /* chosen: 1 LDS-staged cell passes, 0 gathers */
+  int32_t lds_kernels;         /* chosen cell passes: 2 fused, 1 LDS-staged, 0 gathers */
   int32_t persist;             /* chosen: workgroups of a persistent launch (0: one per tile) */
   int32_t step_chunk;          /* chosen Arnoldi steps per host check */
   int32_t graphs;              /* chosen: 1 replay step runs from HIP graphs */
@@ -367,6 +373,16 @@ typedef struct {
 
 jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const double* d_u, double load,
                           void* d_work, void* stream, jfnk_tune_report* report);
+
+/* Sets the cell passes of R(u) and J v by hand (what jfnk_autotune
+ * chooses; every choice gives the same bits): passes 0 = direct gathers,
+ * 1 = LDS-staged gradient and flux passes (mesh info `tiled`), 2 = one
+ * fused pass per tile that recomputes the halo's gradients from a two-ring
+ * copy in LDS (mesh info `fused`); persist = workgroups of a persistent
+ * launch (0: one per tile; rounded up to a multiple of 8).  Call it between
+ * solves, not while one runs on the handle.  Errors: JFNK_E_ARG (null mesh,
+ * passes outside 0..2 or not supported by the mesh, persist < 0). */
+jfnk_status jfnk_set_cell_passes(jfnk_mesh* mesh, int32_t passes, int32_t persist);
 
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* jfnk_last_error(void);

@@ -115,8 +115,10 @@ size_t device_bytes_of(const HostMesh& h) {
          // tiles: slot_loc, halo_ptr and at most one halo entry per slot
          // tiles: slot_loc, slot_lf, halo and incoming-face lists (at most one entry per slot each),
          // per-tile offsets, packed face positions
-         (h.tiled ? 3 * b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 2) + 3 * b(size_t(h.n_cells / kFvBlock + 2) * 4) +
-                        b(size_t(h.n_int) * 4)
+         (h.tiled ? 3 * b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 2) + 4 * b(size_t(h.n_cells / kFvBlock + 2) * 4) +
+                        b(size_t(h.n_int) * 4) +
+                        // second ring (at most one entry per slot) and the halo cells' slot lists
+                        b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 6)
                   : 0);
 }
 
@@ -246,6 +248,10 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     upload(m.b_in_ptr, ua.in_ptr, s);
     upload(m.b_in_face, ua.in_face, s);
     upload(m.b_in_loc, ua.in_loc, s);
+    upload(m.b_h2_ptr, ua.h2_ptr, s);
+    upload(m.b_h2_cells, ua.h2_cells, s);
+    upload(m.b_h1_loc, ua.h1_loc, s);
+    upload(m.b_h1_face, ua.h1_face, s);
   }
   JFNK_HIP(hipStreamSynchronize(s));
   const int S = m.n_seg();
@@ -298,6 +304,13 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.face_stride = int32_t(std::max<int64_t>(ua.faces_max, 1));
   // the deduplicating LDS flux pass needs its staged tile and face forces in LDS
   if (d.tiled && flux_lds_bytes(dim, d.halo_stride, d.face_stride) > size_t(kFluxLdsBytes) * 2) d.lds_kernels = 0;
+  d.h1_width = int32_t(ua.h1_width);
+  d.ring_stride = int32_t(kFvBlock + ua.halo_max + ua.h2_max);
+  d.h2_ptr = h.tiled ? m.b_h2_ptr.as<int32_t>() : nullptr;
+  d.h2_cells = h.tiled ? m.b_h2_cells.as<int32_t>() : nullptr;
+  d.h1_loc = h.tiled ? m.b_h1_loc.as<int16_t>() : nullptr;
+  d.h1_face = h.tiled ? m.b_h1_face.as<int32_t>() : nullptr;
+  d.fused = (d.tiled && fused_fits(dim, ua)) ? 1 : 0;
   jfnk_mesh_info& in = m.info;
   in.n_cells = h.n_cells;
   in.dim = dim;
@@ -310,7 +323,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
                             m.b_ext.bytes + m.b_pc_dinv.bytes + m.b_seg_of_block.bytes + m.b_seg.bytes +
                             m.b_block_first.bytes + m.b_slot_loc.bytes + m.b_halo_ptr.bytes +
                             m.b_halo_cells.bytes + m.b_slot_lf.bytes + m.b_fbeg.bytes + m.b_face_loc.bytes +
-                            m.b_in_ptr.bytes + m.b_in_face.bytes + m.b_in_loc.bytes);
+                            m.b_in_ptr.bytes + m.b_in_face.bytes + m.b_in_loc.bytes + m.b_h2_ptr.bytes +
+                            m.b_h2_cells.bytes + m.b_h1_loc.bytes + m.b_h1_face.bytes);
   in.n_slots = int64_t(ua.slot_nb.size());
   in.n_segments = S;
   in.n_dof_external = m.n_ext_cells * dim;
@@ -318,6 +332,10 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   in.tile_halo_max = int32_t(ua.halo_max);
   in.tile_halo_total = int64_t(ua.halo_cells.size());
   in.tile_incoming_total = int64_t(ua.in_face.size());
+  in.tile_ring2_max = int32_t(ua.h2_max);
+  in.tile_ring2_total = int64_t(ua.h2_cells.size());
+  in.tile_faces_max = int32_t(ua.faces_max);
+  in.fused = d.fused;
   in.setup_ms = now_ms() - t0;
 }
 
@@ -340,6 +358,21 @@ jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const do
     const hipStream_t s = solver_stream(mesh, caller, true);
     autotune(mesh, *opts, d_u, load, d_work, s, report);
     join_stream(mesh, caller, s);
+  });
+}
+
+jfnk_status jfnk_set_cell_passes(jfnk_mesh* mesh, int32_t passes, int32_t persist) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(passes >= 0 && passes <= 2, JFNK_E_ARG, "set_cell_passes: passes must be 0, 1 or 2");
+    JFNK_REQUIRE(passes == 0 || mesh->dev.tiled, JFNK_E_ARG, "set_cell_passes: the mesh is not tile-ordered");
+    JFNK_REQUIRE(passes < 2 || mesh->dev.fused, JFNK_E_ARG,
+                 "set_cell_passes: the fused pass does not fit this mesh's tiles");
+    JFNK_REQUIRE(persist >= 0, JFNK_E_ARG, "set_cell_passes: persist < 0");
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
+    mesh->graphs.clear();  // captured runs hold the old launches
+    mesh->dev.lds_kernels = passes;
+    mesh->dev.persist = persist;
   });
 }
 
@@ -407,6 +440,21 @@ jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* m
     info->n_dof_external = h.n_cells * h.dim;
     info->tiled = h.tiled ? 1 : 0;
     info->tile_halo_max = int32_t(h.tile_halo_max);
+    if (h.tiled) {
+      // the tile lists the device handle would build, host side only
+      jfnk_mesh tmp;
+      tmp.segs.resize(1);
+      tmp.segs[0].host = h;
+      tmp.segs[0].mat = mt;
+      UnionArrays ua;
+      build_union(tmp, ua);
+      info->tile_halo_total = int64_t(ua.halo_cells.size());
+      info->tile_incoming_total = int64_t(ua.in_face.size());
+      info->tile_ring2_max = int32_t(ua.h2_max);
+      info->tile_ring2_total = int64_t(ua.h2_cells.size());
+      info->tile_faces_max = int32_t(ua.faces_max);
+      info->fused = fused_fits(h.dim, ua) ? 1 : 0;
+    }
     for (int64_t i = 0; i < h.n_cells; ++i) {
       const int64_t o = h.old_of_new[i];
       if (xc_out)

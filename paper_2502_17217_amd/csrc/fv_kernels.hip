@@ -86,6 +86,27 @@ __device__ __forceinline__ void traction_le(const Law& m, const double (&g)[D][D
   }
 }
 
+// J^(-1/3) of the neo-Hookean laws: a single-precision seed 2^(-log2|J|/3)
+// with the sign of J, then two Newton corrections in FP64,
+// y <- y + y (1 - J y^3)/3, which leave y within about one ulp (quadratic
+// convergence from ~22 correct bits); J^(-2/3) = y^2 and 1/J = y^3 then
+// cost two products instead of a cube root and two divisions.
+__device__ __forceinline__ double inv_cbrt(double J) {
+#if JFNK_CBRT_LIB
+  return 1.0 / cbrt(J);
+#endif
+  const float a = fabsf(float(J));
+  double y = double(__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(a) * (1.0f / 3.0f)));
+  y = J < 0.0 ? -y : y;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double y3 = (y * y) * y;
+    const double r = fma(-J, y3, 1.0);
+    y = fma(y, r * (1.0 / 3.0), y);
+  }
+  return y;
+}
+
 __device__ __forceinline__ void traction_nh3(const Law& m, const double (&g)[3][3],
                                              const double (&G)[3], double (&t)[3]) {
   double F[3][3];
@@ -112,9 +133,9 @@ __device__ __forceinline__ void traction_nh3(const Law& m, const double (&g)[3][
 #pragma unroll
     for (int k = 0; k < 3; ++k) trb = fma(F[i][k], F[i][k], trb);
   }
-  const double cj = cbrt(J);
-  const double Jm23 = 1.0 / (cj * cj);
-  const double invJ = 1.0 / J;
+  const double y = inv_cbrt(J);
+  const double Jm23 = y * y;
+  const double invJ = Jm23 * y;
   const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
   const double cf = m.mu * Jm23;
 #pragma unroll
@@ -131,9 +152,9 @@ __device__ __forceinline__ void traction_nh2(const Law& m, const double (&g)[2][
   const double FG0 = F00 * G[0] + F01 * G[1];
   const double FG1 = F10 * G[0] + F11 * G[1];
   const double trb = F00 * F00 + F01 * F01 + F10 * F10 + F11 * F11 + 1.0;
-  const double cj = cbrt(J);
-  const double Jm23 = 1.0 / (cj * cj);
-  const double invJ = 1.0 / J;
+  const double y = inv_cbrt(J);
+  const double Jm23 = y * y;
+  const double invJ = Jm23 * y;
   const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
   const double cf = m.mu * Jm23;
   t[0] = fma(cf, FG0, ca * a0);
@@ -232,48 +253,73 @@ struct GradLds {
   }
 };
 
-// Least-squares gradient of cell c (Eq. leastSquaresGrad with the weight
-// |Gamma_f| in the sum and in G_P) and its record {w, grad w}.  ids holds
-// the neighbour ids of the slots in the source's numbering; self is c's id.
 // Neighbour ids and |Gamma_f| of one chunk of a cell's slots.
 struct GradChunk {
   int nb[kChunk];
   double mg[kChunk];
 };
 
-__device__ __forceinline__ void load_grad_chunk(const MeshDev& m, const int32_t* __restrict__ ids, int s0,
-                                                int width, int lane, int k0, GradChunk& gc) {
-  int fc[kChunk];
+// Slots of cell c in its slice of the mesh's slot arrays (ids in the
+// source's numbering).
+struct SliceSlots {
+  const int32_t* ids;
+  int s0, lane, width;
+  __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk& gc) const {
+    int fc[kChunk];
 #pragma unroll
-  for (int k = 0; k < kChunk; ++k) {
-    const int idx = s0 + (k0 + k) * kSlice + lane;
-    gc.nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
-    fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
-  }
+    for (int k = 0; k < kChunk; ++k) {
+      const int idx = s0 + (k0 + k) * kSlice + lane;
+      gc.nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
+      fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
+    }
 #pragma unroll
-  for (int k = 0; k < kChunk; ++k) {
-    const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
-    gc.mg[k] = gc.nb[k] >= 0 ? m.magG[f] : 0.0;
+    for (int k = 0; k < kChunk; ++k) {
+      const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
+      gc.mg[k] = gc.nb[k] >= 0 ? m.magG[f] : 0.0;
+    }
   }
-}
+};
 
-template <int D, class Src>
-__device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, const int32_t* __restrict__ ids,
-                                              int self, int c, double* __restrict__ rec) {
-  const int n = m.n_cells;
-  double wP[D], xP[D];
+// Slots of halo cell i of a tile in the tile's lists (slot-major over the
+// tile's nh halo cells: position in the tile's copy, face number), in the
+// slot order of the cell's own slice.
+struct HaloSlots {
+  const int16_t* loc;
+  const int32_t* face;
+  int nh, i, width;
+  __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk& gc) const {
+    int fc[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int idx = (k0 + k) * nh + i;
+      gc.nb[k] = (k0 + k < width) ? int(loc[idx]) : kSlotPad;
+      fc[k] = (k0 + k < width) ? face[idx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) gc.mg[k] = gc.nb[k] >= 0 ? m.magG[fc[k]] : 0.0;
+  }
+};
+
+// Least-squares gradient (Eq. leastSquaresGrad with the weight |Gamma_f| in
+// the sum and in G_P) of the cell with id self in the source, its slots read
+// from sl in slot order.  Returns w_P and grad w_P.
+template <int D, class Src, class Slots>
+__device__ __forceinline__ void lsq_gradient(const MeshDev& m, const Src& src, const Slots& sl, int self,
+                                             double (&wP)[D], double (&g)[D][D],
+                                             const GradChunk* first = nullptr) {
+  double xP[D];
   src.get(self, wP, xP);
   double Gs[D][D], M[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) Gs[i][j] = M[i][j] = 0.0;
-  const int slice = c / kSlice, lane = c % kSlice;
-  const int s0 = m.slice_ptr[slice];
-  const int width = (m.slice_ptr[slice + 1] - s0) / kSlice;
-  for (int k0 = 0; k0 < width; k0 += kChunk) {
+  for (int k0 = 0; k0 < sl.width; k0 += kChunk) {
     GradChunk gc;
-    load_grad_chunk(m, ids, s0, width, lane, k0, gc);
+    if (k0 == 0 && first != nullptr)
+      gc = *first;
+    else
+      sl.load(m, k0, gc);
     const int* nb = gc.nb;
     const double* mg = gc.mg;
     double xN[kChunk][D], wN[kChunk][D];
@@ -303,7 +349,6 @@ __device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, 
       }
     }
   }
-  double g[D][D];
   if constexpr (D == 3) {
     const double a00 = Gs[1][1] * Gs[2][2] - Gs[1][2] * Gs[1][2];
     const double a01 = Gs[0][2] * Gs[1][2] - Gs[0][1] * Gs[2][2];
@@ -325,6 +370,19 @@ __device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, 
       g[1][j] = (-Gs[0][1] * M[0][j] + Gs[0][0] * M[1][j]) * inv;
     }
   }
+}
+
+// Gradient of cell c and its record {w, grad w}; ids holds the neighbour
+// ids of the slots in the source's numbering and self is c's id.
+template <int D, class Src>
+__device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, const int32_t* __restrict__ ids,
+                                              int self, int c, double* __restrict__ rec) {
+  const int n = m.n_cells;
+  const int slice = c / kSlice, lane = c % kSlice;
+  const int s0 = m.slice_ptr[slice];
+  const SliceSlots sl{ids, s0, lane, (m.slice_ptr[slice + 1] - s0) / kSlice};
+  double wP[D], g[D][D];
+  lsq_gradient<D>(m, src, sl, self, wP, g);
 #pragma unroll
   for (int k = 0; k < D; ++k) rec[size_t(k) * n + c] = wP[k];
 #pragma unroll
@@ -371,7 +429,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_gradient(MeshDev
 // neighbour is read from LDS.  Exits before the barrier are uniform over the
 // workgroup.
 template <int D>
-__global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const double* __restrict__ u,
+__global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_gradient_tiled(MeshDev m, const double* __restrict__ u,
                                                              const double* __restrict__ v, SegScalars sc,
                                                              double* __restrict__ rec, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
@@ -385,16 +443,37 @@ __global__ __launch_bounds__(kFvBlock) void k_gradient_tiled(MeshDev m, const do
     const int base = tile * kFvBlock;
     const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
     const int c = base + threadIdx.x;
-    for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
-      const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
-      double w[D], x[D];
-      if (cg < n) {
-        load_w<D>(u, v, eps, n, cg, w);
-        load_soa<D>(m.xc, n, cg, x);
-      } else {
+    // the tile and the first kFvBlock halo cells in one round trip
+    {
+      const int cg0 = c, cg1 = threadIdx.x < nh ? m.halo_cells[h0 + threadIdx.x] : n;
+      double w0[D], x0[D], w1[D], x1[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) w[k] = x[k] = 0.0;
+      for (int k = 0; k < D; ++k) w0[k] = x0[k] = w1[k] = x1[k] = 0.0;
+      if (cg0 < n) {
+        load_w<D>(u, v, eps, n, cg0, w0);
+        load_soa<D>(m.xc, n, cg0, x0);
       }
+      if (cg1 < n) {
+        load_w<D>(u, v, eps, n, cg1, w1);
+        load_soa<D>(m.xc, n, cg1, x1);
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        lds[k * S + threadIdx.x] = w0[k];
+        lds[(D + k) * S + threadIdx.x] = x0[k];
+      }
+      if (threadIdx.x < nh)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          lds[k * S + kFvBlock + threadIdx.x] = w1[k];
+          lds[(D + k) * S + kFvBlock + threadIdx.x] = x1[k];
+        }
+    }
+    for (int i = threadIdx.x + 2 * kFvBlock; i < kFvBlock + nh; i += kFvBlock) {
+      const int cg = m.halo_cells[h0 + i - kFvBlock];
+      double w[D], x[D];
+      load_w<D>(u, v, eps, n, cg, w);
+      load_soa<D>(m.xc, n, cg, x);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         lds[k * S + i] = w[k];
@@ -629,20 +708,70 @@ __device__ __forceinline__ void load_faces(const MeshDev& m, int tile, int e0, F
   }
 }
 
-// Phase A: the loaded faces, owner first (the canonical operand order).
-template <int D, int LAW>
-__device__ __forceinline__ void face_forces(const SegInfo& si, const FluxLds<D>& src, int e0, const FaceBatch<D>& fb,
+// Phase A: entry j of the loaded faces, owner first (the canonical operand
+// order).
+template <int D, int LAW, class Src>
+__device__ __forceinline__ void one_face_force(const Law& law, const Src& src, const FaceBatch<D>& fb, int j,
+                                               double (&fo)[D]) {
+  double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D];
+  src.get(fb.lo[j], wA, gA, xA);
+  src.get(fb.ln[j], wB, gB, xB);
+  internal_face_force<D, LAW>(law, fb.G[j], fb.wf[j], xA, xB, wA, wB, gA, gB, fo);
+#if JFNK_FACE_SCHED_BARRIER
+  // one neo-Hookean face's operands live at a time: keeps the passes at
+  // two waves per SIMD
+  if constexpr (LAW == JFNK_NEO_HOOKEAN) __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// All loaded faces into registers.
+template <int D, int LAW, class Src>
+__device__ __forceinline__ void face_forces_reg(const SegInfo& si, const Src& src, const FaceBatch<D>& fb,
+                                                double (&fo)[kEnt][D]) {
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+#pragma unroll
+  for (int j = 0; j < kEnt; ++j) {
+    if (j >= fb.n) break;
+    one_face_force<D, LAW>(law, src, fb, j, fo[j]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void store_face_forces(const FaceBatch<D>& fb, const double (&fo)[kEnt][D], int e0,
+                                                  double* __restrict__ ff, int fs) {
+#pragma unroll
+  for (int j = 0; j < kEnt; ++j) {
+    if (j >= fb.n) break;
+#pragma unroll
+    for (int q = 0; q < D; ++q) ff[q * fs + e0 + j * kFvBlock] = fo[j][q];
+  }
+}
+
+// All loaded faces into the face-force rows, each stored when computed.
+template <int D, int LAW, class Src>
+__device__ __forceinline__ void face_forces(const SegInfo& si, const Src& src, int e0, const FaceBatch<D>& fb,
                                             double* __restrict__ ff, int fs) {
   const Law law{si.mu, si.lam, si.kappa, si.aK};
 #pragma unroll
   for (int j = 0; j < kEnt; ++j) {
     if (j >= fb.n) break;
-    double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D], fo[D];
-    src.get(fb.lo[j], wA, gA, xA);
-    src.get(fb.ln[j], wB, gB, xB);
-    internal_face_force<D, LAW>(law, fb.G[j], fb.wf[j], xA, xB, wA, wB, gA, gB, fo);
+    double fo[D];
+    one_face_force<D, LAW>(law, src, fb, j, fo);
 #pragma unroll
     for (int q = 0; q < D; ++q) ff[q * fs + e0 + j * kFvBlock] = fo[q];
+  }
+}
+
+template <int D, int LAWSEL, class Src>
+__device__ __forceinline__ void face_forces_sel(const SegInfo& si, const Src& src, const FaceBatch<D>& fb,
+                                                double (&fo)[kEnt][D]) {
+  if constexpr (LAWSEL == kLawMixed) {
+    if (si.law == JFNK_NEO_HOOKEAN)
+      face_forces_reg<D, JFNK_NEO_HOOKEAN>(si, src, fb, fo);
+    else
+      face_forces_reg<D, JFNK_LINEAR_ELASTIC>(si, src, fb, fo);
+  } else {
+    face_forces_reg<D, LAWSEL>(si, src, fb, fo);
   }
 }
 
@@ -664,14 +793,14 @@ __device__ __forceinline__ void load_slots(const MeshDev& m, int s0, int width, 
   }
 }
 
-// first: the cell's first chunk of slots, loaded before the tile's barriers
+// first: the cell's first chunk of slots, loaded before the tile's
+// barriers; wP, gP: the cell's own w and gradient.
 template <int D, int LAW>
-__device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& si, const FluxLds<D>& src, int self,
-                                              int c, double load, const double* __restrict__ ff, int fs,
-                                              const SlotChunk& first, double (&R)[D]) {
+__device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& si, const double (&wP)[D],
+                                              const double (&gP)[D][D], int c, double load,
+                                              const double* __restrict__ ff, int fs, const SlotChunk& first,
+                                              double (&R)[D]) {
   const Law law{si.mu, si.lam, si.kappa, si.aK};
-  double wP[D], xP[D], gP[D][D];
-  src.get(self, wP, gP, xP);
 #pragma unroll
   for (int q = 0; q < D; ++q) R[q] = 0.0;
   const int slice = c / kSlice, lane = c % kSlice;
@@ -699,6 +828,33 @@ __device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& s
   }
 }
 
+// Phase B of cell c and its output: R(w), or (R(w) - R(u))/eps when jv.
+template <int D, int LAWSEL>
+__device__ __forceinline__ void cell_sum_out(const MeshDev& m, const SegInfo& si, const double (&wP)[D],
+                                             const double (&gP)[D][D], int c, double load,
+                                             const double* __restrict__ ff, int fs, const SlotChunk& first,
+                                             double eps, bool jv, const double (&ru)[D],
+                                             double* __restrict__ out) {
+  const int n = m.n_cells;
+  double R[D];
+  if constexpr (LAWSEL == kLawMixed) {
+    if (si.law == JFNK_NEO_HOOKEAN)
+      tile_cell_sum<D, JFNK_NEO_HOOKEAN>(m, si, wP, gP, c, load, ff, fs, first, R);
+    else
+      tile_cell_sum<D, JFNK_LINEAR_ELASTIC>(m, si, wP, gP, c, load, ff, fs, first, R);
+  } else {
+    tile_cell_sum<D, LAWSEL>(m, si, wP, gP, c, load, ff, fs, first, R);
+  }
+  if (jv) {
+    const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - ru[q]) * ie : 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
+  }
+}
+
 // Tiled flux pass.  The records and centroids of the tile's cells and halo
 // are staged in LDS (rows of length halo_stride).  Phase A evaluates every
 // internal face touching the tile once, spread evenly over the workgroup
@@ -707,7 +863,7 @@ __device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& s
 // gather pass, so both give the same bits.  Exits before a barrier are
 // uniform over the workgroup.
 template <int D, int LAWSEL>
-__global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
+__global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
                                                          SegScalars sc, const double* __restrict__ Ru,
                                                          double* __restrict__ out, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
@@ -737,17 +893,36 @@ __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double
 #pragma unroll
         for (int q = 0; q < D; ++q) ru[q] = Ru[size_t(q) * n + c];
     }
-    for (int i = threadIdx.x; i < kFvBlock + nh; i += kFvBlock) {
-      const int cg = i < kFvBlock ? base + i : m.halo_cells[h0 + i - kFvBlock];
-      if (cg < n) {
+    // the tile and the first kFvBlock halo cells in one round trip
+    {
+      const int cg0 = c, cg1 = threadIdx.x < nh ? m.halo_cells[h0 + threadIdx.x] : n;
+      double r0[kRows], r1[kRows];
 #pragma unroll
-        for (int r = 0; r < D + D * D; ++r) lds[r * S + i] = rec[size_t(r) * n + cg];
+      for (int r = 0; r < kRows; ++r) r0[r] = r1[r] = 0.0;
+      if (cg0 < n) {
 #pragma unroll
-        for (int k = 0; k < D; ++k) lds[(D + D * D + k) * S + i] = m.xc[size_t(k) * n + cg];
-      } else {
+        for (int r = 0; r < D + D * D; ++r) r0[r] = rec[size_t(r) * n + cg0];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) lds[r * S + i] = 0.0;
+        for (int k = 0; k < D; ++k) r0[D + D * D + k] = m.xc[size_t(k) * n + cg0];
       }
+      if (cg1 < n) {
+#pragma unroll
+        for (int r = 0; r < D + D * D; ++r) r1[r] = rec[size_t(r) * n + cg1];
+#pragma unroll
+        for (int k = 0; k < D; ++k) r1[D + D * D + k] = m.xc[size_t(k) * n + cg1];
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) lds[r * S + threadIdx.x] = r0[r];
+      if (threadIdx.x < nh)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) lds[r * S + kFvBlock + threadIdx.x] = r1[r];
+    }
+    for (int i = threadIdx.x + 2 * kFvBlock; i < kFvBlock + nh; i += kFvBlock) {
+      const int cg = m.halo_cells[h0 + i - kFvBlock];
+#pragma unroll
+      for (int r = 0; r < D + D * D; ++r) lds[r * S + i] = rec[size_t(r) * n + cg];
+#pragma unroll
+      for (int k = 0; k < D; ++k) lds[(D + D * D + k) * S + i] = m.xc[size_t(k) * n + cg];
     }
     __syncthreads();
     const SegInfo& si = m.seg[seg];
@@ -769,25 +944,177 @@ __global__ __launch_bounds__(kFvBlock) void k_flux_tiled(MeshDev m, const double
     __syncthreads();
     if (c < n) {
       if (c - si.cell_off < si.n_cells) {
-        const double load = sc.load[seg];
-        double R[D];
-        if constexpr (LAWSEL == kLawMixed) {
-          if (si.law == JFNK_NEO_HOOKEAN)
-            tile_cell_sum<D, JFNK_NEO_HOOKEAN>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
-          else
-            tile_cell_sum<D, JFNK_LINEAR_ELASTIC>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
-        } else {
-          tile_cell_sum<D, LAWSEL>(m, si, src, threadIdx.x, c, load, ff, fs, first, R);
-        }
-        if (Ru != nullptr) {
-          const double eps = sc.eps[seg];
-          const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
+        double wP[D], xP[D], gP[D][D];
+        src.get(threadIdx.x, wP, gP, xP);
+        cell_sum_out<D, LAWSEL>(m, si, wP, gP, c, sc.load[seg], ff, fs, first, Ru ? sc.eps[seg] : 0.0, Ru != nullptr,
+                                ru, out);
+      } else {
 #pragma unroll
-          for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = eps != 0.0 ? (R[q] - ru[q]) * ie : 0.0;
-        } else {
+        for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;  // alignment padding
+      }
+    }
+    __syncthreads();  // the LDS copy is rewritten for the next tile
+  }
+}
+
+// Fused J v pass: one workgroup per tile, nothing but the result written.
+// The tile, its halo and its second ring (the outside cells adjacent to the
+// halo) are staged in LDS as w = u + eps v and centroids (rows of length
+// ring_stride); the gradients of the tile's cells and of its halo cells are
+// computed from that copy into LDS (rows of length halo_stride), in the
+// same slot order as the gradient pass; then phase A and phase B of the
+// tiled flux pass follow, the face forces overwriting the w/centroid rows
+// once phase A has read them.  Every cell's gradient and every face force
+// is the same sequence of operations as in the two passes, so the result
+// is the same bits.  Exits before a barrier are uniform over the workgroup.
+template <int D>
+struct FusedLds {
+  const double* wx;  // [D][R] w, then [D][R] centroids
+  const double* g;   // [D*D][S] gradients
+  int R, S;
+  __device__ __forceinline__ void get(int j, double (&w)[D], double (&gr)[D][D], double (&x)[D]) const {
 #pragma unroll
-          for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = R[q];
+    for (int k = 0; k < D; ++k) w[k] = wx[k * R + j];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) gr[a][b] = g[(a * D + b) * S + j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = wx[(D + k) * R + j];
+  }
+};
+
+constexpr int kStageRounds = 3;
+
+template <int D, int LAWSEL>
+__global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(MeshDev m, const double* __restrict__ u,
+                                                                            const double* __restrict__ v,
+                                                                            SegScalars sc,
+                                                                            const double* __restrict__ Ru,
+                                                                            double* __restrict__ out, int nb_real,
+                                                                            int nb_launch, int wx_size) {
+  extern __shared__ double lds[];
+  const int n = m.n_cells, R = m.ring_stride, S = m.halo_stride, fs = m.face_stride, W = m.h1_width;
+  double* wx = lds;
+  double* gl = lds + wx_size;
+  double* ff = lds;  // face forces, over the w/centroid rows
+  for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
+    const int tile = xcd_block(it, nb_launch);
+    if (tile >= nb_real) continue;
+    const int seg = m.seg_of_block[tile];
+    if (sc.active != nullptr && sc.active[seg] == 0) continue;
+    const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
+    const int base = tile * kFvBlock;
+    const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    const int r0 = m.h2_ptr[tile], n2 = m.h2_ptr[tile + 1] - r0;
+    const int c = base + threadIdx.x;
+    const SegInfo& si = m.seg[seg];
+    const bool real = c < n && c - si.cell_off < si.n_cells;
+    // Staging, three rounds of the copy at once: indices, then every load,
+    // then the LDS writes, so that the copy waits for one round trip to
+    // memory after its indices.
+    const int total = kFvBlock + nh + n2;
+    int cg[kStageRounds];
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      const int i = threadIdx.x + r * kFvBlock;
+      cg[r] = i < kFvBlock        ? base + i
+              : i < kFvBlock + nh ? m.halo_cells[h0 + i - kFvBlock]
+              : i < total         ? m.h2_cells[r0 + i - kFvBlock - nh]
+                                  : n;
+    }
+    double sw[kStageRounds][D], sx[kStageRounds][D];
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      if (cg[r] < n) {
+        load_w<D>(u, v, eps, n, cg[r], sw[r]);
+        load_soa<D>(m.xc, n, cg[r], sx[r]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) sw[r][k] = sx[r][k] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kStageRounds; ++r) {
+      const int i = threadIdx.x + r * kFvBlock;
+      if (i < total) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          wx[k * R + i] = sw[r][k];
+          wx[(D + k) * R + i] = sx[r][k];
         }
+      }
+    }
+    for (int i = threadIdx.x + kStageRounds * kFvBlock; i < total; i += kFvBlock) {
+      const int cgi = i < kFvBlock + nh ? m.halo_cells[h0 + i - kFvBlock] : m.h2_cells[r0 + i - kFvBlock - nh];
+      double w[D], x[D];
+      load_w<D>(u, v, eps, n, cgi, w);
+      load_soa<D>(m.xc, n, cgi, x);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        wx[k * R + i] = w[k];
+        wx[(D + k) * R + i] = x[k];
+      }
+    }
+    __syncthreads();
+    // gradients of the tile's cells, then of its halo cells
+    const GradLds<D> gsrc{wx, R};
+    double wP[D];
+    {
+      double gP[D][D];
+      if (real) {
+        const int s0 = m.slice_ptr[c / kSlice];
+        const SliceSlots sl{m.slot_loc, s0, int(c % kSlice), (m.slice_ptr[c / kSlice + 1] - s0) / kSlice};
+        lsq_gradient<D>(m, gsrc, sl, threadIdx.x, wP, gP);
+      } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          wP[a] = 0.0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) gP[a][b] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) gl[(a * D + b) * S + threadIdx.x] = gP[a][b];
+    }
+    for (int i = threadIdx.x; i < nh; i += kFvBlock) {
+      const HaloSlots hi{m.h1_loc + size_t(h0) * W, m.h1_face + size_t(h0) * W, nh, i, W};
+      double wH[D], gH[D][D];
+      lsq_gradient<D>(m, gsrc, hi, kFvBlock + i, wH, gH);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) gl[(a * D + b) * S + kFvBlock + i] = gH[a][b];
+    }
+    // this lane's faces, in flight while the slower lanes finish
+    FaceBatch<D> fb;
+    load_faces<D>(m, tile, threadIdx.x, fb);
+    __syncthreads();
+    // phase A into registers; the face forces replace the w/centroid rows
+    // once every lane has read them
+    {
+      double fo[kEnt][D];
+      face_forces_sel<D, LAWSEL>(si, FusedLds<D>{wx, gl, R, S}, fb, fo);
+      __syncthreads();
+      store_face_forces<D>(fb, fo, threadIdx.x, ff, fs);
+    }
+    __syncthreads();
+    if (c < n) {
+      if (real) {
+        const int s0 = m.slice_ptr[c / kSlice];
+        SlotChunk first;
+        load_slots(m, s0, (m.slice_ptr[c / kSlice + 1] - s0) / kSlice, c % kSlice, 0, first);
+        double ru[D], gP[D][D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) ru[q] = Ru != nullptr ? Ru[size_t(q) * n + c] : 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) gP[a][b] = gl[(a * D + b) * S + threadIdx.x];
+        cell_sum_out<D, LAWSEL>(m, si, wP, gP, c, sc.load[seg], ff, fs, first, Ru ? sc.eps[seg] : 0.0,
+                                Ru != nullptr, ru, out);
       } else {
 #pragma unroll
         for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;  // alignment padding
@@ -841,7 +1168,38 @@ void flux_launch(const MeshDev& m, const double* rec, const SegScalars& sc, cons
   }
 }
 
+template <int D, int LAWSEL>
+void fused_launch(const MeshDev& m, const double* u, const double* v, const SegScalars& sc, const double* Ru,
+                  double* out, hipStream_t s) {
+  int nr, nl, g;
+  grid_for(m, nr, nl, g);
+  const int wx = fused_wx_doubles(D, m.ring_stride, m.face_stride);
+  const size_t lds = fused_lds_bytes(D, m.ring_stride, m.halo_stride, m.face_stride);
+  hipLaunchKernelGGL((k_jv_fused<D, LAWSEL>), dim3(g), dim3(kFvBlock), lds, s, m, u, v, sc, Ru, out, nr, nl, wx);
+}
+
 }  // namespace
+
+void launch_fused(const MeshDev& m, const double* u, const double* v, const SegScalars& sc, const double* Ru,
+                  double* out, hipStream_t s) {
+  const int mask = m.law_mask;
+  if (m.dim == 3) {
+    if (mask == 2)
+      fused_launch<3, JFNK_NEO_HOOKEAN>(m, u, v, sc, Ru, out, s);
+    else if (mask == 1)
+      fused_launch<3, JFNK_LINEAR_ELASTIC>(m, u, v, sc, Ru, out, s);
+    else
+      fused_launch<3, kLawMixed>(m, u, v, sc, Ru, out, s);
+  } else {
+    if (mask == 2)
+      fused_launch<2, JFNK_NEO_HOOKEAN>(m, u, v, sc, Ru, out, s);
+    else if (mask == 1)
+      fused_launch<2, JFNK_LINEAR_ELASTIC>(m, u, v, sc, Ru, out, s);
+    else
+      fused_launch<2, kLawMixed>(m, u, v, sc, Ru, out, s);
+  }
+  JFNK_HIP(hipGetLastError());
+}
 
 void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
                  hipStream_t s) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <shared_mutex>
 #include <string>
@@ -43,6 +44,14 @@ constexpr int kNumXcd = 8;
 #ifndef JFNK_FV_MINWAVES
 #define JFNK_FV_MINWAVES 1
 #endif
+// waves per SIMD the LDS-tiled cell passes are compiled for
+#ifndef JFNK_TILED_MINWAVES
+#define JFNK_TILED_MINWAVES 1
+#endif
+// scheduling barrier between the neo-Hookean face evaluations of a lane
+#ifndef JFNK_FACE_SCHED_BARRIER
+#define JFNK_FACE_SCHED_BARRIER 1
+#endif
 #ifndef JFNK_XCD_REMAP
 #define JFNK_XCD_REMAP 1
 #endif
@@ -60,6 +69,18 @@ inline int64_t tile_halo_limit(int dim) { return kTileLdsBytes / (8 * (2 * dim +
 constexpr int kFluxLdsBytes = 80 * 1024;
 inline size_t flux_lds_bytes(int dim, int64_t halo_stride, int64_t face_stride) {
   return sizeof(double) * (size_t(2 * dim + dim * dim) * size_t(halo_stride) + size_t(dim) * size_t(face_stride));
+}
+// Face entries of one tile that a lane of the fused J v pass holds in
+// registers between its phases (the pass needs faces_max <= this).
+constexpr int kFusedFaceEntries = 4 * kFvBlock;
+// LDS of the fused J v pass: w and centroids of tile, halo and second ring
+// (later overwritten by the face forces), gradients of tile and halo
+inline int fused_wx_doubles(int dim, int64_t ring_stride, int64_t face_stride) {
+  return int(std::max<int64_t>(2 * dim * ring_stride, dim * face_stride));
+}
+inline size_t fused_lds_bytes(int dim, int64_t ring_stride, int64_t halo_stride, int64_t face_stride) {
+  return sizeof(double) *
+         (size_t(fused_wx_doubles(dim, ring_stride, face_stride)) + size_t(dim * dim) * size_t(halo_stride));
 }
 // slot_nb values
 constexpr int kSlotBoundary = -1;
@@ -107,7 +128,7 @@ struct MeshDev {
   // workgroup's LDS copy (0..kFvBlock-1: inside the tile, kFvBlock + h:
   // entry h of the tile's halo list) or the slot_nb code of other slots
   int32_t tiled;
-  int32_t lds_kernels;       // 1: use the LDS-staged passes on a tiled mesh (tuner's choice)
+  int32_t lds_kernels;       // tiled mesh: 1 LDS-staged passes, 2 fused single pass; 0 gathers (tuner's choice)
   int32_t persist;           // workgroups of a persistent cell-pass launch (0: one per tile)
   int32_t halo_stride;       // kFvBlock + largest halo: LDS row length
   const int32_t* slot_loc;   // [n_slots]
@@ -127,6 +148,19 @@ struct MeshDev {
   const int32_t* in_loc;     // [in_ptr[n_tiles]]
   const int16_t* slot_lf;    // [n_slots]
   int32_t face_stride;       // largest face list of a tile: LDS row length of the face forces
+  // Fused J v pass (fused != 0): a tile also stages its second ring (outside
+  // cells adjacent to the halo, h2_cells[h2_ptr[t] ..]) and recomputes the
+  // halo cells' gradients.  Halo cell i of tile t has its slots, in its own
+  // slot order, at h1_loc/h1_face[halo_ptr[t] * h1_width + k * n_halo + i]:
+  // the neighbour's position in the tile's copy (tile, halo, second ring)
+  // or a slot code, and the face number.
+  int32_t fused;
+  int32_t h1_width;          // slots per halo cell in the lists (largest slice width)
+  int32_t ring_stride;       // kFvBlock + largest halo + largest second ring
+  const int32_t* h2_ptr;     // [n_tiles + 1]
+  const int32_t* h2_cells;   // [h2_ptr[n_tiles]]
+  const int16_t* h1_loc;     // [halo total * h1_width]
+  const int32_t* h1_face;    // [halo total * h1_width]
 };
 
 // Per-call, per-segment device scalars.
@@ -168,8 +202,9 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
 struct UnionArrays {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
   std::vector<int32_t> slot_loc, halo_ptr, halo_cells, fbeg, face_loc, in_ptr, in_face, in_loc;
-  std::vector<int16_t> slot_lf;
-  int64_t halo_max = 0, faces_max = 0;
+  std::vector<int16_t> slot_lf, h1_loc;
+  std::vector<int32_t> h2_ptr, h2_cells, h1_face;
+  int64_t halo_max = 0, faces_max = 0, h2_max = 0, h1_width = 0;
   std::vector<double> xc, face, magG, bface, pc_dinv;
   std::vector<SegInfo> seg;
 };
@@ -286,7 +321,7 @@ struct jfnk_mesh {
   jfnk::MeshDev dev{};
   jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
       b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells, b_slot_lf, b_fbeg,
-      b_face_loc, b_in_ptr, b_in_face, b_in_loc;
+      b_face_loc, b_in_ptr, b_in_face, b_in_loc, b_h2_ptr, b_h2_cells, b_h1_loc, b_h1_face;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
   bool pinned_owned = true;
@@ -315,10 +350,21 @@ inline int rec_doubles(int dim) { return dim + dim * dim; }
 void launch_gradient(const MeshDev& m, const double* u, const double* v, const SegScalars& sc,
                      double* rec, hipStream_t s);
 // out = (R(w) - Ru)/eps if Ru != null else R(w) (per-segment eps and load).
+// Fused single pass: R(w) (v = null, Ru = null) or (R(u + eps v) - R(u))/eps.
+void launch_fused(const MeshDev& m, const double* u, const double* v, const SegScalars& sc, const double* Ru,
+                  double* out, hipStream_t s);
 void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, const double* Ru, double* out,
                  hipStream_t s);
 void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s);
 void build_union(jfnk_mesh& m, UnionArrays& ua);
+// The fused J v pass fits a tiled union: tile positions fit 16 bits, the
+// face entries of a tile one register round, the copy a workgroup's LDS.
+inline bool fused_fits(int dim, const UnionArrays& ua) {
+  const int64_t ring = kFvBlock + ua.halo_max + ua.h2_max;
+  return ring < 32768 && ua.faces_max <= kFusedFaceEntries &&
+         fused_lds_bytes(dim, ring, kFvBlock + ua.halo_max, std::max<int64_t>(ua.faces_max, 1)) <=
+             size_t(kFluxLdsBytes) * 2;
+}
 // Upload the union of m's segments on stream s (mesh handle setup).
 void finish_handle(jfnk_mesh& m, hipStream_t s, double t0);
 size_t device_bytes_of(const HostMesh& h);

@@ -90,6 +90,12 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
                    hipStream_t s) {
   Profiler& p = m->prof;
   SegScalars sc{nullptr, fw.load, active};
+  if (m->dev.lds_kernels == 2) {
+    const int t = p.on ? p.begin(2, s) : -1;
+    launch_fused(m->dev, u, nullptr, sc, nullptr, R, s);
+    if (t >= 0) p.end(t, s);
+    return;
+  }
   int t = p.on ? p.begin(1, s) : -1;
   launch_gradient(m->dev, u, nullptr, sc, fw.grad, s);
   if (t >= 0) p.end(t, s);
@@ -108,6 +114,12 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
     launch_eps_fused(layout_of(m), m->any_large, u, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
   if (t >= 0) p.end(t, s);
   SegScalars sc{fw.eps, fw.load, active};
+  if (m->dev.lds_kernels == 2) {
+    t = p.on ? p.begin(2, s) : -1;
+    launch_fused(m->dev, u, v, sc, Ru, Jv, s);
+    if (t >= 0) p.end(t, s);
+    return;
+  }
   t = p.on ? p.begin(1, s) : -1;
   launch_gradient(m->dev, u, v, sc, fw.grad, s);
   if (t >= 0) p.end(t, s);

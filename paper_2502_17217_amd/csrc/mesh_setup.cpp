@@ -729,6 +729,14 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     ua.in_face.clear();
     ua.in_loc.clear();
     ua.faces_max = 0;
+    ua.h2_ptr.assign(n_blocks + 1, 0);
+    ua.h2_cells.clear();
+    ua.h2_max = 0;
+    ua.h1_width = 0;
+    for (int64_t k = 0; k + 1 < int64_t(ua.slice_ptr.size()); ++k)
+      ua.h1_width = std::max<int64_t>(ua.h1_width, (ua.slice_ptr[k + 1] - ua.slice_ptr[k]) / kSlice);
+    ua.h1_loc.clear();
+    ua.h1_face.clear();
     {
       // owned faces of tile t: owners ascend with the face number (slice order)
       int64_t f = 0;
@@ -766,6 +774,51 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       ua.halo_cells.insert(ua.halo_cells.end(), halo.begin(), halo.end());
       ua.halo_ptr[t + 1] = int32_t(ua.halo_cells.size());
       ua.halo_max = std::max<int64_t>(ua.halo_max, int64_t(halo.size()));
+      // second ring: outside cells adjacent to the halo, not in tile or halo
+      std::vector<int32_t> ring2;
+      auto slots_of = [&](int32_t cell, auto&& fn) {
+        const int64_t sl = cell / kSlice, lane = cell % kSlice;
+        const int32_t w = (ua.slice_ptr[sl + 1] - ua.slice_ptr[sl]) / kSlice;
+        for (int32_t k = 0; k < w; ++k) fn(k, ua.slice_ptr[sl] + k * kSlice + int32_t(lane));
+      };
+      for (int32_t h : halo)
+        slots_of(h, [&](int32_t, int32_t q) {
+          const int32_t nb = ua.slot_nb[q];
+          if (nb >= 0 && nb / kFvBlock != t && !std::binary_search(halo.begin(), halo.end(), nb))
+            ring2.push_back(nb);
+        });
+      std::sort(ring2.begin(), ring2.end());
+      ring2.erase(std::unique(ring2.begin(), ring2.end()), ring2.end());
+      ua.h2_cells.insert(ua.h2_cells.end(), ring2.begin(), ring2.end());
+      ua.h2_ptr[t + 1] = int32_t(ua.h2_cells.size());
+      ua.h2_max = std::max<int64_t>(ua.h2_max, int64_t(ring2.size()));
+      // halo cells' slots in the tile's local numbering, slot-major
+      {
+        const int64_t nh = int64_t(halo.size()), W = ua.h1_width;
+        const size_t off = ua.h1_loc.size();
+        ua.h1_loc.resize(off + size_t(nh * W), int16_t(kSlotPad));
+        ua.h1_face.resize(off + size_t(nh * W), 0);
+        const int32_t nh32 = int32_t(nh);
+        auto local = [&](int32_t cell) -> int32_t {
+          if (cell / kFvBlock == t) return int32_t(cell - c0);
+          auto it = std::lower_bound(halo.begin(), halo.end(), cell);
+          if (it != halo.end() && *it == cell) return kFvBlock + int32_t(it - halo.begin());
+          auto jt = std::lower_bound(ring2.begin(), ring2.end(), cell);
+          return kFvBlock + nh32 + int32_t(jt - ring2.begin());
+        };
+        for (int64_t i = 0; i < nh; ++i)
+          slots_of(halo[i], [&](int32_t k, int32_t q) {
+            const int32_t nb = ua.slot_nb[q], fc = ua.slot_fc[q];
+            const size_t e = off + size_t(k) * size_t(nh) + size_t(i);
+            if (nb >= 0) {
+              ua.h1_loc[e] = int16_t(local(nb));
+              ua.h1_face[e] = fc >= 0 ? fc : ~fc;
+            } else {
+              ua.h1_loc[e] = int16_t(nb);
+              ua.h1_face[e] = fc;
+            }
+          });
+      }
       // face list: owned faces (entries 0 .. n_own-1), then incoming faces
       auto loc_of = [&](int32_t cell) {
         return cell / kFvBlock == t

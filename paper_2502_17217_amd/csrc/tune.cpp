@@ -2,10 +2,10 @@
 // batch): every candidate computes the same bits, so the choice is made on
 // measured time only, on the handle's own mesh and state.
 //
-//   cell passes (gradient + flux of J v): LDS-staged tiles (when the mesh is
-//     tile-ordered) or direct gathers, one workgroup per tile or a
-//     persistent grid of 2, 4 or 8 workgroups per compute unit, each timed
-//     with HIP events over repeated J v products;
+//   cell passes of J v: one fused pass per tile or LDS-staged gradient and
+//     flux passes (when the mesh is tile-ordered), or direct gathers; one
+//     workgroup per tile or a persistent grid of 2, 4 or 8 workgroups per
+//     compute unit, each timed with HIP events over repeated J v products;
 //   Arnoldi schedule: the number of steps enqueued between host checks and
 //     whether runs are replayed from HIP graphs, each timed over the same
 //     preconditioned GMRES solve of J x = -R(u).
@@ -60,7 +60,8 @@ void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o_in, const double* u, double
   } ev{e0, e1};
   // ---- cell passes
   const int tiles = int((m->dev.n_cells + kFvBlock - 1) / kFvBlock);
-  std::vector<int> lds_opts = m->dev.tiled ? std::vector<int>{1, 0} : std::vector<int>{0};
+  std::vector<int> lds_opts{0};
+  if (m->dev.tiled) lds_opts = m->dev.fused ? std::vector<int>{2, 1, 0} : std::vector<int>{1, 0};
   std::vector<int> grid_opts{0};
   for (int k : {2, 4, 8})
     if (k * kComputeUnits < tiles) grid_opts.push_back(k * kComputeUnits);

@@ -48,7 +48,8 @@ class jfnk_mesh_info(C.Structure):
                 ("bandwidth", C.c_int64), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
                 ("n_slots", C.c_int64), ("n_segments", C.c_int32), ("n_dof_external", C.c_int64),
                 ("tiled", C.c_int32), ("tile_halo_max", C.c_int32), ("tile_halo_total", C.c_int64),
-                ("tile_incoming_total", C.c_int64)]
+                ("tile_incoming_total", C.c_int64), ("tile_ring2_max", C.c_int32),
+                ("tile_ring2_total", C.c_int64), ("tile_faces_max", C.c_int32), ("fused", C.c_int32)]
 
 
 class jfnk_gmres_opts(C.Structure):
@@ -113,6 +114,7 @@ def _load():
         "jfnk_profile_enable": [vp, i32],
         "jfnk_profile_read": [vp, vp, vp, i32],
         "jfnk_autotune": [vp, C.POINTER(jfnk_gmres_opts), vp, d, vp, vp, vp],
+        "jfnk_set_cell_passes": [vp, i32, i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -399,6 +401,12 @@ def autotune(mesh, opts, u, work, load=1.0, stream=None):
     _check(_lib.jfnk_autotune(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), float(load), work.c,
                               _stream(stream), C.byref(rep)), "jfnk_autotune")
     return rep.as_dict()
+
+
+def set_cell_passes(mesh, passes, persist=0):
+    """Pin the cell passes of R and J v: 0 gathers, 1 LDS-staged gradient and
+    flux passes, 2 one fused pass per tile; persist = persistent grid size."""
+    _check(_lib.jfnk_set_cell_passes(mesh.handle, int(passes), int(persist)), "jfnk_set_cell_passes")
 
 
 def profile_enable(mesh, on=True):
