@@ -107,7 +107,12 @@ def test_queue_limit(jfnk):
     opts = jfnk.newton_opts(restart=30, precond="jacobi")
     srv = jfnk.Server(hbm_budget=1 << 40, max_slots=1, max_queue=2, dry_run_us_per_kcell=200000.0)
     m = _mesh(6)
-    ts = [srv.submit(m, mg.Material(), opts, keep_solution=False) for _ in range(3)]
+    ts = [srv.submit(m, mg.Material(), opts, keep_solution=False)]
+    # the first request leaves the queue once the worker has taken it
+    t0 = time.time()
+    while srv.poll(ts[0])["state"] == 0 and time.time() - t0 < 10:
+        time.sleep(0.005)
+    ts += [srv.submit(m, mg.Material(), opts, keep_solution=False) for _ in range(2)]
     with pytest.raises(jfnk.JfnkError) as e:
         for _ in range(3):
             ts.append(srv.submit(m, mg.Material(), opts, keep_solution=False))
