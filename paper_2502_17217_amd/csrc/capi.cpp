@@ -112,13 +112,13 @@ size_t device_bytes_of(const HostMesh& h) {
          b(h.xc.size() * 8) + b(size_t(h.n_int) * h.dim * 8) + b(size_t(h.n_int) * 8) +
          b(h.magG.size() * 8) + b(h.bface.size() * 8) + b(h.old_of_new.size() * 4) +
          b(size_t(h.n_cells) * 8) + b(size_t(h.n_cells / kFvBlock + 1) * 4) + 3 * 256 +
-         // tiles: slot_loc, halo_ptr and at most one halo entry per slot
-         // tiles: slot_loc, slot_lf, halo and incoming-face lists (at most one entry per slot each),
-         // per-tile offsets, packed face positions
-         (h.tiled ? 3 * b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 2) + 4 * b(size_t(h.n_cells / kFvBlock + 2) * 4) +
+         // tiles: slot_loc, slot_code, halo, incoming-face and boundary lists (at most one
+         // entry per slot each), per-tile offsets, packed face positions
+         (h.tiled ? 6 * b(h.slot_nb.size() * 4) + 5 * b(size_t(h.n_cells / kFvBlock + 2) * 4) +
                         b(size_t(h.n_int) * 4) +
-                        // second ring (at most one entry per slot) and the halo cells' slot lists
-                        b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 6)
+                        // second ring (at most one entry per slot), the halo cells' slot lists,
+                        // |Gamma_f| per slot
+                        b(h.slot_nb.size() * 4) + b(h.slot_nb.size() * 10) + b(h.slot_nb.size() * 8)
                   : 0);
 }
 
@@ -242,7 +242,10 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     upload(m.b_slot_loc, ua.slot_loc, s);
     upload(m.b_halo_ptr, ua.halo_ptr, s);
     upload(m.b_halo_cells, ua.halo_cells, s);
-    upload(m.b_slot_lf, ua.slot_lf, s);
+    upload(m.b_slot_code, ua.slot_code, s);
+    upload(m.b_bnd_ptr, ua.bnd_ptr, s);
+    upload(m.b_bnd_face, ua.bnd_face, s);
+    upload(m.b_bnd_loc, ua.bnd_loc, s);
     upload(m.b_fbeg, ua.fbeg, s);
     upload(m.b_face_loc, ua.face_loc, s);
     upload(m.b_in_ptr, ua.in_ptr, s);
@@ -251,7 +254,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     upload(m.b_h2_ptr, ua.h2_ptr, s);
     upload(m.b_h2_cells, ua.h2_cells, s);
     upload(m.b_h1_loc, ua.h1_loc, s);
-    upload(m.b_h1_face, ua.h1_face, s);
+    upload(m.b_h1_mg, ua.h1_mg, s);
+    upload(m.b_slot_mg, ua.slot_mg, s);
   }
   JFNK_HIP(hipStreamSynchronize(s));
   const int S = m.n_seg();
@@ -295,13 +299,16 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.slot_loc = h.tiled ? m.b_slot_loc.as<int32_t>() : nullptr;
   d.halo_ptr = h.tiled ? m.b_halo_ptr.as<int32_t>() : nullptr;
   d.halo_cells = h.tiled ? m.b_halo_cells.as<int32_t>() : nullptr;
-  d.slot_lf = h.tiled ? m.b_slot_lf.as<int16_t>() : nullptr;
+  d.slot_code = h.tiled ? m.b_slot_code.as<int32_t>() : nullptr;
+  d.bnd_ptr = h.tiled ? m.b_bnd_ptr.as<int32_t>() : nullptr;
+  d.bnd_face = h.tiled ? m.b_bnd_face.as<int32_t>() : nullptr;
+  d.bnd_loc = h.tiled ? m.b_bnd_loc.as<int32_t>() : nullptr;
   d.fbeg = h.tiled ? m.b_fbeg.as<int32_t>() : nullptr;
   d.face_loc = h.tiled ? m.b_face_loc.as<int32_t>() : nullptr;
   d.in_ptr = h.tiled ? m.b_in_ptr.as<int32_t>() : nullptr;
   d.in_face = h.tiled ? m.b_in_face.as<int32_t>() : nullptr;
   d.in_loc = h.tiled ? m.b_in_loc.as<int32_t>() : nullptr;
-  d.face_stride = int32_t(std::max<int64_t>(ua.faces_max, 1));
+  d.face_stride = int32_t(std::max<int64_t>(ua.ent_max, 1));
   // the deduplicating LDS flux pass needs its staged tile and face forces in LDS
   if (d.tiled && flux_lds_bytes(dim, d.halo_stride, d.face_stride) > size_t(kFluxLdsBytes) * 2) d.lds_kernels = 0;
   d.h1_width = int32_t(ua.h1_width);
@@ -309,7 +316,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.h2_ptr = h.tiled ? m.b_h2_ptr.as<int32_t>() : nullptr;
   d.h2_cells = h.tiled ? m.b_h2_cells.as<int32_t>() : nullptr;
   d.h1_loc = h.tiled ? m.b_h1_loc.as<int16_t>() : nullptr;
-  d.h1_face = h.tiled ? m.b_h1_face.as<int32_t>() : nullptr;
+  d.h1_mg = h.tiled ? m.b_h1_mg.as<double>() : nullptr;
+  d.slot_mg = h.tiled ? m.b_slot_mg.as<double>() : nullptr;
   d.fused = (d.tiled && fused_fits(dim, ua)) ? 1 : 0;
   jfnk_mesh_info& in = m.info;
   in.n_cells = h.n_cells;
@@ -322,9 +330,11 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
                             m.b_fG.bytes + m.b_fw.bytes + m.b_magG.bytes + m.b_bface.bytes +
                             m.b_ext.bytes + m.b_pc_dinv.bytes + m.b_seg_of_block.bytes + m.b_seg.bytes +
                             m.b_block_first.bytes + m.b_slot_loc.bytes + m.b_halo_ptr.bytes +
-                            m.b_halo_cells.bytes + m.b_slot_lf.bytes + m.b_fbeg.bytes + m.b_face_loc.bytes +
+                            m.b_halo_cells.bytes + m.b_slot_code.bytes + m.b_bnd_ptr.bytes +
+                            m.b_bnd_face.bytes + m.b_bnd_loc.bytes + m.b_fbeg.bytes + m.b_face_loc.bytes +
                             m.b_in_ptr.bytes + m.b_in_face.bytes + m.b_in_loc.bytes + m.b_h2_ptr.bytes +
-                            m.b_h2_cells.bytes + m.b_h1_loc.bytes + m.b_h1_face.bytes);
+                            m.b_h2_cells.bytes + m.b_h1_loc.bytes + m.b_h1_mg.bytes +
+                            m.b_slot_mg.bytes);
   in.n_slots = int64_t(ua.slot_nb.size());
   in.n_segments = S;
   in.n_dof_external = m.n_ext_cells * dim;

@@ -180,6 +180,26 @@ __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* 
 
 // Segment sums of partial columns col0 .. col0+ncol-1 for segments larger
 // than kFuseTiles: out[seg * ldo + k].
+// This thread's share of a large segment's column: tiles first + threadIdx.x,
+// + kBlock, + 2 kBlock, ... added in that order; the loads of eight
+// consecutive terms are issued together (the order of the additions is
+// unchanged).
+__device__ __forceinline__ double strided_column_sum(const SegLayout& L, const double* __restrict__ partials,
+                                                     int col, int first, int n) {
+  constexpr int kU = 8;
+  double s = 0;
+  int b = first + threadIdx.x;
+  for (; b + (kU - 1) * kBlock < first + n; b += kU * kBlock) {
+    double x[kU];
+#pragma unroll
+    for (int i = 0; i < kU; ++i) x[i] = partials[pidx(L, col, b + i * kBlock)];
+#pragma unroll
+    for (int i = 0; i < kU; ++i) s += x[i];
+  }
+  for (; b < first + n; b += kBlock) s += partials[pidx(L, col, b)];
+  return s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const double* __restrict__ partials,
                                                          int col0, const int32_t* __restrict__ act,
                                                          double* __restrict__ out, int ldo) {
@@ -188,8 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const doub
   if (act != nullptr && act[seg] == 0) return;
   int first, n;
   if (small_segment(L, seg, first, n)) return;
-  double s = 0;
-  for (int b = first + threadIdx.x; b < first + n; b += kBlock) s += partials[pidx(L, col0 + k, b)];
+  double s = strided_column_sum(L, partials, col0 + k, first, n);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) out[size_t(seg) * ldo + k] = s;
 }
@@ -197,33 +216,77 @@ __global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const doub
 // J v step size, fused: tile sums of |u|^2 and |v|^2 (columns 0 and 1 of the
 // tile's partial row) and, for small segments, eps in the last tile:
 // eps = sqrt(eps_mach) sqrt(1 + |u|) / |v| (0 when v = 0).
+#ifndef JFNK_EPS_TILES
+#define JFNK_EPS_TILES 4
+#endif
+constexpr int kEpsTiles = JFNK_EPS_TILES;  // tiles a workgroup of the step-size kernel sums at once
+
 __device__ __forceinline__ double eps_of(double uu, double vv) {
   const double sqrt_eps = 1.4901161193847656e-08;
   return vv > 0 ? sqrt_eps * sqrt(1.0 + sqrt(uu)) / sqrt(vv) : 0.0;
 }
 
+// Step size of J v per segment (Eq. JF): tile partials of |u|^2 and |v|^2;
+// for a small segment the last of its tiles to finish adds them (one tile
+// per lane) and writes eps, a large one is finished by k_eps_large (no
+// arrival counter shared by thousands of tiles).  A workgroup sums
+// kEpsTiles tiles at once (each tile's partial as tile_norm2 forms it), so
+// that all their loads are in flight together.
 __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double* __restrict__ u,
                                                       const double* __restrict__ v,
                                                       const int32_t* __restrict__ act,
                                                       double* __restrict__ partials, int32_t* __restrict__ tickets,
                                                       double* __restrict__ eps) {
-  __shared__ double wsum[4][kMaxBasis];
-  const int blk = blockIdx.x;
-  const int seg = L.seg_of_block[blk];
-  if (act != nullptr && act[seg] == 0) return;
-  const int c = blk * kFvBlock + threadIdx.x;
-  tile_norm2(L, u, c, wsum, 0);
-  tile_norm2(L, v, c, wsum, 1);
-  store_tile_sums(L, wsum, 2, partials, blk);
-  int first, n;
-  if (!small_segment(L, seg, first, n)) return;
-  if (!last_tile_of_segment(tickets + seg, n)) return;
-  if (threadIdx.x >= 64) return;
-  const double tu = segment_column_sum(L, partials, first, n, 0);
-  const double tv = segment_column_sum(L, partials, first, n, 1);
-  if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
+  __shared__ double wsum[4][2 * kEpsTiles];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int b0 = blockIdx.x * kEpsTiles; b0 < L.n_blocks; b0 += gridDim.x * kEpsTiles) {
+    double su[kEpsTiles], sv[kEpsTiles];
+#pragma unroll
+    for (int j = 0; j < kEpsTiles; ++j) {
+      su[j] = sv[j] = 0.0;
+      const int blk = b0 + j;
+      const int c = blk * kFvBlock + threadIdx.x;
+      if (blk < L.n_blocks && c < L.n_cells && (act == nullptr || act[L.seg_of_block[blk]] != 0))
+        for (int q = 0; q < L.dim; ++q) {
+          const double x = u[size_t(q) * L.n_cells + c];
+          const double y = v[size_t(q) * L.n_cells + c];
+          su[j] = fma(x, x, su[j]);
+          sv[j] = fma(y, y, sv[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kEpsTiles; ++j) {
+      su[j] = wave_sum(su[j]);
+      sv[j] = wave_sum(sv[j]);
+      if (lane == 0) {
+        wsum[wave][2 * j] = su[j];
+        wsum[wave][2 * j + 1] = sv[j];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kEpsTiles) {
+      const int j = threadIdx.x >> 1, blk = b0 + j;
+      if (blk < L.n_blocks && (act == nullptr || act[L.seg_of_block[blk]] != 0))
+        partials[pidx(L, threadIdx.x & 1, blk)] =
+            ((wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) + wsum[2][threadIdx.x]) + wsum[3][threadIdx.x];
+    }
+    for (int j = 0; j < kEpsTiles; ++j) {
+      const int blk = b0 + j;
+      if (blk >= L.n_blocks) break;
+      const int seg = L.seg_of_block[blk];
+      if (act != nullptr && act[seg] == 0) continue;
+      int first, n;
+      if (small_segment(L, seg, first, n) && last_tile_of_segment(tickets + seg, n) && threadIdx.x < 64) {
+        const double tu = segment_column_sum(L, partials, first, n, 0);
+        const double tv = segment_column_sum(L, partials, first, n, 1);
+        if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
+      }
+    }
+    __syncthreads();  // wsum is rewritten by the next round
+  }
 }
 
+// Large segments: tile b to lane (b - first) mod kBlock, then a fixed tree.
 __global__ __launch_bounds__(kBlock) void k_eps_large(SegLayout L, const double* __restrict__ partials,
                                                       const int32_t* __restrict__ act, double* __restrict__ eps) {
   __shared__ double sh[4];
@@ -231,11 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_eps_large(SegLayout L, const double*
   if (act != nullptr && act[seg] == 0) return;
   int first, n;
   if (small_segment(L, seg, first, n)) return;
-  double su = 0, sv = 0;
-  for (int b = first + threadIdx.x; b < first + n; b += kBlock) {
-    su += partials[pidx(L, 0, b)];
-    sv += partials[pidx(L, 1, b)];
-  }
+  double su = strided_column_sum(L, partials, 0, first, n);
+  double sv = strided_column_sum(L, partials, 1, first, n);
   su = block_sum(su, sh);
   sv = block_sum(sv, sh);
   if (threadIdx.x == 0) eps[seg] = eps_of(su, sv);
@@ -261,7 +321,8 @@ void fill_int(int32_t* d, int n, int32_t v, hipStream_t s) {
 
 void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
                       double* partials, int32_t* tickets, double* eps, hipStream_t s) {
-  hipLaunchKernelGGL(k_eps_tiles, dim3(L.n_blocks), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
+  const int grid = (L.n_blocks + kEpsTiles - 1) / kEpsTiles;
+  hipLaunchKernelGGL(k_eps_tiles, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
   if (any_large) hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kBlock), 0, s, L, partials, act, eps);
   JFNK_HIP(hipGetLastError());
 }

@@ -33,6 +33,13 @@
 
 #include "internal.h"
 
+// a * b + c is fused only within one source expression, as the front end
+// reads it (besides the explicit fma() calls), never by the back end across
+// statements: every pass (gathered, LDS-staged, fused, any chunk size or
+// launch shape) then evaluates each expression with the same roundings and
+// gives the same bits.
+#pragma clang fp contract(on)
+
 namespace jfnk {
 
 namespace {
@@ -212,6 +219,11 @@ __device__ __forceinline__ void internal_face_force(const Law& m, const double (
 #define JFNK_CHUNK 6
 #endif
 constexpr int kChunk = JFNK_CHUNK;
+// slots per chunk of the gradients read from the LDS copy of a tile
+#ifndef JFNK_TILED_CHUNK
+#define JFNK_TILED_CHUNK 3
+#endif
+constexpr int kTiledChunk = JFNK_TILED_CHUNK;
 
 template <int D>
 __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int n, int c, double (&w)[D],
@@ -253,27 +265,40 @@ struct GradLds {
   }
 };
 
-// Neighbour ids and |Gamma_f| of one chunk of a cell's slots.
+// Neighbour ids and |Gamma_f| of one chunk of CH of a cell's slots.
+template <int CH>
 struct GradChunk {
-  int nb[kChunk];
-  double mg[kChunk];
+  int nb[CH];
+  double mg[CH];
 };
 
 // Slots of cell c in its slice of the mesh's slot arrays (ids in the
-// source's numbering).
+// source's numbering); |Gamma_f| from the per-slot copy when mg is given,
+// else gathered through the slot's face number.
 struct SliceSlots {
   const int32_t* ids;
   int s0, lane, width;
-  __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk& gc) const {
-    int fc[kChunk];
+  const double* mg = nullptr;
+  template <int CH>
+  __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk<CH>& gc) const {
+    if (mg != nullptr) {
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
+      for (int k = 0; k < CH; ++k) {
+        const int idx = s0 + (k0 + k) * kSlice + lane;
+        gc.nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
+        gc.mg[k] = (k0 + k < width) ? mg[idx] : 0.0;
+      }
+      return;
+    }
+    int fc[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
       const int idx = s0 + (k0 + k) * kSlice + lane;
       gc.nb[k] = (k0 + k < width) ? ids[idx] : kSlotPad;
       fc[k] = (k0 + k < width) ? m.slot_fc[idx] : 0;
     }
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
       const int f = fc[k] >= 0 ? fc[k] : ~fc[k];
       gc.mg[k] = gc.nb[k] >= 0 ? m.magG[f] : 0.0;
     }
@@ -281,32 +306,30 @@ struct SliceSlots {
 };
 
 // Slots of halo cell i of a tile in the tile's lists (slot-major over the
-// tile's nh halo cells: position in the tile's copy, face number), in the
+// tile's nh halo cells: position in the tile's copy, |Gamma_f|), in the
 // slot order of the cell's own slice.
 struct HaloSlots {
   const int16_t* loc;
-  const int32_t* face;
+  const double* mg;
   int nh, i, width;
-  __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk& gc) const {
-    int fc[kChunk];
+  template <int CH>
+  __device__ __forceinline__ void load(const MeshDev&, int k0, GradChunk<CH>& gc) const {
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
       const int idx = (k0 + k) * nh + i;
       gc.nb[k] = (k0 + k < width) ? int(loc[idx]) : kSlotPad;
-      fc[k] = (k0 + k < width) ? face[idx] : 0;
+      gc.mg[k] = (k0 + k < width) ? mg[idx] : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) gc.mg[k] = gc.nb[k] >= 0 ? m.magG[fc[k]] : 0.0;
   }
 };
 
 // Least-squares gradient (Eq. leastSquaresGrad with the weight |Gamma_f| in
 // the sum and in G_P) of the cell with id self in the source, its slots read
-// from sl in slot order.  Returns w_P and grad w_P.
-template <int D, class Src, class Slots>
+// from sl in slot order, CH at a time (the chunk size changes only how many
+// loads are in flight, not the order of the sums).  Returns w_P and grad w_P.
+template <int D, int CH = kChunk, class Src, class Slots>
 __device__ __forceinline__ void lsq_gradient(const MeshDev& m, const Src& src, const Slots& sl, int self,
-                                             double (&wP)[D], double (&g)[D][D],
-                                             const GradChunk* first = nullptr) {
+                                             double (&wP)[D], double (&g)[D][D]) {
   double xP[D];
   src.get(self, wP, xP);
   double Gs[D][D], M[D][D];
@@ -314,22 +337,19 @@ __device__ __forceinline__ void lsq_gradient(const MeshDev& m, const Src& src, c
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) Gs[i][j] = M[i][j] = 0.0;
-  for (int k0 = 0; k0 < sl.width; k0 += kChunk) {
-    GradChunk gc;
-    if (k0 == 0 && first != nullptr)
-      gc = *first;
-    else
-      sl.load(m, k0, gc);
+  for (int k0 = 0; k0 < sl.width; k0 += CH) {
+    GradChunk<CH> gc;
+    sl.template load<CH>(m, k0, gc);
     const int* nb = gc.nb;
     const double* mg = gc.mg;
-    double xN[kChunk][D], wN[kChunk][D];
+    double xN[CH][D], wN[CH][D];
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
       const int nn = nb[k] >= 0 ? nb[k] : self;
       src.get(nn, wN[k], xN[k]);
     }
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
       if (nb[k] < 0) continue;
       double d[D], dd = 0;
 #pragma unroll
@@ -374,15 +394,16 @@ __device__ __forceinline__ void lsq_gradient(const MeshDev& m, const Src& src, c
 
 // Gradient of cell c and its record {w, grad w}; ids holds the neighbour
 // ids of the slots in the source's numbering and self is c's id.
-template <int D, class Src>
+template <int D, int CH = kChunk, class Src>
 __device__ __forceinline__ void gradient_cell(const MeshDev& m, const Src& src, const int32_t* __restrict__ ids,
-                                              int self, int c, double* __restrict__ rec) {
+                                              int self, int c, double* __restrict__ rec,
+                                              const double* __restrict__ mg = nullptr) {
   const int n = m.n_cells;
   const int slice = c / kSlice, lane = c % kSlice;
   const int s0 = m.slice_ptr[slice];
-  const SliceSlots sl{ids, s0, lane, (m.slice_ptr[slice + 1] - s0) / kSlice};
+  const SliceSlots sl{ids, s0, lane, (m.slice_ptr[slice + 1] - s0) / kSlice, mg};
   double wP[D], g[D][D];
-  lsq_gradient<D>(m, src, sl, self, wP, g);
+  lsq_gradient<D, CH>(m, src, sl, self, wP, g);
 #pragma unroll
   for (int k = 0; k < D; ++k) rec[size_t(k) * n + c] = wP[k];
 #pragma unroll
@@ -486,7 +507,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_gradient_tile
         zero_rec<D>(rec, n, c);
       } else {
         const GradLds<D> src{lds, S};
-        gradient_cell<D>(m, src, m.slot_loc, threadIdx.x, c, rec);
+        gradient_cell<D, kTiledChunk>(m, src, m.slot_loc, threadIdx.x, c, rec, m.slot_mg);
       }
     }
     __syncthreads();  // the LDS copy is rewritten for the next tile
@@ -522,13 +543,20 @@ struct FluxLds {
   }
 };
 
-// Boundary face bf of cell P added to R: displacement faces Gamma . sigma_P
+// Record of boundary face bf: Gamma, d_b, value, type.
+__device__ __forceinline__ void load_bface(const MeshDev& m, int bf, double (&r)[kBfaceRec]) {
+  const double* p = m.bface + size_t(bf) * kBfaceRec;
+#pragma unroll
+  for (int k = 0; k < kBfaceRec; ++k) r[k] = p[k];
+}
+
+// Force on boundary face r of cell P: displacement faces Gamma . sigma_P
 // plus the Rhie-Chow term against load * u_bar; traction faces
 // load |Gamma| T_bar and pressure faces -load p Gamma (stored pre-multiplied).
 template <int D, int LAW>
-__device__ __forceinline__ void boundary_force(const MeshDev& m, const Law& law, int bf, double load,
-                                               const double (&wP)[D], const double (&gP)[D][D], double (&R)[D]) {
-  const double* r = m.bface + size_t(bf) * kBfaceRec;
+__device__ __forceinline__ void boundary_face_force(const Law& law, const double (&r)[kBfaceRec], double load,
+                                                    const double (&wP)[D], const double (&gP)[D][D],
+                                                    double (&f)[D]) {
   const int type = int(r[9]);
   if (type == kBcDisp) {
     double G[D], db[D], ub[D], t[D];
@@ -551,11 +579,11 @@ __device__ __forceinline__ void boundary_force(const MeshDev& m, const Law& law,
       double dg = 0;
 #pragma unroll
       for (int i = 0; i < D; ++i) dg = fma(db[i], gP[i][j], dg);
-      R[j] += fma(coef, (ub[j] - wP[j]) - dg, t[j]);
+      f[j] = fma(coef, (ub[j] - wP[j]) - dg, t[j]);
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < D; ++q) R[q] = fma(load, r[6 + q], R[q]);
+    for (int q = 0; q < D; ++q) f[q] = load * r[6 + q];
   }
 }
 
@@ -608,7 +636,11 @@ __device__ __forceinline__ void cell_forces(const MeshDev& m, const Law& law, co
 #pragma unroll
         for (int q = 0; q < D; ++q) R[q] += own ? fo[q] : -fo[q];
       } else if (nb[k] == kSlotBoundary) {
-        boundary_force<D, LAW>(m, law, fc[k], load, wP, gP, R);
+        double r[kBfaceRec], f[D];
+        load_bface(m, fc[k], r);
+        boundary_face_force<D, LAW>(law, r, load, wP, gP, f);
+#pragma unroll
+        for (int q = 0; q < D; ++q) R[q] += f[q];
       }
     }
   }
@@ -685,7 +717,7 @@ constexpr int kEnt = 4;
 template <int D>
 struct FaceBatch {
   int n = 0;
-  int lo[kEnt], ln[kEnt];
+  int pos[kEnt];  // LDS positions: owner (low 16 bits), neighbour (high 16 bits)
   double G[kEnt][D], wf[kEnt];
 };
 
@@ -700,8 +732,7 @@ __device__ __forceinline__ void load_faces(const MeshDev& m, int tile, int e0, F
     if (e >= n_ent) break;
     const int f = e < n_own ? f0 + e : m.in_face[i0 + e - n_own];
     const int packed = e < n_own ? m.face_loc[f] : m.in_loc[i0 + e - n_own];
-    fb.lo[j] = packed & 0xffff;
-    fb.ln[j] = packed >> 16;
+    fb.pos[j] = packed;
     load_soa<D>(m.fG, m.n_int, f, fb.G[j]);
     fb.wf[j] = m.fw[f];
     fb.n = j + 1;
@@ -714,8 +745,8 @@ template <int D, int LAW, class Src>
 __device__ __forceinline__ void one_face_force(const Law& law, const Src& src, const FaceBatch<D>& fb, int j,
                                                double (&fo)[D]) {
   double xA[D], xB[D], wA[D], wB[D], gA[D][D], gB[D][D];
-  src.get(fb.lo[j], wA, gA, xA);
-  src.get(fb.ln[j], wB, gB, xB);
+  src.get(fb.pos[j] & 0xffff, wA, gA, xA);
+  src.get(fb.pos[j] >> 16, wB, gB, xB);
   internal_face_force<D, LAW>(law, fb.G[j], fb.wf[j], xA, xB, wA, wB, gA, gB, fo);
 #if JFNK_FACE_SCHED_BARRIER
   // one neo-Hookean face's operands live at a time: keeps the passes at
@@ -775,32 +806,25 @@ __device__ __forceinline__ void face_forces_sel(const SegInfo& si, const Src& sr
   }
 }
 
-// Phase B: cell c sums its slots in slot order (face forces from LDS with
-// the sign of its side, boundary faces evaluated in place).
-// Slot metadata of one chunk of a cell's slots.
+// Phase B: cell c sums its slots in slot order, every face force (internal
+// with the sign of its side, boundary) read from LDS.
+// Slot codes of one chunk of a cell's slots.
 struct SlotChunk {
-  int nb[kChunk], fc[kChunk], lf[kChunk];
+  int code[kChunk];
 };
 
 __device__ __forceinline__ void load_slots(const MeshDev& m, int s0, int width, int lane, int k0, SlotChunk& sl) {
 #pragma unroll
   for (int k = 0; k < kChunk; ++k) {
     const int idx = s0 + (k0 + k) * kSlice + lane;
-    const bool in = k0 + k < width;
-    sl.nb[k] = in ? m.slot_loc[idx] : kSlotPad;
-    sl.fc[k] = in ? m.slot_fc[idx] : 0;
-    sl.lf[k] = in ? int(m.slot_lf[idx]) : 0;
+    sl.code[k] = k0 + k < width ? m.slot_code[idx] : -1;
   }
 }
 
-// first: the cell's first chunk of slots, loaded before the tile's
-// barriers; wP, gP: the cell's own w and gradient.
-template <int D, int LAW>
-__device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& si, const double (&wP)[D],
-                                              const double (&gP)[D][D], int c, double load,
-                                              const double* __restrict__ ff, int fs, const SlotChunk& first,
-                                              double (&R)[D]) {
-  const Law law{si.mu, si.lam, si.kappa, si.aK};
+// first: the cell's first chunk of slots, loaded before the tile's barriers.
+template <int D>
+__device__ __forceinline__ void tile_cell_sum(const MeshDev& m, int c, const double* __restrict__ ff, int fs,
+                                              const SlotChunk& first, double (&R)[D]) {
 #pragma unroll
   for (int q = 0; q < D; ++q) R[q] = 0.0;
   const int slice = c / kSlice, lane = c % kSlice;
@@ -812,39 +836,26 @@ __device__ __forceinline__ void tile_cell_sum(const MeshDev& m, const SegInfo& s
       cur = first;
     else
       load_slots(m, s0, width, lane, k0, cur);
-    const int* nb = cur.nb;
-    const int* fc = cur.fc;
-    const int* lf = cur.lf;
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
-      if (nb[k] >= 0) {
-        const bool own = fc[k] >= 0;
+      const int code = cur.code[k];
+      if (code >= 0) {
+        const int e = code >> 1;
 #pragma unroll
-        for (int q = 0; q < D; ++q) R[q] += own ? ff[q * fs + lf[k]] : -ff[q * fs + lf[k]];
-      } else if (nb[k] == kSlotBoundary) {
-        boundary_force<D, LAW>(m, law, fc[k], load, wP, gP, R);
+        for (int q = 0; q < D; ++q) R[q] += (code & 1) ? -ff[q * fs + e] : ff[q * fs + e];
       }
     }
   }
 }
 
 // Phase B of cell c and its output: R(w), or (R(w) - R(u))/eps when jv.
-template <int D, int LAWSEL>
-__device__ __forceinline__ void cell_sum_out(const MeshDev& m, const SegInfo& si, const double (&wP)[D],
-                                             const double (&gP)[D][D], int c, double load,
-                                             const double* __restrict__ ff, int fs, const SlotChunk& first,
-                                             double eps, bool jv, const double (&ru)[D],
+template <int D>
+__device__ __forceinline__ void cell_sum_out(const MeshDev& m, int c, const double* __restrict__ ff, int fs,
+                                             const SlotChunk& first, double eps, bool jv, const double (&ru)[D],
                                              double* __restrict__ out) {
   const int n = m.n_cells;
   double R[D];
-  if constexpr (LAWSEL == kLawMixed) {
-    if (si.law == JFNK_NEO_HOOKEAN)
-      tile_cell_sum<D, JFNK_NEO_HOOKEAN>(m, si, wP, gP, c, load, ff, fs, first, R);
-    else
-      tile_cell_sum<D, JFNK_LINEAR_ELASTIC>(m, si, wP, gP, c, load, ff, fs, first, R);
-  } else {
-    tile_cell_sum<D, LAWSEL>(m, si, wP, gP, c, load, ff, fs, first, R);
-  }
+  tile_cell_sum<D>(m, c, ff, fs, first, R);
   if (jv) {
     const double ie = eps != 0.0 ? 1.0 / eps : 0.0;
 #pragma unroll
@@ -855,13 +866,52 @@ __device__ __forceinline__ void cell_sum_out(const MeshDev& m, const SegInfo& si
   }
 }
 
+// Boundary faces of a tile in phase A: entry tid of the tile's boundary
+// list (record loaded ahead of the barriers), the rest (lists longer than
+// kFvBlock) loaded in place.
+struct BndEntry {
+  int loc = -1;
+  double r[kBfaceRec];
+};
+
+__device__ __forceinline__ void load_bnd(const MeshDev& m, int tile, int eb, BndEntry& be) {
+  const int b0 = m.bnd_ptr[tile];
+  be.loc = -1;
+  if (eb < m.bnd_ptr[tile + 1] - b0) {
+    be.loc = m.bnd_loc[b0 + eb];
+    load_bface(m, m.bnd_face[b0 + eb], be.r);
+  }
+}
+
+template <int D, int LAW, class Src>
+__device__ __forceinline__ void bnd_force(const SegInfo& si, const Src& src, const BndEntry& be, double load,
+                                          double (&f)[D]) {
+  const Law law{si.mu, si.lam, si.kappa, si.aK};
+  double wP[D], gP[D][D], xP[D];
+  src.get(be.loc, wP, gP, xP);
+  boundary_face_force<D, LAW>(law, be.r, load, wP, gP, f);
+}
+
+template <int D, int LAWSEL, class Src>
+__device__ __forceinline__ void bnd_force_sel(const SegInfo& si, const Src& src, const BndEntry& be, double load,
+                                              double (&f)[D]) {
+  if constexpr (LAWSEL == kLawMixed) {
+    if (si.law == JFNK_NEO_HOOKEAN)
+      bnd_force<D, JFNK_NEO_HOOKEAN>(si, src, be, load, f);
+    else
+      bnd_force<D, JFNK_LINEAR_ELASTIC>(si, src, be, load, f);
+  } else {
+    bnd_force<D, LAWSEL>(si, src, be, load, f);
+  }
+}
+
 // Tiled flux pass.  The records and centroids of the tile's cells and halo
 // are staged in LDS (rows of length halo_stride).  Phase A evaluates every
-// internal face touching the tile once, spread evenly over the workgroup
-// (owner first, the canonical operand order), into LDS; phase B sums each
-// cell's slots in slot order, the same sequence of operations as the
-// gather pass, so both give the same bits.  Exits before a barrier are
-// uniform over the workgroup.
+// face touching the tile once (its boundary faces, then its internal faces,
+// owner first, the canonical operand order), spread evenly over the
+// workgroup, into LDS; phase B sums each cell's slots in slot order, the
+// same sequence of operations as the gather pass, so both give the same
+// bits.  Exits before a barrier are uniform over the workgroup.
 template <int D, int LAWSEL>
 __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(MeshDev m, const double* __restrict__ rec,
                                                          SegScalars sc, const double* __restrict__ Ru,
@@ -878,8 +928,11 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     const int base = tile * kFvBlock;
     const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
     const int n_ent = m.fbeg[tile + 1] - m.fbeg[tile] + m.in_ptr[tile + 1] - m.in_ptr[tile];
+    const int n_bnd = m.bnd_ptr[tile + 1] - m.bnd_ptr[tile];
     FaceBatch<D> fb;
     load_faces<D>(m, tile, threadIdx.x, fb);
+    BndEntry be;
+    load_bnd(m, tile, threadIdx.x, be);
     // this cell's first chunk of slots and R(u), also ahead of the barriers
     const int c = base + threadIdx.x;
     SlotChunk first;
@@ -927,8 +980,19 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     __syncthreads();
     const SegInfo& si = m.seg[seg];
     const FluxLds<D> src{lds, S};
-    // phase A, kEnt entries per thread per round (one round unless the tile
-    // touches more than kEnt * kFvBlock faces)
+    // phase A: boundary faces (entries n_ent + eb), one per lane per round
+    {
+      const double load = sc.load[seg];
+      for (int eb = threadIdx.x; eb < n_bnd; eb += kFvBlock) {
+        if (eb != int(threadIdx.x)) load_bnd(m, tile, eb, be);
+        double f[D];
+        bnd_force_sel<D, LAWSEL>(si, src, be, load, f);
+#pragma unroll
+        for (int q = 0; q < D; ++q) ff[q * fs + n_ent + eb] = f[q];
+      }
+    }
+    // internal faces, kEnt entries per lane per round (one round unless the
+    // tile touches more than kEnt * kFvBlock faces)
     for (int e0 = threadIdx.x;; e0 += kEnt * kFvBlock) {
       if (e0 != threadIdx.x) load_faces<D>(m, tile, e0, fb);
       if constexpr (LAWSEL == kLawMixed) {
@@ -944,10 +1008,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     __syncthreads();
     if (c < n) {
       if (c - si.cell_off < si.n_cells) {
-        double wP[D], xP[D], gP[D][D];
-        src.get(threadIdx.x, wP, gP, xP);
-        cell_sum_out<D, LAWSEL>(m, si, wP, gP, c, sc.load[seg], ff, fs, first, Ru ? sc.eps[seg] : 0.0, Ru != nullptr,
-                                ru, out);
+        cell_sum_out<D>(m, c, ff, fs, first, Ru ? sc.eps[seg] : 0.0, Ru != nullptr, ru, out);
       } else {
 #pragma unroll
         for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;  // alignment padding
@@ -964,7 +1025,8 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
 // computed from that copy into LDS (rows of length halo_stride), in the
 // same slot order as the gradient pass; then phase A and phase B of the
 // tiled flux pass follow, the face forces overwriting the w/centroid rows
-// once phase A has read them.  Every cell's gradient and every face force
+// once phase A has read them (boundary faces wait in a small row of their
+// own until then).  Every cell's gradient and every face force
 // is the same sequence of operations as in the two passes, so the result
 // is the same bits.  Exits before a barrier are uniform over the workgroup.
 template <int D>
@@ -985,9 +1047,13 @@ struct FusedLds {
 };
 
 constexpr int kStageRounds = 3;
+#ifndef JFNK_FUSED_CHUNK
+#define JFNK_FUSED_CHUNK 3
+#endif
+constexpr int kFusedChunk = JFNK_FUSED_CHUNK;  // slots per chunk of the LDS-sourced gradients
 
 template <int D, int LAWSEL>
-__global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(MeshDev m, const double* __restrict__ u,
+__global__ __launch_bounds__(kFvBlock, JFNK_FUSED_MINWAVES) void k_jv_fused(MeshDev m, const double* __restrict__ u,
                                                                             const double* __restrict__ v,
                                                                             SegScalars sc,
                                                                             const double* __restrict__ Ru,
@@ -997,7 +1063,8 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(Mesh
   const int n = m.n_cells, R = m.ring_stride, S = m.halo_stride, fs = m.face_stride, W = m.h1_width;
   double* wx = lds;
   double* gl = lds + wx_size;
-  double* ff = lds;  // face forces, over the w/centroid rows
+  double* bl = gl + D * D * S;  // boundary face forces until the face rows are free
+  double* ff = lds;             // face forces, over the w/centroid rows
   for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
     const int tile = xcd_block(it, nb_launch);
     if (tile >= nb_real) continue;
@@ -1059,13 +1126,13 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(Mesh
     __syncthreads();
     // gradients of the tile's cells, then of its halo cells
     const GradLds<D> gsrc{wx, R};
-    double wP[D];
     {
-      double gP[D][D];
+      double wP[D], gP[D][D];
       if (real) {
         const int s0 = m.slice_ptr[c / kSlice];
-        const SliceSlots sl{m.slot_loc, s0, int(c % kSlice), (m.slice_ptr[c / kSlice + 1] - s0) / kSlice};
-        lsq_gradient<D>(m, gsrc, sl, threadIdx.x, wP, gP);
+        const SliceSlots sl{m.slot_loc, s0, int(c % kSlice), (m.slice_ptr[c / kSlice + 1] - s0) / kSlice,
+                            m.slot_mg};
+        lsq_gradient<D, kFusedChunk>(m, gsrc, sl, threadIdx.x, wP, gP);
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -1080,24 +1147,38 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(Mesh
         for (int b = 0; b < D; ++b) gl[(a * D + b) * S + threadIdx.x] = gP[a][b];
     }
     for (int i = threadIdx.x; i < nh; i += kFvBlock) {
-      const HaloSlots hi{m.h1_loc + size_t(h0) * W, m.h1_face + size_t(h0) * W, nh, i, W};
+      const HaloSlots hi{m.h1_loc + size_t(h0) * W, m.h1_mg + size_t(h0) * W, nh, i, W};
       double wH[D], gH[D][D];
-      lsq_gradient<D>(m, gsrc, hi, kFvBlock + i, wH, gH);
+      lsq_gradient<D, kFusedChunk>(m, gsrc, hi, kFvBlock + i, wH, gH);
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b) gl[(a * D + b) * S + kFvBlock + i] = gH[a][b];
     }
-    // this lane's faces, in flight while the slower lanes finish
+    // this lane's faces, in flight while the slower lanes finish (a tile
+    // has at most kEnt * kFvBlock internal and kFvBlock boundary faces)
     FaceBatch<D> fb;
     load_faces<D>(m, tile, threadIdx.x, fb);
     __syncthreads();
     // phase A into registers; the face forces replace the w/centroid rows
     // once every lane has read them
     {
+      BndEntry be;
+      load_bnd(m, tile, threadIdx.x, be);
+      const int n_ent = m.fbeg[tile + 1] - m.fbeg[tile] + m.in_ptr[tile + 1] - m.in_ptr[tile];
+      const FusedLds<D> src{wx, gl, R, S};
+      if (be.loc >= 0) {
+        double f[D];
+        bnd_force_sel<D, LAWSEL>(si, src, be, sc.load[seg], f);
+#pragma unroll
+        for (int q = 0; q < D; ++q) bl[q * kFvBlock + threadIdx.x] = f[q];
+      }
       double fo[kEnt][D];
-      face_forces_sel<D, LAWSEL>(si, FusedLds<D>{wx, gl, R, S}, fb, fo);
+      face_forces_sel<D, LAWSEL>(si, src, fb, fo);
       __syncthreads();
+      if (be.loc >= 0)
+#pragma unroll
+        for (int q = 0; q < D; ++q) ff[q * fs + n_ent + threadIdx.x] = bl[q * kFvBlock + threadIdx.x];
       store_face_forces<D>(fb, fo, threadIdx.x, ff, fs);
     }
     __syncthreads();
@@ -1106,15 +1187,10 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_jv_fused(Mesh
         const int s0 = m.slice_ptr[c / kSlice];
         SlotChunk first;
         load_slots(m, s0, (m.slice_ptr[c / kSlice + 1] - s0) / kSlice, c % kSlice, 0, first);
-        double ru[D], gP[D][D];
+        double ru[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) ru[q] = Ru != nullptr ? Ru[size_t(q) * n + c] : 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int b = 0; b < D; ++b) gP[a][b] = gl[(a * D + b) * S + threadIdx.x];
-        cell_sum_out<D, LAWSEL>(m, si, wP, gP, c, sc.load[seg], ff, fs, first, Ru ? sc.eps[seg] : 0.0,
-                                Ru != nullptr, ru, out);
+        cell_sum_out<D>(m, c, ff, fs, first, Ru ? sc.eps[seg] : 0.0, Ru != nullptr, ru, out);
       } else {
 #pragma unroll
         for (int q = 0; q < D; ++q) out[size_t(q) * n + c] = 0.0;  // alignment padding

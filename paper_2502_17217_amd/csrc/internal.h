@@ -48,6 +48,10 @@ constexpr int kNumXcd = 8;
 #ifndef JFNK_TILED_MINWAVES
 #define JFNK_TILED_MINWAVES 1
 #endif
+// waves per SIMD the fused J v pass is compiled for
+#ifndef JFNK_FUSED_MINWAVES
+#define JFNK_FUSED_MINWAVES 1
+#endif
 // scheduling barrier between the neo-Hookean face evaluations of a lane
 #ifndef JFNK_FACE_SCHED_BARRIER
 #define JFNK_FACE_SCHED_BARRIER 1
@@ -74,13 +78,14 @@ inline size_t flux_lds_bytes(int dim, int64_t halo_stride, int64_t face_stride) 
 // registers between its phases (the pass needs faces_max <= this).
 constexpr int kFusedFaceEntries = 4 * kFvBlock;
 // LDS of the fused J v pass: w and centroids of tile, halo and second ring
-// (later overwritten by the face forces), gradients of tile and halo
+// (later overwritten by the face forces), gradients of tile and halo, one
+// row of boundary face forces
 inline int fused_wx_doubles(int dim, int64_t ring_stride, int64_t face_stride) {
   return int(std::max<int64_t>(2 * dim * ring_stride, dim * face_stride));
 }
 inline size_t fused_lds_bytes(int dim, int64_t ring_stride, int64_t halo_stride, int64_t face_stride) {
-  return sizeof(double) *
-         (size_t(fused_wx_doubles(dim, ring_stride, face_stride)) + size_t(dim * dim) * size_t(halo_stride));
+  return sizeof(double) * (size_t(fused_wx_doubles(dim, ring_stride, face_stride)) +
+                           size_t(dim * dim) * size_t(halo_stride) + size_t(dim) * kFvBlock);
 }
 // slot_nb values
 constexpr int kSlotBoundary = -1;
@@ -139,28 +144,35 @@ struct MeshDev {
   // range fbeg[t] .. fbeg[t+1]-1, owner < neighbour) and the incoming faces
   // owned by an earlier tile (in_face[in_ptr[t] ..]); face_loc / in_loc pack
   // the LDS positions of owner (low 16 bits) and neighbour (high 16 bits).
-  // slot_lf gives, for every internal slot, the face's entry in its tile's
-  // list (owned faces first, then incoming), -1 for the other slots.
+  // After the internal faces (n_ent entries) come the tile's boundary faces
+  // (bnd_face[bnd_ptr[t] ..]: boundary-face numbers, bnd_loc: the owner's
+  // position in the tile).  slot_code gives, for every slot, the entry of
+  // its face in the tile's list, 2 entry + 1 on the neighbour side of an
+  // internal face and 2 entry otherwise, -1 for padding slots.
   const int32_t* fbeg;       // [n_tiles + 1]
   const int32_t* face_loc;   // [n_int]
   const int32_t* in_ptr;     // [n_tiles + 1]
   const int32_t* in_face;    // [in_ptr[n_tiles]]
   const int32_t* in_loc;     // [in_ptr[n_tiles]]
-  const int16_t* slot_lf;    // [n_slots]
-  int32_t face_stride;       // largest face list of a tile: LDS row length of the face forces
+  const int32_t* bnd_ptr;    // [n_tiles + 1]
+  const int32_t* bnd_face;   // [bnd_ptr[n_tiles]]
+  const int32_t* bnd_loc;    // [bnd_ptr[n_tiles]]
+  const int32_t* slot_code;  // [n_slots]
+  const double* slot_mg;     // [n_slots] |Gamma_f| of the slot's face (0 for other slots)
+  int32_t face_stride;       // largest face list of a tile (internal + boundary): LDS row length
   // Fused J v pass (fused != 0): a tile also stages its second ring (outside
   // cells adjacent to the halo, h2_cells[h2_ptr[t] ..]) and recomputes the
   // halo cells' gradients.  Halo cell i of tile t has its slots, in its own
-  // slot order, at h1_loc/h1_face[halo_ptr[t] * h1_width + k * n_halo + i]:
+  // slot order, at h1_loc/h1_mg[halo_ptr[t] * h1_width + k * n_halo + i]:
   // the neighbour's position in the tile's copy (tile, halo, second ring)
-  // or a slot code, and the face number.
+  // or a slot code, and |Gamma_f| of the slot's face.
   int32_t fused;
   int32_t h1_width;          // slots per halo cell in the lists (largest slice width)
   int32_t ring_stride;       // kFvBlock + largest halo + largest second ring
   const int32_t* h2_ptr;     // [n_tiles + 1]
   const int32_t* h2_cells;   // [h2_ptr[n_tiles]]
   const int16_t* h1_loc;     // [halo total * h1_width]
-  const int32_t* h1_face;    // [halo total * h1_width]
+  const double* h1_mg;       // [halo total * h1_width]
 };
 
 // Per-call, per-segment device scalars.
@@ -202,9 +214,12 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
 struct UnionArrays {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
   std::vector<int32_t> slot_loc, halo_ptr, halo_cells, fbeg, face_loc, in_ptr, in_face, in_loc;
-  std::vector<int16_t> slot_lf, h1_loc;
-  std::vector<int32_t> h2_ptr, h2_cells, h1_face;
-  int64_t halo_max = 0, faces_max = 0, h2_max = 0, h1_width = 0;
+  std::vector<int16_t> h1_loc;
+  std::vector<int32_t> h2_ptr, h2_cells, bnd_ptr, bnd_face, bnd_loc, slot_code;
+  std::vector<double> h1_mg, slot_mg;
+  // faces_max: largest internal face list of a tile; bnd_max: largest
+  // boundary list; ent_max: largest internal + boundary list
+  int64_t halo_max = 0, faces_max = 0, bnd_max = 0, ent_max = 0, h2_max = 0, h1_width = 0;
   std::vector<double> xc, face, magG, bface, pc_dinv;
   std::vector<SegInfo> seg;
 };
@@ -320,8 +335,9 @@ struct jfnk_mesh {
   std::vector<int32_t> block_first; // [n_seg + 1] first workgroup (kFvBlock cells) of each segment
   jfnk::MeshDev dev{};
   jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
-      b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells, b_slot_lf, b_fbeg,
-      b_face_loc, b_in_ptr, b_in_face, b_in_loc, b_h2_ptr, b_h2_cells, b_h1_loc, b_h1_face;
+      b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells, b_slot_code, b_bnd_ptr, b_bnd_face, b_bnd_loc, b_fbeg,
+      b_face_loc, b_in_ptr, b_in_face, b_in_loc, b_h2_ptr, b_h2_cells, b_h1_loc, b_h1_mg,
+      b_slot_mg;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
   bool pinned_owned = true;
@@ -358,11 +374,12 @@ void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, cons
 void launch_set_scalars(double* d, const double* h_values, int n, hipStream_t s);
 void build_union(jfnk_mesh& m, UnionArrays& ua);
 // The fused J v pass fits a tiled union: tile positions fit 16 bits, the
-// face entries of a tile one register round, the copy a workgroup's LDS.
+// face entries of a tile one register round (internal faces kEnt per lane,
+// boundary faces one per lane), the copy a workgroup's LDS.
 inline bool fused_fits(int dim, const UnionArrays& ua) {
   const int64_t ring = kFvBlock + ua.halo_max + ua.h2_max;
-  return ring < 32768 && ua.faces_max <= kFusedFaceEntries &&
-         fused_lds_bytes(dim, ring, kFvBlock + ua.halo_max, std::max<int64_t>(ua.faces_max, 1)) <=
+  return ring < 32768 && ua.faces_max <= kFusedFaceEntries && ua.bnd_max <= kFvBlock &&
+         fused_lds_bytes(dim, ring, kFvBlock + ua.halo_max, std::max<int64_t>(ua.ent_max, 1)) <=
              size_t(kFluxLdsBytes) * 2;
 }
 // Upload the union of m's segments on stream s (mesh handle setup).

@@ -722,7 +722,12 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   ua.slot_loc.clear();
   if (U.tiled) {
     ua.slot_loc.assign(ua.slot_nb.size(), kSlotPad);
-    ua.slot_lf.assign(ua.slot_nb.size(), int16_t(-1));
+    ua.slot_code.assign(ua.slot_nb.size(), -1);
+    ua.bnd_ptr.assign(n_blocks + 1, 0);
+    ua.bnd_face.clear();
+    ua.bnd_loc.clear();
+    ua.bnd_max = 0;
+    ua.ent_max = 0;
     ua.fbeg.assign(n_blocks + 1, 0);
     ua.face_loc.assign(size_t(U.n_int), 0);
     ua.in_ptr.assign(n_blocks + 1, 0);
@@ -736,7 +741,13 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     for (int64_t k = 0; k + 1 < int64_t(ua.slice_ptr.size()); ++k)
       ua.h1_width = std::max<int64_t>(ua.h1_width, (ua.slice_ptr[k + 1] - ua.slice_ptr[k]) / kSlice);
     ua.h1_loc.clear();
-    ua.h1_face.clear();
+    ua.h1_mg.clear();
+    ua.slot_mg.assign(ua.slot_nb.size(), 0.0);
+    for (size_t q = 0; q < ua.slot_nb.size(); ++q)
+      if (ua.slot_nb[q] >= 0) {
+        const int32_t fc = ua.slot_fc[q];
+        ua.slot_mg[q] = ua.magG[fc >= 0 ? fc : ~fc];
+      }
     {
       // owned faces of tile t: owners ascend with the face number (slice order)
       int64_t f = 0;
@@ -797,7 +808,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         const int64_t nh = int64_t(halo.size()), W = ua.h1_width;
         const size_t off = ua.h1_loc.size();
         ua.h1_loc.resize(off + size_t(nh * W), int16_t(kSlotPad));
-        ua.h1_face.resize(off + size_t(nh * W), 0);
+        ua.h1_mg.resize(off + size_t(nh * W), 0.0);
         const int32_t nh32 = int32_t(nh);
         auto local = [&](int32_t cell) -> int32_t {
           if (cell / kFvBlock == t) return int32_t(cell - c0);
@@ -812,10 +823,9 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
             const size_t e = off + size_t(k) * size_t(nh) + size_t(i);
             if (nb >= 0) {
               ua.h1_loc[e] = int16_t(local(nb));
-              ua.h1_face[e] = fc >= 0 ? fc : ~fc;
+              ua.h1_mg[e] = ua.magG[fc >= 0 ? fc : ~fc];
             } else {
               ua.h1_loc[e] = int16_t(nb);
-              ua.h1_face[e] = fc;
             }
           });
       }
@@ -834,20 +844,34 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
           const int32_t nb = ua.slot_nb[q], fc = ua.slot_fc[q];
           if (nb < 0) continue;
           if (fc >= 0) {
-            ua.slot_lf[q] = int16_t(fc - f0);
+            ua.slot_code[q] = 2 * (fc - f0);
           } else if (nb / kFvBlock == t) {
-            ua.slot_lf[q] = int16_t(~fc - f0);   // owner in this tile
+            ua.slot_code[q] = 2 * (~fc - f0) + 1;   // owner in this tile
           } else {
             ua.in_face.push_back(~fc);
             ua.in_loc.push_back(loc_of(U.fown[~fc]) | (loc_of(U.fnb[~fc]) << 16));
-            ua.slot_lf[q] = int16_t(n_own + n_in++);
+            ua.slot_code[q] = 2 * (n_own + n_in++) + 1;
           }
         }
       ua.in_ptr[t + 1] = int32_t(ua.in_face.size());
-      ua.faces_max = std::max<int64_t>(ua.faces_max, int64_t(n_own) + n_in);
+      // boundary faces after the internal ones
+      const int32_t n_ent = n_own + n_in;
+      int32_t n_b = 0;
+      for (int64_t sl = sl0; sl <= sl1; ++sl)
+        for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
+          if (ua.slot_nb[q] != kSlotBoundary) continue;
+          const int32_t cell = int32_t(sl * kSlice + (q - ua.slice_ptr[sl]) % kSlice);
+          ua.bnd_face.push_back(ua.slot_fc[q]);
+          ua.bnd_loc.push_back(int32_t(cell - c0));
+          ua.slot_code[q] = 2 * (n_ent + n_b++);
+        }
+      ua.bnd_ptr[t + 1] = int32_t(ua.bnd_face.size());
+      ua.faces_max = std::max<int64_t>(ua.faces_max, n_ent);
+      ua.bnd_max = std::max<int64_t>(ua.bnd_max, n_b);
+      ua.ent_max = std::max<int64_t>(ua.ent_max, int64_t(n_ent) + n_b);
     }
     JFNK_REQUIRE(ua.halo_max <= tile_halo_limit(dim), JFNK_E_MESH, "mesh: tile halo exceeds the LDS budget");
-    JFNK_REQUIRE(ua.faces_max < 32768, JFNK_E_MESH, "mesh: too many faces inside a tile");
+    JFNK_REQUIRE(ua.ent_max < 32768, JFNK_E_MESH, "mesh: too many faces inside a tile");
   }
   ua.pc_dinv.resize(N);
   for (int64_t c = 0; c < N; ++c) ua.pc_dinv[c] = 1.0 / U.pc_diag[c];
