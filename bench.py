@@ -55,6 +55,8 @@ def measured_traffic(kernel, dim, law, shape, lds):
     tiled = "_tiled" if lds else ""
     name = {"flux": "jfnk::k_flux%s<%d, 1>" % (tiled, dim),
             "gradient": "jfnk::k_gradient%s<%d>" % (tiled, dim)}.get(kernel)
+    if lds == 2 and kernel == "flux":
+        name = "jfnk::k_jv_fused<%d, 1>" % dim
     k = rec["kernels"].get(name)
     return k["traffic_bytes"] if k else None
 
@@ -76,30 +78,44 @@ def algorithmic_bytes(info, dim, lds_kernels):
     n_int, n_bnd, n_slots = info["n_internal_faces"], info["n_boundary_faces"], info["n_slots"]
     n_slices = (nc + 63) // 64
     n_tiles = (nc + 255) // 256
-    slots = n_slots * 8 + (n_slices + 1) * 4          # neighbour/local index and face index per slot
+    slice_ptr = (n_slices + 1) * 4
     vec = nd * 8
     xc = nc * dim * 8
     rec = nc * (dim + dim * dim) * 8                 # {w, grad w} per cell
     face = n_int * (dim + 1) * 8                     # Gamma_f, w_f
+    bface = n_bnd * 80                               # boundary-face records
     if lds_kernels:
-        halo = info["tile_halo_total"] * 4 + (n_tiles + 1) * 4
-        incoming = info["tile_incoming_total"] * 8 + (n_tiles + 1) * 4
-        return {
+        offs = (n_tiles + 1) * 4
+        halo = info["tile_halo_total"] * 4 + offs
+        # face list of the tiles: packed positions of owned faces, incoming
+        # faces (number + positions), boundary faces (number + owner), offsets
+        flist = n_int * 4 + info["tile_incoming_total"] * 8 + n_bnd * 8 + 3 * offs
+        grad_slots = n_slots * (4 + 8) + slice_ptr   # tile position + |Gamma_f| per slot
+        codes = n_slots * 4 + slice_ptr              # face-list entry and side per slot
+        out = {
             "eps": 2 * vec,
-            # u, v, centroids, halo lists, |Gamma|, slot map; writes the record
-            "gradient": 2 * vec + xc + halo + n_int * 8 + slots + rec,
-            # record, centroids, halo lists, face data and packed positions, incoming
-            # faces, tile face offsets, boundary records, slot map + slot face entry,
-            # R(u); writes J v
-            "flux": rec + xc + halo + face + n_int * 4 + incoming + (n_tiles + 1) * 4 + n_bnd * 80
-                    + slots + n_slots * 2 + 2 * vec,
+            # u, v, centroids, halo lists, slot positions and areas; writes the record
+            "gradient": 2 * vec + xc + halo + grad_slots + rec,
+            # record, centroids, halo lists, face data, tile face lists, boundary
+            # records, slot codes, R(u); writes J v
+            "flux": rec + xc + halo + face + flist + bface + codes + 2 * vec,
         }
+        if lds_kernels == 2:
+            # one pass: u, v, centroids, halo and second-ring lists, slot
+            # positions and areas of the tile cells and of the halo cells
+            # (their lists, one per halo entry and slot), the flux's face data
+            # and codes, R(u); writes J v -- no record
+            per_cell_slots = n_slots / max(nc, 1)
+            ring = (info["tile_halo_total"] + info["tile_ring2_total"]) * 4 + 2 * offs
+            halo_slots = int(info["tile_halo_total"] * per_cell_slots * (2 + 8))
+            out["fused"] = (3 * vec + xc + ring + grad_slots + halo_slots + face + flist + bface + codes)
+        return out
     return {
         "eps": 2 * vec,
         # reads u, v, centroids, |Gamma|, slot map; writes the record
-        "gradient": 2 * vec + xc + n_int * 8 + slots + rec,
+        "gradient": 2 * vec + xc + n_int * 8 + n_slots * 8 + slice_ptr + rec,
         # reads record, centroids, Gamma and w_f, boundary records, slot map, R(u); writes J v
-        "flux": rec + xc + face + n_bnd * 80 + slots + 2 * vec,
+        "flux": rec + xc + face + bface + n_slots * 8 + slice_ptr + 2 * vec,
     }
 
 
@@ -294,6 +310,9 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotune)")
+    ap.add_argument("--cell-passes", type=str, default=None,
+                    help="pin the cell passes instead of tuning: P/G with P = 0 gathers, 1 LDS passes, "
+                         "2 fused pass and G = persistent workgroups (0: one per tile), e.g. 1/1024")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-solve and serving measurements")
     ap.add_argument("--batch-problems", type=int, default=48,
@@ -333,7 +352,12 @@ def main():
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     ud, vd = gm.to_internal(dev(u_ext)), gm.to_internal(dev(v_ext))
     tune = None
-    if not args.no_tune:
+    if args.cell_passes:
+        p, g = (int(x) for x in args.cell_passes.split("/"))
+        jfnk.set_cell_passes(gm, p, g)
+        tune = {"lds_kernels": p, "persist": g, "pinned": True}
+        log("cell passes pinned: %d/%d" % (p, g))
+    elif not args.no_tune:
         # the project's tuner picks the cell-pass launch shape (and Arnoldi
         # schedule) on this mesh and state; untimed, reported
         t = time.time()
@@ -374,14 +398,18 @@ def main():
         jfnk.jv(gm, 1.0, ud, Ru, vd, 0.0, Jv, work)
     prof = jfnk.profile_read(gm, reset=True)
     jfnk.profile_enable(gm, False)
-    ab = algorithmic_bytes(gm.info, 3, tune["lds_kernels"] if tune else gm.info["tiled"])
+    lds = tune["lds_kernels"] if tune else gm.info["tiled"]
+    ab = algorithmic_bytes(gm.info, 3, lds)
+    if lds == 2:
+        # one fused pass, timed as the flux class
+        ab = {"eps": ab["eps"], "flux": ab["fused"]}
     kern = {}
-    for name in ("eps", "gradient", "flux"):
+    for name in ab:
         ms, calls = prof[name]
         avg = ms / max(calls, 1)
         kern[name] = dict(avg_ms=avg, calls=calls, bytes=ab[name],
                           gbs=ab[name] / (avg * 1e-3) / 1e9 if avg > 0 else None)
-    dom = max(("gradient", "flux"), key=lambda k: kern[k]["avg_ms"])
+    dom = max((k for k in kern if k != "eps"), key=lambda k: kern[k]["avg_ms"])
     ach = kern[dom]["gbs"]
     total_bytes = sum(ab.values())
     log("kernels: " + json.dumps(kern))
@@ -444,8 +472,7 @@ def main():
                    "law": mat.law, "cells": gm.n_cells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS if ach else None,
-                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz),
-                                                 tune["lds_kernels"] if tune else gm.info["tiled"]),
+                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz), lds),
                      "kernel": dom, "algorithmic_bytes": kern[dom]["bytes"]},
         "jv_hbm_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "kernels": kern,

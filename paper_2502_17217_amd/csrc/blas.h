@@ -44,6 +44,8 @@ void blas_lincomb(double a, const double* x, double b, const double* z, double* 
                   hipStream_t s);
 // ---- fused reductions (cgs_kernels.hip) ----
 void fill_int(int32_t* d, int n, int32_t v, hipStream_t s);
+// One launch: tickets[0..nt) = 0 and load[0..S) = value.
+void call_setup(int32_t* tickets, int nt, double* load, int S, double value, hipStream_t s);
 // true if some segment has more tiles than the in-kernel finish handles
 bool any_large_segment(const SegLayout& L, const int32_t* h_block_first);
 // eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| per active segment

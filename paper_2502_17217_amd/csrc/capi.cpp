@@ -579,8 +579,7 @@ jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
-    fw.zero_counters(s);
-    fill_device(fw.load, mesh->n_seg(), load, s);
+    fw.setup(s, load);
     residual_into(mesh, d_u, d_R, fw, nullptr, s);
   });
 }
@@ -600,8 +599,7 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
-    fw.zero_counters(s);
-    fill_device(fw.load, mesh->n_seg(), load, s);
+    fw.setup(s, load);
     const double* Ru = d_Ru;
     if (!Ru) {
       residual_into(mesh, d_u, fw.ru, fw, nullptr, s);
@@ -635,10 +633,9 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
-    fw.zero_counters(s);
+    fw.setup(s, load);
     KrylovWork kw;
     kw.carve(c, mesh, opts->restart, precond_work_floats(mesh, opts->precond));
-    fill_device(fw.load, mesh->n_seg(), load, s);
     precond_setup(mesh, opts->precond, s);
     double t_ms[8] = {0};
     std::vector<GmresSeg> r;

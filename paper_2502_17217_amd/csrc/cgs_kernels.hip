@@ -184,32 +184,47 @@ __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* 
 // + kBlock, + 2 kBlock, ... added in that order; the loads of eight
 // consecutive terms are issued together (the order of the additions is
 // unchanged).
+template <int B>
 __device__ __forceinline__ double strided_column_sum(const SegLayout& L, const double* __restrict__ partials,
                                                      int col, int first, int n) {
   constexpr int kU = 8;
   double s = 0;
   int b = first + threadIdx.x;
-  for (; b + (kU - 1) * kBlock < first + n; b += kU * kBlock) {
+  for (; b + (kU - 1) * B < first + n; b += kU * B) {
     double x[kU];
 #pragma unroll
-    for (int i = 0; i < kU; ++i) x[i] = partials[pidx(L, col, b + i * kBlock)];
+    for (int i = 0; i < kU; ++i) x[i] = partials[pidx(L, col, b + i * B)];
 #pragma unroll
     for (int i = 0; i < kU; ++i) s += x[i];
   }
-  for (; b < first + n; b += kBlock) s += partials[pidx(L, col, b)];
+  for (; b < first + n; b += B) s += partials[pidx(L, col, b)];
   return s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_large(SegLayout L, const double* __restrict__ partials,
-                                                         int col0, const int32_t* __restrict__ act,
-                                                         double* __restrict__ out, int ldo) {
-  __shared__ double sh[4];
+// Sum over a kWideBlock-thread workgroup (16 wavefronts in fixed order);
+// valid in thread 0.
+constexpr int kWideBlock = 1024;
+__device__ __forceinline__ double wide_block_sum(double x, double* sh) {
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kWideBlock / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kWideBlock) void k_reduce_large(SegLayout L, const double* __restrict__ partials,
+                                                             int col0, const int32_t* __restrict__ act,
+                                                             double* __restrict__ out, int ldo) {
+  __shared__ double sh[kWideBlock / 64];
   const int k = blockIdx.x, seg = blockIdx.y;
   if (act != nullptr && act[seg] == 0) return;
   int first, n;
   if (small_segment(L, seg, first, n)) return;
-  double s = strided_column_sum(L, partials, col0 + k, first, n);
-  s = block_sum(s, sh);
+  double s = strided_column_sum<kWideBlock>(L, partials, col0 + k, first, n);
+  s = wide_block_sum(s, sh);
   if (threadIdx.x == 0) out[size_t(seg) * ldo + k] = s;
 }
 
@@ -230,8 +245,9 @@ __device__ __forceinline__ double eps_of(double uu, double vv) {
 // for a small segment the last of its tiles to finish adds them (one tile
 // per lane) and writes eps, a large one is finished by k_eps_large (no
 // arrival counter shared by thousands of tiles).  A workgroup sums
-// kEpsTiles tiles at once (each tile's partial as tile_norm2 forms it), so
-// that all their loads are in flight together.
+// kEpsTiles tiles at once, every load issued before the first sum (each
+// tile's partial formed as tile_norm2 forms it).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double* __restrict__ u,
                                                       const double* __restrict__ v,
                                                       const int32_t* __restrict__ act,
@@ -239,28 +255,33 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
                                                       double* __restrict__ eps) {
   __shared__ double wsum[4][2 * kEpsTiles];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = L.n_cells;
   for (int b0 = blockIdx.x * kEpsTiles; b0 < L.n_blocks; b0 += gridDim.x * kEpsTiles) {
-    double su[kEpsTiles], sv[kEpsTiles];
+    double x[kEpsTiles][D], y[kEpsTiles][D];
 #pragma unroll
     for (int j = 0; j < kEpsTiles; ++j) {
-      su[j] = sv[j] = 0.0;
       const int blk = b0 + j;
       const int c = blk * kFvBlock + threadIdx.x;
-      if (blk < L.n_blocks && c < L.n_cells && (act == nullptr || act[L.seg_of_block[blk]] != 0))
-        for (int q = 0; q < L.dim; ++q) {
-          const double x = u[size_t(q) * L.n_cells + c];
-          const double y = v[size_t(q) * L.n_cells + c];
-          su[j] = fma(x, x, su[j]);
-          sv[j] = fma(y, y, sv[j]);
-        }
+      const bool on = blk < L.n_blocks && c < n && (act == nullptr || act[L.seg_of_block[blk]] != 0);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        x[j][q] = on ? u[size_t(q) * n + c] : 0.0;
+        y[j][q] = on ? v[size_t(q) * n + c] : 0.0;
+      }
     }
 #pragma unroll
     for (int j = 0; j < kEpsTiles; ++j) {
-      su[j] = wave_sum(su[j]);
-      sv[j] = wave_sum(sv[j]);
+      double su = 0.0, sv = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        su = fma(x[j][q], x[j][q], su);
+        sv = fma(y[j][q], y[j][q], sv);
+      }
+      su = wave_sum(su);
+      sv = wave_sum(sv);
       if (lane == 0) {
-        wsum[wave][2 * j] = su[j];
-        wsum[wave][2 * j + 1] = sv[j];
+        wsum[wave][2 * j] = su;
+        wsum[wave][2 * j + 1] = sv;
       }
     }
     __syncthreads();
@@ -275,10 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
       if (blk >= L.n_blocks) break;
       const int seg = L.seg_of_block[blk];
       if (act != nullptr && act[seg] == 0) continue;
-      int first, n;
-      if (small_segment(L, seg, first, n) && last_tile_of_segment(tickets + seg, n) && threadIdx.x < 64) {
-        const double tu = segment_column_sum(L, partials, first, n, 0);
-        const double tv = segment_column_sum(L, partials, first, n, 1);
+      int first, cnt;
+      if (small_segment(L, seg, first, cnt) && last_tile_of_segment(tickets + seg, cnt) && threadIdx.x < 64) {
+        const double tu = segment_column_sum(L, partials, first, cnt, 0);
+        const double tv = segment_column_sum(L, partials, first, cnt, 1);
         if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
       }
     }
@@ -286,19 +307,30 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
   }
 }
 
-// Large segments: tile b to lane (b - first) mod kBlock, then a fixed tree.
-__global__ __launch_bounds__(kBlock) void k_eps_large(SegLayout L, const double* __restrict__ partials,
-                                                      const int32_t* __restrict__ act, double* __restrict__ eps) {
-  __shared__ double sh[4];
+// Large segments, one workgroup of kWideBlock threads each: tile b to
+// thread (b - first) mod kWideBlock, then a fixed tree.
+__global__ __launch_bounds__(kWideBlock) void k_eps_large(SegLayout L, const double* __restrict__ partials,
+                                                          const int32_t* __restrict__ act,
+                                                          double* __restrict__ eps) {
+  __shared__ double sh[kWideBlock / 64];
   const int seg = blockIdx.x;
   if (act != nullptr && act[seg] == 0) return;
   int first, n;
   if (small_segment(L, seg, first, n)) return;
-  double su = strided_column_sum(L, partials, 0, first, n);
-  double sv = strided_column_sum(L, partials, 1, first, n);
-  su = block_sum(su, sh);
-  sv = block_sum(sv, sh);
+  double su = strided_column_sum<kWideBlock>(L, partials, 0, first, n);
+  double sv = strided_column_sum<kWideBlock>(L, partials, 1, first, n);
+  su = wide_block_sum(su, sh);
+  sv = wide_block_sum(sv, sh);
   if (threadIdx.x == 0) eps[seg] = eps_of(su, sv);
+}
+
+// Per-call set-up of a workspace: arrival counters to zero, the load factor
+// of every segment.
+__global__ void k_call_setup(int32_t* __restrict__ tickets, int nt, double* __restrict__ load, int S,
+                             double value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nt) tickets[i] = 0;
+  if (i < S) load[i] = value;
 }
 
 __global__ void k_fill_int(int32_t* d, int n, int32_t v) {
@@ -314,6 +346,12 @@ bool any_large_segment(const SegLayout& L, const int32_t* h_block_first) {
   return false;
 }
 
+void call_setup(int32_t* tickets, int nt, double* load, int S, double value, hipStream_t s) {
+  const int n = nt > S ? nt : S;
+  hipLaunchKernelGGL(k_call_setup, dim3((n + 255) / 256), dim3(256), 0, s, tickets, nt, load, S, value);
+  JFNK_HIP(hipGetLastError());
+}
+
 void fill_int(int32_t* d, int n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, d, n, v);
   JFNK_HIP(hipGetLastError());
@@ -322,8 +360,11 @@ void fill_int(int32_t* d, int n, int32_t v, hipStream_t s) {
 void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
                       double* partials, int32_t* tickets, double* eps, hipStream_t s) {
   const int grid = (L.n_blocks + kEpsTiles - 1) / kEpsTiles;
-  hipLaunchKernelGGL(k_eps_tiles, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
-  if (any_large) hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kBlock), 0, s, L, partials, act, eps);
+  if (L.dim == 3)
+    hipLaunchKernelGGL(k_eps_tiles<3>, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
+  else
+    hipLaunchKernelGGL(k_eps_tiles<2>, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
+  if (any_large) hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kWideBlock), 0, s, L, partials, act, eps);
   JFNK_HIP(hipGetLastError());
 }
 
@@ -331,21 +372,22 @@ void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv,
                double* h, double* h2, double* nrm, double* partials, int32_t* tickets, int32_t* counters,
                const GmresDev& G, int j, int max_it, hipStream_t s) {
   const int32_t* act = G.act;
-  const dim3 g(L.n_blocks), b(kBlock);
+  const dim3 g(L.n_blocks), b(kBlock), wide(kWideBlock);
   // pass 1
   hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, nullptr, act, partials, tickets, h, nrm);
   if (any_large) {
-    hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), b, 0, s, L, partials, 0, act, h, kMaxBasis);
-    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), b, 0, s, L, partials, nk, act, nrm + 1, 4);
+    hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), wide, 0, s, L, partials, 0, act, h, kMaxBasis);
+    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, nk, act, nrm + 1, 4);
   }
   // pass 2
   hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, h, act, partials, tickets, h2, nrm);
-  if (any_large) hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), b, 0, s, L, partials, 0, act, h2, kMaxBasis);
+  if (any_large)
+    hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), wide, 0, s, L, partials, 0, act, h2, kMaxBasis);
   // pass 3 (+ Givens when every segment is small)
   hipLaunchKernelGGL(k_cgs_last, g, b, 0, s, L, V, ldv, nk, w, h, h2, act, partials, tickets, counters, nrm, G, j,
                      max_it, any_large ? 0 : 1);
   if (any_large) {
-    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), b, 0, s, L, partials, 0, act, nrm, 4);
+    hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, 0, act, nrm, 4);
     gmres_step_finish(G, L.n_seg, j, max_it, h, h2, nrm, s);
   }
   JFNK_HIP(hipGetLastError());

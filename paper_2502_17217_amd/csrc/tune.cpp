@@ -37,10 +37,9 @@ void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o_in, const double* u, double
   Carver c(work);
   FvWork fw;
   fw.carve(c, m);
-  fw.zero_counters(s);
+  fw.setup(s, load);
   KrylovWork kw;
   kw.carve(c, m, o_in.restart, precond_work_floats(m, o_in.precond));
-  fill_device(fw.load, S, load, s);
   precond_setup(m, o_in.precond, s);
   const bool prof = m->prof.on;
   m->prof.on = false;

@@ -52,6 +52,8 @@ struct FvWork {
   int32_t* step_counters() const { return tickets + 2 * S; }
   // The caller's workspace starts uninitialised: clear the counters once.
   void zero_counters(hipStream_t s) const { fill_int(tickets, 2 * S + 8, 0, s); }
+  // zero_counters and the same load factor for every segment, in one launch
+  void setup(hipStream_t s, double load_value) const { call_setup(tickets, 2 * S + 8, load, S, load_value, s); }
   void carve(Carver& c, const jfnk_mesh* m) { carve(c, m->host.n_cells, m->host.dim, m->n_seg()); }
 };
 
