@@ -40,7 +40,7 @@ def measured_traffic(kernel, dim, law, shape, lds):
     workload)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "jv_kernels_nh_cantilever_1M_traffic.md")
+    path = os.path.join(ROOT, "profiles", "jv_kernels_nh_cantilever_1M%s_traffic.md" % ("_fused" if lds == 2 else ""))
     if shape != (1000, 100, 10) or law != "neo_hookean" or not os.path.exists(path):
         return None
     block = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)

@@ -138,6 +138,7 @@ typedef struct {
   int32_t tile_ring2_max;      /* largest second ring of a tile: outside cells adjacent to its halo */
   int64_t tile_ring2_total;    /* sum over tiles of their second rings */
   int32_t tile_faces_max;      /* largest number of internal faces touching one tile */
+  int32_t tile_entries_max;    /* largest number of faces (internal and boundary) touching one tile */
   int32_t fused;               /* 1: the single-pass J.v kernel fits (tile, two rings and faces in LDS) */
 } jfnk_mesh_info;
 

@@ -345,6 +345,7 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   in.tile_ring2_max = int32_t(ua.h2_max);
   in.tile_ring2_total = int64_t(ua.h2_cells.size());
   in.tile_faces_max = int32_t(ua.faces_max);
+  in.tile_entries_max = int32_t(ua.ent_max);
   in.fused = d.fused;
   in.setup_ms = now_ms() - t0;
 }
@@ -463,6 +464,7 @@ jfnk_status jfnk_inspect_mesh(const jfnk_mesh_desc* desc, const jfnk_material* m
       info->tile_ring2_max = int32_t(ua.h2_max);
       info->tile_ring2_total = int64_t(ua.h2_cells.size());
       info->tile_faces_max = int32_t(ua.faces_max);
+      info->tile_entries_max = int32_t(ua.ent_max);
       info->fused = fused_fits(h.dim, ua) ? 1 : 0;
     }
     for (int64_t i = 0; i < h.n_cells; ++i) {

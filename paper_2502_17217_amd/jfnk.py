@@ -49,7 +49,8 @@ class jfnk_mesh_info(C.Structure):
                 ("n_slots", C.c_int64), ("n_segments", C.c_int32), ("n_dof_external", C.c_int64),
                 ("tiled", C.c_int32), ("tile_halo_max", C.c_int32), ("tile_halo_total", C.c_int64),
                 ("tile_incoming_total", C.c_int64), ("tile_ring2_max", C.c_int32),
-                ("tile_ring2_total", C.c_int64), ("tile_faces_max", C.c_int32), ("fused", C.c_int32)]
+                ("tile_ring2_total", C.c_int64), ("tile_faces_max", C.c_int32), ("tile_entries_max", C.c_int32),
+                ("fused", C.c_int32)]
 
 
 class jfnk_gmres_opts(C.Structure):
