@@ -291,6 +291,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     SegLayout L;
     L.n_seg = S;
     m.any_large = any_large_segment(L, m.block_first.data());
+    m.any_small = false;
+    for (int k = 0; k < S; ++k) m.any_small = m.any_small || m.block_first[k + 1] - m.block_first[k] <= kFuseTiles;
   }
   d.tiled = h.tiled ? 1 : 0;
   d.lds_kernels = d.tiled;
@@ -581,7 +583,7 @@ jfnk_status jfnk_residual(jfnk_mesh* mesh, double load, const double* d_u, doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
-    fw.setup(s, load);
+    fw.setup_uniform(s, load, mesh->any_small);
     residual_into(mesh, d_u, d_R, fw, nullptr, s);
   });
 }
@@ -601,7 +603,7 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
     Carver c(d_work);
     FvWork fw;
     fw.carve(c, mesh);
-    fw.setup(s, load);
+    fw.setup_uniform(s, load, mesh->any_small);
     const double* Ru = d_Ru;
     if (!Ru) {
       residual_into(mesh, d_u, fw.ru, fw, nullptr, s);

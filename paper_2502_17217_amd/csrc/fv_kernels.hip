@@ -698,7 +698,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
       continue;
     }
     const FluxGlobal<D> src{rec, m.xc, n};
-    flux_cell<D, LAWSEL>(m, si, src, m.slot_nb, c, c, sc.load[seg], Ru ? sc.eps[seg] : 0.0, Ru, out);
+    flux_cell<D, LAWSEL>(m, si, src, m.slot_nb, c, c, sc.load_at(seg), Ru ? sc.eps[seg] : 0.0, Ru, out);
   }
 }
 
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     const FluxLds<D> src{lds, S};
     // phase A: boundary faces (entries n_ent + eb), one per lane per round
     {
-      const double load = sc.load[seg];
+      const double load = sc.load_at(seg);
       for (int eb = threadIdx.x; eb < n_bnd; eb += kFvBlock) {
         if (eb != int(threadIdx.x)) load_bnd(m, tile, eb, be);
         double f[D];
@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FUSED_MINWAVES) void k_jv_fused(Mesh
       const FusedLds<D> src{wx, gl, R, S};
       if (be.loc >= 0) {
         double f[D];
-        bnd_force_sel<D, LAWSEL>(si, src, be, sc.load[seg], f);
+        bnd_force_sel<D, LAWSEL>(si, src, be, sc.load_at(seg), f);
 #pragma unroll
         for (int q = 0; q < D; ++q) bl[q * kFvBlock + threadIdx.x] = f[q];
       }

@@ -176,10 +176,17 @@ struct MeshDev {
 };
 
 // Per-call, per-segment device scalars.
+// Segments with at most this many tiles finish their sums inside the
+// producing kernel (in its last tile); larger ones use a separate reduction
+// launch spread over many workgroups.
+constexpr int kFuseTiles = 64;
+
 struct SegScalars {
   const double* eps;         // [n_seg] J v step (null: residual evaluation)
-  const double* load;        // [n_seg] load factor
+  const double* load;        // [n_seg] load factor, or null: load1 for every segment
   const int32_t* active;     // [n_seg] or null: segments with 0 are skipped
+  double load1 = 0.0;
+  __host__ __device__ double load_at(int seg) const { return load != nullptr ? load[seg] : load1; }
 };
 
 // Host-side result of mesh preprocessing (all in internal numbering).
@@ -348,6 +355,7 @@ struct jfnk_mesh {
   jfnk::Tuning tune;
   hipStream_t solve_stream = nullptr;   // own stream for graph capture when the caller passes the null stream
   bool any_large = true;                // a segment has more tiles than the fused reductions finish in-kernel
+  bool any_small = true;                // a segment is finished in-kernel (uses the arrival counters)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int n_seg() const { return int(segs.size()); }
   jfnk_mesh() = default;

@@ -89,7 +89,7 @@ void fill_device(double* d, int64_t n, double value, hipStream_t s) {
 void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const int32_t* active,
                    hipStream_t s) {
   Profiler& p = m->prof;
-  SegScalars sc{nullptr, fw.load, active};
+  SegScalars sc{nullptr, fw.load_ptr(), active, fw.load1};
   if (m->dev.lds_kernels == 2) {
     const int t = p.on ? p.begin(2, s) : -1;
     launch_fused(m->dev, u, nullptr, sc, nullptr, R, s);
@@ -113,7 +113,7 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
   else
     launch_eps_fused(layout_of(m), m->any_large, u, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
   if (t >= 0) p.end(t, s);
-  SegScalars sc{fw.eps, fw.load, active};
+  SegScalars sc{fw.eps, fw.load_ptr(), active, fw.load1};
   if (m->dev.lds_kernels == 2) {
     t = p.on ? p.begin(2, s) : -1;
     launch_fused(m->dev, u, v, sc, Ru, Jv, s);

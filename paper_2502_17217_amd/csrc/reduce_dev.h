@@ -43,9 +43,5 @@ __device__ __forceinline__ bool last_tile_of_segment(int32_t* counter, int n) {
   return last != 0;
 }
 
-// Segments with at most this many tiles finish their sums inside the
-// producing kernel (in its last tile); larger ones use a separate reduction
-// launch spread over many workgroups.
-constexpr int kFuseTiles = 64;
 
 }  // namespace jfnk

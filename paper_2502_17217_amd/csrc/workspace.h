@@ -54,6 +54,17 @@ struct FvWork {
   void zero_counters(hipStream_t s) const { fill_int(tickets, 2 * S + 8, 0, s); }
   // zero_counters and the same load factor for every segment, in one launch
   void setup(hipStream_t s, double load_value) const { call_setup(tickets, 2 * S + 8, load, S, load_value, s); }
+  // For one residual or J v with the same load factor everywhere: the factor
+  // travels as a kernel argument, and the counters are cleared only when a
+  // segment finishes its sums in-kernel (nothing to launch otherwise).
+  bool uniform = false;
+  double load1 = 0.0;
+  void setup_uniform(hipStream_t s, double load_value, bool any_small) {
+    uniform = true;
+    load1 = load_value;
+    if (any_small) zero_counters(s);
+  }
+  const double* load_ptr() const { return uniform ? nullptr : load; }
   void carve(Carver& c, const jfnk_mesh* m) { carve(c, m->host.n_cells, m->host.dim, m->n_seg()); }
 };
 
