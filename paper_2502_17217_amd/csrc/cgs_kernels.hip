@@ -28,35 +28,45 @@ __device__ __forceinline__ bool small_segment(const SegLayout& L, int seg, int& 
   return n <= kFuseTiles;
 }
 
-// w -= sum_k coef[k] V_k on cell c of the tile (all components)
+// w -= sum_k coef[k] V_k on cell c of the tile (all D components at once;
+// each component's sum runs over k in order)
+template <int D>
 __device__ __forceinline__ void combine_cell(const SegLayout& L, const double* __restrict__ V, int64_t ldv,
                                              int nk, const double* __restrict__ coef, double* __restrict__ w,
                                              int c) {
-  for (int q = 0; q < L.dim; ++q) {
-    const size_t o = size_t(q) * L.n_cells + c;
-    double s = 0;
-    for (int k = 0; k < nk; ++k) s = fma(coef[k], V[k * ldv + o], s);
-    w[o] -= s;
+  double s[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    const double ck = coef[k];
+#pragma unroll
+    for (int q = 0; q < D; ++q) s[q] = fma(ck, V[k * ldv + size_t(q) * L.n_cells + c], s[q]);
   }
+#pragma unroll
+  for (int q = 0; q < D; ++q) w[size_t(q) * L.n_cells + c] -= s[q];
 }
 
 // Tile sums of V_k . w (k < nk): per-wavefront butterfly sums go to
 // wsum[wave][k] (store_tile_sums adds the four wavefronts in fixed order).
+template <int D>
 __device__ __forceinline__ void tile_dots(const SegLayout& L, const double* __restrict__ V, int64_t ldv,
                                           int nk, const double* __restrict__ w, int c,
                                           double (*wsum)[kMaxBasis]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double wi[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) wi[q] = c < L.n_cells ? w[size_t(q) * L.n_cells + c] : 0.0;
   for (int k0 = 0; k0 < nk; k0 += 8) {
     double acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     if (c < L.n_cells) {
-      for (int q = 0; q < L.dim; ++q) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
         const size_t o = size_t(q) * L.n_cells + c;
-        const double wi = w[o];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-          if (k0 + k < nk) acc[k] = fma(V[(k0 + k) * ldv + o], wi, acc[k]);
+          if (k0 + k < nk) acc[k] = fma(V[(k0 + k) * ldv + o], wi[q], acc[k]);
       }
     }
 #pragma unroll
@@ -84,14 +94,17 @@ __device__ __forceinline__ double segment_column_sum(const SegLayout& L, const d
 }
 
 // |w|^2 over the tile's cells: per-wavefront sums into wsum[wave][col].
+template <int D>
 __device__ __forceinline__ void tile_norm2(const SegLayout& L, const double* __restrict__ w, int c,
                                            double (*wsum)[kMaxBasis], int col) {
   double s = 0;
-  if (c < L.n_cells)
-    for (int q = 0; q < L.dim; ++q) {
-      const double x = w[size_t(q) * L.n_cells + c];
-      s = fma(x, x, s);
-    }
+  if (c < L.n_cells) {
+    double x[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) x[q] = w[size_t(q) * L.n_cells + c];
+#pragma unroll
+    for (int q = 0; q < D; ++q) s = fma(x[q], x[q], s);
+  }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6][col] = s;
 }
@@ -107,6 +120,7 @@ __device__ __forceinline__ void store_tile_sums(const SegLayout& L, double (*wsu
 
 // Passes 1 and 2.  coef == nullptr: pass 1 (also |w|^2 into column nk,
 // finished into nrm[4 seg + 1]); otherwise pass 2 (w -= V coef first).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_cgs_pass(SegLayout L, const double* __restrict__ V, int64_t ldv,
                                                      int nk, double* __restrict__ w,
                                                      const double* __restrict__ coef,
@@ -118,10 +132,10 @@ __global__ __launch_bounds__(kBlock) void k_cgs_pass(SegLayout L, const double* 
   const int seg = L.seg_of_block[blk];
   if (act != nullptr && act[seg] == 0) return;
   const int c = blk * kFvBlock + threadIdx.x;
-  if (coef != nullptr && c < L.n_cells) combine_cell(L, V, ldv, nk, coef + size_t(seg) * kMaxBasis, w, c);
-  tile_dots(L, V, ldv, nk, w, c, wsum);
+  if (coef != nullptr && c < L.n_cells) combine_cell<D>(L, V, ldv, nk, coef + size_t(seg) * kMaxBasis, w, c);
+  tile_dots<D>(L, V, ldv, nk, w, c, wsum);
   const int ncol = coef == nullptr ? nk + 1 : nk;
-  if (coef == nullptr) tile_norm2(L, w, c, wsum, nk);
+  if (coef == nullptr) tile_norm2<D>(L, w, c, wsum, nk);
   store_tile_sums(L, wsum, ncol, partials, blk);
   int first, n;
   if (!small_segment(L, seg, first, n)) return;
@@ -142,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs_pass(SegLayout L, const double* 
 // Pass 3: w -= V h2, |w|^2 into nrm[4 seg]; with finish != 0 (every segment
 // small) the last tile of each segment also takes the Givens step, and the
 // last segment to finish publishes the count of segments still active.
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* __restrict__ V, int64_t ldv,
                                                      int nk, double* __restrict__ w,
                                                      const double* __restrict__ h1, const double* __restrict__ h2,
@@ -154,8 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* 
   const int seg = L.seg_of_block[blk];
   if (act_in[seg] == 0) return;
   const int c = blk * kFvBlock + threadIdx.x;
-  if (c < L.n_cells) combine_cell(L, V, ldv, nk, h2 + size_t(seg) * kMaxBasis, w, c);
-  tile_norm2(L, w, c, wsum, 0);
+  if (c < L.n_cells) combine_cell<D>(L, V, ldv, nk, h2 + size_t(seg) * kMaxBasis, w, c);
+  tile_norm2<D>(L, w, c, wsum, 0);
   store_tile_sums(L, wsum, 1, partials, blk);
   int first, n;
   if (!small_segment(L, seg, first, n)) return;
@@ -373,19 +388,30 @@ void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv,
                const GmresDev& G, int j, int max_it, hipStream_t s) {
   const int32_t* act = G.act;
   const dim3 g(L.n_blocks), b(kBlock), wide(kWideBlock);
+  const bool d3 = L.dim == 3;
   // pass 1
-  hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, nullptr, act, partials, tickets, h, nrm);
+  if (d3)
+    hipLaunchKernelGGL(k_cgs_pass<3>, g, b, 0, s, L, V, ldv, nk, w, nullptr, act, partials, tickets, h, nrm);
+  else
+    hipLaunchKernelGGL(k_cgs_pass<2>, g, b, 0, s, L, V, ldv, nk, w, nullptr, act, partials, tickets, h, nrm);
   if (any_large) {
     hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), wide, 0, s, L, partials, 0, act, h, kMaxBasis);
     hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, nk, act, nrm + 1, 4);
   }
   // pass 2
-  hipLaunchKernelGGL(k_cgs_pass, g, b, 0, s, L, V, ldv, nk, w, h, act, partials, tickets, h2, nrm);
+  if (d3)
+    hipLaunchKernelGGL(k_cgs_pass<3>, g, b, 0, s, L, V, ldv, nk, w, h, act, partials, tickets, h2, nrm);
+  else
+    hipLaunchKernelGGL(k_cgs_pass<2>, g, b, 0, s, L, V, ldv, nk, w, h, act, partials, tickets, h2, nrm);
   if (any_large)
     hipLaunchKernelGGL(k_reduce_large, dim3(nk, L.n_seg), wide, 0, s, L, partials, 0, act, h2, kMaxBasis);
   // pass 3 (+ Givens when every segment is small)
-  hipLaunchKernelGGL(k_cgs_last, g, b, 0, s, L, V, ldv, nk, w, h, h2, act, partials, tickets, counters, nrm, G, j,
-                     max_it, any_large ? 0 : 1);
+  if (d3)
+    hipLaunchKernelGGL(k_cgs_last<3>, g, b, 0, s, L, V, ldv, nk, w, h, h2, act, partials, tickets, counters, nrm, G,
+                       j, max_it, any_large ? 0 : 1);
+  else
+    hipLaunchKernelGGL(k_cgs_last<2>, g, b, 0, s, L, V, ldv, nk, w, h, h2, act, partials, tickets, counters, nrm, G,
+                       j, max_it, any_large ? 0 : 1);
   if (any_large) {
     hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, 0, act, nrm, 4);
     gmres_step_finish(G, L.n_seg, j, max_it, h, h2, nrm, s);
