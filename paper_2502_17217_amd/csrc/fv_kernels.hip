@@ -1,6 +1,8 @@
 // Residual and Jacobian-free J.v kernels for gfx950.
 //
-// Two passes over the cells, one lane per cell, gather-only (no atomics):
+// Two passes over the cells, one lane per cell, no atomics (gathered from
+// global memory, or staged per tile of 256 cells in LDS; a third form fuses
+// both passes per tile, see k_jv_fused):
 //   k_gradient: least-squares gradient of w = u + eps v (Eq. leastSquaresGrad,
 //               weights omega_f = |Gamma_f| in both the sum and G_P).  G_P is
 //               rebuilt from the cell centroids and face areas on the fly, so
@@ -702,14 +704,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FV_MINWAVES) void k_flux(MeshDev m, 
   }
 }
 
-// Tiled flux pass.  The records and centroids of the tile's cells and halo
-// are staged in LDS (rows of length halo_stride).  Phase A evaluates every
-// internal face touching the tile once, spread evenly over the workgroup
-// (owner first, the canonical operand order), into LDS; phase B sums each
-// cell's slots in slot order (face forces from LDS with the sign of the
-// side, boundary faces evaluated in place), the same sequence of operations
-// as the gather pass, so both give the same bits.  Exits before a barrier
-// are uniform over the workgroup.
+// Face-parallel evaluation in the LDS passes.
 // Face data of up to kEnt entries of the tile's face list (entries
 // e = threadIdx.x + j * kFvBlock), loaded before the staging barrier so that
 // every global load of the tile is in flight at once.
