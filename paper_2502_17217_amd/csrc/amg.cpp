@@ -401,13 +401,19 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
 
 namespace {
 
-void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s, const int32_t* gate) {
+// r64 / z64 (finest level only): the FP64 right-hand side, rounded into b
+// by the first smoothing launch, and the FP64 output z = -x, written by the
+// last one (the casts need no launches of their own).
+void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s, const int32_t* gate,
+            const double* r64 = nullptr, double* z64 = nullptr) {
   const AmgLevel& L = H.levels[l];
   const int dim = H.dim;
   float* x = w + L.off_x;
   float* b = w + L.off_b;
   if (l + 1 == H.levels.size()) {
+    if (r64) amg_cast_in(r64, b, L.n, dim, s, gate);
     amg_dense(H.coarse_inv.as<float>(), b, x, int(H.n_coarse), dim, s, gate);
+    if (z64) amg_cast_out(x, z64, L.n, dim, s, gate);
     return;
   }
   float* r = w + L.off_r;
@@ -416,7 +422,7 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s
   const float* dinv = L.dinv.as<float>();
   ChebCoef cc = cheb_coefficients(L.lmax, degree);
   // pre-smoothing from x = 0
-  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate);
+  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate, r64);
   for (int k = 0; k + 1 < degree; ++k) {
     amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate);
     std::swap(d0, d1);
@@ -427,12 +433,14 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s
   amg_spmv(L.R, r, w + C.off_b, false, dim, s, gate);
   vcycle(H, l + 1, degree, w, s, gate);
   amg_spmv(L.P, w + C.off_x, x, true, dim, s, gate);
-  // post-smoothing
+  // post-smoothing; the start's x += d rides on the first step's launch
   d0 = w + L.off_d0;
   d1 = w + L.off_d1;
-  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate);
+  const bool steps = degree > 1;
+  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate, steps, steps ? nullptr : z64);
   for (int k = 0; k + 1 < degree; ++k) {
-    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate);
+    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate, k == 0,
+                  k + 2 == degree ? z64 : nullptr);
     std::swap(d0, d1);
   }
 }
@@ -444,12 +452,9 @@ void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float*
   JFNK_REQUIRE(m->amg != nullptr, JFNK_E_ARG, "amg: not set up");
   JFNK_REQUIRE(work != nullptr, JFNK_E_ARG, "amg: no workspace");
   const AmgHierarchy& H = *m->amg;
-  const AmgLevel& L0 = H.levels[0];
   Profiler& p = m->prof;
   const int t = p.on ? p.begin(3, s) : -1;
-  amg_cast_in(r, work + L0.off_b, L0.n, H.dim, s, gate);
-  vcycle(H, 0, cheb_degree, work, s, gate);
-  amg_cast_out(work + L0.off_x, z, L0.n, H.dim, s, gate);
+  vcycle(H, 0, cheb_degree, work, s, gate, r, z);
   if (t >= 0) p.end(t, s);
 }
 

@@ -43,15 +43,20 @@ struct AmgHierarchy {
 // ---- kernels (amg_kernels.hip); vectors are component-major FP32 [dim][n] ----
 void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate);
 void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate);
-// Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d
-void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s, const int32_t* gate);
+// Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d; with r64
+// given, b = (float) r64 first (the finest level's FP64 input)
+void amg_cheb_start0(const DevCsr& A, const float* dinv, float* b, float* x, float* r, float* d,
+                     float inv_theta, int dim, hipStream_t s, const int32_t* gate, const double* r64 = nullptr);
 // Chebyshev start from a given x: r = D^-1 (b - A x), d = r/theta, x += d
+// (defer_axpy: the next step applies x += d; z64 given: also z = -x in FP64)
 void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s, const int32_t* gate);
+                    float inv_theta, int dim, hipStream_t s, const int32_t* gate, bool defer_axpy = false,
+                    double* z64 = nullptr);
 // one Chebyshev step: r -= D^-1 A d_in; d_out = c1 d_in + c2 r; x += d_out
+// (pend: x += d_in first, the deferred start update; z64 given: z = -x in FP64)
 void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate);
+                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate, bool pend = false,
+                   double* z64 = nullptr);
 // r = b - A x
 void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
                   const int32_t* gate);

@@ -42,11 +42,13 @@ __global__ __launch_bounds__(kB) void k_cast_out(const float* __restrict__ x, do
   if (i < total) z[i] = -double(x[i]);   // J_tilde = -A
 }
 
+// r64 != null (finest level): the right-hand side arrives in FP64 and is
+// rounded into b here (the cast that would otherwise be its own launch).
 template <int D>
 __global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restrict__ dinv,
-                                                    const float* __restrict__ b, float* __restrict__ x,
+                                                    float* __restrict__ b, float* __restrict__ x,
                                                     float* __restrict__ r, float* __restrict__ d,
-                                                    float inv_theta,
+                                                    float inv_theta, const double* __restrict__ r64,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
@@ -55,7 +57,14 @@ __global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restri
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
-    const float ri = di * b[o];
+    float bo;
+    if (r64 != nullptr) {
+      bo = float(r64[o]);
+      b[o] = bo;
+    } else {
+      bo = b[o];
+    }
+    const float ri = di * bo;
     const float dd = ri * inv_theta;
     r[o] = ri;
     d[o] = dd;
@@ -87,16 +96,25 @@ __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restr
   }
 }
 
+// x += d; z64 != null: also z = -x in FP64 (finest level, J_tilde = -A).
 template <int D>
 __global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restrict__ d, float* __restrict__ x,
+                                                     double* __restrict__ z64,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
-  for (int q = 0; q < D; ++q) x[size_t(q) * n + i] += d[size_t(q) * n + i];
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    const float xo = x[o] + d[o];
+    x[o] = xo;
+    if (z64 != nullptr) z64[o] = -double(xo);
+  }
 }
 
+// pend != 0: the previous start's x += d_in is still to be applied (it is,
+// first: x = (x + d_in) + dd); z64 != null: also z = -x in FP64.
 template <int D>
 __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col,
@@ -104,7 +122,7 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
                                                   const float* __restrict__ dinv,
                                                   const float* __restrict__ d_in, float* __restrict__ d_out,
                                                   float* __restrict__ r, float* __restrict__ x, float c1,
-                                                  float c2,
+                                                  float c2, int pend, double* __restrict__ z64,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
@@ -119,7 +137,11 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
     const float dd = fmaf(c1, d_in[o], c2 * ri);
     r[o] = ri;
     d_out[o] = dd;
-    x[o] += dd;
+    float xo = x[o];
+    if (pend) xo += d_in[o];
+    xo += dd;
+    x[o] = xo;
+    if (z64 != nullptr) z64[o] = -double(xo);
   }
 }
 
@@ -215,25 +237,27 @@ void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, 
   JFNK_HIP(hipGetLastError());
 }
 
-void amg_cheb_start0(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s, const int32_t* gate) {
+void amg_cheb_start0(const DevCsr& A, const float* dinv, float* b, float* x, float* r, float* d,
+                     float inv_theta, int dim, hipStream_t s, const int32_t* gate, const double* r64) {
   JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dinv, b, x, r, d,
-                    inv_theta, gate);
+                    inv_theta, r64, gate);
 }
 
 void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s, const int32_t* gate) {
+                    float inv_theta, int dim, hipStream_t s, const int32_t* gate, bool defer_axpy,
+                    double* z64) {
   // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
-  // by other rows' products in the first pass)
+  // by other rows' products in the first pass), or in the next step's launch
   JFNK_DIM_DISPATCH(dim, k_cheb_start, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
                     A.col.as<int32_t>(), A.val.as<float>(), dinv, b, x, r, d, inv_theta, gate);
-  JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, gate);
+  if (!defer_axpy) JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, z64, gate);
 }
 
 void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate) {
+                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate, bool pend, double* z64) {
   JFNK_DIM_DISPATCH(dim, k_cheb_step, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, gate);
+                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64,
+                    gate);
 }
 
 void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
