@@ -18,6 +18,7 @@ struct HostCsr {
 // Device CSR matrix (FP32 values).
 struct DevCsr {
   int32_t n = 0, m = 0;
+  int32_t lanes = 1;      // lanes that share a row in the row kernels (power of two, <= 64)
   DevBuf ptr, col, val;
   void upload(const HostCsr& h, hipStream_t s);
 };

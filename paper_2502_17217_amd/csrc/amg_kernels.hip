@@ -11,19 +11,35 @@ constexpr int kB = 256;
 
 inline int blocks_for(int64_t n) { return int((n + kB - 1) / kB); }
 
-template <int D>
+// Row i of a CSR matrix times x (D components), shared by the G lanes of a
+// group: lane `sub` takes nonzeros sub, sub + G, ..., then a fixed butterfly
+// over the group leaves the row's sums in every lane of it.
+template <int D, int G>
 __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                         const float* __restrict__ val, const float* __restrict__ x,
-                                        int m, int i, float (&s)[D]) {
+                                        int m, int i, int sub, float (&s)[D]) {
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.f;
   const int a = ptr[i], b = ptr[i + 1];
-  for (int k = a; k < b; ++k) {
+  for (int k = a + sub; k < b; k += G) {
     const float v = val[k];
     const int j = col[k];
 #pragma unroll
     for (int q = 0; q < D; ++q) s[q] = fmaf(v, x[size_t(q) * m + j], s[q]);
   }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < D; ++q) s[q] += __shfl_xor(s[q], off, G);
+  }
+}
+
+// Row and lane-in-group of this thread when G lanes share a row.
+template <int G>
+__device__ __forceinline__ int row_of(int& sub) {
+  sub = threadIdx.x % G;
+  return blockIdx.x * (kB / G) + threadIdx.x / G;
 }
 
 __global__ __launch_bounds__(kB) void k_cast_in(const double* __restrict__ r, float* __restrict__ b,
@@ -72,7 +88,7 @@ __global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restri
   }
 }
 
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col,
                                                    const float* __restrict__ val,
@@ -82,10 +98,12 @@ __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restr
                                                    float inv_theta,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int i = blockIdx.x * kB + threadIdx.x;
+  int sub;
+  const int i = row_of<G>(sub);
   if (i >= n) return;
   float s[D];
-  row_dot<D>(ptr, col, val, x, n, i, s);
+  row_dot<D, G>(ptr, col, val, x, n, i, sub, s);
+  if (sub != 0) return;
   const float di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -115,7 +133,7 @@ __global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restr
 
 // pend != 0: the previous start's x += d_in is still to be applied (it is,
 // first: x = (x + d_in) + dd); z64 != null: also z = -x in FP64.
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col,
                                                   const float* __restrict__ val,
@@ -125,10 +143,12 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
                                                   float c2, int pend, double* __restrict__ z64,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int i = blockIdx.x * kB + threadIdx.x;
+  int sub;
+  const int i = row_of<G>(sub);
   if (i >= n) return;
   float s[D];
-  row_dot<D>(ptr, col, val, d_in, n, i, s);
+  row_dot<D, G>(ptr, col, val, d_in, n, i, sub, s);
+  if (sub != 0) return;
   const float di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -145,31 +165,35 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
   }
 }
 
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ val, const float* __restrict__ b,
                                                  const float* __restrict__ x, float* __restrict__ r,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int i = blockIdx.x * kB + threadIdx.x;
+  int sub;
+  const int i = row_of<G>(sub);
   if (i >= n) return;
   float s[D];
-  row_dot<D>(ptr, col, val, x, n, i, s);
+  row_dot<D, G>(ptr, col, val, x, n, i, sub, s);
+  if (sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) r[size_t(q) * n + i] = b[size_t(q) * n + i] - s[q];
 }
 
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __restrict__ ptr,
                                              const int32_t* __restrict__ col, const float* __restrict__ val,
                                              const float* __restrict__ x, float* __restrict__ y, int accumulate,
     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int i = blockIdx.x * kB + threadIdx.x;
+  int sub;
+  const int i = row_of<G>(sub);
   if (i >= n) return;
   float s[D];
-  row_dot<D>(ptr, col, val, x, m, i, s);
+  row_dot<D, G>(ptr, col, val, x, m, i, sub, s);
+  if (sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
@@ -225,6 +249,32 @@ __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, con
     JFNK_HIP(hipGetLastError());                                                   \
   } while (0)
 
+// Row kernels: dimension and lanes per row (grid sized for lanes * n threads).
+#define JFNK_ROW_CASE(D, G, KERNEL, n, s, ...)                                                      \
+  case G:                                                                                          \
+    hipLaunchKernelGGL((KERNEL<D, G>), dim3(blocks_for(int64_t(n) * G)), dim3(kB), 0, s, __VA_ARGS__); \
+    break;
+#define JFNK_ROW_DISPATCH_D(D, lanes, KERNEL, n, s, ...)   \
+  switch (lanes) {                                        \
+    JFNK_ROW_CASE(D, 1, KERNEL, n, s, __VA_ARGS__)        \
+    JFNK_ROW_CASE(D, 2, KERNEL, n, s, __VA_ARGS__)        \
+    JFNK_ROW_CASE(D, 4, KERNEL, n, s, __VA_ARGS__)        \
+    JFNK_ROW_CASE(D, 8, KERNEL, n, s, __VA_ARGS__)        \
+    JFNK_ROW_CASE(D, 16, KERNEL, n, s, __VA_ARGS__)       \
+    JFNK_ROW_CASE(D, 32, KERNEL, n, s, __VA_ARGS__)       \
+    default:                                              \
+      JFNK_ROW_CASE(D, 64, KERNEL, n, s, __VA_ARGS__)     \
+  }
+#define JFNK_ROW_DISPATCH(dim, lanes, KERNEL, n, s, ...)                       \
+  do {                                                                         \
+    if ((dim) == 3) {                                                          \
+      JFNK_ROW_DISPATCH_D(3, lanes, KERNEL, n, s, __VA_ARGS__)                 \
+    } else {                                                                   \
+      JFNK_ROW_DISPATCH_D(2, lanes, KERNEL, n, s, __VA_ARGS__)                 \
+    }                                                                          \
+    JFNK_HIP(hipGetLastError());                                               \
+  } while (0)
+
 void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
   const int64_t t = n * dim;
   hipLaunchKernelGGL(k_cast_in, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t, gate);
@@ -248,28 +298,27 @@ void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x
                     double* z64) {
   // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
   // by other rows' products in the first pass), or in the next step's launch
-  JFNK_DIM_DISPATCH(dim, k_cheb_start, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), dinv, b, x, r, d, inv_theta, gate);
+  JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_start, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
+                    A.val.as<float>(), dinv, b, x, r, d, inv_theta, gate);
   if (!defer_axpy) JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, z64, gate);
 }
 
 void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
                    float c1, float c2, int dim, hipStream_t s, const int32_t* gate, bool pend, double* z64) {
-  JFNK_DIM_DISPATCH(dim, k_cheb_step, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64,
-                    gate);
+  JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_step, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
+                    A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64, gate);
 }
 
 void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
                   const int32_t* gate) {
-  JFNK_DIM_DISPATCH(dim, k_residual, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, A.ptr.as<int32_t>(),
-                    A.col.as<int32_t>(), A.val.as<float>(), b, x, r, gate);
+  JFNK_ROW_DISPATCH(dim, A.lanes, k_residual, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
+                    A.val.as<float>(), b, x, r, gate);
 }
 
 void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s,
               const int32_t* gate) {
-  JFNK_DIM_DISPATCH(dim, k_spmv, dim3(blocks_for(M.n)), dim3(kB), 0, s, M.n, M.m, M.ptr.as<int32_t>(),
-                    M.col.as<int32_t>(), M.val.as<float>(), x, y, accumulate ? 1 : 0, gate);
+  JFNK_ROW_DISPATCH(dim, M.lanes, k_spmv, M.n, s, M.n, M.m, M.ptr.as<int32_t>(), M.col.as<int32_t>(),
+                    M.val.as<float>(), x, y, accumulate ? 1 : 0, gate);
 }
 
 void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s, const int32_t* gate) {

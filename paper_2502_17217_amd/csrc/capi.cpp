@@ -1,11 +1,14 @@
 // The C ABI of the library (include/jfnk.h): argument checking, error
 // translation, mesh upload, and the Newton driver.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "solver.h"
 
@@ -405,15 +408,41 @@ jfnk_status jfnk_create_batch(const jfnk_mesh_desc* descs, const jfnk_material* 
     const double t0 = now_ms();
     auto m = std::make_unique<jfnk_mesh>();
     m->segs.resize(n);
-    for (int32_t s = 0; s < n; ++s) {
-      try {
-        m->segs[s].mat = make_material(mats[s]);
-        build_host_mesh(descs[s], m->segs[s].mat, m->segs[s].host);
-      } catch (Error& e) {
-        if (n > 1) e.msg = "batch mesh " + std::to_string(s) + ": " + e.msg;
-        throw;
+    // The meshes of a batch are independent: host threads take them in turn.
+    // The error reported is that of the lowest-numbered failing mesh.
+    std::vector<Error> errs(n);
+    std::vector<char> failed(n, 0);
+    std::atomic<int32_t> next{0};
+    auto work = [&] {
+      for (int32_t s; (s = next.fetch_add(1)) < n;) {
+        try {
+          m->segs[s].mat = make_material(mats[s]);
+          build_host_mesh(descs[s], m->segs[s].mat, m->segs[s].host);
+        } catch (Error& e) {
+          errs[s] = e;
+          failed[s] = 1;
+        } catch (const std::bad_alloc&) {
+          errs[s] = Error{JFNK_E_OOM, "host allocation failed"};
+          failed[s] = 1;
+        } catch (const std::exception& e) {
+          errs[s] = Error{JFNK_E_ARG, e.what()};
+          failed[s] = 1;
+        }
       }
-    }
+    };
+    const int nt = std::max(1, std::min<int>(n, int(std::thread::hardware_concurrency()) > 0
+                                                    ? std::min(16, int(std::thread::hardware_concurrency()))
+                                                    : 1));
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nt; ++k) pool.emplace_back(work);
+    work();
+    for (std::thread& t : pool) t.join();
+    for (int32_t s = 0; s < n; ++s)
+      if (failed[s]) {
+        Error e = errs[s];
+        if (n > 1) e.msg = "batch mesh " + std::to_string(s) + ": " + e.msg;
+        throw e;
+      }
     finish_handle(*m, static_cast<hipStream_t>(stream), t0);
     *out = m.release();
   });

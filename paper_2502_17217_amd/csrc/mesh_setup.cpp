@@ -15,11 +15,56 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <exception>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
 namespace jfnk {
+
+namespace {
+
+// f(i) for i in [0, n) on up to 16 host threads (indices handed out in
+// turn); an exception is rethrown after every thread has joined (the one of
+// the lowest index).
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  const int hw = int(std::thread::hardware_concurrency());
+  const int nt = int(std::max<int64_t>(1, std::min<int64_t>({n, int64_t(16), int64_t(hw > 0 ? hw : 1)})));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::mutex mu;
+  std::exception_ptr err;
+  int64_t err_i = n;
+  auto work = [&] {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= n) return;
+      try {
+        f(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (i < err_i) {
+          err_i = i;
+          err = std::current_exception();
+        }
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nt; ++k) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
+
+}  // namespace
 
 Material make_material(const jfnk_material& m) {
   JFNK_REQUIRE(m.law == JFNK_LINEAR_ELASTIC || m.law == JFNK_NEO_HOOKEAN, JFNK_E_ARG,
@@ -759,11 +804,26 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         JFNK_REQUIRE(U.fown[j] / kFvBlock >= U.fown[j - 1] / kFvBlock, JFNK_E_MESH,
                      "mesh: internal faces not grouped by owner tile");
     }
-    std::vector<int32_t> halo;
-    for (int64_t t = 0; t < n_blocks; ++t) {
+    // Per tile: its lists into a buffer of its own (tiles on parallel host
+    // threads; each tile writes only its own slots and owned faces in the
+    // shared arrays), then the buffers are appended in tile order.
+    struct TileLists {
+      std::vector<int32_t> halo, ring2, in_face, in_loc, bnd_face, bnd_loc;
+      std::vector<int16_t> h1_loc;
+      std::vector<double> h1_mg;
+      int32_t n_ent = 0;
+    };
+    std::vector<TileLists> tl(static_cast<size_t>(n_blocks));
+    auto slots_of = [&](int32_t cell, auto&& fn) {
+      const int64_t sl = cell / kSlice, lane = cell % kSlice;
+      const int32_t w = (ua.slice_ptr[sl + 1] - ua.slice_ptr[sl]) / kSlice;
+      for (int32_t k = 0; k < w; ++k) fn(k, ua.slice_ptr[sl] + k * kSlice + int32_t(lane));
+    };
+    auto one_tile = [&](int64_t t) {
+      TileLists& o = tl[size_t(t)];
+      std::vector<int32_t>& halo = o.halo;
       const int64_t c0 = t * kFvBlock, c1 = std::min<int64_t>(N, c0 + kFvBlock);
       const int64_t sl0 = c0 / kSlice, sl1 = (c1 - 1) / kSlice;
-      halo.clear();
       for (int64_t sl = sl0; sl <= sl1; ++sl)
         for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
           const int32_t nb = ua.slot_nb[q];
@@ -782,16 +842,8 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
             ua.slot_loc[q] =
                 kFvBlock + int32_t(std::lower_bound(halo.begin(), halo.end(), nb) - halo.begin());
         }
-      ua.halo_cells.insert(ua.halo_cells.end(), halo.begin(), halo.end());
-      ua.halo_ptr[t + 1] = int32_t(ua.halo_cells.size());
-      ua.halo_max = std::max<int64_t>(ua.halo_max, int64_t(halo.size()));
       // second ring: outside cells adjacent to the halo, not in tile or halo
-      std::vector<int32_t> ring2;
-      auto slots_of = [&](int32_t cell, auto&& fn) {
-        const int64_t sl = cell / kSlice, lane = cell % kSlice;
-        const int32_t w = (ua.slice_ptr[sl + 1] - ua.slice_ptr[sl]) / kSlice;
-        for (int32_t k = 0; k < w; ++k) fn(k, ua.slice_ptr[sl] + k * kSlice + int32_t(lane));
-      };
+      std::vector<int32_t>& ring2 = o.ring2;
       for (int32_t h : halo)
         slots_of(h, [&](int32_t, int32_t q) {
           const int32_t nb = ua.slot_nb[q];
@@ -800,15 +852,11 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         });
       std::sort(ring2.begin(), ring2.end());
       ring2.erase(std::unique(ring2.begin(), ring2.end()), ring2.end());
-      ua.h2_cells.insert(ua.h2_cells.end(), ring2.begin(), ring2.end());
-      ua.h2_ptr[t + 1] = int32_t(ua.h2_cells.size());
-      ua.h2_max = std::max<int64_t>(ua.h2_max, int64_t(ring2.size()));
       // halo cells' slots in the tile's local numbering, slot-major
       {
         const int64_t nh = int64_t(halo.size()), W = ua.h1_width;
-        const size_t off = ua.h1_loc.size();
-        ua.h1_loc.resize(off + size_t(nh * W), int16_t(kSlotPad));
-        ua.h1_mg.resize(off + size_t(nh * W), 0.0);
+        o.h1_loc.assign(size_t(nh * W), int16_t(kSlotPad));
+        o.h1_mg.assign(size_t(nh * W), 0.0);
         const int32_t nh32 = int32_t(nh);
         auto local = [&](int32_t cell) -> int32_t {
           if (cell / kFvBlock == t) return int32_t(cell - c0);
@@ -820,12 +868,12 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         for (int64_t i = 0; i < nh; ++i)
           slots_of(halo[i], [&](int32_t k, int32_t q) {
             const int32_t nb = ua.slot_nb[q], fc = ua.slot_fc[q];
-            const size_t e = off + size_t(k) * size_t(nh) + size_t(i);
+            const size_t e = size_t(k) * size_t(nh) + size_t(i);
             if (nb >= 0) {
-              ua.h1_loc[e] = int16_t(local(nb));
-              ua.h1_mg[e] = ua.magG[fc >= 0 ? fc : ~fc];
+              o.h1_loc[e] = int16_t(local(nb));
+              o.h1_mg[e] = ua.magG[fc >= 0 ? fc : ~fc];
             } else {
-              ua.h1_loc[e] = int16_t(nb);
+              o.h1_loc[e] = int16_t(nb);
             }
           });
       }
@@ -848,27 +896,46 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
           } else if (nb / kFvBlock == t) {
             ua.slot_code[q] = 2 * (~fc - f0) + 1;   // owner in this tile
           } else {
-            ua.in_face.push_back(~fc);
-            ua.in_loc.push_back(loc_of(U.fown[~fc]) | (loc_of(U.fnb[~fc]) << 16));
+            o.in_face.push_back(~fc);
+            o.in_loc.push_back(loc_of(U.fown[~fc]) | (loc_of(U.fnb[~fc]) << 16));
             ua.slot_code[q] = 2 * (n_own + n_in++) + 1;
           }
         }
-      ua.in_ptr[t + 1] = int32_t(ua.in_face.size());
       // boundary faces after the internal ones
       const int32_t n_ent = n_own + n_in;
+      o.n_ent = n_ent;
       int32_t n_b = 0;
       for (int64_t sl = sl0; sl <= sl1; ++sl)
         for (int32_t q = ua.slice_ptr[sl]; q < ua.slice_ptr[sl + 1]; ++q) {
           if (ua.slot_nb[q] != kSlotBoundary) continue;
           const int32_t cell = int32_t(sl * kSlice + (q - ua.slice_ptr[sl]) % kSlice);
-          ua.bnd_face.push_back(ua.slot_fc[q]);
-          ua.bnd_loc.push_back(int32_t(cell - c0));
+          o.bnd_face.push_back(ua.slot_fc[q]);
+          o.bnd_loc.push_back(int32_t(cell - c0));
           ua.slot_code[q] = 2 * (n_ent + n_b++);
         }
+    };
+    parallel_for(n_blocks, one_tile);
+    // append in tile order
+    for (int64_t t = 0; t < n_blocks; ++t) {
+      TileLists& o = tl[size_t(t)];
+      ua.halo_cells.insert(ua.halo_cells.end(), o.halo.begin(), o.halo.end());
+      ua.halo_ptr[t + 1] = int32_t(ua.halo_cells.size());
+      ua.halo_max = std::max<int64_t>(ua.halo_max, int64_t(o.halo.size()));
+      ua.h2_cells.insert(ua.h2_cells.end(), o.ring2.begin(), o.ring2.end());
+      ua.h2_ptr[t + 1] = int32_t(ua.h2_cells.size());
+      ua.h2_max = std::max<int64_t>(ua.h2_max, int64_t(o.ring2.size()));
+      ua.h1_loc.insert(ua.h1_loc.end(), o.h1_loc.begin(), o.h1_loc.end());
+      ua.h1_mg.insert(ua.h1_mg.end(), o.h1_mg.begin(), o.h1_mg.end());
+      ua.in_face.insert(ua.in_face.end(), o.in_face.begin(), o.in_face.end());
+      ua.in_loc.insert(ua.in_loc.end(), o.in_loc.begin(), o.in_loc.end());
+      ua.in_ptr[t + 1] = int32_t(ua.in_face.size());
+      ua.bnd_face.insert(ua.bnd_face.end(), o.bnd_face.begin(), o.bnd_face.end());
+      ua.bnd_loc.insert(ua.bnd_loc.end(), o.bnd_loc.begin(), o.bnd_loc.end());
       ua.bnd_ptr[t + 1] = int32_t(ua.bnd_face.size());
-      ua.faces_max = std::max<int64_t>(ua.faces_max, n_ent);
-      ua.bnd_max = std::max<int64_t>(ua.bnd_max, n_b);
-      ua.ent_max = std::max<int64_t>(ua.ent_max, int64_t(n_ent) + n_b);
+      ua.faces_max = std::max<int64_t>(ua.faces_max, o.n_ent);
+      ua.bnd_max = std::max<int64_t>(ua.bnd_max, int64_t(o.bnd_face.size()));
+      ua.ent_max = std::max<int64_t>(ua.ent_max, int64_t(o.n_ent) + int64_t(o.bnd_face.size()));
+      o = TileLists();
     }
     JFNK_REQUIRE(ua.halo_max <= tile_halo_limit(dim), JFNK_E_MESH, "mesh: tile halo exceeds the LDS budget");
     JFNK_REQUIRE(ua.ent_max < 32768, JFNK_E_MESH, "mesh: too many faces inside a tile");

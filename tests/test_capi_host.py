@@ -110,3 +110,18 @@ def test_singular_least_squares_matrix(jfnk):
     with pytest.raises(jfnk.JfnkError) as e:
         jfnk.inspect_mesh(m, mg.Material())
     assert e.value.status == jfnk.E_MESH
+
+
+def test_batch_reports_lowest_bad_mesh(jfnk):
+    """A batch's meshes are prepared on parallel host threads; the error
+    reported is the lowest-numbered invalid mesh's, before any device work."""
+    good = mg.box_mesh_3d(4, 3, 3)
+    bad = dict(good)
+    nb = good["neighbour"].copy()
+    nb[0] = good["n_cells"] + 5
+    bad["neighbour"] = nb
+    meshes = [good, good, bad, good, bad, good] * 3
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.create_batch(meshes, [mg.Material()] * len(meshes), stream=0)  # null stream: no GPU here
+    assert e.value.status == jfnk.E_MESH
+    assert "batch mesh 2:" in str(e.value)
