@@ -38,6 +38,66 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Setup passes over matrix rows run in chunks of kRowChunk rows on host
+// threads; outputs are assembled in chunk order, so matrices equal the
+// serial build, and sums over rows add per-chunk partials in chunk order.
+constexpr int64_t kRowChunk = 8192;
+
+inline int64_t n_chunks(int64_t n) { return (n + kRowChunk - 1) / kRowChunk; }
+
+// A CSR matrix whose row i is appended by row(i, cols, vals, t) (t: the
+// calling thread's number, for scratch).
+template <class RowFn>
+HostCsr build_rows(int64_t n, int64_t m, RowFn&& row) {
+  const int64_t nc = n_chunks(n);
+  std::vector<std::vector<int32_t>> cnt(nc), cc(nc);
+  std::vector<std::vector<double>> cv(nc);
+  parallel_for(nc, [&](int64_t c, int t) {
+    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+    cnt[c].resize(size_t(hi - lo));
+    for (int64_t i = lo; i < hi; ++i) {
+      const size_t before = cc[c].size();
+      row(i, cc[c], cv[c], t);
+      cnt[c][size_t(i - lo)] = int32_t(cc[c].size() - before);
+    }
+  });
+  HostCsr M;
+  M.n = n;
+  M.m = m;
+  M.ptr.assign(n + 1, 0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (size_t k = 0; k < cnt[c].size(); ++k) {
+      const int64_t i = c * kRowChunk + int64_t(k);
+      M.ptr[i + 1] = M.ptr[i] + cnt[c][k];
+    }
+  M.col.reserve(size_t(M.ptr[n]));
+  M.val.reserve(size_t(M.ptr[n]));
+  for (int64_t c = 0; c < nc; ++c) {
+    M.col.insert(M.col.end(), cc[c].begin(), cc[c].end());
+    M.val.insert(M.val.end(), cv[c].begin(), cv[c].end());
+  }
+  return M;
+}
+
+// Sparse accumulator of one thread: acc/mark over the output columns.
+struct RowAcc {
+  std::vector<double> acc;
+  std::vector<int32_t> mark, cols;
+  void init(int64_t m) {
+    if (int64_t(acc.size()) == m) return;
+    acc.assign(size_t(m), 0.0);
+    mark.assign(size_t(m), -1);
+  }
+  void add(int64_t i, int32_t c, double v) {
+    if (mark[c] != i) {
+      mark[c] = int32_t(i);
+      acc[c] = 0.0;
+      cols.push_back(c);
+    }
+    acc[c] += v;
+  }
+};
+
 HostCsr fine_operator(const HostMesh& h) {
   HostCsr A;
   const int64_t n = h.n_cells;
@@ -64,16 +124,19 @@ HostCsr fine_operator(const HostMesh& h) {
     A.val[pos[b]++] = -h.pc_off[j];
   }
   // sort each row by column
-  std::vector<std::pair<int32_t, double>> tmp;
-  for (int64_t i = 0; i < n; ++i) {
-    tmp.clear();
-    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) tmp.emplace_back(A.col[k], A.val[k]);
-    std::sort(tmp.begin(), tmp.end());
-    for (size_t k = 0; k < tmp.size(); ++k) {
-      A.col[A.ptr[i] + k] = tmp[k].first;
-      A.val[A.ptr[i] + k] = tmp[k].second;
+  parallel_for(n_chunks(n), [&](int64_t c, int) {
+    std::vector<std::pair<int32_t, double>> tmp;
+    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+    for (int64_t i = lo; i < hi; ++i) {
+      tmp.clear();
+      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) tmp.emplace_back(A.col[k], A.val[k]);
+      std::sort(tmp.begin(), tmp.end());
+      for (size_t k = 0; k < tmp.size(); ++k) {
+        A.col[A.ptr[i] + k] = tmp[k].first;
+        A.val[A.ptr[i] + k] = tmp[k].second;
+      }
     }
-  }
+  });
   return A;
 }
 
@@ -87,23 +150,36 @@ std::vector<double> diagonal(const HostCsr& A) {
 
 // lambda_max of D^{-1} A by power iteration from a fixed start vector.
 double lambda_max(const HostCsr& A, const std::vector<double>& d) {
-  const int64_t n = A.n;
-  std::vector<double> x(n), y(n);
+  const int64_t n = A.n, nc = n_chunks(n);
+  std::vector<double> x(n), y(n), part(nc);
   for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
+  auto chunk_sum = [&]() {
+    double t = 0;
+    for (int64_t c = 0; c < nc; ++c) t += part[c];
+    return t;
+  };
   double lam = 1.0;
   for (int it = 0; it < 20; ++it) {
-    double nrm = 0;
-    for (int64_t i = 0; i < n; ++i) nrm += x[i] * x[i];
-    nrm = std::sqrt(nrm);
+    parallel_for(nc, [&](int64_t c, int) {
+      const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+      double t = 0;
+      for (int64_t i = lo; i < hi; ++i) t += x[i] * x[i];
+      part[c] = t;
+    });
+    const double nrm = std::sqrt(chunk_sum());
     for (int64_t i = 0; i < n; ++i) x[i] /= nrm;
-    double num = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      double s = 0;
-      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
-      y[i] = s / d[i];
-      num += y[i] * x[i];
-    }
-    lam = num;
+    parallel_for(nc, [&](int64_t c, int) {
+      const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+      double num = 0;
+      for (int64_t i = lo; i < hi; ++i) {
+        double s = 0;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+        y[i] = s / d[i];
+        num += y[i] * x[i];
+      }
+      part[c] = num;
+    });
+    lam = chunk_sum();
     x.swap(y);
   }
   return lam;
@@ -168,34 +244,21 @@ std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, i
 // P = (I - omega D^{-1} A) P_tent
 HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& d,
                              const std::vector<int32_t>& agg, int64_t nagg, double omega) {
-  HostCsr P;
-  P.n = A.n;
-  P.m = nagg;
-  P.ptr.assign(A.n + 1, 0);
-  std::vector<double> acc(nagg, 0.0);
-  std::vector<int32_t> mark(nagg, -1), cols;
-  for (int64_t i = 0; i < A.n; ++i) {
-    cols.clear();
-    auto add = [&](int32_t c, double v) {
-      if (mark[c] != i) {
-        mark[c] = int32_t(i);
-        acc[c] = 0.0;
-        cols.push_back(c);
-      }
-      acc[c] += v;
-    };
-    if (agg[i] >= 0) add(agg[i], 1.0);
+  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(A.n))));
+  return build_rows(A.n, nagg, [&](int64_t i, std::vector<int32_t>& col, std::vector<double>& val, int t) {
+    RowAcc& r = ra[size_t(t)];
+    r.init(nagg);
+    r.cols.clear();
+    if (agg[i] >= 0) r.add(i, agg[i], 1.0);
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (agg[A.col[k]] >= 0) add(agg[A.col[k]], -omega * A.val[k] / d[i]);
-    std::sort(cols.begin(), cols.end());
-    for (int32_t c : cols) {
-      if (acc[c] == 0.0) continue;
-      P.col.push_back(c);
-      P.val.push_back(acc[c]);
+      if (agg[A.col[k]] >= 0) r.add(i, agg[A.col[k]], -omega * A.val[k] / d[i]);
+    std::sort(r.cols.begin(), r.cols.end());
+    for (int32_t c : r.cols) {
+      if (r.acc[c] == 0.0) continue;
+      col.push_back(c);
+      val.push_back(r.acc[c]);
     }
-    P.ptr[i + 1] = int32_t(P.col.size());
-  }
-  return P;
+  });
 }
 
 HostCsr transpose(const HostCsr& M) {
@@ -218,35 +281,22 @@ HostCsr transpose(const HostCsr& M) {
 }
 
 HostCsr multiply(const HostCsr& X, const HostCsr& Y) {
-  HostCsr Z;
-  Z.n = X.n;
-  Z.m = Y.m;
-  Z.ptr.assign(X.n + 1, 0);
-  std::vector<double> acc(Y.m, 0.0);
-  std::vector<int32_t> mark(Y.m, -1), cols;
-  for (int64_t i = 0; i < X.n; ++i) {
-    cols.clear();
+  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(X.n))));
+  return build_rows(X.n, Y.m, [&](int64_t i, std::vector<int32_t>& col, std::vector<double>& val, int t) {
+    RowAcc& r = ra[size_t(t)];
+    r.init(Y.m);
+    r.cols.clear();
     for (int32_t a = X.ptr[i]; a < X.ptr[i + 1]; ++a) {
       const int32_t j = X.col[a];
       const double xv = X.val[a];
-      for (int32_t b = Y.ptr[j]; b < Y.ptr[j + 1]; ++b) {
-        const int32_t c = Y.col[b];
-        if (mark[c] != i) {
-          mark[c] = int32_t(i);
-          acc[c] = 0.0;
-          cols.push_back(c);
-        }
-        acc[c] += xv * Y.val[b];
-      }
+      for (int32_t b = Y.ptr[j]; b < Y.ptr[j + 1]; ++b) r.add(i, Y.col[b], xv * Y.val[b]);
     }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t c : cols) {
-      Z.col.push_back(c);
-      Z.val.push_back(acc[c]);
+    std::sort(r.cols.begin(), r.cols.end());
+    for (int32_t c : r.cols) {
+      col.push_back(c);
+      val.push_back(r.acc[c]);
     }
-    Z.ptr[i + 1] = int32_t(Z.col.size());
-  }
-  return Z;
+  });
 }
 
 // Inverse of a small SPD matrix by Cholesky (FP64), returned row-major in FP32.

@@ -5,7 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <shared_mutex>
 #include <string>
 #include <vector>
@@ -22,6 +26,51 @@ struct Error {
 };
 
 void set_last_error(const std::string& msg);
+
+// Host threads for setup work: at most 16 and at most the hardware's; one
+// for fewer than four items (starting threads would cost more than it saves).
+inline int host_threads(int64_t items) {
+  const int hw = int(std::thread::hardware_concurrency());
+  if (items < 4) return 1;
+  return int(std::max<int64_t>(1, std::min<int64_t>({items, int64_t(16), int64_t(hw > 0 ? hw : 1)})));
+}
+
+// f(i, t) for i in [0, n) on host_threads(n) threads (indices handed out in
+// turn, t = the calling thread's number for per-thread scratch); an
+// exception is rethrown after every thread has joined (the one of the lowest
+// index).
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  const int nt = host_threads(n);
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i, 0);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::mutex mu;
+  std::exception_ptr err;
+  int64_t err_i = n;
+  auto work = [&](int t) {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= n) return;
+      try {
+        f(i, t);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (i < err_i) {
+          err_i = i;
+          err = std::current_exception();
+        }
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nt; ++k) pool.emplace_back(work, k);
+  work(0);
+  for (std::thread& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
 
 #define JFNK_HIP(expr)                                                                   \
   do {                                                                                   \

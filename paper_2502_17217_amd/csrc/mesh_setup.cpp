@@ -15,56 +15,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <atomic>
-#include <exception>
-#include <mutex>
 #include <numeric>
-#include <thread>
 
 #include "internal.h"
 
 namespace jfnk {
-
-namespace {
-
-// f(i) for i in [0, n) on up to 16 host threads (indices handed out in
-// turn); an exception is rethrown after every thread has joined (the one of
-// the lowest index).
-template <class F>
-void parallel_for(int64_t n, F&& f) {
-  const int hw = int(std::thread::hardware_concurrency());
-  const int nt = int(std::max<int64_t>(1, std::min<int64_t>({n, int64_t(16), int64_t(hw > 0 ? hw : 1)})));
-  if (nt <= 1) {
-    for (int64_t i = 0; i < n; ++i) f(i);
-    return;
-  }
-  std::atomic<int64_t> next{0};
-  std::mutex mu;
-  std::exception_ptr err;
-  int64_t err_i = n;
-  auto work = [&] {
-    for (;;) {
-      const int64_t i = next.fetch_add(1);
-      if (i >= n) return;
-      try {
-        f(i);
-      } catch (...) {
-        std::lock_guard<std::mutex> lk(mu);
-        if (i < err_i) {
-          err_i = i;
-          err = std::current_exception();
-        }
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int k = 1; k < nt; ++k) pool.emplace_back(work);
-  work();
-  for (std::thread& t : pool) t.join();
-  if (err) std::rethrow_exception(err);
-}
-
-}  // namespace
 
 Material make_material(const jfnk_material& m) {
   JFNK_REQUIRE(m.law == JFNK_LINEAR_ELASTIC || m.law == JFNK_NEO_HOOKEAN, JFNK_E_ARG,
@@ -914,7 +869,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
           ua.slot_code[q] = 2 * (n_ent + n_b++);
         }
     };
-    parallel_for(n_blocks, one_tile);
+    parallel_for(n_blocks, [&](int64_t t, int) { one_tile(t); });
     // append in tile order
     for (int64_t t = 0; t < n_blocks; ++t) {
       TileLists& o = tl[size_t(t)];
