@@ -61,21 +61,27 @@ HostCsr build_rows(int64_t n, int64_t m, RowFn&& row) {
       cnt[c][size_t(i - lo)] = int32_t(cc[c].size() - before);
     }
   });
+  // chunk offsets, then every chunk writes its rows in place
+  std::vector<int64_t> off(size_t(nc) + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) off[c + 1] = off[c] + int64_t(cc[c].size());
   HostCsr M;
   M.n = n;
   M.m = m;
-  M.ptr.assign(n + 1, 0);
-  for (int64_t c = 0; c < nc; ++c)
+  M.ptr.resize(size_t(n) + 1);
+  M.ptr[0] = 0;
+  M.col.resize(size_t(off[nc]));
+  M.val.resize(size_t(off[nc]));
+  parallel_for(nc, [&](int64_t c, int) {
+    int64_t p = off[c];
     for (size_t k = 0; k < cnt[c].size(); ++k) {
-      const int64_t i = c * kRowChunk + int64_t(k);
-      M.ptr[i + 1] = M.ptr[i] + cnt[c][k];
+      p += cnt[c][k];
+      M.ptr[c * kRowChunk + int64_t(k) + 1] = int32_t(p);
     }
-  M.col.reserve(size_t(M.ptr[n]));
-  M.val.reserve(size_t(M.ptr[n]));
-  for (int64_t c = 0; c < nc; ++c) {
-    M.col.insert(M.col.end(), cc[c].begin(), cc[c].end());
-    M.val.insert(M.val.end(), cv[c].begin(), cv[c].end());
-  }
+    std::copy(cc[c].begin(), cc[c].end(), M.col.begin() + off[c]);
+    std::copy(cv[c].begin(), cv[c].end(), M.val.begin() + off[c]);
+    std::vector<int32_t>().swap(cc[c]);
+    std::vector<double>().swap(cv[c]);
+  });
   return M;
 }
 
@@ -280,7 +286,10 @@ HostCsr transpose(const HostCsr& M) {
   return T;
 }
 
-HostCsr multiply(const HostCsr& X, const HostCsr& Y) {
+// Z = X Y.  Rows come out with sorted columns unless sorted = false (the
+// intermediate A P: R (A P) adds into each output column in the order of
+// R's columns, whatever the order inside a row of A P).
+HostCsr multiply(const HostCsr& X, const HostCsr& Y, bool sorted = true) {
   std::vector<RowAcc> ra(size_t(host_threads(n_chunks(X.n))));
   return build_rows(X.n, Y.m, [&](int64_t i, std::vector<int32_t>& col, std::vector<double>& val, int t) {
     RowAcc& r = ra[size_t(t)];
@@ -291,7 +300,7 @@ HostCsr multiply(const HostCsr& X, const HostCsr& Y) {
       const double xv = X.val[a];
       for (int32_t b = Y.ptr[j]; b < Y.ptr[j + 1]; ++b) r.add(i, Y.col[b], xv * Y.val[b]);
     }
-    std::sort(r.cols.begin(), r.cols.end());
+    if (sorted) std::sort(r.cols.begin(), r.cols.end());
     for (int32_t c : r.cols) {
       col.push_back(c);
       val.push_back(r.acc[c]);
@@ -425,7 +434,7 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
       std::vector<int32_t> agg = aggregate(A, d, nagg);
       HostCsr P = smoothed_prolongator(A, d, agg, nagg, 4.0 / (3.0 * L.lmax));
       HostCsr R = transpose(P);
-      HostCsr Ac = multiply(R, multiply(A, P));
+      HostCsr Ac = multiply(R, multiply(A, P, false));
       L.A.upload(A, s);
       L.P.upload(P, s);
       L.R.upload(R, s);

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -126,6 +127,67 @@ size_t device_bytes_of(const HostMesh& h) {
 }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+// Persistent worker threads for host setup passes.  Created on first use and
+// kept for the life of the process (the object is never destroyed, so no
+// thread is joined during static destruction).
+class HostPool {
+ public:
+  explicit HostPool(int workers) {
+    for (int k = 1; k <= workers; ++k)
+      std::thread([this, k] { loop(k); }).detach();
+  }
+  bool run(int nt, const std::function<void(int)>& job) {
+    std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+    if (!busy.owns_lock()) return false;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &job;
+      nt_ = nt;
+      remaining_ = nt - 1;
+      ++gen_;
+    }
+    start_.notify_all();
+    job(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return remaining_ == 0; });
+    job_ = nullptr;
+    return true;
+  }
+
+ private:
+  void loop(int k) {
+    int64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* job;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        start_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        if (k >= nt_) continue;
+        job = job_;
+      }
+      (*job)(k);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--remaining_ == 0) done_.notify_all();
+    }
+  }
+  std::mutex busy_, mu_;
+  std::condition_variable start_, done_;
+  const std::function<void(int)>* job_ = nullptr;
+  int nt_ = 0, remaining_ = 0;
+  int64_t gen_ = 0;
+};
+
+}  // namespace
+
+bool host_pool_run(int nt, const std::function<void(int)>& job) {
+  static HostPool* pool = new HostPool(15);
+  if (nt - 1 > 15) return false;
+  return pool->run(nt, job);
+}
 
 hipEvent_t Profiler::get() {
   if (!pool.empty()) {

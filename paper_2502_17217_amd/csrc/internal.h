@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cstdint>
 #include <exception>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <shared_mutex>
@@ -35,10 +36,15 @@ inline int host_threads(int64_t items) {
   return int(std::max<int64_t>(1, std::min<int64_t>({items, int64_t(16), int64_t(hw > 0 ? hw : 1)})));
 }
 
+// Runs job(t) for t = 1 .. nt-1 on persistent host threads (and job(0) on
+// the caller), returning when all have finished.  False when another host
+// thread is using the pool (the caller then starts its own threads).
+bool host_pool_run(int nt, const std::function<void(int)>& job);
+
 // f(i, t) for i in [0, n) on host_threads(n) threads (indices handed out in
 // turn, t = the calling thread's number for per-thread scratch); an
-// exception is rethrown after every thread has joined (the one of the lowest
-// index).
+// exception is rethrown after every thread has finished (the one of the
+// lowest index).
 template <class F>
 void parallel_for(int64_t n, F&& f) {
   const int nt = host_threads(n);
@@ -65,10 +71,12 @@ void parallel_for(int64_t n, F&& f) {
       }
     }
   };
-  std::vector<std::thread> pool;
-  for (int k = 1; k < nt; ++k) pool.emplace_back(work, k);
-  work(0);
-  for (std::thread& th : pool) th.join();
+  if (!host_pool_run(nt, work)) {
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nt; ++k) pool.emplace_back(work, k);
+    work(0);
+    for (std::thread& th : pool) th.join();
+  }
   if (err) std::rethrow_exception(err);
 }
 
