@@ -101,9 +101,6 @@ __device__ __forceinline__ void traction_le(const Law& m, const double (&g)[D][D
 // convergence from ~22 correct bits); J^(-2/3) = y^2 and 1/J = y^3 then
 // cost two products instead of a cube root and two divisions.
 __device__ __forceinline__ double inv_cbrt(double J) {
-#if JFNK_CBRT_LIB
-  return 1.0 / cbrt(J);
-#endif
   const float a = fabsf(float(J));
   double y = double(__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(a) * (1.0f / 3.0f)));
   y = J < 0.0 ? -y : y;

@@ -68,6 +68,14 @@ def test_cells_ordered_in_compact_tiles(jfnk):
     info = jfnk.inspect_mesh(m, mg.Material())
     assert info["tiled"] == 1
     assert 0 < info["tile_halo_max"] <= 300
+    # second ring and face lists of the single-pass kernel: a tile touches
+    # at most 3 internal faces per cell plus its incoming faces; every
+    # boundary face of the box belongs to exactly one tile
+    assert 0 < info["tile_ring2_max"] <= 2 * info["tile_halo_max"]
+    assert info["tile_faces_max"] <= 3 * 256 + info["tile_halo_max"]
+    assert info["tile_faces_max"] <= info["tile_entries_max"]
+    assert info["tile_halo_total"] > 0 and info["tile_ring2_total"] > 0
+    assert info["fused"] == 1
     # stretched cells: tiles stay compact in cell counts, not in metres
     m = mg.box_mesh_3d(200, 20, 6, 10.0, 1.0, 1.0)
     info = jfnk.inspect_mesh(m, mg.Material())
