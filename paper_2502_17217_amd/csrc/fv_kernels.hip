@@ -923,8 +923,11 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     const int n_bnd = m.bnd_ptr[tile + 1] - m.bnd_ptr[tile];
     FaceBatch<D> fb;
     load_faces<D>(m, tile, threadIdx.x, fb);
+    // boundary entries from the last lane down: the first lanes also take the
+    // last round of internal faces, so no lane gets more than its share
+    const int eb0 = kFvBlock - 1 - int(threadIdx.x);
     BndEntry be;
-    load_bnd(m, tile, threadIdx.x, be);
+    load_bnd(m, tile, eb0, be);
     // this cell's first chunk of slots and R(u), also ahead of the barriers
     const int c = base + threadIdx.x;
     SlotChunk first;
@@ -975,8 +978,8 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
     // phase A: boundary faces (entries n_ent + eb), one per lane per round
     {
       const double load = sc.load_at(seg);
-      for (int eb = threadIdx.x; eb < n_bnd; eb += kFvBlock) {
-        if (eb != int(threadIdx.x)) load_bnd(m, tile, eb, be);
+      for (int eb = eb0; eb < n_bnd; eb += kFvBlock) {
+        if (eb != eb0) load_bnd(m, tile, eb, be);
         double f[D];
         bnd_force_sel<D, LAWSEL>(si, src, be, load, f);
 #pragma unroll
@@ -1153,10 +1156,12 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FUSED_MINWAVES) void k_jv_fused(Mesh
     load_faces<D>(m, tile, threadIdx.x, fb);
     __syncthreads();
     // phase A into registers; the face forces replace the w/centroid rows
-    // once every lane has read them
+    // once every lane has read them.  Boundary entries go from the last
+    // lane down (the first lanes also take the last round of internal faces).
     {
+      const int eb0 = kFvBlock - 1 - int(threadIdx.x);
       BndEntry be;
-      load_bnd(m, tile, threadIdx.x, be);
+      load_bnd(m, tile, eb0, be);
       const int n_ent = m.fbeg[tile + 1] - m.fbeg[tile] + m.in_ptr[tile + 1] - m.in_ptr[tile];
       const FusedLds<D> src{wx, gl, R, S};
       if (be.loc >= 0) {
@@ -1170,7 +1175,7 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FUSED_MINWAVES) void k_jv_fused(Mesh
       __syncthreads();
       if (be.loc >= 0)
 #pragma unroll
-        for (int q = 0; q < D; ++q) ff[q * fs + n_ent + threadIdx.x] = bl[q * kFvBlock + threadIdx.x];
+        for (int q = 0; q < D; ++q) ff[q * fs + n_ent + eb0] = bl[q * kFvBlock + threadIdx.x];
       store_face_forces<D>(fb, fo, threadIdx.x, ff, fs);
     }
     __syncthreads();
