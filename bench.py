@@ -326,8 +326,9 @@ def main():
                     help="largest request of the serving leg (log-uniform from 5k cells)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (a large solve would "
+              "shard by contiguous cell blocks with a halo exchange per J.v); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
