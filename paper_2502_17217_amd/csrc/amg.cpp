@@ -372,11 +372,12 @@ ChebCoef cheb_coefficients(double lmax, int degree) {
 void DevCsr::upload(const HostCsr& h, hipStream_t s) {
   n = int32_t(h.n);
   m = int32_t(h.m);
-  // rows of the dense coarse operators are shared by several lanes: about
-  // eight nonzeros per lane, one lane for the short fine-level rows
+  // each row is shared by the fewest lanes (a power of two) that leave at most
+  // three nonzeros to a lane: a short chain of dependent gathers per lane pays
+  // on the short fine-level rows as much as on the dense coarse ones
   const double avg = h.n > 0 ? double(h.col.size()) / double(h.n) : 0.0;
   lanes = 1;
-  while (lanes < 64 && avg > 12.0 * lanes) lanes *= 2;
+  while (lanes < 64 && avg > 3.0 * lanes) lanes *= 2;
   std::vector<float> v(h.val.begin(), h.val.end());
   ptr.alloc(std::max<size_t>(h.ptr.size() * 4, 256));
   col.alloc(std::max<size_t>(h.col.size() * 4, 256));
