@@ -41,47 +41,97 @@ double now_ms() {
 // Setup passes over matrix rows run in chunks of kRowChunk rows on host
 // threads; outputs are assembled in chunk order, so matrices equal the
 // serial build, and sums over rows add per-chunk partials in chunk order.
+// Passes that only build rows use shorter chunks (kBuildChunk), which
+// balance the coarse levels' few long rows over the threads; their results
+// do not depend on the chunk length.
 constexpr int64_t kRowChunk = 8192;
+constexpr int64_t kBuildChunk = 256;
 
-inline int64_t n_chunks(int64_t n) { return (n + kRowChunk - 1) / kRowChunk; }
+inline int64_t n_chunks(int64_t n, int64_t len = kRowChunk) { return (n + len - 1) / len; }
+
+// Row output buffers of the setup passes, handed back after each pass and
+// reused by the next one (at most kKeptScratch kept): a pass appends to
+// memory that earlier passes already mapped instead of growing fresh vectors.
+struct RowScratch {
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+constexpr size_t kKeptScratch = 16;
+
+class ScratchStore {
+ public:
+  std::unique_ptr<RowScratch> take() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) return std::unique_ptr<RowScratch>(new RowScratch());
+    std::unique_ptr<RowScratch> s = std::move(free_.back());
+    free_.pop_back();
+    return s;
+  }
+  void give(std::unique_ptr<RowScratch> s) {
+    s->col.clear();
+    s->val.clear();
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.size() < kKeptScratch) free_.push_back(std::move(s));
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<std::unique_ptr<RowScratch>> free_;
+};
+
+ScratchStore& scratch_store() {
+  static ScratchStore* store = new ScratchStore();  // lives until the process ends
+  return *store;
+}
 
 // A CSR matrix whose row i is appended by row(i, cols, vals, t) (t: the
-// calling thread's number, for scratch).
+// calling thread's number, for scratch).  Each thread appends the rows of its
+// chunks to a buffer of its own; once all row lengths are known the chunks
+// are copied into place in parallel.
 template <class RowFn>
 HostCsr build_rows(int64_t n, int64_t m, RowFn&& row) {
-  const int64_t nc = n_chunks(n);
-  std::vector<std::vector<int32_t>> cnt(nc), cc(nc);
-  std::vector<std::vector<double>> cv(nc);
-  parallel_for(nc, [&](int64_t c, int t) {
-    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
-    cnt[c].resize(size_t(hi - lo));
-    for (int64_t i = lo; i < hi; ++i) {
-      const size_t before = cc[c].size();
-      row(i, cc[c], cv[c], t);
-      cnt[c][size_t(i - lo)] = int32_t(cc[c].size() - before);
-    }
-  });
-  // chunk offsets, then every chunk writes its rows in place
-  std::vector<int64_t> off(size_t(nc) + 1, 0);
-  for (int64_t c = 0; c < nc; ++c) off[c + 1] = off[c] + int64_t(cc[c].size());
+  const int64_t nc = n_chunks(n, kBuildChunk);
+  std::vector<std::unique_ptr<RowScratch>> sp(size_t(host_threads(nc)));
+  std::vector<int32_t> owner(static_cast<size_t>(nc));
+  std::vector<int64_t> beg(static_cast<size_t>(nc)), len(static_cast<size_t>(nc));
   HostCsr M;
   M.n = n;
   M.m = m;
   M.ptr.resize(size_t(n) + 1);
   M.ptr[0] = 0;
+  parallel_for(nc, [&](int64_t c, int t) {
+    if (!sp[size_t(t)]) sp[size_t(t)] = scratch_store().take();
+    RowScratch& sc = *sp[size_t(t)];
+    const int64_t lo = c * kBuildChunk, hi = std::min(n, lo + kBuildChunk);
+    owner[size_t(c)] = t;
+    beg[size_t(c)] = int64_t(sc.col.size());
+    for (int64_t i = lo; i < hi; ++i) {
+      const size_t before = sc.col.size();
+      row(i, sc.col, sc.val, t);
+      M.ptr[size_t(i) + 1] = int32_t(sc.col.size() - before);  // row length for now
+    }
+    len[size_t(c)] = int64_t(sc.col.size()) - beg[size_t(c)];
+  });
+  // chunk offsets, then every chunk writes its row ends and entries in place
+  std::vector<int64_t> off(size_t(nc) + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) off[c + 1] = off[c] + len[c];
+  JFNK_REQUIRE(off[nc] < (int64_t(1) << 31), JFNK_E_ARG, "amg: operator too large for 32-bit row offsets");
   M.col.resize(size_t(off[nc]));
   M.val.resize(size_t(off[nc]));
   parallel_for(nc, [&](int64_t c, int) {
+    const int64_t lo = c * kBuildChunk, hi = std::min(n, lo + kBuildChunk);
     int64_t p = off[c];
-    for (size_t k = 0; k < cnt[c].size(); ++k) {
-      p += cnt[c][k];
-      M.ptr[c * kRowChunk + int64_t(k) + 1] = int32_t(p);
+    for (int64_t i = lo; i < hi; ++i) {
+      p += M.ptr[size_t(i) + 1];
+      M.ptr[size_t(i) + 1] = int32_t(p);
     }
-    std::copy(cc[c].begin(), cc[c].end(), M.col.begin() + off[c]);
-    std::copy(cv[c].begin(), cv[c].end(), M.val.begin() + off[c]);
-    std::vector<int32_t>().swap(cc[c]);
-    std::vector<double>().swap(cv[c]);
+    const RowScratch& sc = *sp[size_t(owner[size_t(c)])];
+    std::copy_n(sc.col.data() + beg[c], len[c], M.col.data() + off[c]);
+    std::copy_n(sc.val.data() + beg[c], len[c], M.val.data() + off[c]);
   });
+  for (auto& b : sp)
+    if (b) scratch_store().give(std::move(b));
   return M;
 }
 
@@ -148,44 +198,54 @@ HostCsr fine_operator(const HostMesh& h) {
 
 std::vector<double> diagonal(const HostCsr& A) {
   std::vector<double> d(A.n, 0.0);
-  for (int64_t i = 0; i < A.n; ++i)
-    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (A.col[k] == i) d[i] = A.val[k];
+  parallel_for(n_chunks(A.n), [&](int64_t c, int) {
+    const int64_t lo = c * kRowChunk, hi = std::min(A.n, lo + kRowChunk);
+    for (int64_t i = lo; i < hi; ++i)
+      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+        if (A.col[k] == i) d[i] = A.val[k];
+  });
   return d;
 }
 
-// lambda_max of D^{-1} A by power iteration from a fixed start vector.
+// lambda_max of D^{-1} A by power iteration from a fixed start vector.  The
+// pass that forms y = D^{-1} A x also sums y*y per chunk, which is the next
+// iteration's |x|^2 in the same order.
 double lambda_max(const HostCsr& A, const std::vector<double>& d) {
   const int64_t n = A.n, nc = n_chunks(n);
-  std::vector<double> x(n), y(n), part(nc);
+  std::vector<double> x(n), y(n), sq(nc), num(nc);
   for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
-  auto chunk_sum = [&]() {
+  auto chunk_sum = [&](const std::vector<double>& part) {
     double t = 0;
     for (int64_t c = 0; c < nc; ++c) t += part[c];
     return t;
   };
+  parallel_for(nc, [&](int64_t c, int) {
+    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+    double t = 0;
+    for (int64_t i = lo; i < hi; ++i) t += x[i] * x[i];
+    sq[c] = t;
+  });
   double lam = 1.0;
   for (int it = 0; it < 20; ++it) {
+    const double nrm = std::sqrt(chunk_sum(sq));
     parallel_for(nc, [&](int64_t c, int) {
       const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
-      double t = 0;
-      for (int64_t i = lo; i < hi; ++i) t += x[i] * x[i];
-      part[c] = t;
+      for (int64_t i = lo; i < hi; ++i) x[i] /= nrm;
     });
-    const double nrm = std::sqrt(chunk_sum());
-    for (int64_t i = 0; i < n; ++i) x[i] /= nrm;
     parallel_for(nc, [&](int64_t c, int) {
       const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
-      double num = 0;
+      double t = 0, q = 0;
       for (int64_t i = lo; i < hi; ++i) {
         double s = 0;
         for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
         y[i] = s / d[i];
-        num += y[i] * x[i];
+        t += y[i] * x[i];
+        q += y[i] * y[i];
       }
-      part[c] = num;
+      num[c] = t;
+      sq[c] = q;
     });
-    lam = chunk_sum();
+    lam = chunk_sum(num);
     x.swap(y);
   }
   return lam;
@@ -250,7 +310,7 @@ std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, i
 // P = (I - omega D^{-1} A) P_tent
 HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& d,
                              const std::vector<int32_t>& agg, int64_t nagg, double omega) {
-  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(A.n))));
+  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(A.n, kBuildChunk))));
   return build_rows(A.n, nagg, [&](int64_t i, std::vector<int32_t>& col, std::vector<double>& val, int t) {
     RowAcc& r = ra[size_t(t)];
     r.init(nagg);
@@ -290,7 +350,7 @@ HostCsr transpose(const HostCsr& M) {
 // intermediate A P: R (A P) adds into each output column in the order of
 // R's columns, whatever the order inside a row of A P).
 HostCsr multiply(const HostCsr& X, const HostCsr& Y, bool sorted = true) {
-  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(X.n))));
+  std::vector<RowAcc> ra(size_t(host_threads(n_chunks(X.n, kBuildChunk))));
   return build_rows(X.n, Y.m, [&](int64_t i, std::vector<int32_t>& col, std::vector<double>& val, int t) {
     RowAcc& r = ra[size_t(t)];
     r.init(Y.m);
