@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <numeric>
 
 #include "amg.h"
@@ -251,16 +252,19 @@ double lambda_max(const HostCsr& A, const std::vector<double>& d) {
   return lam;
 }
 
-std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, int64_t& nagg) {
-  const int64_t n = A.n;
+// Greedy aggregation of rows [lo, hi), which no entry of A connects with
+// other rows.  agg[lo, hi) holds -1 on entry; on return it holds local
+// numbers: the n1 pass-1 aggregates 0..n1-1 and the n3 pass-3 ones after
+// them, each numbered in the order it is formed.
+void aggregate_rows(const HostCsr& A, const std::vector<double>& d, int64_t lo, int64_t hi,
+                    std::vector<int32_t>& agg, int64_t& n1, int64_t& n3) {
   auto strong = [&](int64_t i, int32_t k) {
     const int32_t j = A.col[k];
     return j != i && std::fabs(A.val[k]) >= kTheta * std::sqrt(std::fabs(d[i] * d[j]));
   };
-  std::vector<int32_t> agg(n, -1);
-  nagg = 0;
+  int64_t na = 0;
   // pass 1: seed aggregates whose strong neighbourhood is still free
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = lo; i < hi; ++i) {
     if (agg[i] >= 0) continue;
     bool free = true, any = false;
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
@@ -272,21 +276,22 @@ std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, i
         }
       }
     if (!free || !any) continue;
-    agg[i] = int32_t(nagg);
+    agg[i] = int32_t(na);
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (strong(i, k)) agg[A.col[k]] = int32_t(nagg);
-    ++nagg;
+      if (strong(i, k)) agg[A.col[k]] = int32_t(na);
+    ++na;
   }
+  n1 = na;
   // pass 2: attach leftovers to the most strongly connected pass-1 aggregate
-  std::vector<int32_t> agg1 = agg;
-  for (int64_t i = 0; i < n; ++i) {
-    if (agg1[i] >= 0) continue;
+  const std::vector<int32_t> agg1(agg.begin() + lo, agg.begin() + hi);
+  for (int64_t i = lo; i < hi; ++i) {
+    if (agg1[i - lo] >= 0) continue;
     double best = 0;
     int32_t ba = -1;
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (strong(i, k) && agg1[A.col[k]] >= 0 && std::fabs(A.val[k]) > best) {
+      if (strong(i, k) && agg1[A.col[k] - lo] >= 0 && std::fabs(A.val[k]) > best) {
         best = std::fabs(A.val[k]);
-        ba = agg1[A.col[k]];
+        ba = agg1[A.col[k] - lo];
       }
     if (ba >= 0) agg[i] = ba;
   }
@@ -294,16 +299,80 @@ std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, i
   // Nodes without any strong neighbour (padding rows of a batch, a mesh that
   // has already been reduced to one coarse unknown) stay out of the coarse
   // space: the smoother alone treats them.
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = lo; i < hi; ++i) {
     if (agg[i] >= 0) continue;
     bool any = false;
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1] && !any; ++k) any = strong(i, k);
     if (!any) continue;
-    agg[i] = int32_t(nagg);
+    agg[i] = int32_t(na);
     for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = int32_t(nagg);
-    ++nagg;
+      if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = int32_t(na);
+    ++na;
   }
+  n3 = na - n1;
+}
+
+// Ends of consecutive row ranges that no entry of A connects with each other
+// (the meshes of a batch, and on coarser levels their aggregates), merged
+// into ranges of at least min_len rows.  One range when there is no cut.
+std::vector<int64_t> independent_ranges(const HostCsr& A, int64_t min_len) {
+  const int64_t n = A.n;
+  std::vector<int32_t> lo_col(static_cast<size_t>(n)), hi_col(static_cast<size_t>(n));
+  parallel_for(n_chunks(n), [&](int64_t c, int) {
+    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t a = int32_t(i), b = int32_t(i);
+      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        a = std::min(a, A.col[k]);
+        b = std::max(b, A.col[k]);
+      }
+      lo_col[i] = a;
+      hi_col[i] = b;
+    }
+  });
+  // a cut before row p is valid when no row above reaches p or beyond and no
+  // row from p on reaches above p
+  std::vector<int32_t> below_min(static_cast<size_t>(n) + 1);
+  below_min[n] = std::numeric_limits<int32_t>::max();
+  for (int64_t i = n - 1; i >= 0; --i) below_min[i] = std::min(below_min[i + 1], lo_col[i]);
+  std::vector<int64_t> ends;
+  int64_t start = 0, reach = -1;
+  for (int64_t p = 1; p <= n; ++p) {
+    reach = std::max<int64_t>(reach, hi_col[p - 1]);
+    if (p == n || (reach < p && below_min[p] >= p && p - start >= min_len)) {
+      ends.push_back(p);
+      start = p;
+    }
+  }
+  return ends;
+}
+
+// Aggregates of A (-1: row left out of the coarse space).  Ranges of rows
+// that A does not connect are aggregated in parallel; the numbering is that
+// of one pass over all rows: pass-1 aggregates in row order, then the
+// pass-3 ones in row order.
+std::vector<int32_t> aggregate(const HostCsr& A, const std::vector<double>& d, int64_t& nagg) {
+  const int64_t n = A.n;
+  std::vector<int32_t> agg(n, -1);
+  const std::vector<int64_t> ends =
+      n > 0 ? independent_ranges(A, std::max<int64_t>(kBuildChunk, n / 64)) : std::vector<int64_t>();
+  const int64_t nr = int64_t(ends.size());
+  std::vector<int64_t> n1(static_cast<size_t>(nr)), n3(static_cast<size_t>(nr));
+  parallel_for(nr, [&](int64_t r, int) {
+    aggregate_rows(A, d, r > 0 ? ends[r - 1] : 0, ends[r], agg, n1[r], n3[r]);
+  });
+  std::vector<int64_t> off1(static_cast<size_t>(nr) + 1, 0), off3(static_cast<size_t>(nr) + 1, 0);
+  for (int64_t r = 0; r < nr; ++r) off1[r + 1] = off1[r] + n1[r];
+  off3[0] = off1[nr];
+  for (int64_t r = 0; r < nr; ++r) off3[r + 1] = off3[r] + n3[r];
+  nagg = off3[nr];
+  JFNK_REQUIRE(nagg < (int64_t(1) << 31), JFNK_E_ARG, "amg: too many aggregates");
+  parallel_for(nr, [&](int64_t r, int) {
+    for (int64_t i = r > 0 ? ends[r - 1] : 0; i < ends[r]; ++i) {
+      const int32_t a = agg[i];
+      if (a >= 0) agg[i] = int32_t(a < n1[r] ? off1[r] + a : off3[r] + (a - n1[r]));
+    }
+  });
   return agg;
 }
 
@@ -327,22 +396,56 @@ HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& d,
   });
 }
 
+// Transpose.  The rows of M are cut into one piece per thread; each piece
+// counts its entries per column and takes, inside every column, the slots
+// after those of the pieces above it, so every row of the transpose lists
+// its entries in increasing row of M, as one pass over M would.
 HostCsr transpose(const HostCsr& M) {
   HostCsr T;
   T.n = M.m;
   T.m = M.n;
-  T.ptr.assign(M.m + 1, 0);
-  for (int32_t c : M.col) T.ptr[c + 1]++;
-  for (int64_t i = 0; i < M.m; ++i) T.ptr[i + 1] += T.ptr[i];
+  const int np = host_threads(n_chunks(M.n, kBuildChunk));
+  std::vector<std::vector<int32_t>> cnt(static_cast<size_t>(np));
+  auto piece = [&](int64_t p, int64_t& lo, int64_t& hi) {
+    lo = M.n * p / np;
+    hi = M.n * (p + 1) / np;
+  };
+  parallel_for(np, [&](int64_t p, int) {
+    cnt[p].assign(size_t(M.m), 0);
+    int64_t lo, hi;
+    piece(p, lo, hi);
+    for (int32_t k = M.ptr[lo]; k < M.ptr[hi]; ++k) cnt[p][M.col[k]]++;
+  });
+  // per column: the pieces' start offsets inside it, and its length
+  T.ptr.resize(size_t(M.m) + 1);
+  T.ptr[0] = 0;
+  parallel_for(n_chunks(M.m), [&](int64_t c, int) {
+    const int64_t lo = c * kRowChunk, hi = std::min(M.m, lo + kRowChunk);
+    for (int64_t j = lo; j < hi; ++j) {
+      int32_t s = 0;
+      for (int p = 0; p < np; ++p) {
+        const int32_t t = cnt[p][j];
+        cnt[p][j] = s;
+        s += t;
+      }
+      T.ptr[j + 1] = s;
+    }
+  });
+  for (int64_t j = 0; j < M.m; ++j) T.ptr[j + 1] += T.ptr[j];
   T.col.resize(M.col.size());
   T.val.resize(M.val.size());
-  std::vector<int32_t> pos(T.ptr.begin(), T.ptr.end() - 1);
-  for (int64_t i = 0; i < M.n; ++i)
-    for (int32_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
-      const int32_t c = M.col[k];
-      T.col[pos[c]] = int32_t(i);
-      T.val[pos[c]++] = M.val[k];
-    }
+  parallel_for(np, [&](int64_t p, int) {
+    int64_t lo, hi;
+    piece(p, lo, hi);
+    std::vector<int32_t>& pos = cnt[p];
+    for (int64_t i = lo; i < hi; ++i)
+      for (int32_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+        const int32_t c = M.col[k];
+        const int64_t q = int64_t(T.ptr[c]) + pos[c]++;
+        T.col[q] = int32_t(i);
+        T.val[q] = M.val[k];
+      }
+  });
   return T;
 }
 
