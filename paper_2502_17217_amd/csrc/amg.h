@@ -1,38 +1,11 @@
 // FP32 smoothed-aggregation AMG for the compact-stencil approximate Jacobian.
 #pragma once
 
-#include <memory>
-#include <type_traits>
-#include <utility>
 #include <vector>
 
 #include "internal.h"
 
 namespace jfnk {
-
-// Host vector whose resize leaves new elements of trivial type unset: setup
-// arrays are written in full right after they are sized, by several threads,
-// so their pages are first touched in parallel rather than by one zero fill.
-template <class T>
-struct NoInitAlloc : std::allocator<T> {
-  template <class U>
-  struct rebind {
-    using other = NoInitAlloc<U>;
-  };
-  NoInitAlloc() = default;
-  template <class U>
-  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
-  template <class U>
-  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
-    ::new (static_cast<void*>(p)) U;
-  }
-  template <class U, class... Args>
-  void construct(U* p, Args&&... args) {
-    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
-  }
-};
-template <class T>
-using HostVec = std::vector<T, NoInitAlloc<T>>;
 
 // Host CSR matrix (FP64) used during setup.
 struct HostCsr {

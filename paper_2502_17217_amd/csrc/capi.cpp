@@ -42,15 +42,16 @@ double now_ms() {
 
 // Transpose a row-major [rows][cols] host array (row stride `ld`) into
 // component-major [cols][rows].
-std::vector<double> to_soa(const std::vector<double>& a, int64_t rows, int cols, int ld) {
+template <class V>
+std::vector<double> to_soa(const V& a, int64_t rows, int cols, int ld) {
   std::vector<double> out(size_t(rows) * cols);
   for (int64_t r = 0; r < rows; ++r)
     for (int k = 0; k < cols; ++k) out[size_t(k) * rows + r] = a[size_t(r) * ld + k];
   return out;
 }
 
-template <class T>
-void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+template <class T, class A>
+void upload(DevBuf& b, const std::vector<T, A>& v, hipStream_t s) {
   b.alloc(std::max<size_t>(v.size() * sizeof(T), 256));
   if (!v.empty())
     JFNK_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));

@@ -9,10 +9,13 @@
 #include <cstdint>
 #include <exception>
 #include <functional>
+#include <memory>
 #include <mutex>
-#include <thread>
 #include <shared_mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "jfnk.h"
@@ -275,6 +278,31 @@ Material make_material(const jfnk_material& m);
 void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm);
 
 // Host arrays of a batch union, ready for upload.
+// Host vector whose resize leaves new elements of trivial type unset: large
+// setup arrays that are written in full right after they are sized, by
+// several threads, have their pages first touched in parallel rather than by
+// one zero fill.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
 struct UnionArrays {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc, ext, seg_of_block;
   std::vector<int32_t> slot_loc, halo_ptr, halo_cells, fbeg, face_loc, in_ptr, in_face, in_loc;
@@ -284,7 +312,8 @@ struct UnionArrays {
   // faces_max: largest internal face list of a tile; bnd_max: largest
   // boundary list; ent_max: largest internal + boundary list
   int64_t halo_max = 0, faces_max = 0, bnd_max = 0, ent_max = 0, h2_max = 0, h1_width = 0;
-  std::vector<double> xc, face, magG, bface, pc_dinv;
+  HostVec<double> xc, face, magG, bface;  // sized without zero fill, written in full
+  std::vector<double> pc_dinv;
   std::vector<SegInfo> seg;
 };
 

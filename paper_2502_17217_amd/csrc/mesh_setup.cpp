@@ -43,6 +43,9 @@ Material make_material(const jfnk_material& m) {
 
 namespace {
 
+// Faces per host-thread work item in the geometry passes.
+constexpr int64_t kGeomChunk = 4096;
+
 struct V3 {
   double x = 0, y = 0, z = 0;
 };
@@ -171,14 +174,15 @@ std::vector<int32_t> tile_order(int dim, const std::vector<V3>& xc, const std::v
   };
   std::vector<int32_t> idx(nc);
   std::iota(idx.begin(), idx.end(), 0);
-  std::vector<std::pair<int64_t, int64_t>> stack{{0, nc}};
-  while (!stack.empty()) {
-    const auto [lo, hi] = stack.back();
-    stack.pop_back();
+  // One bisection of idx[lo, hi): the range is split along its longest axis
+  // into the first (tiles / 2) tiles' worth of cells and the rest, and the
+  // split point is returned; a range of at most one tile has its cells put
+  // back in input order and returns hi.
+  auto bisect = [&](int64_t lo, int64_t hi) -> int64_t {
     const int64_t n = hi - lo;
     if (n <= kFvBlock) {
       std::sort(idx.begin() + lo, idx.begin() + hi);
-      continue;
+      return hi;
     }
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
     for (int64_t i = lo; i < hi; ++i)
@@ -197,32 +201,77 @@ std::vector<int32_t> tile_order(int dim, const std::vector<V3>& xc, const std::v
                        const double ca = coord(a, axis), cb = coord(b, axis);
                        return ca < cb || (ca == cb && a < b);
                      });
-    stack.push_back({lo + left, hi});
-    stack.push_back({lo, lo + left});
+    return lo + left;
+  };
+  // The bisections form a binary tree whose leaves (the tiles) hold the same
+  // cells in whatever order its nodes are processed: the nodes of one level
+  // go to host threads together, and once a level has enough nodes each
+  // node's subtree is finished by one thread.
+  std::vector<std::pair<int64_t, int64_t>> level{{0, nc}};
+  while (!level.empty() && level.size() < 64) {
+    std::vector<int64_t> cut(level.size());
+    parallel_for(int64_t(level.size()), [&](int64_t r, int) { cut[r] = bisect(level[r].first, level[r].second); });
+    std::vector<std::pair<int64_t, int64_t>> next;
+    for (size_t r = 0; r < level.size(); ++r)
+      if (cut[r] < level[r].second) {
+        next.push_back({level[r].first, cut[r]});
+        next.push_back({cut[r], level[r].second});
+      }
+    level.swap(next);
   }
+  parallel_for(int64_t(level.size()), [&](int64_t r, int) {
+    std::vector<std::pair<int64_t, int64_t>> stack{level[r]};
+    while (!stack.empty()) {
+      const auto [lo, hi] = stack.back();
+      stack.pop_back();
+      const int64_t cut = bisect(lo, hi);
+      if (cut < hi) {
+        stack.push_back({cut, hi});
+        stack.push_back({lo, cut});
+      }
+    }
+  });
   return idx;
 }
 
 // Largest number of distinct cells outside a tile of kFvBlock cells that
 // share an internal face with a cell of the tile (cell numbers: new_of_old).
+// The outside neighbours are bucketed by tile and each tile's bucket is
+// counted on a host thread.
 int64_t max_tile_halo(const std::vector<int32_t>& new_of_old, const int32_t* owner, const int32_t* nbr,
                       int64_t ni) {
-  std::vector<int64_t> key;
-  key.reserve(size_t(2 * ni));
+  const int64_t nt = (int64_t(new_of_old.size()) + kFvBlock - 1) / kFvBlock;
+  std::vector<int64_t> tptr(static_cast<size_t>(nt) + 1, 0);
   for (int64_t f = 0; f < ni; ++f) {
     const int64_t a = new_of_old[owner[f]], b = new_of_old[nbr[f]];
     if (a / kFvBlock == b / kFvBlock) continue;
-    key.push_back((a / kFvBlock) << 32 | b);
-    key.push_back((b / kFvBlock) << 32 | a);
+    tptr[a / kFvBlock + 1]++;
+    tptr[b / kFvBlock + 1]++;
   }
-  std::sort(key.begin(), key.end());
-  key.erase(std::unique(key.begin(), key.end()), key.end());
-  int64_t best = 0, run = 0;
-  for (size_t i = 0; i < key.size(); ++i) {
-    run = (i > 0 && (key[i] >> 32) == (key[i - 1] >> 32)) ? run + 1 : 1;
-    best = std::max(best, run);
+  for (int64_t t = 0; t < nt; ++t) tptr[t + 1] += tptr[t];
+  std::vector<int32_t> outside(static_cast<size_t>(tptr[nt]));
+  {
+    std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
+    for (int64_t f = 0; f < ni; ++f) {
+      const int32_t a = new_of_old[owner[f]], b = new_of_old[nbr[f]];
+      if (a / kFvBlock == b / kFvBlock) continue;
+      outside[pos[a / kFvBlock]++] = b;
+      outside[pos[b / kFvBlock]++] = a;
+    }
   }
-  return best;
+  constexpr int64_t kTilesPerItem = 64;
+  const int64_t items = (nt + kTilesPerItem - 1) / kTilesPerItem;
+  std::vector<int64_t> best(static_cast<size_t>(items), 0);
+  parallel_for(items, [&](int64_t it, int) {
+    for (int64_t t = it * kTilesPerItem; t < std::min(nt, (it + 1) * kTilesPerItem); ++t) {
+      auto first = outside.begin() + tptr[t], last = outside.begin() + tptr[t + 1];
+      std::sort(first, last);
+      best[it] = std::max<int64_t>(best[it], std::unique(first, last) - first);
+    }
+  });
+  int64_t most = 0;
+  for (int64_t v : best) most = std::max(most, v);
+  return most;
 }
 
 }  // namespace
@@ -284,39 +333,45 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
     if (dim == 3) r.z = d.points[int64_t(i) * dim + 2];
     return r;
   };
+  // faces are independent: chunks of them go to host threads, and the error
+  // reported is that of the first bad face, as in one pass
   std::vector<V3> Gam(nf), xf(nf);
-  for (int64_t f = 0; f < nf; ++f) {
-    const int64_t a = d.face_ptr[f], k = d.face_ptr[f + 1] - a;
-    if (dim == 2) {
-      V3 p0 = P(d.face_pts[a]), p1 = P(d.face_pts[a + 1]);
-      Gam[f] = {p1.y - p0.y, -(p1.x - p0.x), 0.0};
-      xf[f] = 0.5 * (p0 + p1);
-    } else {
-      V3 xbar;
-      for (int64_t i = 0; i < k; ++i) xbar = xbar + P(d.face_pts[a + i]);
-      xbar = (1.0 / double(k)) * xbar;
-      V3 g;
-      std::vector<V3> tri_a(k), tri_c(k);
-      for (int64_t i = 0; i < k; ++i) {
-        V3 pi = P(d.face_pts[a + i]), pj = P(d.face_pts[a + (i + 1) % k]);
-        tri_a[i] = 0.5 * cross(pi - xbar, pj - xbar);
-        tri_c[i] = (1.0 / 3.0) * (pi + pj + xbar);
-        g = g + tri_a[i];
+  parallel_for((nf + kGeomChunk - 1) / kGeomChunk, [&](int64_t chunk, int) {
+    std::vector<V3> tri_a, tri_c;
+    for (int64_t f = chunk * kGeomChunk; f < std::min(nf, (chunk + 1) * kGeomChunk); ++f) {
+      const int64_t a = d.face_ptr[f], k = d.face_ptr[f + 1] - a;
+      if (dim == 2) {
+        V3 p0 = P(d.face_pts[a]), p1 = P(d.face_pts[a + 1]);
+        Gam[f] = {p1.y - p0.y, -(p1.x - p0.x), 0.0};
+        xf[f] = 0.5 * (p0 + p1);
+      } else {
+        V3 xbar;
+        for (int64_t i = 0; i < k; ++i) xbar = xbar + P(d.face_pts[a + i]);
+        xbar = (1.0 / double(k)) * xbar;
+        V3 g;
+        tri_a.resize(size_t(k));
+        tri_c.resize(size_t(k));
+        for (int64_t i = 0; i < k; ++i) {
+          V3 pi = P(d.face_pts[a + i]), pj = P(d.face_pts[a + (i + 1) % k]);
+          tri_a[i] = 0.5 * cross(pi - xbar, pj - xbar);
+          tri_c[i] = (1.0 / 3.0) * (pi + pj + xbar);
+          g = g + tri_a[i];
+        }
+        double mg = std::sqrt(dot(g, g));
+        JFNK_REQUIRE(mg > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
+        V3 n = (1.0 / mg) * g, c;
+        double wsum = 0;
+        for (int64_t i = 0; i < k; ++i) {
+          double w = dot(tri_a[i], n);
+          wsum += w;
+          c = c + w * tri_c[i];
+        }
+        Gam[f] = g;
+        xf[f] = (1.0 / wsum) * c;
       }
-      double mg = std::sqrt(dot(g, g));
-      JFNK_REQUIRE(mg > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
-      V3 n = (1.0 / mg) * g, c;
-      double wsum = 0;
-      for (int64_t i = 0; i < k; ++i) {
-        double w = dot(tri_a[i], n);
-        wsum += w;
-        c = c + w * tri_c[i];
-      }
-      Gam[f] = g;
-      xf[f] = (1.0 / wsum) * c;
+      JFNK_REQUIRE(dot(Gam[f], Gam[f]) > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
     }
-    JFNK_REQUIRE(dot(Gam[f], Gam[f]) > 0, JFNK_E_MESH, "mesh: " + s_face(f) + " has zero area");
-  }
+  });
 
   // ---- cell geometry (input order) ----
   std::vector<int32_t> nfc(nc, 0);
@@ -434,57 +489,76 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
     o2[f] = std::min(a, b);
     n2[f] = std::max(a, b);
   }
-  std::iota(fperm.begin(), fperm.end(), 0);
-  std::stable_sort(fperm.begin(), fperm.end(), [&](int64_t x, int64_t y) {
-    return o2[x] != o2[y] ? o2[x] < o2[y] : n2[x] < n2[y];
-  });
   // Face numbering for coalesced access: faces are grouped by the 64-cell
-  // slice of their owner, then by their rank among the owner's faces, then by
-  // the owner's lane, so that the k-th owned face of 64 consecutive cells
-  // occupies consecutive records.
+  // slice of their owner, then by their rank among the owner's faces (in
+  // order of neighbour, equal neighbours in input order), then by the owner's
+  // lane, so that the k-th owned face of 64 consecutive cells occupies
+  // consecutive records.
   {
-    std::vector<int32_t> rank(ni, 0);
-    for (int64_t j = 1; j < ni; ++j)
-      if (o2[fperm[j]] == o2[fperm[j - 1]]) rank[fperm[j]] = rank[fperm[j - 1]] + 1;
-    std::stable_sort(fperm.begin(), fperm.end(), [&](int64_t x, int64_t y) {
-      const int32_t sx = o2[x] / kSlice, sy = o2[y] / kSlice;
-      if (sx != sy) return sx < sy;
-      if (rank[x] != rank[y]) return rank[x] < rank[y];
-      return o2[x] < o2[y];
-    });
+    std::vector<int64_t> optr(nc + 1, 0);
+    for (int64_t f = 0; f < ni; ++f) optr[o2[f] + 1]++;
+    for (int64_t c = 0; c < nc; ++c) optr[c + 1] += optr[c];
+    std::vector<int64_t> owned(ni);
+    {
+      std::vector<int64_t> pos(optr.begin(), optr.end() - 1);
+      for (int64_t f = 0; f < ni; ++f) owned[pos[o2[f]]++] = f;
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+      auto first = owned.begin() + optr[c], last = owned.begin() + optr[c + 1];
+      if (last - first > 32) {
+        std::stable_sort(first, last, [&](int64_t x, int64_t y) { return n2[x] < n2[y]; });
+        continue;
+      }
+      for (auto it = first + (first != last); it < last; ++it) {  // insertion sort, stable
+        const int64_t f = *it;
+        auto j = it;
+        for (; j > first && n2[*(j - 1)] > n2[f]; --j) *j = *(j - 1);
+        *j = f;
+      }
+    }
+    int64_t q = 0;
+    for (int64_t s0 = 0; s0 < nc; s0 += kSlice) {
+      const int64_t s1 = std::min<int64_t>(nc, s0 + kSlice);
+      int64_t most = 0;
+      for (int64_t c = s0; c < s1; ++c) most = std::max(most, optr[c + 1] - optr[c]);
+      for (int64_t r = 0; r < most; ++r)
+        for (int64_t c = s0; c < s1; ++c)
+          if (optr[c] + r < optr[c + 1]) fperm[q++] = owned[optr[c] + r];
+    }
   }
+  // Face records are independent and filled by host threads (the error
+  // reported is that of the first bad face); the diagonal of the approximate
+  // Jacobian sums over each cell's faces further down, in face order.
   const double aKp = mat.alpha_pc * mat.Kbar;
   hm.face.assign(ni * kFaceRec, 0.0);
   hm.magG.assign(ni, 0.0);
   hm.fown.resize(ni);
   hm.fnb.resize(ni);
   hm.pc_off.resize(ni);
-  hm.pc_diag.assign(nc, 0.0);
-  for (int64_t j = 0; j < ni; ++j) {
-    int64_t f = fperm[j];
-    int32_t A = o2[f], B = n2[f];
-    V3 g = flip[f] ? -1.0 * Gam[f] : Gam[f];
-    double mg = std::sqrt(dot(g, g));
-    V3 n = (1.0 / mg) * g;
-    V3 dAB = XC(B) - XC(A);
-    double dn = dot(dAB, n);
-    JFNK_REQUIRE(dn > 0, JFNK_E_MESH,
-                 "mesh: " + s_face(f) + " has d.n <= 0 (cell centroids on the wrong side)");
-    double w = dot(n, XC(B) - xf[f]) / dn;
-    double* r = &hm.face[j * kFaceRec];
-    if (dim == 3) {
-      r[0] = g.x; r[1] = g.y; r[2] = g.z; r[3] = w;
-    } else {
-      r[0] = g.x; r[1] = g.y; r[2] = w; r[3] = 0.0;
+  parallel_for((ni + kGeomChunk - 1) / kGeomChunk, [&](int64_t chunk, int) {
+    for (int64_t j = chunk * kGeomChunk; j < std::min(ni, (chunk + 1) * kGeomChunk); ++j) {
+      int64_t f = fperm[j];
+      int32_t A = o2[f], B = n2[f];
+      V3 g = flip[f] ? -1.0 * Gam[f] : Gam[f];
+      double mg = std::sqrt(dot(g, g));
+      V3 n = (1.0 / mg) * g;
+      V3 dAB = XC(B) - XC(A);
+      double dn = dot(dAB, n);
+      JFNK_REQUIRE(dn > 0, JFNK_E_MESH,
+                   "mesh: " + s_face(f) + " has d.n <= 0 (cell centroids on the wrong side)");
+      double w = dot(n, XC(B) - xf[f]) / dn;
+      double* r = &hm.face[j * kFaceRec];
+      if (dim == 3) {
+        r[0] = g.x; r[1] = g.y; r[2] = g.z; r[3] = w;
+      } else {
+        r[0] = g.x; r[1] = g.y; r[2] = w; r[3] = 0.0;
+      }
+      hm.magG[j] = mg;
+      hm.fown[j] = A;
+      hm.fnb[j] = B;
+      hm.pc_off[j] = aKp * mg / dn;  // alpha K_bar |Delta| |Gamma| / |d| = alpha K_bar |Gamma| / (d.n)
     }
-    hm.magG[j] = mg;
-    hm.fown[j] = A;
-    hm.fnb[j] = B;
-    double a = aKp * mg / dn;    // alpha K_bar |Delta| |Gamma| / |d| = alpha K_bar |Gamma| / (d.n)
-    hm.pc_off[j] = a;
-    hm.pc_diag[A] -= a;
-    hm.pc_diag[B] -= a;
-  }
+  });
 
   // ---- boundary faces sorted by new owner ----
   std::vector<int64_t> bperm(nb);
@@ -494,67 +568,37 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   });
   hm.bface.assign(nb * kBfaceRec, 0.0);
   hm.bown.resize(nb);
-  for (int64_t j = 0; j < nb; ++j) {
-    int64_t b = bperm[j], f = ni + b;
-    int32_t c = nofo[d.owner[f]];
-    V3 g = Gam[f];
-    V3 db = xf[f] - XC(c);
-    double mg = std::sqrt(dot(g, g));
-    double* r = &hm.bface[j * kBfaceRec];
-    r[0] = g.x; r[1] = g.y; r[2] = g.z;
-    r[3] = db.x; r[4] = db.y; r[5] = db.z;
-    const double* v = &bval[b * 3];
-    if (btype[b] == JFNK_BC_DISPLACEMENT) {
-      double dbn = dot(db, g) / mg;
-      JFNK_REQUIRE(dbn > 0, JFNK_E_MESH, "mesh: displacement " + s_face(f) + " has d.n <= 0");
-      r[6] = v[0]; r[7] = v[1]; r[8] = v[2];
-      r[9] = kBcDisp;
-      double a = aKp * mg / dbn;
-      hm.pc_diag[c] -= a;
-    } else if (btype[b] == JFNK_BC_TRACTION) {
-      r[6] = mg * v[0]; r[7] = mg * v[1]; r[8] = mg * v[2];   // |Gamma| T_bar
-      r[9] = kBcTrac;
-    } else {
-      r[6] = -v[0] * g.x; r[7] = -v[0] * g.y; r[8] = -v[0] * g.z;  // -p Gamma
-      r[9] = kBcPres;
-    }
-    if (dim == 2) { r[2] = r[5] = r[8] = 0.0; }
-    hm.bown[j] = c;
-  }
-
-  // ---- least-squares matrix check (the kernels rebuild G_P on the fly) ----
-  {
-    std::vector<double> G(nc * 6, 0.0);
-    for (int64_t j = 0; j < ni; ++j) {
-      const double* r = &hm.face[j * kFaceRec];
-      V3 g = dim == 3 ? V3{r[0], r[1], r[2]} : V3{r[0], r[1], 0.0};
+  std::vector<double> bdiag(nb, 0.0);  // a displacement face's diagonal term
+  parallel_for((nb + kGeomChunk - 1) / kGeomChunk, [&](int64_t chunk, int) {
+    for (int64_t j = chunk * kGeomChunk; j < std::min(nb, (chunk + 1) * kGeomChunk); ++j) {
+      int64_t b = bperm[j], f = ni + b;
+      int32_t c = nofo[d.owner[f]];
+      V3 g = Gam[f];
+      V3 db = xf[f] - XC(c);
       double mg = std::sqrt(dot(g, g));
-      V3 dd = XC(hm.fnb[j]) - XC(hm.fown[j]);
-      double wt = mg / dot(dd, dd);
-      double e[6] = {dd.x * dd.x, dd.x * dd.y, dd.x * dd.z, dd.y * dd.y, dd.y * dd.z, dd.z * dd.z};
-      for (int k = 0; k < 6; ++k) {
-        G[hm.fown[j] * 6 + k] += wt * e[k];
-        G[hm.fnb[j] * 6 + k] += wt * e[k];
-      }
-    }
-    for (int64_t c = 0; c < nc; ++c) {
-      const double* g = &G[c * 6];
-      double det, scale;
-      if (dim == 3) {
-        det = g[0] * (g[3] * g[5] - g[4] * g[4]) - g[1] * (g[1] * g[5] - g[4] * g[2]) +
-              g[2] * (g[1] * g[4] - g[3] * g[2]);
-        scale = std::pow((g[0] + g[3] + g[5]) / 3.0, 3);
+      double* r = &hm.bface[j * kBfaceRec];
+      r[0] = g.x; r[1] = g.y; r[2] = g.z;
+      r[3] = db.x; r[4] = db.y; r[5] = db.z;
+      const double* v = &bval[b * 3];
+      if (btype[b] == JFNK_BC_DISPLACEMENT) {
+        double dbn = dot(db, g) / mg;
+        JFNK_REQUIRE(dbn > 0, JFNK_E_MESH, "mesh: displacement " + s_face(f) + " has d.n <= 0");
+        r[6] = v[0]; r[7] = v[1]; r[8] = v[2];
+        r[9] = kBcDisp;
+        bdiag[j] = aKp * mg / dbn;
+      } else if (btype[b] == JFNK_BC_TRACTION) {
+        r[6] = mg * v[0]; r[7] = mg * v[1]; r[8] = mg * v[2];   // |Gamma| T_bar
+        r[9] = kBcTrac;
       } else {
-        det = g[0] * g[3] - g[1] * g[1];
-        scale = std::pow((g[0] + g[3]) / 2.0, 2);
+        r[6] = -v[0] * g.x; r[7] = -v[0] * g.y; r[8] = -v[0] * g.z;  // -p Gamma
+        r[9] = kBcPres;
       }
-      JFNK_REQUIRE(det > 1e-10 * scale && scale > 0, JFNK_E_MESH,
-                   "mesh: input " + s_cell(order[c]) +
-                       " has a singular least-squares matrix (too few internal-face directions)");
+      if (dim == 2) { r[2] = r[5] = r[8] = 0.0; }
+      hm.bown[j] = c;
     }
-  }
+  });
 
-  // ---- sliced-ELL slot map ----
+  // ---- per-cell face lists: internal faces ascending, then boundary faces ----
   std::vector<int32_t> cnt(nc + 1, 0);
   for (int64_t j = 0; j < ni; ++j) {
     cnt[hm.fown[j] + 1]++;
@@ -578,6 +622,52 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
       sfc[pos[c]++] = int32_t(j);
     }
   }
+  const int64_t cell_chunks = (nc + kGeomChunk - 1) / kGeomChunk;
+
+  // ---- approximate-Jacobian diagonal: minus the cell's face coefficients ----
+  hm.pc_diag.assign(nc, 0.0);
+  parallel_for(cell_chunks, [&](int64_t chunk, int) {
+    for (int64_t c = chunk * kGeomChunk; c < std::min(nc, (chunk + 1) * kGeomChunk); ++c) {
+      double s = 0.0;
+      for (int32_t k = cnt[c]; k < cnt[c + 1]; ++k) {
+        const int32_t fc = sfc[k];
+        s -= snb[k] == kSlotBoundary ? bdiag[fc] : hm.pc_off[fc >= 0 ? fc : ~fc];
+      }
+      hm.pc_diag[c] = s;
+    }
+  });
+
+  // ---- least-squares matrix check (the kernels rebuild G_P on the fly) ----
+  parallel_for(cell_chunks, [&](int64_t chunk, int) {
+    for (int64_t c = chunk * kGeomChunk; c < std::min(nc, (chunk + 1) * kGeomChunk); ++c) {
+      double g[6] = {0, 0, 0, 0, 0, 0};
+      for (int32_t k = cnt[c]; k < cnt[c + 1]; ++k) {
+        if (snb[k] == kSlotBoundary) continue;
+        const int64_t j = sfc[k] >= 0 ? sfc[k] : ~sfc[k];
+        const double* r = &hm.face[j * kFaceRec];
+        V3 gf = dim == 3 ? V3{r[0], r[1], r[2]} : V3{r[0], r[1], 0.0};
+        double mg = std::sqrt(dot(gf, gf));
+        V3 dd = XC(hm.fnb[j]) - XC(hm.fown[j]);
+        double wt = mg / dot(dd, dd);
+        double e[6] = {dd.x * dd.x, dd.x * dd.y, dd.x * dd.z, dd.y * dd.y, dd.y * dd.z, dd.z * dd.z};
+        for (int q = 0; q < 6; ++q) g[q] += wt * e[q];
+      }
+      double det, scale;
+      if (dim == 3) {
+        det = g[0] * (g[3] * g[5] - g[4] * g[4]) - g[1] * (g[1] * g[5] - g[4] * g[2]) +
+              g[2] * (g[1] * g[4] - g[3] * g[2]);
+        scale = std::pow((g[0] + g[3] + g[5]) / 3.0, 3);
+      } else {
+        det = g[0] * g[3] - g[1] * g[1];
+        scale = std::pow((g[0] + g[3]) / 2.0, 2);
+      }
+      JFNK_REQUIRE(det > 1e-10 * scale && scale > 0, JFNK_E_MESH,
+                   "mesh: input " + s_cell(order[c]) +
+                       " has a singular least-squares matrix (too few internal-face directions)");
+    }
+  });
+
+  // ---- sliced-ELL slot map ----
   const int64_t n_slices = (nc + kSlice - 1) / kSlice;
   hm.slice_ptr.assign(n_slices + 1, 0);
   for (int64_t s = 0; s < n_slices; ++s) {
@@ -590,14 +680,16 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   }
   hm.slot_nb.assign(hm.slice_ptr[n_slices], kSlotPad);
   hm.slot_fc.assign(hm.slice_ptr[n_slices], 0);
-  for (int64_t c = 0; c < nc; ++c) {
-    int64_t s = c / kSlice, lane = c % kSlice;
-    for (int32_t k = 0; k < cnt[c + 1] - cnt[c]; ++k) {
-      int64_t idx = hm.slice_ptr[s] + int64_t(k) * kSlice + lane;
-      hm.slot_nb[idx] = snb[cnt[c] + k];
-      hm.slot_fc[idx] = sfc[cnt[c] + k];
+  parallel_for(cell_chunks, [&](int64_t chunk, int) {
+    for (int64_t c = chunk * kGeomChunk; c < std::min(nc, (chunk + 1) * kGeomChunk); ++c) {
+      int64_t s = c / kSlice, lane = c % kSlice;
+      for (int32_t k = 0; k < cnt[c + 1] - cnt[c]; ++k) {
+        int64_t idx = hm.slice_ptr[s] + int64_t(k) * kSlice + lane;
+        hm.slot_nb[idx] = snb[cnt[c] + k];
+        hm.slot_fc[idx] = sfc[cnt[c] + k];
+      }
     }
-  }
+  });
 }
 
 }  // namespace jfnk
@@ -643,7 +735,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   U.pc_off.resize(face);
   U.pc_diag.assign(N, -1.0);
   U.bandwidth = 0;
-  ua.xc.assign(size_t(N) * dim, 0.0);
+  ua.xc.resize(size_t(N) * dim);   // segments write their cells and zero their padding
   ua.face.resize(size_t(face) * kFaceRec);
   ua.magG.resize(face);
   ua.bface.resize(size_t(bface) * kBfaceRec);
@@ -665,11 +757,13 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   for (int64_t k = 0; k < n_slices; ++k) ua.slice_ptr[k + 1] = ua.slice_ptr[k] + width[k] * kSlice;
   ua.slot_nb.assign(ua.slice_ptr[n_slices], kSlotPad);
   ua.slot_fc.assign(ua.slice_ptr[n_slices], 0);
-  for (int s = 0; s < S; ++s) {
+  // segments fill disjoint ranges: one host thread each
+  parallel_for(S, [&](int64_t s, int) {
     const Segment& g = m.segs[s];
     const HostMesh& h = g.host;
     const int64_t co = g.cell_off, fo = g.face_off, bo = g.bface_off;
-    U.bandwidth = std::max(U.bandwidth, h.bandwidth);
+    const int64_t next = s + 1 < S ? m.segs[s + 1].cell_off : N;
+    std::fill(ua.xc.begin() + (co + h.n_cells) * dim, ua.xc.begin() + next * dim, 0.0);  // padding
     for (int64_t c = 0; c < h.n_cells; ++c) {
       for (int k = 0; k < dim; ++k) ua.xc[(co + c) * dim + k] = h.xc[c * dim + k];
       U.pc_diag[co + c] = h.pc_diag[c];
@@ -697,6 +791,12 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         }
       }
     }
+  });
+  for (int s = 0; s < S; ++s) {
+    const Segment& g = m.segs[s];
+    const HostMesh& h = g.host;
+    const int64_t co = g.cell_off;
+    U.bandwidth = std::max(U.bandwidth, h.bandwidth);
     SegInfo& si = ua.seg[s];
     si.mu = g.mat.mu;
     si.lam = g.mat.lam;
@@ -743,11 +843,15 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     ua.h1_loc.clear();
     ua.h1_mg.clear();
     ua.slot_mg.assign(ua.slot_nb.size(), 0.0);
-    for (size_t q = 0; q < ua.slot_nb.size(); ++q)
-      if (ua.slot_nb[q] >= 0) {
-        const int32_t fc = ua.slot_fc[q];
-        ua.slot_mg[q] = ua.magG[fc >= 0 ? fc : ~fc];
-      }
+    const int64_t n_slots = int64_t(ua.slot_nb.size());
+    parallel_for((n_slots + 16 * kGeomChunk - 1) / (16 * kGeomChunk), [&](int64_t chunk, int) {
+      const int64_t q0 = chunk * 16 * kGeomChunk, q1 = std::min(n_slots, q0 + 16 * kGeomChunk);
+      for (int64_t q = q0; q < q1; ++q)
+        if (ua.slot_nb[q] >= 0) {
+          const int32_t fc = ua.slot_fc[q];
+          ua.slot_mg[q] = ua.magG[fc >= 0 ? fc : ~fc];
+        }
+    });
     {
       // owned faces of tile t: owners ascend with the face number (slice order)
       int64_t f = 0;

@@ -120,6 +120,24 @@ def test_singular_least_squares_matrix(jfnk):
     assert e.value.status == jfnk.E_MESH
 
 
+def test_first_bad_face_reported(jfnk):
+    """Face geometry is computed on parallel host threads in chunks of
+    faces; the error names the lowest-numbered bad face, as one pass over
+    the faces would, even when a later chunk also holds one."""
+    m = mg.box_mesh_2d(100, 100)            # about 20k faces: several chunks
+    assert m["n_faces"] > 3 * 4096
+    bad = dict(m)
+    fpts = m["face_pts"].copy()
+    fptr = m["face_ptr"]
+    for f in (9500, 2100):                  # zero-length faces (both ends on one point)
+        fpts[fptr[f] + 1] = fpts[fptr[f]]
+    bad["face_pts"] = fpts
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.inspect_mesh(bad, mg.Material())
+    assert e.value.status == jfnk.E_MESH
+    assert "face 2100 has zero area" in str(e.value)
+
+
 def test_batch_reports_lowest_bad_mesh(jfnk):
     """A batch's meshes are prepared on parallel host threads; the error
     reported is the lowest-numbered invalid mesh's, before any device work."""
