@@ -155,32 +155,47 @@ struct RowAcc {
   }
 };
 
+// The scalar approximate Jacobian (negated: positive diagonal), rows sorted
+// by column.  Faces go to host threads, which claim slots in their two rows
+// with atomic cursors; the per-row sort of (column, value) pairs then gives
+// the same rows whatever order the slots were claimed in.
 HostCsr fine_operator(const HostMesh& h) {
   HostCsr A;
-  const int64_t n = h.n_cells;
+  const int64_t n = h.n_cells, nf = h.n_int;
   A.n = A.m = n;
-  std::vector<int32_t> cnt(n + 1, 1);
-  for (int64_t j = 0; j < h.n_int; ++j) {
-    cnt[h.fown[j]]++;
-    cnt[h.fnb[j]]++;
-  }
-  A.ptr.assign(n + 1, 0);
+  const int64_t face_chunks = (nf + kRowChunk - 1) / kRowChunk;
+  std::vector<int32_t> cnt(n, 1);
+  parallel_for(face_chunks, [&](int64_t c, int) {
+    for (int64_t j = c * kRowChunk; j < std::min(nf, (c + 1) * kRowChunk); ++j) {
+      __atomic_fetch_add(&cnt[h.fown[j]], 1, __ATOMIC_RELAXED);
+      __atomic_fetch_add(&cnt[h.fnb[j]], 1, __ATOMIC_RELAXED);
+    }
+  });
+  A.ptr.resize(size_t(n) + 1);
+  A.ptr[0] = 0;
   for (int64_t i = 0; i < n; ++i) A.ptr[i + 1] = A.ptr[i] + cnt[i];
   A.col.resize(A.ptr[n]);
   A.val.resize(A.ptr[n]);
-  std::vector<int32_t> pos(A.ptr.begin(), A.ptr.end() - 1);
-  for (int64_t i = 0; i < n; ++i) {
-    A.col[pos[i]] = int32_t(i);
-    A.val[pos[i]++] = -h.pc_diag[i];
-  }
-  for (int64_t j = 0; j < h.n_int; ++j) {
-    const int32_t a = h.fown[j], b = h.fnb[j];
-    A.col[pos[a]] = b;
-    A.val[pos[a]++] = -h.pc_off[j];
-    A.col[pos[b]] = a;
-    A.val[pos[b]++] = -h.pc_off[j];
-  }
-  // sort each row by column
+  std::vector<int32_t>& pos = cnt;  // next free slot of each row
+  parallel_for(n_chunks(n), [&](int64_t c, int) {
+    for (int64_t i = c * kRowChunk; i < std::min(n, (c + 1) * kRowChunk); ++i) {
+      A.col[A.ptr[i]] = int32_t(i);
+      A.val[A.ptr[i]] = -h.pc_diag[i];
+      pos[i] = A.ptr[i] + 1;
+    }
+  });
+  parallel_for(face_chunks, [&](int64_t c, int) {
+    for (int64_t j = c * kRowChunk; j < std::min(nf, (c + 1) * kRowChunk); ++j) {
+      const int32_t a = h.fown[j], b = h.fnb[j];
+      const int32_t pa = __atomic_fetch_add(&pos[a], 1, __ATOMIC_RELAXED);
+      A.col[pa] = b;
+      A.val[pa] = -h.pc_off[j];
+      const int32_t pb = __atomic_fetch_add(&pos[b], 1, __ATOMIC_RELAXED);
+      A.col[pb] = a;
+      A.val[pb] = -h.pc_off[j];
+    }
+  });
+  // sort each row by column (then value, for equal columns)
   parallel_for(n_chunks(n), [&](int64_t c, int) {
     std::vector<std::pair<int32_t, double>> tmp;
     const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
@@ -214,7 +229,10 @@ std::vector<double> diagonal(const HostCsr& A) {
 double lambda_max(const HostCsr& A, const std::vector<double>& d) {
   const int64_t n = A.n, nc = n_chunks(n);
   std::vector<double> x(n), y(n), sq(nc), num(nc);
-  for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
+  parallel_for(nc, [&](int64_t c, int) {
+    const int64_t lo = c * kRowChunk, hi = std::min(n, lo + kRowChunk);
+    for (int64_t i = lo; i < hi; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
+  });
   auto chunk_sum = [&](const std::vector<double>& part) {
     double t = 0;
     for (int64_t c = 0; c < nc; ++c) t += part[c];
