@@ -209,12 +209,12 @@ def traction(g, Gam, c):
     raise ValueError("unknown law %r" % (c["law"],))
 
 
-def residual(u, pr, load=1.0, parts=False):
-    """R(u) per cell, shape [n_cells, dim] (Eq. residual, static, no body force).
+def face_forces(u, pr, load=1.0):
+    """Per-face forces of Eq. (divStressDiscret) and Eq. (RhieChow).
 
-    R_P = sum_f [traction_f + Rhie-Chow_f] with outward orientation: each
-    internal face is evaluated once from its owner's side and added to the
-    owner and subtracted from the neighbour.
+    Returns dict(T_int, RC_int, T_b, RC_b, grad): the traction and the
+    Rhie-Chow force on every internal face (owner side, outward from the
+    owner) and every boundary face, and the cell gradients.
     """
     c = pr["mat"]
     nc, dim = pr["nc"], pr["dim"]
@@ -246,10 +246,24 @@ def residual(u, pr, load=1.0, parts=False):
     T_b[m] = load * pr["magGb"][m][:, None] * pr["bval"][m]
     m = bt == PRES
     T_b[m] = -load * pr["bval"][m][:, :1] * pr["Gb"][m]
+    return dict(T_int=T_int, RC_int=RC_int, T_b=T_b, RC_b=RC_b, grad=g)
+
+
+def residual(u, pr, load=1.0, parts=False):
+    """R(u) per cell, shape [n_cells, dim] (Eq. residual, static, no body force).
+
+    R_P = sum_f [traction_f + Rhie-Chow_f] with outward orientation: each
+    internal face is evaluated once from its owner's side and added to the
+    owner and subtracted from the neighbour.
+    """
+    nc = pr["nc"]
+    P, N, Pb = pr["P"], pr["N"], pr["Pb"]
+    ff = face_forces(u, pr, load)
 
     def assemble(fint, fb):
         return (_scatter(P, fint, nc) - _scatter(N, fint, nc) + _scatter(Pb, fb, nc))
 
     if parts:
-        return dict(traction=assemble(T_int, T_b), rc=assemble(RC_int, RC_b), grad=g)
-    return assemble(T_int + RC_int, T_b + RC_b)
+        return dict(traction=assemble(ff["T_int"], ff["T_b"]), rc=assemble(ff["RC_int"], ff["RC_b"]),
+                    grad=ff["grad"])
+    return assemble(ff["T_int"] + ff["RC_int"], ff["T_b"] + ff["RC_b"])

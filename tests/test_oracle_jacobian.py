@@ -131,3 +131,18 @@ def test_approximate_jacobian_by_hand():
     A = approximate_jacobian_scalar(pr).toarray()
     expect = K * np.array([[-4, 1, 1, 0], [1, -2, 0, 1], [1, 0, -4, 1], [0, 1, 1, -2]])
     assert np.allclose(A, expect, rtol=1e-14)
+
+
+def test_eps_rule_hand_values():
+    """Reading A1, eps = sqrt(eps_mach) sqrt(1 + |u|_2) / |v|_2, at hand-worked
+    points: sqrt(eps_mach) = 2^-26 in FP64, so |u| = 3, |v| = 4 gives
+    2^-26 * 2 / 4 = 2^-27 exactly; |u| = 0, |v| = 1 gives 2^-26; |u| = 8,
+    |v| = 1/2 gives 6 * 2^-26.  A missing square root or another constant
+    fails every one of them."""
+    assert eps_walker_pernice(np.array([3.0, 0.0]), np.array([0.0, 4.0])) == 2.0 ** -27
+    assert eps_walker_pernice(np.array([3.0, 0.0]), np.array([0.0, 4.0])) == 7.450580596923828e-09
+    assert eps_walker_pernice(np.zeros(5), np.array([0.6, 0.8, 0.0, 0.0, 0.0])) == pytest.approx(
+        2.0 ** -26, rel=1e-15)
+    assert eps_walker_pernice(np.array([0.0, 8.0, 0.0]), np.array([0.3, 0.0, 0.4])) == pytest.approx(
+        6.0 * 2.0 ** -26, rel=1e-15)
+    assert eps_walker_pernice(np.ones(4), np.zeros(4)) == 0.0

@@ -226,3 +226,42 @@ def test_lame_cylinder_second_order():
         errs.append(np.sqrt(np.mean(np.sum(e * e, axis=1))))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(orders - spec["displacement_order"]) <= spec["tolerance"]), orders
+
+
+def _sheared_quads(s=0.5):
+    """4 x 3 unit quads sheared into parallelograms: node (i, j) at (i + s j, j)."""
+    m = mg.box_mesh_2d(4, 3, 4.0, 3.0)
+    m["points"] = m["points"].copy()
+    m["points"][:, 0] += s * m["points"][:, 1]
+    return m
+
+
+def test_rhie_chow_skewed_face_worked_by_hand():
+    """Eq. (RhieChow) on a non-orthogonal face: Delta = d/(d.n), worked by hand
+    (tests/golden/rc_skewed_face.md).  The cubic field makes the jump differ
+    from d . grad u_f, so the magnitude of Delta decides the value: a unit
+    Delta = d/|d| would give -6.708 instead of -7.5."""
+    from oracle.fv import face_forces
+    gold = json.load(open(os.path.join(GOLDEN, "rc_skewed_face.json")))
+    m = _sheared_quads()
+    mat = mg.Material("linear_elastic", 8.0 / 3.0, 1.0 / 3.0)
+    pr = prepare(m, mat)
+    assert pr["mat"]["mu"] == pytest.approx(gold["material"]["mu"], rel=1e-14)
+    assert pr["mat"]["lam"] == pytest.approx(gold["material"]["lambda"], rel=1e-14)
+    xc = pr["geo"]["xc"]
+    u = np.zeros((pr["nc"], 2))
+    u[:, 0] = xc[:, 0] ** 3
+    P, N = 1 + 4 * 1, 2 + 4 * 1
+    f = int(np.nonzero((pr["P"] == P) & (pr["N"] == N))[0][0])
+    np.testing.assert_allclose(xc[P], gold["owner_centroid"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(xc[N], gold["neighbour_centroid"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(pr["Gam"][f], gold["face_Gamma"], rtol=0, atol=1e-14)
+    assert pr["w"][f] == pytest.approx(gold["face_weight"], abs=1e-14)
+    ff = face_forces(u.reshape(-1), pr)
+    g = ff["grad"]
+    np.testing.assert_allclose(g[P], gold["grad_owner"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g[N], gold["grad_neighbour"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ff["RC_int"][f], gold["rhie_chow_force"], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(ff["T_int"][f], gold["traction_force"], rtol=0, atol=1e-11)
+    wrong = np.array(gold["rhie_chow_force_if_Delta_were_d_over_abs_d"])
+    assert np.abs(ff["RC_int"][f] - wrong).max() > 0.5
