@@ -15,13 +15,25 @@ Paper passages:
   * Load increments: equal fractions k/N of the applied loads (the
     case descriptions apply loads in equal increments); the next
     increment starts from the previous converged displacement.
+  * Globalisation by line search (Section 3.2): the step length s > 0
+    only has to decrease the residual norm.  Reading: s = 1, 1/2, 1/4,
+    ... and the first s with |R(u + s du)| < |R(u)| is taken (a NaN
+    residual is no decrease); after max_backtrack halvings the last trial
+    is taken.  Without line search s = 1.
+  * Divergence: a residual above dtol |R(u_0)| ends the solve.
+  * jv="complex_step" replaces the finite difference inside GMRES by the
+    exact directional derivative Im R(u + i h v)/h (a Newton-Krylov solve
+    with the exact Jacobian action).  The converged displacement is the
+    same discrete solution; reference solutions use it because the
+    finite difference of the neo-Hookean law as literally written loses
+    digits to cancellation near the reference state.
 """
 
 import numpy as np
 import scipy.sparse.linalg as spla
 
 from .fv import residual
-from .jacobian import jv_fd, approximate_jacobian_scalar
+from .jacobian import jv_fd, jv_complex_step, approximate_jacobian_scalar
 from .krylov import gmres
 
 
@@ -41,12 +53,18 @@ def make_preconditioner(pr, kind):
 
 
 def newton_solve(pr, u0=None, n_increments=1, rtol=1e-6, atol=1e-50, max_newton_it=20,
-                 eta=1e-3, restart=30, precond="lu", max_krylov_it=5000):
-    """Solve R(u) = 0 under equal load increments; returns (u, stats)."""
+                 eta=1e-3, restart=30, precond="lu", max_krylov_it=5000, line_search=False,
+                 max_backtrack=8, dtol=1e8, monitor=None, jv="fd"):
+    """Solve R(u) = 0 under equal load increments; returns (u, stats).
+
+    stats["status"] is "ok", "not_converged", "diverged" or "nan".
+    monitor(increment, iteration, |R|/|R_0|, gmres iterations) is called
+    after every Newton iteration when given (progress output only)."""
     nc, dim = pr["nc"], pr["dim"]
     u = np.zeros(nc * dim) if u0 is None else np.array(u0, dtype=np.float64).reshape(-1)
     M = make_preconditioner(pr, precond)
-    stats = dict(newton_it=[], gmres_it=[], res0=[], res_final=[], converged=True)
+    stats = dict(newton_it=[], gmres_it=[], res0=[], res_final=[], converged=True, status="ok",
+                 steps=[])
     for k in range(1, n_increments + 1):
         load = k / n_increments
         R = residual(u, pr, load).reshape(-1)
@@ -58,21 +76,48 @@ def newton_solve(pr, u0=None, n_increments=1, rtol=1e-6, atol=1e-50, max_newton_
             rn = np.linalg.norm(R)
             if rn <= max(rtol * r0, atol):
                 break
+            if not np.isfinite(rn):
+                stats["converged"] = False
+                stats["status"] = "nan"
+                break
             if it >= max_newton_it:
                 stats["converged"] = False
+                stats["status"] = "not_converged"
+                break
+            if rn > dtol * max(r0, 1e-300):
+                stats["converged"] = False
+                stats["status"] = "diverged"
                 break
             Ru = R
 
-            def A(z, u=u, Ru=Ru):
-                return jv_fd(u, z, pr, load, Ru=Ru)[0]
+            if jv == "complex_step":
+                def A(z, u=u):
+                    return jv_complex_step(u, z, pr, load)
+            else:
+                def A(z, u=u, Ru=Ru):
+                    return jv_fd(u, z, pr, load, Ru=Ru)[0]
 
             du, info = gmres(A, -R, M=M, restart=restart, rtol=eta, max_it=max_krylov_it)
             gm += info["iterations"]
-            u = u + du
-            R = residual(u, pr, load).reshape(-1)
+            s = 1.0
+            u_new = u + du
+            R_new = residual(u_new, pr, load).reshape(-1)
+            if line_search:
+                for _ in range(max_backtrack):
+                    if np.linalg.norm(R_new) < rn:
+                        break
+                    s *= 0.5
+                    u_new = u + s * du
+                    R_new = residual(u_new, pr, load).reshape(-1)
+            stats["steps"].append(s)
+            u, R = u_new, R_new
             it += 1
+            if monitor is not None:
+                monitor(k, it, np.linalg.norm(R) / r0, info["iterations"])
         stats["newton_it"].append(it)
         stats["gmres_it"].append(gm)
         stats["res0"].append(r0)
         stats["res_final"].append(np.linalg.norm(R))
+        if not stats["converged"]:
+            break
     return u, stats

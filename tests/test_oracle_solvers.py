@@ -100,3 +100,58 @@ def test_hyperelastic_dead_load_path_independence():
     assert max(s4["newton_it"]) >= 2
     # and the tip moved substantially
     assert np.abs(u8.reshape(-1, 3)[:, 1]).max() > 0.03
+
+
+# ---------------------------------------------------------------- line search (Section 3.2)
+def _bent_strip(tau):
+    m = mg.box_mesh_2d(12, 3, 4.0, 1.0, jitter=0.1, seed=5)
+    mg.set_patch(m, "xmin", "displacement", (0.0, 0.0))
+    mg.set_patch(m, "xmax", "traction", (0.0, tau))
+    return prepare(m, mg.Material("neo_hookean", 1e6, 0.3))
+
+
+def test_line_search_takes_the_first_halving_that_decreases_the_residual():
+    """A neo-Hookean strip under a large tip shear in one increment: the full
+    first Newton step (the linear solution) raises |R| by orders of magnitude;
+    the step taken is the first of 1, 1/2, 1/4, ... below |R(0)|."""
+    pr = _bent_strip(2e5)
+    u1, _ = newton_solve(pr, rtol=1e-10, max_newton_it=1, eta=1e-12, precond="lu", restart=80)
+    _, st = newton_solve(pr, rtol=1e-10, max_newton_it=1, eta=1e-12, precond="lu", restart=80,
+                         line_search=True)
+    s = st["steps"][0]
+    r0 = np.linalg.norm(residual(np.zeros_like(u1), pr))
+    assert s < 1.0
+    with np.errstate(invalid="ignore"):
+        assert np.linalg.norm(residual(s * u1, pr)) < r0
+        k = 1.0
+        while k > s:
+            rk = np.linalg.norm(residual(k * u1, pr))
+            assert not rk < r0, k
+            k *= 0.5
+
+
+def test_line_search_rescues_a_diverging_newton_solve():
+    pr = _bent_strip(2e5)
+    with np.errstate(invalid="ignore"):
+        _, plain = newton_solve(pr, rtol=1e-6, max_newton_it=40, eta=1e-4, precond="lu", restart=80)
+    _, ls = newton_solve(pr, rtol=1e-6, max_newton_it=40, eta=1e-4, precond="lu", restart=80,
+                         line_search=True)
+    assert plain["status"] in ("nan", "diverged", "not_converged")
+    assert ls["status"] == "ok"
+    assert ls["steps"][-1] == 1.0        # quadratic range reached: full steps again
+
+
+def test_line_search_keeps_full_steps_when_they_decrease():
+    pr = _bent_strip(1e2)
+    u_a, a = newton_solve(pr, rtol=1e-8, max_newton_it=20, eta=1e-6, precond="lu", restart=80)
+    u_b, b = newton_solve(pr, rtol=1e-8, max_newton_it=20, eta=1e-6, precond="lu", restart=80,
+                          line_search=True)
+    assert b["steps"] == [1.0] * len(b["steps"])
+    assert np.array_equal(u_a, u_b)
+
+
+def test_divergence_tolerance_stops_the_solve():
+    pr = _bent_strip(2e3)
+    u, st = newton_solve(pr, rtol=1e-10, max_newton_it=20, eta=1e-10, precond="lu", restart=80, dtol=0.5)
+    assert st["status"] == "diverged" and st["newton_it"] == [0]
+    assert not np.any(u)
