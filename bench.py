@@ -54,11 +54,38 @@ def measured_traffic(kernel, dim, law, shape, lds):
         return None
     tiled = "_tiled" if lds else ""
     name = {"flux": "jfnk::k_flux%s<%d, 1>" % (tiled, dim),
-            "gradient": "jfnk::k_gradient%s<%d>" % (tiled, dim)}.get(kernel)
+            "gradient": "jfnk::k_gradient%s<%d>" % (tiled, dim),
+            "eps": "jfnk::k_eps_tiles<%d, false>" % dim}.get(kernel)
     if lds == 2 and kernel == "flux":
         name = "jfnk::k_jv_fused<%d, 1>" % dim
     k = rec["kernels"].get(name)
     return k["traffic_bytes"] if k else None
+
+
+def jv_traffic(law, shape, lds):
+    """Counted HBM bytes of one whole J.v (sum over its kernels) from the
+    committed counter summary, or None when it does not match the sources."""
+    parts = ["eps", "flux"] if lds == 2 else ["eps", "gradient", "flux"]
+    tot = 0
+    for k in parts:
+        b = measured_traffic(k, 3, law, shape, lds)
+        if b is None:
+            return None
+        tot += b
+    return tot
+
+
+def host_cpu():
+    """Model and logical CPU count of this host (from /proc/cpuinfo)."""
+    model, n = None, 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                n += 1
+                model = model or line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": n or os.cpu_count()}
 
 
 def nominal_centres(meta):
@@ -117,6 +144,37 @@ def algorithmic_bytes(info, dim, lds_kernels):
         # reads record, centroids, Gamma and w_f, boundary records, slot map, R(u); writes J v
         "flux": rec + xc + face + bface + n_slots * 8 + slice_ptr + 2 * vec,
     }
+
+
+def jv_unique_bytes(info, dim, lds_kernels):
+    """Bytes one whole J.v must move with this data layout, every array it
+    reads or writes counted once: u, v, R(u) in and J v out, the centroids,
+    the internal-face data, the boundary records, and the index data of the
+    pass structure in use (slot map or tile lists).  The intermediate record
+    {w, grad w} of the two-pass form and repeated reads (u and v by the step
+    size and the gradient pass, halo rows) are not counted: they are the
+    cost of that form, not of the operation."""
+    nc, nd = info["n_cells"], info["n_dof"]
+    n_int, n_bnd, n_slots = info["n_internal_faces"], info["n_boundary_faces"], info["n_slots"]
+    n_slices = (nc + 63) // 64
+    n_tiles = (nc + 255) // 256
+    slice_ptr = (n_slices + 1) * 4
+    vec = nd * 8
+    xc = nc * dim * 8
+    face = n_int * (dim + 1) * 8
+    bface = n_bnd * 80
+    if lds_kernels:
+        offs = (n_tiles + 1) * 4
+        halo = info["tile_halo_total"] * 4 + offs
+        flist = n_int * 4 + info["tile_incoming_total"] * 8 + n_bnd * 8 + 3 * offs
+        slots = n_slots * (4 + 8 + 4) + 2 * slice_ptr   # tile position, |Gamma_f|, face code
+        index = halo + flist + slots
+        if lds_kernels == 2:
+            per_cell_slots = n_slots / max(nc, 1)
+            index += info["tile_ring2_total"] * 4 + offs + int(info["tile_halo_total"] * per_cell_slots * (2 + 8))
+    else:
+        index = n_slots * 8 + slice_ptr + n_int * 8     # slot map, |Gamma_f| per face
+    return 4 * vec + xc + face + bface + index
 
 
 def _plain_opts(jfnk, n_increments, rtol, eta, restart, max_it):
@@ -244,6 +302,140 @@ def batched_vs_plain(n_problems, n_plain, log):
                       "batched: second pass (the first pass is reported as first_pass_solves_per_s)"}
 
 
+def c2_jv(steps, log):
+    """J.v on the 64^3 block with +-20% node jitter (262,144 cells, linear
+    elastic): evals/s and GB/s.  One J.v moves about 170 MB, which fits the
+    256 MB last-level cache, so three independent input sets (u, v, R(u),
+    J v) are rotated from step to step and no step finds its inputs in the
+    cache from the step before."""
+    import numpy as np
+    import torch
+    import meshgen as mg
+    from paper_2502_17217_amd import jfnk
+    cfg = mg.config_c2()
+    m, mat = cfg["mesh"], cfg["material"]
+    gm = jfnk.create_mesh(m, mat)
+    tw = jfnk.make_workspace(gm, 1, restart=30, precond=jfnk.PC_JACOBI)
+    sets = []
+    for i in range(3):
+        u = mg.configs.random_field(gm.n_dof, 120 + i, 1e-4)
+        v = mg.configs.random_unit_vector(gm.n_dof, 20 + i)
+        ud = gm.to_internal(torch.as_tensor(u, device="cuda"))
+        vd = gm.to_internal(torch.as_tensor(v, device="cuda"))
+        sets.append([u, v, ud, vd, torch.empty_like(ud), torch.empty_like(ud)])
+    tune = jfnk.autotune(gm, jfnk.gmres_opts(restart=30, max_it=100, rtol=1e-3, precond="jacobi"),
+                         sets[0][2], tw)
+    del tw
+    work = jfnk.make_workspace(gm, 0)
+    for st in sets:
+        jfnk.residual(gm, 1.0, st[2], st[4], work)
+    for k in range(30):
+        st = sets[k % 3]
+        jfnk.jv(gm, 1.0, st[2], st[4], st[3], 0.0, st[5], work)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(steps):
+        st = sets[k % 3]
+        jfnk.jv(gm, 1.0, st[2], st[4], st[3], 0.0, st[5], work)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    lds = tune["lds_kernels"]
+    uniq = jv_unique_bytes(gm.info, 3, lds)
+    log("C2 J.v: %.1f us per J.v (%d steps, 3 rotating sets), %.1f MB unique -> %.0f GB/s"
+        % (ms * 1e3, steps, uniq / 1e6, uniq / (ms * 1e-3) / 1e9))
+    # parity of set 0 against the oracle (same eps)
+    from oracle.fv import prepare, residual
+    from oracle.jacobian import jv_fd
+    u, v, ud, vd, Rd, Jd = sets[0]
+    eps = jfnk.jv(gm, 1.0, ud, Rd, vd, 0.0, Jd, work, return_eps=True)[1]
+    pr = prepare(m, mat)
+    Ro = residual(u, pr, 1.0).reshape(-1)
+    Jo, _ = jv_fd(u, v, pr, 1.0, eps=eps, Ru=Ro)
+    err = float(np.linalg.norm(gm.to_external(Jd).cpu().numpy() - Jo) / np.linalg.norm(Jo))
+    log("C2 J.v parity vs oracle: %.2e" % err)
+    out = {"workload": "linear-elastic 64^3 hex block, +-20%% node jitter (seed 2), %d cells, auto eps, "
+                       "3 input sets rotated" % gm.n_cells,
+           "jv_per_s": 1e3 / ms, "ms_per_jv": ms, "unique_bytes": uniq,
+           "gbs": uniq / (ms * 1e-3) / 1e9, "frac": uniq / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "cell_passes": {"lds_kernels": lds, "persist": tune["persist"]},
+           "jv_rel_l2_vs_oracle": err}
+    gm.close()
+    return out
+
+
+def c3_solve(gm, m, mat, n_increments, restart, log, line_search=1):
+    """The 1000x100x10 neo-Hookean cantilever solved to Newton rtol 1e-8 per
+    increment (10 equal increments of the dead shear load), FGMRES(restart)
+    with the FP32 AMG preconditioner.  Every increment is solved by its own
+    call, so that its Newton and GMRES counts are reported and the oracle's
+    residual at the GPU state is checked against the 1e-8 criterion:
+    |R_oracle(u_k; k/N)| <= 1e-8 |R_oracle(u_{k-1}; k/N)|.  Then increment 1
+    is repeated with kernel profiling for the split of the GPU time between
+    J.v, preconditioner and orthogonalisation.  Returns (report, u_final)."""
+    import numpy as np
+    import torch
+    from paper_2502_17217_amd import jfnk
+    from oracle.fv import prepare, residual
+    N = n_increments
+    w = jfnk.make_workspace(gm, 1, restart=restart, precond=jfnk.PC_AMG32)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    mk = lambda k: jfnk.newton_opts(n_increments=N, max_newton_it=25, rtol=1e-8, eta=1e-3, restart=restart,
+                                    max_it=100000, precond="amg32", cheb_degree=3, line_search=line_search,
+                                    inc_begin=k, inc_end=k)
+    pr = prepare(m, mat)
+    incs, u_prev, t_total, status = [], np.zeros(gm.n_dof), 0.0, jfnk.OK
+    for k in range(1, N + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = jfnk.newton_solve(gm, mk(k), u, w, allow=_FAILED)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        t_total += dt
+        ue = gm.to_external(u).cpu().numpy()
+        r_end = float(np.linalg.norm(residual(ue, pr, k / N)))
+        r_beg = float(np.linalg.norm(residual(u_prev, pr, k / N)))
+        u_prev = ue
+        rec = dict(increment=k, status=jfnk.STATUS_NAMES.get(st, st), seconds=dt, newton_it=stats["newton_it"],
+                   gmres_it=stats["gmres_it"], oracle_rel_residual=r_end / r_beg,
+                   tip_uy=float(ue.reshape(-1, 3)[:, 1].max()))
+        incs.append(rec)
+        log("C3 increment %d: %s" % (k, json.dumps(rec)))
+        if st != jfnk.OK:
+            status = st
+            break
+    report = {"workload": "neo-Hookean cantilever 1000x100x10 (1M cells), dead shear tau = 750 Pa in %d "
+                          "increments, Newton rtol 1e-8, eta 1e-3, FGMRES(%d) + FP32 AMG/Chebyshev(3), "
+                          "line search %s" % (N, restart, "on" if line_search else "off"),
+              "status": jfnk.STATUS_NAMES.get(status, status), "seconds": t_total,
+              "increments": incs,
+              "max_oracle_rel_residual": max(r["oracle_rel_residual"] for r in incs),
+              "tip_uy_m": incs[-1]["tip_uy"]}
+    u_final = u.clone()
+    # increment 1 again, profiled (direct launches, HIP events per kernel class)
+    u.zero_()
+    jfnk.profile_enable(gm, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    jfnk.newton_solve(gm, mk(1), u, w, allow=_FAILED)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    prof = jfnk.profile_read(gm, reset=True)
+    jfnk.profile_enable(gm, False)
+    tot = sum(v[0] for v in prof.values())
+    report["phase_split_increment1"] = {
+        "wall_s": wall, "kernel_ms": {k: v[0] for k, v in prof.items()},
+        "launches": {k: v[1] for k, v in prof.items()},
+        "share": {"jv": (prof["eps"][0] + prof["gradient"][0] + prof["flux"][0]) / max(tot, 1e-9),
+                  "precond": prof["precond"][0] / max(tot, 1e-9),
+                  "orthogonalisation": prof["orth"][0] / max(tot, 1e-9),
+                  "other": prof["other"][0] / max(tot, 1e-9)}}
+    log("C3 phase split (increment 1, profiled): " + json.dumps(report["phase_split_increment1"]))
+    del w
+    return report, (u_final if status == jfnk.OK else None)
+
+
 def serving(rate, seconds, max_cells, n_plain, log):
     """Request server (FP32-AMG flexible GMRES, continuous admission onto 4
     streams) on a Poisson stream: latency percentiles at the offered rate,
@@ -331,6 +523,12 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=8.0, help="requests per second")
     ap.add_argument("--serve-max-cells", type=float, default=1e5,
                     help="largest request of the serving leg (log-uniform from 5k cells)")
+    ap.add_argument("--no-c3-solve", action="store_true",
+                    help="skip the full cantilever solve (the J.v state is then the bending field)")
+    ap.add_argument("--c3-restart", type=int, default=200, help="FGMRES restart length of the cantilever solve")
+    ap.add_argument("--c3-increments", type=int, default=10)
+    ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 jittered-block J.v leg")
+    ap.add_argument("--c2-steps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (a large solve would "
@@ -375,6 +573,14 @@ def main():
         log("autotune in %.1fs: lds %d persist %d step_chunk %d graphs %d; J.v candidates %s" %
             (time.time() - t, tune["lds_kernels"], tune["persist"], tune["step_chunk"], tune["graphs"],
              ", ".join("%d/%d %.1fus" % (c["lds"], c["persist"], c["ms"] * 1e3) for c in tune["jv"])))
+    c3 = None
+    state = "large-deflection bending field (tip 3 m), not a solved state"
+    if not args.no_c3_solve:
+        c3, u_fin = c3_solve(gm, m, mat, args.c3_increments, args.c3_restart, log)
+        if u_fin is not None:
+            ud = u_fin
+            u_ext = gm.to_external(ud).cpu().numpy()
+            state = "converged state of the last load increment (solved above)"
     work = jfnk.make_workspace(gm, 0)
     Ru = torch.empty_like(ud)
     Jv = torch.empty_like(ud)
@@ -418,9 +624,12 @@ def main():
         kern[name] = dict(avg_ms=avg, calls=calls, bytes=ab[name],
                           gbs=ab[name] / (avg * 1e-3) / 1e9 if avg > 0 else None)
     dom = max((k for k in kern if k != "eps"), key=lambda k: kern[k]["avg_ms"])
-    ach = kern[dom]["gbs"]
     total_bytes = sum(ab.values())
+    uniq = jv_unique_bytes(gm.info, 3, lds)
+    ach = uniq / (ms_per_step * 1e-3) / 1e9
     log("kernels: " + json.dumps(kern))
+    log("J.v: %.1f MB unique algorithmic bytes, %.1f MB summed over launches, %.1f us -> %.0f GB/s"
+        % (uniq / 1e6, total_bytes / 1e6, ms_per_step * 1e3, ach))
 
     if args.copy_mb:
         a = torch.empty(args.copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -433,7 +642,7 @@ def main():
     parity = None
     cpu = None
     if not (args.no_parity and args.no_cpu_baseline):
-        from threadpoolctl import threadpool_limits
+        from threadpoolctl import threadpool_limits, threadpool_info
         from oracle.fv import prepare, residual
         from oracle.jacobian import jv_fd
         with threadpool_limits(1):
@@ -445,7 +654,14 @@ def main():
             t = time.perf_counter()
             Jo, eps_o = jv_fd(u_ext, v_ext, pr, 1.0, eps=None, Ru=Ru_o)
             cpu_s = time.perf_counter() - t
-        log("oracle J.v in %.2fs" % cpu_s)
+        log("oracle J.v in %.2fs (one thread)" % cpu_s)
+        # the same oracle with its thread pools unrestricted (numpy's
+        # element-wise work stays on one thread; BLAS calls may use more)
+        t = time.perf_counter()
+        jv_fd(u_ext, v_ext, pr, 1.0, eps=None, Ru=Ru_o)
+        cpu_all_s = time.perf_counter() - t
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        log("oracle J.v in %.2fs (thread pools unrestricted, %d BLAS threads)" % (cpu_all_s, blas_threads))
         Jg = gm.to_external(Jv).cpu().numpy()
         parity = dict(jv_rel_l2=float(np.linalg.norm(Jg - Jo) / np.linalg.norm(Jo)),
                       eps_gpu=eps_g, eps_oracle=eps_o,
@@ -455,12 +671,19 @@ def main():
         if not args.no_cpu_baseline:
             cpu = dict(value=1.0 / cpu_s, unit="J·v evals/s", cores=1, kind="oracle",
                        sample="one FD J.v (R(u) cached, geometry precomputed and untimed) of the "
-                              "same %d-cell workload, numpy FP64, single thread" % gm.n_cells)
+                              "same %d-cell workload, numpy FP64, single thread" % gm.n_cells,
+                       host=host_cpu(),
+                       all_threads={"value": 1.0 / cpu_all_s, "blas_threads": blas_threads,
+                                    "note": "thread pools unrestricted; numpy element-wise kernels "
+                                            "run on one thread, so this is close to the one-thread figure"})
 
-    extras = None
+    extras = {"c3_solve": c3}
+    if not args.no_c2:
+        extras["c2_jv"] = c2_jv(args.c2_steps, log)
     if not args.no_extras:
-        extras = {"batched": batched_vs_plain(args.batch_problems, args.plain_sample, log),
-                  "serving": serving(args.serve_rate, args.serve_seconds, args.serve_max_cells, args.plain_sample, log)}
+        extras["batched"] = batched_vs_plain(args.batch_problems, args.plain_sample, log)
+        extras["serving"] = serving(args.serve_rate, args.serve_seconds, args.serve_max_cells,
+                                    args.plain_sample, log)
 
     out = {
         "metric": METRIC,
@@ -475,13 +698,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "neo-Hookean cantilever J.v, %dx%dx%d hex (%d cells, %d dofs), "
-                               "large-deflection state, auto eps" % (nx, ny, nz, gm.n_cells, gm.n_dof),
+        "config": {"workload": "neo-Hookean cantilever J.v, %dx%dx%d hex (%d cells, %d dofs), state: %s, "
+                               "auto eps" % (nx, ny, nz, gm.n_cells, gm.n_dof, state),
                    "law": mat.law, "cells": gm.n_cells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS if ach else None,
-                     "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz), lds),
-                     "kernel": dom, "algorithmic_bytes": kern[dom]["bytes"]},
+                     "frac": ach / HBM_PEAK_GBS, "traffic": jv_traffic(mat.law, (nx, ny, nz), lds),
+                     "unit_of_work": "one whole J.v (step size + cell passes)",
+                     "algorithmic_bytes": uniq, "launch_bytes_sum": total_bytes,
+                     "dominant_kernel": {"name": dom, "algorithmic_bytes": kern[dom]["bytes"],
+                                         "avg_ms": kern[dom]["avg_ms"], "achieved": kern[dom]["gbs"],
+                                         "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
+                                         "traffic": measured_traffic(dom, 3, mat.law, (nx, ny, nz), lds)}},
         "jv_hbm_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "kernels": kern,
         "cpu_baseline": cpu,

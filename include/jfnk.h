@@ -191,14 +191,16 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
                     const double* d_v, double eps, double* d_Jv, double* eps_used,
                     void* d_work, void* stream);
 
-typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2 } jfnk_precond;
+typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_AMG64 = 3 } jfnk_precond;
 
 /* GMRES options (Section 3.2; restarted, right preconditioned, classical
  * Gram-Schmidt applied twice).  The run stops when the true residual
  * |b - J x| <= max(rtol |b|, atol), after max_it Arnoldi steps, or on
  * stagnation.  precond: J_tilde (alpha_pc) as diagonal (Jacobi, FP64) or
- * as an FP32 aggregation-AMG V-cycle with Chebyshev smoothing (flexible
- * GMRES).  eps <= 0 selects the automatic J v step.
+ * as an aggregation-AMG V-cycle with Chebyshev smoothing (flexible GMRES),
+ * stored and applied in FP32 (AMG32) or FP64 (AMG64: the same hierarchy
+ * and cycle in full precision, the reference for the mixed-precision
+ * path).  eps <= 0 selects the automatic J v step.
  * The Givens rotations and the small least-squares problem are updated on
  * the device, so Arnoldi steps are enqueued in runs of step_chunk steps
  * between host checks of the convergence flags (0: the handle's value,
@@ -220,7 +222,17 @@ typedef struct {
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
  * k = 1..n_increments the loads are scaled by k/n_increments; iterate until
  * |R(u)| <= max(rtol |R(u_0)|, atol); each linear solve uses relative
- * tolerance eta. */
+ * tolerance eta.  A residual above dtol |R(u_0)| stops the increment with
+ * JFNK_E_DIVERGED (dtol <= 0: 1e8).
+ * line_search (the globalisation of Section 3.2, which asks only for a step
+ * s > 0 that decreases |R|): 0 takes the full step s = 1; 1 tries
+ * s = 1, 1/2, 1/4, ... and accepts the first with |R(u + s du)| < |R(u)|
+ * (a NaN residual counts as no decrease); after max_backtrack halvings
+ * (<= 0: 8) the last trial is accepted.
+ * inc_begin, inc_end (1-based, inclusive; <= 0: the first and the last):
+ * solve only increments inc_begin .. inc_end of the n_increments, starting
+ * from the given d_u (e.g. the converged state of increment inc_begin - 1),
+ * so that a caller can inspect every increment. */
 typedef struct {
   int32_t n_increments;
   int32_t max_newton_it;
@@ -228,6 +240,11 @@ typedef struct {
   double atol;
   double eta;
   jfnk_gmres_opts gmres;
+  double dtol;
+  int32_t line_search;
+  int32_t max_backtrack;
+  int32_t inc_begin;
+  int32_t inc_end;
 } jfnk_newton_opts;
 
 typedef struct {
@@ -263,9 +280,13 @@ jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, dou
  * returns accumulated milliseconds and launch counts per kernel class:
  * [0] step-size norms, [1] gradient pass, [2] flux/divergence pass (or the
  * fused single pass, which has no separate gradient pass),
- * [3] preconditioner, then optionally resets.  Not for concurrent callers. */
+ * [3] preconditioner, [4] Arnoldi orthogonalisation (both Gram-Schmidt
+ * passes, norm, Givens update, basis scaling), [5] other solver vector work
+ * (solution update and true residual of a cycle), then optionally resets.
+ * While profiling is on, GMRES launches directly (no graph replay).  Not for
+ * concurrent callers. */
 jfnk_status jfnk_profile_enable(jfnk_mesh* mesh, int32_t on);
-jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms /*[4]*/, int64_t* calls /*[4]*/,
+jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms /*[6]*/, int64_t* calls /*[6]*/,
                               int32_t reset);
 
 /* ---- Batches: many independent meshes solved together ----

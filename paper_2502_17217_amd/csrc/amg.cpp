@@ -489,8 +489,8 @@ HostCsr multiply(const HostCsr& X, const HostCsr& Y, bool sorted = true) {
   });
 }
 
-// Inverse of a small SPD matrix by Cholesky (FP64), returned row-major in FP32.
-std::vector<float> dense_inverse(const HostCsr& A) {
+// Inverse of a small SPD matrix by Cholesky (FP64), returned column-major.
+std::vector<double> dense_inverse(const HostCsr& A) {
   const int64_t n = A.n;
   std::vector<double> L(n * n, 0.0);
   for (int64_t i = 0; i < n; ++i)
@@ -510,7 +510,7 @@ std::vector<float> dense_inverse(const HostCsr& A) {
       L[i * n + j] = t / ljj;
     }
   }
-  std::vector<float> inv(n * n);
+  std::vector<double> inv(n * n);
   std::vector<double> x(n);
   for (int64_t c = 0; c < n; ++c) {
     for (int64_t i = 0; i < n; ++i) {
@@ -523,7 +523,7 @@ std::vector<float> dense_inverse(const HostCsr& A) {
       for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * x[k];
       x[i] = t / L[i * n + i];
     }
-    for (int64_t i = 0; i < n; ++i) inv[c * n + i] = float(x[i]);   // column-major
+    for (int64_t i = 0; i < n; ++i) inv[c * n + i] = x[i];   // column-major
   }
   return inv;
 }
@@ -548,9 +548,24 @@ ChebCoef cheb_coefficients(double lmax, int degree) {
   return c;
 }
 
+// Uploads FP64 host values in the hierarchy's precision.
+void upload_values(DevBuf& buf, const double* v, size_t count, bool fp64, hipStream_t s) {
+  buf.alloc(std::max<size_t>(count * (fp64 ? 8 : 4), 256));
+  if (count == 0) return;
+  if (fp64) {
+    JFNK_HIP(hipMemcpyAsync(buf.p, v, count * 8, hipMemcpyHostToDevice, s));
+  } else {
+    std::vector<float> f(v, v + count);
+    JFNK_HIP(hipMemcpyAsync(buf.p, f.data(), count * 4, hipMemcpyHostToDevice, s));
+    JFNK_HIP(hipStreamSynchronize(s));   // f goes out of scope
+    return;
+  }
+  JFNK_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
-void DevCsr::upload(const HostCsr& h, hipStream_t s) {
+void DevCsr::upload(const HostCsr& h, bool fp64, hipStream_t s) {
   n = int32_t(h.n);
   m = int32_t(h.m);
   // each row is shared by the fewest lanes (a power of two) that leave at most
@@ -559,32 +574,30 @@ void DevCsr::upload(const HostCsr& h, hipStream_t s) {
   const double avg = h.n > 0 ? double(h.col.size()) / double(h.n) : 0.0;
   lanes = 1;
   while (lanes < 64 && avg > 3.0 * lanes) lanes *= 2;
-  std::vector<float> v(h.val.begin(), h.val.end());
   ptr.alloc(std::max<size_t>(h.ptr.size() * 4, 256));
   col.alloc(std::max<size_t>(h.col.size() * 4, 256));
-  val.alloc(std::max<size_t>(v.size() * 4, 256));
   JFNK_HIP(hipMemcpyAsync(ptr.p, h.ptr.data(), h.ptr.size() * 4, hipMemcpyHostToDevice, s));
-  if (!h.col.empty()) {
-    JFNK_HIP(hipMemcpyAsync(col.p, h.col.data(), h.col.size() * 4, hipMemcpyHostToDevice, s));
-    JFNK_HIP(hipMemcpyAsync(val.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
-  }
-  JFNK_HIP(hipStreamSynchronize(s));
+  if (!h.col.empty()) JFNK_HIP(hipMemcpyAsync(col.p, h.col.data(), h.col.size() * 4, hipMemcpyHostToDevice, s));
+  upload_values(val, h.val.data(), h.val.size(), fp64, s);
 }
 
 size_t amg_work_floats(int64_t n, int dim) {
-  // upper bound before setup: five work vectors per level with a geometric
-  // level-size bound (each level at most 3/4 of the previous one)
+  // upper bound before setup, in elements of the hierarchy's precision: five
+  // work vectors per level with a geometric level-size bound (each level at
+  // most 3/4 of the previous one)
   return size_t(5) * dim * size_t(4 * n + 64 * kMaxLevels) + 2 * kDenseMax * dim;
 }
 
 size_t amg_work_floats(const jfnk_mesh* m) { return amg_work_floats(m->host.n_cells, m->host.dim); }
 
-void amg_setup(jfnk_mesh* m, hipStream_t s) {
-  if (m->amg) return;
+void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
+  AmgHierarchy*& slot = fp64 ? m->amg64 : m->amg;
+  if (slot) return;
   const double t0 = now_ms();
   auto H = new AmgHierarchy();
   try {
     H->dim = m->host.dim;
+    H->fp64 = fp64;
     HostCsr A = fine_operator(m->host);
     const double nnz0 = double(A.nnz());
     size_t off = 0;
@@ -603,35 +616,46 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
       if (last) {
         L.off_x = take(A.n);
         L.off_b = take(A.n);
-        H->coarse_inv.alloc(size_t(A.n) * A.n * 4);
-        std::vector<float> inv = dense_inverse(A);
-        JFNK_HIP(hipMemcpyAsync(H->coarse_inv.p, inv.data(), inv.size() * 4, hipMemcpyHostToDevice, s));
-        JFNK_HIP(hipStreamSynchronize(s));
+        std::vector<double> inv = dense_inverse(A);
+        upload_values(H->coarse_inv, inv.data(), inv.size(), fp64, s);
+        H->n_coarse = A.n;
+        H->levels.push_back(std::move(L));
+        break;
+      }
+      int64_t nagg = 0;
+      std::vector<int32_t> agg = aggregate(A, d, nagg);
+      if (nagg == 0) {
+        // No row has a strong neighbour (every mesh of a batch already
+        // reduced to uncoupled unknowns): the diagonal inverse solves this
+        // level exactly up to the weak couplings, which the smoothers of the
+        // finer levels treat.
+        L.off_x = take(A.n);
+        L.off_b = take(A.n);
+        std::vector<double> dinv(A.n);
+        for (int64_t i = 0; i < A.n; ++i) dinv[i] = 1.0 / d[i];
+        upload_values(H->coarse_inv, dinv.data(), dinv.size(), fp64, s);
+        H->coarse_diag = true;
         H->n_coarse = A.n;
         H->levels.push_back(std::move(L));
         break;
       }
       L.lmax = lambda_max(A, d);
-      int64_t nagg = 0;
-      std::vector<int32_t> agg = aggregate(A, d, nagg);
       HostCsr P = smoothed_prolongator(A, d, agg, nagg, 4.0 / (3.0 * L.lmax));
       HostCsr R = transpose(P);
       HostCsr Ac = multiply(R, multiply(A, P, false));
-      L.A.upload(A, s);
-      L.P.upload(P, s);
-      L.R.upload(R, s);
-      std::vector<float> dinv(A.n);
-      for (int64_t i = 0; i < A.n; ++i) dinv[i] = float(1.0 / d[i]);
-      L.dinv.alloc(dinv.size() * 4);
-      JFNK_HIP(hipMemcpyAsync(L.dinv.p, dinv.data(), dinv.size() * 4, hipMemcpyHostToDevice, s));
-      JFNK_HIP(hipStreamSynchronize(s));
+      L.A.upload(A, fp64, s);
+      L.P.upload(P, fp64, s);
+      L.R.upload(R, fp64, s);
+      std::vector<double> dinv(A.n);
+      for (int64_t i = 0; i < A.n; ++i) dinv[i] = 1.0 / d[i];
+      upload_values(L.dinv, dinv.data(), dinv.size(), fp64, s);
       L.off_x = take(A.n);
       L.off_b = take(A.n);
       L.off_r = take(A.n);
       L.off_d0 = take(A.n);
       L.off_d1 = take(A.n);
       H->levels.push_back(std::move(L));
-      JFNK_REQUIRE(nagg > 0 && nagg < A.n, JFNK_E_MESH, "amg: aggregation stalled on a large level");
+      JFNK_REQUIRE(nagg < A.n, JFNK_E_MESH, "amg: aggregation stalled on a large level");
       A = std::move(Ac);
     }
     H->work_floats = off;
@@ -642,7 +666,7 @@ void amg_setup(jfnk_mesh* m, hipStream_t s) {
     delete H;
     throw;
   }
-  m->amg = H;
+  slot = H;
 }
 
 namespace {
@@ -650,60 +674,78 @@ namespace {
 // r64 / z64 (finest level only): the FP64 right-hand side, rounded into b
 // by the first smoothing launch, and the FP64 output z = -x, written by the
 // last one (the casts need no launches of their own).
-void vcycle(const AmgHierarchy& H, size_t l, int degree, float* w, hipStream_t s, const int32_t* gate,
+template <class T>
+void vcycle(const AmgHierarchy& H, size_t l, int degree, T* w, hipStream_t s, const int32_t* gate,
             const double* r64 = nullptr, double* z64 = nullptr) {
   const AmgLevel& L = H.levels[l];
   const int dim = H.dim;
-  float* x = w + L.off_x;
-  float* b = w + L.off_b;
+  T* x = w + L.off_x;
+  T* b = w + L.off_b;
   if (l + 1 == H.levels.size()) {
-    if (r64) amg_cast_in(r64, b, L.n, dim, s, gate);
-    amg_dense(H.coarse_inv.as<float>(), b, x, int(H.n_coarse), dim, s, gate);
-    if (z64) amg_cast_out(x, z64, L.n, dim, s, gate);
+    if (r64) amg_cast_in<T>(r64, b, L.n, dim, s, gate);
+    if (H.coarse_diag)
+      amg_diag_solve<T>(H.coarse_inv.as<T>(), b, x, int(H.n_coarse), dim, s, gate);
+    else
+      amg_dense<T>(H.coarse_inv.as<T>(), b, x, int(H.n_coarse), dim, s, gate);
+    if (z64) amg_cast_out<T>(x, z64, L.n, dim, s, gate);
     return;
   }
-  float* r = w + L.off_r;
-  float* d0 = w + L.off_d0;
-  float* d1 = w + L.off_d1;
-  const float* dinv = L.dinv.as<float>();
+  T* r = w + L.off_r;
+  T* d0 = w + L.off_d0;
+  T* d1 = w + L.off_d1;
+  const T* dinv = L.dinv.as<T>();
   ChebCoef cc = cheb_coefficients(L.lmax, degree);
   // pre-smoothing from x = 0
-  amg_cheb_start0(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate, r64);
+  amg_cheb_start0<T>(L.A, dinv, b, x, r, d0, T(cc.inv_theta), dim, s, gate, r64);
   for (int k = 0; k + 1 < degree; ++k) {
-    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate);
+    amg_cheb_step<T>(L.A, dinv, d0, d1, r, x, T(cc.c1[k]), T(cc.c2[k]), dim, s, gate);
     std::swap(d0, d1);
   }
   // coarse-grid correction
-  amg_residual(L.A, b, x, r, dim, s, gate);
+  amg_residual<T>(L.A, b, x, r, dim, s, gate);
   const AmgLevel& C = H.levels[l + 1];
-  amg_spmv(L.R, r, w + C.off_b, false, dim, s, gate);
-  vcycle(H, l + 1, degree, w, s, gate);
-  amg_spmv(L.P, w + C.off_x, x, true, dim, s, gate);
+  amg_spmv<T>(L.R, r, w + C.off_b, false, dim, s, gate);
+  vcycle<T>(H, l + 1, degree, w, s, gate);
+  amg_spmv<T>(L.P, w + C.off_x, x, true, dim, s, gate);
   // post-smoothing; the start's x += d rides on the first step's launch
   d0 = w + L.off_d0;
   d1 = w + L.off_d1;
   const bool steps = degree > 1;
-  amg_cheb_start(L.A, dinv, b, x, r, d0, float(cc.inv_theta), dim, s, gate, steps, steps ? nullptr : z64);
+  amg_cheb_start<T>(L.A, dinv, b, x, r, d0, T(cc.inv_theta), dim, s, gate, steps, steps ? nullptr : z64);
   for (int k = 0; k + 1 < degree; ++k) {
-    amg_cheb_step(L.A, dinv, d0, d1, r, x, float(cc.c1[k]), float(cc.c2[k]), dim, s, gate, k == 0,
-                  k + 2 == degree ? z64 : nullptr);
+    amg_cheb_step<T>(L.A, dinv, d0, d1, r, x, T(cc.c1[k]), T(cc.c2[k]), dim, s, gate, k == 0,
+                     k + 2 == degree ? z64 : nullptr);
     std::swap(d0, d1);
   }
 }
 
 }  // namespace
 
-void amg_apply(jfnk_mesh* m, int cheb_degree, const double* r, double* z, float* work, hipStream_t s,
-               const int32_t* gate) {
-  JFNK_REQUIRE(m->amg != nullptr, JFNK_E_ARG, "amg: not set up");
+// work: the preconditioner region of the solve workspace, holding
+// H.work_floats elements of the hierarchy's precision.
+void amg_apply(jfnk_mesh* m, bool fp64, int cheb_degree, const double* r, double* z, void* work,
+               hipStream_t s, const int32_t* gate) {
+  const AmgHierarchy* H = fp64 ? m->amg64 : m->amg;
+  JFNK_REQUIRE(H != nullptr, JFNK_E_ARG, "amg: not set up");
   JFNK_REQUIRE(work != nullptr, JFNK_E_ARG, "amg: no workspace");
-  const AmgHierarchy& H = *m->amg;
   Profiler& p = m->prof;
   const int t = p.on ? p.begin(3, s) : -1;
-  vcycle(H, 0, cheb_degree, work, s, gate, r, z);
+  if (fp64)
+    vcycle<double>(*H, 0, cheb_degree, static_cast<double*>(work), s, gate, r, z);
+  else
+    vcycle<float>(*H, 0, cheb_degree, static_cast<float*>(work), s, gate, r, z);
   if (t >= 0) p.end(t, s);
 }
 
 void amg_destroy(AmgHierarchy* a) { delete a; }
+
+size_t amg_device_bytes(const AmgHierarchy* a) {
+  if (a == nullptr) return 0;
+  size_t b = a->coarse_inv.bytes;
+  for (const AmgLevel& L : a->levels)
+    b += L.dinv.bytes + L.A.ptr.bytes + L.A.col.bytes + L.A.val.bytes + L.P.ptr.bytes + L.P.col.bytes +
+         L.P.val.bytes + L.R.ptr.bytes + L.R.col.bytes + L.R.val.bytes;
+  return b;
+}
 
 }  // namespace jfnk

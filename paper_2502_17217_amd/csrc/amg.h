@@ -1,4 +1,5 @@
-// FP32 smoothed-aggregation AMG for the compact-stencil approximate Jacobian.
+// Smoothed-aggregation AMG for the compact-stencil approximate Jacobian,
+// stored and applied in FP32 (or FP64 for the full-precision twin).
 #pragma once
 
 #include <vector>
@@ -15,25 +16,27 @@ struct HostCsr {
   int64_t nnz() const { return int64_t(col.size()); }
 };
 
-// Device CSR matrix (FP32 values).
+// Device CSR matrix (FP32 or FP64 values).
 struct DevCsr {
   int32_t n = 0, m = 0;
   int32_t lanes = 1;      // lanes that share a row in the row kernels (power of two, <= 64)
   DevBuf ptr, col, val;
-  void upload(const HostCsr& h, hipStream_t s);
+  void upload(const HostCsr& h, bool fp64, hipStream_t s);
 };
 
 struct AmgLevel {
   int64_t n = 0;
   DevCsr A, P, R;         // operator; prolongation (n x n_next); restriction = P^T
-  DevBuf dinv;            // FP32 inverse diagonal of A
+  DevBuf dinv;            // inverse diagonal of A (the hierarchy's precision)
   double lmax = 2.0;      // largest eigenvalue estimate of D^{-1} A
   size_t off_x = 0, off_b = 0, off_r = 0, off_d0 = 0, off_d1 = 0;  // workspace offsets (floats)
 };
 
 struct AmgHierarchy {
-  std::vector<AmgLevel> levels;      // last level is solved by the dense inverse
-  DevBuf coarse_inv;                 // [n_c][n_c] FP32, column-major
+  std::vector<AmgLevel> levels;      // last level is solved by the dense inverse (or its diagonal)
+  bool fp64 = false;                 // values and work vectors in FP64 (else FP32)
+  bool coarse_diag = false;          // coarsest rows uncoupled: coarse_inv holds D^{-1} only
+  DevBuf coarse_inv;                 // [n_c][n_c] column-major, or [n_c] when coarse_diag
   int64_t n_coarse = 0;
   int dim = 3;
   size_t work_floats = 0;
@@ -41,30 +44,38 @@ struct AmgHierarchy {
   double setup_ms = 0;
 };
 
-// ---- kernels (amg_kernels.hip); vectors are component-major FP32 [dim][n] ----
-void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate);
-void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate);
+// ---- kernels (amg_kernels.hip), T = float or double; vectors are
+// component-major [dim][n] ----
+template <class T>
+void amg_cast_in(const double* r, T* b, int64_t n, int dim, hipStream_t s, const int32_t* gate);
+template <class T>
+void amg_cast_out(const T* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate);
 // Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d; with r64
-// given, b = (float) r64 first (the finest level's FP64 input)
-void amg_cheb_start0(const DevCsr& A, const float* dinv, float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s, const int32_t* gate, const double* r64 = nullptr);
+// given, b = (T) r64 first (the finest level's FP64 input)
+template <class T>
+void amg_cheb_start0(const DevCsr& A, const T* dinv, T* b, T* x, T* r, T* d, T inv_theta, int dim,
+                     hipStream_t s, const int32_t* gate, const double* r64 = nullptr);
 // Chebyshev start from a given x: r = D^-1 (b - A x), d = r/theta, x += d
 // (defer_axpy: the next step applies x += d; z64 given: also z = -x in FP64)
-void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s, const int32_t* gate, bool defer_axpy = false,
-                    double* z64 = nullptr);
+template <class T>
+void amg_cheb_start(const DevCsr& A, const T* dinv, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
+                    hipStream_t s, const int32_t* gate, bool defer_axpy = false, double* z64 = nullptr);
 // one Chebyshev step: r -= D^-1 A d_in; d_out = c1 d_in + c2 r; x += d_out
 // (pend: x += d_in first, the deferred start update; z64 given: z = -x in FP64)
-void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate, bool pend = false,
-                   double* z64 = nullptr);
+template <class T>
+void amg_cheb_step(const DevCsr& A, const T* dinv, const T* d_in, T* d_out, T* r, T* x, T c1, T c2, int dim,
+                   hipStream_t s, const int32_t* gate, bool pend = false, double* z64 = nullptr);
 // r = b - A x
-void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
-                  const int32_t* gate);
+template <class T>
+void amg_residual(const DevCsr& A, const T* b, const T* x, T* r, int dim, hipStream_t s, const int32_t* gate);
 // y = M x (restriction) or y += M x (prolongation, accumulate = true)
-void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s,
-              const int32_t* gate);
+template <class T>
+void amg_spmv(const DevCsr& M, const T* x, T* y, bool accumulate, int dim, hipStream_t s, const int32_t* gate);
 // x = inv * b (dense, n x n)
-void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s, const int32_t* gate);
+template <class T>
+void amg_dense(const T* inv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate);
+// x = dinv * b (coarsest level of uncoupled rows)
+template <class T>
+void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate);
 
 }  // namespace jfnk

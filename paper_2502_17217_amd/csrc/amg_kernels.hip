@@ -1,6 +1,8 @@
-// FP32 kernels of the AMG V-cycle (gfx950).  One thread per matrix row;
-// every kernel handles all displacement components (component-major arrays
-// [dim][n]) so that a matrix row is read once for the dim right-hand sides.
+// Kernels of the AMG V-cycle (gfx950), instantiated for FP32 (the
+// preconditioner of the mixed-precision path) and FP64 (its full-precision
+// twin).  One thread, or a group of lanes, per matrix row; every kernel
+// handles all displacement components (component-major arrays [dim][n]) so
+// that a matrix row is read once for the dim right-hand sides.
 #include "amg.h"
 
 namespace jfnk {
@@ -14,18 +16,18 @@ inline int blocks_for(int64_t n) { return int((n + kB - 1) / kB); }
 // Row i of a CSR matrix times x (D components), shared by the G lanes of a
 // group: lane `sub` takes nonzeros sub, sub + G, ..., then a fixed butterfly
 // over the group leaves the row's sums in every lane of it.
-template <int D, int G>
+template <class T, int D, int G>
 __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                        const float* __restrict__ val, const float* __restrict__ x,
-                                        int m, int i, int sub, float (&s)[D]) {
+                                        const T* __restrict__ val, const T* __restrict__ x,
+                                        int m, int i, int sub, T (&s)[D]) {
 #pragma unroll
-  for (int q = 0; q < D; ++q) s[q] = 0.f;
+  for (int q = 0; q < D; ++q) s[q] = T(0);
   const int a = ptr[i], b = ptr[i + 1];
   for (int k = a + sub; k < b; k += G) {
-    const float v = val[k];
+    const T v = val[k];
     const int j = col[k];
 #pragma unroll
-    for (int q = 0; q < D; ++q) s[q] = fmaf(v, x[size_t(q) * m + j], s[q]);
+    for (int q = 0; q < D; ++q) s[q] = fma(v, x[size_t(q) * m + j], s[q]);
   }
   if constexpr (G > 1) {
 #pragma unroll
@@ -42,17 +44,17 @@ __device__ __forceinline__ int row_of(int& sub) {
   return blockIdx.x * (kB / G) + threadIdx.x / G;
 }
 
-__global__ __launch_bounds__(kB) void k_cast_in(const double* __restrict__ r, float* __restrict__ b,
-                                                int64_t total,
-    const int32_t* __restrict__ gate) {
+template <class T>
+__global__ __launch_bounds__(kB) void k_cast_in(const double* __restrict__ r, T* __restrict__ b,
+                                                int64_t total, const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
-  if (i < total) b[i] = float(r[i]);
+  if (i < total) b[i] = T(r[i]);
 }
 
-__global__ __launch_bounds__(kB) void k_cast_out(const float* __restrict__ x, double* __restrict__ z,
-                                                 int64_t total,
-    const int32_t* __restrict__ gate) {
+template <class T>
+__global__ __launch_bounds__(kB) void k_cast_out(const T* __restrict__ x, double* __restrict__ z,
+                                                 int64_t total, const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x;
   if (i < total) z[i] = -double(x[i]);   // J_tilde = -A
@@ -60,72 +62,71 @@ __global__ __launch_bounds__(kB) void k_cast_out(const float* __restrict__ x, do
 
 // r64 != null (finest level): the right-hand side arrives in FP64 and is
 // rounded into b here (the cast that would otherwise be its own launch).
-template <int D>
-__global__ __launch_bounds__(kB) void k_cheb_start0(int n, const float* __restrict__ dinv,
-                                                    float* __restrict__ b, float* __restrict__ x,
-                                                    float* __restrict__ r, float* __restrict__ d,
-                                                    float inv_theta, const double* __restrict__ r64,
-    const int32_t* __restrict__ gate) {
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_cheb_start0(int n, const T* __restrict__ dinv,
+                                                    T* __restrict__ b, T* __restrict__ x,
+                                                    T* __restrict__ r, T* __restrict__ d,
+                                                    T inv_theta, const double* __restrict__ r64,
+                                                    const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
-  const float di = dinv[i];
+  const T di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
-    float bo;
+    T bo;
     if (r64 != nullptr) {
-      bo = float(r64[o]);
+      bo = T(r64[o]);
       b[o] = bo;
     } else {
       bo = b[o];
     }
-    const float ri = di * bo;
-    const float dd = ri * inv_theta;
+    const T ri = di * bo;
+    const T dd = ri * inv_theta;
     r[o] = ri;
     d[o] = dd;
     x[o] = dd;
   }
 }
 
-template <int D, int G>
+template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col,
-                                                   const float* __restrict__ val,
-                                                   const float* __restrict__ dinv,
-                                                   const float* __restrict__ b, const float* __restrict__ x,
-                                                   float* __restrict__ r, float* __restrict__ d,
-                                                   float inv_theta,
-    const int32_t* __restrict__ gate) {
+                                                   const T* __restrict__ val,
+                                                   const T* __restrict__ dinv,
+                                                   const T* __restrict__ b, const T* __restrict__ x,
+                                                   T* __restrict__ r, T* __restrict__ d,
+                                                   T inv_theta, const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   int sub;
   const int i = row_of<G>(sub);
   if (i >= n) return;
-  float s[D];
-  row_dot<D, G>(ptr, col, val, x, n, i, sub, s);
+  T s[D];
+  row_dot<T, D, G>(ptr, col, val, x, n, i, sub, s);
   if (sub != 0) return;
-  const float di = dinv[i];
+  const T di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
-    const float ri = di * (b[o] - s[q]);
+    const T ri = di * (b[o] - s[q]);
     r[o] = ri;
     d[o] = ri * inv_theta;
   }
 }
 
 // x += d; z64 != null: also z = -x in FP64 (finest level, J_tilde = -A).
-template <int D>
-__global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restrict__ d, float* __restrict__ x,
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const T* __restrict__ d, T* __restrict__ x,
                                                      double* __restrict__ z64,
-    const int32_t* __restrict__ gate) {
+                                                     const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
-    const float xo = x[o] + d[o];
+    const T xo = x[o] + d[o];
     x[o] = xo;
     if (z64 != nullptr) z64[o] = -double(xo);
   }
@@ -133,31 +134,31 @@ __global__ __launch_bounds__(kB) void k_axpy_inplace(int n, const float* __restr
 
 // pend != 0: the previous start's x += d_in is still to be applied (it is,
 // first: x = (x + d_in) + dd); z64 != null: also z = -x in FP64.
-template <int D, int G>
+template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col,
-                                                  const float* __restrict__ val,
-                                                  const float* __restrict__ dinv,
-                                                  const float* __restrict__ d_in, float* __restrict__ d_out,
-                                                  float* __restrict__ r, float* __restrict__ x, float c1,
-                                                  float c2, int pend, double* __restrict__ z64,
-    const int32_t* __restrict__ gate) {
+                                                  const T* __restrict__ val,
+                                                  const T* __restrict__ dinv,
+                                                  const T* __restrict__ d_in, T* __restrict__ d_out,
+                                                  T* __restrict__ r, T* __restrict__ x, T c1,
+                                                  T c2, int pend, double* __restrict__ z64,
+                                                  const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   int sub;
   const int i = row_of<G>(sub);
   if (i >= n) return;
-  float s[D];
-  row_dot<D, G>(ptr, col, val, d_in, n, i, sub, s);
+  T s[D];
+  row_dot<T, D, G>(ptr, col, val, d_in, n, i, sub, s);
   if (sub != 0) return;
-  const float di = dinv[i];
+  const T di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
-    const float ri = r[o] - di * s[q];
-    const float dd = fmaf(c1, d_in[o], c2 * ri);
+    const T ri = r[o] - di * s[q];
+    const T dd = fma(c1, d_in[o], c2 * ri);
     r[o] = ri;
     d_out[o] = dd;
-    float xo = x[o];
+    T xo = x[o];
     if (pend) xo += d_in[o];
     xo += dd;
     x[o] = xo;
@@ -165,34 +166,34 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
   }
 }
 
-template <int D, int G>
+template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col,
-                                                 const float* __restrict__ val, const float* __restrict__ b,
-                                                 const float* __restrict__ x, float* __restrict__ r,
-    const int32_t* __restrict__ gate) {
+                                                 const T* __restrict__ val, const T* __restrict__ b,
+                                                 const T* __restrict__ x, T* __restrict__ r,
+                                                 const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   int sub;
   const int i = row_of<G>(sub);
   if (i >= n) return;
-  float s[D];
-  row_dot<D, G>(ptr, col, val, x, n, i, sub, s);
+  T s[D];
+  row_dot<T, D, G>(ptr, col, val, x, n, i, sub, s);
   if (sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) r[size_t(q) * n + i] = b[size_t(q) * n + i] - s[q];
 }
 
-template <int D, int G>
+template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __restrict__ ptr,
-                                             const int32_t* __restrict__ col, const float* __restrict__ val,
-                                             const float* __restrict__ x, float* __restrict__ y, int accumulate,
-    const int32_t* __restrict__ gate) {
+                                             const int32_t* __restrict__ col, const T* __restrict__ val,
+                                             const T* __restrict__ x, T* __restrict__ y, int accumulate,
+                                             const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   int sub;
   const int i = row_of<G>(sub);
   if (i >= n) return;
-  float s[D];
-  row_dot<D, G>(ptr, col, val, x, m, i, sub, s);
+  T s[D];
+  row_dot<T, D, G>(ptr, col, val, x, m, i, sub, s);
   if (sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -205,23 +206,22 @@ __global__ __launch_bounds__(kB) void k_spmv(int n, int m, const int32_t* __rest
 // contiguous), so the 64 lanes of a wave read consecutive rows of one column
 // and b[j] is a broadcast; the four waves of a workgroup take every fourth
 // column and their partial sums meet in LDS.
-template <int D>
-__global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, const float* __restrict__ b,
-                                              float* __restrict__ x, int n,
-    const int32_t* __restrict__ gate) {
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_dense(const T* __restrict__ inv, const T* __restrict__ b,
+                                              T* __restrict__ x, int n, const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   constexpr int kWaves = kB / 64;
-  __shared__ float part[kWaves][D][64];
+  __shared__ T part[kWaves][D][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
-  float s[D];
+  T s[D];
 #pragma unroll
-  for (int q = 0; q < D; ++q) s[q] = 0.f;
+  for (int q = 0; q < D; ++q) s[q] = T(0);
   if (i < n) {
     for (int j = wave; j < n; j += kWaves) {
-      const float a = inv[size_t(j) * n + i];
+      const T a = inv[size_t(j) * n + i];
 #pragma unroll
-      for (int q = 0; q < D; ++q) s[q] = fmaf(a, b[size_t(q) * n + j], s[q]);
+      for (int q = 0; q < D; ++q) s[q] = fma(a, b[size_t(q) * n + j], s[q]);
     }
   }
 #pragma unroll
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, con
   if (wave == 0 && i < n) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      float t = part[0][q][lane];
+      T t = part[0][q][lane];
 #pragma unroll
       for (int w = 1; w < kWaves; ++w) t += part[w][q][lane];
       x[size_t(q) * n + i] = t;
@@ -238,21 +238,33 @@ __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, con
   }
 }
 
+// x = D^{-1} b: the coarsest level when no two of its rows are coupled.
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_diag_solve(const T* __restrict__ dinv, const T* __restrict__ b,
+                                                   T* __restrict__ x, int n, const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const T di = dinv[i];
+#pragma unroll
+  for (int q = 0; q < D; ++q) x[size_t(q) * n + i] = di * b[size_t(q) * n + i];
+}
+
 }  // namespace
 
 #define JFNK_DIM_DISPATCH(dim, KERNEL, ...)                                        \
   do {                                                                             \
     if ((dim) == 3)                                                                \
-      hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__);                                  \
+      hipLaunchKernelGGL((KERNEL<T, 3>), __VA_ARGS__);                             \
     else                                                                           \
-      hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__);                                  \
+      hipLaunchKernelGGL((KERNEL<T, 2>), __VA_ARGS__);                             \
     JFNK_HIP(hipGetLastError());                                                   \
   } while (0)
 
 // Row kernels: dimension and lanes per row (grid sized for lanes * n threads).
-#define JFNK_ROW_CASE(D, G, KERNEL, n, s, ...)                                                      \
-  case G:                                                                                          \
-    hipLaunchKernelGGL((KERNEL<D, G>), dim3(blocks_for(int64_t(n) * G)), dim3(kB), 0, s, __VA_ARGS__); \
+#define JFNK_ROW_CASE(D, G, KERNEL, n, s, ...)                                                           \
+  case G:                                                                                               \
+    hipLaunchKernelGGL((KERNEL<T, D, G>), dim3(blocks_for(int64_t(n) * G)), dim3(kB), 0, s, __VA_ARGS__); \
     break;
 #define JFNK_ROW_DISPATCH_D(D, lanes, KERNEL, n, s, ...)   \
   switch (lanes) {                                        \
@@ -275,54 +287,82 @@ __global__ __launch_bounds__(kB) void k_dense(const float* __restrict__ inv, con
     JFNK_HIP(hipGetLastError());                                               \
   } while (0)
 
-void amg_cast_in(const double* r, float* b, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
+template <class T>
+void amg_cast_in(const double* r, T* b, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
   const int64_t t = n * dim;
-  hipLaunchKernelGGL(k_cast_in, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t, gate);
+  hipLaunchKernelGGL(k_cast_in<T>, dim3(blocks_for(t)), dim3(kB), 0, s, r, b, t, gate);
   JFNK_HIP(hipGetLastError());
 }
 
-void amg_cast_out(const float* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
+template <class T>
+void amg_cast_out(const T* x, double* z, int64_t n, int dim, hipStream_t s, const int32_t* gate) {
   const int64_t t = n * dim;
-  hipLaunchKernelGGL(k_cast_out, dim3(blocks_for(t)), dim3(kB), 0, s, x, z, t, gate);
+  hipLaunchKernelGGL(k_cast_out<T>, dim3(blocks_for(t)), dim3(kB), 0, s, x, z, t, gate);
   JFNK_HIP(hipGetLastError());
 }
 
-void amg_cheb_start0(const DevCsr& A, const float* dinv, float* b, float* x, float* r, float* d,
-                     float inv_theta, int dim, hipStream_t s, const int32_t* gate, const double* r64) {
+template <class T>
+void amg_cheb_start0(const DevCsr& A, const T* dinv, T* b, T* x, T* r, T* d, T inv_theta, int dim,
+                     hipStream_t s, const int32_t* gate, const double* r64) {
   JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dinv, b, x, r, d,
                     inv_theta, r64, gate);
 }
 
-void amg_cheb_start(const DevCsr& A, const float* dinv, const float* b, float* x, float* r, float* d,
-                    float inv_theta, int dim, hipStream_t s, const int32_t* gate, bool defer_axpy,
-                    double* z64) {
+template <class T>
+void amg_cheb_start(const DevCsr& A, const T* dinv, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
+                    hipStream_t s, const int32_t* gate, bool defer_axpy, double* z64) {
   // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
   // by other rows' products in the first pass), or in the next step's launch
   JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_start, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<float>(), dinv, b, x, r, d, inv_theta, gate);
-  if (!defer_axpy) JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, z64, gate);
+                    A.val.as<T>(), dinv, b, x, r, d, inv_theta, gate);
+  if (!defer_axpy)
+    JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, z64, gate);
 }
 
-void amg_cheb_step(const DevCsr& A, const float* dinv, const float* d_in, float* d_out, float* r, float* x,
-                   float c1, float c2, int dim, hipStream_t s, const int32_t* gate, bool pend, double* z64) {
+template <class T>
+void amg_cheb_step(const DevCsr& A, const T* dinv, const T* d_in, T* d_out, T* r, T* x, T c1, T c2, int dim,
+                   hipStream_t s, const int32_t* gate, bool pend, double* z64) {
   JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_step, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<float>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64, gate);
+                    A.val.as<T>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64, gate);
 }
 
-void amg_residual(const DevCsr& A, const float* b, const float* x, float* r, int dim, hipStream_t s,
-                  const int32_t* gate) {
+template <class T>
+void amg_residual(const DevCsr& A, const T* b, const T* x, T* r, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_ROW_DISPATCH(dim, A.lanes, k_residual, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<float>(), b, x, r, gate);
+                    A.val.as<T>(), b, x, r, gate);
 }
 
-void amg_spmv(const DevCsr& M, const float* x, float* y, bool accumulate, int dim, hipStream_t s,
-              const int32_t* gate) {
+template <class T>
+void amg_spmv(const DevCsr& M, const T* x, T* y, bool accumulate, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_ROW_DISPATCH(dim, M.lanes, k_spmv, M.n, s, M.n, M.m, M.ptr.as<int32_t>(), M.col.as<int32_t>(),
-                    M.val.as<float>(), x, y, accumulate ? 1 : 0, gate);
+                    M.val.as<T>(), x, y, accumulate ? 1 : 0, gate);
 }
 
-void amg_dense(const float* inv, const float* b, float* x, int n, int dim, hipStream_t s, const int32_t* gate) {
+template <class T>
+void amg_dense(const T* inv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_dense, dim3((n + 63) / 64), dim3(kB), 0, s, inv, b, x, n, gate);
 }
+
+template <class T>
+void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate) {
+  JFNK_DIM_DISPATCH(dim, k_diag_solve, dim3(blocks_for(n)), dim3(kB), 0, s, dinv, b, x, n, gate);
+}
+
+#define JFNK_AMG_INSTANTIATE(T)                                                                           \
+  template void amg_cast_in<T>(const double*, T*, int64_t, int, hipStream_t, const int32_t*);             \
+  template void amg_cast_out<T>(const T*, double*, int64_t, int, hipStream_t, const int32_t*);            \
+  template void amg_cheb_start0<T>(const DevCsr&, const T*, T*, T*, T*, T*, T, int, hipStream_t,          \
+                                   const int32_t*, const double*);                                        \
+  template void amg_cheb_start<T>(const DevCsr&, const T*, const T*, T*, T*, T*, T, int, hipStream_t,     \
+                                  const int32_t*, bool, double*);                                         \
+  template void amg_cheb_step<T>(const DevCsr&, const T*, const T*, T*, T*, T*, T, T, int, hipStream_t,   \
+                                 const int32_t*, bool, double*);                                          \
+  template void amg_residual<T>(const DevCsr&, const T*, const T*, T*, int, hipStream_t, const int32_t*); \
+  template void amg_spmv<T>(const DevCsr&, const T*, T*, bool, int, hipStream_t, const int32_t*);         \
+  template void amg_dense<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);              \
+  template void amg_diag_solve<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);
+
+JFNK_AMG_INSTANTIATE(float)
+JFNK_AMG_INSTANTIATE(double)
 
 }  // namespace jfnk

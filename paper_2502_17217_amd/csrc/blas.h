@@ -48,9 +48,11 @@ void fill_int(int32_t* d, int n, int32_t v, hipStream_t s);
 void call_setup(int32_t* tickets, int nt, double* load, int S, double value, hipStream_t s);
 // true if some segment has more tiles than the in-kernel finish handles
 bool any_large_segment(const SegLayout& L, const int32_t* h_block_first);
-// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| per active segment
-void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
-                      double* partials, int32_t* tickets, double* eps, hipStream_t s);
+// eps[s] = sqrt(eps_mach) sqrt(1 + |u_s|) / |v_s| per active segment; uu
+// (may be null): |u_s|^2 already known, at uu[s * ldu] (u is then not read)
+void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* uu, int ldu,
+                      const double* v, const int32_t* act, double* partials, int32_t* tickets, double* eps,
+                      hipStream_t s);
 struct GmresDev;
 // Both classical Gram-Schmidt passes of Arnoldi step j against V_0..V_{nk-1}
 // and the device Givens update (h, h2: [n_seg][kMaxBasis], nrm: [n_seg][4]).

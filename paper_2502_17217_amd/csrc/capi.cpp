@@ -76,9 +76,9 @@ void check_opts(const jfnk_gmres_opts& o) {
   JFNK_REQUIRE(o.restart >= 1 && o.restart < kMaxBasis, JFNK_E_ARG, "gmres: restart out of range");
   JFNK_REQUIRE(o.max_it >= 1, JFNK_E_ARG, "gmres: max_it must be >= 1");
   JFNK_REQUIRE(o.rtol >= 0 && o.atol >= 0, JFNK_E_ARG, "gmres: negative tolerance");
-  JFNK_REQUIRE(o.precond >= JFNK_PC_NONE && o.precond <= JFNK_PC_AMG32, JFNK_E_ARG,
+  JFNK_REQUIRE(o.precond >= JFNK_PC_NONE && o.precond <= JFNK_PC_AMG64, JFNK_E_ARG,
                "gmres: unknown preconditioner");
-  JFNK_REQUIRE(o.precond != JFNK_PC_AMG32 || (o.cheb_degree >= 1 && o.cheb_degree <= 16), JFNK_E_ARG,
+  JFNK_REQUIRE(!amg_precond(o.precond) || (o.cheb_degree >= 1 && o.cheb_degree <= 16), JFNK_E_ARG,
                "gmres: cheb_degree must lie in [1, 16]");
   JFNK_REQUIRE(o.step_chunk >= 0 && o.step_chunk <= o.restart, JFNK_E_ARG,
                "gmres: step_chunk must lie in [0, restart]");
@@ -271,6 +271,7 @@ using namespace jfnk;
 
 jfnk_mesh::~jfnk_mesh() {
   if (amg) amg_destroy(amg);   // its buffers take the capture lock themselves
+  if (amg64) amg_destroy(amg64);
   std::shared_lock<std::shared_mutex> lk(capture_mutex());
   graphs.clear();
   for (hipEvent_t& e : ev)
@@ -588,7 +589,7 @@ jfnk_status jfnk_profile_read(jfnk_mesh* mesh, double* ms, int64_t* calls, int32
   return guarded([&] {
     check_mesh(mesh);
     mesh->prof.collect();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < Profiler::kClasses; ++k) {
       if (ms) ms[k] = mesh->prof.ms[k];
       if (calls) calls[k] = mesh->prof.calls[k];
       if (reset) {
@@ -653,7 +654,7 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
     fw.carve(c, mesh);
     if (op == 1) {
       JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
-      JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG32, JFNK_E_ARG,
+      JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG64, JFNK_E_ARG,
                    "workspace_size: unknown preconditioner");
       KrylovWork kw;
       kw.carve(c, mesh, restart, precond_work_floats(mesh, precond));
@@ -768,6 +769,8 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     JFNK_REQUIRE(opts, JFNK_E_ARG, "newton: null options");
     JFNK_REQUIRE(opts->max_newton_it >= 1, JFNK_E_ARG, "newton: max_newton_it must be >= 1");
     JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0, JFNK_E_ARG, "newton: bad tolerance");
+    JFNK_REQUIRE(opts->line_search == 0 || opts->line_search == 1, JFNK_E_ARG, "newton: line_search must be 0 or 1");
+    JFNK_REQUIRE(opts->max_backtrack <= 60, JFNK_E_ARG, "newton: max_backtrack must be <= 60");
     check_opts(opts->gmres);
     const int S = mesh->n_seg();
     std::vector<int> inc(S);

@@ -261,9 +261,12 @@ __device__ __forceinline__ double eps_of(double uu, double vv) {
 // per lane) and writes eps, a large one is finished by k_eps_large (no
 // arrival counter shared by thousands of tiles).  A workgroup sums
 // kEpsTiles tiles at once, every load issued before the first sum (each
-// tile's partial formed as tile_norm2 forms it).
-template <int D>
+// tile's partial formed as tile_norm2 forms it).  kCachedU: |u|^2 of each
+// segment is given (uu[seg * ldu], u fixed over a linear solve) and u is not
+// read.
+template <int D, bool kCachedU>
 __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double* __restrict__ u,
+                                                      const double* __restrict__ uu, int ldu,
                                                       const double* __restrict__ v,
                                                       const int32_t* __restrict__ act,
                                                       double* __restrict__ partials, int32_t* __restrict__ tickets,
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
       const bool on = blk < L.n_blocks && c < n && (act == nullptr || act[L.seg_of_block[blk]] != 0);
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        x[j][q] = on ? u[size_t(q) * n + c] : 0.0;
+        x[j][q] = (on && !kCachedU) ? u[size_t(q) * n + c] : 0.0;
         y[j][q] = on ? v[size_t(q) * n + c] : 0.0;
       }
     }
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
       if (act != nullptr && act[seg] == 0) continue;
       int first, cnt;
       if (small_segment(L, seg, first, cnt) && last_tile_of_segment(tickets + seg, cnt) && threadIdx.x < 64) {
-        const double tu = segment_column_sum(L, partials, first, cnt, 0);
+        const double tu = kCachedU ? uu[size_t(seg) * ldu] : segment_column_sum(L, partials, first, cnt, 0);
         const double tv = segment_column_sum(L, partials, first, cnt, 1);
         if (threadIdx.x == 0) eps[seg] = eps_of(tu, tv);
       }
@@ -325,6 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_eps_tiles(SegLayout L, const double*
 // Large segments, one workgroup of kWideBlock threads each: tile b to
 // thread (b - first) mod kWideBlock, then a fixed tree.
 __global__ __launch_bounds__(kWideBlock) void k_eps_large(SegLayout L, const double* __restrict__ partials,
+                                                          const double* __restrict__ uu, int ldu,
                                                           const int32_t* __restrict__ act,
                                                           double* __restrict__ eps) {
   __shared__ double sh[kWideBlock / 64];
@@ -332,9 +336,9 @@ __global__ __launch_bounds__(kWideBlock) void k_eps_large(SegLayout L, const dou
   if (act != nullptr && act[seg] == 0) return;
   int first, n;
   if (small_segment(L, seg, first, n)) return;
-  double su = strided_column_sum<kWideBlock>(L, partials, 0, first, n);
+  double su = uu != nullptr ? 0.0 : strided_column_sum<kWideBlock>(L, partials, 0, first, n);
   double sv = strided_column_sum<kWideBlock>(L, partials, 1, first, n);
-  su = wide_block_sum(su, sh);
+  su = uu != nullptr ? uu[size_t(seg) * ldu] : wide_block_sum(su, sh);
   sv = wide_block_sum(sv, sh);
   if (threadIdx.x == 0) eps[seg] = eps_of(su, sv);
 }
@@ -372,14 +376,27 @@ void fill_int(int32_t* d, int n, int32_t v, hipStream_t s) {
   JFNK_HIP(hipGetLastError());
 }
 
-void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* v, const int32_t* act,
-                      double* partials, int32_t* tickets, double* eps, hipStream_t s) {
+void launch_eps_fused(const SegLayout& L, bool any_large, const double* u, const double* uu, int ldu,
+                      const double* v, const int32_t* act, double* partials, int32_t* tickets, double* eps,
+                      hipStream_t s) {
   const int grid = (L.n_blocks + kEpsTiles - 1) / kEpsTiles;
-  if (L.dim == 3)
-    hipLaunchKernelGGL(k_eps_tiles<3>, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
-  else
-    hipLaunchKernelGGL(k_eps_tiles<2>, dim3(grid), dim3(kBlock), 0, s, L, u, v, act, partials, tickets, eps);
-  if (any_large) hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kWideBlock), 0, s, L, partials, act, eps);
+  if (uu != nullptr) {
+    if (L.dim == 3)
+      hipLaunchKernelGGL((k_eps_tiles<3, true>), dim3(grid), dim3(kBlock), 0, s, L, u, uu, ldu, v, act, partials,
+                         tickets, eps);
+    else
+      hipLaunchKernelGGL((k_eps_tiles<2, true>), dim3(grid), dim3(kBlock), 0, s, L, u, uu, ldu, v, act, partials,
+                         tickets, eps);
+  } else {
+    if (L.dim == 3)
+      hipLaunchKernelGGL((k_eps_tiles<3, false>), dim3(grid), dim3(kBlock), 0, s, L, u, uu, ldu, v, act, partials,
+                         tickets, eps);
+    else
+      hipLaunchKernelGGL((k_eps_tiles<2, false>), dim3(grid), dim3(kBlock), 0, s, L, u, uu, ldu, v, act, partials,
+                         tickets, eps);
+  }
+  if (any_large)
+    hipLaunchKernelGGL(k_eps_large, dim3(L.n_seg), dim3(kWideBlock), 0, s, L, partials, uu, ldu, act, eps);
   JFNK_HIP(hipGetLastError());
 }
 

@@ -113,58 +113,87 @@ __device__ __forceinline__ double inv_cbrt(double J) {
   return y;
 }
 
+// Neo-Hookean face force (Appendix B, total Lagrangian form of Appendix A):
+// with a = cof(F) Gamma the force is sigma a, sigma = mu/J dev(bbar) +
+// kappa/2 (J - 1/J) I, bbar = J^(-2/3) F F^T.  It is evaluated through
+// H = F - I = (grad w)^T so that no term of size mu |Gamma| cancels against
+// another: near the reference state the stress is small next to mu, and
+// forming F F^T and J and then subtracting I (or the trace) would leave
+// rounding errors of size eps_mach mu |Gamma| in every face force, which the
+// finite difference of J v divides by eps (about sqrt(eps_mach)).  The
+// exact identities used (3 x 3):
+//   J - 1    = tr H + (sum of the principal 2 x 2 minors of H) + det H
+//   cof F    = (1 + tr H) I - H^T + cof H
+//   J F G - a = (H + H^T - tr H I - cof H) G + (J - 1)(G + H G)  =: q
+//   tr(F F^T) - 3 = 2 tr H + |H|^2
+// so that  dev(bbar) a = J^(-2/3) (q - (tr(F F^T) - 3)/3 a)  and
+//   sigma a = mu J^(-5/3) (q - (tr(F F^T) - 3)/3 a)
+//             + kappa (J - 1)(1 + (J - 1)/2)/J a.
+// Plane strain (F_zz = 1, H_zz = 0): cof H drops out of the in-plane
+// components and J - 1 = tr H + det H.
 __device__ __forceinline__ void traction_nh3(const Law& m, const double (&g)[3][3],
                                              const double (&G)[3], double (&t)[3]) {
-  double F[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) F[a][b] = (a == b ? 1.0 : 0.0) + g[b][a];
-  double C[3][3];
-  C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
-  C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
-  C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
-  C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
-  C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
-  C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
-  C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
-  C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
-  C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  const double J = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
-  double trb = 0, a[3], FG[3];
+  // H[a][b] = g[b][a]
+  double C[3][3];   // cofactor matrix of H
+  C[0][0] = g[1][1] * g[2][2] - g[2][1] * g[1][2];
+  C[0][1] = g[2][1] * g[0][2] - g[0][1] * g[2][2];
+  C[0][2] = g[0][1] * g[1][2] - g[1][1] * g[0][2];
+  C[1][0] = g[2][0] * g[1][2] - g[1][0] * g[2][2];
+  C[1][1] = g[0][0] * g[2][2] - g[2][0] * g[0][2];
+  C[1][2] = g[1][0] * g[0][2] - g[0][0] * g[1][2];
+  C[2][0] = g[1][0] * g[2][1] - g[2][0] * g[1][1];
+  C[2][1] = g[2][0] * g[0][1] - g[0][0] * g[2][1];
+  C[2][2] = g[0][0] * g[1][1] - g[1][0] * g[0][1];
+  const double tr = g[0][0] + g[1][1] + g[2][2];
+  const double detH = g[0][0] * C[0][0] + g[1][0] * C[0][1] + g[2][0] * C[0][2];
+  const double Jm1 = tr + ((C[0][0] + C[1][1] + C[2][2]) + detH);
+  const double J = 1.0 + Jm1;
+  double a[3], q[3], hh = 0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    a[i] = C[i][0] * G[0] + C[i][1] * G[1] + C[i][2] * G[2];
-    FG[i] = F[i][0] * G[0] + F[i][1] * G[1] + F[i][2] * G[2];
+    const double HG = g[0][i] * G[0] + g[1][i] * G[1] + g[2][i] * G[2];
+    const double HtG = g[i][0] * G[0] + g[i][1] * G[1] + g[i][2] * G[2];
+    const double CG = C[i][0] * G[0] + C[i][1] * G[1] + C[i][2] * G[2];
+    a[i] = fma(tr, G[i], G[i]) - HtG + CG;
+    q[i] = ((HG + HtG) - fma(tr, G[i], CG)) + Jm1 * (G[i] + HG);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) trb = fma(F[i][k], F[i][k], trb);
+    for (int k = 0; k < 3; ++k) hh = fma(g[i][k], g[i][k], hh);
   }
+  const double trE = fma(2.0, tr, hh);
   const double y = inv_cbrt(J);
   const double Jm23 = y * y;
   const double invJ = Jm23 * y;
-  const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
-  const double cf = m.mu * Jm23;
+  const double cq = m.mu * (Jm23 * invJ);
+  const double ca = m.kappa * Jm1 * fma(0.5, Jm1, 1.0) * invJ - cq * trE * (1.0 / 3.0);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) t[i] = fma(cf, FG[i], ca * a[i]);
+  for (int i = 0; i < 3; ++i) t[i] = fma(cq, q[i], ca * a[i]);
 }
 
 __device__ __forceinline__ void traction_nh2(const Law& m, const double (&g)[2][2],
                                              const double (&G)[2], double (&t)[2]) {
-  // plane strain: F_zz = 1, out-of-plane terms vanish for an in-plane Gamma
-  const double F00 = 1.0 + g[0][0], F01 = g[1][0], F10 = g[0][1], F11 = 1.0 + g[1][1];
-  const double J = F00 * F11 - F01 * F10;
-  const double a0 = F11 * G[0] - F10 * G[1];
-  const double a1 = -F01 * G[0] + F00 * G[1];
-  const double FG0 = F00 * G[0] + F01 * G[1];
-  const double FG1 = F10 * G[0] + F11 * G[1];
-  const double trb = F00 * F00 + F01 * F01 + F10 * F10 + F11 * F11 + 1.0;
+  // plane strain: F_zz = 1, out-of-plane terms vanish for an in-plane Gamma;
+  // H00 = g00, H01 = g10, H10 = g01, H11 = g11
+  const double tr = g[0][0] + g[1][1];
+  const double detH = g[0][0] * g[1][1] - g[1][0] * g[0][1];
+  const double Jm1 = tr + detH;
+  const double J = 1.0 + Jm1;
+  const double HG0 = g[0][0] * G[0] + g[1][0] * G[1];
+  const double HG1 = g[0][1] * G[0] + g[1][1] * G[1];
+  const double HtG0 = g[0][0] * G[0] + g[0][1] * G[1];
+  const double HtG1 = g[1][0] * G[0] + g[1][1] * G[1];
+  const double a0 = fma(tr, G[0], G[0]) - HtG0;
+  const double a1 = fma(tr, G[1], G[1]) - HtG1;
+  const double q0 = ((HG0 + HtG0) - tr * G[0]) + Jm1 * (G[0] + HG0);
+  const double q1 = ((HG1 + HtG1) - tr * G[1]) + Jm1 * (G[1] + HG1);
+  const double hh = g[0][0] * g[0][0] + g[0][1] * g[0][1] + g[1][0] * g[1][0] + g[1][1] * g[1][1];
+  const double trE = fma(2.0, tr, hh);
   const double y = inv_cbrt(J);
   const double Jm23 = y * y;
   const double invJ = Jm23 * y;
-  const double ca = 0.5 * m.kappa * (J - invJ) - (m.mu / 3.0) * Jm23 * invJ * trb;
-  const double cf = m.mu * Jm23;
-  t[0] = fma(cf, FG0, ca * a0);
-  t[1] = fma(cf, FG1, ca * a1);
+  const double cq = m.mu * (Jm23 * invJ);
+  const double ca = m.kappa * Jm1 * fma(0.5, Jm1, 1.0) * invJ - cq * trE * (1.0 / 3.0);
+  t[0] = fma(cq, q0, ca * a0);
+  t[1] = fma(cq, q1, ca * a1);
 }
 
 template <int D, int LAW>

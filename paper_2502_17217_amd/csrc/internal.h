@@ -365,7 +365,7 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-struct AmgHierarchy;  // FP32 preconditioner (amg.cpp)
+struct AmgHierarchy;  // AMG preconditioner (amg.cpp)
 
 // HIP-event timing of kernel classes (enabled per mesh for measurement).
 struct Profiler {
@@ -376,8 +376,9 @@ struct Profiler {
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
-  double ms[4] = {0, 0, 0, 0};
-  int64_t calls[4] = {0, 0, 0, 0};
+  static constexpr int kClasses = 6;
+  double ms[kClasses] = {0, 0, 0, 0, 0, 0};
+  int64_t calls[kClasses] = {0, 0, 0, 0, 0, 0};
   hipEvent_t get();
   // Record a start event; returns the index for end().
   int begin(int cls, hipStream_t s);
@@ -435,7 +436,8 @@ struct jfnk_mesh {
   size_t pinned_doubles = 0;
   bool pinned_owned = true;
   jfnk_mesh_info info{};
-  jfnk::AmgHierarchy* amg = nullptr;
+  jfnk::AmgHierarchy* amg = nullptr;     // FP32 hierarchy (JFNK_PC_AMG32)
+  jfnk::AmgHierarchy* amg64 = nullptr;   // FP64 hierarchy (JFNK_PC_AMG64)
   jfnk::Profiler prof;
   jfnk::StepGraphs graphs;
   jfnk::Tuning tune;

@@ -12,10 +12,12 @@
 // so their workgroups return at once.  Each restart cycle ends with the true
 // residual b - J x.
 //
-// Newton (Eq. NewtonRaphson, s = 1) with equal load increments k/N per
-// segment (N may differ between segments); convergence per increment when
+// Newton (Eq. NewtonRaphson) with equal load increments k/N per segment (N
+// may differ between segments); convergence per increment when
 // |R(u)| <= max(rtol |R(u_0)|, atol) (Section 3.3, Euclidean norm, stol = 0);
-// linear solves to the relative tolerance eta.
+// linear solves to the relative tolerance eta.  The step length s is 1, or
+// with the line search of Section 3.2 the first of 1, 1/2, 1/4, ... that
+// decreases |R| (per segment).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -105,13 +107,13 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
 }
 
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
-             FvWork& fw, const int32_t* active, hipStream_t s) {
+             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu) {
   Profiler& p = m->prof;
   int t = p.on ? p.begin(0, s) : -1;
   if (eps > 0)
     fill_device(fw.eps, m->n_seg(), eps, s);
   else
-    launch_eps_fused(layout_of(m), m->any_large, u, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
+    launch_eps_fused(layout_of(m), m->any_large, u, uu, 1, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
   if (t >= 0) p.end(t, s);
   SegScalars sc{fw.eps, fw.load_ptr(), active, fw.load1};
   if (m->dev.lds_kernels == 2) {
@@ -148,10 +150,13 @@ void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const doub
     double* Vj = kw.V + size_t(j) * n;
     double* Zj = kw.Z + size_t(j) * n;
     precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
-    jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s);
+    jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s, kw.uu);
+    Profiler& p = m->prof;
+    const int t = p.on ? p.begin(4, s) : -1;
     cgs2_step(L, m->any_large, kw.V, n, j + 1, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, fw.cgs_tickets(),
               fw.step_counters(), kw.gd, j, o.max_it, s);
     if (j + 1 < o.restart) blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
+    if (t >= 0) p.end(t, s);
   }
 }
 
@@ -173,6 +178,9 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   std::vector<char> part = part_in.empty() ? std::vector<char>(S, 1) : part_in;
   out.assign(S, GmresSeg());
   upload_flags(m, part, kw.act, s);
+  // |u|^2 per segment, once: u is fixed over the solve, so the automatic J v
+  // step of every Arnoldi step needs only |v|
+  if (o.eps <= 0) blas_mdot(L, u, 0, 1, u, fw.partials, kw.uu, 1, false, kw.act, s);
   std::vector<double> v2;
   seg_norms2(m, L, b, fw, kw, kw.act, s, v2);
   std::vector<double> target(S), beta(S), prev(S);
@@ -191,7 +199,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   if (x_is_zero) {
     blas_lincomb(1.0, b, 0.0, b, kw.r, n, s);
   } else {
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s, kw.uu);
     for (int g = 0; g < S; ++g) out[g].jv += part[g];
     blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
   }
@@ -299,11 +307,21 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
     }
     const double te = now_ms();
     // x += Z y on the segments that ran, then the true residual
-    gmres_lsq(G, S, kw.y, s);
-    blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s);
-    blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
-    blas_mdot(L, kw.r, 0, 1, kw.r, fw.partials, kw.nrm, 4, false, G.ran, s);
+    {
+      Profiler& p = m->prof;
+      const int t = p.on ? p.begin(5, s) : -1;
+      gmres_lsq(G, S, kw.y, s);
+      blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
+      if (t >= 0) p.end(t, s);
+    }
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s, kw.uu);
+    {
+      Profiler& p = m->prof;
+      const int t = p.on ? p.begin(5, s) : -1;
+      blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
+      blas_mdot(L, kw.r, 0, 1, kw.r, fw.partials, kw.nrm, 4, false, G.ran, s);
+      if (t >= 0) p.end(t, s);
+    }
     JFNK_HIP(hipMemcpy2DAsync(pin, sizeof(double), kw.nrm, 4 * sizeof(double), sizeof(double), S,
                               hipMemcpyDeviceToHost, s));
     JFNK_HIP(hipMemcpyAsync(pin_i, G.its, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
@@ -355,12 +373,20 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
   jfnk_gmres_opts go = o.gmres;
   go.rtol = o.eta;
   go.atol = 0.0;
-  std::vector<int> inc(S, 1), it_inc(S, 0);
+  std::vector<int> inc(S, 1), it_inc(S, 0), last(S);
   std::vector<char> done(S, 0), fresh(S, 1), part(S, 0);
   std::vector<double> load(S), r0(S, 0.0), rn(S), v2;
-  for (int g = 0; g < S; ++g) load[g] = 1.0 / n_inc[g];
+  for (int g = 0; g < S; ++g) {
+    inc[g] = std::min(std::max(o.inc_begin, 1), n_inc[g]);
+    last[g] = o.inc_end > 0 ? std::min(std::max(o.inc_end, inc[g]), n_inc[g]) : n_inc[g];
+    load[g] = double(inc[g]) / n_inc[g];
+  }
   std::vector<GmresSeg> gres;
   double t_ms[8] = {0};
+  const double dtol = o.dtol > 0 ? o.dtol : 1e8;
+  const int max_bt = o.max_backtrack > 0 ? o.max_backtrack : 8;
+  std::vector<double> step(S, 1.0);
+  std::vector<char> trial(S, 0);
   while (true) {
     upload_doubles(m, load, fw.load, s);
     std::vector<char> live(S);
@@ -388,7 +414,7 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
         continue;
       }
       if (rn[g] <= std::max(o.rtol * r0[g], o.atol)) {
-        if (inc[g] >= n_inc[g]) {
+        if (inc[g] >= last[g]) {
           done[g] = 1;
         } else {
           ++inc[g];
@@ -403,7 +429,7 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
         done[g] = 1;
         continue;
       }
-      if (rn[g] > 1e8 * std::max(r0[g], 1e-300)) {
+      if (rn[g] > dtol * std::max(r0[g], 1e-300)) {
         status[g] = JFNK_E_DIVERGED;
         done[g] = 1;
         continue;
@@ -431,7 +457,44 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
         done[g] = 1;
       }
     }
-    blas_axpby(1.0, kw.du, 1.0, u, n, s);
+    if (!o.line_search) {
+      blas_axpby(1.0, kw.du, 1.0, u, n, s);
+      continue;
+    }
+    // Line search: u = u_old + s du per segment, u_old kept in kw.b (the
+    // right-hand side is no longer needed); segments still searching have
+    // their residual evaluated, the others keep their accepted step (their u
+    // is recomputed with the same operands, so it does not change).
+    blas_lincomb(1.0, u, 0.0, u, kw.b, n, s);
+    for (int g = 0; g < S; ++g) {
+      step[g] = 1.0;
+      trial[g] = part[g] && !done[g];
+    }
+    const double tl = now_ms();
+    for (int t = 0;; ++t) {
+      upload_doubles(m, step, kw.fac, s);
+      blas_scale_seg(L, kw.du, kw.fac, kw.w, nullptr, s);
+      blas_lincomb(1.0, kw.b, 1.0, kw.w, u, n, s);
+      bool any = false;
+      for (int g = 0; g < S; ++g) any = any || trial[g];
+      if (!any) break;
+      upload_flags(m, trial, kw.act, s);
+      residual_into(m, u, kw.R, fw, kw.act, s);
+      seg_norms2(m, L, kw.R, fw, kw, kw.act, s, v2);
+      for (int g = 0; g < S; ++g) {
+        if (!trial[g]) continue;
+        const double rt = std::sqrt(v2[g]);
+        if (rt < rn[g] || t >= max_bt) {
+          trial[g] = 0;   // accepted (a NaN never compares below)
+        } else {
+          step[g] *= 0.5;
+        }
+      }
+      bool again = false;
+      for (int g = 0; g < S; ++g) again = again || trial[g];
+      if (!again) break;
+    }
+    t_ms[4] += now_ms() - tl;
   }
   t_ms[0] = now_ms() - t0;
   for (int g = 0; g < S; ++g)

@@ -136,7 +136,12 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   info.n_cells = h.n_cells;
   const jfnk_newton_opts& o = r->opts;
   const size_t pcf = precond_work_floats(h.n_cells, h.dim, o.gmres.precond);
-  const size_t amg_mats = o.gmres.precond == JFNK_PC_AMG32 ? size_t(h.n_cells) * 256 : 0;
+  // AMG matrices: an estimate (about 60 B per fine row in FP32 on the meshes
+  // measured, with margin); the hierarchy's actual bytes are checked after
+  // its setup and any excess is added to the reservation
+  const size_t amg_mats = amg_precond(o.gmres.precond)
+                              ? size_t(h.n_cells) * (o.gmres.precond == JFNK_PC_AMG64 ? 512 : 256)
+                              : 0;
   const size_t foot = device_bytes_of(h) + solve_workspace_bytes(h.n_cells, h.dim, 1, o.gmres.restart, pcf) +
                       amg_mats + size_t(h.n_cells) * h.dim * 16 + (size_t(1) << 20);
   info.footprint_bytes = int64_t(foot);
@@ -185,6 +190,17 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   KrylovWork kw;
   kw.carve(c, m.get(), o.gmres.restart, pcf);
   precond_setup(m.get(), o.gmres.precond, stream);
+  const size_t amg_real = amg_device_bytes(m->amg) + amg_device_bytes(m->amg64);
+  if (amg_real > amg_mats) {
+    // the estimate was short: account for the excess (the hierarchy already
+    // exists, so the budget may be exceeded by it until this request ends)
+    const size_t extra = amg_real - amg_mats;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->in_use += extra;
+    S->peak = std::max(S->peak, S->in_use);
+    release.foot += extra;
+    info.footprint_bytes += int64_t(extra);
+  }
   std::vector<jfnk_stats> st;
   std::vector<jfnk_status> ss;
   newton_solve(m.get(), std::vector<int>(1, std::max(1, o.n_increments)), o, u.as<double>(), fw, kw, stream,
@@ -198,10 +214,11 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   work.release();
   u.release();
   ue.release();
-  if (m->amg) {
-    amg_destroy(m->amg);
-    m->amg = nullptr;
-  }
+  for (AmgHierarchy** a : {&m->amg, &m->amg64})
+    if (*a) {
+      amg_destroy(*a);
+      *a = nullptr;
+    }
   m.reset();
   JFNK_HIP(hipStreamSynchronize(stream));
 }

@@ -18,8 +18,9 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
 
 // J v into Jv using cached Ru; eps <= 0 selects the automatic per-segment
 // step (computed on the device into fw.eps), eps > 0 is used for every segment.
+// uu (may be null): per-segment |u|^2, when already known.
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
-             FvWork& fw, const int32_t* active, hipStream_t s);
+             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu = nullptr);
 
 struct GmresSeg {
   jfnk_status status = JFNK_OK;
@@ -41,12 +42,16 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk
                   double* u, FvWork& fw, KrylovWork& kw, hipStream_t s, std::vector<jfnk_stats>& stats,
                   std::vector<jfnk_status>& status);
 
+inline bool amg_precond(int precond) { return precond == JFNK_PC_AMG32 || precond == JFNK_PC_AMG64; }
+// Preconditioner work region of a solve workspace, in floats (4-byte units).
 size_t precond_work_floats(const jfnk_mesh* m, int precond);
 size_t precond_work_floats(int64_t n_cells, int dim, int precond);
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s);
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
                    KrylovWork& kw, hipStream_t s);
 void amg_destroy(AmgHierarchy* a);
+// Device bytes held by a hierarchy (0 for null).
+size_t amg_device_bytes(const AmgHierarchy* a);
 void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o, const double* u, double load, void* work, hipStream_t s,
               jfnk_tune_report* rep);
 

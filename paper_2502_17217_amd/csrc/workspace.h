@@ -84,6 +84,7 @@ struct KrylovWork {
   double* fac = nullptr;  // [n_seg] per-segment factors
   int32_t* act = nullptr; // [n_seg] active flags
   double* stage = nullptr;  // [3 n_seg] per-cycle values uploaded by the host
+  double* uu = nullptr;     // [n_seg] |u|^2 of the state of the current linear solve
   GmresDev gd;            // device Arnoldi bookkeeping (shares fac and act)
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
@@ -105,6 +106,7 @@ struct KrylovWork {
     fac = c.take<double>(S);
     act = c.take<int32_t>(S);
     stage = c.take<double>(size_t(3) * S);
+    uu = c.take<double>(S);
     gd.mr = restart;
     gd.H = c.take<double>(size_t(S) * restart * (restart + 1));
     gd.cs = c.take<double>(size_t(S) * restart);

@@ -21,8 +21,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_OOM", -4: "E_HIP", -5
                 -6: "E_DIVERGED", -7: "E_NAN", -8: "E_BREAKDOWN", -9: "E_BUSY"}
 BC = {"displacement": 1, "traction": 2, "pressure": 3}
 LAW = {"linear_elastic": 0, "neo_hookean": 1}
-PC_NONE, PC_JACOBI, PC_AMG32 = 0, 1, 2
-PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32}
+PC_NONE, PC_JACOBI, PC_AMG32, PC_AMG64 = 0, 1, 2, 3
+PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32, "amg64": PC_AMG64}
 
 
 class jfnk_patch(C.Structure):
@@ -61,7 +61,9 @@ class jfnk_gmres_opts(C.Structure):
 
 class jfnk_newton_opts(C.Structure):
     _fields_ = [("n_increments", C.c_int32), ("max_newton_it", C.c_int32), ("rtol", C.c_double),
-                ("atol", C.c_double), ("eta", C.c_double), ("gmres", jfnk_gmres_opts)]
+                ("atol", C.c_double), ("eta", C.c_double), ("gmres", jfnk_gmres_opts),
+                ("dtol", C.c_double), ("line_search", C.c_int32), ("max_backtrack", C.c_int32),
+                ("inc_begin", C.c_int32), ("inc_end", C.c_int32)]
 
 
 class jfnk_stats(C.Structure):
@@ -357,8 +359,10 @@ def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI,
     return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs)
 
 
-def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, **gm):
-    return jfnk_newton_opts(n_increments, max_newton_it, rtol, atol, eta, gmres_opts(**gm))
+def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, dtol=0.0,
+                line_search=0, max_backtrack=0, inc_begin=0, inc_end=0, **gm):
+    return jfnk_newton_opts(n_increments, max_newton_it, rtol, atol, eta, gmres_opts(**gm), dtol,
+                            line_search, max_backtrack, inc_begin, inc_end)
 
 
 def gmres(mesh, load, u, Ru, b, x, opts, work, stream=None, allow=(E_NOT_CONVERGED, E_BREAKDOWN)):
@@ -415,11 +419,12 @@ def profile_enable(mesh, on=True):
 
 
 def profile_read(mesh, reset=True):
-    """Accumulated kernel milliseconds and call counts: eps, gradient, flux, preconditioner."""
-    ms = (C.c_double * 4)()
-    calls = (C.c_int64 * 4)()
+    """Accumulated kernel milliseconds and call counts: eps, gradient, flux,
+    preconditioner, orthogonalisation, other solver vector work."""
+    ms = (C.c_double * 6)()
+    calls = (C.c_int64 * 6)()
     _check(_lib.jfnk_profile_read(mesh.handle, ms, calls, 1 if reset else 0), "jfnk_profile_read")
-    names = ["eps", "gradient", "flux", "precond"]
+    names = ["eps", "gradient", "flux", "precond", "orth", "other"]
     return {n: (ms[i], calls[i]) for i, n in enumerate(names)}
 
 

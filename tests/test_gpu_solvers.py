@@ -27,7 +27,8 @@ def _solve_gpu(lib, m, mat, **kw):
     work = lib.make_workspace(gm, 1, restart=restart, precond=pc)
     u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
     opts = lib.newton_opts(**kw)
-    st, stats = lib.newton_solve(gm, opts, u, work)
+    st, stats = lib.newton_solve(gm, opts, u, work,
+                                 allow=(lib.E_NOT_CONVERGED, lib.E_NAN, lib.E_DIVERGED, lib.E_BREAKDOWN))
     out = gm.to_external(u).cpu().numpy()
     gm.close()
     return out, st, stats
@@ -135,14 +136,46 @@ def test_amg32_fgmres_linear_elastic(lib, dim):
     assert sa["gmres_it"] * 3 < sj["gmres_it"]
 
 
-def test_amg32_neo_hookean_cantilever(lib):
+@pytest.mark.parametrize("precond", ["amg32", "amg64"])
+def test_amg_neo_hookean_cantilever(lib, precond):
+    """FP32- and FP64-stored AMG inside FGMRES on a neo-Hookean cantilever:
+    the GPU iterates past the usual tolerance (Newton rtol 1e-10, so that the
+    comparison measures the solver, not the stopping rule), the oracle is
+    solved with the exact (complex-step) Jacobian action down to the rounding
+    floor of its residual, and the converged displacement meets the 1e-8 bar
+    of the FP32-preconditioned path.  The preconditioner's precision changes
+    only the iteration count."""
     m = mg.cantilever_mesh(40, 8, 4, L=(10.0, 1.0, 1.0), tau=400.0)
     mat = mg.Material("neo_hookean", 1e6, 0.45)
     pr = prepare(m, mat)
-    uo, so = o_newton(pr, n_increments=4, rtol=1e-9, max_newton_it=15, eta=1e-6, precond="lu",
-                      max_krylov_it=3000)
-    ug, st, stats = _newton_both(lib, m, mat, 4, 1e-9, 1e-6, restart=50, precond="amg32")
+    uo, so = o_newton(pr, n_increments=4, rtol=1e-9, max_newton_it=20, eta=1e-6, precond="lu",
+                      restart=200, max_krylov_it=6000, jv="complex_step")
+    assert so["status"] == "ok"
+    ug, st, stats = _newton_both(lib, m, mat, 4, 1e-10, 1e-6, restart=100, precond=precond)
     err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
-    print("NH amg32 rel L2", err, stats, so["newton_it"], so["gmres_it"])
+    print("NH", precond, "rel L2", err, stats, so["newton_it"], so["gmres_it"])
     assert st == lib.OK
-    assert err <= 1e-7
+    assert err <= 1e-8
+
+
+def test_line_search_solve_matches_oracle(lib):
+    """Neo-Hookean strip under a large tip shear in one increment: without a
+    line search Newton runs into inverted cells; with the backtracking line
+    search of Section 3.2 both sides converge to the same state."""
+    m = mg.box_mesh_2d(12, 3, 4.0, 1.0, jitter=0.1, seed=5)
+    mg.set_patch(m, "xmin", "displacement", (0.0, 0.0))
+    mg.set_patch(m, "xmax", "traction", (0.0, 2e5))
+    mat = mg.Material("neo_hookean", 1e6, 0.3)
+    pr = prepare(m, mat)
+    uo, so = o_newton(pr, rtol=1e-12, max_newton_it=60, eta=1e-10, precond="lu", restart=80,
+                      line_search=True)
+    assert so["status"] == "ok"
+    ug, st, stats = _solve_gpu(lib, m, mat, n_increments=1, max_newton_it=60, rtol=1e-11, eta=1e-8,
+                               restart=80, max_it=20000, precond="jacobi", line_search=1)
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print("line search NH strip rel L2", err, stats, so["newton_it"], so["steps"])
+    assert st == lib.OK
+    assert err <= 1e-8
+    ug2, st2, _ = _solve_gpu(lib, m, mat, n_increments=1, max_newton_it=60, rtol=1e-11, eta=1e-8,
+                             restart=80, max_it=20000, precond="jacobi", line_search=0)
+    assert st2 != lib.OK
