@@ -191,6 +191,24 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
                     const double* d_v, double eps, double* d_Jv, double* eps_used,
                     void* d_work, void* stream);
 
+/* J v exactly as jfnk_jv computes it (same kernels, same bits), for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  It takes no workspace
+ * and allocates nothing: its scratch (step-size partial sums, per-segment
+ * eps, arrival counters, and the per-cell gradient record when the mesh's
+ * cell passes are not the fused single pass; R(u) too when d_Ru is NULL)
+ * lives in a fixed 32 MiB device array of the library, one per GPU, held
+ * until the process ends.  Arguments as for jfnk_jv (no eps_used: the step
+ * stays on the device).  Errors: JFNK_E_ARG when the mesh needs more
+ * scratch than 32 MiB (the message gives the size; about 96 bytes per cell
+ * for a 3-D mesh on the two-pass kernels), when profiling is enabled on
+ * the mesh, or on the argument errors of jfnk_jv.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Asynchronous
+ * on `stream`. */
+jfnk_status jfnk_jv_noalloc(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
+                            const double* d_v, double eps, double* d_Jv, void* stream);
+
 typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_AMG64 = 3 } jfnk_precond;
 
 /* GMRES options (Section 3.2; restarted, right preconditioned, classical

@@ -118,6 +118,7 @@ def _load():
         "jfnk_profile_read": [vp, vp, vp, i32],
         "jfnk_autotune": [vp, C.POINTER(jfnk_gmres_opts), vp, d, vp, vp, vp],
         "jfnk_set_cell_passes": [vp, i32, i32],
+        "jfnk_jv_noalloc": [vp, d, vp, vp, vp, d, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -350,6 +351,16 @@ def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
     if not return_eps:
         return Jv
     return (Jv, e[0]) if mesh.n_segments == 1 else (Jv, list(e))
+
+
+def jv_noalloc(mesh, load, u, Ru, v, eps, Jv, stream=None):
+    """J v like jv(), with the library's fixed device scratch instead of a
+    workspace (no device allocation; calls overlapping on one GPU race)."""
+    _check(_lib.jfnk_jv_noalloc(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"),
+                                None if Ru is None else _dptr(Ru, mesh.n_dof, "Ru"),
+                                _dptr(v, mesh.n_dof, "v"), float(eps), _dptr(Jv, mesh.n_dof, "Jv"),
+                                _stream(stream)), "jfnk_jv_noalloc")
+    return Jv
 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
