@@ -365,7 +365,7 @@ def c2_jv(steps, log):
     return out
 
 
-def c3_solve(gm, m, mat, n_increments, restart, log, line_search=1):
+def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0):
     """The 1000x100x10 neo-Hookean cantilever solved to Newton rtol 1e-8 per
     increment (10 equal increments of the dead shear load), FGMRES(restart)
     with the FP32 AMG preconditioner.  Every increment is solved by its own
@@ -525,7 +525,7 @@ def main():
                     help="largest request of the serving leg (log-uniform from 5k cells)")
     ap.add_argument("--no-c3-solve", action="store_true",
                     help="skip the full cantilever solve (the J.v state is then the bending field)")
-    ap.add_argument("--c3-restart", type=int, default=200, help="FGMRES restart length of the cantilever solve")
+    ap.add_argument("--c3-restart", type=int, default=50, help="FGMRES restart length of the cantilever solve")
     ap.add_argument("--c3-increments", type=int, default=10)
     ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 jittered-block J.v leg")
     ap.add_argument("--c2-steps", type=int, default=300)

@@ -239,8 +239,10 @@ typedef struct {
 
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
  * k = 1..n_increments the loads are scaled by k/n_increments; iterate until
- * |R(u)| <= max(rtol |R(u_0)|, atol); each linear solve uses relative
- * tolerance eta.  A residual above dtol |R(u_0)| stops the increment with
+ * |R(u)| <= max(rtol |R(u_0)|, atol), or, with stol > 0, until a Newton
+ * correction satisfies |s du| <= stol |u| (the step test of Section 3.3;
+ * stol = 0 as in the paper switches it off); each linear solve uses
+ * relative tolerance eta.  A residual above dtol |R(u_0)| stops the increment with
  * JFNK_E_DIVERGED (dtol <= 0: 1e8).
  * line_search (the globalisation of Section 3.2, which asks only for a step
  * s > 0 that decreases |R|): 0 takes the full step s = 1; 1 tries
@@ -263,6 +265,7 @@ typedef struct {
   int32_t max_backtrack;
   int32_t inc_begin;
   int32_t inc_end;
+  double stol;
 } jfnk_newton_opts;
 
 typedef struct {

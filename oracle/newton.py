@@ -11,7 +11,9 @@ Paper passages:
   * Inexact Newton: the linear system is solved to a relative tolerance
     eta (three orders in the paper): Section 3.2, oversolving.
   * Convergence per load step: |R(u)| <= max(rtol |R(u_0)|, atol) with
-    the Euclidean norm and stol = 0: Section 3.3.
+    the Euclidean norm, or, when stol > 0, a correction |s du| <= stol |u|
+    (the third check of Section 3.3; the paper runs with stol = 0, the
+    default here).
   * Load increments: equal fractions k/N of the applied loads (the
     case descriptions apply loads in equal increments); the next
     increment starts from the previous converged displacement.
@@ -49,12 +51,30 @@ def make_preconditioner(pr, kind):
     if kind == "lu":
         lu = spla.splu(A)
         return lambda r: lu.solve(np.ascontiguousarray(r.reshape(nc, dim))).reshape(-1)
+    if kind == "cg":
+        # the same A^{-1}, applied by a library conjugate-gradient solve per
+        # component (diagonally scaled, to 1e-10 relative): for meshes whose
+        # sparse LU fill is too large; the application is then slightly
+        # inexact, which the flexible GMRES form allows
+        dinv = 1.0 / A.diagonal()
+        Md = spla.LinearOperator(A.shape, matvec=lambda x: dinv * x)
+        Acsr = A.tocsr()
+
+        def apply(r):
+            rr = r.reshape(nc, dim)
+            out = np.empty_like(rr)
+            for k in range(dim):
+                out[:, k], info = spla.cg(Acsr, rr[:, k], M=Md, rtol=1e-10, atol=0.0, maxiter=20000)
+                if info != 0:
+                    raise RuntimeError("cg preconditioner did not converge")
+            return out.reshape(-1)
+        return apply
     raise ValueError(kind)
 
 
 def newton_solve(pr, u0=None, n_increments=1, rtol=1e-6, atol=1e-50, max_newton_it=20,
                  eta=1e-3, restart=30, precond="lu", max_krylov_it=5000, line_search=False,
-                 max_backtrack=8, dtol=1e8, monitor=None, jv="fd"):
+                 max_backtrack=8, dtol=1e8, monitor=None, jv="fd", stol=0.0):
     """Solve R(u) = 0 under equal load increments; returns (u, stats).
 
     stats["status"] is "ok", "not_converged", "diverged" or "nan".
@@ -110,10 +130,13 @@ def newton_solve(pr, u0=None, n_increments=1, rtol=1e-6, atol=1e-50, max_newton_
                     u_new = u + s * du
                     R_new = residual(u_new, pr, load).reshape(-1)
             stats["steps"].append(s)
+            small_step = stol > 0 and s * np.linalg.norm(du) <= stol * np.linalg.norm(u_new)
             u, R = u_new, R_new
             it += 1
             if monitor is not None:
                 monitor(k, it, np.linalg.norm(R) / r0, info["iterations"])
+            if small_step:
+                break
         stats["newton_it"].append(it)
         stats["gmres_it"].append(gm)
         stats["res0"].append(r0)

@@ -768,7 +768,8 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     check_work(d_work);
     JFNK_REQUIRE(opts, JFNK_E_ARG, "newton: null options");
     JFNK_REQUIRE(opts->max_newton_it >= 1, JFNK_E_ARG, "newton: max_newton_it must be >= 1");
-    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0, JFNK_E_ARG, "newton: bad tolerance");
+    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->eta > 0 && opts->stol >= 0, JFNK_E_ARG,
+                 "newton: bad tolerance");
     JFNK_REQUIRE(opts->line_search == 0 || opts->line_search == 1, JFNK_E_ARG, "newton: line_search must be 0 or 1");
     JFNK_REQUIRE(opts->max_backtrack <= 60, JFNK_E_ARG, "newton: max_backtrack must be <= 60");
     check_opts(opts->gmres);

@@ -384,9 +384,20 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
   std::vector<GmresSeg> gres;
   double t_ms[8] = {0};
   const double dtol = o.dtol > 0 ? o.dtol : 1e8;
-  const int max_bt = o.max_backtrack > 0 ? o.max_backtrack : 8;
   std::vector<double> step(S, 1.0);
-  std::vector<char> trial(S, 0);
+  std::vector<char> trial(S, 0), small_step(S, 0);
+  std::vector<double> du2, u2;
+  // step test of Section 3.3: |s du| <= stol |u| after the update ends the
+  // increment (checked at the next residual evaluation)
+  auto check_step = [&](const std::vector<char>& took) {
+    if (o.stol <= 0) return;
+    upload_flags(m, took, kw.act, s);
+    seg_norms2(m, L, kw.du, fw, kw, kw.act, s, du2);
+    seg_norms2(m, L, u, fw, kw, kw.act, s, u2);
+    for (int g = 0; g < S; ++g)
+      if (took[g] && !done[g] && step[g] * std::sqrt(du2[g]) <= o.stol * std::sqrt(u2[g])) small_step[g] = 1;
+  };
+  const int max_bt = o.max_backtrack > 0 ? o.max_backtrack : 8;
   while (true) {
     upload_doubles(m, load, fw.load, s);
     std::vector<char> live(S);
@@ -413,7 +424,8 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
         done[g] = 1;
         continue;
       }
-      if (rn[g] <= std::max(o.rtol * r0[g], o.atol)) {
+      if (rn[g] <= std::max(o.rtol * r0[g], o.atol) || small_step[g]) {
+        small_step[g] = 0;
         if (inc[g] >= last[g]) {
           done[g] = 1;
         } else {
@@ -457,8 +469,10 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
         done[g] = 1;
       }
     }
+    for (int g = 0; g < S; ++g) step[g] = 1.0;
     if (!o.line_search) {
       blas_axpby(1.0, kw.du, 1.0, u, n, s);
+      check_step(part);
       continue;
     }
     // Line search: u = u_old + s du per segment, u_old kept in kw.b (the
@@ -495,6 +509,7 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
       if (!again) break;
     }
     t_ms[4] += now_ms() - tl;
+    check_step(part);
   }
   t_ms[0] = now_ms() - t0;
   for (int g = 0; g < S; ++g)

@@ -63,7 +63,7 @@ class jfnk_newton_opts(C.Structure):
     _fields_ = [("n_increments", C.c_int32), ("max_newton_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("eta", C.c_double), ("gmres", jfnk_gmres_opts),
                 ("dtol", C.c_double), ("line_search", C.c_int32), ("max_backtrack", C.c_int32),
-                ("inc_begin", C.c_int32), ("inc_end", C.c_int32)]
+                ("inc_begin", C.c_int32), ("inc_end", C.c_int32), ("stol", C.c_double)]
 
 
 class jfnk_stats(C.Structure):
@@ -371,9 +371,9 @@ def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI,
 
 
 def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, dtol=0.0,
-                line_search=0, max_backtrack=0, inc_begin=0, inc_end=0, **gm):
+                line_search=0, max_backtrack=0, inc_begin=0, inc_end=0, stol=0.0, **gm):
     return jfnk_newton_opts(n_increments, max_newton_it, rtol, atol, eta, gmres_opts(**gm), dtol,
-                            line_search, max_backtrack, inc_begin, inc_end)
+                            line_search, max_backtrack, inc_begin, inc_end, stol)
 
 
 def gmres(mesh, load, u, Ru, b, x, opts, work, stream=None, allow=(E_NOT_CONVERGED, E_BREAKDOWN)):

@@ -49,7 +49,7 @@ def test_cantilever_vs_oracle(lib, shape):
     work = lib.make_workspace(gm, 1, restart=restart, precond=lib.PC_AMG32)
     u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
     opts = lib.newton_opts(n_increments=10, max_newton_it=30, rtol=1e-10, eta=1e-3, restart=restart,
-                           max_it=200000, precond="amg32", cheb_degree=3)
+                           max_it=200000, precond="amg32", cheb_degree=3, stol=1e-12)
     st, stats = lib.newton_solve(gm, opts, u, work)
     ug = gm.to_external(u).cpu().numpy().reshape(-1, 3)
     uo = ref["u"]

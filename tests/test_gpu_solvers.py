@@ -108,9 +108,9 @@ def test_neo_hookean_cantilever_increments(lib):
 # iteration counts: they are checked through the converged FP64 solution and
 # through the iteration count against the Jacobi preconditioner.
 
-def _newton_both(lib, m, mat, n_inc, rtol, eta, restart=30, precond="amg32", max_it=20000):
-    ug, st, stats = _solve_gpu(lib, m, mat, n_increments=n_inc, max_newton_it=20, rtol=rtol, eta=eta,
-                               restart=restart, max_it=max_it, precond=precond, cheb_degree=3)
+def _newton_both(lib, m, mat, n_inc, rtol, eta, restart=30, precond="amg32", max_it=20000, stol=0.0):
+    ug, st, stats = _solve_gpu(lib, m, mat, n_increments=n_inc, max_newton_it=30, rtol=rtol, eta=eta,
+                               restart=restart, max_it=max_it, precond=precond, cheb_degree=3, stol=stol)
     return ug, st, stats
 
 
@@ -139,8 +139,9 @@ def test_amg32_fgmres_linear_elastic(lib, dim):
 @pytest.mark.parametrize("precond", ["amg32", "amg64"])
 def test_amg_neo_hookean_cantilever(lib, precond):
     """FP32- and FP64-stored AMG inside FGMRES on a neo-Hookean cantilever:
-    the GPU iterates past the usual tolerance (Newton rtol 1e-10, so that the
-    comparison measures the solver, not the stopping rule), the oracle is
+    the GPU iterates past the usual tolerance (Newton rtol 1e-10, or a
+    correction below 1e-12 |u|, so that the comparison measures the solver,
+    not the stopping rule), the oracle is
     solved with the exact (complex-step) Jacobian action down to the rounding
     floor of its residual, and the converged displacement meets the 1e-8 bar
     of the FP32-preconditioned path.  The preconditioner's precision changes
@@ -151,7 +152,7 @@ def test_amg_neo_hookean_cantilever(lib, precond):
     uo, so = o_newton(pr, n_increments=4, rtol=1e-9, max_newton_it=20, eta=1e-6, precond="lu",
                       restart=200, max_krylov_it=6000, jv="complex_step")
     assert so["status"] == "ok"
-    ug, st, stats = _newton_both(lib, m, mat, 4, 1e-10, 1e-6, restart=100, precond=precond)
+    ug, st, stats = _newton_both(lib, m, mat, 4, 1e-10, 1e-3, restart=100, precond=precond, stol=1e-12)
     err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
     print("NH", precond, "rel L2", err, stats, so["newton_it"], so["gmres_it"])
     assert st == lib.OK
