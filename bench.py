@@ -178,9 +178,10 @@ def jv_unique_bytes(info, dim, lds_kernels):
 
 
 def _plain_opts(jfnk, n_increments, rtol, eta, restart, max_it):
-    """One-solve-at-a-time FP64 path: FP64 diagonal (block-Jacobi) preconditioner."""
+    """The plain path: one solve at a time, FP64 AMG preconditioner (the same
+    hierarchy and cycle as the fast path, in FP64), no HIP-graph replay."""
     return jfnk.newton_opts(n_increments=n_increments, max_newton_it=20, rtol=rtol, eta=eta,
-                            restart=restart, max_it=max_it, precond="jacobi")
+                            restart=restart, max_it=max_it, precond="amg64", cheb_degree=3, graphs=0)
 
 
 def _fast_opts(jfnk, n_increments, rtol, eta, restart, max_it):
@@ -203,8 +204,9 @@ def _solve_plain(jfnk, torch, mesh, material, opts):
 
 
 def _one_at_a_time(jfnk, torch, problems, make_opts, log, label):
-    """Solve each problem alone, one after another; returns (seconds, solutions, ok flags, latencies_ms)."""
-    total, sols, ok, lat = 0.0, [], [], []
+    """Solve each problem alone, one after another; returns (seconds,
+    solutions, ok flags, latencies_ms, GMRES iterations)."""
+    total, sols, ok, lat, its = 0.0, [], [], [], []
     for i, p in enumerate(problems):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -215,9 +217,10 @@ def _one_at_a_time(jfnk, torch, problems, make_opts, log, label):
         lat.append(dt * 1e3)
         sols.append(u)
         ok.append(st == jfnk.OK)
-        if i % 8 == 7 or i + 1 == len(problems):
+        its.append(stats["gmres_it"])
+        if i % 32 == 31 or i + 1 == len(problems):
             log("%s: %d/%d solved alone, %.2fs so far" % (label, i + 1, len(problems), total))
-    return total, sols, ok, lat
+    return total, sols, ok, lat, its
 
 
 def _rel(a, b):
@@ -252,15 +255,34 @@ def _batched(jfnk, torch, problems, opts, restart):
             seg_ok[i] = int(seg[k] == jfnk.OK)
             its[i] = stats[k]["gmres_it"]
         gm.close()
+        del w, u
     return total, sols, seg_ok, its
 
 
-def batched_vs_plain(n_problems, n_plain, log):
+def _oracle_errors(problems, sols, n, log):
+    """Relative L2 error of the given GPU solutions against oracle solves of
+    the n smallest problems (sparse-LU-preconditioned GMRES far below the
+    GPU's tolerance)."""
+    from oracle.fv import prepare
+    from oracle.newton import newton_solve
+    order = sorted(range(len(problems)), key=lambda i: problems[i]["mesh"]["n_cells"])[:n]
+    errs = []
+    for i in order:
+        pr = prepare(problems[i]["mesh"], problems[i]["material"])
+        uo, _ = newton_solve(pr, rtol=1e-6, max_newton_it=2, eta=1e-13, precond="lu", restart=100,
+                             max_krylov_it=2000)
+        errs.append(_rel(sols[i], uo))
+    log("oracle errors on %d problems: %s" % (n, ", ".join("%.1e" % e for e in errs)))
+    return errs, [int(problems[i]["mesh"]["n_cells"]) for i in order]
+
+
+def batched_vs_plain(n_problems, n_alone, n_plain, n_oracle, log):
     """Linear-elastic block solves to a final relative residual of 1e-8:
     batched (one handle per dimension, FP32 AMG preconditioner) against the
     same problems solved one at a time with the same preconditioner, and
-    against the one-at-a-time FP64 path (FP64 diagonal preconditioner) on
-    the first n_plain problems (that path needs thousands of iterations)."""
+    against the plain path (one at a time, FP64 AMG, no graph replay) on the
+    first n_plain problems; solutions checked against the oracle on the
+    n_oracle smallest problems."""
     import numpy as np
     import torch
     import meshgen as mg
@@ -276,27 +298,33 @@ def batched_vs_plain(n_problems, n_plain, log):
     t_b, sol_b, ok_b, its = _batched(jfnk, torch, probs, fast, restart)
     log("batched leg: %d problems batched in %.2fs (%d converged; untimed first pass %.2fs)"
         % (len(probs), t_b, sum(ok_b), t_cold))
-    t_a, sol_a, ok_a, _ = _one_at_a_time(jfnk, torch, probs, lambda p: fast, log, "batched leg, FP32-AMG")
+    alone = probs[:n_alone]
+    t_a, sol_a, ok_a, _, its_a = _one_at_a_time(jfnk, torch, alone, lambda p: fast, log, "batched leg, FP32-AMG")
     sample = probs[:n_plain]
     t_bs, sol_bs, ok_bs, _ = _batched(jfnk, torch, sample, fast, restart)
-    t_p, sol_p, ok_p, _ = _one_at_a_time(jfnk, torch, sample,
-                                         lambda p: _plain_opts(jfnk, 1, rtol, rtol, restart, 20000),
-                                         log, "batched leg, FP64 plain")
+    t_p, sol_p, ok_p, _, its_p = _one_at_a_time(jfnk, torch, sample,
+                                                lambda p: _plain_opts(jfnk, 1, rtol, rtol, restart, 100000),
+                                                log, "batched leg, FP64-AMG plain")
+    oerr, ocells = _oracle_errors(probs, sol_b, n_oracle, log)
     cells = int(sum(p["mesh"]["n_cells"] for p in probs))
     return {"workload": "%d linear-elastic 2D/3D block solves (1k-100k cells, %d in total), "
                         "final relative residual 1e-8" % (len(probs), cells),
             "solves_per_s": len(probs) / t_b, "converged": int(sum(ok_b)),
-            "alone_fp32pc_solves_per_s": len(probs) / t_a, "alone_fp32pc_converged": sum(ok_a),
-            "speedup_vs_alone_fp32pc": t_a / t_b,
+            "alone_sample": len(alone),
+            "alone_fp32pc_solves_per_s": len(alone) / t_a, "alone_fp32pc_converged": int(sum(ok_a)),
+            "speedup_vs_alone_fp32pc": (len(probs) / t_b) / (len(alone) / t_a),
             "max_rel_l2_batched_vs_alone": _max_rel(
                 (a, b, x and y) for a, b, x, y in zip(sol_b, sol_a, ok_b, ok_a)),
             "plain_fp64_sample": len(sample),
-            "plain_fp64_solves_per_s": len(sample) / t_p, "plain_fp64_converged": sum(ok_p),
+            "plain_fp64_solves_per_s": len(sample) / t_p, "plain_fp64_converged": int(sum(ok_p)),
             "batched_sample_solves_per_s": len(sample) / t_bs,
             "speedup_vs_plain_fp64": t_p / t_bs,
             "max_rel_l2_batched_vs_plain_fp64": _max_rel(
                 (a, b, x and y) for a, b, x, y in zip(sol_bs, sol_p, ok_bs, ok_p)),
-            "median_gmres_it": float(np.median(its)),
+            "gmres_it_fp32_amg_median": float(np.median(its_a[:len(sample)])),
+            "gmres_it_fp64_amg_median": float(np.median(its_p)),
+            "gmres_it_batched_median": float(np.median(its)),
+            "oracle_rel_l2": oerr, "oracle_cells": ocells,
             "first_pass_solves_per_s": len(probs) / t_cold,
             "timing": "host wall clock incl. device mesh setup, preconditioner setup, solve and copy-out; "
                       "batched: second pass (the first pass is reported as first_pass_solves_per_s)"}
@@ -436,65 +464,106 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0):
     return report, (u_final if status == jfnk.OK else None)
 
 
-def serving(rate, seconds, max_cells, n_plain, log):
-    """Request server (FP32-AMG flexible GMRES, continuous admission onto 4
-    streams) on a Poisson stream: latency percentiles at the offered rate,
-    then the same requests all submitted at once (capacity in solves/s),
-    against the same requests solved one after another alone (same
-    preconditioner) and the one-at-a-time FP64 path on the first n_plain."""
+def _stream_window(jfnk, pool, mk, rate, seconds, max_slots, max_queue, budget, seed, keep=0):
+    """Poisson arrivals at `rate` for `seconds`, request k being pool[k % len];
+    submissions to a full queue are shed.  At the end of the window the
+    backlog is measured and cancelled, running requests finish.  Returns a
+    dict of counts and latencies, and the solutions of the first `keep`
+    requests."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    srv = jfnk.Server(hbm_budget=budget, max_slots=max_slots, max_queue=max_queue)
+    t0 = time.perf_counter()
+    t_next = float(rng.exponential(1.0 / rate))
+    tickets, shed, k = [], 0, 0
+    while t_next <= seconds:
+        now = time.perf_counter() - t0
+        if t_next > now:
+            time.sleep(t_next - now)
+        r = pool[k % len(pool)]
+        t = srv.submit_nowait(r["mesh"], r["material"], mk(r), keep_solution=k < keep)
+        if t is None:
+            shed += 1
+        else:
+            tickets.append((k, t))
+        k += 1
+        t_next += float(rng.exponential(1.0 / rate))
+    now = time.perf_counter() - t0
+    if seconds > now:
+        time.sleep(seconds - now)
+    at_end = srv.metrics()
+    cancelled = srv.cancel_queued()
+    res = [(kk, srv.wait(t)) for kk, t in tickets]
+    final = srv.metrics()
+    srv.close()
+    lat = [info["latency_ms"] for _, (info, _) in res if info["status"] in (jfnk.OK, jfnk.E_NOT_CONVERGED)]
+    done_in_window = at_end["completed"]
+    out = {"offered_req_per_s": rate, "seconds": seconds, "arrived": k, "shed_queue_full": shed,
+           "completed_in_window": done_in_window, "solves_per_s_in_window": done_in_window / seconds,
+           "backlog_at_end": at_end["queued"] + at_end["running"], "cancelled_at_end": cancelled,
+           "completed_total": final["completed"], "failed": final["rejected"],
+           "converged": sum(1 for _, (i, _) in res if i["status"] == jfnk.OK),
+           "p50_ms": float(np.percentile(lat, 50)) if lat else None,
+           "p99_ms": float(np.percentile(lat, 99)) if lat else None,
+           "hbm_peak_bytes": final["hbm_peak"]}
+    sols = {kk: u for kk, (info, u) in res if kk < keep and info["status"] == jfnk.OK}
+    return out, sols
+
+
+def serving(rate, seconds, max_cells, n_pool, sweep, sweep_seconds, n_plain, log):
+    """The request server (FP32-AMG flexible GMRES, continuous admission onto
+    4 streams under an HBM budget) on a Poisson stream of the serving
+    workload: 3-D blocks of 5k-max_cells cells (log-uniform), 70% linear
+    elastic / 30% neo-Hookean with 1-5 increments, Newton rtol 1e-8.  A pool
+    of n_pool requests is generated once and request k of the stream is pool
+    entry k mod n_pool (generating a mesh of up to 2M cells per arrival
+    would take longer than the arrival gap).  The stream runs at the offered
+    rate for `seconds`; what is still queued at the end is the backlog.  A
+    sweep of lower rates finds the highest rate the GPU sustains (nothing
+    shed, backlog no larger than the worker count).  Results are checked:
+    the same request gives bitwise the same solution wherever it falls in
+    the mix, and matches the plain path (one at a time, FP64 AMG, no graph
+    replay) on the n_plain smallest pool entries."""
     import numpy as np
     import torch
     import meshgen as mg
     from paper_2502_17217_amd import jfnk
-    reqs = mg.config_c5_stream(rate=rate, duration=seconds, hi=max_cells)
-    rtol, eta, restart = 1e-8, 1e-4, 30
+    t = time.time()
+    pool = mg.config_c5_stream(rate=rate, duration=1e9, hi=max_cells, max_requests=n_pool)
+    cells = [int(r["mesh"]["n_cells"]) for r in pool]
+    log("serving leg: pool of %d requests generated in %.1fs (%d-%d cells, mean %.0f)"
+        % (len(pool), time.time() - t, min(cells), max(cells), float(np.mean(cells))))
+    rtol, eta, restart = 1e-8, 1e-3, 30
     mk = lambda r: _fast_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000)
-
-    def run(paced):
-        srv = jfnk.Server(hbm_budget=64 << 30, max_slots=4)
-        t0 = time.perf_counter()
-        tickets = []
-        for r in reqs:
-            now = time.perf_counter() - t0
-            if paced and r["t_arrival"] > now:
-                time.sleep(r["t_arrival"] - now)
-            tickets.append(srv.submit(r["mesh"], r["material"], mk(r)))
-        res = [srv.wait(t) for t in tickets]
-        wall = time.perf_counter() - t0
-        mt = srv.metrics()
-        srv.close()
-        return res, wall, mt
-
-    res, t_all, mt = run(True)
-    ok = [i["status"] == jfnk.OK for i, _ in res]
-    log("serving leg: %d requests at %.0f req/s in %.2fs, p50 %.1f ms, p99 %.1f ms, %d converged"
-        % (len(reqs), rate, t_all, mt["p50_ms"], mt["p99_ms"], sum(ok)))
-    res_sat, t_sat, mt_sat = run(False)
-    log("serving leg: the same requests submitted at once: %.2fs" % t_sat)
-    t_a, sol_a, ok_a, lat_a = _one_at_a_time(jfnk, torch, reqs, mk, log, "serving leg, alone")
-    sample = reqs[:n_plain]
-    t_p, sol_p, ok_p, _ = _one_at_a_time(
-        jfnk, torch, sample, lambda r: _plain_opts(jfnk, r["n_increments"], rtol, eta, restart, 20000),
-        log, "serving leg, FP64 plain")
-    return {"workload": "Poisson stream %.0f req/s for %.0f s (%d requests), 3D blocks of 5k-%.0fk cells, "
-                        "70%% linear elastic / 30%% neo-Hookean with 1-5 increments, Newton rtol 1e-8"
-                        % (rate, seconds, len(reqs), max_cells / 1e3),
-            "p50_ms": mt["p50_ms"], "p99_ms": mt["p99_ms"], "solves_per_s_at_rate": mt["solves_per_s"],
-            "converged": sum(ok), "hbm_peak_bytes": mt["hbm_peak"],
-            "saturated_solves_per_s": len(reqs) / t_sat, "saturated_p99_ms": mt_sat["p99_ms"],
-            "alone_fp32pc_solves_per_s": len(reqs) / t_a, "alone_fp32pc_converged": sum(ok_a),
-            "alone_p50_ms_service": float(np.percentile(lat_a, 50)),
-            "alone_p99_ms_service": float(np.percentile(lat_a, 99)),
-            "speedup_saturated_vs_alone": t_a / t_sat,
-            "max_rel_l2_served_vs_alone": _max_rel(
-                (u, a, x and y) for (_, u), a, x, y in zip(res, sol_a, ok, ok_a)),
-            "bitwise_served_equals_saturated": all(
-                np.array_equal(u, v) for (_, u), (_, v) in zip(res, res_sat)),
+    budget, slots, qmax = 64 << 30, 4, 64
+    main, sols = _stream_window(jfnk, pool, mk, rate, seconds, slots, qmax, budget, 5, keep=2 * len(pool))
+    log("serving leg: %s" % json.dumps(main))
+    same = [np.array_equal(sols[k], sols[k + len(pool)]) for k in range(len(pool))
+            if k in sols and k + len(pool) in sols]
+    rates = []
+    for r_ in sweep:
+        o, _ = _stream_window(jfnk, pool, mk, r_, sweep_seconds, slots, qmax, budget, 50 + int(r_ * 10))
+        log("serving sweep: %s" % json.dumps(o))
+        rates.append(o)
+    ok = [o["offered_req_per_s"] for o in rates if o["shed_queue_full"] == 0 and o["backlog_at_end"] <= slots]
+    small = sorted(range(len(pool)), key=lambda k: cells[k])[:n_plain]
+    sample = [pool[k] for k in small]
+    t_p, sol_p, ok_p, lat_p, its_p = _one_at_a_time(
+        jfnk, torch, sample, lambda r: _plain_opts(jfnk, r["n_increments"], rtol, eta, restart, 100000),
+        log, "serving leg, FP64-AMG plain")
+    t_a, sol_a, ok_a, lat_a, its_a = _one_at_a_time(jfnk, torch, sample, mk, log, "serving leg, FP32-AMG alone")
+    served = [(sols[k], sol_p[i], ok_p[i]) for i, k in enumerate(small) if k in sols]
+    return {"workload": "Poisson stream at %.0f req/s for %.0f s, request pool of %d 3-D blocks of 5k-%.0fk "
+                        "cells (mean %.0f), 70%% linear elastic / 30%% neo-Hookean with 1-5 increments, "
+                        "Newton rtol 1e-8, 4 streams, queue limit %d, HBM budget %d GiB"
+                        % (rate, seconds, len(pool), max_cells / 1e3, float(np.mean(cells)), qmax, budget >> 30),
+            "at_offered_rate": main, "sweep": rates,
+            "sustainable_req_per_s": max(ok) if ok else None,
+            "bitwise_same_request_same_result": (all(same) if same else None), "repeat_pairs": len(same),
             "plain_fp64_sample": len(sample), "plain_fp64_solves_per_s": len(sample) / t_p,
-            "plain_fp64_converged": sum(ok_p),
-            "alone_fp32pc_sample_solves_per_s": len(sample) / (sum(lat_a[:len(sample)]) * 1e-3),
-            "max_rel_l2_served_vs_plain_fp64": _max_rel(
-                (u, a, x and y) for (_, u), a, x, y in zip(res, sol_p, ok, ok_p))}
+            "plain_fp64_p50_ms_service": float(np.percentile(lat_p, 50)),
+            "alone_fp32pc_solves_per_s": len(sample) / t_a,
+            "max_rel_l2_served_vs_plain_fp64": _max_rel(served)}
 
 
 def main():
@@ -514,18 +583,26 @@ def main():
                          "2 fused pass and G = persistent workgroups (0: one per tile), e.g. 1/1024")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-solve and serving measurements")
-    ap.add_argument("--batch-problems", type=int, default=48,
+    ap.add_argument("--batch-problems", type=int, default=512,
                     help="problems of the batched workload (log-uniform 1k-100k cells)")
-    ap.add_argument("--plain-sample", type=int, default=4,
-                    help="problems solved on the FP64 diagonal-preconditioned path in each leg")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="length of the Poisson request stream of the serving leg")
-    ap.add_argument("--serve-rate", type=float, default=8.0, help="requests per second")
-    ap.add_argument("--serve-max-cells", type=float, default=1e5,
+    ap.add_argument("--alone-sample", type=int, default=512,
+                    help="batched-workload problems also solved one at a time (FP32 AMG)")
+    ap.add_argument("--plain-sample", type=int, default=32,
+                    help="problems solved on the plain FP64-AMG path in each leg")
+    ap.add_argument("--oracle-sample", type=int, default=4,
+                    help="smallest batched problems checked against the oracle")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the Poisson request stream at the offered rate")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="offered requests per second")
+    ap.add_argument("--serve-max-cells", type=float, default=2e6,
                     help="largest request of the serving leg (log-uniform from 5k cells)")
+    ap.add_argument("--serve-pool", type=int, default=24, help="distinct requests the stream cycles over")
+    ap.add_argument("--serve-sweep", type=str, default="2,4,8", help="lower offered rates for the sweep")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-plain", type=int, default=4, help="pool entries solved on the plain path")
     ap.add_argument("--no-c3-solve", action="store_true",
                     help="skip the full cantilever solve (the J.v state is then the bending field)")
-    ap.add_argument("--c3-restart", type=int, default=50, help="FGMRES restart length of the cantilever solve")
+    ap.add_argument("--c3-restart", type=int, default=200, help="FGMRES restart length of the cantilever solve")
     ap.add_argument("--c3-increments", type=int, default=10)
     ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 jittered-block J.v leg")
     ap.add_argument("--c2-steps", type=int, default=300)
@@ -681,9 +758,11 @@ def main():
     if not args.no_c2:
         extras["c2_jv"] = c2_jv(args.c2_steps, log)
     if not args.no_extras:
-        extras["batched"] = batched_vs_plain(args.batch_problems, args.plain_sample, log)
-        extras["serving"] = serving(args.serve_rate, args.serve_seconds, args.serve_max_cells,
-                                    args.plain_sample, log)
+        extras["batched"] = batched_vs_plain(args.batch_problems, min(args.alone_sample, args.batch_problems),
+                                             args.plain_sample, args.oracle_sample, log)
+        extras["serving"] = serving(args.serve_rate, args.serve_seconds, args.serve_max_cells, args.serve_pool,
+                                    [float(x) for x in args.serve_sweep.split(",") if x],
+                                    args.serve_sweep_seconds, args.serve_plain, log)
 
     out = {
         "metric": METRIC,

@@ -104,17 +104,21 @@ typedef struct {
   const jfnk_patch* patches;   /* must cover faces [n_internal, n_faces) exactly */
 } jfnk_mesh_desc;
 
-typedef enum { JFNK_LINEAR_ELASTIC = 0, JFNK_NEO_HOOKEAN = 1 } jfnk_law;
+/* Appendix B: Hooke's law (linear geometry), and the total Lagrangian
+ * hyperelastic laws neo-Hookean and St. Venant-Kirchhoff. */
+typedef enum { JFNK_LINEAR_ELASTIC = 0, JFNK_NEO_HOOKEAN = 1, JFNK_ST_VENANT_KIRCHHOFF = 2 } jfnk_law;
 
 /* Appendix B laws.  alpha_rc scales the Rhie-Chow term of the residual
  * (Eq. RhieChow); alpha_pc scales the approximate Jacobian used for
- * preconditioning (unity in the paper, Section 3.1). */
+ * preconditioning (unity in the paper, Section 3.1); rho is the density,
+ * used only by the inertia term of transient solves (jfnk_dynamic_step). */
 typedef struct {
   int32_t law;
   double E;
   double nu;
   double alpha_rc;
   double alpha_pc;
+  double rho;
 } jfnk_material;
 
 typedef struct jfnk_mesh jfnk_mesh;
@@ -168,9 +172,9 @@ jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new);
 jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 
-/* Workspace bytes for jfnk_residual / jfnk_jv (op = 0) or for jfnk_gmres and
+/* Workspace bytes for jfnk_residual / jfnk_jv (op = 0), for jfnk_gmres and
  * jfnk_newton_solve with the given restart length and preconditioner
- * (op = 1).  The caller allocates at least that many bytes of device memory,
+ * (op = 1), or for jfnk_dynamic_step (op = 2).  The caller allocates at least that many bytes of device memory,
  * 256-byte aligned, and passes it as d_work. */
 jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t restart,
                                 int32_t precond, size_t* bytes);
@@ -224,7 +228,15 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_
  * between host checks of the convergence flags (0: the handle's value,
  * chosen by jfnk_autotune, default 1); graphs = 1 replays each run from a
  * HIP graph captured on first use, 0 launches directly, 2 takes the
- * handle's choice (default: graphs); results are identical either way. */
+ * handle's choice (default: graphs); results are identical either way.
+ * left = 1: left preconditioning (the paper's choice in Section 3.2): the
+ * Arnoldi vectors are P^{-1} J v, the solution update uses the basis V, and
+ * convergence is judged on the preconditioned residual |P^{-1}(b - J x)|
+ * against rtol |P^{-1} b|.  augment = k > 0 (right preconditioning only):
+ * LGMRES, the augmented restarted GMRES the paper runs (LGMRES(30)+2): the
+ * last k of the restart directions of a cycle are the normalised
+ * corrections x_c - x_{c-1} of the previous k cycles instead of
+ * preconditioned basis vectors (graph replay is not used then). */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -235,6 +247,8 @@ typedef struct {
   double eps;
   int32_t step_chunk;
   int32_t graphs;
+  int32_t left;
+  int32_t augment;
 } jfnk_gmres_opts;
 
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
@@ -293,6 +307,43 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
 /* Newton-Raphson with load increments; d_u holds the initial guess on entry
  * and the final iterate on return. */
 jfnk_status jfnk_newton_solve(jfnk_mesh* mesh, const jfnk_newton_opts* opts, double* d_u,
+                              jfnk_stats* stats, void* d_work, void* stream);
+
+/* ---- Volume terms and transient solves (Section 2.3.1) ----
+ * Body force: h_body is a host array [n_cells][dim] in input cell order
+ * (for a batch, the meshes' arrays concatenated), a force per unit volume,
+ * integrated over each cell by the midpoint rule and scaled by the load
+ * factor like every other load: R_P += load f_b,P Omega_P.  NULL removes
+ * it.  Copied to the device; jfnk_residual, jfnk_jv, jfnk_gmres and the
+ * solvers include it from then on.  Errors: JFNK_E_ARG (non-finite value),
+ * JFNK_E_OOM. */
+jfnk_status jfnk_set_body_force(jfnk_mesh* mesh, const double* h_body, void* stream);
+
+/* Inertia: with dt > 0 the residual gets -rho Omega_P a_P, a_P the BDF2
+ * acceleration of Eq. (inertia2) of the unknown u from the previous
+ * displacements u^t = d_u_n, u^{t-1} = d_u_nm1 and velocities v^t = d_v_n,
+ * v^{t-1} = d_v_nm1 (device, internal layout, caller-owned, read while the
+ * setting is in force); the approximate Jacobian used for preconditioning
+ * gets -9/4 rho Omega_P / dt^2 on its diagonal (Section 3.1).  rho comes from
+ * each mesh's material.  dt <= 0 removes the term.  J v differences only the
+ * surface terms and adds the inertia's exact derivative.  Errors:
+ * JFNK_E_ARG (null pointers, no mesh with rho > 0). */
+jfnk_status jfnk_set_inertia(jfnk_mesh* mesh, double dt, const double* d_u_n, const double* d_u_nm1,
+                             const double* d_v_n, const double* d_v_nm1, void* stream);
+
+/* One BDF2 time step (Section 2.3.1, Eq. inertia2) with the loads at their
+ * full value: on entry d_u, d_u_prev, d_v, d_v_prev, d_a hold u^t, u^{t-1},
+ * v^t, v^{t-1} and a^t (device, internal layout; from rest all zero); the
+ * step starts Newton from the truncated Taylor predictor of Section 3.2,
+ * Eq. (predictor), u^t + dt v^t + dt^2/2 a^t (predictor != 0) or from u^t,
+ * solves R(u^{t+1}) = 0 with the options' Newton and GMRES settings
+ * (n_increments and the increment range are ignored), and on return holds
+ * u^{t+1}, u^t, v^{t+1}, v^t, a^{t+1} with v^{t+1} = (3u^{t+1} - 4u^t +
+ * u^{t-1})/(2 dt) and a^{t+1} = (3v^{t+1} - 4v^t + v^{t-1})/(2 dt).  A body
+ * force set on the mesh applies.  d_work: jfnk_workspace_size op 2.
+ * Returns the Newton status (the histories are updated either way). */
+jfnk_status jfnk_dynamic_step(jfnk_mesh* mesh, double dt, int32_t predictor, const jfnk_newton_opts* opts,
+                              double* d_u, double* d_u_prev, double* d_v, double* d_v_prev, double* d_a,
                               jfnk_stats* stats, void* d_work, void* stream);
 
 /* Kernel timing for measurement tools.  While enabled, every residual / J v
@@ -374,6 +425,7 @@ typedef struct {
   int64_t hbm_in_use, hbm_peak;
   double p50_ms, p99_ms, mean_ms, max_ms;      /* latency of completed requests */
   double solves_per_s;           /* completed / (last completion - first submission) */
+  int64_t cancelled;             /* requests removed by jfnk_server_cancel_queued */
 } jfnk_server_metrics;
 
 jfnk_status jfnk_server_create(const jfnk_server_opts* opts, jfnk_server** out);
@@ -386,6 +438,11 @@ jfnk_status jfnk_server_poll(jfnk_server* srv, uint64_t ticket, jfnk_request_inf
 /* Blocks until the request is done. */
 jfnk_status jfnk_server_wait(jfnk_server* srv, uint64_t ticket, jfnk_request_info* info);
 jfnk_status jfnk_server_metrics_get(jfnk_server* srv, jfnk_server_metrics* m);
+/* Removes every request that no worker has taken yet (their state becomes
+ * done with status JFNK_E_BUSY and the message "cancelled before it
+ * started"); running requests continue.  *n_cancelled (may be NULL) gets the
+ * count.  For ending a measurement window or shedding a backlog. */
+jfnk_status jfnk_server_cancel_queued(jfnk_server* srv, int64_t* n_cancelled);
 /* Finishes running and queued requests, then stops the workers. */
 jfnk_status jfnk_server_destroy(jfnk_server* srv);
 

@@ -29,6 +29,7 @@ class Material:
     nu: float = 0.3
     alpha_rc: float = 1.0              # Rhie-Chow scaling in the residual
     alpha_pc: float = 1.0              # Rhie-Chow scaling in the approximate Jacobian
+    rho: float = 0.0                   # density (transient problems only)
 
     def as_dict(self):
         return asdict(self)

@@ -13,7 +13,12 @@ Paper passages followed (Cardiff et al., arXiv 2502.17217):
     tensor that follows it; boundary faces are excluded.
   * Rhie-Chow stabilisation: Section 2.3.3, Eq. (RhieChow), with
     K_bar = 2 mu + lambda and Delta = d/(d.n).
-  * Laws: Appendix B, Eq. (linearElastic) and Eq. (neoHook).
+  * Laws: Appendix B, Eq. (linearElastic), Eq. (neoHook) and the
+    St. Venant-Kirchhoff law with Eq. (S2sigma).
+  * Volume terms (Section 2.3.1, Eq. volume_integral, midpoint rule): the
+    body force f_b Omega_P and the inertia -rho Omega_P a_P with the BDF2
+    acceleration of Eq. (inertia2); both enter the residual of Section 2.2
+    as R = surface terms + int f_b - int rho d2u/dt2.
 
 Readings where the paper is silent or inconsistent (all listed in the
 design notes of the repository):
@@ -188,6 +193,21 @@ def neo_hookean(g, c):
     return sigma, cof
 
 
+def st_venant_kirchhoff(g, c):
+    """Appendix B: S = 2 mu E + lambda tr(E) I with the Green strain
+    E = (grad u + grad u^T + grad u . grad u^T)/2, and Eq. (S2sigma)
+    sigma = F S F^T / J.  Returns (sigma, cof F), both 3x3."""
+    g3 = _embed3(g)
+    F = np.eye(3) + np.swapaxes(g3, -1, -2)
+    E = 0.5 * (g3 + np.swapaxes(g3, -1, -2) + g3 @ np.swapaxes(g3, -1, -2))
+    trE = np.trace(E, axis1=-2, axis2=-1)
+    S = 2.0 * c["mu"] * E + (c["lam"] * trE)[..., None, None] * np.eye(3)
+    cof = cofactor(F)
+    J = np.einsum("...j,...j->...", F[..., 0, :], cof[..., 0, :])
+    sigma = F @ S @ np.swapaxes(F, -1, -2) / J[..., None, None]
+    return sigma, cof
+
+
 def traction(g, Gam, c):
     """Force on an area vector Gamma from the stress at displacement gradient g.
 
@@ -199,8 +219,8 @@ def traction(g, Gam, c):
     if c["law"] == "linear_elastic":
         s = stress_linear_elastic(g, c)
         return np.einsum("fi,fij->fj", Gam, s)
-    if c["law"] == "neo_hookean":
-        s, cof = neo_hookean(g, c)
+    if c["law"] in ("neo_hookean", "st_venant_kirchhoff"):
+        s, cof = neo_hookean(g, c) if c["law"] == "neo_hookean" else st_venant_kirchhoff(g, c)
         G3 = np.zeros((Gam.shape[0], 3))
         G3[:, :dim] = Gam
         a = np.einsum("fik,fk->fi", cof, G3)
@@ -249,12 +269,61 @@ def face_forces(u, pr, load=1.0):
     return dict(T_int=T_int, RC_int=RC_int, T_b=T_b, RC_b=RC_b, grad=g)
 
 
+def with_source(pr, body=None, rho=0.0, dt=0.0, u_n=None, u_nm1=None, v_n=None, v_nm1=None):
+    """A copy of the prepared problem whose residual includes volume terms:
+    a body force density `body` [n_cells, dim] (force per unit volume,
+    scaled by the load factor like every other load) and, with rho > 0 and
+    dt > 0, the inertia of Eq. (inertia2) from the previous displacements
+    u_n, u_nm1 and velocities v_n, v_nm1 ([n_cells, dim] each)."""
+    q = dict(pr)
+    nc, dim = pr["nc"], pr["dim"]
+    src = {}
+    if body is not None:
+        src["body"] = np.asarray(body, dtype=np.float64).reshape(nc, dim)
+    if rho > 0 and dt > 0:
+        src.update(rho=float(rho), dt=float(dt),
+                   u_n=np.asarray(u_n, dtype=np.float64).reshape(nc, dim),
+                   u_nm1=np.asarray(u_nm1, dtype=np.float64).reshape(nc, dim),
+                   v_n=np.asarray(v_n, dtype=np.float64).reshape(nc, dim),
+                   v_nm1=np.asarray(v_nm1, dtype=np.float64).reshape(nc, dim))
+    q["source"] = src
+    return q
+
+
+def bdf2_velocity(u, u_n, u_nm1, dt):
+    """v^{t+1} = (3 u^{t+1} - 4 u^t + u^{t-1}) / (2 dt) (BDF2, Section 2.3.1)."""
+    return (3.0 * u - 4.0 * u_n + u_nm1) / (2.0 * dt)
+
+
+def bdf2_acceleration(u, src):
+    """Eq. (inertia2): (3 v^{t+1} - 4 v^t + v^{t-1}) / (2 dt) with v^{t+1}
+    the BDF2 velocity of u."""
+    v = bdf2_velocity(u, src["u_n"], src["u_nm1"], src["dt"])
+    return (3.0 * v - 4.0 * src["v_n"] + src["v_nm1"]) / (2.0 * src["dt"])
+
+
+def volume_terms(u, pr, load=1.0):
+    """Body force and inertia of cell P integrated by the midpoint rule:
+    load f_b,P Omega_P - rho a_P Omega_P (zero when no source is set)."""
+    src = pr.get("source") or {}
+    nc, dim = pr["nc"], pr["dim"]
+    u = np.asarray(u).reshape(nc, dim)
+    V = pr["geo"]["V"][:, None]
+    out = np.zeros((nc, dim), dtype=np.result_type(u, float))
+    if "body" in src:
+        out = out + load * src["body"] * V
+    if "rho" in src:
+        out = out - src["rho"] * V * bdf2_acceleration(u, src)
+    return out
+
+
 def residual(u, pr, load=1.0, parts=False):
-    """R(u) per cell, shape [n_cells, dim] (Eq. residual, static, no body force).
+    """R(u) per cell, shape [n_cells, dim] (Eq. residual).
 
     R_P = sum_f [traction_f + Rhie-Chow_f] with outward orientation: each
     internal face is evaluated once from its owner's side and added to the
-    owner and subtracted from the neighbour.
+    owner and subtracted from the neighbour; plus the volume terms (body
+    force, inertia) when the problem carries them (with_source).
     """
     nc = pr["nc"]
     P, N, Pb = pr["P"], pr["N"], pr["Pb"]
@@ -265,5 +334,8 @@ def residual(u, pr, load=1.0, parts=False):
 
     if parts:
         return dict(traction=assemble(ff["T_int"], ff["T_b"]), rc=assemble(ff["RC_int"], ff["RC_b"]),
-                    grad=ff["grad"])
-    return assemble(ff["T_int"] + ff["RC_int"], ff["T_b"] + ff["RC_b"])
+                    grad=ff["grad"], volume=volume_terms(u, pr, load))
+    R = assemble(ff["T_int"] + ff["RC_int"], ff["T_b"] + ff["RC_b"])
+    if pr.get("source"):
+        R = R + volume_terms(u, pr, load)
+    return R

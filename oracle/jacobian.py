@@ -11,7 +11,9 @@ Paper passages:
     off-diagonal coefficients after Eq. (SegSys): off-diagonal
     alpha K_bar |Delta||Gamma|/|d| I, diagonal minus the sum over
     internal and displacement faces; no inertia term (static problems),
-    alpha = alpha_pc.  Blocks are scalar times identity, so the scalar
+    alpha = alpha_pc; with inertia (a problem carrying rho and dt) the
+    diagonal also gets -9/4 rho Omega_P / dt^2 (the BDF2 term of the block
+    diagonal coefficient).  Blocks are scalar times identity, so the scalar
     matrix is returned (component decoupling, Eq. SegSysX-Z).
 """
 
@@ -74,6 +76,9 @@ def approximate_jacobian_scalar(pr):
     coef_b = aK * pr["magDeltab"][m] / pr["magdb"][m] * pr["magGb"][m]
     diag = -(np.bincount(P, weights=coef, minlength=nc) + np.bincount(N, weights=coef, minlength=nc)
              + np.bincount(pr["Pb"][m], weights=coef_b, minlength=nc))
+    src = pr.get("source") or {}
+    if "rho" in src:
+        diag = diag - 2.25 * src["rho"] * pr["geo"]["V"] / src["dt"] ** 2
     rows = np.concatenate([P, N, np.arange(nc)])
     cols = np.concatenate([N, P, np.arange(nc)])
     vals = np.concatenate([coef, coef, diag])

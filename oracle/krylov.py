@@ -19,13 +19,22 @@ Algorithm per restart cycle (Saad's GMRES / FGMRES):
      is the residual norm of the least-squares problem
   y = H^{-1} g, x += Z y, then the true residual b - A x decides
   whether to restart.
+
+Variants the paper's solver used (Section 3.2 and the solver settings of
+Section 4): left preconditioning (left=True: the Arnoldi process runs on
+M A with w = M A v_j, x += V y, and the residual that decides convergence is
+M (b - A x) against rtol |M b|), and LGMRES augmentation (augment = k: in
+every cycle after the first, the last k directions z_j are the normalised
+corrections x_c - x_{c-1} of the most recent cycles, newest first, instead
+of M v_j; Baker, Jessup & Manteuffel's augmented restarted GMRES written in
+the flexible form).
 """
 
 import numpy as np
 
 
 def gmres(apply_A, b, x0=None, M=None, restart=30, rtol=1e-10, atol=0.0, max_it=10000,
-          breakdown_rtol=1e-14, keep_basis=False):
+          breakdown_rtol=1e-14, keep_basis=False, left=False, augment=0):
     """Return (x, info) with info = dict(converged, iterations, res_true, history).
 
     keep_basis=True also returns the last cycle's orthonormal basis in
@@ -35,10 +44,12 @@ def gmres(apply_A, b, x0=None, M=None, restart=30, rtol=1e-10, atol=0.0, max_it=
     n = b.size
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     Mf = (lambda v: v) if M is None else M
-    bnorm = np.linalg.norm(b)
+    resid = (lambda v: Mf(v)) if left else (lambda v: v)
+    bnorm = np.linalg.norm(resid(b))
     target = max(rtol * bnorm, atol)
-    r = b - apply_A(x) if np.any(x) else b.copy()
+    r = resid(b - apply_A(x)) if np.any(x) else resid(b)
     beta = np.linalg.norm(r)
+    aug = []
     history = [beta]
     total = 0
     m = restart
@@ -58,8 +69,12 @@ def gmres(apply_A, b, x0=None, M=None, restart=30, rtol=1e-10, atol=0.0, max_it=
         g[0] = beta
         k = 0
         for j in range(m):
-            Z[j] = Mf(V[j])
-            w = apply_A(Z[j])
+            a = j - (m - augment)
+            if left:
+                w = Mf(apply_A(V[j]))
+            else:
+                Z[j] = aug[a] if 0 <= a < len(aug) else Mf(V[j])
+                w = apply_A(Z[j])
             w0 = np.linalg.norm(w)
             h = V[:j + 1] @ w
             w = w - V[:j + 1].T @ h
@@ -91,8 +106,11 @@ def gmres(apply_A, b, x0=None, M=None, restart=30, rtol=1e-10, atol=0.0, max_it=
         if keep_basis:
             last_basis = V[:k + 1].copy() if hn > breakdown_rtol * max(w0, 1e-300) else V[:k].copy()
         y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
-        x = x + Z[:k].T @ y
-        r = b - apply_A(x)
+        delta = (V[:k] if left else Z[:k]).T @ y
+        x = x + delta
+        if augment > 0 and np.linalg.norm(delta) > 0:
+            aug = ([delta / np.linalg.norm(delta)] + aug)[:augment]
+        r = resid(b - apply_A(x))
         beta = np.linalg.norm(r)
         history.append(beta)
 

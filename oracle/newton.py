@@ -144,3 +144,35 @@ def newton_solve(pr, u0=None, n_increments=1, rtol=1e-6, atol=1e-50, max_newton_
         if not stats["converged"]:
             break
     return u, stats
+
+
+def dynamic_solve(pr, rho, dt, n_steps, body=None, predictor=True, **newton_kw):
+    """Transient solve with the BDF2 inertia of Section 2.3.1, Eq. (inertia2).
+
+    Starts from rest (u = v = 0; the values before the first step are taken
+    equal to those at t = 0, and the acceleration at t = 0 is zero).  Each
+    step solves R(u^{t+1}) = 0 with Newton (loads at their full value),
+    starting from the truncated Taylor predictor of Section 3.2, Eq.
+    (predictor), u^t + dt v^t + dt^2/2 a^t (or from u^t when predictor is
+    False), then updates v^{t+1} by BDF2 and a^{t+1} by BDF2 of the
+    velocities.  Returns (list of displacements per step, list of Newton
+    stats per step)."""
+    from .fv import with_source, bdf2_velocity
+    nc, dim = pr["nc"], pr["dim"]
+    u_n = np.zeros(nc * dim)
+    u_nm1 = u_n.copy()
+    v_n = np.zeros(nc * dim)
+    v_nm1 = v_n.copy()
+    a_n = np.zeros(nc * dim)
+    us, stats = [], []
+    for _ in range(n_steps):
+        q = with_source(pr, body=body, rho=rho, dt=dt, u_n=u_n, u_nm1=u_nm1, v_n=v_n, v_nm1=v_nm1)
+        guess = u_n + dt * v_n + 0.5 * dt * dt * a_n if predictor else u_n.copy()
+        u, st = newton_solve(q, u0=guess, n_increments=1, **newton_kw)
+        v = bdf2_velocity(u, u_n, u_nm1, dt)
+        a_n = (3.0 * v - 4.0 * v_n + v_nm1) / (2.0 * dt)
+        u_nm1, u_n = u_n, u
+        v_nm1, v_n = v_n, v
+        us.append(u.copy())
+        stats.append(st)
+    return us, stats

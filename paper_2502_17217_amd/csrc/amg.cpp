@@ -159,7 +159,7 @@ struct RowAcc {
 // by column.  Faces go to host threads, which claim slots in their two rows
 // with atomic cursors; the per-row sort of (column, value) pairs then gives
 // the same rows whatever order the slots were claimed in.
-HostCsr fine_operator(const HostMesh& h) {
+HostCsr fine_operator(const HostMesh& h, const std::vector<double>& pc_diag) {
   HostCsr A;
   const int64_t n = h.n_cells, nf = h.n_int;
   A.n = A.m = n;
@@ -180,7 +180,7 @@ HostCsr fine_operator(const HostMesh& h) {
   parallel_for(n_chunks(n), [&](int64_t c, int) {
     for (int64_t i = c * kRowChunk; i < std::min(n, (c + 1) * kRowChunk); ++i) {
       A.col[A.ptr[i]] = int32_t(i);
-      A.val[A.ptr[i]] = -h.pc_diag[i];
+      A.val[A.ptr[i]] = -pc_diag[i];
       pos[i] = A.ptr[i] + 1;
     }
   });
@@ -598,7 +598,7 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
   try {
     H->dim = m->host.dim;
     H->fp64 = fp64;
-    HostCsr A = fine_operator(m->host);
+    HostCsr A = fine_operator(m->host, m->pc_diag_eff.empty() ? m->host.pc_diag : m->pc_diag_eff);
     const double nnz0 = double(A.nnz());
     size_t off = 0;
     auto take = [&](int64_t count) {

@@ -83,6 +83,9 @@ void check_opts(const jfnk_gmres_opts& o) {
   JFNK_REQUIRE(o.step_chunk >= 0 && o.step_chunk <= o.restart, JFNK_E_ARG,
                "gmres: step_chunk must lie in [0, restart]");
   JFNK_REQUIRE(o.graphs >= 0 && o.graphs <= 2, JFNK_E_ARG, "gmres: graphs must be 0, 1 or 2");
+  JFNK_REQUIRE(o.left == 0 || o.left == 1, JFNK_E_ARG, "gmres: left must be 0 or 1");
+  JFNK_REQUIRE(o.augment >= 0 && o.augment < o.restart, JFNK_E_ARG, "gmres: augment must lie in [0, restart)");
+  JFNK_REQUIRE(!(o.left && o.augment), JFNK_E_ARG, "gmres: augmentation needs right preconditioning");
 }
 
 // Stream the solvers run on: the caller's, or, when the caller passes the
@@ -292,6 +295,7 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   upload(m.b_slot_nb, ua.slot_nb, s);
   upload(m.b_slot_fc, ua.slot_fc, s);
   upload(m.b_xc, to_soa(ua.xc, h.n_cells, dim, dim), s);
+  upload(m.b_vol, ua.vol, s);
   upload(m.b_fG, to_soa(ua.face, h.n_int, dim, kFaceRec), s);
   {
     std::vector<double> fw(h.n_int);
@@ -343,7 +347,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.n_int = int32_t(h.n_int);
   d.n_seg = S;
   d.law_mask = 0;
-  for (const Segment& g : m.segs) d.law_mask |= (g.mat.law == JFNK_NEO_HOOKEAN) ? 2 : 1;
+  for (const Segment& g : m.segs)
+    d.law_mask |= g.mat.law == JFNK_NEO_HOOKEAN ? 2 : g.mat.law == JFNK_ST_VENANT_KIRCHHOFF ? 4 : 1;
   d.slice_ptr = m.b_slice_ptr.as<int32_t>();
   d.slot_nb = m.b_slot_nb.as<int32_t>();
   d.slot_fc = m.b_slot_fc.as<int32_t>();
@@ -648,16 +653,17 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
   return guarded([&] {
     check_mesh(mesh);
     JFNK_REQUIRE(bytes, JFNK_E_ARG, "null output");
-    JFNK_REQUIRE(op == 0 || op == 1, JFNK_E_ARG, "workspace_size: op must be 0 or 1");
+    JFNK_REQUIRE(op >= 0 && op <= 2, JFNK_E_ARG, "workspace_size: op must be 0, 1 or 2");
     Carver c(nullptr);
     FvWork fw;
     fw.carve(c, mesh);
-    if (op == 1) {
+    if (op >= 1) {
       JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
       JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG64, JFNK_E_ARG,
                    "workspace_size: unknown preconditioner");
       KrylovWork kw;
       kw.carve(c, mesh, restart, precond_work_floats(mesh, precond));
+      if (op == 2) (void)c.take<double>(size_t(mesh->dev.n_cells) * mesh->dev.dim);   // u^t of a transient step
     }
     *bytes = c.off;
   });
@@ -787,6 +793,7 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     fw.zero_counters(s);
     KrylovWork kw;
     kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    set_preconditioner_inertia(mesh, mesh->src.dt, s);
     const double ts = now_ms();
     precond_setup(mesh, opts->gmres.precond, s);
     const double setup = now_ms() - ts;
@@ -803,6 +810,159 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     if (st == JFNK_E_NOT_CONVERGED) set_last_error("newton: iteration limit reached");
     if (st == JFNK_E_DIVERGED) set_last_error("newton: residual diverged");
     if (st == JFNK_E_NAN) set_last_error("newton: residual became NaN/Inf");
+  });
+  return g != JFNK_OK ? g : st;
+}
+
+}  // extern "C"
+
+namespace jfnk {
+
+void set_preconditioner_inertia(jfnk_mesh* m, double dt, hipStream_t s) {
+  if (dt == m->pc_dt) return;
+  const HostMesh& h = m->host;
+  std::vector<double> diag(h.pc_diag.begin(), h.pc_diag.end());
+  if (dt > 0) {
+    // -9/4 rho Omega / dt^2 on the block diagonal (Section 3.1); the volumes
+    // and densities come from the segments in union numbering
+    for (const Segment& g : m->segs)
+      for (int64_t c = 0; c < g.host.n_cells; ++c)
+        diag[g.cell_off + c] -= 2.25 * g.mat.rho * g.host.vol[c] / (dt * dt);
+  }
+  std::vector<double> dinv(diag.size());
+  for (size_t c = 0; c < diag.size(); ++c) dinv[c] = 1.0 / diag[c];
+  JFNK_HIP(hipMemcpyAsync(m->b_pc_dinv.p, dinv.data(), dinv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  JFNK_HIP(hipStreamSynchronize(s));
+  m->pc_diag_eff = dt > 0 ? std::move(diag) : std::vector<double>();
+  for (AmgHierarchy** a : {&m->amg, &m->amg64})
+    if (*a) {
+      amg_destroy(*a);
+      *a = nullptr;
+    }
+  m->pc_dt = dt;
+}
+
+}  // namespace jfnk
+
+extern "C" {
+
+jfnk_status jfnk_set_body_force(jfnk_mesh* mesh, const double* h_body, void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!h_body) {
+      mesh->src.has_body = false;
+      mesh->src.body.release();
+      return;
+    }
+    for (int64_t i = 0; i < mesh->n_ext_cells * mesh->host.dim; ++i)
+      JFNK_REQUIRE(std::isfinite(h_body[i]), JFNK_E_ARG, "set_body_force: value not finite");
+    const size_t bytes = sizeof(double) * size_t(mesh->n_ext_cells) * mesh->host.dim;
+    DevBuf tmp;
+    tmp.alloc(bytes);
+    JFNK_HIP(hipMemcpyAsync(tmp.p, h_body, bytes, hipMemcpyHostToDevice, s));
+    mesh->src.body.alloc(sizeof(double) * size_t(mesh->dev.n_cells) * mesh->dev.dim);
+    JFNK_HIP(hipMemsetAsync(mesh->src.body.p, 0, mesh->src.body.bytes, s));   // padding cells
+    launch_permute(mesh->b_ext.as<int32_t>(), tmp.as<double>(), mesh->src.body.as<double>(), mesh->dev.n_cells,
+                   mesh->dev.dim, true, s);
+    JFNK_HIP(hipStreamSynchronize(s));
+    mesh->src.has_body = true;
+  });
+}
+
+jfnk_status jfnk_set_inertia(jfnk_mesh* mesh, double dt, const double* d_u_n, const double* d_u_nm1,
+                             const double* d_v_n, const double* d_v_nm1, void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(std::isfinite(dt), JFNK_E_ARG, "set_inertia: dt not finite");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt <= 0) {
+      mesh->src.dt = 0;
+      mesh->src.u_n = mesh->src.u_nm1 = mesh->src.v_n = mesh->src.v_nm1 = nullptr;
+      set_preconditioner_inertia(mesh, 0.0, s);
+      return;
+    }
+    check_ptr(d_u_n, "u_n");
+    check_ptr(d_u_nm1, "u_nm1");
+    check_ptr(d_v_n, "v_n");
+    check_ptr(d_v_nm1, "v_nm1");
+    bool any_mass = false;
+    for (const Segment& g : mesh->segs) any_mass = any_mass || g.mat.rho > 0;
+    JFNK_REQUIRE(any_mass, JFNK_E_ARG, "set_inertia: no mesh of the handle has a density rho > 0");
+    mesh->src.dt = dt;
+    mesh->src.u_n = d_u_n;
+    mesh->src.u_nm1 = d_u_nm1;
+    mesh->src.v_n = d_v_n;
+    mesh->src.v_nm1 = d_v_nm1;
+    set_preconditioner_inertia(mesh, dt, s);
+  });
+}
+
+jfnk_status jfnk_dynamic_step(jfnk_mesh* mesh, double dt, int32_t predictor, const jfnk_newton_opts* opts,
+                              double* d_u, double* d_u_prev, double* d_v, double* d_v_prev, double* d_a,
+                              jfnk_stats* stats, void* d_work, void* stream) {
+  jfnk_status st = JFNK_OK;
+  jfnk_status g = guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_ptr(d_u_prev, "u_prev");
+    check_ptr(d_v, "v");
+    check_ptr(d_v_prev, "v_prev");
+    check_ptr(d_a, "a");
+    check_work(d_work);
+    JFNK_REQUIRE(dt > 0 && std::isfinite(dt), JFNK_E_ARG, "dynamic_step: dt must be positive");
+    JFNK_REQUIRE(opts, JFNK_E_ARG, "dynamic_step: null options");
+    JFNK_REQUIRE(opts->max_newton_it >= 1 && opts->eta > 0 && opts->rtol >= 0 && opts->atol >= 0 &&
+                     opts->stol >= 0,
+                 JFNK_E_ARG, "dynamic_step: bad Newton options");
+    check_opts(opts->gmres);
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    const hipStream_t s = solver_stream(mesh, caller, wants_graphs(mesh, opts->gmres));
+    const int64_t n = int64_t(mesh->dev.n_cells) * mesh->dev.dim;
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh);
+    fw.zero_counters(s);
+    KrylovWork kw;
+    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    double* un = c.take<double>(size_t(n));
+    // u^t aside; the unknown starts from the predictor
+    blas_lincomb(1.0, d_u, 0.0, d_u, un, n, s);
+    launch_predict(n, dt, predictor != 0, un, d_v, d_a, d_u, s);
+    mesh->src.dt = dt;
+    mesh->src.u_n = un;
+    mesh->src.u_nm1 = d_u_prev;
+    mesh->src.v_n = d_v;
+    mesh->src.v_nm1 = d_v_prev;
+    struct Clear {
+      jfnk_mesh* m;
+      ~Clear() {
+        m->src.dt = 0;
+        m->src.u_n = m->src.u_nm1 = m->src.v_n = m->src.v_nm1 = nullptr;
+      }
+    } clear{mesh};
+    set_preconditioner_inertia(mesh, dt, s);
+    const double ts = now_ms();
+    precond_setup(mesh, opts->gmres.precond, s);
+    const double setup = now_ms() - ts;
+    jfnk_newton_opts o = *opts;
+    o.n_increments = 1;
+    o.inc_begin = o.inc_end = 0;
+    std::vector<jfnk_stats> sv;
+    std::vector<jfnk_status> stv;
+    newton_solve(mesh, std::vector<int>(mesh->n_seg(), 1), o, d_u, fw, kw, s, sv, stv);
+    for (jfnk_status x : stv)
+      if (st == JFNK_OK && x != JFNK_OK) st = x;
+    // velocity, acceleration and the shift of the histories
+    launch_bdf2_update(n, dt, d_u, un, d_u_prev, d_v, d_v_prev, d_a, s);
+    join_stream(mesh, caller, s);
+    for (int k = 0; k < mesh->n_seg(); ++k) {
+      sv[k].t_ms[5] = setup;
+      if (stats) stats[k] = sv[k];
+    }
+    if (st == JFNK_E_NOT_CONVERGED) set_last_error("dynamic_step: Newton iteration limit reached");
+    if (st == JFNK_E_DIVERGED) set_last_error("dynamic_step: residual diverged");
+    if (st == JFNK_E_NAN) set_last_error("dynamic_step: residual became NaN/Inf");
   });
   return g != JFNK_OK ? g : st;
 }

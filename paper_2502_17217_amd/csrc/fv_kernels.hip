@@ -196,11 +196,51 @@ __device__ __forceinline__ void traction_nh2(const Law& m, const double (&g)[2][
   t[1] = fma(cq, q1, ca * a1);
 }
 
+// St. Venant-Kirchhoff face force (Appendix B): S = 2 mu E + lambda tr(E) I
+// with the Green strain E = (g + g^T + g g^T)/2, sigma = F S F^T / J (Eq.
+// S2sigma); with a = cof(F) Gamma = J F^-T Gamma the force a . sigma is
+// F S Gamma (F = I + g^T), which needs neither J nor the cofactor and has
+// no cancellation against I.  Plane strain: E_zz = 0, in-plane terms only.
+template <int D>
+__device__ __forceinline__ void traction_svk(const Law& m, const double (&g)[D][D],
+                                             const double (&G)[D], double (&t)[D]) {
+  double E[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double gg = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) gg = fma(g[i][k], g[j][k], gg);
+      E[i][j] = 0.5 * ((g[i][j] + g[j][i]) + gg);
+    }
+  double tr = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) tr += E[k][k];
+  double SG[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double e = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) e = fma(E[i][j], G[j], e);
+    SG[i] = fma(2.0 * m.mu, e, m.lam * tr * G[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double h = 0.0;   // (g^T S Gamma)_i = sum_k g[k][i] (S Gamma)_k
+#pragma unroll
+    for (int k = 0; k < D; ++k) h = fma(g[k][i], SG[k], h);
+    t[i] = SG[i] + h;
+  }
+}
+
 template <int D, int LAW>
 __device__ __forceinline__ void traction(const Law& m, const double (&g)[D][D],
                                          const double (&G)[D], double (&t)[D]) {
   if constexpr (LAW == JFNK_LINEAR_ELASTIC) {
     traction_le<D>(m, g, G, t);
+  } else if constexpr (LAW == JFNK_ST_VENANT_KIRCHHOFF) {
+    traction_svk<D>(m, g, G, t);
   } else if constexpr (D == 3) {
     traction_nh3(m, g, G, t);
   } else {
@@ -687,6 +727,8 @@ __device__ __forceinline__ void flux_cell(const MeshDev& m, const SegInfo& si, c
   if constexpr (LAWSEL == kLawMixed) {
     if (si.law == JFNK_NEO_HOOKEAN)
       cell_forces<D, JFNK_NEO_HOOKEAN>(m, law, src, ids, self, c, load, R);
+    else if (si.law == JFNK_ST_VENANT_KIRCHHOFF)
+      cell_forces<D, JFNK_ST_VENANT_KIRCHHOFF>(m, law, src, ids, self, c, load, R);
     else
       cell_forces<D, JFNK_LINEAR_ELASTIC>(m, law, src, ids, self, c, load, R);
   } else {
@@ -820,6 +862,8 @@ __device__ __forceinline__ void face_forces_sel(const SegInfo& si, const Src& sr
   if constexpr (LAWSEL == kLawMixed) {
     if (si.law == JFNK_NEO_HOOKEAN)
       face_forces_reg<D, JFNK_NEO_HOOKEAN>(si, src, fb, fo);
+    else if (si.law == JFNK_ST_VENANT_KIRCHHOFF)
+      face_forces_reg<D, JFNK_ST_VENANT_KIRCHHOFF>(si, src, fb, fo);
     else
       face_forces_reg<D, JFNK_LINEAR_ELASTIC>(si, src, fb, fo);
   } else {
@@ -919,6 +963,8 @@ __device__ __forceinline__ void bnd_force_sel(const SegInfo& si, const Src& src,
   if constexpr (LAWSEL == kLawMixed) {
     if (si.law == JFNK_NEO_HOOKEAN)
       bnd_force<D, JFNK_NEO_HOOKEAN>(si, src, be, load, f);
+    else if (si.law == JFNK_ST_VENANT_KIRCHHOFF)
+      bnd_force<D, JFNK_ST_VENANT_KIRCHHOFF>(si, src, be, load, f);
     else
       bnd_force<D, JFNK_LINEAR_ELASTIC>(si, src, be, load, f);
   } else {
@@ -1022,6 +1068,8 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_flux_tiled(Me
       if constexpr (LAWSEL == kLawMixed) {
         if (si.law == JFNK_NEO_HOOKEAN)
           face_forces<D, JFNK_NEO_HOOKEAN>(si, src, e0, fb, ff, fs);
+        else if (si.law == JFNK_ST_VENANT_KIRCHHOFF)
+          face_forces<D, JFNK_ST_VENANT_KIRCHHOFF>(si, src, e0, fb, ff, fs);
         else
           face_forces<D, JFNK_LINEAR_ELASTIC>(si, src, e0, fb, ff, fs);
       } else {
@@ -1288,6 +1336,8 @@ void launch_fused(const MeshDev& m, const double* u, const double* v, const SegS
   if (m.dim == 3) {
     if (mask == 2)
       fused_launch<3, JFNK_NEO_HOOKEAN>(m, u, v, sc, Ru, out, s);
+    else if (mask == 4)
+      fused_launch<3, JFNK_ST_VENANT_KIRCHHOFF>(m, u, v, sc, Ru, out, s);
     else if (mask == 1)
       fused_launch<3, JFNK_LINEAR_ELASTIC>(m, u, v, sc, Ru, out, s);
     else
@@ -1295,6 +1345,8 @@ void launch_fused(const MeshDev& m, const double* u, const double* v, const SegS
   } else {
     if (mask == 2)
       fused_launch<2, JFNK_NEO_HOOKEAN>(m, u, v, sc, Ru, out, s);
+    else if (mask == 4)
+      fused_launch<2, JFNK_ST_VENANT_KIRCHHOFF>(m, u, v, sc, Ru, out, s);
     else if (mask == 1)
       fused_launch<2, JFNK_LINEAR_ELASTIC>(m, u, v, sc, Ru, out, s);
     else
@@ -1309,6 +1361,8 @@ void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, cons
   if (m.dim == 3) {
     if (mask == 2)
       flux_launch<3, JFNK_NEO_HOOKEAN>(m, rec, sc, Ru, out, s);
+    else if (mask == 4)
+      flux_launch<3, JFNK_ST_VENANT_KIRCHHOFF>(m, rec, sc, Ru, out, s);
     else if (mask == 1)
       flux_launch<3, JFNK_LINEAR_ELASTIC>(m, rec, sc, Ru, out, s);
     else
@@ -1316,6 +1370,8 @@ void launch_flux(const MeshDev& m, const double* rec, const SegScalars& sc, cons
   } else {
     if (mask == 2)
       flux_launch<2, JFNK_NEO_HOOKEAN>(m, rec, sc, Ru, out, s);
+    else if (mask == 4)
+      flux_launch<2, JFNK_ST_VENANT_KIRCHHOFF>(m, rec, sc, Ru, out, s);
     else if (mask == 1)
       flux_launch<2, JFNK_LINEAR_ELASTIC>(m, rec, sc, Ru, out, s);
     else

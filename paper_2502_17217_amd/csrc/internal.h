@@ -165,6 +165,7 @@ struct SegInfo {
   int32_t cell_off;          // first cell of the segment in the union numbering
   int32_t n_cells;           // cells of the segment (cells beyond are padding)
   int32_t pad_;
+  double rho;                // density (inertia term only)
 };
 
 // Read-only device view of a mesh or a batch of meshes (the union of the
@@ -178,7 +179,7 @@ struct MeshDev {
   int32_t n_slices;
   int32_t n_int;             // union internal faces
   int32_t n_seg;
-  int32_t law_mask;          // bit 0: a linear-elastic segment, bit 1: a neo-Hookean segment
+  int32_t law_mask;          // bit 0: linear-elastic, bit 1: neo-Hookean, bit 2: St. Venant-Kirchhoff segment
   const int32_t* slice_ptr;  // [n_slices + 1], in slots (multiples of kSlice)
   const int32_t* slot_nb;    // neighbour cell, kSlotBoundary or kSlotPad
   const int32_t* slot_fc;    // internal: face (owner side) or ~face (neighbour side); boundary: bface
@@ -270,7 +271,7 @@ struct HostMesh {
 
 struct Material {
   int law = JFNK_LINEAR_ELASTIC;
-  double E = 0, nu = 0, alpha_rc = 1, alpha_pc = 1;
+  double E = 0, nu = 0, alpha_rc = 1, alpha_pc = 1, rho = 0;
   double mu = 0, lam = 0, kappa = 0, Kbar = 0;
 };
 
@@ -313,6 +314,7 @@ struct UnionArrays {
   // boundary list; ent_max: largest internal + boundary list
   int64_t halo_max = 0, faces_max = 0, bnd_max = 0, ent_max = 0, h2_max = 0, h1_width = 0;
   HostVec<double> xc, face, magG, bface;  // sized without zero fill, written in full
+  std::vector<double> vol;                  // cell volumes (0 on padding cells)
   std::vector<double> pc_dinv;
   std::vector<SegInfo> seg;
 };
@@ -367,6 +369,20 @@ struct DevBuf {
 
 struct AmgHierarchy;  // AMG preconditioner (amg.cpp)
 
+// Volume terms of the residual (Section 2.3.1): a body force per unit volume
+// and the BDF2 inertia of Eq. (inertia2) from caller-owned previous
+// displacements and velocities (internal layout).
+struct VolumeSource {
+  DevBuf body;                 // [dim][n_cells] body force density (internal layout)
+  bool has_body = false;
+  double dt = 0;               // > 0: inertia included
+  const double* u_n = nullptr;
+  const double* u_nm1 = nullptr;
+  const double* v_n = nullptr;
+  const double* v_nm1 = nullptr;
+  bool active() const { return has_body || dt > 0; }
+};
+
 // HIP-event timing of kernel classes (enabled per mesh for measurement).
 struct Profiler {
   bool on = false;
@@ -406,7 +422,7 @@ struct StepGraphs {
   const void* work = nullptr;
   const double* u = nullptr;
   const double* Ru = nullptr;
-  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0;
+  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0, left = -1;
   double eps = 0;
   std::vector<hipGraphExec_t> exec;  // one per chunk of steps (null until captured)
   void clear();
@@ -436,6 +452,10 @@ struct jfnk_mesh {
   size_t pinned_doubles = 0;
   bool pinned_owned = true;
   jfnk_mesh_info info{};
+  jfnk::VolumeSource src;
+  jfnk::DevBuf b_vol;                    // [n_cells] cell volumes (union; 0 on padding)
+  double pc_dt = 0;                      // inertia time step included in the preconditioners (0: none)
+  std::vector<double> pc_diag_eff;       // J_tilde diagonal with the inertia term (empty: host.pc_diag)
   jfnk::AmgHierarchy* amg = nullptr;     // FP32 hierarchy (JFNK_PC_AMG32)
   jfnk::AmgHierarchy* amg64 = nullptr;   // FP64 hierarchy (JFNK_PC_AMG64)
   jfnk::Profiler prof;

@@ -96,6 +96,7 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
     const int t = p.on ? p.begin(2, s) : -1;
     launch_fused(m->dev, u, nullptr, sc, nullptr, R, s);
     if (t >= 0) p.end(t, s);
+    if (m->src.active()) launch_source(m, sc, u, R, R, true, s);
     return;
   }
   int t = p.on ? p.begin(1, s) : -1;
@@ -104,11 +105,18 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
   t = p.on ? p.begin(2, s) : -1;
   launch_flux(m->dev, fw.grad, sc, nullptr, R, s);
   if (t >= 0) p.end(t, s);
+  if (m->src.active()) launch_source(m, sc, u, R, R, true, s);
 }
 
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
-             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu) {
+             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu, bool ru_surface) {
   Profiler& p = m->prof;
+  if (m->src.active() && !ru_surface) {
+    // the finite difference runs on the surface terms only: the volume
+    // terms are affine in u, their derivative is added exactly below
+    launch_source(m, SegScalars{nullptr, fw.load_ptr(), active, fw.load1}, u, Ru, fw.ru_src, false, s);
+    Ru = fw.ru_src;
+  }
   int t = p.on ? p.begin(0, s) : -1;
   if (eps > 0)
     fill_device(fw.eps, m->n_seg(), eps, s);
@@ -120,14 +128,15 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
     t = p.on ? p.begin(2, s) : -1;
     launch_fused(m->dev, u, v, sc, Ru, Jv, s);
     if (t >= 0) p.end(t, s);
-    return;
+  } else {
+    t = p.on ? p.begin(1, s) : -1;
+    launch_gradient(m->dev, u, v, sc, fw.grad, s);
+    if (t >= 0) p.end(t, s);
+    t = p.on ? p.begin(2, s) : -1;
+    launch_flux(m->dev, fw.grad, sc, Ru, Jv, s);
+    if (t >= 0) p.end(t, s);
   }
-  t = p.on ? p.begin(1, s) : -1;
-  launch_gradient(m->dev, u, v, sc, fw.grad, s);
-  if (t >= 0) p.end(t, s);
-  t = p.on ? p.begin(2, s) : -1;
-  launch_flux(m->dev, fw.grad, sc, Ru, Jv, s);
-  if (t >= 0) p.end(t, s);
+  if (m->src.dt > 0) launch_inertia_jv(m, sc, v, Jv, s);
 }
 
 void StepGraphs::clear() {
@@ -140,17 +149,27 @@ void StepGraphs::clear() {
 namespace {
 
 // Arnoldi steps j0 <= j < j1 for every active segment: z_j = P^{-1} v_j,
-// w = J z_j, two classical Gram-Schmidt passes, |w|, the device-side Givens
-// update, and v_{j+1} = w / h_{j+1,j}.  No host interaction: capturable.
-void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const double* Ru,
-                   const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, int j0, int j1, hipStream_t s) {
-  const int S = m->n_seg();
+// w = J z_j (right preconditioning; with augmentation the last n_aug
+// directions z_j are the stored corrections instead), or w = P^{-1} J v_j
+// (left), then two classical Gram-Schmidt passes, |w|, the device-side
+// Givens update, and v_{j+1} = w / h_{j+1,j}.  No host interaction:
+// capturable.
+void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const double* Ru, bool ru_surface,
+                   const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, int j0, int j1, hipStream_t s,
+                   int n_aug = 0) {
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
   for (int j = j0; j < j1; ++j) {
     double* Vj = kw.V + size_t(j) * n;
     double* Zj = kw.Z + size_t(j) * n;
-    precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
-    jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s, kw.uu);
+    if (o.left) {
+      jv_into(m, u, Ru, Vj, o.eps, Zj, fw, kw.act, s, kw.uu, ru_surface);
+      precond_apply(m, o.precond, o.cheb_degree, Zj, kw.w, kw, s);
+    } else {
+      // augmentation directions occupy slots restart - augment .. of Z
+      const int a = j - (o.restart - o.augment);
+      if (a < 0 || a >= n_aug) precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
+      jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface);
+    }
     Profiler& p = m->prof;
     const int t = p.on ? p.begin(4, s) : -1;
     cgs2_step(L, m->any_large, kw.V, n, j + 1, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, fw.cgs_tickets(),
@@ -178,11 +197,25 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   std::vector<char> part = part_in.empty() ? std::vector<char>(S, 1) : part_in;
   out.assign(S, GmresSeg());
   upload_flags(m, part, kw.act, s);
+  // with volume terms the J v of every step differences the surface terms
+  // only: their part of R(u) is formed once here
+  const bool ru_surface = m->src.active();
+  if (ru_surface) {
+    launch_source(m, SegScalars{nullptr, fw.load_ptr(), kw.act, fw.load1}, u, Ru, fw.ru_src, false, s);
+    Ru = fw.ru_src;
+  }
   // |u|^2 per segment, once: u is fixed over the solve, so the automatic J v
   // step of every Arnoldi step needs only |v|
   if (o.eps <= 0) blas_mdot(L, u, 0, 1, u, fw.partials, kw.uu, 1, false, kw.act, s);
   std::vector<double> v2;
-  seg_norms2(m, L, b, fw, kw, kw.act, s, v2);
+  // left preconditioning measures every residual after P^{-1}: the target
+  // is rtol |P^{-1} b| (P^{-1} b formed in the first Z slot, free here)
+  if (o.left) {
+    precond_apply(m, o.precond, o.cheb_degree, b, kw.Z, kw, s, false);
+    seg_norms2(m, L, kw.Z, fw, kw, kw.act, s, v2);
+  } else {
+    seg_norms2(m, L, b, fw, kw, kw.act, s, v2);
+  }
   std::vector<double> target(S), beta(S), prev(S);
   std::vector<int> stalls(S, 0);
   std::vector<char> done(S, 0);
@@ -195,13 +228,17 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       done[g] = 1;
     }
   }
-  // r = b - J x
+  // r = b - J x, or P^{-1}(b - J x) with left preconditioning
   if (x_is_zero) {
-    blas_lincomb(1.0, b, 0.0, b, kw.r, n, s);
+    blas_lincomb(1.0, o.left ? kw.Z : b, 0.0, b, kw.r, n, s);
   } else {
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s, kw.uu);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface);
     for (int g = 0; g < S; ++g) out[g].jv += part[g];
     blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
+    if (o.left) {
+      precond_apply(m, o.precond, o.cheb_degree, kw.r, kw.w, kw, s, false);
+      blas_lincomb(1.0, kw.w, 0.0, kw.w, kw.r, n, s);
+    }
   }
   seg_norms2(m, L, kw.r, fw, kw, kw.act, s, v2);
   for (int g = 0; g < S; ++g) {
@@ -215,12 +252,14 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   const int n_chunks = (mr + K - 1) / K;
   // Graphs need a capturable stream and unchanged launch arguments.
   const int graphs = o.graphs == 2 ? m->tune.graphs : o.graphs;
-  const bool use_graphs = graphs != 0 && s != nullptr && !m->prof.on;
+  // augmentation changes the steps from cycle to cycle: direct launches
+  const bool use_graphs = graphs != 0 && s != nullptr && !m->prof.on && o.augment == 0;
   if (use_graphs) {
     StepGraphs& sg = m->graphs;
     const void* work = static_cast<const void*>(kw.V);
     if (sg.work != work || sg.u != u || sg.Ru != Ru || sg.restart != mr || sg.precond != o.precond ||
-        sg.cheb != o.cheb_degree || sg.chunk != K || sg.eps != o.eps || sg.max_it != o.max_it) {
+        sg.cheb != o.cheb_degree || sg.chunk != K || sg.eps != o.eps || sg.max_it != o.max_it ||
+        sg.left != o.left) {
       sg.clear();
       sg.work = work;
       sg.u = u;
@@ -231,6 +270,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       sg.chunk = K;
       sg.eps = o.eps;
       sg.max_it = o.max_it;
+      sg.left = o.left;
       sg.exec.assign(n_chunks, nullptr);
     }
   }
@@ -241,6 +281,8 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   double* stage = m->pinned + m->pinned_doubles / 2;
   std::vector<int> its(S, 0);
   std::vector<char> act(S);
+  int n_aug = 0;   // augmentation directions available (LGMRES)
+  std::vector<double> dfac(S);
   while (true) {
     bool any = false;
     for (int g = 0; g < S; ++g) {
@@ -283,7 +325,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
           hipGraph_t gr = nullptr;
           JFNK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
           try {
-            enqueue_steps(m, L, u, Ru, o, fw, kw, j0, j1, s);
+            enqueue_steps(m, L, u, Ru, ru_surface, o, fw, kw, j0, j1, s, n_aug);
           } catch (...) {
             (void)hipStreamEndCapture(s, &gr);
             if (gr) (void)hipGraphDestroy(gr);
@@ -296,7 +338,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
         }
         JFNK_HIP(hipGraphLaunch(ex, s));
       } else {
-        enqueue_steps(m, L, u, Ru, o, fw, kw, j0, j1, s);
+        enqueue_steps(m, L, u, Ru, ru_surface, o, fw, kw, j0, j1, s, n_aug);
       }
       JFNK_HIP(hipMemcpyAsync(pin_nact + (c & 63), G.nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       JFNK_HIP(hipEventRecord(mesh_event(m, c & 1), s));
@@ -311,14 +353,37 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       Profiler& p = m->prof;
       const int t = p.on ? p.begin(5, s) : -1;
       gmres_lsq(G, S, kw.y, s);
-      blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
+      if (o.left) {
+        blas_combine(L, kw.V, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
+      } else if (o.augment > 0) {
+        // the cycle's correction delta = Z y goes to x and, normalised, to the
+        // first augmentation slot; older corrections move one slot on
+        fill_device(kw.r, n, 0.0, s);
+        blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, kw.r, G.ran, s, G.kk);
+        blas_axpby(1.0, kw.r, 1.0, x, n, s);
+        const int a0 = mr - o.augment;
+        for (int i = std::min(n_aug, o.augment - 1); i > 0; --i)
+          blas_lincomb(1.0, kw.Z + size_t(a0 + i - 1) * n, 0.0, kw.Z, kw.Z + size_t(a0 + i) * n, n, s);
+        std::vector<double> d2;
+        seg_norms2(m, L, kw.r, fw, kw, G.ran, s, d2);
+        for (int g = 0; g < S; ++g) dfac[g] = d2[g] > 0 ? 1.0 / std::sqrt(d2[g]) : 0.0;
+        upload_doubles(m, dfac, kw.stage, s);
+        blas_scale_seg(L, kw.r, kw.stage, kw.Z + size_t(a0) * n, G.ran, s);
+        n_aug = std::min(n_aug + 1, o.augment);
+      } else {
+        blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
+      }
       if (t >= 0) p.end(t, s);
     }
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s, kw.uu);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s, kw.uu, ru_surface);
     {
       Profiler& p = m->prof;
       const int t = p.on ? p.begin(5, s) : -1;
       blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
+      if (o.left) {
+        precond_apply(m, o.precond, o.cheb_degree, kw.r, kw.w, kw, s, false);
+        blas_lincomb(1.0, kw.w, 0.0, kw.w, kw.r, n, s);
+      }
       blas_mdot(L, kw.r, 0, 1, kw.r, fw.partials, kw.nrm, 4, false, G.ran, s);
       if (t >= 0) p.end(t, s);
     }

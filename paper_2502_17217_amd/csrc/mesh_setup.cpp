@@ -22,8 +22,8 @@
 namespace jfnk {
 
 Material make_material(const jfnk_material& m) {
-  JFNK_REQUIRE(m.law == JFNK_LINEAR_ELASTIC || m.law == JFNK_NEO_HOOKEAN, JFNK_E_ARG,
-               "material: unknown law");
+  JFNK_REQUIRE(m.law == JFNK_LINEAR_ELASTIC || m.law == JFNK_NEO_HOOKEAN || m.law == JFNK_ST_VENANT_KIRCHHOFF,
+               JFNK_E_ARG, "material: unknown law");
   JFNK_REQUIRE(m.E > 0 && std::isfinite(m.E), JFNK_E_ARG, "material: E must be positive");
   JFNK_REQUIRE(m.nu > -1.0 && m.nu < 0.5, JFNK_E_ARG, "material: nu must lie in (-1, 0.5)");
   JFNK_REQUIRE(m.alpha_rc >= 0 && m.alpha_pc > 0, JFNK_E_ARG,
@@ -34,6 +34,8 @@ Material make_material(const jfnk_material& m) {
   r.nu = m.nu;
   r.alpha_rc = m.alpha_rc;
   r.alpha_pc = m.alpha_pc;
+  JFNK_REQUIRE(m.rho >= 0 && std::isfinite(m.rho), JFNK_E_ARG, "material: rho must be >= 0");
+  r.rho = m.rho;
   r.mu = m.E / (2.0 * (1.0 + m.nu));
   r.lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
   r.kappa = m.E / (3.0 * (1.0 - 2.0 * m.nu));
@@ -736,6 +738,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   U.pc_diag.assign(N, -1.0);
   U.bandwidth = 0;
   ua.xc.resize(size_t(N) * dim);   // segments write their cells and zero their padding
+  ua.vol.assign(N, 0.0);
   ua.face.resize(size_t(face) * kFaceRec);
   ua.magG.resize(face);
   ua.bface.resize(size_t(bface) * kBfaceRec);
@@ -766,6 +769,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     std::fill(ua.xc.begin() + (co + h.n_cells) * dim, ua.xc.begin() + next * dim, 0.0);  // padding
     for (int64_t c = 0; c < h.n_cells; ++c) {
       for (int k = 0; k < dim; ++k) ua.xc[(co + c) * dim + k] = h.xc[c * dim + k];
+      ua.vol[co + c] = h.vol[c];
       U.pc_diag[co + c] = h.pc_diag[c];
       ua.ext[co + c] = int32_t(g.ext_off + h.old_of_new[c]);
     }
@@ -803,6 +807,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     si.kappa = g.mat.kappa;
     si.aK = g.mat.alpha_rc * g.mat.Kbar;
     si.law = g.mat.law;
+    si.rho = g.mat.rho;
     si.cell_off = int32_t(co);
     si.n_cells = int32_t(h.n_cells);
     si.pad_ = 0;

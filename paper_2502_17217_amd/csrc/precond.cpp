@@ -34,9 +34,9 @@ void precond_setup(jfnk_mesh* m, int precond, hipStream_t s) {
 // Arnoldi steps) is zero, so that steps enqueued past convergence cost only
 // their launches.
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
-                   KrylovWork& kw, hipStream_t s) {
+                   KrylovWork& kw, hipStream_t s, bool gated) {
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
-  const int32_t* gate = kw.gd.nact;
+  const int32_t* gate = gated ? kw.gd.nact : nullptr;
   if (precond == JFNK_PC_JACOBI) {
     blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, s, gate);
   } else if (amg_precond(precond)) {

@@ -94,7 +94,7 @@ struct jfnk_server {
   uint64_t next_id = 1;
   size_t in_use = 0, peak = 0;
   uint64_t budget_next = 0, budget_serving = 0;   // FIFO tickets for reservations
-  int64_t submitted = 0, completed = 0, rejected = 0, running = 0;
+  int64_t submitted = 0, completed = 0, rejected = 0, running = 0, cancelled = 0;
   double first_submit = -1, last_done = -1;
   std::vector<double> latencies;
 };
@@ -331,6 +331,11 @@ jfnk_status jfnk_server_submit(jfnk_server* S, const jfnk_mesh_desc* desc, const
     JFNK_REQUIRE(opts->gmres.restart >= 1 && opts->gmres.restart < kMaxBasis && opts->n_increments >= 1 &&
                      opts->max_newton_it >= 1 && opts->eta > 0,
                  JFNK_E_ARG, "server_submit: bad options");
+    {
+      // a full queue refuses at once, before the description is copied
+      std::lock_guard<std::mutex> lk(S->mu);
+      JFNK_REQUIRE(int64_t(S->queue.size()) < S->opts.max_queue, JFNK_E_BUSY, "server_submit: queue full");
+    }
     auto r = std::make_unique<Request>();
     r->desc.copy(*desc);
     r->mat = *mat;
@@ -384,6 +389,7 @@ jfnk_status jfnk_server_metrics_get(jfnk_server* S, jfnk_server_metrics* m) {
     m->rejected = S->rejected;
     m->running = S->running;
     m->queued = int64_t(S->queue.size());
+    m->cancelled = S->cancelled;
     m->hbm_in_use = int64_t(S->in_use);
     m->hbm_peak = int64_t(S->peak);
     std::vector<double> l = S->latencies;
@@ -402,6 +408,29 @@ jfnk_status jfnk_server_metrics_get(jfnk_server* S, jfnk_server_metrics* m) {
       const double span = S->last_done - S->first_submit;
       m->solves_per_s = span > 0 ? 1000.0 * double(S->completed) / span : 0.0;
     }
+  });
+}
+
+jfnk_status jfnk_server_cancel_queued(jfnk_server* S, int64_t* n_cancelled) {
+  return srv_guard([&] {
+    JFNK_REQUIRE(S, JFNK_E_ARG, "server_cancel_queued: null server");
+    int64_t n = 0;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      const double t = clock_ms() - S->t0;
+      for (Request* r : S->queue) {
+        r->info.status = JFNK_E_BUSY;
+        r->info.state = 2;
+        r->info.t_done_ms = t;
+        r->info.latency_ms = t - r->info.t_submit_ms;
+        std::snprintf(r->info.error, sizeof(r->info.error), "cancelled before it started");
+        ++n;
+      }
+      S->queue.clear();
+      S->cancelled += n;
+    }
+    S->cv_done.notify_all();
+    if (n_cancelled) *n_cancelled = n;
   });
 }
 

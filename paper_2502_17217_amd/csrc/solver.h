@@ -18,9 +18,26 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
 
 // J v into Jv using cached Ru; eps <= 0 selects the automatic per-segment
 // step (computed on the device into fw.eps), eps > 0 is used for every segment.
-// uu (may be null): per-segment |u|^2, when already known.
+// uu (may be null): per-segment |u|^2, when already known.  With volume
+// terms set on the mesh (body force, inertia), Ru is the full R(u) unless
+// ru_surface is true, in which case it is R(u) without its volume terms.
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
-             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu = nullptr);
+             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu = nullptr,
+             bool ru_surface = false);
+
+// ---- volume terms (source_kernels.hip) ----
+// out = in + S(u) (add) or out = in - S(u): S = load f_b Omega - rho Omega a_BDF2(u)
+void launch_source(const jfnk_mesh* m, const SegScalars& sc, const double* u, const double* in, double* out,
+                   bool add, hipStream_t s);
+// jv -= rho Omega 9/(4 dt^2) v
+void launch_inertia_jv(const jfnk_mesh* m, const SegScalars& sc, const double* v, double* jv, hipStream_t s);
+void launch_predict(int64_t total, double dt, bool taylor, const double* un, const double* v, const double* acc,
+                    double* u, hipStream_t s);
+void launch_bdf2_update(int64_t total, double dt, const double* u, const double* un, double* u_prev, double* v,
+                        double* v_prev, double* acc, hipStream_t s);
+// J_tilde's diagonal with the inertia term of time step dt (0: none): the
+// Jacobi inverse is updated and AMG hierarchies built for another dt dropped.
+void set_preconditioner_inertia(jfnk_mesh* m, double dt, hipStream_t s);
 
 struct GmresSeg {
   jfnk_status status = JFNK_OK;
@@ -47,8 +64,10 @@ inline bool amg_precond(int precond) { return precond == JFNK_PC_AMG32 || precon
 size_t precond_work_floats(const jfnk_mesh* m, int precond);
 size_t precond_work_floats(int64_t n_cells, int dim, int precond);
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s);
+// gated: the kernels skip when no segment is taking Arnoldi steps (inside a
+// cycle); outside a cycle the application must not be gated.
 void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, double* z,
-                   KrylovWork& kw, hipStream_t s);
+                   KrylovWork& kw, hipStream_t s, bool gated = true);
 void amg_destroy(AmgHierarchy* a);
 // Device bytes held by a hierarchy (0 for null).
 size_t amg_device_bytes(const AmgHierarchy* a);

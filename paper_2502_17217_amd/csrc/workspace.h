@@ -33,6 +33,7 @@ inline int64_t n_tiles(const jfnk_mesh* m) { return n_tiles(m->host.n_cells); }
 struct FvWork {
   double* grad = nullptr;      // [rec_doubles(dim)][n_cells] per-cell {w, grad w}
   double* ru = nullptr;        // [n_dof] R(u) when not supplied
+  double* ru_src = nullptr;    // [n_dof] R(u) without its volume terms (J v with body force / inertia)
   double* partials = nullptr;  // [n_tiles * kMaxBasis]
   double* eps = nullptr;       // [n_seg] J v step per segment
   double* load = nullptr;      // [n_seg] load factor per segment
@@ -42,6 +43,7 @@ struct FvWork {
     S = S_;
     grad = c.take<double>(size_t(n) * rec_doubles(dim));
     ru = c.take<double>(size_t(n) * dim);
+    ru_src = c.take<double>(size_t(n) * dim);
     partials = c.take<double>(size_t(n_tiles(n)) * kMaxBasis);
     eps = c.take<double>(S);
     load = c.take<double>(S);

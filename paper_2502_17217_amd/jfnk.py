@@ -20,7 +20,7 @@ OK, E_ARG, E_MESH, E_OOM, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_NAN, E_BREAKDOWN
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_OOM", -4: "E_HIP", -5: "E_NOT_CONVERGED",
                 -6: "E_DIVERGED", -7: "E_NAN", -8: "E_BREAKDOWN", -9: "E_BUSY"}
 BC = {"displacement": 1, "traction": 2, "pressure": 3}
-LAW = {"linear_elastic": 0, "neo_hookean": 1}
+LAW = {"linear_elastic": 0, "neo_hookean": 1, "st_venant_kirchhoff": 2}
 PC_NONE, PC_JACOBI, PC_AMG32, PC_AMG64 = 0, 1, 2, 3
 PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32, "amg64": PC_AMG64}
 
@@ -39,7 +39,7 @@ class jfnk_mesh_desc(C.Structure):
 
 class jfnk_material(C.Structure):
     _fields_ = [("law", C.c_int32), ("E", C.c_double), ("nu", C.c_double),
-                ("alpha_rc", C.c_double), ("alpha_pc", C.c_double)]
+                ("alpha_rc", C.c_double), ("alpha_pc", C.c_double), ("rho", C.c_double)]
 
 
 class jfnk_mesh_info(C.Structure):
@@ -56,7 +56,8 @@ class jfnk_mesh_info(C.Structure):
 class jfnk_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
-                ("eps", C.c_double), ("step_chunk", C.c_int32), ("graphs", C.c_int32)]
+                ("eps", C.c_double), ("step_chunk", C.c_int32), ("graphs", C.c_int32),
+                ("left", C.c_int32), ("augment", C.c_int32)]
 
 
 class jfnk_newton_opts(C.Structure):
@@ -119,6 +120,9 @@ def _load():
         "jfnk_autotune": [vp, C.POINTER(jfnk_gmres_opts), vp, d, vp, vp, vp],
         "jfnk_set_cell_passes": [vp, i32, i32],
         "jfnk_jv_noalloc": [vp, d, vp, vp, vp, d, vp, vp],
+        "jfnk_set_body_force": [vp, vp, vp],
+        "jfnk_set_inertia": [vp, d, vp, vp, vp, vp, vp],
+        "jfnk_dynamic_step": [vp, d, i32, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -218,7 +222,11 @@ def _make_desc(mesh):
 
 def _make_material(material):
     get = (lambda k: getattr(material, k)) if hasattr(material, "law") else (lambda k: material[k])
-    return jfnk_material(LAW[get("law")], get("E"), get("nu"), get("alpha_rc"), get("alpha_pc"))
+    try:
+        rho = float(get("rho"))
+    except (AttributeError, KeyError):
+        rho = 0.0
+    return jfnk_material(LAW[get("law")], get("E"), get("nu"), get("alpha_rc"), get("alpha_pc"), rho)
 
 
 def _info_dict(info):
@@ -363,11 +371,46 @@ def jv_noalloc(mesh, load, u, Ru, v, eps, Jv, stream=None):
     return Jv
 
 
+def set_body_force(mesh, body, stream=None):
+    """Body force per unit volume, [n_cells, dim] in input order (None removes it)."""
+    if body is None:
+        _check(_lib.jfnk_set_body_force(mesh.handle, None, _stream(stream)), "jfnk_set_body_force")
+        return
+    b = np.ascontiguousarray(body, dtype=np.float64).reshape(-1)
+    if b.size != mesh.n_dof_external:
+        raise ValueError("body force has %d values, expected %d" % (b.size, mesh.n_dof_external))
+    _check(_lib.jfnk_set_body_force(mesh.handle, b.ctypes.data, _stream(stream)), "jfnk_set_body_force")
+
+
+def set_inertia(mesh, dt, u_n=None, u_nm1=None, v_n=None, v_nm1=None, stream=None):
+    """BDF2 inertia from previous states (internal-layout device tensors); dt <= 0 removes it."""
+    if dt <= 0:
+        _check(_lib.jfnk_set_inertia(mesh.handle, 0.0, None, None, None, None, _stream(stream)), "jfnk_set_inertia")
+        return
+    _check(_lib.jfnk_set_inertia(mesh.handle, float(dt), _dptr(u_n, mesh.n_dof, "u_n"),
+                                 _dptr(u_nm1, mesh.n_dof, "u_nm1"), _dptr(v_n, mesh.n_dof, "v_n"),
+                                 _dptr(v_nm1, mesh.n_dof, "v_nm1"), _stream(stream)), "jfnk_set_inertia")
+
+
+def dynamic_step(mesh, dt, opts, u, u_prev, v, v_prev, a, work, predictor=True, stream=None,
+                 allow=(E_NOT_CONVERGED,)):
+    """One BDF2 time step in place on (u, u_prev, v, v_prev, a); returns (status, stats)."""
+    st = (jfnk_stats * mesh.n_segments)()
+    s = _lib.jfnk_dynamic_step(mesh.handle, float(dt), 1 if predictor else 0, C.byref(opts),
+                               _dptr(u, mesh.n_dof, "u"), _dptr(u_prev, mesh.n_dof, "u_prev"),
+                               _dptr(v, mesh.n_dof, "v"), _dptr(v_prev, mesh.n_dof, "v_prev"),
+                               _dptr(a, mesh.n_dof, "a"), C.cast(st, C.c_void_p), work.c, _stream(stream))
+    _check(s, "jfnk_dynamic_step", allow)
+    out = [x.as_dict() for x in st]
+    return s, (out[0] if mesh.n_segments == 1 else out)
+
+
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
-               step_chunk=0, graphs=2):
+               step_chunk=0, graphs=2, left=0, augment=0):
     if isinstance(precond, str):
         precond = PRECOND[precond]
-    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs)
+    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs,
+                           int(left), int(augment))
 
 
 def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, dtol=0.0,
@@ -462,7 +505,8 @@ class jfnk_server_metrics(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("running", C.c_int64), ("queued", C.c_int64), ("hbm_in_use", C.c_int64),
                 ("hbm_peak", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("solves_per_s", C.c_double)]
+                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("solves_per_s", C.c_double),
+                ("cancelled", C.c_int64)]
 
 
 def _server_sigs():
@@ -474,6 +518,7 @@ def _server_sigs():
         "jfnk_server_wait": [vp, C.c_uint64, C.POINTER(jfnk_request_info)],
         "jfnk_server_metrics_get": [vp, C.POINTER(jfnk_server_metrics)],
         "jfnk_server_destroy": [vp],
+        "jfnk_server_cancel_queued": [vp, C.POINTER(C.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(_lib, name)
@@ -516,6 +561,21 @@ class Server:
         info = jfnk_request_info()
         _check(_lib.jfnk_server_wait(self.handle, ticket, C.byref(info)), "jfnk_server_wait")
         return info.as_dict(), self._out.get(ticket)
+
+    def cancel_queued(self):
+        """Drop every request no worker has started; returns how many."""
+        n = C.c_int64()
+        _check(_lib.jfnk_server_cancel_queued(self.handle, C.byref(n)), "jfnk_server_cancel_queued")
+        return n.value
+
+    def submit_nowait(self, mesh, material, opts, keep_solution=False):
+        """submit() that returns None instead of raising when the queue is full."""
+        try:
+            return self.submit(mesh, material, opts, keep_solution)
+        except JfnkError as e:
+            if e.status == E_BUSY:
+                return None
+            raise
 
     def metrics(self):
         m = jfnk_server_metrics()

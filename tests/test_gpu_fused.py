@@ -28,6 +28,7 @@ CASES = [
     (3, (13, 11, 7), "neo_hookean"),
     (3, (3, 3, 3), "neo_hookean"),       # one partial tile
     (3, (41, 29, 19), "neo_hookean"),    # 89 tiles, ragged tail
+    (3, (13, 11, 7), "st_venant_kirchhoff"),
 ]
 
 
@@ -112,7 +113,7 @@ def _batch():
         m = mg.box_mesh_3d(*sh, 1.0, 0.7 + 0.1 * i, 0.9, jitter=0.15, seed=300 + i)
         mg.set_patch(m, "xmin", "displacement", (0.0, 0.0, 0.0))
         mg.set_patch(m, "xmax", "traction", tuple(rng.uniform(-1, 1, 3) * 2e3))
-        law = "neo_hookean" if i % 2 else "linear_elastic"
+        law = ["linear_elastic", "neo_hookean", "st_venant_kirchhoff", "neo_hookean"][i]
         probs.append((m, mg.Material(law, float(rng.uniform(1e5, 1e6)), float(rng.uniform(0.2, 0.4)))))
     return probs
 

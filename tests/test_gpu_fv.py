@@ -1,7 +1,7 @@
 """GPU parity of the residual and J.v kernels against the oracle.
 
 Element-by-element comparison on the same seeded inputs, at sizes that span
-several 256-cell workgroups with a ragged tail, for both laws, 2-D and 3-D,
+several 256-cell workgroups with a ragged tail, for the three laws, 2-D and 3-D,
 distorted meshes, all boundary types, and degenerate cases (one partial
 slice, zero direction vector).  Tolerances:
   * residual: |R_gpu - R_oracle|_inf <= 1e-11 * (largest face force), i.e.
@@ -30,6 +30,8 @@ CASES = [
     (3, (13, 11, 7), "linear_elastic"),
     (3, (13, 11, 7), "neo_hookean"),
     (3, (3, 3, 3), "neo_hookean"),      # one partial 64-cell slice
+    (2, (37, 29), "st_venant_kirchhoff"),
+    (3, (13, 11, 7), "st_venant_kirchhoff"),
 ]
 
 

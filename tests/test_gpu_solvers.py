@@ -180,3 +180,44 @@ def test_line_search_solve_matches_oracle(lib):
     ug2, st2, _ = _solve_gpu(lib, m, mat, n_increments=1, max_newton_it=60, rtol=1e-11, eta=1e-8,
                              restart=80, max_it=20000, precond="jacobi", line_search=0)
     assert st2 != lib.OK
+
+
+# ---------------------------------------------------------------- GMRES variants of Section 3.2
+@pytest.mark.parametrize("variant", ["left", "lgmres"])
+def test_gmres_variants_reach_the_oracle_solution(lib, variant):
+    """Left preconditioning and LGMRES augmentation (the variants the paper's
+    PETSc solver ran) converge to the same discrete solution as the oracle;
+    with the cycle length fixed, augmentation needs fewer Arnoldi steps on the
+    slender cantilever's first linear solve."""
+    m = mg.box_mesh_3d(9, 8, 7, 1.0, 0.8, 0.6, jitter=0.2, seed=12)
+    mg.set_patch(m, "ymin", "displacement", (0.0, 0.0, 0.0))
+    mg.set_patch(m, "ymax", "pressure", (5e6, 0, 0))
+    mg.set_patch(m, "xmax", "traction", (1e6, 0.0, 2e5))
+    mat = mg.Material("linear_elastic", 200e9, 0.3)
+    pr = prepare(m, mat)
+    uo, _ = o_newton(pr, n_increments=1, rtol=1e-6, max_newton_it=3, eta=1e-12, precond="lu",
+                     max_krylov_it=400)
+    kw = dict(left=1) if variant == "left" else dict(augment=3)
+    ug, st, stats = _solve_gpu(lib, m, mat, n_increments=1, max_newton_it=2, rtol=1e-11, eta=1e-11,
+                               restart=20, max_it=20000, precond="amg32", **kw)
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print(variant, "rel L2", err, stats)
+    assert st == lib.OK and err <= 1e-9
+    if variant == "lgmres":
+        cfg = mg.config_c3(200, 20, 2)
+        gm = lib.create_mesh(cfg["mesh"], cfg["material"])
+        its = {}
+        for aug in (0, 5):
+            work = lib.make_workspace(gm, 1, restart=30, precond=lib.PC_AMG32)
+            u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+            R = torch.empty_like(u)
+            lib.residual(gm, 0.1, u, R, work)
+            x = torch.zeros_like(u)
+            o = lib.gmres_opts(restart=30, max_it=20000, rtol=1e-3, precond=lib.PC_AMG32, augment=aug)
+            s2, st2 = lib.gmres(gm, 0.1, u, R, -R, x, o, work)
+            assert s2 == lib.OK
+            its[aug] = st2["gmres_it"]
+            del work
+        print("cantilever first solve, 30 directions per cycle: GMRES", its[0], "LGMRES(+5)", its[5])
+        assert its[5] < its[0]
+        gm.close()

@@ -102,3 +102,46 @@ def test_plane_strain_embedding():
     s2 = neo_hookean(g2, c)[0]
     s3 = neo_hookean(g3, c)[0]
     assert np.allclose(s2, s3)
+
+
+# ---------------------------------------------------------------- St. Venant-Kirchhoff
+from oracle.fv import st_venant_kirchhoff, traction  # noqa: E402
+
+
+@pytest.mark.parametrize("s", [0.8, 1.0, 1.25, 1.6])
+def test_st_venant_kirchhoff_uniaxial_stretch(s):
+    """F = diag(s, 1, 1): E = diag((s^2 - 1)/2, 0, 0), S = 2 mu E + lam tr E I,
+    sigma = F S F^T / J = diag(s S11, S22 / s, S33 / s) with J = s."""
+    c = _consts("st_venant_kirchhoff", 5.6e6, 0.4)
+    g = np.zeros((1, 3, 3))
+    g[0, 0, 0] = s - 1.0
+    sig, _ = st_venant_kirchhoff(g, c)
+    E11 = 0.5 * (s * s - 1.0)
+    S11 = (2 * c["mu"] + c["lam"]) * E11
+    S22 = c["lam"] * E11
+    assert np.allclose(np.diag(sig[0]), [s * S11, S22 / s, S22 / s], rtol=1e-13, atol=1e-6)
+    assert np.allclose(sig[0] - np.diag(np.diag(sig[0])), 0.0, atol=1e-6)
+    # the face force on the reference face with normal e_x is F S Gamma
+    G = np.array([[2.0, 0.0, 0.0]])
+    t = traction(g, G, c)[0]
+    assert np.allclose(t, [s * S11 * 2.0, 0.0, 0.0], rtol=1e-13, atol=1e-6)
+
+
+def test_st_venant_kirchhoff_objective_under_rotation():
+    c = _consts("st_venant_kirchhoff", 5.6e6, 0.4)
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    g = (Q - np.eye(3)).T[None]       # F = I + g^T = Q
+    sig, _ = st_venant_kirchhoff(g, c)
+    assert np.abs(sig).max() <= 1e-9 * c["mu"]
+
+
+def test_st_venant_kirchhoff_small_strain_limit():
+    """d sigma / d(grad u) at grad u = 0 is Hooke's law (complex step)."""
+    c = _consts("st_venant_kirchhoff", 5.6e6, 0.4)
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((1, 3, 3))
+    h = 1e-30
+    sig, _ = st_venant_kirchhoff(1j * h * d, c)
+    lin = stress_linear_elastic(d, c)
+    assert np.allclose(sig.imag / h, lin, rtol=1e-13, atol=1e-13 * np.abs(lin).max())

@@ -155,3 +155,25 @@ def test_divergence_tolerance_stops_the_solve():
     u, st = newton_solve(pr, rtol=1e-10, max_newton_it=20, eta=1e-10, precond="lu", restart=80, dtol=0.5)
     assert st["status"] == "diverged" and st["newton_it"] == [0]
     assert not np.any(u)
+
+
+# ---------------------------------------------------------------- GMRES variants
+def test_left_preconditioned_and_augmented_gmres_reach_the_dense_solution():
+    """Left preconditioning and LGMRES augmentation change the iterates, not
+    the solution: both reach the dense solve; with the cycle length fixed,
+    two augmentation vectors cut the iteration count of restarted GMRES."""
+    rng = np.random.default_rng(11)
+    n = 120
+    A = np.diag(np.linspace(1.0, 400.0, n)) + rng.standard_normal((n, n)) * 0.8
+    b = rng.standard_normal(n)
+    d = np.diag(A).copy()
+    x_ref = np.linalg.solve(A, b)
+    xl, il = gmres(lambda z: A @ z, b, M=lambda r: r / d, restart=20, rtol=1e-12, left=True, max_it=4000)
+    assert il["converged"]
+    assert np.linalg.norm(xl - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    # same cycle length (10 directions), two of them augmentation vectors
+    x0, i0 = gmres(lambda z: A @ z, b, restart=10, rtol=1e-10, max_it=20000)
+    xa, ia = gmres(lambda z: A @ z, b, restart=10, rtol=1e-10, max_it=20000, augment=2)
+    assert ia["converged"]
+    assert np.linalg.norm(xa - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    assert ia["iterations"] < 0.8 * i0["iterations"]

@@ -120,3 +120,26 @@ def test_queue_limit(jfnk):
     for t in ts:
         srv.wait(t)
     srv.close()
+
+
+def test_cancel_queued_backlog(jfnk):
+    """Ending a measurement window: queued requests are cancelled (done,
+    E_BUSY, 'cancelled'), the running one finishes normally, and the
+    metrics count them apart from completed and rejected requests."""
+    opts = jfnk.newton_opts(restart=30, precond="jacobi")
+    srv = jfnk.Server(hbm_budget=1 << 40, max_slots=1, dry_run_us_per_kcell=100000.0)
+    m = _mesh(6)
+    ts = [srv.submit(m, mg.Material(), opts, keep_solution=False) for _ in range(5)]
+    t0 = time.time()
+    while srv.poll(ts[0])["state"] == 0 and time.time() - t0 < 10:
+        time.sleep(0.005)
+    n = srv.cancel_queued()
+    assert n == 4
+    infos = [srv.wait(t)[0] for t in ts]
+    assert infos[0]["status"] == jfnk.OK
+    for i in infos[1:]:
+        assert i["status"] == jfnk.E_BUSY and i["state"] == 2 and "cancelled" in i["error"]
+    mt = srv.metrics()
+    assert mt["cancelled"] == 4 and mt["completed"] == 1 and mt["queued"] == 0
+    assert srv.cancel_queued() == 0
+    srv.close()
