@@ -20,13 +20,13 @@ both sides):
 ``n_cells``      int
 ``patches``      list of dicts, boundary faces grouped contiguously:
                  ``name``, ``start`` (first face index), ``size``,
-                 ``type`` in {"displacement", "traction", "pressure"},
+                 ``type`` in {"displacement", "traction", "pressure", "symmetry"},
                  ``value`` (3 floats: displacement, traction vector, or
                  pressure in value[0]), optional ``per_face`` [size, dim]
 """
 
 from .structured import (box_mesh_2d, box_mesh_3d, annulus_mesh_2d,
-                         set_patch, mesh_summary, renumber_cells)
+                         set_patch, mesh_summary, renumber_cells, mirrored_box_pair)
 from .configs import (config_c1, config_c2, config_c3, config_c4,
                       config_c5_stream, Material, cantilever_mesh)
 
@@ -34,5 +34,5 @@ __all__ = [
     "box_mesh_2d", "box_mesh_3d", "annulus_mesh_2d", "set_patch",
     "mesh_summary", "renumber_cells", "config_c1", "config_c2",
     "config_c3", "config_c4", "config_c5_stream", "Material",
-    "cantilever_mesh",
+    "cantilever_mesh", "mirrored_box_pair",
 ]

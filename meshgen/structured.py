@@ -227,10 +227,11 @@ def set_patch(mesh, name, type, value=(0.0, 0.0, 0.0), per_face=None):
     """Set the boundary condition of one patch (in place); returns the mesh.
 
     type: "displacement" (value = prescribed u), "traction" (value = T),
-    or "pressure" (value[0] = p, traction = -p n on the undeformed face).
+    "pressure" (value[0] = p, traction = -p n on the undeformed face), or
+    "symmetry" (a mirror plane; the value is unused).
     per_face, if given, overrides value with one vector per patch face.
     """
-    if type not in ("displacement", "traction", "pressure"):
+    if type not in ("displacement", "traction", "pressure", "symmetry"):
         raise ValueError("unknown patch type %r" % (type,))
     for p in mesh["patches"]:
         if p["name"] == name:
@@ -246,6 +247,41 @@ def set_patch(mesh, name, type, value=(0.0, 0.0, 0.0), per_face=None):
                 p["per_face"] = None
             return mesh
     raise KeyError(name)
+
+
+def mirrored_box_pair(dim, m, ny, nz=1, L=1.0, Ly=1.0, Lz=1.0, jitter=0.0, seed=None):
+    """A box mesh on [0, 2L] whose nodes are mirror images across x = L,
+    and the mesh of its left half [0, L] with the same nodes.
+
+    The full mesh has 2m cells along x; its node jitter is drawn for the
+    left half (plus the plane) and mirrored to the right half, nodes on the
+    plane keeping x = L.  Returns (half, full, left, mirror): full-mesh cell
+    numbers of the half mesh's cells (half cell k is full cell left[k]) and
+    of their mirror images (mirror[k]).  Patches of the half mesh keep the
+    box names; its plane x = L is the patch "xmax".
+    """
+    if dim == 2:
+        full = box_mesh_2d(2 * m, ny, 2 * L, Ly, jitter=jitter, seed=seed)
+        half = box_mesh_2d(m, ny, L, Ly)
+        nyz = ny + 1
+    else:
+        full = box_mesh_3d(2 * m, ny, nz, 2 * L, Ly, Lz, jitter=jitter, seed=seed)
+        half = box_mesh_3d(m, ny, nz, L, Ly, Lz)
+        nyz = (ny + 1) * (nz + 1)
+    nxf = 2 * m + 1
+    pts = full["points"].reshape(nyz, nxf, dim).copy()
+    # right half (i > m) = mirror of left (2m - i); the plane i = m at x = L
+    pts[:, m + 1:, :] = pts[:, m - 1::-1, :]
+    pts[:, m + 1:, 0] = 2.0 * L - pts[:, m + 1:, 0]
+    pts[:, m, 0] = L
+    full["points"] = np.ascontiguousarray(pts.reshape(-1, dim))
+    half["points"] = np.ascontiguousarray(pts[:, :m + 1, :].reshape(-1, dim))
+    ncyz = ny * (nz if dim == 3 else 1)
+    k = np.arange(m * ncyz)
+    i, rest = k % m, k // m
+    left = rest * (2 * m) + i
+    mirror = rest * (2 * m) + (2 * m - 1 - i)
+    return half, full, left, mirror
 
 
 def mesh_summary(mesh):

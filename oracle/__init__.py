@@ -28,10 +28,11 @@ Modules
 from .geometry import mesh_geometry
 from .fv import residual, gradient, material_constants, prepare
 from .jacobian import (jv_fd, jv_complex_step, eps_walker_pernice, brute_force_jacobian,
-                       approximate_jacobian_scalar)
+                       approximate_jacobian, approximate_jacobian_scalar)
 from .krylov import gmres
 from .newton import newton_solve, dynamic_solve
 
 __all__ = ["mesh_geometry", "residual", "gradient", "material_constants", "prepare",
            "jv_fd", "jv_complex_step", "eps_walker_pernice", "brute_force_jacobian",
-           "approximate_jacobian_scalar", "gmres", "newton_solve"]
+           "approximate_jacobian", "approximate_jacobian_scalar", "gmres", "newton_solve",
+           "dynamic_solve"]

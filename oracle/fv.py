@@ -36,6 +36,16 @@ design notes of the repository):
   * Prescribed boundary values (displacements, tractions, pressures) are
     all multiplied by the load factor of the current increment;
     a pressure patch applies the dead load -p Gamma_o.
+  * Symmetry planes (Section 2.3.2, Eq. symm, and the symmetry sums of
+    Eq. leastSquaresGrad and Eq. RhieChow): the face sees the mirror
+    image of cell P, x_P' = x_P + d_s with d_s = 2 ((x_f - x_P).n) n,
+    u_P' = R u_P and grad u_P' = R grad u_P R, R = I - 2 n n.  The face
+    gradient is the average grad u_s = (grad u_P + R grad u_P R)/2 and the
+    face stress is the law evaluated at it, as on internal faces (for the
+    linear law this is (sigma_P + R sigma_P R)/2, whose traction is the
+    normal part (n.sigma_P.n) n).  The printed second line of Eq. symm,
+    (I - n n).sigma_P, has zero traction on the face and is not used.
+    The least-squares weight is |Gamma_s| as on internal faces.
   * Plane strain (2-D): unit depth; the neo-Hookean law works on the
     3x3 tensors with F_zz = 1.
 
@@ -47,8 +57,22 @@ import numpy as np
 
 from .geometry import mesh_geometry
 
-DISP, TRAC, PRES = 1, 2, 3
-_TYPE = {"displacement": DISP, "traction": TRAC, "pressure": PRES}
+DISP, TRAC, PRES, SYMM = 1, 2, 3, 4
+_TYPE = {"displacement": DISP, "traction": TRAC, "pressure": PRES, "symmetry": SYMM}
+
+
+def reflect_vector(u, n):
+    """R u with R = I - 2 n n (mirror image across the plane of normal n)."""
+    return u - 2.0 * np.einsum("fi,fi->f", u, n)[:, None] * n
+
+
+def reflect_tensor(g, n):
+    """R g R, the mirror image of a second-order tensor field."""
+    gn = np.einsum("fij,fj->fi", g, n)          # g . n
+    ng = np.einsum("fi,fij->fj", n, g)          # n . g
+    ngn = np.einsum("fi,fi->f", ng, n)
+    return (g - 2.0 * gn[:, :, None] * n[:, None, :] - 2.0 * n[:, :, None] * ng[:, None, :]
+            + 4.0 * ngn[:, None, None] * n[:, :, None] * n[:, None, :])
 
 
 def material_constants(mat):
@@ -93,16 +117,7 @@ def prepare(mesh, mat):
     magd = np.linalg.norm(d, axis=1)
     magDelta = np.linalg.norm(Delta, axis=1)
 
-    # least-squares vectors, omega_f = |Gamma_f| in both sum and G_P
-    dd = np.einsum("fi,fi->f", d, d)
-    outer = magG[:, None, None] * d[:, :, None] * d[:, None, :] / dd[:, None, None]
-    G = _scatter(P, outer, nc) + _scatter(N, outer, nc)
-    Ginv = np.linalg.inv(G)
-    c_own = magG[:, None] * np.einsum("fij,fj->fi", Ginv[P], d) / dd[:, None]
-    c_nb = magG[:, None] * np.einsum("fij,fj->fi", Ginv[N], -d) / dd[:, None]
-
     # boundary faces
-    b = np.arange(n_int, nf)
     Pb = mesh["owner"][n_int:].astype(np.int64)
     Gb = geo["Gamma"][n_int:]
     magGb = np.linalg.norm(Gb, axis=1)
@@ -125,24 +140,51 @@ def prepare(mesh, mat):
         raise ValueError("displacement face with d.n <= 0")
     with np.errstate(divide="ignore", invalid="ignore"):
         Deltab = np.where(disp[:, None], db / dbn[:, None], 0.0)
+
+    # symmetry faces: the mirror image of x_P lies at x_P + d_s
+    sym = np.nonzero(btype == SYMM)[0]
+    if np.any(dbn[sym] <= 0.0):
+        raise ValueError("symmetry face with d.n <= 0")
+    Ps, ns = Pb[sym], nb_hat[sym]
+    ds = 2.0 * dbn[sym][:, None] * ns
+    magGs = magGb[sym]
+
+    # least-squares vectors, omega_f = |Gamma_f| in both sum and G_P
+    dd = np.einsum("fi,fi->f", d, d)
+    outer = magG[:, None, None] * d[:, :, None] * d[:, None, :] / dd[:, None, None]
+    G = _scatter(P, outer, nc) + _scatter(N, outer, nc)
+    dds = np.einsum("fi,fi->f", ds, ds)
+    if sym.size:
+        G = G + _scatter(Ps, magGs[:, None, None] * ds[:, :, None] * ds[:, None, :] / dds[:, None, None], nc)
+    Ginv = np.linalg.inv(G)
+    c_own = magG[:, None] * np.einsum("fij,fj->fi", Ginv[P], d) / dd[:, None]
+    c_nb = magG[:, None] * np.einsum("fij,fj->fi", Ginv[N], -d) / dd[:, None]
+    c_sym = magGs[:, None] * np.einsum("fij,fj->fi", Ginv[Ps], ds) / dds[:, None]
     return dict(mesh=mesh, dim=dim, nc=nc, n_int=n_int, geo=geo, mat=material_constants(mat),
                 P=P, N=N, Gam=Gam, magG=magG, n=n, d=d, magd=magd, w=w, Delta=Delta,
                 magDelta=magDelta, G=G, c_own=c_own, c_nb=c_nb,
                 Pb=Pb, Gb=Gb, magGb=magGb, db=db, magdb=np.linalg.norm(db, axis=1),
                 Deltab=Deltab, magDeltab=np.linalg.norm(Deltab, axis=1),
-                btype=btype, bval=bval)
+                btype=btype, bval=bval,
+                sym=sym, Ps=Ps, ns=ns, ds=ds, magds=np.linalg.norm(ds, axis=1), c_sym=c_sym)
 
 
 def gradient(u, pr):
     """Least-squares cell gradient, (grad u)_P[i, j] = d u_j / d x_i.
 
-    Eq. (leastSquaresGrad): sum over internal faces of c_{P,f} (x) (u_N - u_P).
+    Eq. (leastSquaresGrad): sum over internal faces of c_{P,f} (x) (u_N - u_P)
+    plus, over symmetry faces, c_{P,s} (x) (R_s u_P - u_P).
     """
     P, N = pr["P"], pr["N"]
     du = u[N] - u[P]
     g_own = pr["c_own"][:, :, None] * du[:, None, :]
     g_nb = pr["c_nb"][:, :, None] * (-du)[:, None, :]
-    return _scatter(P, g_own, pr["nc"]) + _scatter(N, g_nb, pr["nc"])
+    g = _scatter(P, g_own, pr["nc"]) + _scatter(N, g_nb, pr["nc"])
+    if pr["sym"].size:
+        Ps = pr["Ps"]
+        dus = reflect_vector(u[Ps], pr["ns"]) - u[Ps]
+        g = g + _scatter(Ps, pr["c_sym"][:, :, None] * dus[:, None, :], pr["nc"])
+    return g
 
 
 def stress_linear_elastic(g, c):
@@ -262,6 +304,18 @@ def face_forces(u, pr, load=1.0):
         jumpb = (pr["magDeltab"][m] / pr["magdb"][m])[:, None] * (ubar - u[Pb[m]])
         Dgb = np.einsum("fi,fij->fj", pr["Deltab"][m], gP)
         RC_b[m] = aK * (jumpb - Dgb) * pr["magGb"][m][:, None]
+    sym = pr["sym"]
+    if sym.size:
+        # Eq. (symm): the face sees cell P and its mirror image
+        Ps, ns = pr["Ps"], pr["ns"]
+        gP = g[Ps]
+        gs = 0.5 * (gP + reflect_tensor(gP, ns))
+        T_b[sym] = traction(gs, pr["Gb"][sym], c)
+        Deltas = pr["ds"] / np.einsum("fi,fi->f", pr["ds"], ns)[:, None]     # = n
+        jumps = (np.linalg.norm(Deltas, axis=1) / pr["magds"])[:, None] * \
+            (reflect_vector(u[Ps], ns) - u[Ps])
+        Dgs = np.einsum("fi,fij->fj", Deltas, gs)
+        RC_b[sym] = aK * (jumps - Dgs) * pr["magGb"][sym][:, None]
     m = bt == TRAC
     T_b[m] = load * pr["magGb"][m][:, None] * pr["bval"][m]
     m = bt == PRES

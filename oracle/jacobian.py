@@ -13,8 +13,17 @@ Paper passages:
     internal and displacement faces; no inertia term (static problems),
     alpha = alpha_pc; with inertia (a problem carrying rho and dt) the
     diagonal also gets -9/4 rho Omega_P / dt^2 (the BDF2 term of the block
-    diagonal coefficient).  Blocks are scalar times identity, so the scalar
-    matrix is returned (component decoupling, Eq. SegSysX-Z).
+    diagonal coefficient).  Without symmetry planes the blocks are scalar
+    times identity, so the scalar matrix is returned (component
+    decoupling, Eq. SegSysX-Z).
+  * Symmetry faces add a block proportional to n (x) n to the diagonal
+    block.  Reading: the block is the derivative of the symmetry sum of
+    the compact diffusion term that J_tilde is defined from (Section 3.1,
+    Eq. diffusion), alpha K_bar |Delta_s|/|d_s| |Gamma_s| (R u_P - u_P),
+    i.e. -2 alpha K_bar |Delta_s|/|d_s| |Gamma_s| n (x) n; the printed
+    coefficient lacks the factor 2 of R - I = -2 n n.  With the factor, the
+    J_tilde of a half mesh equals the J_tilde of the mirrored full mesh
+    folded across the plane.
 """
 
 import numpy as np
@@ -65,8 +74,37 @@ def brute_force_jacobian(u, pr, load=1.0, h=1e-30):
     return J
 
 
+def approximate_jacobian(pr):
+    """J_tilde as a sparse [n_cells*dim]^2 matrix (cells interleaved with
+    components), including the n (x) n blocks of symmetry faces."""
+    nc, dim = pr["nc"], pr["dim"]
+    A = sp.kron(_scalar_part(pr), sp.identity(dim), format="csr")
+    sym = pr["sym"]
+    if sym.size == 0:
+        return A
+    c = pr["mat"]
+    aK = c["alpha_pc"] * c["Kbar"]
+    coef = 2.0 * aK / pr["magds"] * pr["magGb"][sym]      # |Delta_s| = 1
+    ns = pr["ns"]
+    blocks = -coef[:, None, None] * ns[:, :, None] * ns[:, None, :]
+    Ps = pr["Ps"]
+    shape = blocks.shape
+    rows = np.broadcast_to(Ps[:, None, None] * dim + np.arange(dim)[None, :, None], shape)
+    cols = np.broadcast_to(Ps[:, None, None] * dim + np.arange(dim)[None, None, :], shape)
+    S = sp.csr_matrix((blocks.reshape(-1), (rows.reshape(-1), cols.reshape(-1))), shape=A.shape)
+    return (A + S).tocsr()
+
+
 def approximate_jacobian_scalar(pr):
-    """Scalar matrix A with J_tilde = A (x) I_dim (cells interleaved with components)."""
+    """Scalar matrix A with J_tilde = A (x) I_dim (cells interleaved with
+    components); only for meshes without symmetry planes."""
+    if pr["sym"].size:
+        raise ValueError("J_tilde of a mesh with symmetry planes is not scalar; use approximate_jacobian")
+    return _scalar_part(pr)
+
+
+def _scalar_part(pr):
+    """The scalar (component-independent) part of J_tilde."""
     c = pr["mat"]
     aK = c["alpha_pc"] * c["Kbar"]
     nc = pr["nc"]

@@ -35,7 +35,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from .fv import residual
-from .jacobian import jv_fd, jv_complex_step, approximate_jacobian_scalar
+from .jacobian import jv_fd, jv_complex_step, approximate_jacobian, approximate_jacobian_scalar
 from .krylov import gmres
 
 
@@ -44,6 +44,28 @@ def make_preconditioner(pr, kind):
     nc, dim = pr["nc"], pr["dim"]
     if kind in (None, "none"):
         return None
+    if pr["sym"].size:
+        # symmetry planes couple the components of J_tilde (n (x) n blocks):
+        # the block matrix itself, in the interleaved order
+        B = approximate_jacobian(pr).tocsc()
+        if kind == "jacobi":
+            dinv = 1.0 / B.diagonal()
+            return lambda r: dinv * r
+        if kind == "lu":
+            lu = spla.splu(B)
+            return lambda r: lu.solve(np.ascontiguousarray(r))
+        if kind == "cg":
+            dinv = 1.0 / B.diagonal()
+            Md = spla.LinearOperator(B.shape, matvec=lambda x: dinv * x)
+            Bcsr = B.tocsr()
+
+            def apply_block(r):
+                out, info = spla.cg(Bcsr, r, M=Md, rtol=1e-10, atol=0.0, maxiter=20000)
+                if info != 0:
+                    raise RuntimeError("cg preconditioner did not converge")
+                return out
+            return apply_block
+        raise ValueError(kind)
     A = approximate_jacobian_scalar(pr).tocsc()
     if kind == "jacobi":
         dinv = 1.0 / A.diagonal()
