@@ -63,12 +63,20 @@ typedef enum {
 } jfnk_status;
 
 /* Boundary classes of Section 2.3: prescribed displacement, prescribed
- * traction; a pressure patch is a traction -p n on the undeformed face
- * (dead load).  Symmetry planes are not supported. */
+ * traction, symmetry plane; a pressure patch is a traction -p n on the
+ * undeformed face (dead load).  A symmetry face (Eq. symm and the symmetry
+ * sums of Eq. leastSquaresGrad and Eq. RhieChow) sees the mirror image of
+ * its cell across the face's plane: the face gradient is the average of
+ * the cell's gradient and its mirror image, the face stress the law at that
+ * gradient (normal traction only), and the Rhie-Chow term acts on the
+ * normal displacement; its value and per_face entries are ignored.  Its
+ * block of the approximate Jacobian is not scalar times identity; the
+ * preconditioners keep the diagonal of that block per component. */
 typedef enum {
   JFNK_BC_DISPLACEMENT = 1,
   JFNK_BC_TRACTION = 2,
-  JFNK_BC_PRESSURE = 3
+  JFNK_BC_PRESSURE = 3,
+  JFNK_BC_SYMMETRY = 4
 } jfnk_bc_type;
 
 /* One boundary patch: faces [start, start + size) of the face list.
@@ -172,10 +180,11 @@ jfnk_status jfnk_mesh_order(const jfnk_mesh* mesh, int32_t* old_of_new);
 jfnk_status jfnk_to_internal(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* d_out, void* stream);
 
-/* Workspace bytes for jfnk_residual / jfnk_jv (op = 0), for jfnk_gmres and
- * jfnk_newton_solve with the given restart length and preconditioner
- * (op = 1), or for jfnk_dynamic_step (op = 2).  The caller allocates at least that many bytes of device memory,
- * 256-byte aligned, and passes it as d_work. */
+/* Workspace bytes for jfnk_residual / jfnk_jv (op = 0), for jfnk_gmres,
+ * jfnk_newton_solve and jfnk_segregated_solve with the given restart length
+ * and preconditioner (op = 1), for jfnk_dynamic_step (op = 2), or for
+ * jfnk_jv_central (op = 3).  The caller allocates at least that many bytes
+ * of device memory, 256-byte aligned, and passes it as d_work. */
 jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t restart,
                                 int32_t precond, size_t* bytes);
 
@@ -210,6 +219,15 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
  * uses that GPU's one array: calls that overlap on one GPU (other streams,
  * other threads) race and must be serialised by the caller.  Asynchronous
  * on `stream`. */
+/* Central-difference J v (Section 3.2, Eq. JF with the symmetric
+ * difference): Jv = (R(u + eps v) - R(u - eps v)) / (2 eps), second order in
+ * eps.  eps <= 0 selects eps_mach^(1/3) sqrt(1 + |u|_2) / |v|_2 per mesh
+ * segment (0 when v = 0, then Jv = 0); eps > 0 is used as given.  Costs two
+ * residual passes and needs no R(u).  d_work: jfnk_workspace_size op 3.
+ * eps_used (host, may be NULL): the step per segment.  Errors as jfnk_jv. */
+jfnk_status jfnk_jv_central(jfnk_mesh* mesh, double load, const double* d_u, const double* d_v, double eps,
+                            double* d_Jv, double* eps_used, void* d_work, void* stream);
+
 jfnk_status jfnk_jv_noalloc(jfnk_mesh* mesh, double load, const double* d_u, const double* d_Ru,
                             const double* d_v, double eps, double* d_Jv, void* stream);
 
@@ -236,7 +254,13 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_
  * LGMRES, the augmented restarted GMRES the paper runs (LGMRES(30)+2): the
  * last k of the restart directions of a cycle are the normalised
  * corrections x_c - x_{c-1} of the previous k cycles instead of
- * preconditioned basis vectors (graph replay is not used then). */
+ * preconditioned basis vectors (graph replay is not used then).
+ * fd_central = 1: every product J v is the central difference
+ * (R(u + eps v) - R(u - eps v)) / (2 eps), second order in eps where the
+ * forward difference of Eq. JF is first order, at the cost of one more
+ * residual pass; the automatic step is then
+ * eps_mach^(1/3) sqrt(1 + |u|) / |v| (the step that balances its truncation
+ * and rounding errors), an explicit eps is used as given. */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -249,6 +273,7 @@ typedef struct {
   int32_t graphs;
   int32_t left;
   int32_t augment;
+  int32_t fd_central;
 } jfnk_gmres_opts;
 
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment
@@ -266,7 +291,12 @@ typedef struct {
  * inc_begin, inc_end (1-based, inclusive; <= 0: the first and the last):
  * solve only increments inc_begin .. inc_end of the n_increments, starting
  * from the given d_u (e.g. the converged state of increment inc_begin - 1),
- * so that a caller can inspect every increment. */
+ * so that a caller can inspect every increment.
+ * central_below > 0: the linear solves of the Newton iterations that start
+ * with |R(u)| <= central_below |R(u_0)| use the central difference for J v
+ * (gmres.fd_central), whose smaller error lets the last iterations of a
+ * stiff problem reach a tight rtol that the forward difference stalls
+ * above. */
 typedef struct {
   int32_t n_increments;
   int32_t max_newton_it;
@@ -280,7 +310,29 @@ typedef struct {
   int32_t inc_begin;
   int32_t inc_end;
   double stol;
+  double central_below;
 } jfnk_newton_opts;
+
+/* Segregated solution procedure (Section 3.1, Eq. SegSys and the
+ * component systems Eq. SegSysX-Z), the classic algorithm the paper
+ * compares against: per load increment, u_{k+1} = u_k + du with
+ * J_tilde du = -R(u_k), each displacement component's system solved by
+ * preconditioned conjugate gradients on -J_tilde until its residual has
+ * fallen by the factor inner_rtol (Section 3.2 uses 0.9); converged when
+ * |R(u)| <= max(rtol |R(u_0)|, atol) (no step test, as in Section 3.3).
+ * precond: JFNK_PC_JACOBI, JFNK_PC_AMG32 or JFNK_PC_AMG64 (one V-cycle per
+ * CG iteration; the paper used incomplete Cholesky), cheb_degree as in
+ * jfnk_gmres_opts. */
+typedef struct {
+  int32_t n_increments;
+  int32_t max_outer_it;        /* per increment */
+  double rtol;
+  double atol;
+  double inner_rtol;           /* in (0, 1) */
+  int32_t max_inner_it;        /* CG iterations per outer iteration */
+  int32_t precond;
+  int32_t cheb_degree;
+} jfnk_segregated_opts;
 
 typedef struct {
   int32_t newton_it;           /* total Newton iterations */
@@ -381,6 +433,16 @@ jfnk_status jfnk_segment_info(const jfnk_mesh* mesh, int32_t seg, int64_t* cell_
  * n_increments: host [n] (NULL: opts->n_increments for all).  Meshes finish
  * independently; stats and seg_status (host [n], may be NULL) are per mesh;
  * the return value is the first non-OK mesh status. */
+/* Segregated solve of a single-mesh handle (see jfnk_segregated_opts)
+ * from the given d_u.  d_work: a solve workspace (jfnk_workspace_size op 1)
+ * for opts->precond, any restart.  stats: newton_it counts the outer
+ * iterations, gmres_it the CG iterations, res0 / res_final the residual
+ * norms of the last increment, t_ms[0] the wall time.  Returns JFNK_OK,
+ * JFNK_E_NOT_CONVERGED (max_outer_it reached in an increment; d_u holds the
+ * last iterate), JFNK_E_NAN, or JFNK_E_ARG (batch handle, bad option). */
+jfnk_status jfnk_segregated_solve(jfnk_mesh* mesh, const jfnk_segregated_opts* opts, double* d_u,
+                                  jfnk_stats* stats, void* d_work, void* stream);
+
 jfnk_status jfnk_newton_solve_batch(jfnk_mesh* mesh, const int32_t* n_increments,
                                     const jfnk_newton_opts* opts, double* d_u, jfnk_stats* stats,
                                     jfnk_status* seg_status, void* d_work, void* stream);

@@ -7,6 +7,10 @@ Paper passages:
   * Exact directional derivative for checking the finite difference:
     complex step, J v = Im R(u + i h v) / h (all residual arithmetic is
     analytic in u).
+  * Central difference (the symmetric form of Eq. JF, second order in
+    eps): (R(u + eps v) - R(u - eps v)) / (2 eps) with the step
+    eps_mach^(1/3) sqrt(1 + ||u||_2) / ||v||_2 (the cube-root step that
+    balances its truncation and rounding errors).
   * Approximate Jacobian J_tilde: Section 3.1, the block diagonal and
     off-diagonal coefficients after Eq. (SegSys): off-diagonal
     alpha K_bar |Delta||Gamma|/|d| I, diagonal minus the sum over
@@ -39,6 +43,26 @@ def eps_walker_pernice(u, v):
     if nv == 0.0:
         return 0.0
     return SQRT_EPS_MACH * np.sqrt(1.0 + np.linalg.norm(u)) / nv
+
+
+def eps_central(u, v):
+    nv = np.linalg.norm(v)
+    if nv == 0.0:
+        return 0.0
+    return np.cbrt(np.finfo(np.float64).eps) * np.sqrt(1.0 + np.linalg.norm(u)) / nv
+
+
+def jv_fd_central(u, v, pr, load=1.0, eps=None):
+    """Central-difference J v; returns (Jv, eps)."""
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    if eps is None:
+        eps = eps_central(u, v)
+    if eps == 0.0:
+        return np.zeros_like(v), 0.0
+    Rp = residual(u + eps * v, pr, load).reshape(-1)
+    Rm = residual(u - eps * v, pr, load).reshape(-1)
+    return (Rp - Rm) / (2.0 * eps), eps
 
 
 def jv_fd(u, v, pr, load=1.0, eps=None, Ru=None):

@@ -598,7 +598,20 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
   try {
     H->dim = m->host.dim;
     H->fp64 = fp64;
-    HostCsr A = fine_operator(m->host, m->pc_diag_eff.empty() ? m->host.pc_diag : m->pc_diag_eff);
+    // With symmetry faces the hierarchy is built from the component mean of
+    // the diagonal; the finest level adds back each component's deviation.
+    const std::vector<double>& diag0 = m->pc_diag_eff.empty() ? m->host.pc_diag : m->pc_diag_eff;
+    const std::vector<double>& sym = m->host.pc_sym;
+    std::vector<double> diag_mean;
+    if (!sym.empty()) {
+      diag_mean = diag0;
+      for (size_t c = 0; c < diag_mean.size(); ++c) {
+        double t = 0.0;
+        for (int q = 0; q < H->dim; ++q) t += sym[c * H->dim + q];
+        diag_mean[c] += t / H->dim;
+      }
+    }
+    HostCsr A = fine_operator(m->host, sym.empty() ? diag0 : diag_mean);
     const double nnz0 = double(A.nnz());
     size_t off = 0;
     auto take = [&](int64_t count) {
@@ -646,9 +659,24 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
       L.A.upload(A, fp64, s);
       L.P.upload(P, fp64, s);
       L.R.upload(R, fp64, s);
-      std::vector<double> dinv(A.n);
-      for (int64_t i = 0; i < A.n; ++i) dinv[i] = 1.0 / d[i];
-      upload_values(L.dinv, dinv.data(), dinv.size(), fp64, s);
+      if (H->levels.empty() && !sym.empty()) {
+        // finest level: A_q = A + diag(e_q), e_q = -(sym_q - mean), and the
+        // inverse of its diagonal per component (A = -J_tilde)
+        const int D = H->dim;
+        std::vector<double> e(size_t(D) * A.n), dinv(size_t(D) * A.n);
+        for (int q = 0; q < D; ++q)
+          for (int64_t i = 0; i < A.n; ++i) {
+            const double eq = -(diag0[i] + sym[size_t(i) * D + q]) - d[i];
+            e[size_t(q) * A.n + i] = eq;
+            dinv[size_t(q) * A.n + i] = 1.0 / (d[i] + eq);
+          }
+        upload_values(L.ecorr, e.data(), e.size(), fp64, s);
+        upload_values(L.dinv, dinv.data(), dinv.size(), fp64, s);
+      } else {
+        std::vector<double> dinv(A.n);
+        for (int64_t i = 0; i < A.n; ++i) dinv[i] = 1.0 / d[i];
+        upload_values(L.dinv, dinv.data(), dinv.size(), fp64, s);
+      }
       L.off_x = take(A.n);
       L.off_b = take(A.n);
       L.off_r = take(A.n);
@@ -693,7 +721,12 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, T* w, hipStream_t s, co
   T* r = w + L.off_r;
   T* d0 = w + L.off_d0;
   T* d1 = w + L.off_d1;
-  const T* dinv = L.dinv.as<T>();
+  AmgDiag<T> dinv;
+  dinv.dinv = L.dinv.as<T>();
+  if (L.ecorr.p != nullptr) {
+    dinv.dstride = int(L.n);
+    dinv.ecorr = L.ecorr.as<T>();
+  }
   ChebCoef cc = cheb_coefficients(L.lmax, degree);
   // pre-smoothing from x = 0
   amg_cheb_start0<T>(L.A, dinv, b, x, r, d0, T(cc.inv_theta), dim, s, gate, r64);
@@ -702,7 +735,7 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, T* w, hipStream_t s, co
     std::swap(d0, d1);
   }
   // coarse-grid correction
-  amg_residual<T>(L.A, b, x, r, dim, s, gate);
+  amg_residual<T>(L.A, dinv, b, x, r, dim, s, gate);
   const AmgLevel& C = H.levels[l + 1];
   amg_spmv<T>(L.R, r, w + C.off_b, false, dim, s, gate);
   vcycle<T>(H, l + 1, degree, w, s, gate);
@@ -743,7 +776,7 @@ size_t amg_device_bytes(const AmgHierarchy* a) {
   if (a == nullptr) return 0;
   size_t b = a->coarse_inv.bytes;
   for (const AmgLevel& L : a->levels)
-    b += L.dinv.bytes + L.A.ptr.bytes + L.A.col.bytes + L.A.val.bytes + L.P.ptr.bytes + L.P.col.bytes +
+    b += L.dinv.bytes + L.ecorr.bytes + L.A.ptr.bytes + L.A.col.bytes + L.A.val.bytes + L.P.ptr.bytes + L.P.col.bytes +
          L.P.val.bytes + L.R.ptr.bytes + L.R.col.bytes + L.R.val.bytes;
   return b;
 }

@@ -27,7 +27,9 @@ struct DevCsr {
 struct AmgLevel {
   int64_t n = 0;
   DevCsr A, P, R;         // operator; prolongation (n x n_next); restriction = P^T
-  DevBuf dinv;            // inverse diagonal of A (the hierarchy's precision)
+  DevBuf dinv;            // inverse diagonal of A (the hierarchy's precision); [dim][n] when ecorr is set
+  DevBuf ecorr;           // finest level of a mesh with symmetry faces: [dim][n] per-component
+                          // diagonal added to A (A holds the component mean); empty otherwise
   double lmax = 2.0;      // largest eigenvalue estimate of D^{-1} A
   size_t off_x = 0, off_b = 0, off_r = 0, off_d0 = 0, off_d1 = 0;  // workspace offsets (floats)
 };
@@ -44,6 +46,16 @@ struct AmgHierarchy {
   double setup_ms = 0;
 };
 
+// The diagonal a smoothing kernel uses: the inverse diagonal, shared by the
+// components (dstride 0) or per component (dstride n), and the optional
+// per-component diagonal correction of the finest level.
+template <class T>
+struct AmgDiag {
+  const T* dinv = nullptr;
+  int dstride = 0;
+  const T* ecorr = nullptr;
+};
+
 // ---- kernels (amg_kernels.hip), T = float or double; vectors are
 // component-major [dim][n] ----
 template <class T>
@@ -53,21 +65,22 @@ void amg_cast_out(const T* x, double* z, int64_t n, int dim, hipStream_t s, cons
 // Chebyshev start from x = 0: r = D^-1 b, d = r/theta, x = d; with r64
 // given, b = (T) r64 first (the finest level's FP64 input)
 template <class T>
-void amg_cheb_start0(const DevCsr& A, const T* dinv, T* b, T* x, T* r, T* d, T inv_theta, int dim,
+void amg_cheb_start0(const DevCsr& A, const AmgDiag<T>& dg, T* b, T* x, T* r, T* d, T inv_theta, int dim,
                      hipStream_t s, const int32_t* gate, const double* r64 = nullptr);
 // Chebyshev start from a given x: r = D^-1 (b - A x), d = r/theta, x += d
 // (defer_axpy: the next step applies x += d; z64 given: also z = -x in FP64)
 template <class T>
-void amg_cheb_start(const DevCsr& A, const T* dinv, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
+void amg_cheb_start(const DevCsr& A, const AmgDiag<T>& dg, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
                     hipStream_t s, const int32_t* gate, bool defer_axpy = false, double* z64 = nullptr);
 // one Chebyshev step: r -= D^-1 A d_in; d_out = c1 d_in + c2 r; x += d_out
 // (pend: x += d_in first, the deferred start update; z64 given: z = -x in FP64)
 template <class T>
-void amg_cheb_step(const DevCsr& A, const T* dinv, const T* d_in, T* d_out, T* r, T* x, T c1, T c2, int dim,
-                   hipStream_t s, const int32_t* gate, bool pend = false, double* z64 = nullptr);
+void amg_cheb_step(const DevCsr& A, const AmgDiag<T>& dg, const T* d_in, T* d_out, T* r, T* x, T c1, T c2,
+                   int dim, hipStream_t s, const int32_t* gate, bool pend = false, double* z64 = nullptr);
 // r = b - A x
 template <class T>
-void amg_residual(const DevCsr& A, const T* b, const T* x, T* r, int dim, hipStream_t s, const int32_t* gate);
+void amg_residual(const DevCsr& A, const AmgDiag<T>& dg, const T* b, const T* x, T* r, int dim, hipStream_t s,
+                  const int32_t* gate);
 // y = M x (restriction) or y += M x (prolongation, accumulate = true)
 template <class T>
 void amg_spmv(const DevCsr& M, const T* x, T* y, bool accumulate, int dim, hipStream_t s, const int32_t* gate);

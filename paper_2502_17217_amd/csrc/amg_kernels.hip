@@ -37,6 +37,20 @@ __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const i
   }
 }
 
+// Finest level of a mesh with symmetry faces: component q's operator is the
+// stored matrix plus the diagonal ecorr[q] (the per-component part of the
+// symmetry blocks), s[q] += ecorr[q][i] x[q][i]; no-op when ecorr is null.
+template <class T, int D>
+__device__ __forceinline__ void diag_correct(const T* __restrict__ ecorr, const T* __restrict__ x, int n, int i,
+                                             T (&s)[D]) {
+  if (ecorr == nullptr) return;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * n + i;
+    s[q] = fma(ecorr[o], x[o], s[q]);
+  }
+}
+
 // Row and lane-in-group of this thread when G lanes share a row.
 template <int G>
 __device__ __forceinline__ int row_of(int& sub) {
@@ -63,7 +77,7 @@ __global__ __launch_bounds__(kB) void k_cast_out(const T* __restrict__ x, double
 // r64 != null (finest level): the right-hand side arrives in FP64 and is
 // rounded into b here (the cast that would otherwise be its own launch).
 template <class T, int D>
-__global__ __launch_bounds__(kB) void k_cheb_start0(int n, const T* __restrict__ dinv,
+__global__ __launch_bounds__(kB) void k_cheb_start0(int n, const T* __restrict__ dinv, int dstride,
                                                     T* __restrict__ b, T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ d,
                                                     T inv_theta, const double* __restrict__ r64,
@@ -71,10 +85,10 @@ __global__ __launch_bounds__(kB) void k_cheb_start0(int n, const T* __restrict__
   if (gate != nullptr && *gate == 0) return;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
-  const T di = dinv[i];
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
+    const T di = dinv[size_t(q) * dstride + i];
     T bo;
     if (r64 != nullptr) {
       bo = T(r64[o]);
@@ -94,7 +108,8 @@ template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col,
                                                    const T* __restrict__ val,
-                                                   const T* __restrict__ dinv,
+                                                   const T* __restrict__ dinv, int dstride,
+                                                   const T* __restrict__ ecorr,
                                                    const T* __restrict__ b, const T* __restrict__ x,
                                                    T* __restrict__ r, T* __restrict__ d,
                                                    T inv_theta, const int32_t* __restrict__ gate) {
@@ -105,10 +120,11 @@ __global__ __launch_bounds__(kB) void k_cheb_start(int n, const int32_t* __restr
   T s[D];
   row_dot<T, D, G>(ptr, col, val, x, n, i, sub, s);
   if (sub != 0) return;
-  const T di = dinv[i];
+  diag_correct<T, D>(ecorr, x, n, i, s);
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
+    const T di = dinv[size_t(q) * dstride + i];
     const T ri = di * (b[o] - s[q]);
     r[o] = ri;
     d[o] = ri * inv_theta;
@@ -138,7 +154,8 @@ template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col,
                                                   const T* __restrict__ val,
-                                                  const T* __restrict__ dinv,
+                                                  const T* __restrict__ dinv, int dstride,
+                                                  const T* __restrict__ ecorr,
                                                   const T* __restrict__ d_in, T* __restrict__ d_out,
                                                   T* __restrict__ r, T* __restrict__ x, T c1,
                                                   T c2, int pend, double* __restrict__ z64,
@@ -150,10 +167,11 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
   T s[D];
   row_dot<T, D, G>(ptr, col, val, d_in, n, i, sub, s);
   if (sub != 0) return;
-  const T di = dinv[i];
+  diag_correct<T, D>(ecorr, d_in, n, i, s);
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const size_t o = size_t(q) * n + i;
+    const T di = dinv[size_t(q) * dstride + i];
     const T ri = r[o] - di * s[q];
     const T dd = fma(c1, d_in[o], c2 * ri);
     r[o] = ri;
@@ -169,7 +187,8 @@ __global__ __launch_bounds__(kB) void k_cheb_step(int n, const int32_t* __restri
 template <class T, int D, int G>
 __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col,
-                                                 const T* __restrict__ val, const T* __restrict__ b,
+                                                 const T* __restrict__ val, const T* __restrict__ ecorr,
+                                                 const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ r,
                                                  const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
@@ -179,6 +198,7 @@ __global__ __launch_bounds__(kB) void k_residual(int n, const int32_t* __restric
   T s[D];
   row_dot<T, D, G>(ptr, col, val, x, n, i, sub, s);
   if (sub != 0) return;
+  diag_correct<T, D>(ecorr, x, n, i, s);
 #pragma unroll
   for (int q = 0; q < D; ++q) r[size_t(q) * n + i] = b[size_t(q) * n + i] - s[q];
 }
@@ -302,34 +322,36 @@ void amg_cast_out(const T* x, double* z, int64_t n, int dim, hipStream_t s, cons
 }
 
 template <class T>
-void amg_cheb_start0(const DevCsr& A, const T* dinv, T* b, T* x, T* r, T* d, T inv_theta, int dim,
+void amg_cheb_start0(const DevCsr& A, const AmgDiag<T>& dg, T* b, T* x, T* r, T* d, T inv_theta, int dim,
                      hipStream_t s, const int32_t* gate, const double* r64) {
-  JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dinv, b, x, r, d,
-                    inv_theta, r64, gate);
+  JFNK_DIM_DISPATCH(dim, k_cheb_start0, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, dg.dinv, dg.dstride, b, x,
+                    r, d, inv_theta, r64, gate);
 }
 
 template <class T>
-void amg_cheb_start(const DevCsr& A, const T* dinv, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
+void amg_cheb_start(const DevCsr& A, const AmgDiag<T>& dg, const T* b, T* x, T* r, T* d, T inv_theta, int dim,
                     hipStream_t s, const int32_t* gate, bool defer_axpy, double* z64) {
   // r = D^-1 (b - A x), d = r / theta, then x += d in a second pass (x is read
   // by other rows' products in the first pass), or in the next step's launch
   JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_start, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<T>(), dinv, b, x, r, d, inv_theta, gate);
+                    A.val.as<T>(), dg.dinv, dg.dstride, dg.ecorr, b, x, r, d, inv_theta, gate);
   if (!defer_axpy)
     JFNK_DIM_DISPATCH(dim, k_axpy_inplace, dim3(blocks_for(A.n)), dim3(kB), 0, s, A.n, d, x, z64, gate);
 }
 
 template <class T>
-void amg_cheb_step(const DevCsr& A, const T* dinv, const T* d_in, T* d_out, T* r, T* x, T c1, T c2, int dim,
-                   hipStream_t s, const int32_t* gate, bool pend, double* z64) {
+void amg_cheb_step(const DevCsr& A, const AmgDiag<T>& dg, const T* d_in, T* d_out, T* r, T* x, T c1, T c2,
+                   int dim, hipStream_t s, const int32_t* gate, bool pend, double* z64) {
   JFNK_ROW_DISPATCH(dim, A.lanes, k_cheb_step, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<T>(), dinv, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64, gate);
+                    A.val.as<T>(), dg.dinv, dg.dstride, dg.ecorr, d_in, d_out, r, x, c1, c2, pend ? 1 : 0, z64,
+                    gate);
 }
 
 template <class T>
-void amg_residual(const DevCsr& A, const T* b, const T* x, T* r, int dim, hipStream_t s, const int32_t* gate) {
+void amg_residual(const DevCsr& A, const AmgDiag<T>& dg, const T* b, const T* x, T* r, int dim, hipStream_t s,
+                  const int32_t* gate) {
   JFNK_ROW_DISPATCH(dim, A.lanes, k_residual, A.n, s, A.n, A.ptr.as<int32_t>(), A.col.as<int32_t>(),
-                    A.val.as<T>(), b, x, r, gate);
+                    A.val.as<T>(), dg.ecorr, b, x, r, gate);
 }
 
 template <class T>
@@ -351,13 +373,14 @@ void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t
 #define JFNK_AMG_INSTANTIATE(T)                                                                           \
   template void amg_cast_in<T>(const double*, T*, int64_t, int, hipStream_t, const int32_t*);             \
   template void amg_cast_out<T>(const T*, double*, int64_t, int, hipStream_t, const int32_t*);            \
-  template void amg_cheb_start0<T>(const DevCsr&, const T*, T*, T*, T*, T*, T, int, hipStream_t,          \
+  template void amg_cheb_start0<T>(const DevCsr&, const AmgDiag<T>&, T*, T*, T*, T*, T, int, hipStream_t, \
                                    const int32_t*, const double*);                                        \
-  template void amg_cheb_start<T>(const DevCsr&, const T*, const T*, T*, T*, T*, T, int, hipStream_t,     \
-                                  const int32_t*, bool, double*);                                         \
-  template void amg_cheb_step<T>(const DevCsr&, const T*, const T*, T*, T*, T*, T, T, int, hipStream_t,   \
-                                 const int32_t*, bool, double*);                                          \
-  template void amg_residual<T>(const DevCsr&, const T*, const T*, T*, int, hipStream_t, const int32_t*); \
+  template void amg_cheb_start<T>(const DevCsr&, const AmgDiag<T>&, const T*, T*, T*, T*, T, int,         \
+                                  hipStream_t, const int32_t*, bool, double*);                            \
+  template void amg_cheb_step<T>(const DevCsr&, const AmgDiag<T>&, const T*, T*, T*, T*, T, T, int,       \
+                                 hipStream_t, const int32_t*, bool, double*);                             \
+  template void amg_residual<T>(const DevCsr&, const AmgDiag<T>&, const T*, const T*, T*, int,            \
+                                hipStream_t, const int32_t*);                                             \
   template void amg_spmv<T>(const DevCsr&, const T*, T*, bool, int, hipStream_t, const int32_t*);         \
   template void amg_dense<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);              \
   template void amg_diag_solve<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);

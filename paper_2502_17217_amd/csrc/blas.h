@@ -60,9 +60,12 @@ void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv,
                double* h, double* h2, double* nrm, double* partials, int32_t* tickets, int32_t* counters,
                const GmresDev& G, int j, int max_it, hipStream_t s);
 
-// z = D^{-1} r with one scalar per cell applied to every component
-// (skipped entirely when gate is given and *gate == 0)
-void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim,
+// eps[s] *= factor, eps_neg[s] = -eps[s] (central-difference step)
+void blas_central_eps(double* eps, double* eps_neg, int S, double factor, hipStream_t s);
+// z = D^{-1} r with one scalar per cell applied to every component, or one
+// per cell and component when per_comp (dinv [dim][n_cells]); skipped
+// entirely when gate is given and *gate == 0
+void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim, bool per_comp,
                  hipStream_t s, const int32_t* gate = nullptr);
 
 }  // namespace jfnk

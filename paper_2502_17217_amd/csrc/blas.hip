@@ -140,17 +140,27 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(double a, const double* __re
 }
 
 // z[k][c] = dinv[c] * r[k][c]  (diagonal of the scalar approximate Jacobian,
-// applied to every component of the component-major vector)
+// applied to every component of the component-major vector), or
+// dinv[k][c] * r[k][c] when per_comp (meshes with symmetry faces)
 __global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ dinv,
                                                    const double* __restrict__ r,
                                                    double* __restrict__ z, int64_t n_cells, int dim,
-                                                   const int32_t* __restrict__ gate) {
+                                                   int per_comp, const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
+  const int64_t ds = per_comp ? n_cells : 0;
   for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n_cells; c += stride) {
-    const double s = dinv[c];
-    for (int k = 0; k < dim; ++k) z[k * n_cells + c] = s * r[k * n_cells + c];
+    for (int k = 0; k < dim; ++k) z[k * n_cells + c] = dinv[k * ds + c] * r[k * n_cells + c];
   }
+}
+
+// Central-difference step from the forward one: eps *= factor, eps_neg = -eps.
+__global__ void k_central_eps(double* __restrict__ eps, double* __restrict__ eps_neg, int S, double factor) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  const double e = eps[i] * factor;
+  eps[i] = e;
+  eps_neg[i] = -e;
 }
 
 inline int grid_stride_blocks(int64_t n) {
@@ -208,10 +218,15 @@ void blas_lincomb(double a, const double* x, double b, const double* z, double* 
   JFNK_HIP(hipGetLastError());
 }
 
-void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim,
+void blas_central_eps(double* eps, double* eps_neg, int S, double factor, hipStream_t s) {
+  hipLaunchKernelGGL(k_central_eps, dim3((S + 255) / 256), dim3(256), 0, s, eps, eps_neg, S, factor);
+  JFNK_HIP(hipGetLastError());
+}
+
+void blas_jacobi(const double* dinv, const double* r, double* z, int64_t n_cells, int dim, bool per_comp,
                  hipStream_t s, const int32_t* gate) {
   hipLaunchKernelGGL(k_jacobi, dim3(grid_stride_blocks(n_cells)), dim3(kBlock), 0, s, dinv, r, z,
-                     n_cells, dim, gate);
+                     n_cells, dim, per_comp ? 1 : 0, gate);
   JFNK_HIP(hipGetLastError());
 }
 

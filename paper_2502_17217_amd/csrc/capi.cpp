@@ -86,6 +86,7 @@ void check_opts(const jfnk_gmres_opts& o) {
   JFNK_REQUIRE(o.left == 0 || o.left == 1, JFNK_E_ARG, "gmres: left must be 0 or 1");
   JFNK_REQUIRE(o.augment >= 0 && o.augment < o.restart, JFNK_E_ARG, "gmres: augment must lie in [0, restart)");
   JFNK_REQUIRE(!(o.left && o.augment), JFNK_E_ARG, "gmres: augmentation needs right preconditioning");
+  JFNK_REQUIRE(o.fd_central == 0 || o.fd_central == 1, JFNK_E_ARG, "gmres: fd_central must be 0 or 1");
 }
 
 // Stream the solvers run on: the caller's, or, when the caller passes the
@@ -326,6 +327,7 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
     upload(m.b_h2_cells, ua.h2_cells, s);
     upload(m.b_h1_loc, ua.h1_loc, s);
     upload(m.b_h1_mg, ua.h1_mg, s);
+    if (!h.pc_sym.empty()) upload(m.b_h1_fc, ua.h1_fc, s);
     upload(m.b_slot_mg, ua.slot_mg, s);
   }
   JFNK_HIP(hipStreamSynchronize(s));
@@ -391,6 +393,8 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
   d.h2_cells = h.tiled ? m.b_h2_cells.as<int32_t>() : nullptr;
   d.h1_loc = h.tiled ? m.b_h1_loc.as<int16_t>() : nullptr;
   d.h1_mg = h.tiled ? m.b_h1_mg.as<double>() : nullptr;
+  d.has_symm = h.pc_sym.empty() ? 0 : 1;
+  d.h1_fc = (h.tiled && d.has_symm) ? m.b_h1_fc.as<int32_t>() : nullptr;
   d.slot_mg = h.tiled ? m.b_slot_mg.as<double>() : nullptr;
   d.fused = (d.tiled && fused_fits(dim, ua)) ? 1 : 0;
   jfnk_mesh_info& in = m.info;
@@ -408,7 +412,7 @@ void finish_handle(jfnk_mesh& m, hipStream_t s, double t0) {
                             m.b_bnd_face.bytes + m.b_bnd_loc.bytes + m.b_fbeg.bytes + m.b_face_loc.bytes +
                             m.b_in_ptr.bytes + m.b_in_face.bytes + m.b_in_loc.bytes + m.b_h2_ptr.bytes +
                             m.b_h2_cells.bytes + m.b_h1_loc.bytes + m.b_h1_mg.bytes +
-                            m.b_slot_mg.bytes);
+                            m.b_slot_mg.bytes + m.b_h1_fc.bytes);
   in.n_slots = int64_t(ua.slot_nb.size());
   in.n_segments = S;
   in.n_dof_external = m.n_ext_cells * dim;
@@ -653,11 +657,14 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
   return guarded([&] {
     check_mesh(mesh);
     JFNK_REQUIRE(bytes, JFNK_E_ARG, "null output");
-    JFNK_REQUIRE(op >= 0 && op <= 2, JFNK_E_ARG, "workspace_size: op must be 0, 1 or 2");
+    JFNK_REQUIRE(op >= 0 && op <= 3, JFNK_E_ARG, "workspace_size: op must be 0, 1, 2 or 3");
     Carver c(nullptr);
     FvWork fw;
     fw.carve(c, mesh);
-    if (op >= 1) {
+    if (op == 3) {
+      (void)c.take<double>(size_t(mesh->dev.n_cells) * mesh->dev.dim);   // R(u - eps v)
+      (void)c.take<double>(mesh->n_seg());                                // -eps
+    } else if (op >= 1) {
       JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
       JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG64, JFNK_E_ARG,
                    "workspace_size: unknown preconditioner");
@@ -709,6 +716,33 @@ jfnk_status jfnk_jv(jfnk_mesh* mesh, double load, const double* d_u, const doubl
       Ru = fw.ru;
     }
     jv_into(mesh, d_u, Ru, d_v, eps, d_Jv, fw, nullptr, s);
+    if (eps_used) {
+      JFNK_HIP(hipMemcpyAsync(mesh->pinned, fw.eps, sizeof(double) * mesh->n_seg(), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipStreamSynchronize(s));
+      std::memcpy(eps_used, mesh->pinned, sizeof(double) * mesh->n_seg());
+    }
+  });
+}
+
+jfnk_status jfnk_jv_central(jfnk_mesh* mesh, double load, const double* d_u, const double* d_v, double eps,
+                            double* d_Jv, double* eps_used, void* d_work, void* stream) {
+  return guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_ptr(d_v, "v");
+    check_ptr(d_Jv, "Jv");
+    check_work(d_work);
+    JFNK_REQUIRE(d_Jv != d_u && d_Jv != d_v, JFNK_E_ARG, "jv_central: output aliases an input");
+    JFNK_REQUIRE(std::isfinite(eps) && std::isfinite(load), JFNK_E_ARG, "jv_central: eps/load not finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh);
+    CentralFd cfd;
+    cfd.rm = c.take<double>(size_t(mesh->dev.n_cells) * mesh->dev.dim);
+    cfd.eps_neg = c.take<double>(mesh->n_seg());
+    fw.setup_uniform(s, load, mesh->any_small);
+    jv_into(mesh, d_u, nullptr, d_v, eps, d_Jv, fw, nullptr, s, nullptr, false, &cfd);
     if (eps_used) {
       JFNK_HIP(hipMemcpyAsync(mesh->pinned, fw.eps, sizeof(double) * mesh->n_seg(), hipMemcpyDeviceToHost, s));
       JFNK_HIP(hipStreamSynchronize(s));
@@ -778,6 +812,8 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
                  "newton: bad tolerance");
     JFNK_REQUIRE(opts->line_search == 0 || opts->line_search == 1, JFNK_E_ARG, "newton: line_search must be 0 or 1");
     JFNK_REQUIRE(opts->max_backtrack <= 60, JFNK_E_ARG, "newton: max_backtrack must be <= 60");
+    JFNK_REQUIRE(opts->central_below >= 0 && std::isfinite(opts->central_below), JFNK_E_ARG,
+                 "newton: central_below must be finite and >= 0");
     check_opts(opts->gmres);
     const int S = mesh->n_seg();
     std::vector<int> inc(S);
@@ -829,8 +865,7 @@ void set_preconditioner_inertia(jfnk_mesh* m, double dt, hipStream_t s) {
       for (int64_t c = 0; c < g.host.n_cells; ++c)
         diag[g.cell_off + c] -= 2.25 * g.mat.rho * g.host.vol[c] / (dt * dt);
   }
-  std::vector<double> dinv(diag.size());
-  for (size_t c = 0; c < diag.size(); ++c) dinv[c] = 1.0 / diag[c];
+  const std::vector<double> dinv = jacobi_inverse(diag, h.pc_sym, h.dim);
   JFNK_HIP(hipMemcpyAsync(m->b_pc_dinv.p, dinv.data(), dinv.size() * sizeof(double), hipMemcpyHostToDevice, s));
   JFNK_HIP(hipStreamSynchronize(s));
   m->pc_diag_eff = dt > 0 ? std::move(diag) : std::vector<double>();
@@ -980,6 +1015,40 @@ jfnk_status jfnk_newton_solve_batch(jfnk_mesh* mesh, const int32_t* n_increments
                                     const jfnk_newton_opts* opts, double* d_u, jfnk_stats* stats,
                                     jfnk_status* seg_status, void* d_work, void* stream) {
   return newton_common(mesh, n_increments, opts, d_u, stats, seg_status, d_work, stream);
+}
+
+jfnk_status jfnk_segregated_solve(jfnk_mesh* mesh, const jfnk_segregated_opts* opts, double* d_u,
+                                  jfnk_stats* stats, void* d_work, void* stream) {
+  jfnk_status st = JFNK_OK;
+  jfnk_status g = guarded([&] {
+    check_mesh(mesh);
+    check_ptr(d_u, "u");
+    check_work(d_work);
+    JFNK_REQUIRE(opts, JFNK_E_ARG, "segregated: null options");
+    JFNK_REQUIRE(mesh->n_seg() == 1, JFNK_E_ARG, "segregated: single-mesh handles only");
+    JFNK_REQUIRE(opts->n_increments >= 1 && opts->max_outer_it >= 1 && opts->max_inner_it >= 1, JFNK_E_ARG,
+                 "segregated: n_increments, max_outer_it and max_inner_it must be >= 1");
+    JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->inner_rtol > 0 && opts->inner_rtol < 1,
+                 JFNK_E_ARG, "segregated: bad tolerance");
+    JFNK_REQUIRE(opts->precond == JFNK_PC_JACOBI || amg_precond(opts->precond), JFNK_E_ARG,
+                 "segregated: precond must be JACOBI, AMG32 or AMG64");
+    JFNK_REQUIRE(!amg_precond(opts->precond) || (opts->cheb_degree >= 1 && opts->cheb_degree <= 16), JFNK_E_ARG,
+                 "segregated: cheb_degree must lie in [1, 16]");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c(d_work);
+    FvWork fw;
+    fw.carve(c, mesh);
+    fw.zero_counters(s);
+    KrylovWork kw;
+    kw.carve(c, mesh, 1, precond_work_floats(mesh, opts->precond));
+    set_preconditioner_inertia(mesh, mesh->src.dt, s);
+    jfnk_stats sv{};
+    segregated_solve(mesh, *opts, d_u, fw, kw, s, sv, st);
+    if (stats) *stats = sv;
+    if (st == JFNK_E_NOT_CONVERGED) set_last_error("segregated: outer iteration limit reached");
+    if (st == JFNK_E_NAN) set_last_error("segregated: residual became NaN/Inf");
+  });
+  return g != JFNK_OK ? g : st;
 }
 
 }  // extern "C"

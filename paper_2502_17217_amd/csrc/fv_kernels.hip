@@ -342,11 +342,13 @@ struct GradChunk {
 
 // Slots of cell c in its slice of the mesh's slot arrays (ids in the
 // source's numbering); |Gamma_f| from the per-slot copy when mg is given,
-// else gathered through the slot's face number.
+// else gathered through the slot's face number.  bface(k): the boundary
+// face of boundary slot k.
 struct SliceSlots {
   const int32_t* ids;
   int s0, lane, width;
   const double* mg = nullptr;
+  __device__ __forceinline__ int bface(const MeshDev& m, int k) const { return m.slot_fc[s0 + k * kSlice + lane]; }
   template <int CH>
   __device__ __forceinline__ void load(const MeshDev& m, int k0, GradChunk<CH>& gc) const {
     if (mg != nullptr) {
@@ -380,6 +382,8 @@ struct HaloSlots {
   const int16_t* loc;
   const double* mg;
   int nh, i, width;
+  const int32_t* fc;  // boundary faces of the boundary slots (meshes with symmetry faces)
+  __device__ __forceinline__ int bface(const MeshDev&, int k) const { return fc[k * nh + i]; }
   template <int CH>
   __device__ __forceinline__ void load(const MeshDev&, int k0, GradChunk<CH>& gc) const {
 #pragma unroll
@@ -390,6 +394,33 @@ struct HaloSlots {
     }
   }
 };
+
+// Symmetry face bf of a cell with value wP (Eq. leastSquaresGrad, its
+// symmetry sum): the mirror image at d_s = 2 h n, h = d_b . n, with value
+// R wP, so G_P += |Gamma| n n and the sum += -(|Gamma| / h) (n . wP) n n.
+// Other boundary faces add nothing.
+template <int D>
+__device__ __forceinline__ void symmetry_lsq(const MeshDev& m, int bf, const double (&wP)[D], double (&Gs)[D][D],
+                                             double (&M)[D][D]) {
+  const double* r = m.bface + size_t(bf) * kBfaceRec;
+  if (int(r[9]) != kBcSymm) return;
+  double n[D], mg = 0, h = 0, wn = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    n[q] = r[6 + q];
+    mg = fma(r[q], n[q], mg);
+    h = fma(r[3 + q], n[q], h);
+    wn = fma(wP[q], n[q], wn);
+  }
+  const double a = -(mg / h) * wn;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      Gs[i][j] = fma(mg * n[i], n[j], Gs[i][j]);
+      M[i][j] = fma(a * n[i], n[j], M[i][j]);
+    }
+}
 
 // Least-squares gradient (Eq. leastSquaresGrad with the weight |Gamma_f| in
 // the sum and in G_P) of the cell with id self in the source, its slots read
@@ -418,7 +449,10 @@ __device__ __forceinline__ void lsq_gradient(const MeshDev& m, const Src& src, c
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-      if (nb[k] < 0) continue;
+      if (nb[k] < 0) {
+        if (m.has_symm && nb[k] == kSlotBoundary) symmetry_lsq<D>(m, sl.bface(m, k0 + k), wP, Gs, M);
+        continue;
+      }
       double d[D], dd = 0;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
@@ -619,14 +653,48 @@ __device__ __forceinline__ void load_bface(const MeshDev& m, int bf, double (&r)
 }
 
 // Force on boundary face r of cell P: displacement faces Gamma . sigma_P
-// plus the Rhie-Chow term against load * u_bar; traction faces
+// plus the Rhie-Chow term against load * u_bar; symmetry faces the internal
+// face force against the mirror image of P (Eq. symm: centroid x_P + 2 h n,
+// value R wP, gradient R grad wP R, weight 1/2); traction faces
 // load |Gamma| T_bar and pressure faces -load p Gamma (stored pre-multiplied).
 template <int D, int LAW>
 __device__ __forceinline__ void boundary_face_force(const Law& law, const double (&r)[kBfaceRec], double load,
                                                     const double (&wP)[D], const double (&gP)[D][D],
                                                     double (&f)[D]) {
   const int type = int(r[9]);
-  if (type == kBcDisp) {
+  if (type == kBcSymm) {
+    double G[D], n[D], xA[D], xB[D], wB[D], gB[D][D], gn[D], ng[D];
+    double h = 0, wn = 0, ngn = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      G[q] = r[q];
+      n[q] = r[6 + q];
+      h = fma(r[3 + q], n[q], h);
+      wn = fma(wP[q], n[q], wn);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      gn[i] = 0;
+      ng[i] = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        gn[i] = fma(gP[i][j], n[j], gn[i]);
+        ng[i] = fma(n[j], gP[j][i], ng[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) ngn = fma(n[i], gn[i], ngn);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      xA[i] = 0.0;
+      xB[i] = 2.0 * h * n[i];
+      wB[i] = fma(-2.0 * wn, n[i], wP[i]);
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        gB[i][j] = gP[i][j] - 2.0 * gn[i] * n[j] - 2.0 * n[i] * ng[j] + 4.0 * ngn * n[i] * n[j];
+    }
+    internal_face_force<D, LAW>(law, G, 0.5, xA, xB, wP, wB, gP, gB, f);
+  } else if (type == kBcDisp) {
     double G[D], db[D], ub[D], t[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -1219,7 +1287,8 @@ __global__ __launch_bounds__(kFvBlock, JFNK_FUSED_MINWAVES) void k_jv_fused(Mesh
         for (int b = 0; b < D; ++b) gl[(a * D + b) * S + threadIdx.x] = gP[a][b];
     }
     for (int i = threadIdx.x; i < nh; i += kFvBlock) {
-      const HaloSlots hi{m.h1_loc + size_t(h0) * W, m.h1_mg + size_t(h0) * W, nh, i, W};
+      const HaloSlots hi{m.h1_loc + size_t(h0) * W, m.h1_mg + size_t(h0) * W, nh, i, W,
+                         m.h1_fc != nullptr ? m.h1_fc + size_t(h0) * W : nullptr};
       double wH[D], gH[D][D];
       lsq_gradient<D, kFusedChunk>(m, gsrc, hi, kFvBlock + i, wH, gH);
 #pragma unroll

@@ -154,8 +154,9 @@ constexpr int kSlotPad = -2;
 // boundary-face record {Gamma(3), d_b(3), value(3), type}
 constexpr int kFaceRec = 4;
 constexpr int kBfaceRec = 10;
-// boundary type codes in the record
-constexpr int kBcDisp = 1, kBcTrac = 2, kBcPres = 3;
+// boundary type codes in the record (a symmetry record holds
+// {Gamma, d_b, unit normal, type})
+constexpr int kBcDisp = 1, kBcTrac = 2, kBcPres = 3, kBcSymm = 4;
 
 // Per-segment constants (one segment = one mesh of a batch).
 struct SegInfo {
@@ -180,6 +181,8 @@ struct MeshDev {
   int32_t n_int;             // union internal faces
   int32_t n_seg;
   int32_t law_mask;          // bit 0: linear-elastic, bit 1: neo-Hookean, bit 2: St. Venant-Kirchhoff segment
+  int32_t has_symm;          // some boundary face is a symmetry plane (its record type kBcSymm)
+  int32_t pad_symm_;
   const int32_t* slice_ptr;  // [n_slices + 1], in slots (multiples of kSlice)
   const int32_t* slot_nb;    // neighbour cell, kSlotBoundary or kSlotPad
   const int32_t* slot_fc;    // internal: face (owner side) or ~face (neighbour side); boundary: bface
@@ -234,6 +237,7 @@ struct MeshDev {
   const int32_t* h2_cells;   // [h2_ptr[n_tiles]]
   const int16_t* h1_loc;     // [halo total * h1_width]
   const double* h1_mg;       // [halo total * h1_width]
+  const int32_t* h1_fc;      // [halo total * h1_width] boundary face of a boundary slot (has_symm only)
 };
 
 // Per-call, per-segment device scalars.
@@ -264,6 +268,9 @@ struct HostMesh {
   std::vector<int32_t> slice_ptr, slot_nb, slot_fc;
   std::vector<double> pc_diag;      // approximate Jacobian, scalar diagonal (alpha_pc)
   std::vector<double> pc_off;       // per internal face off-diagonal coefficient
+  // symmetry faces: per-component addition to the diagonal, [n_cells][dim]
+  // (the diagonal of the n n block); empty when the mesh has none
+  std::vector<double> pc_sym;
   int64_t bandwidth = 0;
   bool tiled = false;               // cell order is in compact tiles whose halos fit the LDS budget
   int64_t tile_halo_max = 0;
@@ -277,6 +284,10 @@ struct Material {
 
 Material make_material(const jfnk_material& m);
 void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm);
+// Inverse of the approximate Jacobian's diagonal for the Jacobi
+// preconditioner: [n] from the scalar diagonal, or [dim][n] when sym (the
+// symmetry faces' per-component additions, [n][dim]) is not empty.
+std::vector<double> jacobi_inverse(const std::vector<double>& diag, const std::vector<double>& sym, int dim);
 
 // Host arrays of a batch union, ready for upload.
 // Host vector whose resize leaves new elements of trivial type unset: large
@@ -310,12 +321,13 @@ struct UnionArrays {
   std::vector<int16_t> h1_loc;
   std::vector<int32_t> h2_ptr, h2_cells, bnd_ptr, bnd_face, bnd_loc, slot_code;
   std::vector<double> h1_mg, slot_mg;
+  std::vector<int32_t> h1_fc;
   // faces_max: largest internal face list of a tile; bnd_max: largest
   // boundary list; ent_max: largest internal + boundary list
   int64_t halo_max = 0, faces_max = 0, bnd_max = 0, ent_max = 0, h2_max = 0, h1_width = 0;
   HostVec<double> xc, face, magG, bface;  // sized without zero fill, written in full
   std::vector<double> vol;                  // cell volumes (0 on padding cells)
-  std::vector<double> pc_dinv;
+  std::vector<double> pc_dinv;              // [n] or, with symmetry faces, [dim][n]
   std::vector<SegInfo> seg;
 };
 
@@ -422,7 +434,7 @@ struct StepGraphs {
   const void* work = nullptr;
   const double* u = nullptr;
   const double* Ru = nullptr;
-  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0, left = -1;
+  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0, left = -1, central = -1;
   double eps = 0;
   std::vector<hipGraphExec_t> exec;  // one per chunk of steps (null until captured)
   void clear();
@@ -447,7 +459,7 @@ struct jfnk_mesh {
   jfnk::DevBuf b_slice_ptr, b_slot_nb, b_slot_fc, b_xc, b_fG, b_fw, b_magG, b_bface, b_ext, b_pc_dinv,
       b_seg_of_block, b_seg, b_block_first, b_slot_loc, b_halo_ptr, b_halo_cells, b_slot_code, b_bnd_ptr, b_bnd_face, b_bnd_loc, b_fbeg,
       b_face_loc, b_in_ptr, b_in_face, b_in_loc, b_h2_ptr, b_h2_cells, b_h1_loc, b_h1_mg,
-      b_slot_mg;
+      b_slot_mg, b_h1_fc;
   double* pinned = nullptr;         // pinned host scalars for D2H reads
   size_t pinned_doubles = 0;
   bool pinned_owned = true;
@@ -458,6 +470,9 @@ struct jfnk_mesh {
   std::vector<double> pc_diag_eff;       // J_tilde diagonal with the inertia term (empty: host.pc_diag)
   jfnk::AmgHierarchy* amg = nullptr;     // FP32 hierarchy (JFNK_PC_AMG32)
   jfnk::AmgHierarchy* amg64 = nullptr;   // FP64 hierarchy (JFNK_PC_AMG64)
+  jfnk::DevBuf b_seg_ad, b_seg_ao;       // -J_tilde for the segregated solver: diagonal, face off-diagonals
+  bool seg_jt_ready = false;
+  double seg_jt_dt = 0;                  // inertia time step included in b_seg_ad
   jfnk::Profiler prof;
   jfnk::StepGraphs graphs;
   jfnk::Tuning tune;

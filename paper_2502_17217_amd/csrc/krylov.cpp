@@ -42,6 +42,8 @@ __global__ void k_fill(double* d, int64_t n, double v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = v;
 }
 
+}  // namespace
+
 // Per-segment squared norms of x (device scratch kw.nrm, column 0).
 void seg_norms2(jfnk_mesh* m, const SegLayout& L, const double* x, FvWork& fw, KrylovWork& kw,
                 const int32_t* act, hipStream_t s, std::vector<double>& out) {
@@ -68,8 +70,6 @@ void upload_doubles(jfnk_mesh* m, const std::vector<double>& v, double* d, hipSt
   JFNK_HIP(hipMemcpyAsync(d, p, sizeof(double) * v.size(), hipMemcpyHostToDevice, s));
   JFNK_HIP(hipStreamSynchronize(s));
 }
-
-}  // namespace
 
 SegLayout layout_of(const jfnk_mesh* m) {
   SegLayout L;
@@ -109,8 +109,13 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
 }
 
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
-             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu, bool ru_surface) {
+             FvWork& fw, const int32_t* active, hipStream_t s, const double* uu, bool ru_surface,
+             const CentralFd* cfd) {
   Profiler& p = m->prof;
+  if (cfd != nullptr) {
+    jv_central(m, u, v, eps, Jv, fw, active, s, uu, *cfd);
+    return;
+  }
   if (m->src.active() && !ru_surface) {
     // the finite difference runs on the surface terms only: the volume
     // terms are affine in u, their derivative is added exactly below
@@ -139,6 +144,47 @@ void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, d
   if (m->src.dt > 0) launch_inertia_jv(m, sc, v, Jv, s);
 }
 
+// (R(u + eps v) - R(u - eps v)) / (2 eps) with the cube-root step: the
+// forward-difference step times eps_mach^(-1/6), or eps as given.
+void jv_central(jfnk_mesh* m, const double* u, const double* v, double eps, double* Jv, FvWork& fw,
+                const int32_t* active, hipStream_t s, const double* uu, const CentralFd& cfd) {
+  Profiler& p = m->prof;
+  const int S = m->n_seg();
+  int t = p.on ? p.begin(0, s) : -1;
+  if (eps > 0) {
+    fill_device(fw.eps, S, eps, s);
+    blas_central_eps(fw.eps, cfd.eps_neg, S, 1.0, s);
+  } else {
+    launch_eps_fused(layout_of(m), m->any_large, u, uu, 1, v, active, fw.partials, fw.eps_tickets(), fw.eps, s);
+    blas_central_eps(fw.eps, cfd.eps_neg, S, kCentralStepFactor, s);
+  }
+  if (t >= 0) p.end(t, s);
+  // surface terms at u - eps v, then at u + eps v against them
+  const SegScalars scm{cfd.eps_neg, fw.load_ptr(), active, fw.load1};
+  const SegScalars scp{fw.eps, fw.load_ptr(), active, fw.load1};
+  if (m->dev.lds_kernels == 2) {
+    t = p.on ? p.begin(2, s) : -1;
+    launch_fused(m->dev, u, v, scm, nullptr, cfd.rm, s);
+    launch_fused(m->dev, u, v, scp, cfd.rm, Jv, s);
+    if (t >= 0) p.end(t, s);
+  } else {
+    t = p.on ? p.begin(1, s) : -1;
+    launch_gradient(m->dev, u, v, scm, fw.grad, s);
+    if (t >= 0) p.end(t, s);
+    t = p.on ? p.begin(2, s) : -1;
+    launch_flux(m->dev, fw.grad, scm, nullptr, cfd.rm, s);
+    if (t >= 0) p.end(t, s);
+    t = p.on ? p.begin(1, s) : -1;
+    launch_gradient(m->dev, u, v, scp, fw.grad, s);
+    if (t >= 0) p.end(t, s);
+    t = p.on ? p.begin(2, s) : -1;
+    launch_flux(m->dev, fw.grad, scp, cfd.rm, Jv, s);
+    if (t >= 0) p.end(t, s);
+  }
+  blas_lincomb(0.5, Jv, 0.0, Jv, Jv, int64_t(m->dev.n_cells) * m->dev.dim, s);
+  if (m->src.dt > 0) launch_inertia_jv(m, scp, v, Jv, s);
+}
+
 void StepGraphs::clear() {
   for (hipGraphExec_t& e : exec)
     if (e) (void)hipGraphExecDestroy(e);
@@ -158,17 +204,19 @@ void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const doub
                    const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, int j0, int j1, hipStream_t s,
                    int n_aug = 0) {
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
+  const CentralFd cfd{kw.rm, kw.eps_neg};
+  const CentralFd* c = o.fd_central ? &cfd : nullptr;
   for (int j = j0; j < j1; ++j) {
     double* Vj = kw.V + size_t(j) * n;
     double* Zj = kw.Z + size_t(j) * n;
     if (o.left) {
-      jv_into(m, u, Ru, Vj, o.eps, Zj, fw, kw.act, s, kw.uu, ru_surface);
+      jv_into(m, u, Ru, Vj, o.eps, Zj, fw, kw.act, s, kw.uu, ru_surface, c);
       precond_apply(m, o.precond, o.cheb_degree, Zj, kw.w, kw, s);
     } else {
       // augmentation directions occupy slots restart - augment .. of Z
       const int a = j - (o.restart - o.augment);
       if (a < 0 || a >= n_aug) precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
-      jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface);
+      jv_into(m, u, Ru, Zj, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface, c);
     }
     Profiler& p = m->prof;
     const int t = p.on ? p.begin(4, s) : -1;
@@ -195,6 +243,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   const SegLayout L = layout_of(m);
   const double t0 = now_ms();
   std::vector<char> part = part_in.empty() ? std::vector<char>(S, 1) : part_in;
+  const CentralFd cfd{kw.rm, kw.eps_neg};
   out.assign(S, GmresSeg());
   upload_flags(m, part, kw.act, s);
   // with volume terms the J v of every step differences the surface terms
@@ -232,7 +281,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   if (x_is_zero) {
     blas_lincomb(1.0, o.left ? kw.Z : b, 0.0, b, kw.r, n, s);
   } else {
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface, o.fd_central ? &cfd : nullptr);
     for (int g = 0; g < S; ++g) out[g].jv += part[g];
     blas_lincomb(1.0, b, -1.0, kw.w, kw.r, n, s);
     if (o.left) {
@@ -259,7 +308,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
     const void* work = static_cast<const void*>(kw.V);
     if (sg.work != work || sg.u != u || sg.Ru != Ru || sg.restart != mr || sg.precond != o.precond ||
         sg.cheb != o.cheb_degree || sg.chunk != K || sg.eps != o.eps || sg.max_it != o.max_it ||
-        sg.left != o.left) {
+        sg.left != o.left || sg.central != o.fd_central) {
       sg.clear();
       sg.work = work;
       sg.u = u;
@@ -271,6 +320,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       sg.eps = o.eps;
       sg.max_it = o.max_it;
       sg.left = o.left;
+      sg.central = o.fd_central;
       sg.exec.assign(n_chunks, nullptr);
     }
   }
@@ -375,7 +425,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       }
       if (t >= 0) p.end(t, s);
     }
-    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s, kw.uu, ru_surface);
+    jv_into(m, u, Ru, x, o.eps, kw.w, fw, G.ran, s, kw.uu, ru_surface, o.fd_central ? &cfd : nullptr);
     {
       Profiler& p = m->prof;
       const int t = p.on ? p.begin(5, s) : -1;
@@ -518,6 +568,11 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_inc, const jfnk_newton
       if (pending) continue;
       break;
     }
+    // central differences once some segment is within central_below of its target
+    go.fd_central = o.gmres.fd_central;
+    if (o.central_below > 0)
+      for (int g = 0; g < S; ++g)
+        if (part[g] && rn[g] <= o.central_below * r0[g]) go.fd_central = 1;
     // J du = -R on the segments that need a step (du = 0 elsewhere)
     blas_lincomb(-1.0, kw.R, 0.0, kw.R, kw.b, n, s);
     fill_device(kw.du, n, 0.0, s);

@@ -310,7 +310,7 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
                "mesh: null patch array");
   for (int32_t p = 0; p < d.n_patches; ++p) {
     const jfnk_patch& pt = d.patches[p];
-    JFNK_REQUIRE(pt.type >= 1 && pt.type <= 3, JFNK_E_ARG,
+    JFNK_REQUIRE(pt.type >= 1 && pt.type <= 4, JFNK_E_ARG,
                  "mesh: patch " + std::to_string(p) + " has an unknown type");
     JFNK_REQUIRE(pt.start >= ni && pt.size >= 0 && pt.start + pt.size <= nf, JFNK_E_ARG,
                  "mesh: patch " + std::to_string(p) + " face range outside the boundary faces");
@@ -571,6 +571,7 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   hm.bface.assign(nb * kBfaceRec, 0.0);
   hm.bown.resize(nb);
   std::vector<double> bdiag(nb, 0.0);  // a displacement face's diagonal term
+  std::vector<char> bsym(nb, 0);       // symmetry face (its diagonal block is aKp |Gamma| / h n n)
   parallel_for((nb + kGeomChunk - 1) / kGeomChunk, [&](int64_t chunk, int) {
     for (int64_t j = chunk * kGeomChunk; j < std::min(nb, (chunk + 1) * kGeomChunk); ++j) {
       int64_t b = bperm[j], f = ni + b;
@@ -591,6 +592,14 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
       } else if (btype[b] == JFNK_BC_TRACTION) {
         r[6] = mg * v[0]; r[7] = mg * v[1]; r[8] = mg * v[2];   // |Gamma| T_bar
         r[9] = kBcTrac;
+      } else if (btype[b] == JFNK_BC_SYMMETRY) {
+        // the cell's mirror image lies at x_P + 2 h n, h = d_b . n
+        double h = dot(db, g) / mg;
+        JFNK_REQUIRE(h > 0, JFNK_E_MESH, "mesh: symmetry " + s_face(f) + " has d.n <= 0");
+        r[6] = g.x / mg; r[7] = g.y / mg; r[8] = g.z / mg;        // unit normal
+        r[9] = kBcSymm;
+        bdiag[j] = aKp * mg / h;
+        bsym[j] = 1;
       } else {
         r[6] = -v[0] * g.x; r[7] = -v[0] * g.y; r[8] = -v[0] * g.z;  // -p Gamma
         r[9] = kBcPres;
@@ -627,12 +636,22 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
   const int64_t cell_chunks = (nc + kGeomChunk - 1) / kGeomChunk;
 
   // ---- approximate-Jacobian diagonal: minus the cell's face coefficients ----
+  // A symmetry face's block, the derivative of the compact term's symmetry
+  // sum, -2 aKp |Delta_s| |Gamma| / |d_s| n n = -aKp |Gamma| / h n n, keeps
+  // its diagonal per component (exact for planes normal to an axis).
   hm.pc_diag.assign(nc, 0.0);
+  const bool any_sym = std::find(bsym.begin(), bsym.end(), 1) != bsym.end();
+  if (any_sym) hm.pc_sym.assign(size_t(nc) * dim, 0.0);
   parallel_for(cell_chunks, [&](int64_t chunk, int) {
     for (int64_t c = chunk * kGeomChunk; c < std::min(nc, (chunk + 1) * kGeomChunk); ++c) {
       double s = 0.0;
       for (int32_t k = cnt[c]; k < cnt[c + 1]; ++k) {
         const int32_t fc = sfc[k];
+        if (snb[k] == kSlotBoundary && bsym[fc]) {
+          const double* r = &hm.bface[size_t(fc) * kBfaceRec];
+          for (int q = 0; q < dim; ++q) hm.pc_sym[size_t(c) * dim + q] -= bdiag[fc] * r[6 + q] * r[6 + q];
+          continue;
+        }
         s -= snb[k] == kSlotBoundary ? bdiag[fc] : hm.pc_off[fc >= 0 ? fc : ~fc];
       }
       hm.pc_diag[c] = s;
@@ -644,7 +663,15 @@ void build_host_mesh(const jfnk_mesh_desc& d, const Material& mat, HostMesh& hm)
     for (int64_t c = chunk * kGeomChunk; c < std::min(nc, (chunk + 1) * kGeomChunk); ++c) {
       double g[6] = {0, 0, 0, 0, 0, 0};
       for (int32_t k = cnt[c]; k < cnt[c + 1]; ++k) {
-        if (snb[k] == kSlotBoundary) continue;
+        if (snb[k] == kSlotBoundary) {
+          if (!bsym[sfc[k]]) continue;
+          // the mirror image: |Gamma| n n
+          const double* r = &hm.bface[size_t(sfc[k]) * kBfaceRec];
+          const double mgs = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+          const double e[6] = {r[6] * r[6], r[6] * r[7], r[6] * r[8], r[7] * r[7], r[7] * r[8], r[8] * r[8]};
+          for (int q = 0; q < 6; ++q) g[q] += mgs * e[q];
+          continue;
+        }
         const int64_t j = sfc[k] >= 0 ? sfc[k] : ~sfc[k];
         const double* r = &hm.face[j * kFaceRec];
         V3 gf = dim == 3 ? V3{r[0], r[1], r[2]} : V3{r[0], r[1], 0.0};
@@ -736,6 +763,9 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
   U.fnb.resize(face);
   U.pc_off.resize(face);
   U.pc_diag.assign(N, -1.0);
+  bool any_sym = false;
+  for (int s = 0; s < S; ++s) any_sym = any_sym || !m.segs[s].host.pc_sym.empty();
+  if (any_sym) U.pc_sym.assign(size_t(N) * dim, 0.0);
   U.bandwidth = 0;
   ua.xc.resize(size_t(N) * dim);   // segments write their cells and zero their padding
   ua.vol.assign(N, 0.0);
@@ -771,6 +801,8 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       for (int k = 0; k < dim; ++k) ua.xc[(co + c) * dim + k] = h.xc[c * dim + k];
       ua.vol[co + c] = h.vol[c];
       U.pc_diag[co + c] = h.pc_diag[c];
+      if (!h.pc_sym.empty())
+        for (int k = 0; k < dim; ++k) U.pc_sym[(co + c) * dim + k] = h.pc_sym[c * dim + k];
       ua.ext[co + c] = int32_t(g.ext_off + h.old_of_new[c]);
     }
     for (int64_t j = 0; j < h.n_int; ++j) {
@@ -847,6 +879,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       ua.h1_width = std::max<int64_t>(ua.h1_width, (ua.slice_ptr[k + 1] - ua.slice_ptr[k]) / kSlice);
     ua.h1_loc.clear();
     ua.h1_mg.clear();
+    ua.h1_fc.clear();
     ua.slot_mg.assign(ua.slot_nb.size(), 0.0);
     const int64_t n_slots = int64_t(ua.slot_nb.size());
     parallel_for((n_slots + 16 * kGeomChunk - 1) / (16 * kGeomChunk), [&](int64_t chunk, int) {
@@ -875,6 +908,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       std::vector<int32_t> halo, ring2, in_face, in_loc, bnd_face, bnd_loc;
       std::vector<int16_t> h1_loc;
       std::vector<double> h1_mg;
+      std::vector<int32_t> h1_fc;
       int32_t n_ent = 0;
     };
     std::vector<TileLists> tl(static_cast<size_t>(n_blocks));
@@ -921,6 +955,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
         const int64_t nh = int64_t(halo.size()), W = ua.h1_width;
         o.h1_loc.assign(size_t(nh * W), int16_t(kSlotPad));
         o.h1_mg.assign(size_t(nh * W), 0.0);
+        o.h1_fc.assign(size_t(nh * W), 0);
         const int32_t nh32 = int32_t(nh);
         auto local = [&](int32_t cell) -> int32_t {
           if (cell / kFvBlock == t) return int32_t(cell - c0);
@@ -938,6 +973,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
               o.h1_mg[e] = ua.magG[fc >= 0 ? fc : ~fc];
             } else {
               o.h1_loc[e] = int16_t(nb);
+              if (nb == kSlotBoundary) o.h1_fc[e] = fc;
             }
           });
       }
@@ -990,6 +1026,7 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
       ua.h2_max = std::max<int64_t>(ua.h2_max, int64_t(o.ring2.size()));
       ua.h1_loc.insert(ua.h1_loc.end(), o.h1_loc.begin(), o.h1_loc.end());
       ua.h1_mg.insert(ua.h1_mg.end(), o.h1_mg.begin(), o.h1_mg.end());
+      ua.h1_fc.insert(ua.h1_fc.end(), o.h1_fc.begin(), o.h1_fc.end());
       ua.in_face.insert(ua.in_face.end(), o.in_face.begin(), o.in_face.end());
       ua.in_loc.insert(ua.in_loc.end(), o.in_loc.begin(), o.in_loc.end());
       ua.in_ptr[t + 1] = int32_t(ua.in_face.size());
@@ -1004,8 +1041,20 @@ void build_union(jfnk_mesh& m, UnionArrays& ua) {
     JFNK_REQUIRE(ua.halo_max <= tile_halo_limit(dim), JFNK_E_MESH, "mesh: tile halo exceeds the LDS budget");
     JFNK_REQUIRE(ua.ent_max < 32768, JFNK_E_MESH, "mesh: too many faces inside a tile");
   }
-  ua.pc_dinv.resize(N);
-  for (int64_t c = 0; c < N; ++c) ua.pc_dinv[c] = 1.0 / U.pc_diag[c];
+  ua.pc_dinv = jacobi_inverse(U.pc_diag, U.pc_sym, dim);
+}
+
+std::vector<double> jacobi_inverse(const std::vector<double>& diag, const std::vector<double>& sym, int dim) {
+  const size_t n = diag.size();
+  if (sym.empty()) {
+    std::vector<double> out(n);
+    for (size_t c = 0; c < n; ++c) out[c] = 1.0 / diag[c];
+    return out;
+  }
+  std::vector<double> out(n * dim);
+  for (int q = 0; q < dim; ++q)
+    for (size_t c = 0; c < n; ++c) out[q * n + c] = 1.0 / (diag[c] + sym[c * dim + q]);
+  return out;
 }
 
 }  // namespace jfnk

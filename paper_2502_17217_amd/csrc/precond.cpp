@@ -38,7 +38,7 @@ void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, 
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
   const int32_t* gate = gated ? kw.gd.nact : nullptr;
   if (precond == JFNK_PC_JACOBI) {
-    blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, s, gate);
+    blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, m->dev.has_symm != 0, s, gate);
   } else if (amg_precond(precond)) {
     amg_apply(m, precond == JFNK_PC_AMG64, cheb_degree, r, z, kw.pc, s, gate);
   } else {

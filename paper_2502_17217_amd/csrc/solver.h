@@ -11,6 +11,12 @@ namespace jfnk {
 
 SegLayout layout_of(const jfnk_mesh* m);
 void fill_device(double* d, int64_t n, double value, hipStream_t s);
+// Per-segment squared norms of x, read back to the host (waits on s).
+void seg_norms2(jfnk_mesh* m, const SegLayout& L, const double* x, FvWork& fw, KrylovWork& kw,
+                const int32_t* act, hipStream_t s, std::vector<double>& out);
+// Host values / flags to the device through the pinned staging area (waits on s).
+void upload_flags(jfnk_mesh* m, const std::vector<char>& flag, int32_t* d_act, hipStream_t s);
+void upload_doubles(jfnk_mesh* m, const std::vector<double>& v, double* d, hipStream_t s);
 
 // R(u) into R with the per-segment load factors in fw.load (device).
 void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const int32_t* active,
@@ -21,9 +27,19 @@ void residual_into(jfnk_mesh* m, const double* u, double* R, FvWork& fw, const i
 // uu (may be null): per-segment |u|^2, when already known.  With volume
 // terms set on the mesh (body force, inertia), Ru is the full R(u) unless
 // ru_surface is true, in which case it is R(u) without its volume terms.
+// Central difference (R(u + eps v) - R(u - eps v)) / (2 eps): the regions
+// it uses (R(u - eps v) and -eps per segment); Ru is then not used.
+struct CentralFd {
+  double* rm = nullptr;
+  double* eps_neg = nullptr;
+};
+// eps_mach^(1/3) / eps_mach^(1/2): the automatic central step from the forward one
+constexpr double kCentralStepFactor = 406.3746693038589;
 void jv_into(jfnk_mesh* m, const double* u, const double* Ru, const double* v, double eps, double* Jv,
              FvWork& fw, const int32_t* active, hipStream_t s, const double* uu = nullptr,
-             bool ru_surface = false);
+             bool ru_surface = false, const CentralFd* cfd = nullptr);
+void jv_central(jfnk_mesh* m, const double* u, const double* v, double eps, double* Jv, FvWork& fw,
+                const int32_t* active, hipStream_t s, const double* uu, const CentralFd& cfd);
 
 // ---- volume terms (source_kernels.hip) ----
 // out = in + S(u) (add) or out = in - S(u): S = load f_b Omega - rho Omega a_BDF2(u)
@@ -53,6 +69,10 @@ struct GmresSeg {
 void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* b, double* x,
                  bool x_is_zero, const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, hipStream_t s,
                  const std::vector<char>& part, std::vector<GmresSeg>& out, double* t_ms);
+
+// Segregated quasi-Newton iteration with J_tilde (single-mesh handles).
+void segregated_solve(jfnk_mesh* m, const jfnk_segregated_opts& o, double* u, FvWork& fw, KrylovWork& kw,
+                      hipStream_t s, jfnk_stats& st, jfnk_status& status);
 
 // Newton-Raphson with per-segment load increments; per-segment stats.
 void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk_newton_opts& o,

@@ -87,6 +87,8 @@ struct KrylovWork {
   int32_t* act = nullptr; // [n_seg] active flags
   double* stage = nullptr;  // [3 n_seg] per-cycle values uploaded by the host
   double* uu = nullptr;     // [n_seg] |u|^2 of the state of the current linear solve
+  double* rm = nullptr;     // [n_dof] R(u - eps v) of a central-difference J v
+  double* eps_neg = nullptr;  // [n_seg] -eps of a central-difference J v
   GmresDev gd;            // device Arnoldi bookkeeping (shares fac and act)
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
@@ -109,6 +111,8 @@ struct KrylovWork {
     act = c.take<int32_t>(S);
     stage = c.take<double>(size_t(3) * S);
     uu = c.take<double>(S);
+    rm = c.take<double>(n_dof);
+    eps_neg = c.take<double>(S);
     gd.mr = restart;
     gd.H = c.take<double>(size_t(S) * restart * (restart + 1));
     gd.cs = c.take<double>(size_t(S) * restart);

@@ -19,7 +19,7 @@ OK, E_ARG, E_MESH, E_OOM, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_NAN, E_BREAKDOWN
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_OOM", -4: "E_HIP", -5: "E_NOT_CONVERGED",
                 -6: "E_DIVERGED", -7: "E_NAN", -8: "E_BREAKDOWN", -9: "E_BUSY"}
-BC = {"displacement": 1, "traction": 2, "pressure": 3}
+BC = {"displacement": 1, "traction": 2, "pressure": 3, "symmetry": 4}
 LAW = {"linear_elastic": 0, "neo_hookean": 1, "st_venant_kirchhoff": 2}
 PC_NONE, PC_JACOBI, PC_AMG32, PC_AMG64 = 0, 1, 2, 3
 PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32, "amg64": PC_AMG64}
@@ -57,14 +57,21 @@ class jfnk_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
                 ("eps", C.c_double), ("step_chunk", C.c_int32), ("graphs", C.c_int32),
-                ("left", C.c_int32), ("augment", C.c_int32)]
+                ("left", C.c_int32), ("augment", C.c_int32), ("fd_central", C.c_int32)]
 
 
 class jfnk_newton_opts(C.Structure):
     _fields_ = [("n_increments", C.c_int32), ("max_newton_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("eta", C.c_double), ("gmres", jfnk_gmres_opts),
                 ("dtol", C.c_double), ("line_search", C.c_int32), ("max_backtrack", C.c_int32),
-                ("inc_begin", C.c_int32), ("inc_end", C.c_int32), ("stol", C.c_double)]
+                ("inc_begin", C.c_int32), ("inc_end", C.c_int32), ("stol", C.c_double),
+                ("central_below", C.c_double)]
+
+
+class jfnk_segregated_opts(C.Structure):
+    _fields_ = [("n_increments", C.c_int32), ("max_outer_it", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("inner_rtol", C.c_double), ("max_inner_it", C.c_int32),
+                ("precond", C.c_int32), ("cheb_degree", C.c_int32)]
 
 
 class jfnk_stats(C.Structure):
@@ -123,6 +130,8 @@ def _load():
         "jfnk_set_body_force": [vp, vp, vp],
         "jfnk_set_inertia": [vp, d, vp, vp, vp, vp, vp],
         "jfnk_dynamic_step": [vp, d, i32, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp, vp, vp, vp, vp],
+        "jfnk_segregated_solve": [vp, C.POINTER(jfnk_segregated_opts), vp, vp, vp, vp],
+        "jfnk_jv_central": [vp, d, vp, vp, d, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -361,6 +370,19 @@ def jv(mesh, load, u, Ru, v, eps, Jv, work, stream=None, return_eps=False):
     return (Jv, e[0]) if mesh.n_segments == 1 else (Jv, list(e))
 
 
+def jv_central(mesh, load, u, v, eps, Jv, work, stream=None, return_eps=False):
+    """Central-difference J v (R(u + eps v) - R(u - eps v)) / (2 eps) into Jv
+    (workspace op 3); with return_eps also the step(s) used."""
+    e = (C.c_double * mesh.n_segments)()
+    _check(_lib.jfnk_jv_central(mesh.handle, float(load), _dptr(u, mesh.n_dof, "u"), _dptr(v, mesh.n_dof, "v"),
+                                float(eps), _dptr(Jv, mesh.n_dof, "Jv"),
+                                C.cast(e, C.c_void_p) if return_eps else None, work.c, _stream(stream)),
+           "jfnk_jv_central")
+    if not return_eps:
+        return Jv
+    return (Jv, e[0]) if mesh.n_segments == 1 else (Jv, list(e))
+
+
 def jv_noalloc(mesh, load, u, Ru, v, eps, Jv, stream=None):
     """J v like jv(), with the library's fixed device scratch instead of a
     workspace (no device allocation; calls overlapping on one GPU race)."""
@@ -406,17 +428,17 @@ def dynamic_step(mesh, dt, opts, u, u_prev, v, v_prev, a, work, predictor=True, 
 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
-               step_chunk=0, graphs=2, left=0, augment=0):
+               step_chunk=0, graphs=2, left=0, augment=0, fd_central=0):
     if isinstance(precond, str):
         precond = PRECOND[precond]
     return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs,
-                           int(left), int(augment))
+                           int(left), int(augment), int(fd_central))
 
 
 def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, dtol=0.0,
-                line_search=0, max_backtrack=0, inc_begin=0, inc_end=0, stol=0.0, **gm):
+                line_search=0, max_backtrack=0, inc_begin=0, inc_end=0, stol=0.0, central_below=0.0, **gm):
     return jfnk_newton_opts(n_increments, max_newton_it, rtol, atol, eta, gmres_opts(**gm), dtol,
-                            line_search, max_backtrack, inc_begin, inc_end, stol)
+                            line_search, max_backtrack, inc_begin, inc_end, stol, central_below)
 
 
 def gmres(mesh, load, u, Ru, b, x, opts, work, stream=None, allow=(E_NOT_CONVERGED, E_BREAKDOWN)):
@@ -436,6 +458,23 @@ def newton_solve(mesh, opts, u, work, stream=None, allow=(E_NOT_CONVERGED,)):
     _check(s, "jfnk_newton_solve", allow)
     out = [x.as_dict() for x in st]
     return s, (out[0] if mesh.n_segments == 1 else out)
+
+
+def segregated_opts(n_increments=1, max_outer_it=100000, rtol=1e-6, atol=1e-50, inner_rtol=0.9,
+                    max_inner_it=200, precond="amg32", cheb_degree=3):
+    pc = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    return jfnk_segregated_opts(n_increments, max_outer_it, rtol, atol, inner_rtol, max_inner_it, pc, cheb_degree)
+
+
+def segregated_solve(mesh, opts, u, work, stream=None, allow=(E_NOT_CONVERGED,)):
+    """The segregated quasi-Newton iteration with J_tilde (single mesh);
+    returns (status, stats: newton_it = outer iterations, gmres_it = CG
+    iterations)."""
+    st = jfnk_stats()
+    s = _lib.jfnk_segregated_solve(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), C.byref(st),
+                                   work.c, _stream(stream))
+    _check(s, "jfnk_segregated_solve", allow)
+    return s, st.as_dict()
 
 
 def newton_solve_batch(mesh, opts, u, work, n_increments=None, stream=None, allow=(E_NOT_CONVERGED,)):

@@ -18,7 +18,7 @@ import torch
 
 import meshgen as mg
 from oracle.fv import residual as o_residual
-from oracle.jacobian import jv_fd, eps_walker_pernice, jv_complex_step
+from oracle.jacobian import jv_fd, eps_walker_pernice, jv_complex_step, jv_fd_central, eps_central
 
 from gpu_common import Pair, jittered, with_bcs, to_dev
 
@@ -108,6 +108,31 @@ def test_jv_parity_and_eps(pair):
     Jv2 = torch.empty_like(ud)
     jfnk.jv(pair.gm, load, ud, None, vd, eps_o, Jv2, pair.work)
     assert torch.equal(Jv, Jv2)
+
+
+def test_jv_central_parity(pair):
+    """Central-difference J v: the automatic step equals the oracle's, the
+    product with the same step matches the oracle's central difference, and
+    it is closer to the exact product than the forward difference."""
+    jfnk = pair.jfnk
+    u = _state(pair, 5, 1.0)
+    v = np.random.default_rng(6).standard_normal(pair.n)
+    load = 0.8
+    ud, vd = pair.internal(u), pair.internal(v)
+    work3 = jfnk.make_workspace(pair.gm, 3)
+    J = torch.empty_like(ud)
+    _, eps_g = jfnk.jv_central(pair.gm, load, ud, vd, 0.0, J, work3, return_eps=True)
+    eps_c = eps_central(u, v)
+    assert eps_g == pytest.approx(eps_c, rel=1e-13)
+    Jo, _ = jv_fd_central(u, v, pair.pr, load, eps=eps_c)
+    jfnk.jv_central(pair.gm, load, ud, vd, eps_c, J, work3)
+    Jg = pair.external(J)
+    rel = np.linalg.norm(Jg - Jo) / np.linalg.norm(Jo)
+    exact = jv_complex_step(u, v, pair.pr, load)
+    ec = np.linalg.norm(Jg - exact) / np.linalg.norm(exact)
+    print("central jv rel err vs oracle", rel, "vs exact", ec)
+    assert rel <= 1e-6
+    assert ec <= 1e-8
 
 
 def test_jv_zero_direction(pair):

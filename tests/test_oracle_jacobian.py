@@ -17,7 +17,7 @@ import pytest
 import meshgen as mg
 from oracle.fv import prepare, residual
 from oracle.jacobian import (jv_fd, jv_complex_step, brute_force_jacobian, eps_walker_pernice,
-                             approximate_jacobian_scalar)
+                             approximate_jacobian_scalar, jv_fd_central, eps_central)
 
 
 def _small(dim, law, jitter=0.2, seed=3):
@@ -59,6 +59,33 @@ def test_fd_jv_scales_with_eps_for_nonlinear_law():
     e1 = np.linalg.norm(jv_fd(u, v, pr, eps=1e-3)[0] - exact)
     e2 = np.linalg.norm(jv_fd(u, v, pr, eps=5e-4)[0] - exact)
     assert 1.8 < e1 / e2 < 2.2
+
+
+def test_central_difference_is_second_order():
+    """The central difference: error second order in eps (a halving of eps
+    quarters it), exact for the linear law, and at its automatic step far
+    closer to the exact product than the forward difference."""
+    pr = _small(3, "neo_hookean")
+    n = pr["nc"] * 3
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(n) * 0.05
+    v = rng.standard_normal(n)
+    exact = jv_complex_step(u, v, pr)
+    e1 = np.linalg.norm(jv_fd_central(u, v, pr, eps=2e-3)[0] - exact)
+    e2 = np.linalg.norm(jv_fd_central(u, v, pr, eps=1e-3)[0] - exact)
+    assert 3.6 < e1 / e2 < 4.4
+    c, eps = jv_fd_central(u, v, pr)
+    assert eps == np.cbrt(2.0 ** -52) * np.sqrt(1.0 + np.linalg.norm(u)) / np.linalg.norm(v)
+    f, _ = jv_fd(u, v, pr)
+    ec = np.linalg.norm(c - exact) / np.linalg.norm(exact)
+    ef = np.linalg.norm(f - exact) / np.linalg.norm(exact)
+    assert ec < 1e-9 and ec < 0.05 * ef, (ec, ef)
+    # hand value of the step: |u| = 3, |v| = 4 -> eps_mach^(1/3) * 2 / 4
+    assert eps_central(np.array([3.0, 0.0]), np.array([0.0, 4.0])) == np.cbrt(2.0 ** -52) / 2
+    # the linear law is affine in u: any step gives J v to rounding
+    pl = _small(3, "linear_elastic")
+    el = jv_complex_step(u, v, pl)
+    assert np.linalg.norm(jv_fd_central(u, v, pl, eps=0.3)[0] - el) <= 1e-12 * np.linalg.norm(el)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
