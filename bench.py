@@ -400,7 +400,12 @@ def segregated_vs_jfnk(log):
     same FP32 AMG, inner factor 0.9), both to |R| <= 1e-6 |R(u_0)| (the
     paper's rtol), timed on the host clock around each solve (device mesh
     and preconditioner set up beforehand, untimed).  speedup = segregated
-    time / JFNK time, as the paper defines it."""
+    time / JFNK time, as the paper defines it.  The segregated iteration
+    is capped at 5,000 outer iterations per increment: on the bending
+    cantilever it is still far from 1e-6 there (the speedup is then a lower
+    bound, with the residual reached), and on the nearly incompressible
+    neo-Hookean cantilever it diverges, like the paper's segregated runs
+    marked as diverged."""
     import numpy as np
     import torch
     import meshgen as mg
@@ -415,9 +420,6 @@ def segregated_vs_jfnk(log):
     cm = mg.cantilever_mesh(200, 20, 2, tau=75.0)
     cases.append(("3-D cantilever 200x20x2 (bending), linear elastic, nu 0.3", cm,
                   mg.Material("linear_elastic", 1e6, 0.3), 1))
-    cm = mg.cantilever_mesh(200, 20, 2, tau=75.0)
-    cases.append(("3-D cantilever 200x20x2 (bending), linear elastic, nu 0.45", cm,
-                  mg.Material("linear_elastic", 1e6, 0.45), 1))
     cn = mg.cantilever_mesh(100, 10, 2, tau=400.0)
     cases.append(("3-D cantilever 100x10x2, neo-Hookean, 4 increments", cn, mg.Material("neo_hookean", 1e6, 0.45), 4))
     out = []
@@ -435,7 +437,7 @@ def segregated_vs_jfnk(log):
         torch.cuda.synchronize()
         tj = time.perf_counter() - t
         u2 = torch.zeros_like(u1)
-        so = jfnk.segregated_opts(n_increments=ninc, max_outer_it=50000, rtol=1e-6, inner_rtol=0.9,
+        so = jfnk.segregated_opts(n_increments=ninc, max_outer_it=5000, rtol=1e-6, inner_rtol=0.9,
                                   precond="amg32")
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -447,8 +449,11 @@ def segregated_vs_jfnk(log):
                    jfnk=dict(status=jfnk.STATUS_NAMES.get(st1, st1), seconds=tj, newton_it=s1["newton_it"],
                              gmres_it=s1["gmres_it"]),
                    segregated=dict(status=jfnk.STATUS_NAMES.get(st2, st2), seconds=ts, outer_it=s2["newton_it"],
-                                   cg_it=s2["gmres_it"]),
-                   speedup=ts / tj, rel_l2_between=diff)
+                                   cg_it=s2["gmres_it"],
+                                   rel_residual_reached=s2["res_final"] / max(s2["res0"], 1e-300)),
+                   speedup=ts / tj if st2 == jfnk.OK else None,
+                   speedup_lower_bound=ts / tj if st2 == jfnk.E_NOT_CONVERGED else None,
+                   rel_l2_between=diff if st2 == jfnk.OK else None)
         log("segregated vs JFNK: " + json.dumps(rec))
         out.append(rec)
         del w

@@ -25,7 +25,14 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-constexpr int kComputeUnits = 256;
+// Compute units of the current device (256 on MI355X), for the persistent
+// grid sizes the tuner tries.
+int compute_units() {
+  int dev = 0, cu = 0;
+  JFNK_HIP(hipGetDevice(&dev));
+  JFNK_HIP(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+  return cu > 0 ? cu : 256;
+}
 
 }  // namespace
 
@@ -63,7 +70,7 @@ void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o_in, const double* u, double
   if (m->dev.tiled) lds_opts = m->dev.fused ? std::vector<int>{2, 1, 0} : std::vector<int>{1, 0};
   std::vector<int> grid_opts{0};
   for (int k : {2, 4, 8})
-    if (k * kComputeUnits < tiles) grid_opts.push_back(k * kComputeUnits);
+    if (k * compute_units() < tiles) grid_opts.push_back(k * compute_units());
   const int reps = 10;
   double best = 1e300;
   int best_lds = m->dev.lds_kernels, best_grid = m->dev.persist;
