@@ -462,7 +462,7 @@ def segregated_vs_jfnk(log):
                         "inner factor 0.9), both to rtol 1e-6", "cases": out}
 
 
-def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12):
+def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, only=0):
     """The 1000x100x10 neo-Hookean cantilever solved to Newton rtol 1e-8 per
     increment (10 equal increments of the dead shear load), FGMRES(restart)
     with the FP32 AMG preconditioner.  Every increment is solved by its own
@@ -502,7 +502,7 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12):
         return float(torch.linalg.norm(Rp - Rg)) / r0
 
     incs, u_prev, t_total, status = [], np.zeros(gm.n_dof), 0.0, jfnk.OK
-    for k in range(1, N + 1):
+    for k in range(1, (min(only, N) if only > 0 else N) + 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
         st, stats = jfnk.newton_solve(gm, mk(k), u, w, allow=_FAILED)
@@ -701,6 +701,8 @@ def main():
                     help="skip the full cantilever solve (the J.v state is then the bending field)")
     ap.add_argument("--c3-restart", type=int, default=200, help="FGMRES restart length of the cantilever solve")
     ap.add_argument("--c3-increments", type=int, default=10)
+    ap.add_argument("--c3-only-increments", type=int, default=0,
+                    help="solve only the first K load increments (profiling runs; 0: all)")
     ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 jittered-block J.v leg")
     ap.add_argument("--c2-steps", type=int, default=300)
     ap.add_argument("--no-segregated", action="store_true", help="skip the segregated-vs-JFNK comparison")
@@ -751,11 +753,13 @@ def main():
     c3 = None
     state = "large-deflection bending field (tip 3 m), not a solved state"
     if not args.no_c3_solve:
-        c3, u_fin = c3_solve(gm, m, mat, args.c3_increments, args.c3_restart, log)
+        c3, u_fin = c3_solve(gm, m, mat, args.c3_increments, args.c3_restart, log, only=args.c3_only_increments)
         if u_fin is not None:
             ud = u_fin
             u_ext = gm.to_external(ud).cpu().numpy()
-            state = "converged state of the last load increment (solved above)"
+            k_last = len(c3["increments"])
+            state = ("converged state of the last load increment (solved above)" if k_last == args.c3_increments
+                     else "converged state of load increment %d of %d (solved above)" % (k_last, args.c3_increments))
     work = jfnk.make_workspace(gm, 0)
     Ru = torch.empty_like(ud)
     Jv = torch.empty_like(ud)
