@@ -185,7 +185,10 @@ def _plain_opts(jfnk, n_increments, rtol, eta, restart, max_it):
 
 
 def _fast_opts(jfnk, n_increments, rtol, eta, restart, max_it):
-    """FP32 aggregation-AMG / Chebyshev(3) preconditioner inside flexible GMRES."""
+    """FP32 aggregation-AMG / Chebyshev(3) preconditioner inside flexible GMRES
+    (FP64 Z basis: these meshes are small and launch-bound, so the FP32
+    basis's extra rounding launch per step would cost more than its memory
+    saves)."""
     return jfnk.newton_opts(n_increments=n_increments, max_newton_it=20, rtol=rtol, eta=eta,
                             restart=restart, max_it=max_it, precond="amg32", cheb_degree=3)
 
@@ -244,7 +247,7 @@ def _batched(jfnk, torch, problems, opts, restart):
         torch.cuda.synchronize()
         t = time.perf_counter()
         gm = jfnk.create_batch([problems[i]["mesh"] for i in idx], [problems[i]["material"] for i in idx])
-        w = jfnk.make_workspace(gm, 1, restart=restart, precond=jfnk.PC_AMG32)
+        w = jfnk.make_workspace(gm, 1, restart=restart, precond=opts.gmres.precond)
         u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
         st, stats, seg = jfnk.newton_solve_batch(gm, opts, u, w)
         ue = gm.to_external(u).cpu().numpy()
@@ -279,9 +282,10 @@ def _oracle_errors(problems, sols, n, log):
                              max_krylov_it=2000)
         errs.append(_rel(sols[i], uo))
         gm = jfnk.create_mesh(m, mat)
-        w = jfnk.make_workspace(gm, 1, restart=30, precond=jfnk.PC_AMG32)
+        ro = _fast_opts(jfnk, 1, 1e-4, 1e-6, 30, 20000)
+        w = jfnk.make_workspace(gm, 1, restart=30, precond=ro.gmres.precond)
         u = gm.to_internal(torch.as_tensor(np.ascontiguousarray(sols[i]), device="cuda"))
-        jfnk.newton_solve(gm, _fast_opts(jfnk, 1, 1e-4, 1e-6, 30, 20000), u, w, allow=_FAILED)
+        jfnk.newton_solve(gm, ro, u, w, allow=_FAILED)
         refined.append(_rel(gm.to_external(u).cpu().numpy(), uo))
         gm.close()
         del w
@@ -497,11 +501,15 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
     from paper_2502_17217_amd import jfnk
     from oracle.fv import prepare, residual
     N = n_increments
-    w = jfnk.make_workspace(gm, 1, restart=restart, precond=jfnk.PC_AMG32)
+    # the flexible-GMRES directions are stored in FP32 (same bits as the FP64
+    # basis with the FP32 V-cycle, checked on increment 1 below)
+    pc = "amg32+z32"
+    ws = {z: jfnk.workspace_size(gm, 1, restart, "amg32" + z) for z in ("", "+z32")}
+    w = jfnk.make_workspace(gm, 1, restart=restart, precond=pc)
     u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
-    mk = lambda k: jfnk.newton_opts(n_increments=N, max_newton_it=25, rtol=1e-8, eta=1e-3, restart=restart,
-                                    max_it=100000, precond="amg32", cheb_degree=3, line_search=line_search,
-                                    inc_begin=k, inc_end=k, stol=stol)
+    mk = lambda k, pc=pc: jfnk.newton_opts(n_increments=N, max_newton_it=25, rtol=1e-8, eta=1e-3,
+                                           restart=restart, max_it=100000, precond=pc, cheb_degree=3,
+                                           line_search=line_search, inc_begin=k, inc_end=k, stol=stol)
     pr = prepare(m, mat)
     w0 = jfnk.make_workspace(gm, 0)
     Rg, Rp = torch.empty_like(u), torch.empty_like(u)
@@ -537,20 +545,23 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
                    oracle_rel_residual=r_end / r_beg, oracle_gpu_gap_rel=gap,
                    tip_uy=float(ue.reshape(-1, 3)[:, 1].max()))
         incs.append(rec)
+        if k == 1:
+            u_inc1 = u.clone()
         log("C3 increment %d: %s" % (k, json.dumps(rec)))
         if st != jfnk.OK:
             status = st
             break
     report = {"workload": "neo-Hookean cantilever 1000x100x10 (1M cells), dead shear tau = 750 Pa in %d "
                           "increments, Newton rtol 1e-8 (or the step test |du| <= %g |u| at the FP64 rounding "
-                          "floor), eta 1e-3, FGMRES(%d) + FP32 AMG/Chebyshev(3), line search %s"
+                          "floor), eta 1e-3, FGMRES(%d) + FP32 AMG/Chebyshev(3), FP32 Z basis, line search %s"
                           % (N, stol, restart, "on" if line_search else "off"),
               "status": jfnk.STATUS_NAMES.get(status, status), "seconds": t_total,
               "increments": incs,
               "max_oracle_rel_residual": max(r["oracle_rel_residual"] for r in incs),
               "max_floor_rel": max(r["floor_rel"] for r in incs),
               "all_at_rtol_or_floor": all(r["at_rtol_or_floor"] for r in incs),
-              "tip_uy_m": incs[-1]["tip_uy"]}
+              "tip_uy_m": incs[-1]["tip_uy"],
+              "workspace_mb": {"fp64_z_basis": ws[""] / 1e6, "fp32_z_basis": ws["+z32"] / 1e6}}
     u_final = u.clone()
     # increment 1 again, profiled (direct launches, HIP events per kernel class)
     u.zero_()
@@ -572,6 +583,17 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
                   "other": prof["other"][0] / max(tot, 1e-9)}}
     log("C3 phase split (increment 1, profiled): " + json.dumps(report["phase_split_increment1"]))
     del w
+    # increment 1 once more with the FP64 Z basis: the same bits
+    w64 = jfnk.make_workspace(gm, 1, restart=restart, precond="amg32")
+    u.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    jfnk.newton_solve(gm, mk(1, "amg32"), u, w64, allow=_FAILED)
+    torch.cuda.synchronize()
+    report["increment1_fp64_z_basis"] = {"seconds": time.perf_counter() - t,
+                                         "same_bits_as_fp32_z_basis": bool(torch.equal(u, u_inc1))}
+    log("C3 increment 1 with the FP64 Z basis: " + json.dumps(report["increment1_fp64_z_basis"]))
+    del w64
     return report, (u_final if status == jfnk.OK else None)
 
 

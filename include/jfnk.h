@@ -183,7 +183,9 @@ jfnk_status jfnk_to_external(const jfnk_mesh* mesh, const double* d_in, double* 
 /* Workspace bytes for jfnk_residual / jfnk_jv (op = 0), for jfnk_gmres,
  * jfnk_newton_solve and jfnk_segregated_solve with the given restart length
  * and preconditioner (op = 1), for jfnk_dynamic_step (op = 2), or for
- * jfnk_jv_central (op = 3).  The caller allocates at least that many bytes
+ * jfnk_jv_central (op = 3).  precond may carry JFNK_PC_Z32 (ops 1 and 2),
+ * and the solve given this workspace must then carry it too (and the
+ * other way round).  The caller allocates at least that many bytes
  * of device memory, 256-byte aligned, and passes it as d_work. */
 jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t restart,
                                 int32_t precond, size_t* bytes);
@@ -233,6 +235,21 @@ jfnk_status jfnk_jv_noalloc(jfnk_mesh* mesh, double load, const double* d_u, con
 
 typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_AMG64 = 3 } jfnk_precond;
 
+/* Flag ORed into a preconditioner value (the GMRES options' precond, and
+ * the precond of jfnk_workspace_size, which must then carry it too): the
+ * directions z_j = P^{-1} v_j of the flexible GMRES (Section 3.2) are
+ * stored in FP32, halving that region of the workspace (restart * n_dof
+ * floats plus one FP64 vector instead of restart * n_dof doubles).  Each
+ * direction is rounded to FP32 when formed and its J v takes the rounded
+ * value, so the Arnoldi relation holds for the stored basis.  With AMG32 the
+ * V-cycle's output is already an FP32 value and the solve gives the same
+ * bits as with the FP64 basis; with JACOBI, AMG64 or NONE the rounding
+ * perturbs the preconditioner by one FP32 rounding (the solve stays
+ * flexible GMRES and converges to the same tolerance).  Right
+ * preconditioning without augmentation only (JFNK_E_ARG otherwise); not
+ * for jfnk_segregated_solve. */
+#define JFNK_PC_Z32 16
+
 /* GMRES options (Section 3.2; restarted, right preconditioned, classical
  * Gram-Schmidt applied twice).  The run stops when the true residual
  * |b - J x| <= max(rtol |b|, atol), after max_it Arnoldi steps, or on
@@ -255,6 +272,7 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_
  * last k of the restart directions of a cycle are the normalised
  * corrections x_c - x_{c-1} of the previous k cycles instead of
  * preconditioned basis vectors (graph replay is not used then).
+ * precond | JFNK_PC_Z32 stores the directions z_j in FP32 (see the flag).
  * fd_central = 1: every product J v is the central difference
  * (R(u + eps v) - R(u - eps v)) / (2 eps), second order in eps where the
  * forward difference of Eq. JF is first order, at the cost of one more

@@ -34,6 +34,13 @@ void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const d
 void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
                   double sign, double* w, const int32_t* active, hipStream_t s,
                   const int32_t* nk_seg = nullptr);
+// the same over a basis stored in FP32
+void blas_combine(const SegLayout& L, const float* V, int64_t ldv, int nk, const double* h, int ldh,
+                  double sign, double* w, const int32_t* active, hipStream_t s,
+                  const int32_t* nk_seg = nullptr);
+// zf = z rounded to FP32 (to nearest); back: also z = double(zf).  Skipped
+// entirely when gate is given and *gate == 0.
+void blas_round_fp32(double* z, float* zf, int64_t n, bool back, hipStream_t s, const int32_t* gate = nullptr);
 // y = scale[s] * x on each segment s
 void blas_scale_seg(const SegLayout& L, const double* x, const double* scale, double* y,
                     const int32_t* active, hipStream_t s);

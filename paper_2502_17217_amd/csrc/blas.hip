@@ -85,7 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_seg(SegLayout L, const double
 }
 
 // w += sign * sum_{k<nk} h[seg * ldh + k] V_k on the tile's segment
-__global__ __launch_bounds__(kBlock) void k_combine(SegLayout L, const double* __restrict__ V, int64_t ldv,
+// B: the basis element type (double, or float for an FP32 basis, each
+// element taken exactly to FP64 before its product).
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_combine(SegLayout L, const B* __restrict__ V, int64_t ldv,
                                                     int nk_all, const double* __restrict__ h, int ldh,
                                                     double sign, const int32_t* __restrict__ active,
                                                     const int32_t* __restrict__ nk_seg,
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(SegLayout L, const double* _
   for (int q = 0; q < L.dim; ++q) {
     const size_t o = size_t(q) * L.n_cells + c;
     double s = 0;
-    for (int k = 0; k < nk; ++k) s = fma(hs[k], V[k * ldv + o], s);
+    for (int k = 0; k < nk; ++k) s = fma(hs[k], double(V[k * ldv + o]), s);
     w[o] = fma(sign, s, w[o]);
   }
 }
@@ -154,6 +157,19 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ di
   }
 }
 
+// zf = z rounded to FP32 (to nearest); back: also z = zf, so that both hold
+// the same value.  Skipped when gate is given and *gate == 0.
+__global__ __launch_bounds__(kBlock) void k_round_fp32(double* __restrict__ z, float* __restrict__ zf, int64_t n,
+                                                       int back, const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+    const float f = float(z[i]);
+    zf[i] = f;
+    if (back) z[i] = double(f);
+  }
+}
+
 // Central-difference step from the forward one: eps *= factor, eps_neg = -eps.
 __global__ void k_central_eps(double* __restrict__ eps, double* __restrict__ eps_neg, int S, double factor) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,8 +212,20 @@ void blas_mdot(const SegLayout& L, const double* V, int64_t ldv, int nk, const d
 
 void blas_combine(const SegLayout& L, const double* V, int64_t ldv, int nk, const double* h, int ldh,
                   double sign, double* w, const int32_t* active, hipStream_t s, const int32_t* nk_seg) {
-  hipLaunchKernelGGL(k_combine, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign, active,
-                     nk_seg, w);
+  hipLaunchKernelGGL(k_combine<double>, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign,
+                     active, nk_seg, w);
+  JFNK_HIP(hipGetLastError());
+}
+
+void blas_combine(const SegLayout& L, const float* V, int64_t ldv, int nk, const double* h, int ldh,
+                  double sign, double* w, const int32_t* active, hipStream_t s, const int32_t* nk_seg) {
+  hipLaunchKernelGGL(k_combine<float>, dim3(L.n_blocks), dim3(kBlock), 0, s, L, V, ldv, nk, h, ldh, sign,
+                     active, nk_seg, w);
+  JFNK_HIP(hipGetLastError());
+}
+
+void blas_round_fp32(double* z, float* zf, int64_t n, bool back, hipStream_t s, const int32_t* gate) {
+  hipLaunchKernelGGL(k_round_fp32, dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, z, zf, n, back ? 1 : 0, gate);
   JFNK_HIP(hipGetLastError());
 }
 

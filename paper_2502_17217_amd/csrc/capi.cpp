@@ -76,8 +76,10 @@ void check_opts(const jfnk_gmres_opts& o) {
   JFNK_REQUIRE(o.restart >= 1 && o.restart < kMaxBasis, JFNK_E_ARG, "gmres: restart out of range");
   JFNK_REQUIRE(o.max_it >= 1, JFNK_E_ARG, "gmres: max_it must be >= 1");
   JFNK_REQUIRE(o.rtol >= 0 && o.atol >= 0, JFNK_E_ARG, "gmres: negative tolerance");
-  JFNK_REQUIRE(o.precond >= JFNK_PC_NONE && o.precond <= JFNK_PC_AMG64, JFNK_E_ARG,
+  JFNK_REQUIRE(pc_kind(o.precond) >= JFNK_PC_NONE && pc_kind(o.precond) <= JFNK_PC_AMG64, JFNK_E_ARG,
                "gmres: unknown preconditioner");
+  JFNK_REQUIRE(!pc_z32(o.precond) || (!o.left && !o.augment), JFNK_E_ARG,
+               "gmres: the FP32 Z basis needs right preconditioning without augmentation");
   JFNK_REQUIRE(!amg_precond(o.precond) || (o.cheb_degree >= 1 && o.cheb_degree <= 16), JFNK_E_ARG,
                "gmres: cheb_degree must lie in [1, 16]");
   JFNK_REQUIRE(o.step_chunk >= 0 && o.step_chunk <= o.restart, JFNK_E_ARG,
@@ -666,10 +668,10 @@ jfnk_status jfnk_workspace_size(const jfnk_mesh* mesh, int32_t op, int32_t resta
       (void)c.take<double>(mesh->n_seg());                                // -eps
     } else if (op >= 1) {
       JFNK_REQUIRE(restart >= 1 && restart < kMaxBasis, JFNK_E_ARG, "workspace_size: bad restart");
-      JFNK_REQUIRE(precond >= JFNK_PC_NONE && precond <= JFNK_PC_AMG64, JFNK_E_ARG,
+      JFNK_REQUIRE(pc_kind(precond) >= JFNK_PC_NONE && pc_kind(precond) <= JFNK_PC_AMG64, JFNK_E_ARG,
                    "workspace_size: unknown preconditioner");
       KrylovWork kw;
-      kw.carve(c, mesh, restart, precond_work_floats(mesh, precond));
+      kw.carve(c, mesh, restart, precond_work_floats(mesh, precond), pc_z32(precond));
       if (op == 2) (void)c.take<double>(size_t(mesh->dev.n_cells) * mesh->dev.dim);   // u^t of a transient step
     }
     *bytes = c.off;
@@ -772,7 +774,7 @@ jfnk_status jfnk_gmres(jfnk_mesh* mesh, double load, const double* d_u, const do
     fw.carve(c, mesh);
     fw.setup(s, load);
     KrylovWork kw;
-    kw.carve(c, mesh, opts->restart, precond_work_floats(mesh, opts->precond));
+    kw.carve(c, mesh, opts->restart, precond_work_floats(mesh, opts->precond), pc_z32(opts->precond));
     precond_setup(mesh, opts->precond, s);
     double t_ms[8] = {0};
     std::vector<GmresSeg> r;
@@ -828,7 +830,8 @@ static jfnk_status newton_common(jfnk_mesh* mesh, const int32_t* n_increments, c
     fw.carve(c, mesh);
     fw.zero_counters(s);
     KrylovWork kw;
-    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond),
+             pc_z32(opts->gmres.precond));
     set_preconditioner_inertia(mesh, mesh->src.dt, s);
     const double ts = now_ms();
     precond_setup(mesh, opts->gmres.precond, s);
@@ -959,7 +962,8 @@ jfnk_status jfnk_dynamic_step(jfnk_mesh* mesh, double dt, int32_t predictor, con
     fw.carve(c, mesh);
     fw.zero_counters(s);
     KrylovWork kw;
-    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond));
+    kw.carve(c, mesh, opts->gmres.restart, precond_work_floats(mesh, opts->gmres.precond),
+             pc_z32(opts->gmres.precond));
     double* un = c.take<double>(size_t(n));
     // u^t aside; the unknown starts from the predictor
     blas_lincomb(1.0, d_u, 0.0, d_u, un, n, s);
@@ -1030,8 +1034,8 @@ jfnk_status jfnk_segregated_solve(jfnk_mesh* mesh, const jfnk_segregated_opts* o
                  "segregated: n_increments, max_outer_it and max_inner_it must be >= 1");
     JFNK_REQUIRE(opts->rtol >= 0 && opts->atol >= 0 && opts->inner_rtol > 0 && opts->inner_rtol < 1,
                  JFNK_E_ARG, "segregated: bad tolerance");
-    JFNK_REQUIRE(opts->precond == JFNK_PC_JACOBI || amg_precond(opts->precond), JFNK_E_ARG,
-                 "segregated: precond must be JACOBI, AMG32 or AMG64");
+    JFNK_REQUIRE(!pc_z32(opts->precond) && (opts->precond == JFNK_PC_JACOBI || amg_precond(opts->precond)),
+                 JFNK_E_ARG, "segregated: precond must be JACOBI, AMG32 or AMG64");
     JFNK_REQUIRE(!amg_precond(opts->precond) || (opts->cheb_degree >= 1 && opts->cheb_degree <= 16), JFNK_E_ARG,
                  "segregated: cheb_degree must lie in [1, 16]");
     const hipStream_t s = static_cast<hipStream_t>(stream);

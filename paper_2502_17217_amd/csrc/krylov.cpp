@@ -208,11 +208,23 @@ void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const doub
   const CentralFd* c = o.fd_central ? &cfd : nullptr;
   for (int j = j0; j < j1; ++j) {
     double* Vj = kw.V + size_t(j) * n;
-    double* Zj = kw.Z + size_t(j) * n;
-    if (o.left) {
+    if (kw.z32) {
+      // FP32 basis (right preconditioning, no augmentation): z_j is formed in
+      // zd, rounded to FP32 into its slot, and J v takes the rounded value,
+      // the same number the solution update reads back.  The AMG32 V-cycle
+      // writes FP32 values already, so zd needs no rewrite then.
+      precond_apply(m, o.precond, o.cheb_degree, Vj, kw.zd, kw, s);
+      Profiler& p = m->prof;
+      const int t = p.on ? p.begin(3, s) : -1;
+      blas_round_fp32(kw.zd, kw.Zf + size_t(j) * n, n, pc_kind(o.precond) != JFNK_PC_AMG32, s, kw.gd.nact);
+      if (t >= 0) p.end(t, s);
+      jv_into(m, u, Ru, kw.zd, o.eps, kw.w, fw, kw.act, s, kw.uu, ru_surface, c);
+    } else if (o.left) {
+      double* Zj = kw.Z + size_t(j) * n;
       jv_into(m, u, Ru, Vj, o.eps, Zj, fw, kw.act, s, kw.uu, ru_surface, c);
       precond_apply(m, o.precond, o.cheb_degree, Zj, kw.w, kw, s);
     } else {
+      double* Zj = kw.Z + size_t(j) * n;
       // augmentation directions occupy slots restart - augment .. of Z
       const int a = j - (o.restart - o.augment);
       if (a < 0 || a >= n_aug) precond_apply(m, o.precond, o.cheb_degree, Vj, Zj, kw, s);
@@ -244,6 +256,9 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
   const double t0 = now_ms();
   std::vector<char> part = part_in.empty() ? std::vector<char>(S, 1) : part_in;
   const CentralFd cfd{kw.rm, kw.eps_neg};
+  JFNK_REQUIRE(kw.z32 == pc_z32(o.precond), JFNK_E_ARG, "gmres: workspace carved for another Z basis");
+  JFNK_REQUIRE(!kw.z32 || (!o.left && o.augment == 0), JFNK_E_ARG,
+               "gmres: the FP32 Z basis needs right preconditioning without augmentation");
   out.assign(S, GmresSeg());
   upload_flags(m, part, kw.act, s);
   // with volume terms the J v of every step differences the surface terms
@@ -420,6 +435,8 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
         upload_doubles(m, dfac, kw.stage, s);
         blas_scale_seg(L, kw.r, kw.stage, kw.Z + size_t(a0) * n, G.ran, s);
         n_aug = std::min(n_aug + 1, o.augment);
+      } else if (kw.z32) {
+        blas_combine(L, kw.Zf, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
       } else {
         blas_combine(L, kw.Z, n, mr, kw.y, kMaxBasis, 1.0, x, G.ran, s, G.kk);
       }

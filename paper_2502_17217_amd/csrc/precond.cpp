@@ -17,6 +17,7 @@ void amg_apply(jfnk_mesh* m, bool fp64, int cheb_degree, const double* r, double
                hipStream_t s, const int32_t* gate);
 
 size_t precond_work_floats(int64_t n_cells, int dim, int precond) {
+  precond = pc_kind(precond);
   if (precond == JFNK_PC_AMG32) return amg_work_floats(n_cells, dim);
   if (precond == JFNK_PC_AMG64) return 2 * amg_work_floats(n_cells, dim);
   return 0;
@@ -27,7 +28,7 @@ size_t precond_work_floats(const jfnk_mesh* m, int precond) {
 }
 
 void precond_setup(jfnk_mesh* m, int precond, hipStream_t s) {
-  if (amg_precond(precond)) amg_setup(m, precond == JFNK_PC_AMG64, s);
+  if (amg_precond(precond)) amg_setup(m, pc_kind(precond) == JFNK_PC_AMG64, s);
 }
 
 // The kernels return at once when gate (the count of segments still taking
@@ -37,6 +38,7 @@ void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, 
                    KrylovWork& kw, hipStream_t s, bool gated) {
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
   const int32_t* gate = gated ? kw.gd.nact : nullptr;
+  precond = pc_kind(precond);
   if (precond == JFNK_PC_JACOBI) {
     blas_jacobi(m->b_pc_dinv.as<double>(), r, z, m->dev.n_cells, m->dev.dim, m->dev.has_symm != 0, s, gate);
   } else if (amg_precond(precond)) {

@@ -140,9 +140,10 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   // measured, with margin); the hierarchy's actual bytes are checked after
   // its setup and any excess is added to the reservation
   const size_t amg_mats = amg_precond(o.gmres.precond)
-                              ? size_t(h.n_cells) * (o.gmres.precond == JFNK_PC_AMG64 ? 512 : 256)
+                              ? size_t(h.n_cells) * (pc_kind(o.gmres.precond) == JFNK_PC_AMG64 ? 512 : 256)
                               : 0;
-  const size_t foot = device_bytes_of(h) + solve_workspace_bytes(h.n_cells, h.dim, 1, o.gmres.restart, pcf) +
+  const bool z32 = pc_z32(o.gmres.precond);
+  const size_t foot = device_bytes_of(h) + solve_workspace_bytes(h.n_cells, h.dim, 1, o.gmres.restart, pcf, z32) +
                       amg_mats + size_t(h.n_cells) * h.dim * 16 + (size_t(1) << 20);
   info.footprint_bytes = int64_t(foot);
   if (foot > S->opts.hbm_budget) {
@@ -178,7 +179,7 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   } ctx_reset;
   finish_handle(*m, stream, clock_ms());
   DevBuf work, u, ue;
-  const size_t wbytes = solve_workspace_bytes(h.n_cells, h.dim, 1, o.gmres.restart, pcf);
+  const size_t wbytes = solve_workspace_bytes(h.n_cells, h.dim, 1, o.gmres.restart, pcf, z32);
   work.alloc(wbytes);
   u.alloc(sizeof(double) * h.n_cells * h.dim);
   ue.alloc(sizeof(double) * h.n_cells * h.dim);
@@ -188,7 +189,7 @@ void run_request(jfnk_server* S, Request* r, uint64_t ticket, hipStream_t stream
   fw.carve(c, m.get());
   fw.zero_counters(stream);
   KrylovWork kw;
-  kw.carve(c, m.get(), o.gmres.restart, pcf);
+  kw.carve(c, m.get(), o.gmres.restart, pcf, z32);
   precond_setup(m.get(), o.gmres.precond, stream);
   const size_t amg_real = amg_device_bytes(m->amg) + amg_device_bytes(m->amg64);
   if (amg_real > amg_mats) {

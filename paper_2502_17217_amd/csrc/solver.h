@@ -79,7 +79,11 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk
                   double* u, FvWork& fw, KrylovWork& kw, hipStream_t s, std::vector<jfnk_stats>& stats,
                   std::vector<jfnk_status>& status);
 
-inline bool amg_precond(int precond) { return precond == JFNK_PC_AMG32 || precond == JFNK_PC_AMG64; }
+// The preconditioner of a precond value, and whether it carries the FP32
+// Z-basis flag.
+inline int pc_kind(int precond) { return precond & ~JFNK_PC_Z32; }
+inline bool pc_z32(int precond) { return (precond & JFNK_PC_Z32) != 0; }
+inline bool amg_precond(int precond) { return pc_kind(precond) == JFNK_PC_AMG32 || pc_kind(precond) == JFNK_PC_AMG64; }
 // Preconditioner work region of a solve workspace, in floats (4-byte units).
 size_t precond_work_floats(const jfnk_mesh* m, int precond);
 size_t precond_work_floats(int64_t n_cells, int dim, int precond);

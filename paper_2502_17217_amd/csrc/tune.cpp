@@ -46,7 +46,7 @@ void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o_in, const double* u, double
   fw.carve(c, m);
   fw.setup(s, load);
   KrylovWork kw;
-  kw.carve(c, m, o_in.restart, precond_work_floats(m, o_in.precond));
+  kw.carve(c, m, o_in.restart, precond_work_floats(m, o_in.precond), pc_z32(o_in.precond));
   precond_setup(m, o_in.precond, s);
   const bool prof = m->prof.on;
   m->prof.on = false;

@@ -73,7 +73,10 @@ struct FvWork {
 // Additional regions used by the Krylov solver and Newton.
 struct KrylovWork {
   double* V = nullptr;    // [(m+1)][n_dof] orthonormal basis
-  double* Z = nullptr;    // [m][n_dof] preconditioned directions (flexible GMRES)
+  double* Z = nullptr;    // [m][n_dof] preconditioned directions (flexible GMRES), or null:
+  float* Zf = nullptr;    // [m][n_dof] the same in FP32 (Z-basis flag), with
+  double* zd = nullptr;   // [n_dof] the direction being formed, in FP64
+  bool z32 = false;       // the Z basis is Zf
   double* w = nullptr;    // [n_dof]
   double* r = nullptr;    // [n_dof]
   double* b = nullptr;    // [n_dof] Newton right-hand side
@@ -92,12 +95,18 @@ struct KrylovWork {
   GmresDev gd;            // device Arnoldi bookkeeping (shares fac and act)
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
-  void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f) {
-    carve(c, m->host.n_cells * m->host.dim, m->n_seg(), restart, pc_f);
+  void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f, bool z32 = false) {
+    carve(c, m->host.n_cells * m->host.dim, m->n_seg(), restart, pc_f, z32);
   }
-  void carve(Carver& c, int64_t n_dof, int S, int restart, size_t pc_f) {
+  void carve(Carver& c, int64_t n_dof, int S, int restart, size_t pc_f, bool z32 = false) {
     V = c.take<double>(size_t(restart + 1) * n_dof);
-    Z = c.take<double>(size_t(restart) * n_dof);
+    this->z32 = z32;
+    if (z32) {
+      Zf = c.take<float>(size_t(restart) * n_dof);
+      zd = c.take<double>(n_dof);
+    } else {
+      Z = c.take<double>(size_t(restart) * n_dof);
+    }
     w = c.take<double>(n_dof);
     r = c.take<double>(n_dof);
     b = c.take<double>(n_dof);
@@ -132,12 +141,12 @@ struct KrylovWork {
 };
 
 // Workspace bytes of a solve (op 1) on n cells of dimension dim in S segments.
-inline size_t solve_workspace_bytes(int64_t n, int dim, int S, int restart, size_t pc_floats) {
+inline size_t solve_workspace_bytes(int64_t n, int dim, int S, int restart, size_t pc_floats, bool z32 = false) {
   Carver c(nullptr);
   FvWork fw;
   fw.carve(c, n, dim, S);
   KrylovWork kw;
-  kw.carve(c, n * dim, S, restart, pc_floats);
+  kw.carve(c, n * dim, S, restart, pc_floats, z32);
   return c.off;
 }
 

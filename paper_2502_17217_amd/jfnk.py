@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_OOM", -4: "E_HIP", -5
 BC = {"displacement": 1, "traction": 2, "pressure": 3, "symmetry": 4}
 LAW = {"linear_elastic": 0, "neo_hookean": 1, "st_venant_kirchhoff": 2}
 PC_NONE, PC_JACOBI, PC_AMG32, PC_AMG64 = 0, 1, 2, 3
+PC_Z32 = 16  # ORed into a precond value: the flexible-GMRES directions stored in FP32
 PRECOND = {"none": PC_NONE, "jacobi": PC_JACOBI, "amg32": PC_AMG32, "amg64": PC_AMG64}
 
 
@@ -342,9 +343,19 @@ def create_batch(meshes, materials, stream=None):
     return Mesh(list(meshes), list(materials), stream)
 
 
+def _pc(precond):
+    """A precond value from an int or a name ("amg32", "jacobi+z32", ...)."""
+    if not isinstance(precond, str):
+        return int(precond)
+    base, _, flag = precond.partition("+")
+    if flag not in ("", "z32"):
+        raise ValueError("unknown preconditioner flag %r" % flag)
+    return PRECOND[base] | (PC_Z32 if flag else 0)
+
+
 def workspace_size(mesh, op=0, restart=30, precond=PC_JACOBI):
     n = C.c_size_t()
-    _check(_lib.jfnk_workspace_size(mesh.handle, op, restart, precond, C.byref(n)), "jfnk_workspace_size")
+    _check(_lib.jfnk_workspace_size(mesh.handle, op, restart, _pc(precond), C.byref(n)), "jfnk_workspace_size")
     return n.value
 
 
@@ -429,9 +440,7 @@ def dynamic_step(mesh, dt, opts, u, u_prev, v, v_prev, a, work, predictor=True, 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
                step_chunk=0, graphs=2, left=0, augment=0, fd_central=0):
-    if isinstance(precond, str):
-        precond = PRECOND[precond]
-    return jfnk_gmres_opts(restart, max_it, rtol, atol, precond, cheb_degree, eps, step_chunk, graphs,
+    return jfnk_gmres_opts(restart, max_it, rtol, atol, _pc(precond), cheb_degree, eps, step_chunk, graphs,
                            int(left), int(augment), int(fd_central))
 
 
@@ -462,7 +471,7 @@ def newton_solve(mesh, opts, u, work, stream=None, allow=(E_NOT_CONVERGED,)):
 
 def segregated_opts(n_increments=1, max_outer_it=100000, rtol=1e-6, atol=1e-50, inner_rtol=0.9,
                     max_inner_it=200, precond="amg32", cheb_degree=3):
-    pc = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    pc = _pc(precond)
     return jfnk_segregated_opts(n_increments, max_outer_it, rtol, atol, inner_rtol, max_inner_it, pc, cheb_degree)
 
 

@@ -43,6 +43,18 @@ def jfnk():
     return j
 
 
+def test_header_constants_match_binding(jfnk):
+    """The enum values and flags the binding passes are the header's."""
+    text = open(HEADER).read()
+    assert int(re.search(r"#define JFNK_PC_Z32 (\d+)", text).group(1)) == jfnk.PC_Z32
+    for name, val in re.findall(r"JFNK_PC_(NONE|JACOBI|AMG32|AMG64) = (\d+)", text):
+        assert getattr(jfnk, "PC_" + name) == int(val), name
+    assert jfnk._pc("amg32+z32") == jfnk.PC_AMG32 | jfnk.PC_Z32
+    assert jfnk._pc("jacobi") == jfnk.PC_JACOBI
+    with pytest.raises(ValueError):
+        jfnk._pc("amg32+z16")
+
+
 @pytest.mark.parametrize("kind", ["2d", "3d", "annulus"])
 def test_inspect_geometry_matches_oracle(jfnk, kind):
     if kind == "2d":
