@@ -184,13 +184,16 @@ def _plain_opts(jfnk, n_increments, rtol, eta, restart, max_it):
                             restart=restart, max_it=max_it, precond="amg64", cheb_degree=3, graphs=0)
 
 
+_ORTH = [1]   # the fast path's Arnoldi orthogonalisation (--orth)
+
+
 def _fast_opts(jfnk, n_increments, rtol, eta, restart, max_it):
     """FP32 aggregation-AMG / Chebyshev(3) preconditioner inside flexible GMRES
     (FP64 Z basis: these meshes are small and launch-bound, so the FP32
     basis's extra rounding launch per step would cost more than its memory
     saves)."""
     return jfnk.newton_opts(n_increments=n_increments, max_newton_it=20, rtol=rtol, eta=eta,
-                            restart=restart, max_it=max_it, precond="amg32", cheb_degree=3)
+                            restart=restart, max_it=max_it, precond="amg32", cheb_degree=3, orth=_ORTH[0])
 
 
 _FAILED = (-5, -6, -7, -8)   # not converged, diverged, NaN, breakdown: reported, not raised
@@ -480,7 +483,7 @@ def segregated_vs_jfnk(log):
                         "inner factor 0.9), both to rtol 1e-6", "cases": out}
 
 
-def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, only=0):
+def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, only=0, orth=0):
     """The 1000x100x10 neo-Hookean cantilever solved to Newton rtol 1e-8 per
     increment (10 equal increments of the dead shear load), FGMRES(restart)
     with the FP32 AMG preconditioner.  Every increment is solved by its own
@@ -509,7 +512,8 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
     u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
     mk = lambda k, pc=pc: jfnk.newton_opts(n_increments=N, max_newton_it=25, rtol=1e-8, eta=1e-3,
                                            restart=restart, max_it=100000, precond=pc, cheb_degree=3,
-                                           line_search=line_search, inc_begin=k, inc_end=k, stol=stol)
+                                           line_search=line_search, inc_begin=k, inc_end=k, stol=stol,
+                                           orth=orth)
     pr = prepare(m, mat)
     w0 = jfnk.make_workspace(gm, 0)
     Rg, Rp = torch.empty_like(u), torch.empty_like(u)
@@ -553,8 +557,9 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
             break
     report = {"workload": "neo-Hookean cantilever 1000x100x10 (1M cells), dead shear tau = 750 Pa in %d "
                           "increments, Newton rtol 1e-8 (or the step test |du| <= %g |u| at the FP64 rounding "
-                          "floor), eta 1e-3, FGMRES(%d) + FP32 AMG/Chebyshev(3), FP32 Z basis, line search %s"
-                          % (N, stol, restart, "on" if line_search else "off"),
+                          "floor), eta 1e-3, FGMRES(%d) + FP32 AMG/Chebyshev(3), FP32 Z basis, %s, line search %s"
+                          % (N, stol, restart, ("delayed reorthogonalisation" if orth else "Gram-Schmidt twice"),
+                             "on" if line_search else "off"),
               "status": jfnk.STATUS_NAMES.get(status, status), "seconds": t_total,
               "increments": incs,
               "max_oracle_rel_residual": max(r["oracle_rel_residual"] for r in incs),
@@ -742,7 +747,11 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 jittered-block J.v leg")
     ap.add_argument("--c2-steps", type=int, default=300)
     ap.add_argument("--no-segregated", action="store_true", help="skip the segregated-vs-JFNK comparison")
+    ap.add_argument("--orth", type=int, default=1,
+                    help="Arnoldi orthogonalisation of the fast path and the cantilever solve: 0 Gram-Schmidt "
+                         "twice, 1 delayed reorthogonalisation")
     args = ap.parse_args()
+    _ORTH[0] = args.orth
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (a large solve would "
               "shard by contiguous cell blocks with a halo exchange per J.v); run with --gpus 1",
@@ -789,7 +798,8 @@ def main():
     c3 = None
     state = "large-deflection bending field (tip 3 m), not a solved state"
     if not args.no_c3_solve:
-        c3, u_fin = c3_solve(gm, m, mat, args.c3_increments, args.c3_restart, log, only=args.c3_only_increments)
+        c3, u_fin = c3_solve(gm, m, mat, args.c3_increments, args.c3_restart, log, only=args.c3_only_increments,
+                             orth=args.orth)
         if u_fin is not None:
             ud = u_fin
             u_ext = gm.to_external(ud).cpu().numpy()

@@ -278,7 +278,17 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_
  * forward difference of Eq. JF is first order, at the cost of one more
  * residual pass; the automatic step is then
  * eps_mach^(1/3) sqrt(1 + |u|) / |v| (the step that balances its truncation
- * and rounding errors), an explicit eps is used as given. */
+ * and rounding errors), an explicit eps is used as given.
+ * orth: the Arnoldi orthogonalisation.  0: classical Gram-Schmidt applied
+ * twice (three passes over the basis per step, four reads of it).
+ * 1: classical Gram-Schmidt with delayed reorthogonalisation (DCGS2): each
+ * step reads the basis twice, once for the dots of the new vector J z_j and
+ * of the previous step's vector against the basis, once to reorthogonalise
+ * that previous vector and orthogonalise the new one; the Hessenberg column
+ * of step j is completed, and its Givens rotation taken, in step j + 1, so
+ * the solve notices convergence one J v later.  Same Krylov space and
+ * arithmetic precision; the iterates differ from orth = 0 by rounding.
+ * Right preconditioning only, restart <= 250 (JFNK_E_ARG otherwise). */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -292,6 +302,7 @@ typedef struct {
   int32_t left;
   int32_t augment;
   int32_t fd_central;
+  int32_t orth;
 } jfnk_gmres_opts;
 
 /* Newton options (Eq. NewtonRaphson, Section 3.3): per load increment

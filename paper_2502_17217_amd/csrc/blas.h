@@ -67,6 +67,17 @@ void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv,
                double* h, double* h2, double* nrm, double* partials, int32_t* tickets, int32_t* counters,
                const GmresDev& G, int j, int max_it, hipStream_t s);
 
+// Arnoldi step j with delayed reorthogonalisation (DCGS2): V_j holds the
+// previous step's vector orthogonalised once (unit computed norm), w = J z_j.
+// Completes Hessenberg column j-1 (its Givens step included), writes the
+// final v_j into V_j, orthogonalises w once against V_0..V_j (first-pass
+// column j) and leaves 1/|w| in G.fac for scaling w into V_{j+1}.
+// closing: only the completion of column j-1 (end of a cycle, j = restart).
+// partials2: a second region of n_blocks * kMaxBasis doubles.
+void dcgs_step(const SegLayout& L, bool any_large, double* V, int64_t ldv, int j, double* w, double* h, double* h2,
+               double* nrm, double* partials, double* partials2, int32_t* tickets, const GmresDev& G, int max_it,
+               bool closing, hipStream_t s);
+
 // eps[s] *= factor, eps_neg[s] = -eps[s] (central-difference step)
 void blas_central_eps(double* eps, double* eps_neg, int S, double factor, hipStream_t s);
 // z = D^{-1} r with one scalar per cell applied to every component, or one

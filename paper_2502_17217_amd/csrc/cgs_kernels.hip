@@ -14,6 +14,7 @@
 //   pass 2: w -= V h, then h2 = V^T w
 //   pass 3: w -= V h2, then |w|^2, and (when every segment is small) the
 //           device Givens update of each segment in its last tile.
+// and the two passes of the delayed-reorthogonalisation variant (DCGS2).
 #include "blas.h"
 #include "gmres_step_dev.h"
 #include "reduce_dev.h"
@@ -191,6 +192,244 @@ __global__ __launch_bounds__(kBlock) void k_cgs_last(SegLayout L, const double* 
     counters[0] = 0;
     counters[1] = 0;
   }
+}
+
+// ---- Gram-Schmidt with delayed reorthogonalisation (DCGS2) ----
+// Step j holds u = V_j, the basis vector of step j-1 orthogonalised once
+// and scaled to unit computed norm, and w = J z_j.  One read of V_0..V_j
+// gives the dots of both u and w against V_0..V_{j-1}; u's second
+// orthogonalisation u = alpha v_j + V a then completes column j-1 of the
+// Hessenberg matrix, and a second read forms v_j and w's first
+// orthogonalisation together.  Two reads of the basis per step instead of
+// four; the Givens step of column j-1 is taken in step j, and a closing
+// pass (dots of V_m only) completes the last column of a cycle.
+
+// Pass 1 of step j: tile sums of a_k = V_k . u and b_k = V_k . w (k < j),
+// c = u . w, d = u . u and |w|^2, from one read of V_0..V_j.  Columns: a,
+// then c, d, |w|^2 at j, j+1, j+2 of partials; b at 0..j-1 of partials2.
+// The last tile of a small segment finishes them into h[seg] and h2[seg].
+// w == null (closing pass): a and d only.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_dcgs_dots(SegLayout L, const double* __restrict__ V, int64_t ldv,
+                                                      int j, const double* __restrict__ w,
+                                                      const int32_t* __restrict__ act,
+                                                      double* __restrict__ partials,
+                                                      double* __restrict__ partials2,
+                                                      int32_t* __restrict__ tickets, double* __restrict__ h,
+                                                      double* __restrict__ h2) {
+  __shared__ double wa[4][kMaxBasis];
+  __shared__ double wb[4][kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (act[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool in = c < L.n_cells;
+  const bool has_w = w != nullptr;
+  double ui[D], wi[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = size_t(q) * L.n_cells + c;
+    ui[q] = in ? V[j * ldv + o] : 0.0;
+    wi[q] = (in && has_w) ? w[o] : 0.0;
+  }
+  for (int k0 = 0; k0 < j; k0 += 8) {
+    double aa[8], bb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) aa[k] = bb[k] = 0.0;
+    if (in) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const size_t o = size_t(q) * L.n_cells + c;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k0 + k < j) {
+            const double x = V[(k0 + k) * ldv + o];
+            aa[k] = fma(x, ui[q], aa[k]);
+            bb[k] = fma(x, wi[q], bb[k]);
+          }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k0 + k < j) {
+        const double sa = wave_sum(aa[k]);
+        const double sb = has_w ? wave_sum(bb[k]) : 0.0;
+        if (lane == 0) {
+          wa[wave][k0 + k] = sa;
+          wb[wave][k0 + k] = sb;
+        }
+      }
+  }
+  double cu = 0.0, du = 0.0, ww = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    cu = fma(ui[q], wi[q], cu);
+    du = fma(ui[q], ui[q], du);
+    ww = fma(wi[q], wi[q], ww);
+  }
+  cu = wave_sum(cu);
+  du = wave_sum(du);
+  ww = wave_sum(ww);
+  if (lane == 0) {
+    wa[wave][j] = cu;
+    wa[wave][j + 1] = du;
+    wa[wave][j + 2] = ww;
+  }
+  store_tile_sums(L, wa, j + 3, partials, blk);
+  store_tile_sums(L, wb, j, partials2, blk);
+  int first, n;
+  if (!small_segment(L, seg, first, n)) return;
+  if (!last_tile_of_segment(tickets + seg, n)) return;
+  // each wavefront finishes every fourth column
+  for (int k = wave; k < 2 * j + 3; k += 4) {
+    const bool A = k < j + 3;
+    const double t = segment_column_sum(L, A ? partials : partials2, first, n, A ? k : k - (j + 3));
+    if (lane == 0) {
+      if (A)
+        h[size_t(seg) * kMaxBasis + k] = t;
+      else
+        h2[size_t(seg) * kMaxBasis + k - (j + 3)] = t;
+    }
+  }
+}
+
+// Step j per segment (one workgroup over all segments), from a, c, d, |w|^2
+// (h[s]) and b (h2[s]).  For j > 0: alpha = sqrt(d - |a|^2) completes
+// column j-1 (rows += sigma a, subdiagonal sigma alpha, sigma its first-pass
+// subdiagonal) and takes its Givens step; d <= |a|^2 means u lies in the
+// span of the basis (a breakdown: subdiagonal 0, the segment stops).  Then,
+// unless the segment stops or last (closing pass), the first-pass column j
+// (rows b, diagonal h_jj = (c - a.b) / alpha), with alpha and h_jj kept in
+// nrm[4s+2], nrm[4s+3] for the update pass.  Step 0 has nothing to
+// complete: alpha = 1, h_00 = c.
+__global__ __launch_bounds__(kBlock) void k_dcgs_finalize(GmresDev G, int S, int j, int max_it,
+                                                          const double* __restrict__ h,
+                                                          const double* __restrict__ h2,
+                                                          double* __restrict__ nrm, int last) {
+  const int mr = G.mr;
+  for (int s = threadIdx.x; s < S; s += kBlock) {
+    if (G.act[s] == 0) continue;
+    const double* a = h + size_t(s) * kMaxBasis;
+    const double* b = h2 + size_t(s) * kMaxBasis;
+    const double cu = a[j], du = a[j + 1], ww = a[j + 2];
+    if (!isfinite(du) || (!last && (!isfinite(cu) || !isfinite(ww)))) {
+      segment_stop(G, s, true);
+      continue;
+    }
+    double alpha = 1.0;
+    if (j > 0) {
+      double aa = 0.0;
+      for (int i = 0; i < j; ++i) aa = fma(a[i], a[i], aa);
+      const double rem = du - aa;
+      const bool in_span = !(rem > 0.0);
+      alpha = in_span ? 0.0 : sqrt(rem);
+      double* Hp = G.H + (size_t(s) * mr + j - 1) * (mr + 1);
+      const double sigma = Hp[j];
+      for (int i = 0; i < j; ++i) Hp[i] = fma(sigma, a[i], Hp[i]);
+      Hp[j] = sigma * alpha;
+      const int more = givens_apply(G, s, j - 1, max_it);
+      if (!more || in_span) {
+        segment_stop(G, s, false);
+        continue;
+      }
+    }
+    if (last) continue;
+    double ab = 0.0;
+    for (int i = 0; i < j; ++i) ab = fma(a[i], b[i], ab);
+    const double hjj = (cu - ab) / alpha;
+    double* Hj = G.H + (size_t(s) * mr + j) * (mr + 1);
+    for (int i = 0; i < j; ++i) Hj[i] = b[i];
+    Hj[j] = hjj;
+    nrm[4 * s + 2] = alpha;
+    nrm[4 * s + 3] = hjj;
+  }
+}
+
+// Pass 2 of step j: v_j = (u - V a) / alpha into V_j and w = w - V b - h_jj v_j
+// from one read of V_0..V_{j-1}, then the tile sums of |w|^2 (column 0),
+// finished into nrm[4 seg] for a small segment.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_dcgs_update(SegLayout L, double* __restrict__ V, int64_t ldv, int j,
+                                                        double* __restrict__ w, const double* __restrict__ h,
+                                                        const double* __restrict__ h2,
+                                                        double* __restrict__ nrm, const int32_t* __restrict__ act,
+                                                        double* __restrict__ partials,
+                                                        int32_t* __restrict__ tickets) {
+  __shared__ double wsum[4][kMaxBasis];
+  const int blk = blockIdx.x;
+  const int seg = L.seg_of_block[blk];
+  if (act[seg] == 0) return;
+  const int c = blk * kFvBlock + threadIdx.x;
+  if (c < L.n_cells) {
+    const double* a = h + size_t(seg) * kMaxBasis;
+    const double* b = h2 + size_t(seg) * kMaxBasis;
+    double sa[D], sb[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) sa[q] = sb[q] = 0.0;
+    for (int k = 0; k < j; ++k) {
+      const double ak = a[k], bk = b[k];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const double x = V[k * ldv + size_t(q) * L.n_cells + c];
+        sa[q] = fma(ak, x, sa[q]);
+        sb[q] = fma(bk, x, sb[q]);
+      }
+    }
+    const double alpha = nrm[4 * seg + 2], hjj = nrm[4 * seg + 3];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const size_t o = size_t(q) * L.n_cells + c;
+      const double v = (V[j * ldv + o] - sa[q]) / alpha;
+      V[j * ldv + o] = v;
+      w[o] = fma(-hjj, v, w[o] - sb[q]);
+    }
+  }
+  tile_norm2<D>(L, w, c, wsum, 0);
+  store_tile_sums(L, wsum, 1, partials, blk);
+  int first, n;
+  if (!small_segment(L, seg, first, n)) return;
+  if (!last_tile_of_segment(tickets + seg, n)) return;
+  if (threadIdx.x >= 64) return;
+  const double t = segment_column_sum(L, partials, first, n, 0);
+  if (threadIdx.x == 0) nrm[4 * seg] = t;
+}
+
+// End of step j per segment (one workgroup over all segments): sigma = |w|
+// is the first-pass subdiagonal of column j (completed by step j + 1) and
+// 1/sigma scales w into u_{j+1}; sigma negligible against |w| before the
+// pass (a breakdown) completes column j as it stands and stops the segment.
+// Publishes the count of segments still taking steps.
+__global__ __launch_bounds__(kBlock) void k_dcgs_step_end(GmresDev G, int S, int j, int max_it,
+                                                          const double* __restrict__ h,
+                                                          const double* __restrict__ nrm) {
+  __shared__ int count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  const int mr = G.mr;
+  for (int s = threadIdx.x; s < S; s += kBlock) {
+    if (G.act[s] == 0) {
+      G.fac[s] = 0.0;
+      continue;
+    }
+    const double sigma = sqrt(nrm[4 * s]);
+    const double w0 = sqrt(h[size_t(s) * kMaxBasis + j + 2]);
+    double* Hj = G.H + (size_t(s) * mr + j) * (mr + 1);
+    Hj[j + 1] = sigma;
+    if (!isfinite(sigma)) {
+      segment_stop(G, s, true);
+      continue;
+    }
+    if (sigma <= 1e-14 * fmax(w0, 1e-300)) {
+      (void)givens_apply(G, s, j, max_it);
+      segment_stop(G, s, false);
+      continue;
+    }
+    G.fac[s] = 1.0 / sigma;
+    atomicAdd(&count, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) G.nact[0] = count;
 }
 
 // Segment sums of partial columns col0 .. col0+ncol-1 for segments larger
@@ -432,6 +671,34 @@ void cgs2_step(const SegLayout& L, bool any_large, const double* V, int64_t ldv,
   if (any_large) {
     hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, 0, act, nrm, 4);
     gmres_step_finish(G, L.n_seg, j, max_it, h, h2, nrm, s);
+  }
+  JFNK_HIP(hipGetLastError());
+}
+
+void dcgs_step(const SegLayout& L, bool any_large, double* V, int64_t ldv, int j, double* w, double* h, double* h2,
+               double* nrm, double* partials, double* partials2, int32_t* tickets, const GmresDev& G, int max_it,
+               bool closing, hipStream_t s) {
+  const int32_t* act = G.act;
+  const dim3 g(L.n_blocks), b(kBlock), wide(kWideBlock);
+  const bool d3 = L.dim == 3;
+  const double* wd = closing ? nullptr : w;
+  if (d3)
+    hipLaunchKernelGGL(k_dcgs_dots<3>, g, b, 0, s, L, V, ldv, j, wd, act, partials, partials2, tickets, h, h2);
+  else
+    hipLaunchKernelGGL(k_dcgs_dots<2>, g, b, 0, s, L, V, ldv, j, wd, act, partials, partials2, tickets, h, h2);
+  if (any_large) {
+    hipLaunchKernelGGL(k_reduce_large, dim3(j + 3, L.n_seg), wide, 0, s, L, partials, 0, act, h, kMaxBasis);
+    if (j > 0)
+      hipLaunchKernelGGL(k_reduce_large, dim3(j, L.n_seg), wide, 0, s, L, partials2, 0, act, h2, kMaxBasis);
+  }
+  hipLaunchKernelGGL(k_dcgs_finalize, dim3(1), b, 0, s, G, L.n_seg, j, max_it, h, h2, nrm, closing ? 1 : 0);
+  if (!closing) {
+    if (d3)
+      hipLaunchKernelGGL(k_dcgs_update<3>, g, b, 0, s, L, V, ldv, j, w, h, h2, nrm, act, partials, tickets);
+    else
+      hipLaunchKernelGGL(k_dcgs_update<2>, g, b, 0, s, L, V, ldv, j, w, h, h2, nrm, act, partials, tickets);
+    if (any_large) hipLaunchKernelGGL(k_reduce_large, dim3(1, L.n_seg), wide, 0, s, L, partials, 0, act, nrm, 4);
+    hipLaunchKernelGGL(k_dcgs_step_end, dim3(1), b, 0, s, G, L.n_seg, j, max_it, h, nrm);
   }
   JFNK_HIP(hipGetLastError());
 }

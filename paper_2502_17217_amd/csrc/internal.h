@@ -434,7 +434,7 @@ struct StepGraphs {
   const void* work = nullptr;
   const double* u = nullptr;
   const double* Ru = nullptr;
-  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0, left = -1, central = -1;
+  int restart = 0, precond = -1, cheb = 0, chunk = 0, max_it = 0, left = -1, central = -1, orth = -1;
   double eps = 0;
   std::vector<hipGraphExec_t> exec;  // one per chunk of steps (null until captured)
   void clear();

@@ -232,9 +232,17 @@ void enqueue_steps(jfnk_mesh* m, const SegLayout& L, const double* u, const doub
     }
     Profiler& p = m->prof;
     const int t = p.on ? p.begin(4, s) : -1;
-    cgs2_step(L, m->any_large, kw.V, n, j + 1, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, fw.cgs_tickets(),
-              fw.step_counters(), kw.gd, j, o.max_it, s);
-    if (j + 1 < o.restart) blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
+    if (o.orth) {
+      // V_{j+1} is kept at the end of a cycle too: the closing pass
+      // reorthogonalises it to complete the cycle's last column
+      dcgs_step(L, m->any_large, kw.V, n, j, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, kw.partials2,
+                fw.cgs_tickets(), kw.gd, o.max_it, false, s);
+      blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
+    } else {
+      cgs2_step(L, m->any_large, kw.V, n, j + 1, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, fw.cgs_tickets(),
+                fw.step_counters(), kw.gd, j, o.max_it, s);
+      if (j + 1 < o.restart) blas_scale_seg(L, kw.w, kw.fac, kw.V + size_t(j + 1) * n, kw.act, s);
+    }
     if (t >= 0) p.end(t, s);
   }
 }
@@ -323,7 +331,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
     const void* work = static_cast<const void*>(kw.V);
     if (sg.work != work || sg.u != u || sg.Ru != Ru || sg.restart != mr || sg.precond != o.precond ||
         sg.cheb != o.cheb_degree || sg.chunk != K || sg.eps != o.eps || sg.max_it != o.max_it ||
-        sg.left != o.left || sg.central != o.fd_central) {
+        sg.left != o.left || sg.central != o.fd_central || sg.orth != o.orth) {
       sg.clear();
       sg.work = work;
       sg.u = u;
@@ -336,6 +344,7 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
       sg.max_it = o.max_it;
       sg.left = o.left;
       sg.central = o.fd_central;
+      sg.orth = o.orth;
       sg.exec.assign(n_chunks, nullptr);
     }
   }
@@ -411,6 +420,15 @@ void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* 
         JFNK_HIP(hipEventSynchronize(mesh_event(m, (c - 1) & 1)));
         if (pin_nact[(c - 1) & 63] == 0) break;
       }
+    }
+    // delayed reorthogonalisation: the segments still taking steps after the
+    // cycle's last step complete its column with a closing pass
+    if (o.orth) {
+      Profiler& p = m->prof;
+      const int t = p.on ? p.begin(4, s) : -1;
+      dcgs_step(L, m->any_large, kw.V, n, mr, kw.w, kw.h, kw.h2, kw.nrm, fw.partials, kw.partials2,
+                fw.cgs_tickets(), kw.gd, o.max_it, true, s);
+      if (t >= 0) p.end(t, s);
     }
     const double te = now_ms();
     // x += Z y on the segments that ran, then the true residual

@@ -79,6 +79,10 @@ void newton_solve(jfnk_mesh* m, const std::vector<int>& n_increments, const jfnk
                   double* u, FvWork& fw, KrylovWork& kw, hipStream_t s, std::vector<jfnk_stats>& stats,
                   std::vector<jfnk_status>& status);
 
+// Longest restart of the delayed-reorthogonalisation Arnoldi (its dots of
+// step j take j + 3 partial columns, at most kMaxBasis).
+constexpr int kMaxDcgsRestart = 250;
+
 // The preconditioner of a precond value, and whether it carries the FP32
 // Z-basis flag.
 inline int pc_kind(int precond) { return precond & ~JFNK_PC_Z32; }

@@ -92,13 +92,15 @@ struct KrylovWork {
   double* uu = nullptr;     // [n_seg] |u|^2 of the state of the current linear solve
   double* rm = nullptr;     // [n_dof] R(u - eps v) of a central-difference J v
   double* eps_neg = nullptr;  // [n_seg] -eps of a central-difference J v
+  double* partials2 = nullptr;  // [n_tiles * kMaxBasis] second tile-sum region (DCGS2 dots)
   GmresDev gd;            // device Arnoldi bookkeeping (shares fac and act)
   float* pc = nullptr;    // preconditioner work (FP32)
   size_t pc_floats = 0;
   void carve(Carver& c, const jfnk_mesh* m, int restart, size_t pc_f, bool z32 = false) {
-    carve(c, m->host.n_cells * m->host.dim, m->n_seg(), restart, pc_f, z32);
+    carve(c, m->host.n_cells, m->host.dim, m->n_seg(), restart, pc_f, z32);
   }
-  void carve(Carver& c, int64_t n_dof, int S, int restart, size_t pc_f, bool z32 = false) {
+  void carve(Carver& c, int64_t n_cells, int dim, int S, int restart, size_t pc_f, bool z32 = false) {
+    const int64_t n_dof = n_cells * dim;
     V = c.take<double>(size_t(restart + 1) * n_dof);
     this->z32 = z32;
     if (z32) {
@@ -122,6 +124,7 @@ struct KrylovWork {
     uu = c.take<double>(S);
     rm = c.take<double>(n_dof);
     eps_neg = c.take<double>(S);
+    partials2 = c.take<double>(size_t(n_tiles(n_cells)) * kMaxBasis);
     gd.mr = restart;
     gd.H = c.take<double>(size_t(S) * restart * (restart + 1));
     gd.cs = c.take<double>(size_t(S) * restart);
@@ -146,7 +149,7 @@ inline size_t solve_workspace_bytes(int64_t n, int dim, int S, int restart, size
   FvWork fw;
   fw.carve(c, n, dim, S);
   KrylovWork kw;
-  kw.carve(c, n * dim, S, restart, pc_floats, z32);
+  kw.carve(c, n, dim, S, restart, pc_floats, z32);
   return c.off;
 }
 

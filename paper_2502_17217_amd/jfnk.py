@@ -58,7 +58,7 @@ class jfnk_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
                 ("eps", C.c_double), ("step_chunk", C.c_int32), ("graphs", C.c_int32),
-                ("left", C.c_int32), ("augment", C.c_int32), ("fd_central", C.c_int32)]
+                ("left", C.c_int32), ("augment", C.c_int32), ("fd_central", C.c_int32), ("orth", C.c_int32)]
 
 
 class jfnk_newton_opts(C.Structure):
@@ -438,10 +438,15 @@ def dynamic_step(mesh, dt, opts, u, u_prev, v, v_prev, a, work, predictor=True, 
     return s, (out[0] if mesh.n_segments == 1 else out)
 
 
+ORTH = {"cgs2": 0, "dcgs2": 1}
+
+
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
-               step_chunk=0, graphs=2, left=0, augment=0, fd_central=0):
+               step_chunk=0, graphs=2, left=0, augment=0, fd_central=0, orth=0):
+    """orth: 0 or "cgs2" (Gram-Schmidt twice), 1 or "dcgs2" (delayed reorthogonalisation)."""
+    orth = ORTH[orth] if isinstance(orth, str) else int(orth)
     return jfnk_gmres_opts(restart, max_it, rtol, atol, _pc(precond), cheb_degree, eps, step_chunk, graphs,
-                           int(left), int(augment), int(fd_central))
+                           int(left), int(augment), int(fd_central), orth)
 
 
 def newton_opts(n_increments=1, max_newton_it=20, rtol=1e-6, atol=1e-50, eta=1e-3, dtol=0.0,

@@ -1,0 +1,196 @@
+"""Arnoldi with delayed reorthogonalisation (gmres orth = 1, DCGS2) on the GPU.
+
+The orthogonalisation changes the rounding of the Krylov iterates, not the
+method, so the bar is the converged solution against the oracle's (1e-8
+relative, the solves run to 1e-10) and the iteration count against the
+two-pass classical Gram-Schmidt of orth = 0:
+
+* GMRES on a jittered block with the Jacobi and the FP32-AMG preconditioner,
+  with restarts short enough that every cycle ends in the closing pass;
+* a mesh of more than 64 tiles (per-segment sums finished by the separate
+  large-segment reduction);
+* graph replay against direct launches (the same bits);
+* Newton on the neo-Hookean cantilever, and a batch of meshes against the
+  oracle per mesh and against each mesh solved alone;
+* with the FP32 Z basis (AMG32): the same bits as with the FP64 basis;
+* options it refuses.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+from oracle.fv import prepare
+from oracle.newton import newton_solve as o_newton
+
+pytestmark = pytest.mark.gpu
+
+
+def _block(shape=(17, 15, 13), seed=22):
+    m = mg.box_mesh_3d(*shape, 1.0, 0.9, 0.8, jitter=0.15, seed=seed)
+    mg.set_patch(m, "xmin", "displacement", (0.0, 0.0, 0.0))
+    mg.set_patch(m, "xmax", "traction", (1e6, -3e5, 2e5))
+    return m, mg.Material("linear_elastic", 200e9, 0.3)
+
+
+def _oracle(m, mat):
+    pr = prepare(m, mat)
+    uo, _ = o_newton(pr, n_increments=1, rtol=1e-6, max_newton_it=3, eta=1e-12, precond="lu",
+                     max_krylov_it=600)
+    return uo
+
+
+def _gmres(lib, gm, precond, rtol, restart, orth, graphs=2, step_chunk=0):
+    work = lib.make_workspace(gm, 1, restart=restart, precond=precond)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    R = torch.empty_like(u)
+    lib.residual(gm, 1.0, u, R, work)
+    x = torch.zeros_like(u)
+    opts = lib.gmres_opts(restart=restart, max_it=20000, rtol=rtol, precond=precond, graphs=graphs,
+                          step_chunk=step_chunk, orth=orth)
+    st, stats = lib.gmres(gm, 1.0, u, R, -R, x, opts, work)
+    return st, stats, x
+
+
+@pytest.mark.parametrize("precond,restart", [("jacobi", 30), ("jacobi", 7), ("amg32", 30), ("amg32", 4)])
+def test_dcgs_gmres_vs_oracle(lib, precond, restart):
+    m, mat = _block()
+    uo = _oracle(m, mat)
+    gm = lib.create_mesh(m, mat)
+    its = {}
+    for orth in (0, 1):
+        s, st, x = _gmres(lib, gm, precond, 1e-10, restart, orth)
+        err = np.linalg.norm(gm.to_external(x).cpu().numpy() - uo) / np.linalg.norm(uo)
+        print(precond, "restart", restart, "orth", orth, lib.STATUS_NAMES.get(s, s), st["gmres_it"], "steps",
+              st["restarts"], "restarts, rel L2 vs oracle %.2e" % err)
+        assert s == lib.OK
+        assert err <= 1e-8
+        its[orth] = st["gmres_it"]
+    assert its[1] <= 1.1 * its[0] + 5
+    gm.close()
+
+
+def test_dcgs_large_segment(lib):
+    m, mat = _block((40, 40, 12), seed=5)
+    assert m["n_cells"] > 64 * 256
+    uo = _oracle(m, mat)
+    gm = lib.create_mesh(m, mat)
+    for orth in (0, 1):
+        s, st, x = _gmres(lib, gm, "amg32", 1e-10, 30, orth)
+        err = np.linalg.norm(gm.to_external(x).cpu().numpy() - uo) / np.linalg.norm(uo)
+        print("40x40x12 amg32 orth", orth, st["gmres_it"], "steps, rel L2 vs oracle %.2e" % err)
+        assert s == lib.OK
+        assert err <= 1e-8
+    gm.close()
+
+
+def test_dcgs_graphs_same_bits(lib):
+    m, mat = _block()
+    gm = lib.create_mesh(m, mat)
+    runs = [_gmres(lib, gm, "amg32", 1e-10, 20, 1, graphs=g, step_chunk=k) for g, k in ((0, 1), (1, 4), (1, 8))]
+    for s, st, x in runs:
+        assert s == lib.OK
+        assert st["gmres_it"] == runs[0][1]["gmres_it"]
+        assert torch.equal(x, runs[0][2])
+    gm.close()
+
+
+def test_dcgs_z32_same_bits(lib):
+    m, mat = _block()
+    gm = lib.create_mesh(m, mat)
+    s64, st64, x64 = _gmres(lib, gm, "amg32", 1e-10, 30, 1)
+    s32, st32, x32 = _gmres(lib, gm, "amg32+z32", 1e-10, 30, 1)
+    assert s64 == s32 == lib.OK
+    assert st64["gmres_it"] == st32["gmres_it"]
+    assert torch.equal(x64, x32)
+    gm.close()
+
+
+def test_dcgs_newton_cantilever(lib):
+    m = mg.cantilever_mesh(20, 4, 2, L=(5.0, 1.0, 1.0), tau=600.0)
+    mat = mg.Material("neo_hookean", 1e6, 0.45)
+    pr = prepare(m, mat)
+    uo, _ = o_newton(pr, n_increments=3, rtol=1e-10, max_newton_it=15, eta=1e-8, precond="lu", max_krylov_it=2000)
+    gm = lib.create_mesh(m, mat)
+    work = lib.make_workspace(gm, 1, restart=30, precond=lib.PC_AMG32)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    opts = lib.newton_opts(n_increments=3, max_newton_it=15, rtol=1e-10, eta=1e-8, restart=30, max_it=20000,
+                           precond="amg32", cheb_degree=3, orth=1)
+    st, stats = lib.newton_solve(gm, opts, u, work)
+    err = np.linalg.norm(gm.to_external(u).cpu().numpy() - uo) / np.linalg.norm(uo)
+    print("NH cantilever DCGS2:", stats["newton_it"], "Newton,", stats["gmres_it"], "GMRES, rel L2 %.2e" % err)
+    assert st == lib.OK
+    assert err <= 1e-8
+    gm.close()
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg32"])
+def test_dcgs_batch_vs_oracle_and_alone(lib, precond):
+    rng = np.random.default_rng(91)
+    probs = []
+    for i, sh in enumerate([(5, 4, 6), (9, 7, 5), (4, 11, 3), (30, 30, 20)]):
+        m = mg.box_mesh_3d(*sh, 1.0, 0.7 + 0.1 * i, 0.9, jitter=0.15, seed=400 + i)
+        mg.set_patch(m, "xmin", "displacement", (0.0, 0.0, 0.0))
+        mg.set_patch(m, "xmax", "traction", tuple(rng.uniform(-1, 1, 3) * 2e3))
+        law = "neo_hookean" if i == 1 else "linear_elastic"
+        probs.append((m, mg.Material(law, float(rng.uniform(1e5, 1e6)), float(rng.uniform(0.2, 0.4)))))
+    n_inc = [1, 3, 2, 1]
+    gm = lib.create_batch([p[0] for p in probs], [p[1] for p in probs])
+    mk = lambda k=None: lib.newton_opts(max_newton_it=20, rtol=1e-10, eta=1e-8, restart=40, max_it=20000,
+                                        precond=precond, cheb_degree=3, orth=1,
+                                        **({} if k is None else {"n_increments": k}))
+    work = lib.make_workspace(gm, 1, restart=40, precond=precond)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    st, stats, seg = lib.newton_solve_batch(gm, mk(), u, work, n_increments=n_inc)
+    assert st == lib.OK and all(x == lib.OK for x in seg), (st, seg)
+    ue = gm.to_external(u).cpu().numpy()
+    # the same batch with Gram-Schmidt twice
+    o0 = mk()
+    o0.gmres.orth = 0
+    u0 = torch.zeros_like(u)
+    st0, _, seg0 = lib.newton_solve_batch(gm, o0, u0, work, n_increments=n_inc)
+    assert st0 == lib.OK and all(x == lib.OK for x in seg0), (st0, seg0)
+    ue0 = gm.to_external(u0).cpu().numpy()
+    for s, (m, mat) in enumerate(probs):
+        sl = gm.segment_slice_external(s)
+        if m["n_cells"] <= 4096:
+            # the large mesh's oracle solve takes minutes: it is compared with
+            # the oracle alone in test_dcgs_large_segment
+            pr = prepare(m, mat)
+            uo, _ = o_newton(pr, n_increments=n_inc[s], rtol=1e-10, max_newton_it=20, eta=1e-9, precond="lu",
+                             max_krylov_it=4000)
+            err = np.linalg.norm(ue[sl] - uo) / np.linalg.norm(uo)
+        else:
+            err = 0.0
+        vs0 = np.linalg.norm(ue[sl] - ue0[sl]) / np.linalg.norm(ue0[sl])
+        g1 = lib.create_batch([m], [mat])
+        w1 = lib.make_workspace(g1, 1, restart=40, precond=precond)
+        u1 = torch.zeros(g1.n_dof, dtype=torch.float64, device="cuda")
+        lib.newton_solve(g1, mk(n_inc[s]), u1, w1)
+        ua = g1.to_external(u1).cpu().numpy()
+        diff = np.linalg.norm(ua - ue[sl]) / np.linalg.norm(ua)
+        print(precond, "mesh", s, "cells", m["n_cells"], "err %.2e" % err, "vs Gram-Schmidt twice %.2e" % vs0,
+              "alone vs mixed %.2e" % diff, "bitwise" if np.array_equal(ua, ue[sl]) else "", flush=True)
+        assert err <= 1e-8
+        assert vs0 <= 1e-8
+        assert diff <= 1e-8
+        g1.close()
+    gm.close()
+
+
+def test_dcgs_option_errors(lib):
+    m, mat = _block()
+    gm = lib.create_mesh(m, mat)
+    work = lib.make_workspace(gm, 1, restart=251, precond=lib.PC_JACOBI)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    R = torch.empty_like(u)
+    lib.residual(gm, 1.0, u, R, work)
+    x = torch.zeros_like(u)
+    for kw in (dict(orth=1, left=1), dict(orth=1, restart=251), dict(orth=2)):
+        o = lib.gmres_opts(**{"restart": 30, "max_it": 10, "rtol": 1e-6, **kw})
+        with pytest.raises(lib.JfnkError) as e:
+            lib.gmres(gm, 1.0, u, R, -R, x, o, work)
+        assert e.value.status == lib.E_ARG, kw
+    assert torch.count_nonzero(x).item() == 0
+    gm.close()
