@@ -288,7 +288,9 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_JACOBI = 1, JFNK_PC_AMG32 = 2, JFNK_PC_
  * of step j is completed, and its Givens rotation taken, in step j + 1, so
  * the solve notices convergence one J v later.  Same Krylov space and
  * arithmetic precision; the iterates differ from orth = 0 by rounding.
- * Right preconditioning only, restart <= 250 (JFNK_E_ARG otherwise). */
+ * Right preconditioning only, restart <= 250 (JFNK_E_ARG otherwise).
+ * 2: the handle's choice (jfnk_autotune times both; DCGS2 until tuned),
+ * CGS2 wherever DCGS2 does not apply. */
 typedef struct {
   int32_t restart;
   int32_t max_it;
@@ -545,8 +547,10 @@ jfnk_status jfnk_server_destroy(jfnk_server* srv);
  * gradient and flux passes, or direct gathers; one workgroup per tile or a
  * persistent grid), and the Arnoldi schedule
  * (steps per host check, HIP-graph replay) on one GMRES solve of
- * J x = -R(u) with `opts`.  Later solves use the choice when their options
- * ask for the handle's values (step_chunk = 0, graphs = 2).  d_work: a
+ * J x = -R(u) with `opts`, then the orthogonalisation (CGS2 or DCGS2) on
+ * the same solve under the chosen schedule.  Later solves use the choice
+ * when their options ask for the handle's values (step_chunk = 0,
+ * graphs = 2, orth = 2).  d_work: a
  * solve workspace (op 1) for opts.restart and opts.precond.  The report
  * (may be NULL) lists every candidate and its time. */
 typedef struct {
@@ -560,6 +564,8 @@ typedef struct {
   int32_t n_solve;
   int32_t solve_chunk[8], solve_graphs[8];
   double solve_ms[8];          /* time of the same GMRES solve per candidate */
+  int32_t orth;                /* chosen orthogonalisation: 0 CGS2, 1 DCGS2 */
+  double orth_ms[2];           /* the solve with CGS2 and with DCGS2 (0: not timed, DCGS2 not applicable) */
 } jfnk_tune_report;
 
 jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const double* d_u, double load,

@@ -89,8 +89,8 @@ void check_opts(const jfnk_gmres_opts& o) {
   JFNK_REQUIRE(o.augment >= 0 && o.augment < o.restart, JFNK_E_ARG, "gmres: augment must lie in [0, restart)");
   JFNK_REQUIRE(!(o.left && o.augment), JFNK_E_ARG, "gmres: augmentation needs right preconditioning");
   JFNK_REQUIRE(o.fd_central == 0 || o.fd_central == 1, JFNK_E_ARG, "gmres: fd_central must be 0 or 1");
-  JFNK_REQUIRE(o.orth == 0 || o.orth == 1, JFNK_E_ARG, "gmres: orth must be 0 or 1");
-  JFNK_REQUIRE(o.orth == 0 || (!o.left && o.restart <= kMaxDcgsRestart), JFNK_E_ARG,
+  JFNK_REQUIRE(o.orth >= 0 && o.orth <= 2, JFNK_E_ARG, "gmres: orth must be 0, 1 or 2");
+  JFNK_REQUIRE(o.orth != 1 || (!o.left && o.restart <= kMaxDcgsRestart), JFNK_E_ARG,
                "gmres: orth = 1 needs right preconditioning and restart <= 250");
 }
 

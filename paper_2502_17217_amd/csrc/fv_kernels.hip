@@ -58,6 +58,28 @@ __device__ __forceinline__ int xcd_block(int bid, int nb_launch) {
 #endif
 }
 
+// Head of a tile's halo list for the gradient pass: the tile of loop
+// position it, its halo range, and the id of this thread's cell among the
+// first kFvBlock halo cells (n_cells when none).  A persistent workgroup
+// loads the head of its next tile while it works on the current one, so the
+// staging loads of the halo values need not wait for their ids.  (The flux
+// pass loads its heads in place: with its larger register file the early
+// load measured slower there.)
+struct HaloHead {
+  int tile, h0, nh, cg1;
+};
+
+__device__ __forceinline__ HaloHead halo_head(const MeshDev& m, int it, int nb_real, int nb_launch) {
+  HaloHead hh{nb_real, 0, 0, m.n_cells};
+  if (it < nb_launch) hh.tile = xcd_block(it, nb_launch);
+  if (hh.tile < nb_real) {
+    hh.h0 = m.halo_ptr[hh.tile];
+    hh.nh = m.halo_ptr[hh.tile + 1] - hh.h0;
+    if (int(threadIdx.x) < hh.nh) hh.cg1 = m.halo_cells[hh.h0 + threadIdx.x];
+  }
+  return hh;
+}
+
 template <int D>
 __device__ __forceinline__ void load_w(const double* __restrict__ u, const double* __restrict__ v,
                                        double eps, int n, int c, double (&w)[D]) {
@@ -557,18 +579,21 @@ __global__ __launch_bounds__(kFvBlock, JFNK_TILED_MINWAVES) void k_gradient_tile
                                                              double* __restrict__ rec, int nb_real, int nb_launch) {
   extern __shared__ double lds[];
   const int n = m.n_cells, S = m.halo_stride;
+  HaloHead next = halo_head(m, blockIdx.x, nb_real, nb_launch);
   for (int it = blockIdx.x; it < nb_launch; it += gridDim.x) {
-    const int tile = xcd_block(it, nb_launch);
+    const HaloHead hh = next;
+    next = halo_head(m, it + gridDim.x, nb_real, nb_launch);
+    const int tile = hh.tile;
     if (tile >= nb_real) continue;
     const int seg = m.seg_of_block[tile];
     if (sc.active != nullptr && sc.active[seg] == 0) continue;
     const double eps = (v != nullptr) ? sc.eps[seg] : 0.0;
     const int base = tile * kFvBlock;
-    const int h0 = m.halo_ptr[tile], nh = m.halo_ptr[tile + 1] - h0;
+    const int h0 = hh.h0, nh = hh.nh;
     const int c = base + threadIdx.x;
     // the tile and the first kFvBlock halo cells in one round trip
     {
-      const int cg0 = c, cg1 = threadIdx.x < nh ? m.halo_cells[h0 + threadIdx.x] : n;
+      const int cg0 = c, cg1 = hh.cg1;
       double w0[D], x0[D], w1[D], x1[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) w0[k] = x0[k] = w1[k] = x1[k] = 0.0;

@@ -444,6 +444,7 @@ struct StepGraphs {
 struct Tuning {
   int step_chunk = 1;    // Arnoldi steps enqueued between host convergence checks
   int graphs = 1;        // replay runs of steps from HIP graphs
+  int orth = 1;          // Arnoldi orthogonalisation where DCGS2 applies (1 DCGS2, 0 CGS2)
   int tuned = 0;         // 1 once jfnk_autotune has run
 };
 }  // namespace jfnk

@@ -255,8 +255,11 @@ hipEvent_t mesh_event(jfnk_mesh* m, int i) {
 }  // namespace
 
 void gmres_solve(jfnk_mesh* m, const double* u, const double* Ru, const double* b, double* x,
-                 bool x_is_zero, const jfnk_gmres_opts& o, FvWork& fw, KrylovWork& kw, hipStream_t s,
+                 bool x_is_zero, const jfnk_gmres_opts& o_in, FvWork& fw, KrylovWork& kw, hipStream_t s,
                  const std::vector<char>& part_in, std::vector<GmresSeg>& out, double* t_ms) {
+  // orth = 2: the handle's choice where DCGS2 applies
+  jfnk_gmres_opts o = o_in;
+  if (o.orth == 2) o.orth = (!o.left && o.restart <= kMaxDcgsRestart) ? m->tune.orth : 0;
   const int S = m->n_seg();
   const int64_t n = int64_t(m->dev.n_cells) * m->dev.dim;
   const int mr = o.restart;

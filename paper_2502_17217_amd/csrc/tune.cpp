@@ -1,6 +1,7 @@
 // Launch-shape and schedule tuner for one mesh handle (a single mesh or a
-// batch): every candidate computes the same bits, so the choice is made on
-// measured time only, on the handle's own mesh and state.
+// batch): every launch-shape and schedule candidate computes the same bits,
+// so the choice is made on measured time only, on the handle's own mesh and
+// state.
 //
 //   cell passes of J v: one fused pass per tile or LDS-staged gradient and
 //     flux passes (when the mesh is tile-ordered), or direct gathers; one
@@ -8,7 +9,11 @@
 //     compute unit, each timed with HIP events over repeated J v products;
 //   Arnoldi schedule: the number of steps enqueued between host checks and
 //     whether runs are replayed from HIP graphs, each timed over the same
-//     preconditioned GMRES solve of J x = -R(u).
+//     preconditioned GMRES solve of J x = -R(u);
+//   orthogonalisation (for solves that leave it to the handle): Gram-Schmidt
+//     twice or with delayed reorthogonalisation, timed on the same solve
+//     under the chosen schedule.  The two differ in rounding, not in the
+//     method; a solve that names one gets that one.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -139,9 +144,31 @@ void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o_in, const double* u, double
   }
   m->tune.step_chunk = best_chunk;
   m->tune.graphs = best_graphs;
-  m->tune.tuned = 1;
   r.step_chunk = best_chunk;
   r.graphs = best_graphs;
+  // ---- orthogonalisation, under the chosen schedule (where DCGS2 applies)
+  r.orth = m->tune.orth;
+  if (!o_in.left && o_in.restart <= kMaxDcgsRestart) {
+    double t_orth[2] = {0.0, 0.0};
+    for (int orth = 0; orth < 2; ++orth) {
+      jfnk_gmres_opts o = o_in;
+      o.step_chunk = best_chunk;
+      o.graphs = best_graphs;
+      o.orth = orth;
+      std::vector<GmresSeg> res;
+      for (int pass = 0; pass < 2; ++pass) {
+        fill_device(kw.du, n, 0.0, s);
+        JFNK_HIP(hipStreamSynchronize(s));
+        const double t0 = now_ms();
+        gmres_solve(m, u, kw.R, kw.b, kw.du, true, o, fw, kw, s, {}, res, nullptr);
+        if (pass == 1) t_orth[orth] = now_ms() - t0;
+      }
+      r.orth_ms[orth] = t_orth[orth];
+    }
+    m->tune.orth = t_orth[1] <= t_orth[0] ? 1 : 0;
+    r.orth = m->tune.orth;
+  }
+  m->tune.tuned = 1;
   m->graphs.clear();
   m->prof.on = prof;
   if (rep) *rep = r;

@@ -90,7 +90,8 @@ class jfnk_tune_report(C.Structure):
     _fields_ = [("lds_kernels", C.c_int32), ("persist", C.c_int32), ("step_chunk", C.c_int32),
                 ("graphs", C.c_int32), ("n_jv", C.c_int32), ("jv_lds", C.c_int32 * 16),
                 ("jv_persist", C.c_int32 * 16), ("jv_ms", C.c_double * 16), ("n_solve", C.c_int32),
-                ("solve_chunk", C.c_int32 * 8), ("solve_graphs", C.c_int32 * 8), ("solve_ms", C.c_double * 8)]
+                ("solve_chunk", C.c_int32 * 8), ("solve_graphs", C.c_int32 * 8), ("solve_ms", C.c_double * 8),
+                ("orth", C.c_int32), ("orth_ms", C.c_double * 2)]
 
     def as_dict(self):
         return {"lds_kernels": self.lds_kernels, "persist": self.persist, "step_chunk": self.step_chunk,
@@ -98,7 +99,8 @@ class jfnk_tune_report(C.Structure):
                 "jv": [{"lds": self.jv_lds[i], "persist": self.jv_persist[i], "ms": self.jv_ms[i]}
                        for i in range(self.n_jv)],
                 "solve": [{"step_chunk": self.solve_chunk[i], "graphs": self.solve_graphs[i],
-                           "ms": self.solve_ms[i]} for i in range(self.n_solve)]}
+                           "ms": self.solve_ms[i]} for i in range(self.n_solve)],
+                "orth": self.orth, "orth_ms": list(self.orth_ms)}
 
 
 def _load():
@@ -438,12 +440,13 @@ def dynamic_step(mesh, dt, opts, u, u_prev, v, v_prev, a, work, predictor=True, 
     return s, (out[0] if mesh.n_segments == 1 else out)
 
 
-ORTH = {"cgs2": 0, "dcgs2": 1}
+ORTH = {"cgs2": 0, "dcgs2": 1, "auto": 2}
 
 
 def gmres_opts(restart=30, max_it=1000, rtol=1e-10, atol=0.0, precond=PC_JACOBI, cheb_degree=3, eps=0.0,
                step_chunk=0, graphs=2, left=0, augment=0, fd_central=0, orth=0):
-    """orth: 0 or "cgs2" (Gram-Schmidt twice), 1 or "dcgs2" (delayed reorthogonalisation)."""
+    """orth: 0 or "cgs2" (Gram-Schmidt twice), 1 or "dcgs2" (delayed reorthogonalisation),
+    2 or "auto" (the handle's choice, see autotune)."""
     orth = ORTH[orth] if isinstance(orth, str) else int(orth)
     return jfnk_gmres_opts(restart, max_it, rtol, atol, _pc(precond), cheb_degree, eps, step_chunk, graphs,
                            int(left), int(augment), int(fd_central), orth)

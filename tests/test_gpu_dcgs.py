@@ -187,7 +187,7 @@ def test_dcgs_option_errors(lib):
     R = torch.empty_like(u)
     lib.residual(gm, 1.0, u, R, work)
     x = torch.zeros_like(u)
-    for kw in (dict(orth=1, left=1), dict(orth=1, restart=251), dict(orth=2)):
+    for kw in (dict(orth=1, left=1), dict(orth=1, restart=251), dict(orth=3)):
         o = lib.gmres_opts(**{"restart": 30, "max_it": 10, "rtol": 1e-6, **kw})
         with pytest.raises(lib.JfnkError) as e:
             lib.gmres(gm, 1.0, u, R, -R, x, o, work)

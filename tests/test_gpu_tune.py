@@ -2,7 +2,9 @@
 the same bits (fused, LDS-staged or gathered cell passes, one workgroup per tile
 or a persistent grid, any run length of Arnoldi steps, graphs or not), so
 tuning changes time only.  Checked on a mesh large enough for persistent
-grids (more tiles than 512 workgroups)."""
+grids (more tiles than 512 workgroups).  The orthogonalisation it also
+times (Gram-Schmidt twice or delayed) changes rounding, not the method: a
+solve that leaves it to the handle gets the tuner's choice."""
 
 import numpy as np
 import pytest
@@ -56,4 +58,14 @@ def test_tuner_choices_keep_results(lib):
     st1, s1 = lib.newton_solve(gm, nopts, u1, work)
     assert st0 == st1 and s0["gmres_it"] == s1["gmres_it"]
     assert torch.equal(u0, u1)
+    # the orthogonalisation left to the handle is the one the tuner chose
+    assert rep["orth"] in (0, 1) and all(t > 0 for t in rep["orth_ms"])
+    out = []
+    for orth in ("auto", rep["orth"]):
+        ua = torch.zeros_like(u)
+        oa = lib.newton_opts(n_increments=1, max_newton_it=6, rtol=1e-6, eta=1e-4, restart=20, max_it=400,
+                             precond="amg32", cheb_degree=3, orth=orth)
+        sta, sa = lib.newton_solve(gm, oa, ua, work)
+        out.append((ua, sa["gmres_it"], sta))
+    assert out[0][2] == out[1][2] and out[0][1] == out[1][1] and torch.equal(out[0][0], out[1][0])
     gm.close()
