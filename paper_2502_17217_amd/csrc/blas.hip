@@ -1,7 +1,7 @@
 // Vector kernels for the Krylov solver and the J.v step size, gfx950.
 //
 // Reductions are deterministic and per segment: one workgroup per tile of
-// kFvBlock cells (fixed butterfly over the 64 lanes of a wavefront, fixed
+// kFvBlock cells (fixed reduction over the 64 lanes of a wavefront, fixed
 // order over the 4 wavefronts), then one workgroup per segment sums that
 // segment's tile partials in a fixed order.  A segment's result depends only
 // on its own values, not on the other segments of a batch.

@@ -4,7 +4,7 @@
 // One workgroup per tile of kFvBlock cells.  A pass computes its tile's
 // partial sums and, for segments of at most kFuseTiles tiles, the last tile
 // of the segment to finish adds the segment's partials (one tile per lane,
-// fixed butterfly) and writes the result, so a whole pass is one launch.  Larger segments leave
+// fixed wavefront reduction) and writes the result, so a whole pass is one launch.  Larger segments leave
 // their partials to a separate reduction launch (k_reduce_large), spread
 // over one workgroup per (column, segment).  Which of the two a segment
 // takes depends only on its own size, so a mesh gets the same bits alone
@@ -47,7 +47,7 @@ __device__ __forceinline__ void combine_cell(const SegLayout& L, const double* _
   for (int q = 0; q < D; ++q) w[size_t(q) * L.n_cells + c] -= s[q];
 }
 
-// Tile sums of V_k . w (k < nk): per-wavefront butterfly sums go to
+// Tile sums of V_k . w (k < nk): per-wavefront sums go to
 // wsum[wave][k] (store_tile_sums adds the four wavefronts in fixed order).
 template <int D>
 __device__ __forceinline__ void tile_dots(const SegLayout& L, const double* __restrict__ V, int64_t ldv,
@@ -86,7 +86,7 @@ __device__ __forceinline__ size_t pidx(const SegLayout& L, int col, int tile) {
 }
 
 // Segment sum of partial column col over tiles first .. first+n-1 (n <= 64),
-// one tile per lane and a fixed butterfly; valid in every lane of the wave.
+// one tile per lane and the fixed wavefront reduction; valid in every lane.
 __device__ __forceinline__ double segment_column_sum(const SegLayout& L, const double* __restrict__ partials,
                                                      int first, int n, int col) {
   const int lane = threadIdx.x & 63;

@@ -1,17 +1,41 @@
 // Device helpers for the deterministic per-segment reductions (included by
 // HIP sources only).  A workgroup is one tile of kFvBlock cells of one
-// segment; tile sums use a fixed butterfly over the 64 lanes of a wavefront
-// and a fixed order over the 4 wavefronts.
+// segment; tile sums use a fixed reduction over the 64 lanes of a
+// wavefront (wave_sum) and a fixed order over the 4 wavefronts.
 #pragma once
 
 #include "internal.h"
 
 namespace jfnk {
 
+// x from lane (i permuted by the DPP pattern CTRL) of the wavefront, both
+// 32-bit halves moved by the VALU's data-parallel-primitive path (no LDS).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, false));
+  const unsigned hi = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ double read_lane(double x, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), lane));
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), the same bits in
+// every lane: within each row of 16 lanes, partners exchange by DPP (xor 1,
+// xor 2, the half-row mirror, the row mirror; a + b and b + a are the same
+// number, so the lanes of a row agree), then the four row sums are read into
+// scalar registers and added as (r0 + r1) + (r2 + r3).
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  x += dpp_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141>(x);  // row_half_mirror
+  x += dpp_f64<0x140>(x);  // row_mirror
+  return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
 }
 
 // Sum over a 256-thread workgroup; valid in thread 0.
