@@ -4,6 +4,7 @@
 // handles all displacement components (component-major arrays [dim][n]) so
 // that a matrix row is read once for the dim right-hand sides.
 #include "amg.h"
+#include "reduce_dev.h"
 
 namespace jfnk {
 
@@ -14,8 +15,8 @@ constexpr int kB = 256;
 inline int blocks_for(int64_t n) { return int((n + kB - 1) / kB); }
 
 // Row i of a CSR matrix times x (D components), shared by the G lanes of a
-// group: lane `sub` takes nonzeros sub, sub + G, ..., then a fixed butterfly
-// over the group leaves the row's sums in every lane of it.
+// group: lane `sub` takes nonzeros sub, sub + G, ..., then a fixed reduction
+// over the group (group_sum) leaves the row's sums in every lane of it.
 template <class T, int D, int G>
 __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                         const T* __restrict__ val, const T* __restrict__ x,
@@ -31,9 +32,7 @@ __device__ __forceinline__ void row_dot(const int32_t* __restrict__ ptr, const i
   }
   if constexpr (G > 1) {
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1)
-#pragma unroll
-      for (int q = 0; q < D; ++q) s[q] += __shfl_xor(s[q], off, G);
+    for (int q = 0; q < D; ++q) s[q] = group_sum<G>(s[q]);
   }
 }
 

@@ -8,14 +8,37 @@
 
 namespace jfnk {
 
-// x from lane (i permuted by the DPP pattern CTRL) of the wavefront, both
-// 32-bit halves moved by the VALU's data-parallel-primitive path (no LDS).
+// x from lane (i permuted by the DPP pattern CTRL) of the wavefront, each
+// 32-bit half moved by the VALU's data-parallel-primitive path (no LDS).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
   const unsigned lo = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, false));
   const unsigned hi = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false));
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) { return dpp_f64<CTRL>(x); }
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) { return dpp_f32<CTRL>(x); }
+
+// Sum over each aligned group of G lanes (G a power of two up to 64, every
+// lane active), the same bits in every lane of a group: DPP exchanges inside
+// rows of 16 lanes (xor 1, xor 2, the half-row mirror, the row mirror), then
+// shuffles across rows.
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T x) {
+  if constexpr (G >= 2) x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) x += dpp_move<0x141>(x);  // row_half_mirror
+  if constexpr (G >= 16) x += dpp_move<0x140>(x); // row_mirror
+  if constexpr (G >= 32) x += __shfl_xor(x, 16, G);
+  if constexpr (G >= 64) x += __shfl_xor(x, 32, G);
+  return x;
 }
 
 __device__ __forceinline__ double read_lane(double x, int lane) {
