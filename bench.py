@@ -566,7 +566,9 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
               "max_floor_rel": max(r["floor_rel"] for r in incs),
               "all_at_rtol_or_floor": all(r["at_rtol_or_floor"] for r in incs),
               "tip_uy_m": incs[-1]["tip_uy"],
-              "workspace_mb": {"fp64_z_basis": ws[""] / 1e6, "fp32_z_basis": ws["+z32"] / 1e6}}
+              "workspace_mb": {"fp64_z_basis": ws[""] / 1e6, "fp32_z_basis": ws["+z32"] / 1e6},
+              "amg_hierarchy": jfnk.amg_info(gm, jfnk.PC_AMG32)}
+    log("C3 AMG hierarchy: " + json.dumps(report["amg_hierarchy"]))
     u_final = u.clone()
     # increment 1 again, profiled (direct launches, HIP events per kernel class)
     u.zero_()

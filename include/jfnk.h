@@ -581,6 +581,28 @@ jfnk_status jfnk_autotune(jfnk_mesh* mesh, const jfnk_gmres_opts* opts, const do
  * passes outside 0..2 or not supported by the mesh, persist < 0). */
 jfnk_status jfnk_set_cell_passes(jfnk_mesh* mesh, int32_t passes, int32_t persist);
 
+/* Shape of a handle's AMG hierarchy (Section 3.2's preconditioner built on
+ * J_tilde of Section 3.1) for precond AMG32 or AMG64, once a solve or
+ * jfnk_autotune has built it: levels from the finest, the scalar unknowns
+ * (rows) of each, the stored nonzeros of each level's operator and the
+ * lanes that share a row in its kernels (both 0 at the coarsest level,
+ * which is solved by a dense inverse or, when its rows are uncoupled, a
+ * diagonal), operator complexity, set-up time and device bytes.  Errors:
+ * JFNK_E_ARG (null arguments, precond not AMG32 or AMG64, hierarchy not
+ * built). */
+typedef struct {
+  int32_t n_levels;
+  int32_t coarse_dense;        /* coarsest level: 1 dense inverse, 0 diagonal */
+  int64_t rows[16];
+  int64_t nnz[16];
+  int32_t lanes[16];
+  double operator_complexity;  /* sum of the levels' nonzeros over the finest level's */
+  double setup_ms;
+  int64_t device_bytes;
+} jfnk_amg_info;
+
+jfnk_status jfnk_amg_info_get(const jfnk_mesh* mesh, int32_t precond, jfnk_amg_info* info);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* jfnk_last_error(void);
 

@@ -58,7 +58,10 @@ def build(verbose=False, jobs=None):
             if err.strip():
                 print("[%s]\n%s" % (os.path.basename(src), err), file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    # rocSOLVER (with rocBLAS) forms the dense inverse of a large AMG coarse level at set-up
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(_hipcc()))), "lib")
+    cmd = ([_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs +
+           ["-L", rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocsolver", "-lrocblas"])
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (p.stdout, p.stderr))

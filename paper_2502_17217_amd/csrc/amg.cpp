@@ -23,6 +23,9 @@
 #include <limits>
 #include <numeric>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "amg.h"
 #include "solver.h"
 
@@ -31,7 +34,16 @@ namespace jfnk {
 namespace {
 
 constexpr double kTheta = 0.08;
-constexpr int64_t kDenseMax = 200;
+// Coarsening stops at kHostDenseMax rows, whose dense inverse is formed on
+// the host; on a single mesh of at least kDeviceDenseMinRows rows it stops
+// at kDenseMax rows instead, the inverse formed on the device (rocSOLVER
+// Cholesky factor and inverse): the coarse levels in between cost a launch
+// chain per V-cycle that such a solve repeats thousands of times, while on
+// small meshes and batches the set-up time of the larger inverse would not
+// be repaid.
+constexpr int64_t kDenseMax = 5000;
+constexpr int64_t kHostDenseMax = 200;
+constexpr int64_t kDeviceDenseMinRows = 262144;
 constexpr int kMaxLevels = 16;
 
 double now_ms() {
@@ -563,11 +575,63 @@ void upload_values(DevBuf& buf, const double* v, size_t count, bool fp64, hipStr
   JFNK_HIP(hipStreamSynchronize(s));
 }
 
+void check_rocblas(rocblas_status st, const char* what) {
+  JFNK_REQUIRE(st == rocblas_status_success, JFNK_E_HIP, std::string("amg: ") + what + " failed");
+}
+
+// Inverse of the SPD coarse operator A on the device: the dense matrix (with
+// the host path's diagonal shift) to the device, its Cholesky factor and
+// inverse by rocSOLVER in FP64, then both triangles in the hierarchy's
+// precision, column-major.
+void dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& out) {
+  const int64_t n = A.n;
+  std::vector<double> M(size_t(n) * size_t(n), 0.0);
+  double shift = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      M[size_t(A.col[k]) * n + i] = A.val[k];
+      if (A.col[k] == i) shift = std::max(shift, std::fabs(A.val[k]));
+    }
+  shift *= 1e-12;
+  for (int64_t i = 0; i < n; ++i) M[size_t(i) * n + i] += shift;
+  DevBuf dm, dinfo;
+  dm.alloc(M.size() * sizeof(double));
+  dinfo.alloc(256);
+  JFNK_HIP(hipMemcpyAsync(dm.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  rocblas_handle h = nullptr;
+  check_rocblas(rocblas_create_handle(&h), "rocblas_create_handle");
+  struct Handle {
+    rocblas_handle h;
+    ~Handle() { (void)rocblas_destroy_handle(h); }
+  } guard{h};
+  check_rocblas(rocblas_set_stream(h, s), "rocblas_set_stream");
+  rocblas_int info = 0;
+  check_rocblas(rocsolver_dpotrf(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
+                                 dinfo.as<rocblas_int>()),
+                "Cholesky factorisation");
+  JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  JFNK_HIP(hipStreamSynchronize(s));
+  JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator not positive definite");
+  check_rocblas(rocsolver_dpotri(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
+                                 dinfo.as<rocblas_int>()),
+                "inverse from the Cholesky factor");
+  JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  JFNK_HIP(hipStreamSynchronize(s));
+  JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator singular");
+  out.alloc(M.size() * (fp64 ? 8 : 4));
+  if (fp64)
+    amg_sym_from_lower<double>(dm.as<double>(), out.as<double>(), int(n), s);
+  else
+    amg_sym_from_lower<float>(dm.as<double>(), out.as<float>(), int(n), s);
+  JFNK_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 void DevCsr::upload(const HostCsr& h, bool fp64, hipStream_t s) {
   n = int32_t(h.n);
   m = int32_t(h.m);
+  nnz = int64_t(h.col.size());
   // each row is shared by the fewest lanes (a power of two) that leave at most
   // three nonzeros to a lane: a short chain of dependent gathers per lane pays
   // on the short fine-level rows as much as on the dense coarse ones
@@ -585,7 +649,8 @@ size_t amg_work_floats(int64_t n, int dim) {
   // upper bound before setup, in elements of the hierarchy's precision: five
   // work vectors per level with a geometric level-size bound (each level at
   // most 3/4 of the previous one)
-  return size_t(5) * dim * size_t(4 * n + 64 * kMaxLevels) + 2 * kDenseMax * dim;
+  return size_t(5) * dim * size_t(4 * n + 64 * kMaxLevels) +
+         size_t(2 + n_chunks(kDenseMax, kDenseChunk)) * kDenseMax * dim;
 }
 
 size_t amg_work_floats(const jfnk_mesh* m) { return amg_work_floats(m->host.n_cells, m->host.dim); }
@@ -612,6 +677,7 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
       }
     }
     HostCsr A = fine_operator(m->host, sym.empty() ? diag0 : diag_mean);
+    const int64_t dense_max = (m->n_seg() == 1 && A.n >= kDeviceDenseMinRows) ? kDenseMax : kHostDenseMax;
     const double nnz0 = double(A.nnz());
     size_t off = 0;
     auto take = [&](int64_t count) {
@@ -624,13 +690,18 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
       AmgLevel L;
       L.n = A.n;
       std::vector<double> d = diagonal(A);
-      const bool last = A.n <= kDenseMax || int(H->levels.size()) + 1 >= kMaxLevels;
+      const bool last = A.n <= dense_max || int(H->levels.size()) + 1 >= kMaxLevels;
       H->op_complexity += double(A.nnz()) / nnz0;
       if (last) {
         L.off_x = take(A.n);
         L.off_b = take(A.n);
-        std::vector<double> inv = dense_inverse(A);
-        upload_values(H->coarse_inv, inv.data(), inv.size(), fp64, s);
+        if (A.n <= kHostDenseMax) {
+          std::vector<double> inv = dense_inverse(A);
+          upload_values(H->coarse_inv, inv.data(), inv.size(), fp64, s);
+        } else {
+          dense_inverse_device(A, fp64, s, H->coarse_inv);
+          H->off_part = take(n_chunks(A.n, kDenseChunk) * A.n);
+        }
         H->n_coarse = A.n;
         H->levels.push_back(std::move(L));
         break;
@@ -713,6 +784,8 @@ void vcycle(const AmgHierarchy& H, size_t l, int degree, T* w, hipStream_t s, co
     if (r64) amg_cast_in<T>(r64, b, L.n, dim, s, gate);
     if (H.coarse_diag)
       amg_diag_solve<T>(H.coarse_inv.as<T>(), b, x, int(H.n_coarse), dim, s, gate);
+    else if (H.n_coarse > kHostDenseMax)
+      amg_dense_chunked<T>(H.coarse_inv.as<T>(), b, x, w + H.off_part, int(H.n_coarse), dim, s, gate);
     else
       amg_dense<T>(H.coarse_inv.as<T>(), b, x, int(H.n_coarse), dim, s, gate);
     if (z64) amg_cast_out<T>(x, z64, L.n, dim, s, gate);
@@ -771,6 +844,22 @@ void amg_apply(jfnk_mesh* m, bool fp64, int cheb_degree, const double* r, double
 }
 
 void amg_destroy(AmgHierarchy* a) { delete a; }
+
+void amg_describe(const AmgHierarchy& H, jfnk_amg_info& info) {
+  info = jfnk_amg_info{};
+  info.n_levels = int32_t(H.levels.size());
+  info.coarse_dense = H.coarse_diag ? 0 : 1;
+  for (size_t l = 0; l < H.levels.size() && l < 16; ++l) {
+    const AmgLevel& L = H.levels[l];
+    info.rows[l] = L.n;
+    const bool last = l + 1 == H.levels.size();
+    info.nnz[l] = last ? 0 : L.A.nnz;
+    info.lanes[l] = last ? 0 : L.A.lanes;
+  }
+  info.operator_complexity = H.op_complexity;
+  info.setup_ms = H.setup_ms;
+  info.device_bytes = int64_t(amg_device_bytes(&H));
+}
 
 size_t amg_device_bytes(const AmgHierarchy* a) {
   if (a == nullptr) return 0;

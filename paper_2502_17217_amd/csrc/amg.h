@@ -20,6 +20,7 @@ struct HostCsr {
 struct DevCsr {
   int32_t n = 0, m = 0;
   int32_t lanes = 1;      // lanes that share a row in the row kernels (power of two, <= 64)
+  int64_t nnz = 0;
   DevBuf ptr, col, val;
   void upload(const HostCsr& h, bool fp64, hipStream_t s);
 };
@@ -40,6 +41,7 @@ struct AmgHierarchy {
   bool coarse_diag = false;          // coarsest rows uncoupled: coarse_inv holds D^{-1} only
   DevBuf coarse_inv;                 // [n_c][n_c] column-major, or [n_c] when coarse_diag
   int64_t n_coarse = 0;
+  size_t off_part = 0;               // work offset of the chunked dense product's partial sums
   int dim = 3;
   size_t work_floats = 0;
   double op_complexity = 0;          // sum nnz(A_l) / nnz(A_0)
@@ -87,6 +89,15 @@ void amg_spmv(const DevCsr& M, const T* x, T* y, bool accumulate, int dim, hipSt
 // x = inv * b (dense, n x n)
 template <class T>
 void amg_dense(const T* inv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate);
+// the same for larger n in two passes: chunks of kDenseChunk columns into
+// part ([ceil(n / kDenseChunk)][dim][n]), then their sum in chunk order
+constexpr int kDenseChunk = 256;
+template <class T>
+void amg_dense_chunked(const T* inv, const T* b, T* x, T* part, int n, int dim, hipStream_t s,
+                       const int32_t* gate);
+// out (n x n, both triangles, T) from the lower triangle of a column-major FP64 matrix
+template <class T>
+void amg_sym_from_lower(const double* lo, T* out, int n, hipStream_t s);
 // x = dinv * b (coarsest level of uncoupled rows)
 template <class T>
 void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate);

@@ -257,6 +257,68 @@ __global__ __launch_bounds__(kB) void k_dense(const T* __restrict__ inv, const T
   }
 }
 
+// Larger coarsest levels, first of two passes: workgroup (ib, jc) sums
+// columns jc*kDenseChunk .. +kDenseChunk of rows ib*64 .. +63 (the four waves
+// take every fourth column and meet in LDS in a fixed order) into
+// part[jc][q][i]; the second pass adds the chunks in order.  Enough
+// workgroups to stream the whole inverse at once.
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_dense_part(const T* __restrict__ inv, const T* __restrict__ b,
+                                                   T* __restrict__ part, int n, const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  constexpr int kWaves = kB / 64;
+  __shared__ T acc[kWaves][D][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int j0 = blockIdx.y * kDenseChunk, j1 = min(n, j0 + kDenseChunk);
+  T s[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = T(0);
+  if (i < n) {
+    for (int j = j0 + wave; j < j1; j += kWaves) {
+      const T a = inv[size_t(j) * n + i];
+#pragma unroll
+      for (int q = 0; q < D; ++q) s[q] = fma(a, b[size_t(q) * n + j], s[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) acc[wave][q][lane] = s[q];
+  __syncthreads();
+  if (wave == 0 && i < n) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T t = acc[0][q][lane];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) t += acc[w][q][lane];
+      part[(size_t(blockIdx.y) * D + q) * n + i] = t;
+    }
+  }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kB) void k_dense_sum(const T* __restrict__ part, T* __restrict__ x, int n, int nc,
+                                                  const int32_t* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    T t = part[size_t(q) * n + i];
+    for (int c = 1; c < nc; ++c) t += part[(size_t(c) * D + q) * n + i];
+    x[size_t(q) * n + i] = t;
+  }
+}
+
+// Both triangles of the inverse from the lower triangle rocSOLVER leaves
+// (column-major, FP64), in the hierarchy's precision.
+template <class T>
+__global__ __launch_bounds__(kB) void k_sym_from_lower(const double* __restrict__ lo, T* __restrict__ out, int n) {
+  const int64_t t = int64_t(blockIdx.x) * kB + threadIdx.x;
+  if (t >= int64_t(n) * n) return;
+  const int j = int(t / n), i = int(t % n);
+  out[t] = T(i >= j ? lo[size_t(j) * n + i] : lo[size_t(i) * n + j]);
+}
+
 // x = D^{-1} b: the coarsest level when no two of its rows are coupled.
 template <class T, int D>
 __global__ __launch_bounds__(kB) void k_diag_solve(const T* __restrict__ dinv, const T* __restrict__ b,
@@ -365,6 +427,20 @@ void amg_dense(const T* inv, const T* b, T* x, int n, int dim, hipStream_t s, co
 }
 
 template <class T>
+void amg_dense_chunked(const T* inv, const T* b, T* x, T* part, int n, int dim, hipStream_t s,
+                       const int32_t* gate) {
+  const int nc = (n + kDenseChunk - 1) / kDenseChunk;
+  JFNK_DIM_DISPATCH(dim, k_dense_part, dim3((n + 63) / 64, nc), dim3(kB), 0, s, inv, b, part, n, gate);
+  JFNK_DIM_DISPATCH(dim, k_dense_sum, dim3(blocks_for(n)), dim3(kB), 0, s, part, x, n, nc, gate);
+}
+
+template <class T>
+void amg_sym_from_lower(const double* lo, T* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_from_lower<T>, dim3(blocks_for(int64_t(n) * n)), dim3(kB), 0, s, lo, out, n);
+  JFNK_HIP(hipGetLastError());
+}
+
+template <class T>
 void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t s, const int32_t* gate) {
   JFNK_DIM_DISPATCH(dim, k_diag_solve, dim3(blocks_for(n)), dim3(kB), 0, s, dinv, b, x, n, gate);
 }
@@ -382,6 +458,8 @@ void amg_diag_solve(const T* dinv, const T* b, T* x, int n, int dim, hipStream_t
                                 hipStream_t, const int32_t*);                                             \
   template void amg_spmv<T>(const DevCsr&, const T*, T*, bool, int, hipStream_t, const int32_t*);         \
   template void amg_dense<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);              \
+  template void amg_dense_chunked<T>(const T*, const T*, T*, T*, int, int, hipStream_t, const int32_t*);  \
+  template void amg_sym_from_lower<T>(const double*, T*, int, hipStream_t);                               \
   template void amg_diag_solve<T>(const T*, const T*, T*, int, int, hipStream_t, const int32_t*);
 
 JFNK_AMG_INSTANTIATE(float)

@@ -470,6 +470,18 @@ jfnk_status jfnk_set_cell_passes(jfnk_mesh* mesh, int32_t passes, int32_t persis
   });
 }
 
+jfnk_status jfnk_amg_info_get(const jfnk_mesh* mesh, int32_t precond, jfnk_amg_info* info) {
+  return guarded([&] {
+    check_mesh(mesh);
+    JFNK_REQUIRE(info != nullptr, JFNK_E_ARG, "amg_info: null output");
+    JFNK_REQUIRE(precond == JFNK_PC_AMG32 || precond == JFNK_PC_AMG64, JFNK_E_ARG,
+                 "amg_info: precond must be AMG32 or AMG64");
+    const AmgHierarchy* H = precond == JFNK_PC_AMG64 ? mesh->amg64 : mesh->amg;
+    JFNK_REQUIRE(H != nullptr, JFNK_E_ARG, "amg_info: hierarchy not built yet (run a solve or jfnk_autotune)");
+    amg_describe(*H, *info);
+  });
+}
+
 const char* jfnk_version(void) { return "jfnk-mi355x 0.1 (gfx950)"; }
 
 

@@ -99,6 +99,7 @@ void precond_apply(jfnk_mesh* m, int precond, int cheb_degree, const double* r, 
 void amg_destroy(AmgHierarchy* a);
 // Device bytes held by a hierarchy (0 for null).
 size_t amg_device_bytes(const AmgHierarchy* a);
+void amg_describe(const AmgHierarchy& H, jfnk_amg_info& info);
 void autotune(jfnk_mesh* m, const jfnk_gmres_opts& o, const double* u, double load, void* work, hipStream_t s,
               jfnk_tune_report* rep);
 

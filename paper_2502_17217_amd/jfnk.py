@@ -135,6 +135,7 @@ def _load():
         "jfnk_dynamic_step": [vp, d, i32, C.POINTER(jfnk_newton_opts), vp, vp, vp, vp, vp, vp, vp, vp],
         "jfnk_segregated_solve": [vp, C.POINTER(jfnk_segregated_opts), vp, vp, vp, vp],
         "jfnk_jv_central": [vp, d, vp, vp, d, vp, vp, vp, vp],
+        "jfnk_amg_info_get": [vp, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -516,6 +517,22 @@ def autotune(mesh, opts, u, work, load=1.0, stream=None):
     _check(_lib.jfnk_autotune(mesh.handle, C.byref(opts), _dptr(u, mesh.n_dof, "u"), float(load), work.c,
                               _stream(stream), C.byref(rep)), "jfnk_autotune")
     return rep.as_dict()
+
+
+class jfnk_amg_info(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("coarse_dense", C.c_int32), ("rows", C.c_int64 * 16),
+                ("nnz", C.c_int64 * 16), ("lanes", C.c_int32 * 16), ("operator_complexity", C.c_double),
+                ("setup_ms", C.c_double), ("device_bytes", C.c_int64)]
+
+
+def amg_info(mesh, precond=PC_AMG32):
+    """Shape of the handle's AMG hierarchy (built by a solve or autotune)."""
+    i = jfnk_amg_info()
+    _check(_lib.jfnk_amg_info_get(mesh.handle, _pc(precond), C.cast(C.pointer(i), C.c_void_p)), "jfnk_amg_info_get")
+    n = i.n_levels
+    return {"levels": n, "rows": list(i.rows[:n]), "nnz": list(i.nnz[:n]), "lanes": list(i.lanes[:n]),
+            "coarse": "dense" if i.coarse_dense else "diagonal", "operator_complexity": i.operator_complexity,
+            "setup_ms": i.setup_ms, "device_bytes": i.device_bytes}
 
 
 def set_cell_passes(mesh, passes, persist=0):
