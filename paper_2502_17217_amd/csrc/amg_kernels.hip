@@ -295,18 +295,26 @@ __global__ __launch_bounds__(kB) void k_dense_part(const T* __restrict__ inv, co
   }
 }
 
+// Second pass: one thread per (row, component), the chunks' partial sums
+// loaded eight at a time and added in chunk order.
 template <class T, int D>
 __global__ __launch_bounds__(kB) void k_dense_sum(const T* __restrict__ part, T* __restrict__ x, int n, int nc,
                                                   const int32_t* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int i = blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t >= D * n) return;
+  const int q = t / n, i = t % n;
+  T s = part[size_t(q) * n + i];
+  int c = 1;
+  for (; c + 8 <= nc; c += 8) {
+    T v[8];
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    T t = part[size_t(q) * n + i];
-    for (int c = 1; c < nc; ++c) t += part[(size_t(c) * D + q) * n + i];
-    x[size_t(q) * n + i] = t;
+    for (int k = 0; k < 8; ++k) v[k] = part[(size_t(c + k) * D + q) * n + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
   }
+  for (; c < nc; ++c) s += part[(size_t(c) * D + q) * n + i];
+  x[size_t(q) * n + i] = s;
 }
 
 // Both triangles of the inverse from the lower triangle rocSOLVER leaves
@@ -431,7 +439,7 @@ void amg_dense_chunked(const T* inv, const T* b, T* x, T* part, int n, int dim, 
                        const int32_t* gate) {
   const int nc = (n + kDenseChunk - 1) / kDenseChunk;
   JFNK_DIM_DISPATCH(dim, k_dense_part, dim3((n + 63) / 64, nc), dim3(kB), 0, s, inv, b, part, n, gate);
-  JFNK_DIM_DISPATCH(dim, k_dense_sum, dim3(blocks_for(n)), dim3(kB), 0, s, part, x, n, nc, gate);
+  JFNK_DIM_DISPATCH(dim, k_dense_sum, dim3(blocks_for(int64_t(dim) * n)), dim3(kB), 0, s, part, x, n, nc, gate);
 }
 
 template <class T>
