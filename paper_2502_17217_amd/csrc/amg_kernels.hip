@@ -275,7 +275,18 @@ __global__ __launch_bounds__(kB) void k_dense_part(const T* __restrict__ inv, co
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = T(0);
   if (i < n) {
-    for (int j = j0 + wave; j < j1; j += kWaves) {
+    // eight of this wave's columns loaded at a time, then added in order
+    int j = j0 + wave;
+    for (; j + 7 * kWaves < j1; j += 8 * kWaves) {
+      T a[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] = inv[size_t(j + k * kWaves) * n + i];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < D; ++q) s[q] = fma(a[k], b[size_t(q) * n + j + k * kWaves], s[q]);
+    }
+    for (; j < j1; j += kWaves) {
       const T a = inv[size_t(j) * n + i];
 #pragma unroll
       for (int q = 0; q < D; ++q) s[q] = fma(a, b[size_t(q) * n + j], s[q]);
