@@ -294,52 +294,85 @@ __global__ __launch_bounds__(kBlock) void k_dcgs_dots(SegLayout L, const double*
   }
 }
 
-// Step j per segment (one workgroup over all segments), from a, c, d, |w|^2
-// (h[s]) and b (h2[s]).  For j > 0: alpha = sqrt(d - |a|^2) completes
-// column j-1 (rows += sigma a, subdiagonal sigma alpha, sigma its first-pass
-// subdiagonal) and takes its Givens step; d <= |a|^2 means u lies in the
-// span of the basis (a breakdown: subdiagonal 0, the segment stops).  Then,
-// unless the segment stops or last (closing pass), the first-pass column j
-// (rows b, diagonal h_jj = (c - a.b) / alpha), with alpha and h_jj kept in
-// nrm[4s+2], nrm[4s+3] for the update pass.  Step 0 has nothing to
-// complete: alpha = 1, h_00 = c.
-__global__ __launch_bounds__(kBlock) void k_dcgs_finalize(GmresDev G, int S, int j, int max_it,
-                                                          const double* __restrict__ h,
-                                                          const double* __restrict__ h2,
-                                                          double* __restrict__ nrm, int last) {
+// Step j, one wavefront per segment, from a, c, d, |w|^2 (h[s]) and b
+// (h2[s]).  For j > 0: alpha = sqrt(d - |a|^2) completes column j-1 (rows
+// += sigma a, subdiagonal sigma alpha, sigma its first-pass subdiagonal) and
+// takes its Givens step; d <= |a|^2 means u lies in the span of the basis (a
+// breakdown: subdiagonal 0, the segment stops).  Then, unless the segment
+// stops or last (closing pass), the first-pass column j (rows b, diagonal
+// h_jj = (c - a.b) / alpha), with alpha and h_jj kept in nrm[4s+2],
+// nrm[4s+3] for the update pass.  Step 0 has nothing to complete: alpha = 1,
+// h_00 = c.  The dot products |a|^2 and a.b are lane-strided sums reduced in
+// the fixed wavefront order; the Givens rotations of column j-1 run in one
+// lane on a copy in LDS.
+__global__ __launch_bounds__(64) void k_dcgs_finalize(GmresDev G, int j, int max_it, const double* __restrict__ h,
+                                                      const double* __restrict__ h2, double* __restrict__ nrm,
+                                                      int last) {
+  __shared__ double col[kMaxBasis + 1];
+  __shared__ double cl[kMaxBasis], sl[kMaxBasis];
+  __shared__ int go;
+  const int s = blockIdx.x, lane = threadIdx.x;
+  if (G.act[s] == 0) return;
   const int mr = G.mr;
-  for (int s = threadIdx.x; s < S; s += kBlock) {
-    if (G.act[s] == 0) continue;
-    const double* a = h + size_t(s) * kMaxBasis;
-    const double* b = h2 + size_t(s) * kMaxBasis;
-    const double cu = a[j], du = a[j + 1], ww = a[j + 2];
-    if (!isfinite(du) || (!last && (!isfinite(cu) || !isfinite(ww)))) {
-      segment_stop(G, s, true);
-      continue;
+  const double* a = h + size_t(s) * kMaxBasis;
+  const double* b = h2 + size_t(s) * kMaxBasis;
+  const double cu = a[j], du = a[j + 1], ww = a[j + 2];
+  if (!isfinite(du) || (!last && (!isfinite(cu) || !isfinite(ww)))) {
+    if (lane == 0) segment_stop(G, s, true);
+    return;
+  }
+  double pa = 0.0, pb = 0.0;
+  for (int i = lane; i < j; i += 64) {
+    pa = fma(a[i], a[i], pa);
+    pb = fma(a[i], b[i], pb);
+  }
+  const double aa = wave_sum(pa), ab = wave_sum(pb);
+  double alpha = 1.0;
+  if (j > 0) {
+    const double rem = du - aa;
+    const bool in_span = !(rem > 0.0);
+    alpha = in_span ? 0.0 : sqrt(rem);
+    double* Hp = G.H + (size_t(s) * mr + j - 1) * (mr + 1);
+    const double sigma = Hp[j];
+    for (int i = lane; i < j; i += 64) col[i] = fma(sigma, a[i], Hp[i]);
+    for (int i = lane; i < j - 1; i += 64) {
+      cl[i] = G.cs[size_t(s) * mr + i];
+      sl[i] = G.sn[size_t(s) * mr + i];
     }
-    double alpha = 1.0;
-    if (j > 0) {
-      double aa = 0.0;
-      for (int i = 0; i < j; ++i) aa = fma(a[i], a[i], aa);
-      const double rem = du - aa;
-      const bool in_span = !(rem > 0.0);
-      alpha = in_span ? 0.0 : sqrt(rem);
-      double* Hp = G.H + (size_t(s) * mr + j - 1) * (mr + 1);
-      const double sigma = Hp[j];
-      for (int i = 0; i < j; ++i) Hp[i] = fma(sigma, a[i], Hp[i]);
-      Hp[j] = sigma * alpha;
-      const int more = givens_apply(G, s, j - 1, max_it);
-      if (!more || in_span) {
-        segment_stop(G, s, false);
-        continue;
+    if (lane == 0) col[j] = sigma * alpha;
+    __syncthreads();
+    if (lane == 0) {
+      // the rotations of columns 0..j-2, then column j-1's own
+      const int c0 = j - 1;
+      for (int i = 0; i < c0; ++i) {
+        const double t = cl[i] * col[i] + sl[i] * col[i + 1];
+        col[i + 1] = -sl[i] * col[i] + cl[i] * col[i + 1];
+        col[i] = t;
       }
+      double* g = G.g + size_t(s) * (mr + 1);
+      const double rr = hypot(col[c0], col[c0 + 1]);
+      const double cn = col[c0] / rr, sn = col[c0 + 1] / rr;
+      G.cs[size_t(s) * mr + c0] = cn;
+      G.sn[size_t(s) * mr + c0] = sn;
+      col[c0] = rr;
+      col[c0 + 1] = 0.0;
+      g[c0 + 1] = -sn * g[c0];
+      g[c0] = cn * g[c0];
+      G.its[s] += 1;
+      G.kk[s] = c0 + 1;
+      const bool more = !(fabs(g[c0 + 1]) <= G.target[s] || G.its[s] >= max_it);
+      go = more && !in_span;
+      if (!go) segment_stop(G, s, false);
     }
-    if (last) continue;
-    double ab = 0.0;
-    for (int i = 0; i < j; ++i) ab = fma(a[i], b[i], ab);
-    const double hjj = (cu - ab) / alpha;
-    double* Hj = G.H + (size_t(s) * mr + j) * (mr + 1);
-    for (int i = 0; i < j; ++i) Hj[i] = b[i];
+    __syncthreads();
+    for (int i = lane; i <= j; i += 64) Hp[i] = col[i];
+    if (!go) return;
+  }
+  if (last) return;
+  const double hjj = (cu - ab) / alpha;
+  double* Hj = G.H + (size_t(s) * mr + j) * (mr + 1);
+  for (int i = lane; i < j; i += 64) Hj[i] = b[i];
+  if (lane == 0) {
     Hj[j] = hjj;
     nrm[4 * s + 2] = alpha;
     nrm[4 * s + 3] = hjj;
@@ -691,7 +724,7 @@ void dcgs_step(const SegLayout& L, bool any_large, double* V, int64_t ldv, int j
     if (j > 0)
       hipLaunchKernelGGL(k_reduce_large, dim3(j, L.n_seg), wide, 0, s, L, partials2, 0, act, h2, kMaxBasis);
   }
-  hipLaunchKernelGGL(k_dcgs_finalize, dim3(1), b, 0, s, G, L.n_seg, j, max_it, h, h2, nrm, closing ? 1 : 0);
+  hipLaunchKernelGGL(k_dcgs_finalize, dim3(L.n_seg), dim3(64), 0, s, G, j, max_it, h, h2, nrm, closing ? 1 : 0);
   if (!closing) {
     if (d3)
       hipLaunchKernelGGL(k_dcgs_update<3>, g, b, 0, s, L, V, ldv, j, w, h, h2, nrm, act, partials, tickets);
