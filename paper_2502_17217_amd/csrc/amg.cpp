@@ -594,31 +594,42 @@ void dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& ou
     }
   shift *= 1e-12;
   for (int64_t i = 0; i < n; ++i) M[size_t(i) * n + i] += shift;
+  // every buffer is allocated before the library section below holds the
+  // capture lock (DevBuf allocation and release take it themselves) and
+  // released after it
   DevBuf dm, dinfo;
   dm.alloc(M.size() * sizeof(double));
   dinfo.alloc(256);
-  JFNK_HIP(hipMemcpyAsync(dm.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  rocblas_handle h = nullptr;
-  check_rocblas(rocblas_create_handle(&h), "rocblas_create_handle");
-  struct Handle {
-    rocblas_handle h;
-    ~Handle() { (void)rocblas_destroy_handle(h); }
-  } guard{h};
-  check_rocblas(rocblas_set_stream(h, s), "rocblas_set_stream");
-  rocblas_int info = 0;
-  check_rocblas(rocsolver_dpotrf(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
-                                 dinfo.as<rocblas_int>()),
-                "Cholesky factorisation");
-  JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
-  JFNK_HIP(hipStreamSynchronize(s));
-  JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator not positive definite");
-  check_rocblas(rocsolver_dpotri(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
-                                 dinfo.as<rocblas_int>()),
-                "inverse from the Cholesky factor");
-  JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
-  JFNK_HIP(hipStreamSynchronize(s));
-  JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator singular");
   out.alloc(M.size() * (fp64 ? 8 : 4));
+  JFNK_HIP(hipMemcpyAsync(dm.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  {
+    // rocBLAS and rocSOLVER make device-wide calls of their own (handle and
+    // workspace set-up, work on the legacy stream) that the runtime rejects
+    // while another thread of the process captures a graph on a blocking
+    // stream: like allocations, the whole section holds the capture lock
+    // shared, from handle creation to its destruction
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
+    rocblas_handle h = nullptr;
+    check_rocblas(rocblas_create_handle(&h), "rocblas_create_handle");
+    struct Handle {
+      rocblas_handle h;
+      ~Handle() { (void)rocblas_destroy_handle(h); }
+    } guard{h};
+    check_rocblas(rocblas_set_stream(h, s), "rocblas_set_stream");
+    rocblas_int info = 0;
+    check_rocblas(rocsolver_dpotrf(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
+                                   dinfo.as<rocblas_int>()),
+                  "Cholesky factorisation");
+    JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipStreamSynchronize(s));
+    JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator not positive definite");
+    check_rocblas(rocsolver_dpotri(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
+                                   dinfo.as<rocblas_int>()),
+                  "inverse from the Cholesky factor");
+    JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipStreamSynchronize(s));
+    JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator singular");
+  }
   if (fp64)
     amg_sym_from_lower<double>(dm.as<double>(), out.as<double>(), int(n), s);
   else
