@@ -604,6 +604,19 @@ def c3_solve(gm, m, mat, n_increments, restart, log, line_search=0, stol=1e-12, 
     return report, (u_final if status == jfnk.OK else None)
 
 
+def _failures(jfnk, res):
+    """Requests that ended with an error (not those cancelled before they
+    started): count per status and the first message of each."""
+    out = {}
+    for _, (info, _) in res:
+        if info["status"] in (jfnk.OK, jfnk.E_NOT_CONVERGED, jfnk.E_BUSY):
+            continue
+        name = jfnk.STATUS_NAMES.get(info["status"], str(info["status"]))
+        e = out.setdefault(name, {"count": 0, "first": "%s (%d cells)" % (info.get("error", ""), info.get("n_cells", 0))})
+        e["count"] += 1
+    return out
+
+
 def _stream_window(jfnk, pool, mk, rate, seconds, max_slots, max_queue, budget, seed, keep=0):
     """Poisson arrivals at `rate` for `seconds`, request k being pool[k % len];
     submissions to a full queue are shed.  At the end of the window the
@@ -643,6 +656,7 @@ def _stream_window(jfnk, pool, mk, rate, seconds, max_slots, max_queue, budget, 
            "backlog_at_end": at_end["queued"] + at_end["running"], "cancelled_at_end": cancelled,
            "completed_total": final["completed"], "failed": final["rejected"],
            "converged": sum(1 for _, (i, _) in res if i["status"] == jfnk.OK),
+           "failures": _failures(jfnk, res),
            "p50_ms": float(np.percentile(lat, 50)) if lat else None,
            "p99_ms": float(np.percentile(lat, 99)) if lat else None,
            "hbm_peak_bytes": final["hbm_peak"]}
