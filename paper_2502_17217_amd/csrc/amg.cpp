@@ -582,8 +582,9 @@ void check_rocblas(rocblas_status st, const char* what) {
 // Inverse of the SPD coarse operator A on the device: the dense matrix (with
 // the host path's diagonal shift) to the device, its Cholesky factor and
 // inverse by rocSOLVER in FP64, then both triangles in the hierarchy's
-// precision, column-major.
-void dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& out) {
+// precision, column-major.  Returns false (out released) when the Cholesky
+// factorisation finds the shifted operator not positive definite.
+bool dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& out) {
   const int64_t n = A.n;
   std::vector<double> M(size_t(n) * size_t(n), 0.0);
   double shift = 0;
@@ -602,6 +603,7 @@ void dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& ou
   dinfo.alloc(256);
   out.alloc(M.size() * (fp64 ? 8 : 4));
   JFNK_HIP(hipMemcpyAsync(dm.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  bool pd = true;
   {
     // rocBLAS and rocSOLVER make device-wide calls of their own (handle and
     // workspace set-up, work on the legacy stream) that the runtime rejects
@@ -622,19 +624,26 @@ void dense_inverse_device(const HostCsr& A, bool fp64, hipStream_t s, DevBuf& ou
                   "Cholesky factorisation");
     JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
     JFNK_HIP(hipStreamSynchronize(s));
-    JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator not positive definite");
-    check_rocblas(rocsolver_dpotri(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
-                                   dinfo.as<rocblas_int>()),
-                  "inverse from the Cholesky factor");
-    JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    JFNK_HIP(hipStreamSynchronize(s));
-    JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator singular");
+    pd = info == 0;
+    if (pd) {
+      check_rocblas(rocsolver_dpotri(h, rocblas_fill_lower, rocblas_int(n), dm.as<double>(), rocblas_int(n),
+                                     dinfo.as<rocblas_int>()),
+                    "inverse from the Cholesky factor");
+      JFNK_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+      JFNK_HIP(hipStreamSynchronize(s));
+      JFNK_REQUIRE(info == 0, JFNK_E_MESH, "amg: coarse operator singular");
+    }
+  }
+  if (!pd) {
+    out.release();
+    return false;
   }
   if (fp64)
     amg_sym_from_lower<double>(dm.as<double>(), out.as<double>(), int(n), s);
   else
     amg_sym_from_lower<float>(dm.as<double>(), out.as<float>(), int(n), s);
   JFNK_HIP(hipStreamSynchronize(s));
+  return true;
 }
 
 }  // namespace
@@ -688,7 +697,7 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
       }
     }
     HostCsr A = fine_operator(m->host, sym.empty() ? diag0 : diag_mean);
-    const int64_t dense_max = (m->n_seg() == 1 && A.n >= kDeviceDenseMinRows) ? kDenseMax : kHostDenseMax;
+    int64_t dense_max = (m->n_seg() == 1 && A.n >= kDeviceDenseMinRows) ? kDenseMax : kHostDenseMax;
     const double nnz0 = double(A.nnz());
     size_t off = 0;
     auto take = [&](int64_t count) {
@@ -701,8 +710,17 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
       AmgLevel L;
       L.n = A.n;
       std::vector<double> d = diagonal(A);
-      const bool last = A.n <= dense_max || int(H->levels.size()) + 1 >= kMaxLevels;
+      bool last = A.n <= dense_max || int(H->levels.size()) + 1 >= kMaxLevels;
       H->op_complexity += double(A.nnz()) / nnz0;
+      if (last && A.n > kHostDenseMax && !dense_inverse_device(A, fp64, s, H->coarse_inv)) {
+        // not positive definite in FP64 at this size (the Galerkin products
+        // of a nonsymmetric or nearly singular fine operator): coarsen on to
+        // the host limit, as a batch or a small mesh does
+        JFNK_REQUIRE(int(H->levels.size()) + 1 < kMaxLevels, JFNK_E_MESH,
+                     "amg: coarse operator not positive definite");
+        dense_max = kHostDenseMax;
+        last = false;
+      }
       if (last) {
         L.off_x = take(A.n);
         L.off_b = take(A.n);
@@ -710,7 +728,6 @@ void amg_setup(jfnk_mesh* m, bool fp64, hipStream_t s) {
           std::vector<double> inv = dense_inverse(A);
           upload_values(H->coarse_inv, inv.data(), inv.size(), fp64, s);
         } else {
-          dense_inverse_device(A, fp64, s, H->coarse_inv);
           H->off_part = take(n_chunks(A.n, kDenseChunk) * A.n);
         }
         H->n_coarse = A.n;
