@@ -71,3 +71,31 @@ def test_large_mesh_dense_coarse_level(lib, precond):
     print("oracle |R(u_gpu)| / |R(0)| %.2e" % rel)
     assert rel <= 2 * rtol
     gm.close()
+
+
+def test_served_pool_mesh_coarse_level(lib):
+    """The 1,081,472-cell block of the serving stream's request pool (seeded
+    generator, 24 requests of up to 2M cells): its 5000-row coarse operator
+    was found not positive definite by the device Cholesky in two serving
+    runs (among concurrent requests), which failed the request; run alone its
+    1,924-row coarse operator factorises.  A hierarchy whose factorisation
+    fails coarsens on to the 200-row host limit; either way the
+    preconditioned GMRES solve of J x = -R(0) converges."""
+    pool = mg.config_c5_stream(rate=200.0, duration=1e9, hi=2e6, max_requests=24)
+    hit = [r for r in pool if r["mesh"]["n_cells"] == 1081472]
+    assert hit, sorted(r["mesh"]["n_cells"] for r in pool)
+    r = hit[0]
+    print("pool mesh: %d cells, %s" % (r["mesh"]["n_cells"], r["material"].law), flush=True)
+    gm = lib.create_mesh(r["mesh"], r["material"])
+    work = lib.make_workspace(gm, 1, restart=30, precond=lib.PC_AMG32)
+    u = torch.zeros(gm.n_dof, dtype=torch.float64, device="cuda")
+    R = torch.empty_like(u)
+    lib.residual(gm, 1.0, u, R, work)
+    x = torch.zeros_like(u)
+    st, stats = lib.gmres(gm, 1.0, u, R, -R, x, lib.gmres_opts(restart=30, max_it=5000, rtol=1e-8, precond="amg32"),
+                          work)
+    info = lib.amg_info(gm, lib.PC_AMG32)
+    print(stats["gmres_it"], "GMRES;", info, flush=True)
+    assert st == lib.OK
+    assert info["coarse"] == "dense" and info["rows"][-1] <= 5000
+    gm.close()
